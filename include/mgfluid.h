@@ -1,0 +1,193 @@
+/*
+ * mgfluid.h -- C ABI of the MI355X (gfx950) multigrid solver for the
+ * axisymmetric 2D drift-diffusion fluid equations of Ristivojevic & Petrovic,
+ * "Multigrid solver for axisymmetrical 2D fluid equations" (arXiv:0811.4446).
+ *
+ * Problem (Sec. 2): electron and ion densities n_e, n_p and potential V on
+ * (r, z) in [0, R] x [0, d]; continuity Eqs. (1)-(2) with drift-diffusion
+ * fluxes Eqs. (3)-(4), Poisson Eq. (5).  Axisymmetric; radial nodes
+ * r_i = i R / nr (equidistant), axial nodes z_j given (non-equidistant).
+ * Electrodes at z = 0 and z = d (Dirichlet), zero radial flux at r = 0 and
+ * r = R.
+ *
+ * Memory.  Every device field is a row-major (nr+1) x pitch array of
+ * doubles, element (i, j) at [i*pitch + j], i = radial node, j = axial node,
+ * z contiguous; pitch comes from mg_query.  Columns j > nz are padding and
+ * never read.  All device memory (fields and the workspace) is allocated and
+ * owned by the caller; the library owns only its host-side context.
+ *
+ * Streams.  Every call enqueues its kernels on the stream given to
+ * mg_setup (a hipStream_t passed as void*).  Calls that must read a norm
+ * (mg_solve, implicit_step, solve_steady, and vcycle with a non-NULL
+ * relres_out) synchronise that stream before returning.
+ *
+ * Errors.  0 on success, a negative MG_E* code on failure; mg_last_error()
+ * returns a message for the calling thread.  Arguments are validated before
+ * any device work.  A context is not thread-safe; distinct contexts on
+ * distinct streams are independent.
+ */
+#ifndef MGFLUID_H
+#define MGFLUID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_ABI_VERSION 1
+
+#define MG_OK 0
+#define MG_EINVAL (-1)      /* bad argument (null pointer, grid, enum, version) */
+#define MG_EHIP (-2)        /* a HIP runtime call failed                        */
+#define MG_ENOCONV (-3)     /* not converged within the cycle/step budget       */
+#define MG_ENONFINITE (-4)  /* a norm became NaN or Inf                          */
+#define MG_EREJECT (-5)     /* time step rejected past the retry budget          */
+#define MG_ENOMEM (-6)      /* workspace smaller than mg_query reported          */
+
+typedef struct mg_ctx mg_ctx;
+
+typedef enum { MG_FP64 = 0, MG_FP32_IR = 1 } mg_prec;
+typedef enum { MG_EQ_POISSON = 0, MG_EQ_ELECTRON = 1, MG_EQ_ION = 2 } mg_eq;
+typedef enum { MG_SMOOTH_RB = 0, MG_SMOOTH_ZEBRA = 1 } mg_smoother;
+typedef enum { MG_COUPLE_DECOUPLED = 0, MG_COUPLE_NEWTON = 2 } mg_coupling;
+
+/* Grid and multigrid configuration.
+ *   nr, nz       radial / axial intervals; min(nr, nz) = coarsest_n * 2^L and
+ *                both divisible by 2^L (L coarsenings, nested grids)
+ *   R, d         domain [0, R] x [0, d]
+ *   z_host       host array of nz+1 strictly increasing axial nodes with
+ *                z[0] = 0 and z[nz] = d; copied during mg_setup
+ *   coarsest_n   smaller dimension of the coarsest grid (>= 2; default 8)
+ *   nu1, nu2     pre- and post-smoothing sweeps of the V-cycle
+ *   smoother     mg_smoother: red-black point or zebra z-line Gauss-Seidel
+ *   prec         mg_prec: FP64 cycles, or FP32 cycles inside FP64
+ *                iterative refinement                                    */
+typedef struct {
+    int32_t abi_version;
+    int32_t nr, nz;
+    double R, d;
+    const double *z_host;
+    int32_t coarsest_n, nu1, nu2;
+    int32_t smoother, prec;
+} mg_grid_desc;
+
+/* Physics of Eqs. (3)-(5): mobilities, diffusion coefficients, the Poisson
+ * coupling k = e n0 / eps0, and the electrode (Dirichlet) values. */
+typedef struct {
+    double mu_e, mu_p, D_e, D_p, k;
+    double V_bottom, V_top;
+    double ne_bottom, ne_top, np_bottom, np_top;
+} mg_physics;
+
+/* Device state in the field layout above (caller-owned). */
+typedef struct {
+    double *V, *ne, *np;
+    const double *Se, *Sp;
+} mg_state;
+
+/* Time-stepping schedule (Sec. 2, last paragraphs): dt starts at dt0 and
+ * is multiplied by `growth` after each accepted step, capped at dt_max.
+ * The run stops when max over species of ||n^{k+1}-n^k||_2/||n^{k+1}||_2 <
+ * steady_tol.  Linear solves stop at relative residual lin_rtol.  A step
+ * is rejected (and retried with the previous dt, then halved) when a
+ * solve fails or the Newton correction exceeds reject_limit. */
+typedef struct {
+    double dt0, growth, dt_max, steady_tol, lin_rtol;
+    int32_t max_steps, max_cycles, coupling, max_newton;
+    double newton_tol, reject_limit;
+} mg_schedule;
+
+typedef struct {
+    int32_t steps, rejected, vcycles, newton_its;
+    double last_change, final_relres, seconds, t_end;
+} mg_report;
+
+/* Pitch (elements per row of a level-0 field) and workspace size in bytes.
+ * Pure host computation, no HIP call.  Returns MG_EINVAL for a bad grid. */
+int mg_query(const mg_grid_desc *desc, int64_t *pitch_elems, int64_t *workspace_bytes);
+
+/* Build a context over caller-allocated device workspace of at least the
+ * size mg_query reported (256-byte aligned).  Computes the per-level grid
+ * tables of Sec. 2 (nested coarse grids) and zeroes the workspace on
+ * `stream`.  The context keeps pointers into the workspace; the caller keeps
+ * it alive until mg_destroy. */
+int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
+             void *stream, mg_ctx **out);
+
+/* Free the host-side context (the workspace stays the caller's). */
+void mg_destroy(mg_ctx *ctx);
+
+/* Assemble equation `eq` on every grid level.
+ *   MG_EQ_POISSON   Eqs. (12)-(13) in finite-volume form with the charge of
+ *                   st->ne, st->np on the finest level (dt unused)
+ *   MG_EQ_ELECTRON, MG_EQ_ION
+ *                   backward-Euler Scharfetter-Gummel operator, Eqs. (7)-(11),
+ *                   with potential st->V (injected to the coarse levels),
+ *                   old density st->ne / st->np and source st->Se / st->Sp;
+ *                   dt <= 0 or dt = +inf gives the steady operator.
+ * Also writes the electrode values of `phys` into the electrode rows of the
+ * field that the equation solves for. */
+int sg_assemble(mg_ctx *ctx, int eq, const mg_physics *phys, const mg_state *st, double dt);
+
+/* Run `ncycles` V(nu1, nu2) cycles on equation `eq` (assembled before) for
+ * the device field x (electrode rows hold the boundary values).  If
+ * relres_out is non-NULL the strong-form relative residual after the last
+ * cycle is written there (this synchronises the stream). */
+int vcycle(mg_ctx *ctx, int eq, double *x, int32_t ncycles, double *relres_out);
+
+/* V-cycles until the strong-form relative residual ||(f-Ax)/vol||_2 /
+ * ||b/vol||_2 <= rtol, at most max_cycles.  MG_ENOCONV leaves the last
+ * iterate in x.  In MG_FP32_IR mode each refinement step runs FP32 cycles
+ * on the FP64 residual (defect correction). */
+int mg_solve(mg_ctx *ctx, int eq, double *x, double rtol, int32_t max_cycles,
+             int32_t *cycles_out, double *relres_out);
+
+/* Strong-form relative residual of x for equation eq (synchronises). */
+int mg_relres(mg_ctx *ctx, int eq, const double *x, double *relres_out);
+
+/* One backward-Euler step of length dt, Eq. (7).
+ *   MG_COUPLE_DECOUPLED: Poisson with the densities of step k, then the SG
+ *     electron and ion equations with the new potential.
+ *   MG_COUPLE_NEWTON: Newton-Raphson on the coupled system (Eq. 14).
+ * st is updated in place; rep (optional) receives counts. */
+int implicit_step(mg_ctx *ctx, const mg_physics *phys, mg_state *st, double dt,
+                  const mg_schedule *sched, mg_report *rep);
+
+/* Backward-Euler steps with growing dt until the densities are steady
+ * (Sec. 2, multilevel prolongation paragraph and the time-step rule). */
+int solve_steady(mg_ctx *ctx, const mg_physics *phys, mg_state *st,
+                 const mg_schedule *sched, mg_report *rep);
+
+/* Multilevel prolongation (Sec. 2): interpolate the state of the grid of
+ * `coarse` onto the twice finer grid of `fine` (bilinear, the multigrid
+ * prolongation), electrode rows set from phys.  Both contexts must share R,
+ * d and the nested z nodes. */
+int prolong_state(mg_ctx *coarse, const mg_state *src, mg_ctx *fine, mg_state *dst,
+                  const mg_physics *phys);
+
+/* ---- introspection used by the tests (kernel-level parity) ---- */
+
+/* Number of levels and the size of level l. */
+int mg_levels(const mg_ctx *ctx);
+int mg_level_shape(const mg_ctx *ctx, int level, int32_t *nr, int32_t *nz, int64_t *pitch);
+
+/* Copy coefficient `which` (0..5 = a, b, c, d, e, f) of equation eq on
+ * level l into the device buffer dst ((nr_l+1) x pitch_l doubles). */
+int mg_copy_coef(mg_ctx *ctx, int eq, int level, int which, double *dst);
+
+/* One smoothing half-sweep (colour/parity 0 or 1) of equation eq on level
+ * 0 applied to x, with the configured smoother. */
+int mg_smooth_half(mg_ctx *ctx, int eq, double *x, int colour);
+
+/* r = f - A x on the unknown nodes of level 0 (0 on electrode rows). */
+int mg_residual(mg_ctx *ctx, int eq, const double *x, double *r);
+
+/* Thread-local message of the last error. */
+const char *mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGFLUID_H */

@@ -1,0 +1,600 @@
+// Host side of the C ABI (include/mgfluid.h): grid hierarchy, workspace
+// carving, assembly on all levels, V-cycle recursion, stop tests and the
+// time-step drivers.  Every kernel goes to the context's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "mg_internal.h"
+
+using namespace mgf;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_OK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(MG_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+constexpr int64_t kAlign = 256;
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Carver {
+    char *base;
+    int64_t off = 0;
+    template <class T>
+    T *take(int64_t count) {
+        off = round_up(off, kAlign);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * (int64_t)sizeof(T);
+        return p;
+    }
+};
+
+int64_t level_pitch(int nz) { return round_up(nz + 1, 16); }
+
+int count_levels(int nr, int nz, int coarsest) {
+    if (nr < 2 || nz < 2 || coarsest < 2) return -1;
+    int m = nr < nz ? nr : nz;
+    if (m % coarsest) return -1;
+    int q = m / coarsest, L = 0;
+    while (q > 1) {
+        if (q & 1) return -1;
+        q >>= 1;
+        ++L;
+    }
+    if (nr % (1 << L) || nz % (1 << L)) return -1;
+    return L + 1;
+}
+
+int validate(const mg_grid_desc *d) {
+    if (!d) return fail(MG_EINVAL, "null grid descriptor");
+    if (d->abi_version != MG_ABI_VERSION)
+        return fail(MG_EINVAL, "abi_version %d, library has %d", d->abi_version, MG_ABI_VERSION);
+    if (!d->z_host) return fail(MG_EINVAL, "null z_host");
+    if (!(d->R > 0) || !(d->d > 0)) return fail(MG_EINVAL, "R and d must be positive");
+    if (d->smoother != MG_SMOOTH_RB && d->smoother != MG_SMOOTH_ZEBRA)
+        return fail(MG_EINVAL, "bad smoother %d", d->smoother);
+    if (d->prec != MG_FP64 && d->prec != MG_FP32_IR) return fail(MG_EINVAL, "bad precision %d", d->prec);
+    if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->nu1 > 16 || d->nu2 > 16)
+        return fail(MG_EINVAL, "bad smoothing counts %d, %d", d->nu1, d->nu2);
+    int nl = count_levels(d->nr, d->nz, d->coarsest_n);
+    if (nl < 1 || nl > kMaxLevels)
+        return fail(MG_EINVAL, "grid %dx%d cannot be coarsened to %d by halving", d->nr, d->nz, d->coarsest_n);
+    if (d->nz - 1 > 64 * 16) return fail(MG_EINVAL, "nz = %d exceeds the z-line limit 1025", d->nz);
+    int nrc = d->nr >> (nl - 1), nzc = d->nz >> (nl - 1);
+    if ((nrc + 1) * (nzc - 1) > kMaxCoarseUnknowns)
+        return fail(MG_EINVAL, "coarsest grid has %d unknowns (limit %d)", (nrc + 1) * (nzc - 1),
+                    kMaxCoarseUnknowns);
+    const double *z = d->z_host;
+    if (z[0] != 0.0 || z[d->nz] != d->d) return fail(MG_EINVAL, "z must start at 0 and end at d");
+    for (int j = 0; j < d->nz; ++j)
+        if (!(z[j + 1] > z[j])) return fail(MG_EINVAL, "z not strictly increasing at j = %d", j);
+    return MG_OK;
+}
+
+}  // namespace
+
+struct mg_ctx {
+    mg_grid_desc desc;
+    std::vector<double> zhost;
+    int nlev = 0;
+    Level lev[kMaxLevels];
+    hipStream_t stream = nullptr;
+    double *partials = nullptr;  // residual-kernel block sums
+    double *scal = nullptr;      // device scalars
+    double *coarse_scratch = nullptr;
+    double *pinned = nullptr;    // host-pinned readback
+    double *nk_copy = nullptr;   // spare level-0 field
+    double *spare[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool assembled[3] = {false, false, false};
+    int64_t vcycles = 0;
+};
+
+namespace {
+
+// Lay out every workspace array; with ctx->... pointers filled when
+// `base` is non-null.  Returns the byte count.
+int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
+    Carver cv{base};
+    int nl = count_levels(d->nr, d->nz, d->coarsest_n);
+    bool ir = d->prec == MG_FP32_IR;
+    for (int l = 0; l < nl; ++l) {
+        int nr = d->nr >> l, nz = d->nz >> l;
+        int64_t pitch = level_pitch(nz);
+        int64_t nf = (int64_t)(nr + 1) * pitch;
+        Level L;
+        memset(&L, 0, sizeof L);
+        L.g.nr = nr;
+        L.g.nz = nz;
+        L.g.pitch = pitch;
+        L.g.dr = d->R / nr;
+        L.g.wr = cv.take<double>(nr + 1);
+        L.g.fr = cv.take<double>(nr + 1);
+        L.g.z = cv.take<double>(nz + 1);
+        L.g.dz = cv.take<double>(nz);
+        L.g.dzc = cv.take<double>(nz + 1);
+        L.g.wl = cv.take<double>(nz / 2 + 1);
+        for (int e = 0; e < 3; ++e) {
+            Op<double> &o = L.op[e];
+            o.a = cv.take<double>(nf);
+            o.b = cv.take<double>(nf);
+            o.c = cv.take<double>(nf);
+            o.d = cv.take<double>(nf);
+            o.e = cv.take<double>(nf);
+            o.f = cv.take<double>(nf);
+            if (ir) {
+                Op<float> &p = L.op32[e];
+                p.a = cv.take<float>(nf);
+                p.b = cv.take<float>(nf);
+                p.c = cv.take<float>(nf);
+                p.d = cv.take<float>(nf);
+                p.e = cv.take<float>(nf);
+                p.f = cv.take<float>(nf);
+            }
+        }
+        L.x = cv.take<double>(nf);
+        L.r = cv.take<double>(nf);
+        L.vinj = cv.take<double>(nf);
+        if (ir) {
+            L.x32 = cv.take<float>(nf);
+            L.r32 = cv.take<float>(nf);
+        }
+        if (l == nl - 1) {
+            int n = (nr + 1) * (nz - 1);
+            L.ncoarse = n;
+            for (int e = 0; e < 3; ++e) {
+                L.cinv[e] = cv.take<double>((int64_t)n * n);
+                if (ir) L.cinv32[e] = cv.take<float>((int64_t)n * n);
+            }
+            double *scr = cv.take<double>((int64_t)n * 2 * n);
+            if (c) c->coarse_scratch = scr;
+        }
+        if (c) c->lev[l] = L;
+    }
+    int64_t nf0 = (int64_t)(d->nr + 1) * level_pitch(d->nz);
+    Geom g0;
+    g0.nr = d->nr;
+    g0.nz = d->nz;
+    int nblk = ((d->nz + 1 + 63) / 64) * ((d->nr + 1 + 3) / 4);
+    double *part = cv.take<double>(2 * (int64_t)nblk + 16);
+    double *scal = cv.take<double>(64);
+    double *nk = cv.take<double>(nf0);
+    double *sp[4];
+    for (int t = 0; t < 4; ++t) sp[t] = cv.take<double>(nf0);
+    if (c) {
+        c->partials = part;
+        c->scal = scal;
+        c->nk_copy = nk;
+        for (int t = 0; t < 4; ++t) c->spare[t] = sp[t];
+        c->nlev = nl;
+    }
+    return round_up(cv.off, kAlign);
+}
+
+// Grid tables of Sec. 2 for one level (host, FP64).
+void level_tables(const mg_grid_desc *d, const double *zl, int nr, int nz, std::vector<double> &wr,
+                  std::vector<double> &fr, std::vector<double> &dz, std::vector<double> &dzc,
+                  std::vector<double> &wl) {
+    double R = d->R, dr = R / nr;
+    wr.assign(nr + 1, 0.0);
+    fr.assign(nr + 1, 0.0);
+    for (int i = 0; i <= nr; ++i) {
+        if (i == 0)
+            wr[i] = dr * dr / 8.0;
+        else if (i == nr)
+            wr[i] = 0.5 * dr * (R - 0.25 * dr);
+        else
+            wr[i] = (i * dr) * dr;
+        if (i < nr) fr[i] = (i + 0.5) * dr;
+    }
+    dz.assign(nz, 0.0);
+    for (int j = 0; j < nz; ++j) dz[j] = zl[j + 1] - zl[j];
+    dzc.assign(nz + 1, 0.0);
+    for (int j = 1; j < nz; ++j) dzc[j] = 0.5 * (zl[j + 1] - zl[j - 1]);
+    wl.assign(nz / 2 + 1, 0.0);
+    for (int J = 0; J < nz / 2; ++J) {
+        double h0 = zl[2 * J + 1] - zl[2 * J];
+        double h1 = zl[2 * J + 2] - zl[2 * J + 1];
+        wl[J] = h1 / (h0 + h1);
+    }
+}
+
+int check_ctx(const mg_ctx *c) {
+    if (!c) return fail(MG_EINVAL, "null context");
+    return MG_OK;
+}
+
+int check_eq(int eq) {
+    if (eq < 0 || eq > 2) return fail(MG_EINVAL, "bad equation %d", eq);
+    return MG_OK;
+}
+
+// ---- V-cycle --------------------------------------------------------------
+
+template <class T>
+Op<T> op_of(mg_ctx *c, int l, int eq);
+template <>
+Op<double> op_of<double>(mg_ctx *c, int l, int eq) { return c->lev[l].op[eq]; }
+template <>
+Op<float> op_of<float>(mg_ctx *c, int l, int eq) { return c->lev[l].op32[eq]; }
+
+template <class T>
+T *x_of(mg_ctx *c, int l);
+template <>
+double *x_of<double>(mg_ctx *c, int l) { return c->lev[l].x; }
+template <>
+float *x_of<float>(mg_ctx *c, int l) { return c->lev[l].x32; }
+
+template <class T>
+T *r_of(mg_ctx *c, int l);
+template <>
+double *r_of<double>(mg_ctx *c, int l) { return c->lev[l].r; }
+template <>
+float *r_of<float>(mg_ctx *c, int l) { return c->lev[l].r32; }
+
+template <class T>
+const T *cinv_of(mg_ctx *c, int eq);
+template <>
+const double *cinv_of<double>(mg_ctx *c, int eq) { return c->lev[c->nlev - 1].cinv[eq]; }
+template <>
+const float *cinv_of<float>(mg_ctx *c, int eq) { return c->lev[c->nlev - 1].cinv32[eq]; }
+
+template <class T>
+void smooth(mg_ctx *c, int l, int eq, T *x, int sweeps) {
+    const Geom &g = c->lev[l].g;
+    Op<T> op = op_of<T>(c, l, eq);
+    for (int s = 0; s < sweeps; ++s)
+        for (int col = 0; col < 2; ++col) {
+            if (c->desc.smoother == MG_SMOOTH_RB)
+                launch_rbgs<T>(g, op, x, col, c->stream);
+            else
+                launch_zline<T>(g, op, x, col, c->stream);
+        }
+}
+
+// V(nu1, nu2) on level l for the field x (level l layout).
+template <class T>
+void vcycle_level(mg_ctx *c, int l, int eq, T *x) {
+    hipStream_t s = c->stream;
+    const Level &L = c->lev[l];
+    if (l == c->nlev - 1) {
+        launch_coarse_solve<T>(L.g, op_of<T>(c, l, eq), cinv_of<T>(c, eq), x, s);
+        return;
+    }
+    smooth<T>(c, l, eq, x, c->desc.nu1);
+    T *r = r_of<T>(c, l);
+    launch_residual<T, T, T>(L.g, op_of<T>(c, l, eq), nullptr, x, r, nullptr, nullptr, s);
+    const Level &C = c->lev[l + 1];
+    Op<T> oc = op_of<T>(c, l + 1, eq);
+    launch_restrict<T>(L.g, r, C.g, oc.f, s);
+    T *xc = x_of<T>(c, l + 1);
+    launch_fill(xc, (int64_t)(C.g.nr + 1) * C.g.pitch, T(0), s);
+    vcycle_level<T>(c, l + 1, eq, xc);
+    launch_prolong<T>(L.g, x, C.g, xc, s);
+    smooth<T>(c, l, eq, x, c->desc.nu2);
+}
+
+// Strong-form relative residual of the FP64 system (synchronises).
+int relres64(mg_ctx *c, int eq, const double *x, double *out) {
+    const Level &L = c->lev[0];
+    int nb = 0;
+    launch_residual<double, double, double>(L.g, L.op[eq], nullptr, x, L.r, c->partials, &nb, c->stream);
+    launch_sum_partials(c->partials, nb, 2, c->scal, c->stream);
+    HIP_OK(hipMemcpyAsync(c->pinned, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    double rr = c->pinned[0], bb = c->pinned[1];
+    *out = (bb > 0.0) ? sqrt(rr / bb) : sqrt(rr);
+    return MG_OK;
+}
+
+// One FP64 cycle, or one FP32 cycle applied as a defect correction.
+int one_cycle(mg_ctx *c, int eq, double *x) {
+    if (c->desc.prec == MG_FP64) {
+        vcycle_level<double>(c, 0, eq, x);
+    } else {
+        const Level &L = c->lev[0];
+        hipStream_t s = c->stream;
+        // FP64 residual -> FP32 right-hand side of the correction equation
+        launch_residual<double, double, float>(L.g, L.op[eq], nullptr, x, L.op32[eq].f, nullptr, nullptr, s);
+        launch_fill(L.x32, (int64_t)(L.g.nr + 1) * L.g.pitch, 0.0f, s);
+        vcycle_level<float>(c, 0, eq, L.x32);
+        launch_add_f32(L.g, x, L.x32, s);
+    }
+    c->vcycles++;
+    return MG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *mg_last_error(void) { return g_err; }
+
+int mg_query(const mg_grid_desc *desc, int64_t *pitch_elems, int64_t *workspace_bytes) {
+    int st = validate(desc);
+    if (st) return st;
+    if (pitch_elems) *pitch_elems = level_pitch(desc->nz);
+    if (workspace_bytes) *workspace_bytes = carve(nullptr, desc, nullptr);
+    return MG_OK;
+}
+
+int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes, void *stream,
+             mg_ctx **out) {
+    int st = validate(desc);
+    if (st) return st;
+    if (!out) return fail(MG_EINVAL, "null output pointer");
+    if (!workspace) return fail(MG_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(MG_EINVAL, "workspace must be %d-byte aligned", (int)kAlign);
+    int64_t need = carve(nullptr, desc, nullptr);
+    if (workspace_bytes < need)
+        return fail(MG_ENOMEM, "workspace has %lld bytes, needs %lld", (long long)workspace_bytes,
+                    (long long)need);
+    mg_ctx *c = new (std::nothrow) mg_ctx();
+    if (!c) return fail(MG_ENOMEM, "host allocation failed");
+    c->desc = *desc;
+    c->zhost.assign(desc->z_host, desc->z_host + desc->nz + 1);
+    c->desc.z_host = c->zhost.data();
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    carve(c, desc, reinterpret_cast<char *>(workspace));
+    hipError_t e = hipHostMalloc((void **)&c->pinned, 64 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(MG_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    e = hipMemsetAsync(workspace, 0, (size_t)need, c->stream);
+    // level tables
+    std::vector<double> zl, wr, fr, dz, dzc, wl;
+    for (int l = 0; l < c->nlev && e == hipSuccess; ++l) {
+        Level &L = c->lev[l];
+        zl.resize(L.g.nz + 1);
+        for (int j = 0; j <= L.g.nz; ++j) zl[j] = c->zhost[(size_t)j << l];
+        level_tables(desc, zl.data(), L.g.nr, L.g.nz, wr, fr, dz, dzc, wl);
+        e = hipMemcpyAsync((void *)L.g.wr, wr.data(), wr.size() * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void *)L.g.fr, fr.data(), fr.size() * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void *)L.g.z, zl.data(), zl.size() * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void *)L.g.dz, dz.data(), dz.size() * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void *)L.g.dzc, dzc.data(), dzc.size() * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void *)L.g.wl, wl.data(), wl.size() * 8, hipMemcpyHostToDevice, c->stream);
+        // the host vectors are reused next level: wait for the copies
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return fail(MG_EHIP, "mg_setup: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return MG_OK;
+}
+
+void mg_destroy(mg_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+int mg_levels(const mg_ctx *ctx) { return ctx ? ctx->nlev : MG_EINVAL; }
+
+int mg_level_shape(const mg_ctx *ctx, int level, int32_t *nr, int32_t *nz, int64_t *pitch) {
+    if (int st = check_ctx(ctx)) return st;
+    if (level < 0 || level >= ctx->nlev) return fail(MG_EINVAL, "bad level %d", level);
+    const Geom &g = ctx->lev[level].g;
+    if (nr) *nr = g.nr;
+    if (nz) *nz = g.nz;
+    if (pitch) *pitch = g.pitch;
+    return MG_OK;
+}
+
+int sg_assemble(mg_ctx *c, int eq, const mg_physics *ph, const mg_state *st, double dt) {
+    if (int e = check_ctx(c)) return e;
+    if (int e = check_eq(eq)) return e;
+    if (!ph || !st) return fail(MG_EINVAL, "null physics or state");
+    hipStream_t s = c->stream;
+    const Geom &g0 = c->lev[0].g;
+    if (eq == MG_EQ_POISSON) {
+        if (!st->ne || !st->np || !st->V) return fail(MG_EINVAL, "Poisson needs V, ne and np");
+        launch_set_electrodes(g0, st->V, ph->V_bottom, ph->V_top, s);
+        for (int l = 0; l < c->nlev; ++l)
+            launch_poisson_assemble(c->lev[l].g, c->lev[l].op[eq], st->ne, st->np, ph->k, l == 0, s);
+    } else {
+        bool el = eq == MG_EQ_ELECTRON;
+        double *n = el ? st->ne : st->np;
+        const double *S = el ? st->Se : st->Sp;
+        double mu = el ? ph->mu_e : ph->mu_p;
+        double D = el ? ph->D_e : ph->D_p;
+        if (!st->V || !n) return fail(MG_EINVAL, "continuity needs V and the density");
+        if (!(D > 0) || !(mu >= 0)) return fail(MG_EINVAL, "need D > 0 and mu >= 0");
+        double sgn = el ? -1.0 : 1.0;
+        double q = -sgn * mu / D;
+        double dt_inv = (dt > 0 && isfinite(dt)) ? 1.0 / dt : 0.0;
+        launch_set_electrodes(g0, n, el ? ph->ne_bottom : ph->np_bottom, el ? ph->ne_top : ph->np_top, s);
+        const double *V = st->V;
+        for (int l = 0; l < c->nlev; ++l) {
+            const Level &L = c->lev[l];
+            if (l > 0) {
+                launch_inject(c->lev[l - 1].g, V, L.g, L.vinj, s);
+                V = L.vinj;
+            }
+            launch_sg_assemble(L.g, L.op[eq], V, l == 0 ? n : nullptr, l == 0 ? S : nullptr, q, D, dt_inv, s);
+        }
+    }
+    const Level &Lc = c->lev[c->nlev - 1];
+    if (c->desc.prec == MG_FP32_IR)
+        for (int l = 0; l < c->nlev; ++l) launch_op_to_f32(c->lev[l].g, c->lev[l].op[eq], c->lev[l].op32[eq], s);
+    launch_coarse_factor(Lc.g, Lc.op[eq], c->coarse_scratch, Lc.cinv[eq], Lc.cinv32[eq], s);
+    c->assembled[eq] = true;
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+int vcycle(mg_ctx *c, int eq, double *x, int32_t ncycles, double *relres_out) {
+    if (int e = check_ctx(c)) return e;
+    if (int e = check_eq(eq)) return e;
+    if (!x) return fail(MG_EINVAL, "null x");
+    if (!c->assembled[eq]) return fail(MG_EINVAL, "equation %d not assembled", eq);
+    for (int k = 0; k < ncycles; ++k) one_cycle(c, eq, x);
+    HIP_OK(hipGetLastError());
+    if (relres_out) return relres64(c, eq, x, relres_out);
+    return MG_OK;
+}
+
+int mg_relres(mg_ctx *c, int eq, const double *x, double *relres_out) {
+    if (int e = check_ctx(c)) return e;
+    if (int e = check_eq(eq)) return e;
+    if (!x || !relres_out) return fail(MG_EINVAL, "null pointer");
+    if (!c->assembled[eq]) return fail(MG_EINVAL, "equation %d not assembled", eq);
+    return relres64(c, eq, x, relres_out);
+}
+
+int mg_solve(mg_ctx *c, int eq, double *x, double rtol, int32_t max_cycles, int32_t *cycles_out,
+             double *relres_out) {
+    if (int e = check_ctx(c)) return e;
+    if (int e = check_eq(eq)) return e;
+    if (!x) return fail(MG_EINVAL, "null x");
+    if (!c->assembled[eq]) return fail(MG_EINVAL, "equation %d not assembled", eq);
+    double rr = 0;
+    int st = relres64(c, eq, x, &rr);
+    if (st) return st;
+    int k = 0;
+    while (isfinite(rr) && rr > rtol && k < max_cycles) {
+        one_cycle(c, eq, x);
+        ++k;
+        st = relres64(c, eq, x, &rr);
+        if (st) return st;
+    }
+    if (cycles_out) *cycles_out = k;
+    if (relres_out) *relres_out = rr;
+    if (!isfinite(rr)) return fail(MG_ENONFINITE, "residual is not finite after %d cycles", k);
+    if (rr > rtol) return fail(MG_ENOCONV, "relative residual %.3e > %.3e after %d cycles", rr, rtol, k);
+    return MG_OK;
+}
+
+int mg_copy_coef(mg_ctx *c, int eq, int level, int which, double *dst) {
+    if (int e = check_ctx(c)) return e;
+    if (int e = check_eq(eq)) return e;
+    if (level < 0 || level >= c->nlev || which < 0 || which > 5 || !dst)
+        return fail(MG_EINVAL, "bad level/which/dst");
+    const Level &L = c->lev[level];
+    const double *src[6] = {L.op[eq].a, L.op[eq].b, L.op[eq].c, L.op[eq].d, L.op[eq].e, L.op[eq].f};
+    HIP_OK(hipMemcpyAsync(dst, src[which], (size_t)(L.g.nr + 1) * L.g.pitch * sizeof(double),
+                          hipMemcpyDeviceToDevice, c->stream));
+    return MG_OK;
+}
+
+int mg_smooth_half(mg_ctx *c, int eq, double *x, int colour) {
+    if (int e = check_ctx(c)) return e;
+    if (int e = check_eq(eq)) return e;
+    if (!x || (colour != 0 && colour != 1)) return fail(MG_EINVAL, "bad x or colour");
+    const Level &L = c->lev[0];
+    if (c->desc.smoother == MG_SMOOTH_RB)
+        launch_rbgs<double>(L.g, L.op[eq], x, colour, c->stream);
+    else
+        launch_zline<double>(L.g, L.op[eq], x, colour, c->stream);
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+int mg_residual(mg_ctx *c, int eq, const double *x, double *r) {
+    if (int e = check_ctx(c)) return e;
+    if (int e = check_eq(eq)) return e;
+    if (!x || !r) return fail(MG_EINVAL, "null x or r");
+    const Level &L = c->lev[0];
+    launch_residual<double, double, double>(L.g, L.op[eq], nullptr, x, r, nullptr, nullptr, c->stream);
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+int implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
+                  mg_report *rep) {
+    if (int e = check_ctx(c)) return e;
+    if (!ph || !st || !sc) return fail(MG_EINVAL, "null physics, state or schedule");
+    if (!(dt > 0)) return fail(MG_EINVAL, "dt must be positive");
+    if (sc->coupling != MG_COUPLE_DECOUPLED)
+        return fail(MG_EINVAL, "coupling %d not available in implicit_step", sc->coupling);
+    int total = 0, cyc = 0;
+    double rr = 0, worst = 0;
+    // Poisson with the densities of step k
+    int e = sg_assemble(c, MG_EQ_POISSON, ph, st, dt);
+    if (e) return e;
+    e = mg_solve(c, MG_EQ_POISSON, st->V, sc->lin_rtol, sc->max_cycles, &cyc, &rr);
+    total += cyc;
+    worst = rr > worst ? rr : worst;
+    if (e) return e;
+    // SG continuity for the electrons, then the ions, with the new potential
+    for (int eq = MG_EQ_ELECTRON; eq <= MG_EQ_ION; ++eq) {
+        e = sg_assemble(c, eq, ph, st, dt);
+        if (e) return e;
+        e = mg_solve(c, eq, eq == MG_EQ_ELECTRON ? st->ne : st->np, sc->lin_rtol, sc->max_cycles, &cyc, &rr);
+        total += cyc;
+        worst = rr > worst ? rr : worst;
+        if (e) return e;
+    }
+    if (rep) {
+        rep->vcycles += total;
+        rep->final_relres = worst;
+        rep->steps += 1;
+    }
+    return MG_OK;
+}
+
+int solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep) {
+    if (int e = check_ctx(c)) return e;
+    if (!ph || !st || !sc) return fail(MG_EINVAL, "null physics, state or schedule");
+    (void)rep;
+    return fail(MG_EINVAL, "solve_steady: not built yet");
+}
+
+int prolong_state(mg_ctx *coarse, const mg_state *src, mg_ctx *fine, mg_state *dst, const mg_physics *ph) {
+    if (!coarse || !fine || !src || !dst || !ph) return fail(MG_EINVAL, "null argument");
+    const Geom &gc = coarse->lev[0].g;
+    if (fine->nlev < 2 || fine->lev[1].g.nr != gc.nr || fine->lev[1].g.nz != gc.nz)
+        return fail(MG_EINVAL, "fine grid must be the 2x refinement of the coarse grid");
+    for (int j = 0; j <= gc.nz; ++j)
+        if (coarse->zhost[j] != fine->zhost[2 * j])
+            return fail(MG_EINVAL, "z nodes are not nested at j = %d", j);
+    // tables of the fine level 0 carry the weights; the coarse fields use the
+    // coarse context's pitch, which equals the fine context's level-1 pitch.
+    const Geom &gf = fine->lev[0].g;
+    hipStream_t s = fine->stream;
+    HIP_OK(hipStreamSynchronize(coarse->stream));
+    launch_prolong_state(gf, dst->V, gc, src->V, s);
+    launch_prolong_state(gf, dst->ne, gc, src->ne, s);
+    launch_prolong_state(gf, dst->np, gc, src->np, s);
+    launch_set_electrodes(gf, dst->V, ph->V_bottom, ph->V_top, s);
+    launch_set_electrodes(gf, dst->ne, ph->ne_bottom, ph->ne_top, s);
+    launch_set_electrodes(gf, dst->np, ph->np_bottom, ph->np_top, s);
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+}  // extern "C"

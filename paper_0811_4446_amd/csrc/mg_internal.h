@@ -1,0 +1,80 @@
+// Internal declarations shared by the library's translation units.
+// Device fields are row-major (nr+1) x pitch, z (index j) contiguous.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mgfluid.h"
+
+namespace mgf {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCoarseUnknowns = 1024;
+
+// Per-level grid tables and sizes, passed to kernels by value.
+struct Geom {
+    int nr, nz;
+    int64_t pitch;
+    double dr;
+    const double *wr;   // radial width of node i (area of its z-faces), nr+1
+    const double *fr;   // radius of face i+1/2, nr (fr[nr] = 0)
+    const double *z;    // axial nodes, nz+1
+    const double *dz;   // z[j+1]-z[j], nz
+    const double *dzc;  // axial control width (dz[j-1]+dz[j])/2, nz+1 (0 at electrodes)
+    const double *wl;   // prolongation weight of coarse node J for fine node 2J+1, nz/2
+};
+
+// Five-point operator plus right-hand side, FV (integrated) form:
+// a x[i-1][j] + b x[i][j] + c x[i+1][j] + d x[i][j-1] + e x[i][j+1] = f.
+template <class T>
+struct Op {
+    T *a, *b, *c, *d, *e, *f;
+};
+
+struct Level {
+    Geom g;
+    Op<double> op[3];
+    Op<float> op32[3];
+    double *x, *r, *vinj;
+    float *x32, *r32;
+    double *cinv[3];   // coarsest level only: transposed inverse, n x n
+    float *cinv32[3];
+    int ncoarse;       // unknowns on the coarsest level
+};
+
+// ---- kernel launchers (mg_kernels.hip) ----
+void launch_poisson_assemble(const Geom &g, Op<double> op, const double *ne, const double *np,
+                             double k, bool charge, hipStream_t s);
+void launch_sg_assemble(const Geom &g, Op<double> op, const double *V, const double *nk,
+                        const double *S, double q, double D, double dt_inv, hipStream_t s);
+void launch_inject(const Geom &gf, const double *vf, const Geom &gc, double *vc, hipStream_t s);
+void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s);
+void launch_fill(double *p, int64_t n, double v, hipStream_t s);
+void launch_fill(float *p, int64_t n, float v, hipStream_t s);
+template <class T>
+void launch_rbgs(const Geom &g, Op<T> op, T *x, int colour, hipStream_t s);
+template <class T>
+void launch_zline(const Geom &g, Op<T> op, T *x, int parity, hipStream_t s);
+// r = f - A x; if partials != nullptr also per-block sums of (r/vol)^2 and (b/vol)^2.
+template <class TA, class TX, class TR>
+void launch_residual(const Geom &g, Op<TA> op, const TX *f_override, const TX *x, TR *r,
+                     double *partials, int *nblocks_out, hipStream_t s);
+template <class T>
+void launch_restrict(const Geom &gf, const T *rf, const Geom &gc, T *fc, hipStream_t s);
+template <class T>
+void launch_prolong(const Geom &gf, T *xf, const Geom &gc, const T *xc, hipStream_t s);
+void launch_coarse_factor(const Geom &g, Op<double> op, double *scratch, double *invT, float *invT32,
+                          hipStream_t s);
+template <class T>
+void launch_coarse_solve(const Geom &g, Op<T> op, const T *invT, T *x, hipStream_t s);
+void launch_sum_partials(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s);
+void launch_diff_norms(const Geom &g, const double *a, const double *b, double *partials,
+                       int *nblocks_out, hipStream_t s);
+int residual_blocks(const Geom &g);
+void launch_copy_field(const Geom &g, const double *src, double *dst, hipStream_t s);
+void launch_to_f32(const Geom &g, const double *src, float *dst, hipStream_t s);
+void launch_add_f32(const Geom &g, double *x, const float *e, hipStream_t s);
+void launch_op_to_f32(const Geom &g, Op<double> op, Op<float> o32, hipStream_t s);
+void launch_prolong_state(const Geom &gf, double *xf, const Geom &gc, const double *xc, hipStream_t s);
+
+}  // namespace mgf

@@ -1,0 +1,248 @@
+"""Thin Python binding of libmgfluid.so (include/mgfluid.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  PyTorch provides device memory (tensors) and the stream.
+Device fields are float64 tensors of shape (nr+1, pitch) -- z contiguous,
+columns beyond nz are padding; ``Solver.field`` / ``Solver.upload`` create
+them and ``Solver.download`` returns the (nr+1, nz+1) numpy view.
+
+The library must be built (``python -m paper_0811_4446_amd.build``); there
+is no fallback: a missing library or GPU raises.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch  # loaded first so that the library binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgfluid.so")
+
+ABI_VERSION = 1
+FP64, FP32_IR = 0, 1
+POISSON, ELECTRON, ION = 0, 1, 2
+SMOOTH_RB, SMOOTH_ZEBRA = 0, 1
+DECOUPLED, NEWTON = 0, 2
+
+ERRORS = {-1: "MG_EINVAL", -2: "MG_EHIP", -3: "MG_ENOCONV", -4: "MG_ENONFINITE",
+          -5: "MG_EREJECT", -6: "MG_ENOMEM"}
+
+_D, _I32, _I64, _VP = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+_PD = ctypes.POINTER(ctypes.c_double)
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("abi_version", _I32), ("nr", _I32), ("nz", _I32), ("R", _D), ("d", _D),
+                ("z_host", _PD), ("coarsest_n", _I32), ("nu1", _I32), ("nu2", _I32),
+                ("smoother", _I32), ("prec", _I32)]
+
+
+class Physics(ctypes.Structure):
+    _fields_ = [(n, _D) for n in ("mu_e", "mu_p", "D_e", "D_p", "k", "V_bottom", "V_top",
+                                  "ne_bottom", "ne_top", "np_bottom", "np_top")]
+
+    @classmethod
+    def of(cls, d):
+        return cls(**{k: float(d[k]) for k, _ in cls._fields_})
+
+
+class State(ctypes.Structure):
+    _fields_ = [("V", _VP), ("ne", _VP), ("np", _VP), ("Se", _VP), ("Sp", _VP)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("dt0", _D), ("growth", _D), ("dt_max", _D), ("steady_tol", _D), ("lin_rtol", _D),
+                ("max_steps", _I32), ("max_cycles", _I32), ("coupling", _I32), ("max_newton", _I32),
+                ("newton_tol", _D), ("reject_limit", _D)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("steps", _I32), ("rejected", _I32), ("vcycles", _I32), ("newton_its", _I32),
+                ("last_change", _D), ("final_relres", _D), ("seconds", _D), ("t_end", _D)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol the header declares, with its ctypes signature
+SIGNATURES = {
+    "mg_query": (ctypes.c_int, [ctypes.POINTER(GridDesc), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "mg_setup": (ctypes.c_int, [ctypes.POINTER(GridDesc), _VP, _I64, _VP, ctypes.POINTER(_VP)]),
+    "mg_destroy": (None, [_VP]),
+    "sg_assemble": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(Physics), ctypes.POINTER(State), _D]),
+    "vcycle": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _I32, _PD]),
+    "mg_solve": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _D, _I32, ctypes.POINTER(_I32), _PD]),
+    "mg_relres": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _PD]),
+    "implicit_step": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _D,
+                                     ctypes.POINTER(Schedule), ctypes.POINTER(Report)]),
+    "solve_steady": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State),
+                                    ctypes.POINTER(Schedule), ctypes.POINTER(Report)]),
+    "prolong_state": (ctypes.c_int, [_VP, ctypes.POINTER(State), _VP, ctypes.POINTER(State),
+                                     ctypes.POINTER(Physics)]),
+    "mg_levels": (ctypes.c_int, [_VP]),
+    "mg_level_shape": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                      ctypes.POINTER(_I64)]),
+    "mg_copy_coef": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP]),
+    "mg_smooth_half": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int]),
+    "mg_residual": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP]),
+    "mg_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmgfluid.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmgfluid.so is not built: run python -m paper_0811_4446_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+def _check(code):
+    if code != 0:
+        raise MGError(code, lib().mg_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def make_desc(nr, nz, z, R=1.0, d=1.0, coarsest=8, nu1=2, nu2=2, smoother=SMOOTH_ZEBRA, prec=FP64):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    desc = GridDesc(ABI_VERSION, nr, nz, R, d, z.ctypes.data_as(_PD), coarsest, nu1, nu2, smoother, prec)
+    desc._z_keep = z
+    return desc
+
+
+def query(desc):
+    pitch, ws = _I64(0), _I64(0)
+    _check(lib().mg_query(ctypes.byref(desc), ctypes.byref(pitch), ctypes.byref(ws)))
+    return pitch.value, ws.value
+
+
+class Solver:
+    """One grid (and its multigrid hierarchy) on one device and stream."""
+
+    def __init__(self, nr, nz, z, R=1.0, d=1.0, coarsest=8, nu1=2, nu2=2,
+                 smoother=SMOOTH_ZEBRA, prec=FP64, device="cuda:0", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("mgfluid needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.nr, self.nz, self.R, self.d = nr, nz, R, d
+        self.z = np.ascontiguousarray(z, dtype=np.float64)
+        self.device = torch.device(device)
+        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, smoother, prec)
+        self.pitch, self.ws_bytes = query(self.desc)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(self.ws_bytes // 8 + 64, dtype=torch.float64, device=self.device)
+        assert self.workspace.data_ptr() % 256 == 0
+        h = _VP()
+        _check(lib().mg_setup(ctypes.byref(self.desc), _ptr(self.workspace), self.ws_bytes,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.ctx = h
+        self.nlev = lib().mg_levels(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().mg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- fields ----
+    def field(self, fill=0.0):
+        return torch.full((self.nr + 1, self.pitch), fill, dtype=torch.float64, device=self.device)
+
+    def upload(self, arr):
+        arr = np.asarray(arr, dtype=np.float64)
+        assert arr.shape == (self.nr + 1, self.nz + 1), arr.shape
+        t = self.field()
+        t[:, : self.nz + 1] = torch.from_numpy(np.ascontiguousarray(arr)).to(self.device)
+        return t
+
+    def download(self, t):
+        torch.cuda.synchronize(self.device)
+        return t[:, : self.nz + 1].cpu().numpy().copy()
+
+    def state(self, V, ne, np_, Se=None, Sp=None):
+        st = State(_ptr(V).value, _ptr(ne).value, _ptr(np_).value,
+                   _ptr(Se).value if Se is not None else None,
+                   _ptr(Sp).value if Sp is not None else None)
+        st._keep = (V, ne, np_, Se, Sp)
+        return st
+
+    # ---- calls ----
+    def assemble(self, eq, phys, state, dt=math.inf):
+        _check(lib().sg_assemble(self.ctx, eq, ctypes.byref(phys), ctypes.byref(state), float(dt)))
+
+    def vcycle(self, eq, x, ncycles=1, want_relres=False):
+        rr = _D(0.0)
+        _check(lib().vcycle(self.ctx, eq, _ptr(x), ncycles, ctypes.byref(rr) if want_relres else None))
+        return rr.value if want_relres else None
+
+    def solve(self, eq, x, rtol=1e-10, max_cycles=200, raise_on_noconv=True):
+        cyc, rr = _I32(0), _D(0.0)
+        code = lib().mg_solve(self.ctx, eq, _ptr(x), rtol, max_cycles, ctypes.byref(cyc), ctypes.byref(rr))
+        if code != 0 and (raise_on_noconv or code != -3):
+            _check(code)
+        return cyc.value, rr.value
+
+    def relres(self, eq, x):
+        rr = _D(0.0)
+        _check(lib().mg_relres(self.ctx, eq, _ptr(x), ctypes.byref(rr)))
+        return rr.value
+
+    def coef(self, eq, level, which):
+        nr, nz, pitch = _I32(0), _I32(0), _I64(0)
+        _check(lib().mg_level_shape(self.ctx, level, ctypes.byref(nr), ctypes.byref(nz), ctypes.byref(pitch)))
+        t = torch.zeros((nr.value + 1, pitch.value), dtype=torch.float64, device=self.device)
+        _check(lib().mg_copy_coef(self.ctx, eq, level, which, _ptr(t)))
+        torch.cuda.synchronize(self.device)
+        return t[:, : nz.value + 1].cpu().numpy().copy()
+
+    def smooth_half(self, eq, x, colour):
+        _check(lib().mg_smooth_half(self.ctx, eq, _ptr(x), colour))
+
+    def residual(self, eq, x, r):
+        _check(lib().mg_residual(self.ctx, eq, _ptr(x), _ptr(r)))
+
+    def step(self, phys, state, dt, sched):
+        rep = Report()
+        _check(lib().implicit_step(self.ctx, ctypes.byref(phys), ctypes.byref(state), float(dt),
+                                   ctypes.byref(sched), ctypes.byref(rep)))
+        return rep
+
+    def steady(self, phys, state, sched):
+        rep = Report()
+        code = lib().solve_steady(self.ctx, ctypes.byref(phys), ctypes.byref(state), ctypes.byref(sched),
+                                  ctypes.byref(rep))
+        return code, rep
+
+
+def schedule(dt0=1e-4, growth=1.5, dt_max=0.1, steady_tol=1e-8, lin_rtol=1e-10, max_steps=100000,
+             max_cycles=200, coupling=DECOUPLED, max_newton=10, newton_tol=1e-6, reject_limit=1e30):
+    return Schedule(dt0, growth, dt_max, steady_tol, lin_rtol, max_steps, max_cycles, coupling,
+                    max_newton, newton_tol, reject_limit)
+
+
+def prolong_state(coarse, src, fine, dst, phys):
+    _check(lib().prolong_state(coarse.ctx, ctypes.byref(src), fine.ctx, ctypes.byref(dst), ctypes.byref(phys)))
