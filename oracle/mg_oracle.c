@@ -782,3 +782,86 @@ int or_step_decoupled(int nr, int nz, double R, const double *z,
     or_mg_destroy(h);
     return worst;
 }
+
+/* ------------------------------------------------------------------ */
+/* Newton-Raphson blocks of the coupled system (Sec. 2, Eq. 14).        */
+/* Unknowns per node u = (n_e, n_p, V).  The continuity rows depend on  */
+/* V through alpha; this returns the derivative of one SG row          */
+/*   F = sum over faces area*phi_out + vol*(n - n^k)*dt_inv - vol*S     */
+/* with respect to V at the node and its four neighbours, as five       */
+/* coefficient arrays (a, b, c, d, e: V_{i-1}, V_i, V_{i+1}, V_{j-1},    */
+/* V_{j+1}).  Uses F'(x) = F(x)(1 - G(x))/x and G'(x) = F'(x) + 1; for  */
+/* |x| < 0.1, where 1 - G(x) cancels, the Taylor series of F' from the   */
+/* Bernoulli numbers: -1/2 + x/6 - x^3/180 + x^5/5040 - x^7/151200      */
+/* + x^9/4790016 (next term below 1e-19 there).                         */
+/* ------------------------------------------------------------------ */
+
+double or_bernoulli_dF(double x)
+{
+    if (fabs(x) < 0.1) {
+        double x2 = x * x;
+        return -0.5 + x * (1.0 / 6.0 + x2 * (-1.0 / 180.0 + x2 * (1.0 / 5040.0
+               + x2 * (-1.0 / 151200.0 + x2 * (1.0 / 4790016.0)))));
+    }
+    double F = or_bernoulli_F(x);
+    return F * (1.0 - or_bernoulli_G(x)) / x;
+}
+
+void or_sg_dV(int nr, int nz, double R, const double *z, int s, double mu,
+              double D, const double *V, const double *n, double *a, double *b,
+              double *c, double *d, double *e)
+{
+    double dr = R / nr;
+    double q = -(double)s * mu / D;
+    size_t nn = (size_t)(nr + 1) * (nz + 1);
+    memset(a, 0, nn * sizeof(double));
+    memset(b, 0, nn * sizeof(double));
+    memset(c, 0, nn * sizeof(double));
+    memset(d, 0, nn * sizeof(double));
+    memset(e, 0, nn * sizeof(double));
+    for (int i = 0; i <= nr; ++i) {
+        double w = radial_width(i, nr, R);
+        for (int j = 1; j < nz; ++j) {
+            size_t p = IDX(i, j, nz);
+            double dzc = axial_width(z, j);
+            double center = 0.0;
+            if (i < nr) { /* term g (G(al) n_p - F(al) n_{i+1}), al = q (V_{i+1} - V_p) */
+                size_t pn = IDX(i + 1, j, nz);
+                double g = face_radius(i, nr, R) * dzc * D / dr;
+                double al = q * (V[pn] - V[p]);
+                double dF = or_bernoulli_dF(al);
+                double sl = g * ((dF + 1.0) * n[p] - dF * n[pn]);
+                c[p] = q * sl;
+                center -= q * sl;
+            }
+            if (i > 0) { /* term g (F(al) n_p - G(al) n_{i-1}), al = q (V_p - V_{i-1}) */
+                size_t pn = IDX(i - 1, j, nz);
+                double g = face_radius(i - 1, nr, R) * dzc * D / dr;
+                double al = q * (V[p] - V[pn]);
+                double dF = or_bernoulli_dF(al);
+                double sl = g * (dF * n[p] - (dF + 1.0) * n[pn]);
+                a[p] = -q * sl;
+                center += q * sl;
+            }
+            {
+                size_t pn = p + 1;
+                double g = w * D / (z[j + 1] - z[j]);
+                double al = q * (V[pn] - V[p]);
+                double dF = or_bernoulli_dF(al);
+                double sl = g * ((dF + 1.0) * n[p] - dF * n[pn]);
+                e[p] = q * sl;
+                center -= q * sl;
+            }
+            {
+                size_t pn = p - 1;
+                double g = w * D / (z[j] - z[j - 1]);
+                double al = q * (V[p] - V[pn]);
+                double dF = or_bernoulli_dF(al);
+                double sl = g * (dF * n[p] - (dF + 1.0) * n[pn]);
+                d[p] = -q * sl;
+                center += q * sl;
+            }
+            b[p] = center;
+        }
+    }
+}

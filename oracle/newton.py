@@ -1,0 +1,179 @@
+"""Coupled backward-Euler step by Newton-Raphson (Sec. 2, Eq. 14) and the
+steady driver (Sec. 2, time-step rule and multilevel prolongation).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Unknowns per node u = (n_e, n_p, V) on i = 0..nr, j = 1..nz-1.  The
+nonlinear residual in finite-volume form is
+    F_e = A_e(V) n_e - vol (S_e + n_e^k / dt)          (Eqs. 7-11, s = -1)
+    F_p = A_p(V) n_p - vol (S_p + n_p^k / dt)          (s = +1)
+    F_V = A_P V - vol k (n_p - n_e)                    (Eqs. 12-13)
+where A_e, A_p are the SG operators assembled with the current V and A_P
+is the Poisson operator (all from mg_oracle.c).  The Jacobian is the
+3x3-block five-point matrix of Eq. (14); each linear system J du = -F is
+solved exactly with SciPy's sparse LU.
+"""
+import ctypes
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import _p, lib, poisson_assemble, sg_assemble, apply, volumes
+
+
+def _sg_dV(nr, nz, R, z, s, mu, D, V, n):
+    L = lib()
+    if not hasattr(L, "_dv_ready"):
+        P = ctypes.POINTER(ctypes.c_double)
+        L.or_sg_dV.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, ctypes.c_int,
+                               ctypes.c_double, ctypes.c_double, P, P] + [P] * 5
+        L.or_bernoulli_dF.restype = ctypes.c_double
+        L.or_bernoulli_dF.argtypes = [ctypes.c_double]
+        L._dv_ready = True
+    out = [np.zeros((nr + 1, nz + 1)) for _ in range(5)]
+    L.or_sg_dV(nr, nz, R, _p(z), int(s), mu, D, _p(V), _p(n), *[_p(o) for o in out])
+    return out
+
+
+def bernoulli_dF(x):
+    _sg_dV(2, 2, 1.0, np.array([0.0, 0.5, 1.0]), 1, 1.0, 1.0, np.zeros((3, 3)), np.zeros((3, 3)))
+    return lib().or_bernoulli_dF(float(x))
+
+
+class Coupled:
+    """Residual and Jacobian of the coupled BE system on one grid."""
+
+    def __init__(self, nr, nz, R, z, phys):
+        self.nr, self.nz, self.R = nr, nz, R
+        self.z = np.ascontiguousarray(z, dtype=np.float64)
+        self.ph = dict(phys)
+        self.vol = volumes(nr, nz, R, self.z)
+        self.P = poisson_assemble(nr, nz, R, self.z, 0.0)
+        m = nz - 1
+        self.m = m
+        self.nun = (nr + 1) * m
+        ii, jj = np.meshgrid(np.arange(nr + 1), np.arange(1, nz), indexing="ij")
+        self.ii, self.jj = ii.ravel(), jj.ravel()
+        self.node = (ii * m + (jj - 1)).ravel()
+
+    def electrodes(self, V, ne, np_):
+        ph = self.ph
+        V[:, 0], V[:, -1] = ph["V_bottom"], ph["V_top"]
+        ne[:, 0], ne[:, -1] = ph["ne_bottom"], ph["ne_top"]
+        np_[:, 0], np_[:, -1] = ph["np_bottom"], ph["np_top"]
+
+    def residual(self, V, ne, np_, nek, npk, Se, Sp, dt_inv):
+        ph, nr, nz, R, z = self.ph, self.nr, self.nz, self.R, self.z
+        Ae = sg_assemble(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], dt_inv, V, nek, Se)
+        Ap = sg_assemble(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], dt_inv, V, npk, Sp)
+        Fe = apply(Ae, ne) - Ae[5]
+        Fp = apply(Ap, np_) - Ap[5]
+        FV = apply(self.P, V) - self.vol * ph["k"] * (np_ - ne)
+        return (Fe, Fp, FV), (Ae, Ap)
+
+    def pack(self, Fe, Fp, FV):
+        out = np.empty(3 * self.nun)
+        out[0::3] = Fe[:, 1:-1].ravel()
+        out[1::3] = Fp[:, 1:-1].ravel()
+        out[2::3] = FV[:, 1:-1].ravel()
+        return out
+
+    def unpack(self, vec):
+        nr, nz = self.nr, self.nz
+        f = [np.zeros((nr + 1, nz + 1)) for _ in range(3)]
+        for k in range(3):
+            f[k][:, 1:-1] = vec[k::3].reshape(nr + 1, nz - 1)
+        return f
+
+    def jacobian(self, V, ne, np_, Ae, Ap):
+        """Sparse 3x3-block five-point Jacobian (Eq. 14)."""
+        ph, nr, nz, R, z = self.ph, self.nr, self.nz, self.R, self.z
+        eV = _sg_dV(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], V, ne)
+        pV = _sg_dV(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], V, np_)
+        rows, cols, vals = [], [], []
+        i, j, node, m = self.ii, self.jj, self.node, self.m
+        offs = {0: (-1, 0), 1: (0, 0), 2: (1, 0), 3: (0, -1), 4: (0, 1)}  # a, b, c, d, e
+        for w, (di, dj) in offs.items():
+            ni, nj = i + di, j + dj
+            ok = (ni >= 0) & (ni <= nr) & (nj >= 1) & (nj <= nz - 1)
+            src = node[ok]
+            dst = (ni * m + (nj - 1))[ok]
+            sel = (i[ok], j[ok])
+            for (rf, cf, arr) in ((0, 0, Ae[w]), (0, 2, eV[w]), (1, 1, Ap[w]), (1, 2, pV[w]),
+                                  (2, 2, self.P[w])):
+                rows.append(3 * src + rf)
+                cols.append(3 * dst + cf)
+                vals.append(arr[sel])
+        kv = self.vol[i, j] * ph["k"]
+        rows += [3 * node + 2, 3 * node + 2]
+        cols += [3 * node + 0, 3 * node + 1]
+        vals += [kv, -kv]
+        n = 3 * self.nun
+        return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(n, n))
+
+
+def newton_step(cp, V, ne, np_, Se, Sp, dt, max_newton=10, tol=1e-6, history=None):
+    """One BE step by Newton (Sec. 2): iterate J du = -F from u^k until the
+    relative l1 norm of the correction of every field is < tol.  Updates
+    V, ne, np_ in place and returns (converged, iterations)."""
+    dt_inv = 0.0 if not np.isfinite(dt) else 1.0 / dt
+    cp.electrodes(V, ne, np_)
+    nek, npk = ne.copy(), np_.copy()
+    for it in range(1, max_newton + 1):
+        (Fe, Fp, FV), (Ae, Ap) = cp.residual(V, ne, np_, nek, npk, Se, Sp, dt_inv)
+        J = cp.jacobian(V, ne, np_, Ae, Ap)
+        du = spla.splu(J).solve(-cp.pack(Fe, Fp, FV))
+        dne, dnp, dV = cp.unpack(du)
+        ne += dne
+        np_ += dnp
+        V += dV
+        rel = [np.abs(dne).sum() / max(np.abs(ne).sum(), 1e-300),
+               np.abs(dnp).sum() / max(np.abs(np_).sum(), 1e-300),
+               np.abs(dV).sum() / max(np.abs(V).sum(), 1e-300)]
+        if history is not None:
+            history.append(rel)
+        if not np.all(np.isfinite(du)):
+            return False, it
+        if max(rel) < tol:
+            return True, it
+    return False, max_newton
+
+
+def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
+           max_steps=100000, newton_tol=1e-6, max_newton=10, dts=None, log=None):
+    """Steps with dt <- min(growth*dt, dt_max) until max over species of
+    ||n^{k+1}-n^k||_2/||n^{k+1}||_2 < tol.  A step whose Newton iteration
+    does not converge, or that produces a negative density, is rejected
+    and retried with half the step.  If `dts` is given, that sequence of
+    accepted steps is replayed instead.  Returns (steps, rejected, dt_list)."""
+    dt = dt0
+    acc, rej, seq = 0, 0, []
+    while acc < max_steps:
+        if dts is not None:
+            if acc >= len(dts):
+                break
+            dt = dts[acc]
+        s0 = (V.copy(), ne.copy(), np_.copy())
+        ok, its = newton_step(cp, V, ne, np_, Se, Sp, dt, max_newton, newton_tol)
+        if ok:
+            floor = -1e-12 * max(np.abs(ne).max(), np.abs(np_).max())
+            ok = ne.min() >= floor and np_.min() >= floor
+        if not ok:
+            V[:], ne[:], np_[:] = s0
+            rej += 1
+            dt *= 0.5
+            if rej > 200:
+                raise RuntimeError("too many rejected steps")
+            continue
+        acc += 1
+        seq.append(dt)
+        ch = max(np.linalg.norm((ne - s0[1])[:, 1:-1]) / np.linalg.norm(ne[:, 1:-1]),
+                 np.linalg.norm((np_ - s0[2])[:, 1:-1]) / np.linalg.norm(np_[:, 1:-1]))
+        if log is not None:
+            log.append((acc, dt, its, ch))
+        if dts is None and ch < tol:
+            break
+        dt = min(growth * dt, dt_max)
+    return acc, rej, seq
