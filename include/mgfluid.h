@@ -62,7 +62,10 @@ typedef enum { MG_COUPLE_DECOUPLED = 0, MG_COUPLE_NEWTON = 2 } mg_coupling;
  *   nu1, nu2     pre- and post-smoothing sweeps of the V-cycle
  *   smoother     mg_smoother: red-black point or zebra z-line Gauss-Seidel
  *   prec         mg_prec: FP64 cycles, or FP32 cycles inside FP64
- *                iterative refinement                                    */
+ *                iterative refinement
+ *   krylov_m     restart length of the FGMRES solver of the coupled
+ *                Newton systems (Eq. 14); 0 leaves that path (and its
+ *                workspace) out, max 40                                  */
 typedef struct {
     int32_t abi_version;
     int32_t nr, nz;
@@ -70,6 +73,7 @@ typedef struct {
     const double *z_host;
     int32_t coarsest_n, nu1, nu2;
     int32_t smoother, prec;
+    int32_t krylov_m;
 } mg_grid_desc;
 
 /* Physics of Eqs. (3)-(5): mobilities, diffusion coefficients, the Poisson

@@ -145,10 +145,13 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
            max_steps=100000, newton_tol=1e-6, max_newton=10, dts=None, log=None):
     """Steps with dt <- min(growth*dt, dt_max) until max over species of
     ||n^{k+1}-n^k||_2/||n^{k+1}||_2 < tol.  A step whose Newton iteration
-    does not converge, or that produces a negative density, is rejected
-    and retried with half the step.  If `dts` is given, that sequence of
-    accepted steps is replayed instead.  Returns (steps, rejected, dt_list)."""
+    does not converge, or that ends with a density below -1e-10 times its
+    mean magnitude, is rejected: it is retried with the last accepted step
+    (Sec. 2), or with half the step if it already was that long.  If `dts`
+    is given, that sequence of accepted steps is replayed instead.
+    Returns (steps, rejected, dt_list)."""
     dt = dt0
+    dt_acc = 0.0
     acc, rej, seq = 0, 0, []
     while acc < max_steps:
         if dts is not None:
@@ -158,12 +161,13 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
         s0 = (V.copy(), ne.copy(), np_.copy())
         ok, its = newton_step(cp, V, ne, np_, Se, Sp, dt, max_newton, newton_tol)
         if ok:
-            floor = -1e-12 * max(np.abs(ne).max(), np.abs(np_).max())
-            ok = ne.min() >= floor and np_.min() >= floor
+            un = (slice(None), slice(1, -1))
+            ok = (ne[un].min() >= -1e-10 * np.abs(ne[un]).mean()
+                  and np_[un].min() >= -1e-10 * np.abs(np_[un]).mean())
         if not ok:
             V[:], ne[:], np_[:] = s0
             rej += 1
-            dt *= 0.5
+            dt = dt_acc if (dt_acc > 0 and dt > dt_acc) else 0.5 * dt
             if rej > 200:
                 raise RuntimeError("too many rejected steps")
             continue
@@ -173,6 +177,7 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
                  np.linalg.norm((np_ - s0[2])[:, 1:-1]) / np.linalg.norm(np_[:, 1:-1]))
         if log is not None:
             log.append((acc, dt, its, ch))
+        dt_acc = dt
         if dts is None and ch < tol:
             break
         dt = min(growth * dt, dt_max)

@@ -12,13 +12,17 @@
 
 #include "mg_internal.h"
 
+namespace {
+constexpr int kMaxKrylovDesc = 40;
+}
+
 using namespace mgf;
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
 
-int fail(int code, const char *fmt, ...) {
+int mgf::fail(int code, const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof g_err, fmt, ap);
@@ -26,30 +30,7 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIP_OK(call)                                                                   \
-    do {                                                                               \
-        hipError_t e_ = (call);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(MG_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
-    } while (0)
-
-constexpr int64_t kAlign = 256;
-
-int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
-// Bump allocator over the caller's workspace; with base == nullptr it only
-// measures.
-struct Carver {
-    char *base;
-    int64_t off = 0;
-    template <class T>
-    T *take(int64_t count) {
-        off = round_up(off, kAlign);
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += count * (int64_t)sizeof(T);
-        return p;
-    }
-};
+namespace {
 
 int64_t level_pitch(int nz) { return round_up(nz + 1, 16); }
 
@@ -82,6 +63,8 @@ int validate(const mg_grid_desc *d) {
     if (nl < 1 || nl > kMaxLevels)
         return fail(MG_EINVAL, "grid %dx%d cannot be coarsened to %d by halving", d->nr, d->nz, d->coarsest_n);
     if (d->nz - 1 > 64 * 16) return fail(MG_EINVAL, "nz = %d exceeds the z-line limit 1025", d->nz);
+    if (d->krylov_m < 0 || d->krylov_m > kMaxKrylovDesc)
+        return fail(MG_EINVAL, "krylov_m = %d outside 0..%d", d->krylov_m, kMaxKrylovDesc);
     int nrc = d->nr >> (nl - 1), nzc = d->nz >> (nl - 1);
     if ((nrc + 1) * (nzc - 1) > kMaxCoarseUnknowns)
         return fail(MG_EINVAL, "coarsest grid has %d unknowns (limit %d)", (nrc + 1) * (nzc - 1),
@@ -94,22 +77,6 @@ int validate(const mg_grid_desc *d) {
 }
 
 }  // namespace
-
-struct mg_ctx {
-    mg_grid_desc desc;
-    std::vector<double> zhost;
-    int nlev = 0;
-    Level lev[kMaxLevels];
-    hipStream_t stream = nullptr;
-    double *partials = nullptr;  // residual-kernel block sums
-    double *scal = nullptr;      // device scalars
-    double *coarse_scratch = nullptr;
-    double *pinned = nullptr;    // host-pinned readback
-    double *nk_copy = nullptr;   // spare level-0 field
-    double *spare[4] = {nullptr, nullptr, nullptr, nullptr};
-    bool assembled[3] = {false, false, false};
-    int64_t vcycles = 0;
-};
 
 namespace {
 
@@ -179,16 +146,15 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
     int nblk = ((d->nz + 1 + 63) / 64) * ((d->nr + 1 + 3) / 4);
     double *part = cv.take<double>(2 * (int64_t)nblk + 16);
     double *scal = cv.take<double>(64);
-    double *nk = cv.take<double>(nf0);
     double *sp[4];
     for (int t = 0; t < 4; ++t) sp[t] = cv.take<double>(nf0);
     if (c) {
         c->partials = part;
         c->scal = scal;
-        c->nk_copy = nk;
         for (int t = 0; t < 4; ++t) c->spare[t] = sp[t];
         c->nlev = nl;
     }
+    carve_newton(c, d, cv, nl);
     return round_up(cv.off, kAlign);
 }
 
@@ -361,7 +327,7 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     c->desc.z_host = c->zhost.data();
     c->stream = reinterpret_cast<hipStream_t>(stream);
     carve(c, desc, reinterpret_cast<char *>(workspace));
-    hipError_t e = hipHostMalloc((void **)&c->pinned, 64 * sizeof(double), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
         return fail(MG_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
@@ -534,13 +500,8 @@ int mg_residual(mg_ctx *c, int eq, const double *x, double *r) {
     return MG_OK;
 }
 
-int implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
-                  mg_report *rep) {
-    if (int e = check_ctx(c)) return e;
-    if (!ph || !st || !sc) return fail(MG_EINVAL, "null physics, state or schedule");
-    if (!(dt > 0)) return fail(MG_EINVAL, "dt must be positive");
-    if (sc->coupling != MG_COUPLE_DECOUPLED)
-        return fail(MG_EINVAL, "coupling %d not available in implicit_step", sc->coupling);
+static int decoupled_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
+                          mg_report *rep) {
     int total = 0, cyc = 0;
     double rr = 0, worst = 0;
     // Poisson with the densities of step k
@@ -567,11 +528,70 @@ int implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, cons
     return MG_OK;
 }
 
+int implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
+                  mg_report *rep) {
+    if (int e = check_ctx(c)) return e;
+    if (!ph || !st || !sc) return fail(MG_EINVAL, "null physics, state or schedule");
+    if (!st->V || !st->ne || !st->np) return fail(MG_EINVAL, "state needs V, ne and np");
+    if (!(dt > 0)) return fail(MG_EINVAL, "dt must be positive");
+    if (sc->coupling == MG_COUPLE_DECOUPLED) return decoupled_step(c, ph, st, dt, sc, rep);
+    if (sc->coupling != MG_COUPLE_NEWTON) return fail(MG_EINVAL, "bad coupling %d", sc->coupling);
+    if (!st->Se || !st->Sp) return fail(MG_EINVAL, "the Newton step needs both sources");
+    bool conv = false;
+    int e = newton_implicit_step(c, ph, st, dt, sc, rep, &conv);
+    if (e) return e;
+    if (!conv) return fail(MG_ENOCONV, "Newton did not converge in %d iterations", sc->max_newton);
+    return MG_OK;
+}
+
 int solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep) {
     if (int e = check_ctx(c)) return e;
     if (!ph || !st || !sc) return fail(MG_EINVAL, "null physics, state or schedule");
-    (void)rep;
-    return fail(MG_EINVAL, "solve_steady: not built yet");
+    if (!st->V || !st->ne || !st->np || !st->Se || !st->Sp) return fail(MG_EINVAL, "incomplete state");
+    if (!(sc->dt0 > 0) || !(sc->growth >= 1.0) || !(sc->dt_max >= sc->dt0))
+        return fail(MG_EINVAL, "bad time-step schedule");
+    if (sc->coupling == MG_COUPLE_NEWTON) return newton_solve_steady(c, ph, st, sc, rep);
+    if (sc->coupling != MG_COUPLE_DECOUPLED) return fail(MG_EINVAL, "bad coupling %d", sc->coupling);
+    // decoupled steps (stable only while dt stays below the dielectric
+    // relaxation time); no rejection logic beyond solver failure
+    mg_report local;
+    memset(&local, 0, sizeof local);
+    mg_report *R = rep ? rep : &local;
+    memset(R, 0, sizeof *R);
+    auto t0 = std::chrono::steady_clock::now();
+    double dt = sc->dt0;
+    int64_t p0 = (int64_t)(c->lev[0].g.nr + 1) * c->lev[0].g.pitch;
+    int status = MG_ENOCONV;
+    while (R->steps < sc->max_steps) {
+        launch_copy_field(c->lev[0].g, st->ne, c->spare[0], c->stream);
+        launch_copy_field(c->lev[0].g, st->np, c->spare[1], c->stream);
+        int e = decoupled_step(c, ph, st, dt, sc, R);
+        if (e) return e;
+        R->t_end += dt;
+        int nb = 0;
+        launch_diff_norms(c->lev[0].g, st->ne, c->spare[0], c->partials, &nb, c->stream);
+        launch_sum_partials(c->partials, nb, 2, c->scal, c->stream);
+        launch_diff_norms(c->lev[0].g, st->np, c->spare[1], c->partials, &nb, c->stream);
+        launch_sum_partials(c->partials, nb, 2, c->scal + 2, c->stream);
+        HIP_OK(hipMemcpyAsync(c->pinned, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        const double *o = c->pinned;
+        double ch = fmax(sqrt(o[0] / fmax(o[1], 1e-300)), sqrt(o[2] / fmax(o[3], 1e-300)));
+        R->last_change = ch;
+        if (!isfinite(ch)) {
+            status = fail(MG_ENONFINITE, "density change is not finite");
+            break;
+        }
+        if (ch < sc->steady_tol) {
+            status = MG_OK;
+            break;
+        }
+        dt = fmin(sc->growth * dt, sc->dt_max);
+    }
+    (void)p0;
+    R->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (status == MG_ENOCONV) fail(MG_ENOCONV, "not steady after %d steps", R->steps);
+    return status;
 }
 
 int prolong_state(mg_ctx *coarse, const mg_state *src, mg_ctx *fine, mg_state *dst, const mg_physics *ph) {

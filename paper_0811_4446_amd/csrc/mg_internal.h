@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/mgfluid.h"
 
 namespace mgf {
@@ -77,4 +79,75 @@ void launch_add_f32(const Geom &g, double *x, const float *e, hipStream_t s);
 void launch_op_to_f32(const Geom &g, Op<double> op, Op<float> o32, hipStream_t s);
 void launch_prolong_state(const Geom &gf, double *xf, const Geom &gc, const double *xc, hipStream_t s);
 
+int fail(int code, const char *fmt, ...);
+
+#define HIP_OK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::mgf::fail(MG_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t kAlign = 256;
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Carver {
+    char *base;
+    int64_t off = 0;
+    template <class T>
+    T *take(int64_t count) {
+        off = round_up(off, kAlign);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * (int64_t)sizeof(T);
+        return p;
+    }
+};
+
+// Per-level storage of the coupled (3x3-block) Newton path.
+struct BLevel {
+    double *J;      // kBPlanes planes
+    double *x, *r;  // 3-field correction and residual
+    double *st;     // injected state (V, ne, np), levels >= 1
+    double *cinvT;  // coarsest level: transposed inverse of the block matrix
+};
+
+struct NewtonWork {
+    int m = 0;                 // FGMRES restart length (0: path disabled)
+    BLevel lev[kMaxLevels];
+    double *V = nullptr;       // Krylov basis, (m+1) 3-field vectors
+    double *Z = nullptr;       // preconditioned directions, m vectors
+    double *w = nullptr;       // work vector
+    double *delta = nullptr;   // Newton correction
+    double *snap = nullptr;    // state at the start of the step (V, ne, np)
+    double *partials = nullptr;
+    double *dev = nullptr;     // device scalars (dots, norms, y)
+    double *scratch = nullptr; // coarsest factorisation workspace
+};
+
+}  // namespace mgf
+
+struct mg_ctx {
+    mg_grid_desc desc;
+    std::vector<double> zhost;
+    int nlev = 0;
+    mgf::Level lev[mgf::kMaxLevels];
+    hipStream_t stream = nullptr;
+    double *partials = nullptr;  // residual-kernel block sums
+    double *scal = nullptr;      // device scalars
+    double *coarse_scratch = nullptr;
+    double *pinned = nullptr;    // host-pinned readback
+    double *spare[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool assembled[3] = {false, false, false};
+    int64_t vcycles = 0;
+    mgf::NewtonWork nw;
+};
+
+namespace mgf {
+// Newton path (mg_newton_host.hip)
+void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl);
+int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
+                         mg_report *rep, bool *converged);
+int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep);
 }  // namespace mgf

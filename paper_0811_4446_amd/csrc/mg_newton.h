@@ -1,0 +1,48 @@
+// Declarations of the coupled Newton (3x3-block) path.
+#pragma once
+#include "mg_internal.h"
+
+namespace mgf {
+
+constexpr int kMaxKrylov = 40;
+constexpr int kBPlanes = 30;
+constexpr int kEE = 0, kEV = 5, kPP = 10, kPV = 15, kVV = 20, kVe = 25, kVp = 26, kFe = 27, kFp = 28, kFV = 29;
+
+// Block operator: kBPlanes planes of (nr+1) x pitch doubles.
+struct BOp {
+    double *base;
+    int64_t plane;
+    __host__ __device__ double *pl(int k) const { return base + (int64_t)k * plane; }
+};
+
+struct NewtonPhys {
+    double qe, qp;   // -s mu / D for electrons (s = -1) and ions (s = +1)
+    double De, Dp, k, dt_inv;
+};
+
+void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
+                            const double *nek, const double *npk, const double *Se, const double *Sp,
+                            const NewtonPhys &ph, bool with_rhs, hipStream_t s);
+void launch_block_rbgs(const Geom &g, const BOp &J, const double *f, double *x, int colour, hipStream_t s);
+void launch_block_residual(const Geom &g, const BOp &J, const double *f, const double *x, double *r, bool apply,
+                           hipStream_t s);
+void launch_restrict3(const Geom &gf, const double *rf, int64_t pf, const Geom &gc, double *fc, int64_t pc,
+                      hipStream_t s);
+void launch_prolong3(const Geom &gf, double *xf, int64_t pf, const Geom &gc, const double *xc, int64_t pc,
+                     hipStream_t s);
+void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
+                    double *out, int64_t pc, hipStream_t s);
+void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s);
+void launch_block_coarse_solve(const Geom &g, const BOp &J, const double *f, const double *invT, double *x,
+                               hipStream_t s);
+int block_vec_blocks(const Geom &g);
+void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
+                       int64_t plane, double3 cw, double *partials, double *out, hipStream_t s);
+void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
+                       const double *h, double sign, hipStream_t s);
+void launch_scale_by_norm(const Geom &g, const double *src, double *dst, int64_t plane, const double *nrm2,
+                          hipStream_t s);
+void launch_newton_update(const Geom &g, double *V, double *ne, double *np, const double *du, int64_t plane,
+                          double *partials, double *out, hipStream_t s);
+
+}  // namespace mgf

@@ -1,0 +1,593 @@
+// Coupled Newton-Raphson path (Sec. 2, Eq. 14): the 3x3-block five-point
+// Jacobian of the backward-Euler system in u = (n_e, n_p, V), its block
+// multigrid (collective red-black Gauss-Seidel: the three unknowns of a
+// node are relaxed together), and the BLAS-1 kernels of the FGMRES solver
+// it preconditions.  FP64 throughout.
+//
+// Block coefficient planes (each (nr+1) x pitch, FV-integrated rows):
+//   kind*5 + w   kind: 0 ee, 1 eV, 2 pp, 3 pV, 4 VV;  w: 0 a (i-1), 1 b
+//                (centre), 2 c (i+1), 3 d (j-1), 4 e (j+1)
+//   25 Ve, 26 Vp (centre couplings of the Poisson row to the densities)
+//   27..29  right-hand side of the e, p and V rows
+// A 3-field vector is three consecutive planes (n_e, n_p, V).
+#include <math.h>
+
+#include "mg_newton.h"
+
+namespace mgf {
+
+namespace {
+
+constexpr int kTX = 64;
+constexpr int kTY = 4;
+
+inline dim3 grid2d(const Geom &g) { return dim3((g.nz + 1 + kTX - 1) / kTX, (g.nr + 1 + kTY - 1) / kTY); }
+inline __device__ int64_t at(const Geom &g, int i, int j) { return (int64_t)i * g.pitch + j; }
+
+inline __device__ double bF(double x) {
+    if (fabs(x) < 1e-3) {
+        double x2 = x * x;
+        return 1.0 - 0.5 * x + x2 * (1.0 / 12.0) - x2 * x2 * (1.0 / 720.0);
+    }
+    return x / expm1(x);
+}
+
+// F'(x) = F(x) (1 - G(x)) / x with G(x) = F(-x); for |x| < 0.1 the Taylor
+// series from the Bernoulli numbers (the closed form cancels there).
+inline __device__ double bdF(double x) {
+    if (fabs(x) < 0.1) {
+        double x2 = x * x;
+        return -0.5 + x * (1.0 / 6.0 + x2 * (-1.0 / 180.0 + x2 * (1.0 / 5040.0 +
+                     x2 * (-1.0 / 151200.0 + x2 * (1.0 / 4790016.0)))));
+    }
+    return bF(x) * (1.0 - bF(-x)) / x;
+}
+
+struct Face {
+    double nb_n, c_n;   // neighbour coefficient and centre contribution (density column)
+    double nb_V, c_V;   // same for the potential column
+};
+
+// Face between the centre node and a neighbour.  `plus` = neighbour in +r/+z.
+// q = -s mu/D, gd = area * D / distance.
+inline __device__ Face sg_face(bool plus, double q, double gd, double Vc, double Vn, double nc, double nn) {
+    Face f;
+    if (plus) {  // outward flux gd (nc G(al) - nn F(al)), al = q (Vn - Vc)
+        double al = q * (Vn - Vc);
+        double F = bF(al), G = bF(-al), dF = bdF(al);
+        f.nb_n = -gd * F;
+        f.c_n = gd * G;
+        double sl = gd * ((dF + 1.0) * nc - dF * nn);
+        f.nb_V = q * sl;
+        f.c_V = -q * sl;
+    } else {     // outward flux gd (nc F(al) - nn G(al)), al = q (Vc - Vn)
+        double al = q * (Vc - Vn);
+        double F = bF(al), G = bF(-al), dF = bdF(al);
+        f.nb_n = -gd * G;
+        f.c_n = gd * F;
+        double sl = gd * (dF * nc - (dF + 1.0) * nn);
+        f.nb_V = -q * sl;
+        f.c_V = q * sl;
+    }
+    return f;
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian (Eq. 14) and Newton right-hand side -F at the state (V, ne, np).
+// Continuity rows: F = sum over faces area*phi_out + vol (n - n^k)/dt - vol S
+// (Eqs. 7-11); Poisson row: F = A_P V - vol k (n_p - n_e) (Eqs. 12-13).
+// ---------------------------------------------------------------------------
+__global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, const double *__restrict__ ne,
+                                  const double *__restrict__ np, const double *__restrict__ nek,
+                                  const double *__restrict__ npk, const double *__restrict__ Se,
+                                  const double *__restrict__ Sp, NewtonPhys ph, int with_rhs) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    int64_t p = at(g, i, j);
+    if (j == 0 || j == g.nz) {
+        for (int k = 0; k < kBPlanes; ++k) J.pl(k)[p] = 0.0;
+        return;
+    }
+    double w = g.wr[i], dzc = g.dzc[j], vol = w * dzc;
+    double Vc = V[p], ec = ne[p], pc = np[p];
+    double ee[5] = {0, 0, 0, 0, 0}, eV[5] = {0, 0, 0, 0, 0}, pp[5] = {0, 0, 0, 0, 0}, pV[5] = {0, 0, 0, 0, 0},
+           VV[5] = {0, 0, 0, 0, 0};
+    int64_t nbp[5] = {p - g.pitch, p, p + g.pitch, p - 1, p + 1};
+    bool has[5] = {i > 0, false, i < g.nr, true, true};
+    double geo[5];
+    geo[0] = (i > 0) ? g.fr[i - 1] * dzc / g.dr : 0.0;
+    geo[2] = (i < g.nr) ? g.fr[i] * dzc / g.dr : 0.0;
+    geo[3] = w / g.dz[j - 1];
+    geo[4] = w / g.dz[j];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        if (d == 1 || !has[d]) continue;
+        bool plus = (d == 2 || d == 4);
+        int64_t q = nbp[d];
+        double Vn = V[q];
+        Face fe = sg_face(plus, ph.qe, geo[d] * ph.De, Vc, Vn, ec, ne[q]);
+        Face fp = sg_face(plus, ph.qp, geo[d] * ph.Dp, Vc, Vn, pc, np[q]);
+        ee[d] = fe.nb_n;
+        ee[1] += fe.c_n;
+        eV[d] = fe.nb_V;
+        eV[1] += fe.c_V;
+        pp[d] = fp.nb_n;
+        pp[1] += fp.c_n;
+        pV[d] = fp.nb_V;
+        pV[1] += fp.c_V;
+        VV[d] = -geo[d];
+        VV[1] += geo[d];
+    }
+    ee[1] += vol * ph.dt_inv;
+    pp[1] += vol * ph.dt_inv;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        J.pl(kEE + d)[p] = ee[d];
+        J.pl(kEV + d)[p] = eV[d];
+        J.pl(kPP + d)[p] = pp[d];
+        J.pl(kPV + d)[p] = pV[d];
+        J.pl(kVV + d)[p] = VV[d];
+    }
+    double kv = vol * ph.k;
+    J.pl(kVe)[p] = kv;
+    J.pl(kVp)[p] = -kv;
+    if (with_rhs) {
+        double Fe = ee[1] * ec - vol * (Se[p] + nek[p] * ph.dt_inv);
+        double Fp = pp[1] * pc - vol * (Sp[p] + npk[p] * ph.dt_inv);
+        double FV = VV[1] * Vc - kv * (pc - ec);
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            if (d == 1 || !has[d]) continue;
+            int64_t q = nbp[d];
+            Fe += ee[d] * ne[q];
+            Fp += pp[d] * np[q];
+            FV += VV[d] * V[q];
+        }
+        J.pl(kFe)[p] = -Fe;
+        J.pl(kFp)[p] = -Fp;
+        J.pl(kFV)[p] = -FV;
+    } else {
+        J.pl(kFe)[p] = 0.0;
+        J.pl(kFp)[p] = 0.0;
+        J.pl(kFV)[p] = 0.0;
+    }
+}
+
+// Sum over the four neighbours of B_nb x_nb for the three rows.
+inline __device__ void nb_sum(const Geom &g, const BOp &J, const double *x, int64_t plane, int i, int64_t p,
+                              double &se, double &sp, double &sv) {
+    const double *xe = x, *xp = x + plane, *xv = x + 2 * plane;
+    int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
+    int dirs[4] = {0, 2, 3, 4};
+    bool has[4] = {i > 0, i < g.nr, true, true};
+    se = sp = sv = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (!has[t]) continue;
+        int d = dirs[t];
+        int64_t q = nbp[t];
+        double v = xv[q];
+        se += J.pl(kEE + d)[p] * xe[q] + J.pl(kEV + d)[p] * v;
+        sp += J.pl(kPP + d)[p] * xp[q] + J.pl(kPV + d)[p] * v;
+        sv += J.pl(kVV + d)[p] * v;
+    }
+}
+
+// Collective red-black Gauss-Seidel half-sweep: at every node of the colour
+// the 3x3 centre block is solved exactly for (n_e, n_p, V) with the
+// neighbours held fixed.  The block [[ee,0,eV],[0,pp,pV],[Ve,Vp,VV]] is
+// reduced to the potential first.
+__global__ void k_block_rbgs(Geom g, BOp J, const double *__restrict__ f, double *__restrict__ x, int colour) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > g.nr || j < 1 || j >= g.nz || ((i + j) & 1) != colour) return;
+    int64_t p = at(g, i, j);
+    int64_t plane = J.plane;
+    double se, sp, sv;
+    nb_sum(g, J, x, plane, i, p, se, sp, sv);
+    double re = f[p] - se, rp = f[p + plane] - sp, rv = f[p + 2 * plane] - sv;
+    double ee = J.pl(kEE + 1)[p], eV = J.pl(kEV + 1)[p], pp = J.pl(kPP + 1)[p], pV = J.pl(kPV + 1)[p];
+    double VV = J.pl(kVV + 1)[p], Ve = J.pl(kVe)[p], Vp = J.pl(kVp)[p];
+    double a = Ve / ee, b = Vp / pp;
+    double xv = (rv - a * re - b * rp) / (VV - a * eV - b * pV);
+    x[p] = (re - eV * xv) / ee;
+    x[p + plane] = (rp - pV * xv) / pp;
+    x[p + 2 * plane] = xv;
+}
+
+// r = f - B x (apply == 0) or r = B x (apply == 1), 3 fields, 0 on electrodes.
+__global__ void k_block_residual(Geom g, BOp J, const double *__restrict__ f, const double *__restrict__ x,
+                                 double *__restrict__ r, int apply) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    int64_t p = at(g, i, j), plane = J.plane;
+    if (j == 0 || j == g.nz) {
+        r[p] = r[p + plane] = r[p + 2 * plane] = 0.0;
+        return;
+    }
+    double se, sp, sv;
+    nb_sum(g, J, x, plane, i, p, se, sp, sv);
+    double xe = x[p], xp = x[p + plane], xv = x[p + 2 * plane];
+    se += J.pl(kEE + 1)[p] * xe + J.pl(kEV + 1)[p] * xv;
+    sp += J.pl(kPP + 1)[p] * xp + J.pl(kPV + 1)[p] * xv;
+    sv += J.pl(kVV + 1)[p] * xv + J.pl(kVe)[p] * xe + J.pl(kVp)[p] * xp;
+    if (apply) {
+        r[p] = se;
+        r[p + plane] = sp;
+        r[p + 2 * plane] = sv;
+    } else {
+        r[p] = f[p] - se;
+        r[p + plane] = f[p + plane] - sp;
+        r[p + 2 * plane] = f[p + 2 * plane] - sv;
+    }
+}
+
+// Three-field restriction (P^T of the bilinear prolongation), same weights
+// as the scalar path.
+__global__ void k_restrict3(Geom gf, const double *__restrict__ rf, int64_t pf, Geom gc, double *__restrict__ fc,
+                            int64_t pc) {
+    int J_ = blockIdx.x * kTX + threadIdx.x;
+    int I = blockIdx.y * kTY + threadIdx.y;
+    if (I > gc.nr || J_ > gc.nz) return;
+    int64_t q = at(gc, I, J_);
+    if (J_ == 0 || J_ == gc.nz) {
+        fc[q] = fc[q + pc] = fc[q + 2 * pc] = 0.0;
+        return;
+    }
+    double wdn = 1.0 - gf.wl[J_ - 1], wup = gf.wl[J_];
+    double acc[3] = {0, 0, 0};
+    for (int di = -1; di <= 1; ++di) {
+        int i = 2 * I + di;
+        if (i < 0 || i > gf.nr) continue;
+        double wi = (di == 0) ? 1.0 : 0.5;
+        int64_t p = at(gf, i, 2 * J_);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const double *r = rf + f * pf;
+            acc[f] += wi * (wdn * r[p - 1] + r[p] + wup * r[p + 1]);
+        }
+    }
+    fc[q] = acc[0];
+    fc[q + pc] = acc[1];
+    fc[q + 2 * pc] = acc[2];
+}
+
+__global__ void k_prolong3(Geom gf, double *__restrict__ xf, int64_t pf, Geom gc, const double *__restrict__ xc,
+                           int64_t pc) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > gf.nr || j < 1 || j >= gf.nz) return;
+    int I0 = i >> 1, I1 = (i + 1) >> 1;
+    int64_t p = at(gf, i, j);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const double *c = xc + f * pc;
+        double v0, v1;
+        if ((j & 1) == 0) {
+            v0 = c[at(gc, I0, j >> 1)];
+            v1 = c[at(gc, I1, j >> 1)];
+        } else {
+            int J_ = j >> 1;
+            double wl = gf.wl[J_], wu = 1.0 - wl;
+            v0 = wl * c[at(gc, I0, J_)] + wu * c[at(gc, I0, J_ + 1)];
+            v1 = wl * c[at(gc, I1, J_)] + wu * c[at(gc, I1, J_ + 1)];
+        }
+        xf[p + f * pf] += (i & 1) ? 0.5 * (v0 + v1) : v0;
+    }
+}
+
+__global__ void k_inject3(Geom gf, const double *__restrict__ V, const double *__restrict__ ne,
+                          const double *__restrict__ np, Geom gc, double *__restrict__ out, int64_t pc) {
+    int J_ = blockIdx.x * kTX + threadIdx.x;
+    int I = blockIdx.y * kTY + threadIdx.y;
+    if (I > gc.nr || J_ > gc.nz) return;
+    int64_t q = at(gc, I, J_), p = at(gf, 2 * I, 2 * J_);
+    out[q] = V[p];
+    out[q + pc] = ne[p];
+    out[q + 2 * pc] = np[p];
+}
+
+// Coarsest grid: explicit inverse of the dense block matrix (Gauss-Jordan,
+// partial pivoting, one workgroup); unknown (i, j, field) has index
+// 3*(i*(nz-1) + j-1) + field.  Stored transposed.
+__global__ __launch_bounds__(1024) void k_block_coarse_factor(Geom g, BOp J, double *__restrict__ M,
+                                                              double *__restrict__ invT) {
+    const int m = g.nz - 1;
+    const int n = 3 * (g.nr + 1) * m;
+    const int n2 = 2 * n;
+    for (int64_t t = threadIdx.x; t < (int64_t)n * n2; t += blockDim.x) M[t] = 0.0;
+    __syncthreads();
+    for (int node = threadIdx.x; node < (g.nr + 1) * m; node += blockDim.x) {
+        int i = node / m, j = node % m + 1;
+        int64_t p = at(g, i, j);
+        int rowb = 3 * node;
+        int nbnode[5] = {node - m, node, node + m, node - 1, node + 1};
+        bool has[5] = {i > 0, true, i < g.nr, j > 1, j < m};
+        for (int d = 0; d < 5; ++d) {
+            if (!has[d]) continue;
+            int colb = 3 * nbnode[d];
+            M[(int64_t)(rowb + 0) * n2 + colb + 0] = J.pl(kEE + d)[p];
+            M[(int64_t)(rowb + 0) * n2 + colb + 2] = J.pl(kEV + d)[p];
+            M[(int64_t)(rowb + 1) * n2 + colb + 1] = J.pl(kPP + d)[p];
+            M[(int64_t)(rowb + 1) * n2 + colb + 2] = J.pl(kPV + d)[p];
+            M[(int64_t)(rowb + 2) * n2 + colb + 2] = J.pl(kVV + d)[p];
+        }
+        M[(int64_t)(rowb + 2) * n2 + rowb + 0] = J.pl(kVe)[p];
+        M[(int64_t)(rowb + 2) * n2 + rowb + 1] = J.pl(kVp)[p];
+        for (int f = 0; f < 3; ++f) M[(int64_t)(rowb + f) * n2 + n + rowb + f] = 1.0;
+    }
+    __syncthreads();
+    __shared__ int piv;
+    __shared__ double fcol[3 * kMaxCoarseUnknowns];
+    for (int col = 0; col < n; ++col) {
+        if (threadIdx.x == 0) {
+            int best = col;
+            double bv = fabs(M[(int64_t)col * n2 + col]);
+            for (int rr = col + 1; rr < n; ++rr) {
+                double v = fabs(M[(int64_t)rr * n2 + col]);
+                if (v > bv) {
+                    bv = v;
+                    best = rr;
+                }
+            }
+            piv = best;
+        }
+        __syncthreads();
+        const int pv = piv;
+        if (pv != col)
+            for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+                double tmp = M[(int64_t)col * n2 + t];
+                M[(int64_t)col * n2 + t] = M[(int64_t)pv * n2 + t];
+                M[(int64_t)pv * n2 + t] = tmp;
+            }
+        __syncthreads();
+        const double pinv = 1.0 / M[(int64_t)col * n2 + col];
+        __syncthreads();
+        for (int t = threadIdx.x; t < n2; t += blockDim.x) M[(int64_t)col * n2 + t] *= pinv;
+        for (int rr = threadIdx.x; rr < n; rr += blockDim.x) fcol[rr] = M[(int64_t)rr * n2 + col];
+        __syncthreads();
+        for (int64_t t = threadIdx.x; t < (int64_t)n * n2; t += blockDim.x) {
+            int rr = (int)(t / n2), cc = (int)(t % n2);
+            if (rr == col) continue;
+            double fct = fcol[rr];
+            if (fct != 0.0) M[(int64_t)rr * n2 + cc] -= fct * M[(int64_t)col * n2 + cc];
+        }
+        __syncthreads();
+    }
+    for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
+        int row = (int)(t / n), k = (int)(t % n);
+        invT[(int64_t)k * n + row] = M[(int64_t)row * n2 + n + k];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOp J, const double *__restrict__ f,
+                                                             const double *__restrict__ invT,
+                                                             double *__restrict__ x) {
+    const int m = g.nz - 1;
+    const int nn = (g.nr + 1) * m;
+    const int n = 3 * nn;
+    __shared__ double rhs[3 * kMaxCoarseUnknowns];
+    for (int node = threadIdx.x; node < nn; node += blockDim.x) {
+        int i = node / m, j = node % m + 1;
+        int64_t p = at(g, i, j);
+        rhs[3 * node + 0] = f[p];
+        rhs[3 * node + 1] = f[p + J.plane];
+        rhs[3 * node + 2] = f[p + 2 * J.plane];
+    }
+    __syncthreads();
+    for (int row = threadIdx.x; row < n; row += blockDim.x) {
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += invT[(int64_t)k * n + row] * rhs[k];
+        int node = row / 3, f = row % 3;
+        int i = node / m, j = node % m + 1;
+        x[at(g, i, j) + f * J.plane] = acc;
+    }
+}
+
+// ---- FGMRES BLAS-1 (weighted inner product) ----
+// <u, v>_W = sum over unknown nodes and fields of u v (c_f / vol)^2.
+__global__ __launch_bounds__(256) void k_wdot_multi(Geom g, const double *__restrict__ w,
+                                                     const double *__restrict__ basis, int64_t vstride, int nv,
+                                                     int64_t plane, double3 cw, double *__restrict__ partials) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    __shared__ double sh[kTY][kMaxKrylov + 1];
+    bool ok = i <= g.nr && j >= 1 && j < g.nz;
+    int64_t p = ok ? at(g, i, j) : 0;
+    double iv = ok ? 1.0 / (g.wr[i] * g.dzc[j]) : 0.0;
+    double we = ok ? w[p] * cw.x * cw.x * iv * iv : 0.0;
+    double wp = ok ? w[p + plane] * cw.y * cw.y * iv * iv : 0.0;
+    double wv = ok ? w[p + 2 * plane] * cw.z * cw.z * iv * iv : 0.0;
+    for (int v = 0; v < nv; ++v) {
+        const double *b = basis + v * vstride;
+        double s = ok ? (we * b[p] + wp * b[p + plane] + wv * b[p + 2 * plane]) : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
+    }
+    __syncthreads();
+    int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    int t = threadIdx.y * kTX + threadIdx.x;
+    if (t < nv) {
+        double s = 0.0;
+        for (int y = 0; y < kTY; ++y) s += sh[y][t];
+        partials[(int64_t)blk * nv + t] = s;
+    }
+}
+
+// out[c] = sum over blocks of partials[b*ncomp + c], fixed order (one
+// workgroup per component).
+__global__ __launch_bounds__(256) void k_sum_cols(const double *__restrict__ part, int nblocks, int ncomp,
+                                                   double *__restrict__ out) {
+    int c = blockIdx.x;
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) acc += part[(int64_t)b * ncomp + c];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sh[0];
+}
+
+// w = alpha * (w - sum_v h[v] basis_v)   (alpha = 1, or 1/h_next on demand)
+__global__ void k_axpy_multi(Geom g, double *__restrict__ w, const double *__restrict__ basis, int64_t vstride,
+                             int nv, int64_t plane, const double *__restrict__ h, double sign) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > g.nr || j < 1 || j >= g.nz) return;
+    int64_t p = at(g, i, j);
+    for (int f = 0; f < 3; ++f) {
+        int64_t q = p + f * plane;
+        double acc = w[q];
+        for (int v = 0; v < nv; ++v) acc += sign * h[v] * basis[v * vstride + q];
+        w[q] = acc;
+    }
+}
+
+// dst = src * (1 / sqrt(*nrm2))
+__global__ void k_scale_by_norm(Geom g, const double *__restrict__ src, double *__restrict__ dst, int64_t plane,
+                                const double *__restrict__ nrm2) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    int64_t p = at(g, i, j);
+    double s = 1.0 / sqrt(*nrm2);
+    bool un = j >= 1 && j < g.nz;
+    for (int f = 0; f < 3; ++f) dst[p + f * plane] = un ? src[p + f * plane] * s : 0.0;
+}
+
+// Newton update u += du on the unknown nodes, with per-block sums of
+// |du_f| and |u_f| (l1) and the minima of the densities.
+__global__ __launch_bounds__(256) void k_newton_update(Geom g, double *__restrict__ V, double *__restrict__ ne,
+                                                        double *__restrict__ np, const double *__restrict__ du,
+                                                        int64_t plane, double *__restrict__ partials) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    double s[8] = {0, 0, 0, 0, 0, 0, 1e300, 1e300};
+    if (i <= g.nr && j >= 1 && j < g.nz) {
+        int64_t p = at(g, i, j);
+        double de = du[p], dp = du[p + plane], dv = du[p + 2 * plane];
+        double a = ne[p] + de, b = np[p] + dp, c = V[p] + dv;
+        ne[p] = a;
+        np[p] = b;
+        V[p] = c;
+        s[0] = fabs(de);
+        s[1] = fabs(a);
+        s[2] = fabs(dp);
+        s[3] = fabs(b);
+        s[4] = fabs(dv);
+        s[5] = fabs(c);
+        s[6] = a;
+        s[7] = b;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] += __shfl_xor(s[k], off);
+        s[6] = fmin(s[6], __shfl_xor(s[6], off));
+        s[7] = fmin(s[7], __shfl_xor(s[7], off));
+    }
+    __shared__ double sh[kTY][8];
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 8; ++k) sh[threadIdx.y][k] = s[k];
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        double o[8] = {0, 0, 0, 0, 0, 0, 1e300, 1e300};
+        for (int y = 0; y < kTY; ++y) {
+            for (int k = 0; k < 6; ++k) o[k] += sh[y][k];
+            o[6] = fmin(o[6], sh[y][6]);
+            o[7] = fmin(o[7], sh[y][7]);
+        }
+        int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        for (int k = 0; k < 8; ++k) partials[(int64_t)blk * 8 + k] = o[k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_newton(const double *__restrict__ part, int nblocks,
+                                                        double *__restrict__ out) {
+    __shared__ double sh[8][256];
+    double o[8] = {0, 0, 0, 0, 0, 0, 1e300, 1e300};
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        for (int k = 0; k < 6; ++k) o[k] += part[(int64_t)b * 8 + k];
+        o[6] = fmin(o[6], part[(int64_t)b * 8 + 6]);
+        o[7] = fmin(o[7], part[(int64_t)b * 8 + 7]);
+    }
+    for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] = o[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+            sh[6][threadIdx.x] = fmin(sh[6][threadIdx.x], sh[6][threadIdx.x + w]);
+            sh[7][threadIdx.x] = fmin(sh[7][threadIdx.x], sh[7][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+}  // namespace
+
+static const dim3 kB2(kTX, kTY);
+
+void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
+                            const double *nek, const double *npk, const double *Se, const double *Sp,
+                            const NewtonPhys &ph, bool with_rhs, hipStream_t s) {
+    k_newton_assemble<<<grid2d(g), kB2, 0, s>>>(g, J, V, ne, np, nek, npk, Se, Sp, ph, with_rhs ? 1 : 0);
+}
+void launch_block_rbgs(const Geom &g, const BOp &J, const double *f, double *x, int colour, hipStream_t s) {
+    k_block_rbgs<<<grid2d(g), kB2, 0, s>>>(g, J, f, x, colour);
+}
+void launch_block_residual(const Geom &g, const BOp &J, const double *f, const double *x, double *r, bool apply,
+                           hipStream_t s) {
+    k_block_residual<<<grid2d(g), kB2, 0, s>>>(g, J, f, x, r, apply ? 1 : 0);
+}
+void launch_restrict3(const Geom &gf, const double *rf, int64_t pf, const Geom &gc, double *fc, int64_t pc,
+                      hipStream_t s) {
+    k_restrict3<<<grid2d(gc), kB2, 0, s>>>(gf, rf, pf, gc, fc, pc);
+}
+void launch_prolong3(const Geom &gf, double *xf, int64_t pf, const Geom &gc, const double *xc, int64_t pc,
+                     hipStream_t s) {
+    k_prolong3<<<grid2d(gf), kB2, 0, s>>>(gf, xf, pf, gc, xc, pc);
+}
+void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
+                    double *out, int64_t pc, hipStream_t s) {
+    k_inject3<<<grid2d(gc), kB2, 0, s>>>(gf, V, ne, np, gc, out, pc);
+}
+void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s) {
+    k_block_coarse_factor<<<1, 1024, 0, s>>>(g, J, scratch, invT);
+}
+void launch_block_coarse_solve(const Geom &g, const BOp &J, const double *f, const double *invT, double *x,
+                               hipStream_t s) {
+    k_block_coarse_solve<<<1, 1024, 0, s>>>(g, J, f, invT, x);
+}
+int block_vec_blocks(const Geom &g) {
+    dim3 gr = grid2d(g);
+    return (int)(gr.x * gr.y);
+}
+void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
+                       int64_t plane, double3 cw, double *partials, double *out, hipStream_t s) {
+    dim3 gr = grid2d(g);
+    k_wdot_multi<<<gr, kB2, 0, s>>>(g, w, basis, vstride, nv, plane, cw, partials);
+    k_sum_cols<<<nv, 256, 0, s>>>(partials, (int)(gr.x * gr.y), nv, out);
+}
+void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
+                       const double *h, double sign, hipStream_t s) {
+    k_axpy_multi<<<grid2d(g), kB2, 0, s>>>(g, w, basis, vstride, nv, plane, h, sign);
+}
+void launch_scale_by_norm(const Geom &g, const double *src, double *dst, int64_t plane, const double *nrm2,
+                          hipStream_t s) {
+    k_scale_by_norm<<<grid2d(g), kB2, 0, s>>>(g, src, dst, plane, nrm2);
+}
+void launch_newton_update(const Geom &g, double *V, double *ne, double *np, const double *du, int64_t plane,
+                          double *partials, double *out, hipStream_t s) {
+    dim3 gr = grid2d(g);
+    k_newton_update<<<gr, kB2, 0, s>>>(g, V, ne, np, du, plane, partials);
+    k_reduce_newton<<<1, 256, 0, s>>>(partials, (int)(gr.x * gr.y), out);
+}
+
+}  // namespace mgf

@@ -1,0 +1,381 @@
+// Host side of the coupled Newton path (Sec. 2, Eq. 14): workspace layout,
+// block V-cycle, restarted FGMRES (right preconditioned by one block
+// V-cycle, weighted inner product), Newton iteration of one backward-Euler
+// step, and the steady driver with the paper's time-step rule.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+
+#include "mg_newton.h"
+
+namespace mgf {
+
+namespace {
+
+int64_t plane_of(const Level &L) { return (int64_t)(L.g.nr + 1) * L.g.pitch; }
+
+BOp bop(mg_ctx *c, int l) { return BOp{c->nw.lev[l].J, plane_of(c->lev[l])}; }
+
+// Field weights of the inner product: Poisson rows are scaled by 1/k so that
+// all three equations are measured in density units.
+double3 field_weights(const mg_physics *ph) {
+    return make_double3(1.0, 1.0, ph->k > 0 ? 1.0 / ph->k : 1.0);
+}
+
+void block_vcycle(mg_ctx *c, int l, const double *f, double *x) {
+    hipStream_t s = c->stream;
+    const Level &L = c->lev[l];
+    BOp J = bop(c, l);
+    BLevel &B = c->nw.lev[l];
+    if (l == c->nlev - 1) {
+        launch_block_coarse_solve(L.g, J, f, B.cinvT, x, s);
+        return;
+    }
+    for (int k = 0; k < c->desc.nu1; ++k)
+        for (int col = 0; col < 2; ++col) launch_block_rbgs(L.g, J, f, x, col, s);
+    launch_block_residual(L.g, J, f, x, B.r, false, s);
+    const Level &C = c->lev[l + 1];
+    BOp Jc = bop(c, l + 1);
+    double *fc = Jc.pl(kFe);
+    launch_restrict3(L.g, B.r, plane_of(L), C.g, fc, plane_of(C), s);
+    double *xc = c->nw.lev[l + 1].x;
+    launch_fill(xc, 3 * plane_of(C), 0.0, s);
+    block_vcycle(c, l + 1, fc, xc);
+    launch_prolong3(L.g, x, plane_of(L), C.g, xc, plane_of(C), s);
+    for (int k = 0; k < c->desc.nu2; ++k)
+        for (int col = 0; col < 2; ++col) launch_block_rbgs(L.g, J, f, x, col, s);
+}
+
+// Assemble the Jacobian on every level: level 0 at the current state with
+// the Newton right-hand side; coarser levels at the injected state.
+void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt_inv) {
+    hipStream_t s = c->stream;
+    NewtonPhys np_;
+    np_.qe = ph->mu_e / ph->D_e;   // -s mu/D with s = -1
+    np_.qp = -ph->mu_p / ph->D_p;  // s = +1
+    np_.De = ph->D_e;
+    np_.Dp = ph->D_p;
+    np_.k = ph->k;
+    np_.dt_inv = dt_inv;
+    const double *snap = c->nw.snap;
+    int64_t p0 = plane_of(c->lev[0]);
+    launch_newton_assemble(c->lev[0].g, bop(c, 0), st->V, st->ne, st->np, snap + p0, snap + 2 * p0, st->Se,
+                           st->Sp, np_, true, s);
+    const double *V = st->V, *ne = st->ne, *np = st->np;
+    for (int l = 1; l < c->nlev; ++l) {
+        const Level &F = c->lev[l - 1], &C = c->lev[l];
+        int64_t pc = plane_of(C);
+        double *out = c->nw.lev[l].st;
+        launch_inject3(F.g, V, ne, np, C.g, out, pc, s);
+        V = out;
+        ne = out + pc;
+        np = out + 2 * pc;
+        launch_newton_assemble(C.g, bop(c, l), V, ne, np, nullptr, nullptr, nullptr, nullptr, np_, false, s);
+    }
+    const Level &Lc = c->lev[c->nlev - 1];
+    launch_block_coarse_factor(Lc.g, bop(c, c->nlev - 1), c->nw.scratch, c->nw.lev[c->nlev - 1].cinvT, s);
+}
+
+// Givens-rotation least squares of the Arnoldi relation (host, small).
+struct Arnoldi {
+    int m;
+    double H[kMaxKrylov + 1][kMaxKrylov];
+    double cs[kMaxKrylov], sn[kMaxKrylov], g[kMaxKrylov + 1];
+    void start(double beta) {
+        memset(g, 0, sizeof g);
+        g[0] = beta;
+    }
+    // column k is in H[0..k+1][k]; returns the residual-norm estimate
+    double add(int k) {
+        for (int i = 0; i < k; ++i) {
+            double a = H[i][k], b = H[i + 1][k];
+            H[i][k] = cs[i] * a + sn[i] * b;
+            H[i + 1][k] = -sn[i] * a + cs[i] * b;
+        }
+        double a = H[k][k], b = H[k + 1][k];
+        double r = hypot(a, b);
+        cs[k] = r > 0 ? a / r : 1.0;
+        sn[k] = r > 0 ? b / r : 0.0;
+        H[k][k] = r;
+        H[k + 1][k] = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        return fabs(g[k + 1]);
+    }
+    void solve(int k, double *y) {  // upper triangular H[0..k-1][0..k-1] y = g
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int t = i + 1; t < k; ++t) s -= H[i][t] * y[t];
+            y[i] = s / H[i][i];
+        }
+    }
+};
+
+// Solve J delta = b (b = the Newton right-hand side planes of level 0) to
+// weighted relative residual rtol.  Returns the iteration count in *its.
+int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, double *relres) {
+    hipStream_t s = c->stream;
+    NewtonWork &W = c->nw;
+    const Level &L0 = c->lev[0];
+    const Geom &g = L0.g;
+    int64_t p0 = plane_of(L0), vs = 3 * p0;
+    BOp J = bop(c, 0);
+    const double *b = J.pl(kFe);
+    double3 cw = field_weights(ph);
+    double *dev = W.dev;  // [0..m] dots, [m+1..2m+1] second pass, [2m+2] norm^2, y at [3m+8..]
+    const int m = W.m;
+    double *host = c->pinned;
+    Arnoldi A;
+    launch_fill(W.delta, vs, 0.0, s);
+    // r0 = b
+    launch_wdot_multi(g, b, b, vs, 1, p0, cw, W.partials, dev, s);
+    HIP_OK(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double beta0 = sqrt(host[0]);
+    *its = 0;
+    *relres = 0.0;
+    if (!(beta0 > 0)) {
+        if (!isfinite(beta0)) return fail(MG_ENONFINITE, "Newton residual is not finite");
+        return MG_OK;
+    }
+    launch_scale_by_norm(g, b, W.V, p0, dev, s);
+    double beta = beta0;
+    int total = 0;
+    while (true) {
+        A.start(beta);
+        int k = 0;
+        double est = beta;
+        for (; k < m && total < maxit; ++k) {
+            double *vk = W.V + k * vs, *zk = W.Z + k * vs, *vk1 = W.V + (k + 1) * vs;
+            launch_fill(zk, vs, 0.0, s);
+            block_vcycle(c, 0, vk, zk);
+            launch_block_residual(g, J, nullptr, zk, W.w, true, s);  // w = J z_k
+            // classical Gram-Schmidt, twice
+            launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev, s);
+            launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev, -1.0, s);
+            launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev + (m + 1), s);
+            launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev + (m + 1), -1.0, s);
+            launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev + 2 * m + 2, s);
+            launch_scale_by_norm(g, W.w, vk1, p0, dev + 2 * m + 2, s);
+            HIP_OK(hipMemcpyAsync(host, dev, (2 * m + 3) * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            for (int i = 0; i <= k; ++i) A.H[i][k] = host[i] + host[m + 1 + i];
+            A.H[k + 1][k] = sqrt(host[2 * m + 2]);
+            ++total;
+            c->vcycles++;
+            est = A.add(k);
+            if (!isfinite(est)) return fail(MG_ENONFINITE, "FGMRES breakdown (non-finite)");
+            if (est <= rtol * beta0 || A.H[k][k] == 0.0) {
+                ++k;
+                break;
+            }
+        }
+        double y[kMaxKrylov];
+        A.solve(k, y);
+        for (int i = 0; i < k; ++i) host[i] = y[i];
+        HIP_OK(hipMemcpyAsync(dev + 3 * m + 8, host, k * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_axpy_multi(g, W.delta, W.Z, vs, k, p0, dev + 3 * m + 8, 1.0, s);
+        // true residual for the restart / final check
+        launch_block_residual(g, J, b, W.delta, W.w, false, s);
+        launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev, s);
+        HIP_OK(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        beta = sqrt(host[0]);
+        *its = total;
+        *relres = beta / beta0;
+        if (!isfinite(beta)) return fail(MG_ENONFINITE, "FGMRES residual is not finite");
+        if (beta <= rtol * beta0 * 1.0000001 || est <= rtol * beta0) return MG_OK;
+        if (total >= maxit)
+            return fail(MG_ENOCONV, "FGMRES: relative residual %.3e after %d iterations", beta / beta0, total);
+        launch_scale_by_norm(g, W.w, W.V, p0, dev, s);
+    }
+}
+
+void copy_state(mg_ctx *c, const mg_state *st, double *dst) {
+    const Level &L0 = c->lev[0];
+    int64_t p0 = plane_of(L0);
+    launch_copy_field(L0.g, st->V, dst, c->stream);
+    launch_copy_field(L0.g, st->ne, dst + p0, c->stream);
+    launch_copy_field(L0.g, st->np, dst + 2 * p0, c->stream);
+}
+
+void restore_state(mg_ctx *c, const double *src, mg_state *st) {
+    const Level &L0 = c->lev[0];
+    int64_t p0 = plane_of(L0);
+    launch_copy_field(L0.g, src, st->V, c->stream);
+    launch_copy_field(L0.g, src + p0, st->ne, c->stream);
+    launch_copy_field(L0.g, src + 2 * p0, st->np, c->stream);
+}
+
+// Newton iterations of one BE step; the step's starting state is in W.snap.
+int newton_iterate(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
+                   mg_report *rep, bool *converged) {
+    hipStream_t s = c->stream;
+    const Level &L0 = c->lev[0];
+    int64_t p0 = plane_of(L0);
+    double dt_inv = (dt > 0 && isfinite(dt)) ? 1.0 / dt : 0.0;
+    *converged = false;
+    int maxn = sc->max_newton > 0 ? sc->max_newton : 10;
+    for (int it = 1; it <= maxn; ++it) {
+        assemble_all(c, ph, st, dt_inv);
+        int its = 0;
+        double rr = 0;
+        int e = fgmres(c, ph, sc->lin_rtol, sc->max_cycles > 0 ? sc->max_cycles : 200, &its, &rr);
+        if (rep) {
+            rep->final_relres = rr;
+            rep->newton_its += 1;
+            rep->vcycles += its;
+        }
+        if (e == MG_ENOCONV || e == MG_ENONFINITE) return MG_OK;  // step fails: caller rejects
+        if (e) return e;
+        launch_newton_update(L0.g, st->V, st->ne, st->np, c->nw.delta, p0, c->nw.partials, c->scal, s);
+        HIP_OK(hipMemcpyAsync(c->pinned, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        const double *o = c->pinned;
+        double re = o[0] / fmax(o[1], 1e-300), rp = o[2] / fmax(o[3], 1e-300), rv = o[4] / fmax(o[5], 1e-300);
+        double mx = fmax(re, fmax(rp, rv));
+        if (!isfinite(mx)) return MG_OK;
+        if (mx > sc->reject_limit) return MG_OK;
+        if (mx < sc->newton_tol) {
+            // the converged densities must be non-negative to rounding
+            double cnt = (double)(L0.g.nr + 1) * (L0.g.nz - 1);
+            *converged = o[6] >= -1e-10 * o[1] / cnt && o[7] >= -1e-10 * o[3] / cnt;
+            return MG_OK;
+        }
+    }
+    return MG_OK;
+}
+
+// Relative change max_species ||n - n^k||_2 / ||n||_2 against the snapshot.
+int step_change(mg_ctx *c, const mg_state *st, double *change, double *minn) {
+    const Level &L0 = c->lev[0];
+    int64_t p0 = plane_of(L0);
+    hipStream_t s = c->stream;
+    int nb = 0;
+    launch_diff_norms(L0.g, st->ne, c->nw.snap + p0, c->partials, &nb, s);
+    launch_sum_partials(c->partials, nb, 2, c->scal, s);
+    launch_diff_norms(L0.g, st->np, c->nw.snap + 2 * p0, c->partials, &nb, s);
+    launch_sum_partials(c->partials, nb, 2, c->scal + 2, s);
+    HIP_OK(hipMemcpyAsync(c->pinned, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double *o = c->pinned;
+    *change = fmax(sqrt(o[0] / fmax(o[1], 1e-300)), sqrt(o[2] / fmax(o[3], 1e-300)));
+    (void)minn;
+    return MG_OK;
+}
+
+}  // namespace
+
+void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
+    int m = d->krylov_m;
+    if (c) c->nw.m = m;
+    if (m <= 0) return;
+    int64_t p0 = 0;
+    for (int l = 0; l < nl; ++l) {
+        int nr = d->nr >> l, nz = d->nz >> l;
+        int64_t pitch = round_up(nz + 1, 16);
+        int64_t pl = (int64_t)(nr + 1) * pitch;
+        if (l == 0) p0 = pl;
+        BLevel B;
+        memset(&B, 0, sizeof B);
+        B.J = cv.take<double>(kBPlanes * pl);
+        B.x = cv.take<double>(3 * pl);
+        B.r = cv.take<double>(3 * pl);
+        B.st = (l > 0) ? cv.take<double>(3 * pl) : nullptr;
+        if (l == nl - 1) {
+            int64_t n = 3 * (int64_t)(nr + 1) * (nz - 1);
+            B.cinvT = cv.take<double>(n * n);
+            double *scr = cv.take<double>(n * 2 * n);
+            if (c) c->nw.scratch = scr;
+        }
+        if (c) c->nw.lev[l] = B;
+    }
+    double *V = cv.take<double>((int64_t)(m + 1) * 3 * p0);
+    double *Z = cv.take<double>((int64_t)m * 3 * p0);
+    double *w = cv.take<double>(3 * p0);
+    double *delta = cv.take<double>(3 * p0);
+    double *snap = cv.take<double>(3 * p0);
+    int nblk = ((d->nz + 1 + 63) / 64) * ((d->nr + 1 + 3) / 4);
+    double *part = cv.take<double>((int64_t)nblk * (m + 2) + (int64_t)nblk * 8 + 64);
+    double *dev = cv.take<double>(4 * kMaxKrylov + 64);
+    if (c) {
+        c->nw.V = V;
+        c->nw.Z = Z;
+        c->nw.w = w;
+        c->nw.delta = delta;
+        c->nw.snap = snap;
+        c->nw.partials = part;
+        c->nw.dev = dev;
+    }
+}
+
+int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
+                         mg_report *rep, bool *converged) {
+    if (c->nw.m <= 0) return fail(MG_EINVAL, "context built with krylov_m = 0: no Newton workspace");
+    const Level &L0 = c->lev[0];
+    launch_set_electrodes(L0.g, st->V, ph->V_bottom, ph->V_top, c->stream);
+    launch_set_electrodes(L0.g, st->ne, ph->ne_bottom, ph->ne_top, c->stream);
+    launch_set_electrodes(L0.g, st->np, ph->np_bottom, ph->np_top, c->stream);
+    copy_state(c, st, c->nw.snap);
+    int e = newton_iterate(c, ph, st, dt, sc, rep, converged);
+    if (e) return e;
+    if (rep) rep->steps += 1;
+    return MG_OK;
+}
+
+int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep) {
+    if (c->nw.m <= 0) return fail(MG_EINVAL, "context built with krylov_m = 0: no Newton workspace");
+    auto t0 = std::chrono::steady_clock::now();
+    mg_report local;
+    memset(&local, 0, sizeof local);
+    mg_report *R = rep ? rep : &local;
+    memset(R, 0, sizeof *R);
+    const Level &L0 = c->lev[0];
+    launch_set_electrodes(L0.g, st->V, ph->V_bottom, ph->V_top, c->stream);
+    launch_set_electrodes(L0.g, st->ne, ph->ne_bottom, ph->ne_top, c->stream);
+    launch_set_electrodes(L0.g, st->np, ph->np_bottom, ph->np_top, c->stream);
+    double dt = sc->dt0, dt_acc = 0.0, t = 0.0;
+    int consecutive_rejects = 0;
+    int status = MG_ENOCONV;
+    while (R->steps < sc->max_steps) {
+        copy_state(c, st, c->nw.snap);
+        bool ok = false;
+        int e = newton_iterate(c, ph, st, dt, sc, R, &ok);
+        if (e) return e;
+        if (!ok) {
+            restore_state(c, c->nw.snap, st);
+            R->rejected++;
+            if (++consecutive_rejects > 60) {
+                status = fail(MG_EREJECT, "time step rejected %d times in a row (dt = %.3e)", consecutive_rejects, dt);
+                break;
+            }
+            // retry with the last accepted step (Sec. 2), then halve
+            dt = (dt_acc > 0 && dt > dt_acc) ? dt_acc : 0.5 * dt;
+            continue;
+        }
+        consecutive_rejects = 0;
+        R->steps++;
+        t += dt;
+        double ch = 0;
+        e = step_change(c, st, &ch, nullptr);
+        if (e) return e;
+        R->last_change = ch;
+        if (!isfinite(ch)) {
+            status = fail(MG_ENONFINITE, "density change is not finite");
+            break;
+        }
+        dt_acc = dt;
+        if (ch < sc->steady_tol) {
+            status = MG_OK;
+            break;
+        }
+        dt = fmin(sc->growth * dt, sc->dt_max);
+    }
+    R->t_end = t;
+    R->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (status == MG_ENOCONV) fail(MG_ENOCONV, "not steady after %d steps (change %.3e)", R->steps, R->last_change);
+    return status;
+}
+
+}  // namespace mgf

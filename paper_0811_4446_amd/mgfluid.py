@@ -35,7 +35,7 @@ _PD = ctypes.POINTER(ctypes.c_double)
 class GridDesc(ctypes.Structure):
     _fields_ = [("abi_version", _I32), ("nr", _I32), ("nz", _I32), ("R", _D), ("d", _D),
                 ("z_host", _PD), ("coarsest_n", _I32), ("nu1", _I32), ("nu2", _I32),
-                ("smoother", _I32), ("prec", _I32)]
+                ("smoother", _I32), ("prec", _I32), ("krylov_m", _I32)]
 
 
 class Physics(ctypes.Structure):
@@ -123,9 +123,11 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def make_desc(nr, nz, z, R=1.0, d=1.0, coarsest=8, nu1=2, nu2=2, smoother=SMOOTH_ZEBRA, prec=FP64):
+def make_desc(nr, nz, z, R=1.0, d=1.0, coarsest=8, nu1=2, nu2=2, smoother=SMOOTH_ZEBRA, prec=FP64,
+              krylov_m=0):
     z = np.ascontiguousarray(z, dtype=np.float64)
-    desc = GridDesc(ABI_VERSION, nr, nz, R, d, z.ctypes.data_as(_PD), coarsest, nu1, nu2, smoother, prec)
+    desc = GridDesc(ABI_VERSION, nr, nz, R, d, z.ctypes.data_as(_PD), coarsest, nu1, nu2, smoother, prec,
+                    krylov_m)
     desc._z_keep = z
     return desc
 
@@ -140,13 +142,13 @@ class Solver:
     """One grid (and its multigrid hierarchy) on one device and stream."""
 
     def __init__(self, nr, nz, z, R=1.0, d=1.0, coarsest=8, nu1=2, nu2=2,
-                 smoother=SMOOTH_ZEBRA, prec=FP64, device="cuda:0", stream=None):
+                 smoother=SMOOTH_ZEBRA, prec=FP64, krylov_m=0, device="cuda:0", stream=None):
         if not torch.cuda.is_available():
             raise RuntimeError("mgfluid needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.nr, self.nz, self.R, self.d = nr, nz, R, d
         self.z = np.ascontiguousarray(z, dtype=np.float64)
         self.device = torch.device(device)
-        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, smoother, prec)
+        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, smoother, prec, krylov_m)
         self.pitch, self.ws_bytes = query(self.desc)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(self.ws_bytes // 8 + 64, dtype=torch.float64, device=self.device)
@@ -225,10 +227,13 @@ class Solver:
     def residual(self, eq, x, r):
         _check(lib().mg_residual(self.ctx, eq, _ptr(x), _ptr(r)))
 
-    def step(self, phys, state, dt, sched):
+    def step(self, phys, state, dt, sched, raise_on_noconv=True):
         rep = Report()
-        _check(lib().implicit_step(self.ctx, ctypes.byref(phys), ctypes.byref(state), float(dt),
-                                   ctypes.byref(sched), ctypes.byref(rep)))
+        code = lib().implicit_step(self.ctx, ctypes.byref(phys), ctypes.byref(state), float(dt),
+                                   ctypes.byref(sched), ctypes.byref(rep))
+        if code != 0 and (raise_on_noconv or code != -3):
+            _check(code)
+        rep.code = code
         return rep
 
     def steady(self, phys, state, sched):

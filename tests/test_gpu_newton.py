@@ -1,0 +1,84 @@
+"""Parity of the coupled Newton path (Sec. 2, Eq. 14) with the oracle: one
+backward-Euler step, and whole steady runs with the paper's time-step rule
+(the oracle solves each Newton system by sparse LU; the library by FGMRES
+preconditioned with a block V-cycle, iterated to the same tolerance)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import newton as NW
+from paper_0811_4446_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def M():
+    from paper_0811_4446_amd import mgfluid
+    return mgfluid
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _gpu(N, V, ne, np_, S, krylov_m=20, smoother=1):
+    m = M()
+    z = I.z_cos(N)
+    sol = m.Solver(N, N, z, smoother=smoother, krylov_m=krylov_m)
+    t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)]
+    st = sol.state(t[0], t[1], t[2], t[3], t[3])
+    return sol, t, st
+
+
+def _start(N, seed=0):
+    z = I.z_cos(N)
+    ne = I.initial_density(N, N, seed)
+    return z, I.initial_potential(N, N, z), ne, ne.copy(), I.source(N, N, z)
+
+
+@pytest.mark.parametrize("N,dt,pre", [(16, 1e-4, 0), (32, 1e-4, 0), (32, 1e-3, 12), (64, 0.1, 25)])
+def test_newton_step_matches_oracle(N, dt, pre):
+    """One BE step from the initial state (or after `pre` oracle steps of the
+    steady schedule): same Newton iterates within FP64 rounding."""
+    _say("newton step", N, dt, pre)
+    m = M()
+    z, V, ne, np_, S = _start(N)
+    ph = dict(I.PHYS)
+    cp = NW.Coupled(N, N, 1.0, z, ph)
+    if pre:
+        NW.steady(cp, V, ne, np_, S, S, max_steps=pre)
+    sol, t, st = _gpu(N, V, ne, np_, S)
+    hist = []
+    ok, its = NW.newton_step(cp, V, ne, np_, S, S, dt, max_newton=20, tol=1e-11, history=hist)
+    assert ok
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-13, max_cycles=400, max_newton=20, newton_tol=1e-11)
+    rep = sol.step(m.Physics.of(ph), st, dt, sc)
+    assert rep.newton_its == its, (rep.newton_its, its)
+    for tt, ref in zip(t[:3], (V, ne, np_)):
+        assert relmax(sol.download(tt), ref) <= 1e-11
+
+
+def test_steady_run_matches_oracle_33():
+    """The whole steady run at 33x33 from the random start: the library's
+    solve_steady takes the same accepted steps (dt x1.5 up to 0.1, stop at
+    relative change 1e-8) and ends in the oracle's state."""
+    _say("steady 33")
+    m = M()
+    N = 32
+    z, V, ne, np_, S = _start(N)
+    ph = dict(I.PHYS)
+    sol, t, st = _gpu(N, V, ne, np_, S)
+    cp = NW.Coupled(N, N, 1.0, z, ph)
+    acc, rej, seq = NW.steady(cp, V, ne, np_, S, S, tol=1e-8, newton_tol=1e-10)
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-12, max_cycles=400, newton_tol=1e-10, steady_tol=1e-8)
+    code, rep = sol.steady(m.Physics.of(ph), st, sc)
+    assert code == 0, m.lib().mg_last_error()
+    assert rep.steps == acc and rep.rejected == rej, (rep.steps, acc, rep.rejected, rej)
+    for tt, ref in zip(t[:3], (V, ne, np_)):
+        assert relmax(sol.download(tt), ref) <= 1e-9
+    print("steady 33: steps %d, newton %d, fgmres %d" % (rep.steps, rep.newton_its, rep.vcycles))
