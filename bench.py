@@ -1,0 +1,190 @@
+#!/usr/bin/env python
+"""Benchmark of the steady axisymmetric drift-diffusion solver on one MI355X.
+
+Workload: the multilevel-prolongation chain of Sec. 2 on the synthetic
+discharge (dimensionless physics, cos-stretched z grid, Gaussian source):
+65x65 from a seeded random start -> steady -> bilinear prolongation ->
+129x129 -> steady -> prolongation -> 257x257 -> steady.  Each time step is
+a coupled backward-Euler step solved by Newton (Eq. 14) with FGMRES
+preconditioned by a block V(2,2) cycle; dt starts at 1e-4 and grows x1.5
+per accepted step up to 0.1; the run is steady when the relative density
+change per step drops below 1e-8.  Applied voltage V_top in {0.5, 1, 2}.
+
+A bench "step" is the timed 257x257 stage for all three voltages, from
+initial states already resident in HBM.  `value` is the mean
+time-to-steady per voltage (seconds, lower is better).
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build uses one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("time-to-steady at 257² & 1025² (s), V-cycle HBM GB/s; "
+          "plain FP64 vs chosen forms")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def schedule(M, lin_rtol):
+    return M.schedule(dt0=1e-4, growth=1.5, dt_max=0.1, steady_tol=1e-8, lin_rtol=lin_rtol,
+                      max_steps=20000, max_cycles=400, coupling=M.NEWTON, max_newton=10,
+                      newton_tol=1e-6)
+
+
+def chain_to(M, I, N_final, vtop, lin_rtol, seed=0, N0=64):
+    """Steady runs N0 -> ... -> N_final/2, then prolong to N_final.  Returns
+    the fine solver and its initial (V, ne, np, S) device fields."""
+    phys = dict(I.PHYS)
+    phys["V_top"] = vtop
+    P = M.Physics.of(phys)
+    N = N0
+    z = I.z_cos(N)
+    sol = M.Solver(N, N, z, krylov_m=30, coarsest=4)
+    ne = I.initial_density(N, N, seed)
+    t = [sol.upload(I.initial_potential(N, N, z, 0.0, vtop)), sol.upload(ne), sol.upload(ne),
+         sol.upload(I.source(N, N, z))]
+    info = []
+    while True:
+        st = sol.state(t[0], t[1], t[2], t[3], t[3])
+        t0 = time.time()
+        code, rep = sol.steady(P, st, schedule(M, lin_rtol))
+        if code != 0:
+            raise RuntimeError("steady %d failed: %s" % (N, M.lib().mg_last_error()))
+        info.append(dict(N=N, steps=rep.steps, seconds=time.time() - t0))
+        if 2 * N == N_final:
+            break
+        N2 = 2 * N
+        z2 = I.z_cos(N2)
+        fine = M.Solver(N2, N2, z2, krylov_m=30, coarsest=4)
+        t2 = [fine.field(), fine.field(), fine.field(), fine.upload(I.source(N2, N2, z2))]
+        M.prolong_state(sol, st, fine, fine.state(t2[0], t2[1], t2[2], t2[3], t2[3]), P)
+        sol, t, N = fine, t2, N2
+    z2 = I.z_cos(N_final)
+    fine = M.Solver(N_final, N_final, z2, krylov_m=30, coarsest=4)
+    t2 = [fine.field(), fine.field(), fine.field(), fine.upload(I.source(N_final, N_final, z2))]
+    M.prolong_state(sol, sol.state(t[0], t[1], t[2], t[3], t[3]), fine,
+                    fine.state(t2[0], t2[1], t2[2], t2[3], t2[3]), P)
+    return fine, t2, P, info
+
+
+def cpu_baseline(I, newton_its_gpu, vtop=1.0, N=256):
+    """The oracle (plain FP64; SciPy sparse LU for each Newton system) on the
+    host: one Newton iteration at 257x257 (residual, Jacobian, LU solve),
+    timed single-threaded and scaled by the GPU run's Newton iteration
+    count."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import scipy.sparse.linalg as spla
+    from oracle import newton as NW
+    z = I.z_cos(N)
+    phys = dict(I.PHYS)
+    phys["V_top"] = vtop
+    cp = NW.Coupled(N, N, 1.0, z, phys)
+    ne = I.initial_density(N, N, 0)
+    np_ = ne.copy()
+    V = I.initial_potential(N, N, z, 0.0, vtop)
+    S = I.source(N, N, z)
+    t0 = time.time()
+    (Fe, Fp, FV), (Ae, Ap) = cp.residual(V, ne, np_, ne, np_, S, S, 1e4)
+    J = cp.jacobian(V, ne, np_, Ae, Ap)
+    du = spla.splu(J).solve(-cp.pack(Fe, Fp, FV))
+    per_it = time.time() - t0
+    assert du.shape[0] == J.shape[0]
+    return dict(value=round(per_it * newton_its_gpu, 1), unit="s", cores=1, kind="oracle",
+                sample="1 oracle Newton iteration at %dx%d (residual, Jacobian, sparse LU) = %.2f s, "
+                       "x %d Newton iterations of the GPU run (extrapolated)" % (N + 1, N + 1, per_it,
+                                                                                 newton_its_gpu))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--lin-rtol", type=float, default=1e-8)
+    ap.add_argument("--vtops", type=str, default="0.5,1,2")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (asked for %d); the batch of "
+              "independent solves would shard across GPUs, see the design notes" % args.gpus)
+        sys.exit(2)
+
+    import torch
+    from paper_0811_4446_amd import inputs as I
+    from paper_0811_4446_amd import mgfluid as M
+
+    vtops = [float(v) for v in args.vtops.split(",")]
+    N = 256
+    cases = []
+    for vt in vtops:
+        fine, t, P, info = chain_to(M, I, N, vt, args.lin_rtol)
+        log("prep V_top=%g: %s" % (vt, info))
+        cases.append((vt, fine, t, P, info))
+    # initial 257x257 states for every timed run, resident in HBM
+    runs = []
+    for k in range(args.warmup + args.steps):
+        for vt, fine, t, P, info in cases:
+            runs.append((vt, fine, [x.clone() for x in t[:3]] + [t[3]], P))
+    torch.cuda.synchronize()
+    for r in range(args.warmup * len(cases)):
+        vt, fine, t, P = runs[r]
+        code, rep = fine.steady(P, fine.state(t[0], t[1], t[2], t[3], t[3]), schedule(M, args.lin_rtol))
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.time()
+    for r in range(args.warmup * len(cases), len(runs)):
+        vt, fine, t, P = runs[r]
+        code, rep = fine.steady(P, fine.state(t[0], t[1], t[2], t[3], t[3]), schedule(M, args.lin_rtol))
+        if code != 0:
+            raise RuntimeError("257x257 steady failed: %s" % M.lib().mg_last_error())
+        reps.append((vt, rep.as_dict()))
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    nrun = args.steps * len(cases)
+    value = elapsed / nrun
+    for vt, rd in reps:
+        log("V_top=%g steps=%d newton=%d fgmres=%d t=%.3f s" % (vt, rd["steps"], rd["newton_its"],
+                                                              rd["vcycles"], rd["seconds"]))
+    # roofline of the dominant kernel: the collective red-black block smoother
+    fine = cases[-1][1]
+    avg_ms = fine.time_kernel(0, 0, reps=200)
+    nodes = (N + 1) * (N - 1)
+    # per half-sweep: the updated colour reads 27 Jacobian entries + 3 rhs and
+    # writes 3 unknowns; the other colour's 3 unknowns are read once
+    bytes_launch = 8.0 * nodes * (33 + 3) / 2.0
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", kernel="k_block_rbgs", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                avg_launch_us=round(avg_ms * 1e3, 3), algorithmic_bytes_per_launch=int(bytes_launch))
+    steps_mean = sum(rd["steps"] for _, rd in reps) / len(reps)
+    newton_mean = sum(rd["newton_its"] for _, rd in reps) / len(reps)
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "steady 257x257 from the prolonged 129x129 steady state, coupled Newton BE, "
+                               "dt x1.5 to 0.1, stop at relative change 1e-8",
+                   "grid": "257x257, r uniform, z cos-stretched", "V_top": vtops,
+                   "lin_rtol": args.lin_rtol, "mean_steps": steps_mean,
+                   "runs": [dict(V_top=vt, steps=rd["steps"], newton=rd["newton_its"], fgmres=rd["vcycles"],
+                                 seconds=round(rd["seconds"], 3)) for vt, rd in reps],
+                   "chain": [dict(V_top=c[0], stages=c[4]) for c in cases]},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(I, int(round(newton_mean)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -187,6 +187,15 @@ int mg_smooth_half(mg_ctx *ctx, int eq, double *x, int colour);
 /* r = f - A x on the unknown nodes of level 0 (0 on electrode rows). */
 int mg_residual(mg_ctx *ctx, int eq, const double *x, double *r);
 
+/* Time one kernel of the hot path: `reps` back-to-back launches on the
+ * context's stream between two HIP events; *avg_ms receives the mean
+ * duration of one launch.  which: 0 collective red-black block smoother
+ * half-sweep of the Newton system (level 0; needs an assembled Jacobian),
+ * 1 zebra z-line half-sweep, 2 point red-black half-sweep, 3 residual
+ * (scalar equation `eq`, assembled before).  Overwrites the level-0 work
+ * vectors only.  Synchronises. */
+int mg_time_kernel(mg_ctx *ctx, int which, int eq, int32_t reps, double *avg_ms);
+
 /* Thread-local message of the last error. */
 const char *mg_last_error(void);
 

@@ -594,6 +594,38 @@ int solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedul
     return status;
 }
 
+int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
+    if (int e = check_ctx(c)) return e;
+    if (!avg_ms || reps < 1) return fail(MG_EINVAL, "bad reps or null output");
+    if (which == 0) return time_block_smoother(c, reps, avg_ms);
+    if (int e = check_eq(eq)) return e;
+    if (!c->assembled[eq]) return fail(MG_EINVAL, "equation %d not assembled", eq);
+    if (which < 1 || which > 3) return fail(MG_EINVAL, "bad kernel id %d", which);
+    const Level &L = c->lev[0];
+    double *x = c->spare[0], *r = c->spare[1];
+    launch_copy_field(L.g, L.op[eq].f, x, c->stream);
+    hipEvent_t a, b;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    HIP_OK(hipEventRecord(a, c->stream));
+    for (int k = 0; k < reps; ++k) {
+        if (which == 1)
+            launch_zline<double>(L.g, L.op[eq], x, k & 1, c->stream);
+        else if (which == 2)
+            launch_rbgs<double>(L.g, L.op[eq], x, k & 1, c->stream);
+        else
+            launch_residual<double, double, double>(L.g, L.op[eq], nullptr, x, r, nullptr, nullptr, c->stream);
+    }
+    HIP_OK(hipEventRecord(b, c->stream));
+    HIP_OK(hipEventSynchronize(b));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *avg_ms = ms / reps;
+    return MG_OK;
+}
+
 int prolong_state(mg_ctx *coarse, const mg_state *src, mg_ctx *fine, mg_state *dst, const mg_physics *ph) {
     if (!coarse || !fine || !src || !dst || !ph) return fail(MG_EINVAL, "null argument");
     const Geom &gc = coarse->lev[0].g;

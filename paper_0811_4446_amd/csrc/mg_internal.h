@@ -150,4 +150,5 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl);
 int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
                          mg_report *rep, bool *converged);
 int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep);
+int time_block_smoother(mg_ctx *c, int reps, double *avg_ms);
 }  // namespace mgf

@@ -571,6 +571,73 @@ __global__ __launch_bounds__(256) void k_coarse_factor(Geom g, Op<double> op, do
     }
 }
 
+// Same factorisation with the augmented matrix resident in LDS (n <= 63).
+constexpr int kLdsGJ = 63;
+__global__ __launch_bounds__(256) void k_coarse_factor_lds(Geom g, Op<double> op, double *__restrict__ invT,
+                                                            float *__restrict__ invT32) {
+    const int m = g.nz - 1;
+    const int n = (g.nr + 1) * m;
+    const int n2 = 2 * n;
+    __shared__ double M[kLdsGJ * 2 * kLdsGJ];
+    __shared__ double fcol[kLdsGJ];
+    __shared__ int piv;
+    for (int t = threadIdx.x; t < n * n2; t += blockDim.x) M[t] = 0.0;
+    __syncthreads();
+    for (int row = threadIdx.x; row < n; row += blockDim.x) {
+        int i = row / m, j = row % m + 1;
+        int64_t p = at(g, i, j);
+        double *Mr = M + row * n2;
+        Mr[row] = op.b[p];
+        if (i > 0) Mr[row - m] = op.a[p];
+        if (i < g.nr) Mr[row + m] = op.c[p];
+        if (j > 1) Mr[row - 1] = op.d[p];
+        if (j < m) Mr[row + 1] = op.e[p];
+        Mr[n + row] = 1.0;
+    }
+    __syncthreads();
+    for (int col = 0; col < n; ++col) {
+        if (threadIdx.x == 0) {
+            int best = col;
+            double bv = fabs(M[col * n2 + col]);
+            for (int rr = col + 1; rr < n; ++rr) {
+                double v = fabs(M[rr * n2 + col]);
+                if (v > bv) {
+                    bv = v;
+                    best = rr;
+                }
+            }
+            piv = best;
+        }
+        __syncthreads();
+        const int pv = piv;
+        if (pv != col)
+            for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+                double tmp = M[col * n2 + t];
+                M[col * n2 + t] = M[pv * n2 + t];
+                M[pv * n2 + t] = tmp;
+            }
+        __syncthreads();
+        const double pinv = 1.0 / M[col * n2 + col];
+        __syncthreads();
+        for (int t = threadIdx.x; t < n2; t += blockDim.x) M[col * n2 + t] *= pinv;
+        for (int rr = threadIdx.x; rr < n; rr += blockDim.x) fcol[rr] = M[rr * n2 + col];
+        __syncthreads();
+        for (int t = threadIdx.x; t < n * n2; t += blockDim.x) {
+            int rr = t / n2, cc = t % n2;
+            if (rr == col) continue;
+            double fct = fcol[rr];
+            if (fct != 0.0) M[rr * n2 + cc] -= fct * M[col * n2 + cc];
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+        int row = t / n, k = t % n;
+        double v = M[row * n2 + n + k];
+        invT[(int64_t)k * n + row] = v;
+        if (invT32) invT32[(int64_t)k * n + row] = (float)v;
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_coarse_solve(Geom g, Op<T> op, const T *__restrict__ invT,
                                                        T *__restrict__ x) {
@@ -718,7 +785,11 @@ void launch_prolong_state(const Geom &gf, double *xf, const Geom &gc, const doub
 
 void launch_coarse_factor(const Geom &g, Op<double> op, double *scratch, double *invT, float *invT32,
                           hipStream_t s) {
-    k_coarse_factor<<<1, 256, 0, s>>>(g, op, scratch, invT, invT32);
+    int n = (g.nr + 1) * (g.nz - 1);
+    if (n <= kLdsGJ)
+        k_coarse_factor_lds<<<1, 256, 0, s>>>(g, op, invT, invT32);
+    else
+        k_coarse_factor<<<1, 256, 0, s>>>(g, op, scratch, invT, invT32);
 }
 
 template <class T>

@@ -362,6 +362,78 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor(Geom g, BOp J, dou
     }
 }
 
+// Same factorisation with the augmented matrix resident in LDS (n <= 63).
+constexpr int kLdsGJ = 63;
+__global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J, double *__restrict__ invT) {
+    const int m = g.nz - 1;
+    const int n = 3 * (g.nr + 1) * m;
+    const int n2 = 2 * n;
+    __shared__ double M[kLdsGJ * 2 * kLdsGJ];
+    __shared__ double fcol[kLdsGJ];
+    __shared__ int piv;
+    for (int t = threadIdx.x; t < n * n2; t += blockDim.x) M[t] = 0.0;
+    __syncthreads();
+    for (int node = threadIdx.x; node < (g.nr + 1) * m; node += blockDim.x) {
+        int i = node / m, j = node % m + 1;
+        int64_t p = at(g, i, j);
+        int rowb = 3 * node;
+        int nbnode[5] = {node - m, node, node + m, node - 1, node + 1};
+        bool has[5] = {i > 0, true, i < g.nr, j > 1, j < m};
+        for (int d = 0; d < 5; ++d) {
+            if (!has[d]) continue;
+            int colb = 3 * nbnode[d];
+            M[(rowb + 0) * n2 + colb + 0] = J.pl(kEE + d)[p];
+            M[(rowb + 0) * n2 + colb + 2] = J.pl(kEV + d)[p];
+            M[(rowb + 1) * n2 + colb + 1] = J.pl(kPP + d)[p];
+            M[(rowb + 1) * n2 + colb + 2] = J.pl(kPV + d)[p];
+            M[(rowb + 2) * n2 + colb + 2] = J.pl(kVV + d)[p];
+        }
+        M[(rowb + 2) * n2 + rowb + 0] = J.pl(kVe)[p];
+        M[(rowb + 2) * n2 + rowb + 1] = J.pl(kVp)[p];
+        for (int f = 0; f < 3; ++f) M[(rowb + f) * n2 + n + rowb + f] = 1.0;
+    }
+    __syncthreads();
+    for (int col = 0; col < n; ++col) {
+        if (threadIdx.x == 0) {
+            int best = col;
+            double bv = fabs(M[col * n2 + col]);
+            for (int rr = col + 1; rr < n; ++rr) {
+                double v = fabs(M[rr * n2 + col]);
+                if (v > bv) {
+                    bv = v;
+                    best = rr;
+                }
+            }
+            piv = best;
+        }
+        __syncthreads();
+        const int pv = piv;
+        if (pv != col)
+            for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+                double tmp = M[col * n2 + t];
+                M[col * n2 + t] = M[pv * n2 + t];
+                M[pv * n2 + t] = tmp;
+            }
+        __syncthreads();
+        const double pinv = 1.0 / M[col * n2 + col];
+        __syncthreads();
+        for (int t = threadIdx.x; t < n2; t += blockDim.x) M[col * n2 + t] *= pinv;
+        for (int rr = threadIdx.x; rr < n; rr += blockDim.x) fcol[rr] = M[rr * n2 + col];
+        __syncthreads();
+        for (int t = threadIdx.x; t < n * n2; t += blockDim.x) {
+            int rr = t / n2, cc = t % n2;
+            if (rr == col) continue;
+            double fct = fcol[rr];
+            if (fct != 0.0) M[rr * n2 + cc] -= fct * M[col * n2 + cc];
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+        int row = t / n, k = t % n;
+        invT[(int64_t)k * n + row] = M[row * n2 + n + k];
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOp J, const double *__restrict__ f,
                                                              const double *__restrict__ invT,
                                                              double *__restrict__ x) {
@@ -559,7 +631,11 @@ void launch_inject3(const Geom &gf, const double *V, const double *ne, const dou
     k_inject3<<<grid2d(gc), kB2, 0, s>>>(gf, V, ne, np, gc, out, pc);
 }
 void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s) {
-    k_block_coarse_factor<<<1, 1024, 0, s>>>(g, J, scratch, invT);
+    int n = 3 * (g.nr + 1) * (g.nz - 1);
+    if (n <= kLdsGJ)
+        k_block_coarse_factor_lds<<<1, 1024, 0, s>>>(g, J, invT);
+    else
+        k_block_coarse_factor<<<1, 1024, 0, s>>>(g, J, scratch, invT);
 }
 void launch_block_coarse_solve(const Geom &g, const BOp &J, const double *f, const double *invT, double *x,
                                hipStream_t s) {

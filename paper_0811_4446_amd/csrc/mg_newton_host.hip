@@ -378,4 +378,25 @@ int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_
     return status;
 }
 
+int time_block_smoother(mg_ctx *c, int reps, double *avg_ms) {
+    if (c->nw.m <= 0) return fail(MG_EINVAL, "no Newton workspace (krylov_m = 0)");
+    const Level &L0 = c->lev[0];
+    BOp J = bop(c, 0);
+    double *x = c->nw.lev[0].x;
+    hipEvent_t a, b;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    launch_block_rbgs(L0.g, J, J.pl(kFe), x, 0, c->stream);
+    HIP_OK(hipEventRecord(a, c->stream));
+    for (int r = 0; r < reps; ++r) launch_block_rbgs(L0.g, J, J.pl(kFe), x, r & 1, c->stream);
+    HIP_OK(hipEventRecord(b, c->stream));
+    HIP_OK(hipEventSynchronize(b));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *avg_ms = ms / reps;
+    return MG_OK;
+}
+
 }  // namespace mgf

@@ -86,6 +86,7 @@ SIGNATURES = {
     "mg_copy_coef": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP]),
     "mg_smooth_half": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int]),
     "mg_residual": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP]),
+    "mg_time_kernel": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _I32, _PD]),
     "mg_last_error": (ctypes.c_char_p, []),
 }
 
@@ -235,6 +236,11 @@ class Solver:
             _check(code)
         rep.code = code
         return rep
+
+    def time_kernel(self, which, eq=0, reps=50):
+        ms = _D(0.0)
+        _check(lib().mg_time_kernel(self.ctx, which, eq, reps, ctypes.byref(ms)))
+        return ms.value
 
     def steady(self, phys, state, sched):
         rep = Report()
