@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--lin-rtol", type=float, default=1e-8)
+    ap.add_argument("--lin-rtol", type=float, default=1e-3)
     ap.add_argument("--vtops", type=str, default="0.5,1,2")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <chrono>
@@ -327,6 +328,10 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     c->desc.z_host = c->zhost.data();
     c->stream = reinterpret_cast<hipStream_t>(stream);
     carve(c, desc, reinterpret_cast<char *>(workspace));
+    // debugging switches: per-level launches instead of the fused coarse
+    // sub-cycle, eager launches instead of captured graphs
+    c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
+    c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
@@ -365,6 +370,9 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
 
 void mg_destroy(mg_ctx *ctx) {
     if (!ctx) return;
+    for (int t = 0; t < 64; ++t)
+        if (ctx->nw.exec[t]) (void)hipGraphExecDestroy(ctx->nw.exec[t]);
+    if (ctx->nw.cap) (void)hipStreamDestroy(ctx->nw.cap);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
 }

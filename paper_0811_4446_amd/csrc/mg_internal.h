@@ -124,6 +124,13 @@ struct NewtonWork {
     double *partials = nullptr;
     double *dev = nullptr;     // device scalars (dots, norms, y)
     double *scratch = nullptr; // coarsest factorisation workspace
+    // one captured graph per Arnoldi index k (block V-cycle, product,
+    // orthogonalisation, readback), replayed on the context's stream
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec[64] = {};
+    double cw_cap[3] = {0, 0, 0};
+    bool use_graphs = true;
+    bool fuse = true;  // single-workgroup coarse sub-cycle
 };
 
 }  // namespace mgf

@@ -15,6 +15,20 @@ struct BOp {
     __host__ __device__ double *pl(int k) const { return base + (int64_t)k * plane; }
 };
 
+// Levels run by the single-workgroup coarse sub-cycle (last = coarsest).
+constexpr int kMaxFused = 8;
+constexpr int kMaxFusedCoarse = 1024;  // 3 x unknown nodes of the coarsest level
+struct FusedLevels {
+    int n, nu1, nu2;
+    Geom g[kMaxFused];
+    double *J[kMaxFused];
+    int64_t plane[kMaxFused];
+    double *x[kMaxFused];
+    double *r[kMaxFused];
+    const double *f0;
+    const double *invT;
+};
+
 struct NewtonPhys {
     double qe, qp;   // -s mu / D for electrons (s = -1) and ions (s = +1)
     double De, Dp, k, dt_inv;
@@ -36,6 +50,7 @@ void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, do
 void launch_block_coarse_solve(const Geom &g, const BOp &J, const double *f, const double *invT, double *x,
                                hipStream_t s);
 int block_vec_blocks(const Geom &g);
+void launch_block_subcycle(const FusedLevels &F, hipStream_t s);
 void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
                        int64_t plane, double3 cw, double *partials, double *out, hipStream_t s);
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,

@@ -174,14 +174,10 @@ inline __device__ void nb_sum(const Geom &g, const BOp &J, const double *x, int6
     }
 }
 
-// Collective red-black Gauss-Seidel half-sweep: at every node of the colour
-// the 3x3 centre block is solved exactly for (n_e, n_p, V) with the
-// neighbours held fixed.  The block [[ee,0,eV],[0,pp,pV],[Ve,Vp,VV]] is
-// reduced to the potential first.
-__global__ void k_block_rbgs(Geom g, BOp J, const double *__restrict__ f, double *__restrict__ x, int colour) {
-    int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
-    if (i > g.nr || j < 1 || j >= g.nz || ((i + j) & 1) != colour) return;
+// Collective Gauss-Seidel update of one node: the 3x3 centre block is
+// solved exactly for (n_e, n_p, V) with the neighbours held fixed.  The block
+// [[ee,0,eV],[0,pp,pV],[Ve,Vp,VV]] is reduced to the potential first.
+inline __device__ void block_gs_node(const Geom &g, const BOp &J, const double *f, double *x, int i, int j) {
     int64_t p = at(g, i, j);
     int64_t plane = J.plane;
     double se, sp, sv;
@@ -196,12 +192,19 @@ __global__ void k_block_rbgs(Geom g, BOp J, const double *__restrict__ f, double
     x[p + 2 * plane] = xv;
 }
 
-// r = f - B x (apply == 0) or r = B x (apply == 1), 3 fields, 0 on electrodes.
-__global__ void k_block_residual(Geom g, BOp J, const double *__restrict__ f, const double *__restrict__ x,
-                                 double *__restrict__ r, int apply) {
+// Red-black half-sweep: every unknown node with (i+j)%2 == colour.  Nodes of
+// one colour only read nodes of the other colour.
+__global__ void k_block_rbgs(Geom g, BOp J, const double *__restrict__ f, double *__restrict__ x, int colour) {
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
-    if (i > g.nr || j > g.nz) return;
+    if (i > g.nr || j < 1 || j >= g.nz || ((i + j) & 1) != colour) return;
+    block_gs_node(g, J, f, x, i, j);
+}
+
+// r = f - B x (apply == 0) or r = B x (apply == 1) at one node, 3 fields,
+// 0 on the electrode rows.
+inline __device__ void block_residual_node(const Geom &g, const BOp &J, const double *f, const double *x,
+                                           double *r, int apply, int i, int j) {
     int64_t p = at(g, i, j), plane = J.plane;
     if (j == 0 || j == g.nz) {
         r[p] = r[p + plane] = r[p + 2 * plane] = 0.0;
@@ -224,13 +227,18 @@ __global__ void k_block_residual(Geom g, BOp J, const double *__restrict__ f, co
     }
 }
 
+__global__ void k_block_residual(Geom g, BOp J, const double *__restrict__ f, const double *__restrict__ x,
+                                 double *__restrict__ r, int apply) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    block_residual_node(g, J, f, x, r, apply, i, j);
+}
+
 // Three-field restriction (P^T of the bilinear prolongation), same weights
-// as the scalar path.
-__global__ void k_restrict3(Geom gf, const double *__restrict__ rf, int64_t pf, Geom gc, double *__restrict__ fc,
-                            int64_t pc) {
-    int J_ = blockIdx.x * kTX + threadIdx.x;
-    int I = blockIdx.y * kTY + threadIdx.y;
-    if (I > gc.nr || J_ > gc.nz) return;
+// as the scalar path, at coarse node (I, J_).
+inline __device__ void restrict3_node(const Geom &gf, const double *rf, int64_t pf, const Geom &gc, double *fc,
+                                      int64_t pc, int I, int J_) {
     int64_t q = at(gc, I, J_);
     if (J_ == 0 || J_ == gc.nz) {
         fc[q] = fc[q + pc] = fc[q + 2 * pc] = 0.0;
@@ -254,11 +262,17 @@ __global__ void k_restrict3(Geom gf, const double *__restrict__ rf, int64_t pf, 
     fc[q + 2 * pc] = acc[2];
 }
 
-__global__ void k_prolong3(Geom gf, double *__restrict__ xf, int64_t pf, Geom gc, const double *__restrict__ xc,
-                           int64_t pc) {
-    int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
-    if (i > gf.nr || j < 1 || j >= gf.nz) return;
+__global__ void k_restrict3(Geom gf, const double *__restrict__ rf, int64_t pf, Geom gc, double *__restrict__ fc,
+                            int64_t pc) {
+    int J_ = blockIdx.x * kTX + threadIdx.x;
+    int I = blockIdx.y * kTY + threadIdx.y;
+    if (I > gc.nr || J_ > gc.nz) return;
+    restrict3_node(gf, rf, pf, gc, fc, pc, I, J_);
+}
+
+// Bilinear prolongation of the coarse correction, added at fine node (i, j).
+inline __device__ void prolong3_node(const Geom &gf, double *xf, int64_t pf, const Geom &gc, const double *xc,
+                                     int64_t pc, int i, int j) {
     int I0 = i >> 1, I1 = (i + 1) >> 1;
     int64_t p = at(gf, i, j);
 #pragma unroll
@@ -276,6 +290,14 @@ __global__ void k_prolong3(Geom gf, double *__restrict__ xf, int64_t pf, Geom gc
         }
         xf[p + f * pf] += (i & 1) ? 0.5 * (v0 + v1) : v0;
     }
+}
+
+__global__ void k_prolong3(Geom gf, double *__restrict__ xf, int64_t pf, Geom gc, const double *__restrict__ xc,
+                           int64_t pc) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > gf.nr || j < 1 || j >= gf.nz) return;
+    prolong3_node(gf, xf, pf, gc, xc, pc, i, j);
 }
 
 __global__ void k_inject3(Geom gf, const double *__restrict__ V, const double *__restrict__ ne,
@@ -434,27 +456,110 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
     }
 }
 
-__global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOp J, const double *__restrict__ f,
-                                                             const double *__restrict__ invT,
-                                                             double *__restrict__ x) {
+// x = A^{-1} f on the coarsest grid by the whole workgroup (rhs staged in
+// `rhs`, at least 3 * nodes doubles of LDS).
+inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const double *f, const double *invT,
+                                             double *x, double *rhs) {
     const int m = g.nz - 1;
     const int nn = (g.nr + 1) * m;
     const int n = 3 * nn;
-    __shared__ double rhs[3 * kMaxCoarseUnknowns];
     for (int node = threadIdx.x; node < nn; node += blockDim.x) {
         int i = node / m, j = node % m + 1;
         int64_t p = at(g, i, j);
         rhs[3 * node + 0] = f[p];
-        rhs[3 * node + 1] = f[p + J.plane];
-        rhs[3 * node + 2] = f[p + 2 * J.plane];
+        rhs[3 * node + 1] = f[p + plane];
+        rhs[3 * node + 2] = f[p + 2 * plane];
     }
     __syncthreads();
     for (int row = threadIdx.x; row < n; row += blockDim.x) {
         double acc = 0.0;
         for (int k = 0; k < n; ++k) acc += invT[(int64_t)k * n + row] * rhs[k];
-        int node = row / 3, f = row % 3;
+        int node = row / 3, fl = row % 3;
         int i = node / m, j = node % m + 1;
-        x[at(g, i, j) + f * J.plane] = acc;
+        x[at(g, i, j) + fl * plane] = acc;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOp J, const double *__restrict__ f,
+                                                             const double *__restrict__ invT,
+                                                             double *__restrict__ x) {
+    __shared__ double rhs[3 * kMaxCoarseUnknowns];
+    block_coarse_solve_wg(g, J.plane, f, invT, x, rhs);
+}
+
+// ---------------------------------------------------------------------------
+// The coarse end of the block V-cycle in one workgroup: levels 0..n-1 of
+// `F` (the last is the coarsest) are small enough that per-level launches
+// would cost more than the work, so one workgroup runs their smoothing,
+// residual, restriction, coarse solve and prolongation with barriers in
+// between, node by node exactly as the per-level kernels do.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevels F) {
+    __shared__ double rhs[3 * kMaxFusedCoarse];
+    const int n = F.n;
+    const int nt = blockDim.x;
+    for (int q = 0; q < n - 1; ++q) {
+        const Geom &g = F.g[q];
+        BOp J{F.J[q], F.plane[q]};
+        const double *f = (q == 0) ? F.f0 : J.pl(kFe);
+        double *x = F.x[q];
+        const int nodes = (g.nr + 1) * (g.nz + 1);
+        if (q > 0) {
+            for (int t = threadIdx.x; t < nodes; t += nt) {
+                int i = t / (g.nz + 1), j = t % (g.nz + 1);
+                int64_t p = at(g, i, j);
+                x[p] = x[p + J.plane] = x[p + 2 * J.plane] = 0.0;
+            }
+            __syncthreads();
+        }
+        for (int s = 0; s < F.nu1; ++s)
+            for (int col = 0; col < 2; ++col) {
+                for (int t = threadIdx.x; t < nodes; t += nt) {
+                    int i = t / (g.nz + 1), j = t % (g.nz + 1);
+                    if (j >= 1 && j < g.nz && ((i + j) & 1) == col) block_gs_node(g, J, f, x, i, j);
+                }
+                __syncthreads();
+            }
+        for (int t = threadIdx.x; t < nodes; t += nt) {
+            int i = t / (g.nz + 1), j = t % (g.nz + 1);
+            block_residual_node(g, J, f, x, F.r[q], 0, i, j);
+        }
+        __syncthreads();
+        const Geom &gc = F.g[q + 1];
+        BOp Jc{F.J[q + 1], F.plane[q + 1]};
+        const int cnodes = (gc.nr + 1) * (gc.nz + 1);
+        for (int t = threadIdx.x; t < cnodes; t += nt) {
+            int I = t / (gc.nz + 1), J_ = t % (gc.nz + 1);
+            restrict3_node(g, F.r[q], J.plane, gc, Jc.pl(kFe), Jc.plane, I, J_);
+        }
+        __syncthreads();
+    }
+    {
+        const int q = n - 1;
+        BOp J{F.J[q], F.plane[q]};
+        const double *f = (q == 0) ? F.f0 : J.pl(kFe);
+        block_coarse_solve_wg(F.g[q], J.plane, f, F.invT, F.x[q], rhs);
+        __syncthreads();
+    }
+    for (int q = n - 2; q >= 0; --q) {
+        const Geom &g = F.g[q];
+        BOp J{F.J[q], F.plane[q]};
+        const double *f = (q == 0) ? F.f0 : J.pl(kFe);
+        double *x = F.x[q];
+        const int nodes = (g.nr + 1) * (g.nz + 1);
+        for (int t = threadIdx.x; t < nodes; t += nt) {
+            int i = t / (g.nz + 1), j = t % (g.nz + 1);
+            if (j >= 1 && j < g.nz) prolong3_node(g, x, J.plane, F.g[q + 1], F.x[q + 1], F.plane[q + 1], i, j);
+        }
+        __syncthreads();
+        for (int s = 0; s < F.nu2; ++s)
+            for (int col = 0; col < 2; ++col) {
+                for (int t = threadIdx.x; t < nodes; t += nt) {
+                    int i = t / (g.nz + 1), j = t % (g.nz + 1);
+                    if (j >= 1 && j < g.nz && ((i + j) & 1) == col) block_gs_node(g, J, f, x, i, j);
+                }
+                __syncthreads();
+            }
     }
 }
 
@@ -641,6 +746,7 @@ void launch_block_coarse_solve(const Geom &g, const BOp &J, const double *f, con
                                hipStream_t s) {
     k_block_coarse_solve<<<1, 1024, 0, s>>>(g, J, f, invT, x);
 }
+void launch_block_subcycle(const FusedLevels &F, hipStream_t s) { k_block_subcycle<<<1, 1024, 0, s>>>(F); }
 int block_vec_blocks(const Geom &g) {
     dim3 gr = grid2d(g);
     return (int)(gr.x * gr.y);

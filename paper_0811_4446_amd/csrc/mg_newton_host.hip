@@ -23,11 +23,31 @@ double3 field_weights(const mg_physics *ph) {
     return make_double3(1.0, 1.0, ph->k > 0 ? 1.0 / ph->k : 1.0);
 }
 
-void block_vcycle(mg_ctx *c, int l, const double *f, double *x) {
-    hipStream_t s = c->stream;
+// Levels at or below this size run in the single-workgroup sub-cycle.
+constexpr int kFuseMaxN = 32;
+
+void block_vcycle(mg_ctx *c, int l, const double *f, double *x, hipStream_t s) {
     const Level &L = c->lev[l];
     BOp J = bop(c, l);
     BLevel &B = c->nw.lev[l];
+    if (c->nw.fuse && L.g.nr <= kFuseMaxN && L.g.nz <= kFuseMaxN && c->nlev - l <= kMaxFused) {
+        FusedLevels F;
+        memset(&F, 0, sizeof F);
+        F.n = c->nlev - l;
+        F.nu1 = c->desc.nu1;
+        F.nu2 = c->desc.nu2;
+        for (int q = 0; q < F.n; ++q) {
+            F.g[q] = c->lev[l + q].g;
+            F.J[q] = c->nw.lev[l + q].J;
+            F.plane[q] = plane_of(c->lev[l + q]);
+            F.x[q] = (q == 0) ? x : c->nw.lev[l + q].x;
+            F.r[q] = c->nw.lev[l + q].r;
+        }
+        F.f0 = f;
+        F.invT = c->nw.lev[c->nlev - 1].cinvT;
+        launch_block_subcycle(F, s);
+        return;
+    }
     if (l == c->nlev - 1) {
         launch_block_coarse_solve(L.g, J, f, B.cinvT, x, s);
         return;
@@ -41,7 +61,7 @@ void block_vcycle(mg_ctx *c, int l, const double *f, double *x) {
     launch_restrict3(L.g, B.r, plane_of(L), C.g, fc, plane_of(C), s);
     double *xc = c->nw.lev[l + 1].x;
     launch_fill(xc, 3 * plane_of(C), 0.0, s);
-    block_vcycle(c, l + 1, fc, xc);
+    block_vcycle(c, l + 1, fc, xc, s);
     launch_prolong3(L.g, x, plane_of(L), C.g, xc, plane_of(C), s);
     for (int k = 0; k < c->desc.nu2; ++k)
         for (int col = 0; col < 2; ++col) launch_block_rbgs(L.g, J, f, x, col, s);
@@ -112,6 +132,66 @@ struct Arnoldi {
     }
 };
 
+// One Arnoldi step k: z_k = M v_k (block V-cycle), w = J z_k, two passes of
+// classical Gram-Schmidt against v_0..v_k, v_{k+1} = w/|w|, and the
+// readback of the k+1 projections (twice) and |w|^2 to pinned memory.
+void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
+    NewtonWork &W = c->nw;
+    const Level &L0 = c->lev[0];
+    const Geom &g = L0.g;
+    int64_t p0 = plane_of(L0), vs = 3 * p0;
+    BOp J = bop(c, 0);
+    const int m = W.m;
+    double *dev = W.dev;
+    double *vk = W.V + k * vs, *zk = W.Z + k * vs, *vk1 = W.V + (k + 1) * vs;
+    launch_fill(zk, vs, 0.0, s);
+    block_vcycle(c, 0, vk, zk, s);
+    launch_block_residual(g, J, nullptr, zk, W.w, true, s);  // w = J z_k
+    launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev, s);
+    launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev, -1.0, s);
+    launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev + (m + 1), s);
+    launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev + (m + 1), -1.0, s);
+    launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev + 2 * m + 2, s);
+    launch_scale_by_norm(g, W.w, vk1, p0, dev + 2 * m + 2, s);
+    (void)hipMemcpyAsync(c->pinned, dev, (2 * m + 3) * sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+// Run Arnoldi step k on the context stream, from a captured graph when
+// graphs are enabled (captured on a private stream at first use; a change
+// of the inner-product weights recaptures).
+int run_arnoldi(mg_ctx *c, int k, double3 cw) {
+    NewtonWork &W = c->nw;
+    if (!W.use_graphs) {
+        arnoldi_step(c, k, cw, c->stream);
+        return MG_OK;
+    }
+    if (W.cw_cap[0] != cw.x || W.cw_cap[1] != cw.y || W.cw_cap[2] != cw.z) {
+        for (int t = 0; t < 64; ++t)
+            if (W.exec[t]) {
+                (void)hipGraphExecDestroy(W.exec[t]);
+                W.exec[t] = nullptr;
+            }
+        W.cw_cap[0] = cw.x;
+        W.cw_cap[1] = cw.y;
+        W.cw_cap[2] = cw.z;
+    }
+    if (!W.cap) HIP_OK(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
+    if (!W.exec[k]) {
+        hipGraph_t graph = nullptr;
+        HIP_OK(hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal));
+        arnoldi_step(c, k, cw, W.cap);
+        HIP_OK(hipStreamEndCapture(W.cap, &graph));
+        hipError_t e = hipGraphInstantiate(&W.exec[k], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            W.exec[k] = nullptr;
+            return fail(MG_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+    }
+    HIP_OK(hipGraphLaunch(W.exec[k], c->stream));
+    return MG_OK;
+}
+
 // Solve J delta = b (b = the Newton right-hand side planes of level 0) to
 // weighted relative residual rtol.  Returns the iteration count in *its.
 int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, double *relres) {
@@ -147,18 +227,8 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
         int k = 0;
         double est = beta;
         for (; k < m && total < maxit; ++k) {
-            double *vk = W.V + k * vs, *zk = W.Z + k * vs, *vk1 = W.V + (k + 1) * vs;
-            launch_fill(zk, vs, 0.0, s);
-            block_vcycle(c, 0, vk, zk);
-            launch_block_residual(g, J, nullptr, zk, W.w, true, s);  // w = J z_k
-            // classical Gram-Schmidt, twice
-            launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev, s);
-            launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev, -1.0, s);
-            launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev + (m + 1), s);
-            launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev + (m + 1), -1.0, s);
-            launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev + 2 * m + 2, s);
-            launch_scale_by_norm(g, W.w, vk1, p0, dev + 2 * m + 2, s);
-            HIP_OK(hipMemcpyAsync(host, dev, (2 * m + 3) * sizeof(double), hipMemcpyDeviceToHost, s));
+            int e = run_arnoldi(c, k, cw);
+            if (e) return e;
             HIP_OK(hipStreamSynchronize(s));
             for (int i = 0; i <= k; ++i) A.H[i][k] = host[i] + host[m + 1 + i];
             A.H[k + 1][k] = sqrt(host[2 * m + 2]);

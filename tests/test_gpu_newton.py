@@ -82,3 +82,36 @@ def test_steady_run_matches_oracle_33():
     for tt, ref in zip(t[:3], (V, ne, np_)):
         assert relmax(sol.download(tt), ref) <= 1e-9
     print("steady 33: steps %d, newton %d, fgmres %d" % (rep.steps, rep.newton_its, rep.vcycles))
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_fused_subcycle_and_graphs_match_eager(N, monkeypatch):
+    """The single-workgroup coarse sub-cycle and the captured Arnoldi graphs
+    (replayed many times, with eager work in between) give bitwise the same
+    Newton steps as per-level eager launches."""
+    _say("fused/graph", N)
+    m = M()
+    z, V, ne, np_, S = _start(N)
+    ph = dict(I.PHYS)
+    cp = NW.Coupled(N, N, 1.0, z, ph)
+    NW.steady(cp, V, ne, np_, S, S, max_steps=15)
+    results = {}
+    for fuse in (1, 0):
+        for graphs in (1, 0):
+            if fuse:
+                monkeypatch.delenv("MGF_NO_FUSE", raising=False)
+            else:
+                monkeypatch.setenv("MGF_NO_FUSE", "1")
+            if graphs:
+                monkeypatch.delenv("MGF_NO_GRAPHS", raising=False)
+            else:
+                monkeypatch.setenv("MGF_NO_GRAPHS", "1")
+            sol, t, st = _gpu(N, V, ne, np_, S, krylov_m=20)
+            sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-10, max_cycles=400, newton_tol=1e-10)
+            for dt in (1e-3, 1e-2, 0.1):
+                sol.step(m.Physics.of(ph), st, dt, sc)
+            results[(fuse, graphs)] = [sol.download(x) for x in t[:3]]
+    base = results[(0, 0)]
+    for key, res in results.items():
+        for a, b in zip(res, base):
+            assert np.array_equal(a, b), key
