@@ -111,6 +111,8 @@ struct BLevel {
     double *x, *r;  // 3-field correction and residual
     double *st;     // injected state (V, ne, np), levels >= 1
     double *cinvT;  // coarsest level: transposed inverse of the block matrix
+    // FP32 copies for the mixed-precision preconditioner
+    float *J32, *x32, *r32, *cinvT32;
 };
 
 struct NewtonWork {
@@ -124,6 +126,8 @@ struct NewtonWork {
     double *partials = nullptr;
     double *dev = nullptr;     // device scalars (dots, norms, y)
     double *scratch = nullptr; // coarsest factorisation workspace
+    float *f32 = nullptr;      // FP32 right-hand side of the preconditioner (level 0)
+    bool prec32 = false;       // block V-cycle in FP32 inside FP64 FGMRES
     // one captured graph per Arnoldi index k (block V-cycle, product,
     // orthogonalisation, readback), replayed on the context's stream
     hipStream_t cap = nullptr;

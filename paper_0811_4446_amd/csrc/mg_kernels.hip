@@ -682,17 +682,39 @@ __global__ void k_add_f32(Geom g, double *__restrict__ x, const float *__restric
     x[at(g, i, j)] += (double)e[at(g, i, j)];
 }
 
+// FP32 copy of a five-point operator that keeps its column sums.  Rounding
+// b on its own would bury the small part of the diagonal that makes the
+// matrix non-singular (vol/dt plus electrode outflow, next to fluxes many
+// orders larger), so b is rebuilt from the exact FP64 column excess
+// delta_i = b_i + sum of the entries of column i in the neighbour rows,
+// minus those neighbour entries as rounded to FP32.
+__device__ inline double col_nb_sum(const Geom &g, const double *a, const double *c, const double *d,
+                                    const double *e, int i, int j, bool f32round) {
+    double s = 0.0;
+    auto rd = [&](double v) { return f32round ? (double)(float)v : v; };
+    if (i > 0) s += rd(c[at(g, i - 1, j)]);       // row (i-1, j) couples to (i, j) through c
+    if (i < g.nr) s += rd(a[at(g, i + 1, j)]);    // row (i+1, j) through a
+    if (j > 1) s += rd(e[at(g, i, j - 1)]);       // row (i, j-1) through e
+    if (j < g.nz - 1) s += rd(d[at(g, i, j + 1)]);  // row (i, j+1) through d
+    return s;
+}
+
 __global__ void k_op_to_f32(Geom g, Op<double> o, Op<float> o32) {
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     int64_t p = at(g, i, j);
     o32.a[p] = (float)o.a[p];
-    o32.b[p] = (float)o.b[p];
     o32.c[p] = (float)o.c[p];
     o32.d[p] = (float)o.d[p];
     o32.e[p] = (float)o.e[p];
     o32.f[p] = 0.0f;
+    if (j == 0 || j == g.nz) {
+        o32.b[p] = (float)o.b[p];
+        return;
+    }
+    double excess = o.b[p] + col_nb_sum(g, o.a, o.c, o.d, o.e, i, j, false);
+    o32.b[p] = (float)(excess - col_nb_sum(g, o.a, o.c, o.d, o.e, i, j, true));
 }
 
 }  // namespace

@@ -8,25 +8,28 @@ constexpr int kMaxKrylov = 40;
 constexpr int kBPlanes = 30;
 constexpr int kEE = 0, kEV = 5, kPP = 10, kPV = 15, kVV = 20, kVe = 25, kVp = 26, kFe = 27, kFp = 28, kFV = 29;
 
-// Block operator: kBPlanes planes of (nr+1) x pitch doubles.
-struct BOp {
-    double *base;
+// Block operator: kBPlanes planes of (nr+1) x pitch values.
+template <class T>
+struct BOpT {
+    T *base;
     int64_t plane;
-    __host__ __device__ double *pl(int k) const { return base + (int64_t)k * plane; }
+    __host__ __device__ T *pl(int k) const { return base + (int64_t)k * plane; }
 };
+using BOp = BOpT<double>;
 
 // Levels run by the single-workgroup coarse sub-cycle (last = coarsest).
 constexpr int kMaxFused = 8;
 constexpr int kMaxFusedCoarse = 1024;  // 3 x unknown nodes of the coarsest level
-struct FusedLevels {
+template <class T>
+struct FusedLevelsT {
     int n, nu1, nu2;
     Geom g[kMaxFused];
-    double *J[kMaxFused];
+    T *J[kMaxFused];
     int64_t plane[kMaxFused];
-    double *x[kMaxFused];
-    double *r[kMaxFused];
-    const double *f0;
-    const double *invT;
+    T *x[kMaxFused];
+    T *r[kMaxFused];
+    const T *f0;
+    const T *invT;
 };
 
 struct NewtonPhys {
@@ -37,20 +40,26 @@ struct NewtonPhys {
 void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
                             const double *nek, const double *npk, const double *Se, const double *Sp,
                             const NewtonPhys &ph, bool with_rhs, hipStream_t s);
-void launch_block_rbgs(const Geom &g, const BOp &J, const double *f, double *x, int colour, hipStream_t s);
-void launch_block_residual(const Geom &g, const BOp &J, const double *f, const double *x, double *r, bool apply,
+template <class T>
+void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s);
+template <class T>
+void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s);
-void launch_restrict3(const Geom &gf, const double *rf, int64_t pf, const Geom &gc, double *fc, int64_t pc,
-                      hipStream_t s);
-void launch_prolong3(const Geom &gf, double *xf, int64_t pf, const Geom &gc, const double *xc, int64_t pc,
-                     hipStream_t s);
+template <class T>
+void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc, int64_t pc, hipStream_t s);
+template <class T>
+void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s);
 void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
                     double *out, int64_t pc, hipStream_t s);
 void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s);
-void launch_block_coarse_solve(const Geom &g, const BOp &J, const double *f, const double *invT, double *x,
-                               hipStream_t s);
+template <class T>
+void launch_block_coarse_solve(const Geom &g, const BOpT<T> &J, const T *f, const T *invT, T *x, hipStream_t s);
 int block_vec_blocks(const Geom &g);
-void launch_block_subcycle(const FusedLevels &F, hipStream_t s);
+template <class T>
+void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s);
+void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s);
+void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s);
 void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
                        int64_t plane, double3 cw, double *partials, double *out, hipStream_t s);
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,

@@ -155,19 +155,20 @@ __global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, c
 }
 
 // Sum over the four neighbours of B_nb x_nb for the three rows.
-inline __device__ void nb_sum(const Geom &g, const BOp &J, const double *x, int64_t plane, int i, int64_t p,
-                              double &se, double &sp, double &sv) {
-    const double *xe = x, *xp = x + plane, *xv = x + 2 * plane;
+template <class T>
+inline __device__ void nb_sum(const Geom &g, const BOpT<T> &J, const T *x, int64_t plane, int i, int64_t p,
+                              T &se, T &sp, T &sv) {
+    const T *xe = x, *xp = x + plane, *xv = x + 2 * plane;
     int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
     int dirs[4] = {0, 2, 3, 4};
     bool has[4] = {i > 0, i < g.nr, true, true};
-    se = sp = sv = 0.0;
+    se = sp = sv = T(0);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         if (!has[t]) continue;
         int d = dirs[t];
         int64_t q = nbp[t];
-        double v = xv[q];
+        T v = xv[q];
         se += J.pl(kEE + d)[p] * xe[q] + J.pl(kEV + d)[p] * v;
         sp += J.pl(kPP + d)[p] * xp[q] + J.pl(kPV + d)[p] * v;
         sv += J.pl(kVV + d)[p] * v;
@@ -177,16 +178,17 @@ inline __device__ void nb_sum(const Geom &g, const BOp &J, const double *x, int6
 // Collective Gauss-Seidel update of one node: the 3x3 centre block is
 // solved exactly for (n_e, n_p, V) with the neighbours held fixed.  The block
 // [[ee,0,eV],[0,pp,pV],[Ve,Vp,VV]] is reduced to the potential first.
-inline __device__ void block_gs_node(const Geom &g, const BOp &J, const double *f, double *x, int i, int j) {
+template <class T>
+inline __device__ void block_gs_node(const Geom &g, const BOpT<T> &J, const T *f, T *x, int i, int j) {
     int64_t p = at(g, i, j);
     int64_t plane = J.plane;
-    double se, sp, sv;
+    T se, sp, sv;
     nb_sum(g, J, x, plane, i, p, se, sp, sv);
-    double re = f[p] - se, rp = f[p + plane] - sp, rv = f[p + 2 * plane] - sv;
-    double ee = J.pl(kEE + 1)[p], eV = J.pl(kEV + 1)[p], pp = J.pl(kPP + 1)[p], pV = J.pl(kPV + 1)[p];
-    double VV = J.pl(kVV + 1)[p], Ve = J.pl(kVe)[p], Vp = J.pl(kVp)[p];
-    double a = Ve / ee, b = Vp / pp;
-    double xv = (rv - a * re - b * rp) / (VV - a * eV - b * pV);
+    T re = f[p] - se, rp = f[p + plane] - sp, rv = f[p + 2 * plane] - sv;
+    T ee = J.pl(kEE + 1)[p], eV = J.pl(kEV + 1)[p], pp = J.pl(kPP + 1)[p], pV = J.pl(kPV + 1)[p];
+    T VV = J.pl(kVV + 1)[p], Ve = J.pl(kVe)[p], Vp = J.pl(kVp)[p];
+    T a = Ve / ee, b = Vp / pp;
+    T xv = (rv - a * re - b * rp) / (VV - a * eV - b * pV);
     x[p] = (re - eV * xv) / ee;
     x[p + plane] = (rp - pV * xv) / pp;
     x[p + 2 * plane] = xv;
@@ -194,7 +196,8 @@ inline __device__ void block_gs_node(const Geom &g, const BOp &J, const double *
 
 // Red-black half-sweep: every unknown node with (i+j)%2 == colour.  Nodes of
 // one colour only read nodes of the other colour.
-__global__ void k_block_rbgs(Geom g, BOp J, const double *__restrict__ f, double *__restrict__ x, int colour) {
+template <class T>
+__global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__restrict__ x, int colour) {
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j < 1 || j >= g.nz || ((i + j) & 1) != colour) return;
@@ -203,16 +206,17 @@ __global__ void k_block_rbgs(Geom g, BOp J, const double *__restrict__ f, double
 
 // r = f - B x (apply == 0) or r = B x (apply == 1) at one node, 3 fields,
 // 0 on the electrode rows.
-inline __device__ void block_residual_node(const Geom &g, const BOp &J, const double *f, const double *x,
-                                           double *r, int apply, int i, int j) {
+template <class T>
+inline __device__ void block_residual_node(const Geom &g, const BOpT<T> &J, const T *f, const T *x,
+                                           T *r, int apply, int i, int j) {
     int64_t p = at(g, i, j), plane = J.plane;
     if (j == 0 || j == g.nz) {
-        r[p] = r[p + plane] = r[p + 2 * plane] = 0.0;
+        r[p] = r[p + plane] = r[p + 2 * plane] = T(0);
         return;
     }
-    double se, sp, sv;
+    T se, sp, sv;
     nb_sum(g, J, x, plane, i, p, se, sp, sv);
-    double xe = x[p], xp = x[p + plane], xv = x[p + 2 * plane];
+    T xe = x[p], xp = x[p + plane], xv = x[p + 2 * plane];
     se += J.pl(kEE + 1)[p] * xe + J.pl(kEV + 1)[p] * xv;
     sp += J.pl(kPP + 1)[p] * xp + J.pl(kPV + 1)[p] * xv;
     sv += J.pl(kVV + 1)[p] * xv + J.pl(kVe)[p] * xe + J.pl(kVp)[p] * xp;
@@ -227,8 +231,9 @@ inline __device__ void block_residual_node(const Geom &g, const BOp &J, const do
     }
 }
 
-__global__ void k_block_residual(Geom g, BOp J, const double *__restrict__ f, const double *__restrict__ x,
-                                 double *__restrict__ r, int apply) {
+template <class T>
+__global__ void k_block_residual(Geom g, BOpT<T> J, const T *__restrict__ f, const T *__restrict__ x,
+                                 T *__restrict__ r, int apply) {
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
@@ -237,23 +242,24 @@ __global__ void k_block_residual(Geom g, BOp J, const double *__restrict__ f, co
 
 // Three-field restriction (P^T of the bilinear prolongation), same weights
 // as the scalar path, at coarse node (I, J_).
-inline __device__ void restrict3_node(const Geom &gf, const double *rf, int64_t pf, const Geom &gc, double *fc,
+template <class T>
+inline __device__ void restrict3_node(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc,
                                       int64_t pc, int I, int J_) {
     int64_t q = at(gc, I, J_);
     if (J_ == 0 || J_ == gc.nz) {
-        fc[q] = fc[q + pc] = fc[q + 2 * pc] = 0.0;
+        fc[q] = fc[q + pc] = fc[q + 2 * pc] = T(0);
         return;
     }
-    double wdn = 1.0 - gf.wl[J_ - 1], wup = gf.wl[J_];
-    double acc[3] = {0, 0, 0};
+    T wdn = T(1) - gf.wl[J_ - 1], wup = gf.wl[J_];
+    T acc[3] = {0, 0, 0};
     for (int di = -1; di <= 1; ++di) {
         int i = 2 * I + di;
         if (i < 0 || i > gf.nr) continue;
-        double wi = (di == 0) ? 1.0 : 0.5;
+        T wi = (di == 0) ? T(1) : T(0.5);
         int64_t p = at(gf, i, 2 * J_);
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            const double *r = rf + f * pf;
+            const T *r = rf + f * pf;
             acc[f] += wi * (wdn * r[p - 1] + r[p] + wup * r[p + 1]);
         }
     }
@@ -262,7 +268,8 @@ inline __device__ void restrict3_node(const Geom &gf, const double *rf, int64_t 
     fc[q + 2 * pc] = acc[2];
 }
 
-__global__ void k_restrict3(Geom gf, const double *__restrict__ rf, int64_t pf, Geom gc, double *__restrict__ fc,
+template <class T>
+__global__ void k_restrict3(Geom gf, const T *__restrict__ rf, int64_t pf, Geom gc, T *__restrict__ fc,
                             int64_t pc) {
     int J_ = blockIdx.x * kTX + threadIdx.x;
     int I = blockIdx.y * kTY + threadIdx.y;
@@ -271,28 +278,30 @@ __global__ void k_restrict3(Geom gf, const double *__restrict__ rf, int64_t pf, 
 }
 
 // Bilinear prolongation of the coarse correction, added at fine node (i, j).
-inline __device__ void prolong3_node(const Geom &gf, double *xf, int64_t pf, const Geom &gc, const double *xc,
+template <class T>
+inline __device__ void prolong3_node(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc,
                                      int64_t pc, int i, int j) {
     int I0 = i >> 1, I1 = (i + 1) >> 1;
     int64_t p = at(gf, i, j);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        const double *c = xc + f * pc;
-        double v0, v1;
+        const T *c = xc + f * pc;
+        T v0, v1;
         if ((j & 1) == 0) {
             v0 = c[at(gc, I0, j >> 1)];
             v1 = c[at(gc, I1, j >> 1)];
         } else {
             int J_ = j >> 1;
-            double wl = gf.wl[J_], wu = 1.0 - wl;
+            T wl = gf.wl[J_], wu = T(1) - wl;
             v0 = wl * c[at(gc, I0, J_)] + wu * c[at(gc, I0, J_ + 1)];
             v1 = wl * c[at(gc, I1, J_)] + wu * c[at(gc, I1, J_ + 1)];
         }
-        xf[p + f * pf] += (i & 1) ? 0.5 * (v0 + v1) : v0;
+        xf[p + f * pf] += (i & 1) ? T(0.5) * (v0 + v1) : v0;
     }
 }
 
-__global__ void k_prolong3(Geom gf, double *__restrict__ xf, int64_t pf, Geom gc, const double *__restrict__ xc,
+template <class T>
+__global__ void k_prolong3(Geom gf, T *__restrict__ xf, int64_t pf, Geom gc, const T *__restrict__ xc,
                            int64_t pc) {
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
@@ -458,8 +467,9 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
 
 // x = A^{-1} f on the coarsest grid by the whole workgroup (rhs staged in
 // `rhs`, at least 3 * nodes doubles of LDS).
-inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const double *f, const double *invT,
-                                             double *x, double *rhs) {
+template <class T>
+inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const T *f, const T *invT,
+                                             T *x, T *rhs) {
     const int m = g.nz - 1;
     const int nn = (g.nr + 1) * m;
     const int n = 3 * nn;
@@ -472,7 +482,7 @@ inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const
     }
     __syncthreads();
     for (int row = threadIdx.x; row < n; row += blockDim.x) {
-        double acc = 0.0;
+        T acc = T(0);
         for (int k = 0; k < n; ++k) acc += invT[(int64_t)k * n + row] * rhs[k];
         int node = row / 3, fl = row % 3;
         int i = node / m, j = node % m + 1;
@@ -480,10 +490,11 @@ inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const
     }
 }
 
-__global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOp J, const double *__restrict__ f,
-                                                             const double *__restrict__ invT,
-                                                             double *__restrict__ x) {
-    __shared__ double rhs[3 * kMaxCoarseUnknowns];
+template <class T>
+__global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOpT<T> J, const T *__restrict__ f,
+                                                             const T *__restrict__ invT,
+                                                             T *__restrict__ x) {
+    __shared__ T rhs[3 * kMaxCoarseUnknowns];
     block_coarse_solve_wg(g, J.plane, f, invT, x, rhs);
 }
 
@@ -494,21 +505,22 @@ __global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOp J, cons
 // residual, restriction, coarse solve and prolongation with barriers in
 // between, node by node exactly as the per-level kernels do.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevels F) {
-    __shared__ double rhs[3 * kMaxFusedCoarse];
+template <class T>
+__global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F) {
+    __shared__ T rhs[3 * kMaxFusedCoarse];
     const int n = F.n;
     const int nt = blockDim.x;
     for (int q = 0; q < n - 1; ++q) {
         const Geom &g = F.g[q];
-        BOp J{F.J[q], F.plane[q]};
-        const double *f = (q == 0) ? F.f0 : J.pl(kFe);
-        double *x = F.x[q];
+        BOpT<T> J{F.J[q], F.plane[q]};
+        const T *f = (q == 0) ? F.f0 : J.pl(kFe);
+        T *x = F.x[q];
         const int nodes = (g.nr + 1) * (g.nz + 1);
         if (q > 0) {
             for (int t = threadIdx.x; t < nodes; t += nt) {
                 int i = t / (g.nz + 1), j = t % (g.nz + 1);
                 int64_t p = at(g, i, j);
-                x[p] = x[p + J.plane] = x[p + 2 * J.plane] = 0.0;
+                x[p] = x[p + J.plane] = x[p + 2 * J.plane] = T(0);
             }
             __syncthreads();
         }
@@ -526,7 +538,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevels F) {
         }
         __syncthreads();
         const Geom &gc = F.g[q + 1];
-        BOp Jc{F.J[q + 1], F.plane[q + 1]};
+        BOpT<T> Jc{F.J[q + 1], F.plane[q + 1]};
         const int cnodes = (gc.nr + 1) * (gc.nz + 1);
         for (int t = threadIdx.x; t < cnodes; t += nt) {
             int I = t / (gc.nz + 1), J_ = t % (gc.nz + 1);
@@ -536,16 +548,16 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevels F) {
     }
     {
         const int q = n - 1;
-        BOp J{F.J[q], F.plane[q]};
-        const double *f = (q == 0) ? F.f0 : J.pl(kFe);
+        BOpT<T> J{F.J[q], F.plane[q]};
+        const T *f = (q == 0) ? F.f0 : J.pl(kFe);
         block_coarse_solve_wg(F.g[q], J.plane, f, F.invT, F.x[q], rhs);
         __syncthreads();
     }
     for (int q = n - 2; q >= 0; --q) {
         const Geom &g = F.g[q];
-        BOp J{F.J[q], F.plane[q]};
-        const double *f = (q == 0) ? F.f0 : J.pl(kFe);
-        double *x = F.x[q];
+        BOpT<T> J{F.J[q], F.plane[q]};
+        const T *f = (q == 0) ? F.f0 : J.pl(kFe);
+        T *x = F.x[q];
         const int nodes = (g.nr + 1) * (g.nz + 1);
         for (int t = threadIdx.x; t < nodes; t += nt) {
             int i = t / (g.nz + 1), j = t % (g.nz + 1);
@@ -716,20 +728,22 @@ void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const 
                             const NewtonPhys &ph, bool with_rhs, hipStream_t s) {
     k_newton_assemble<<<grid2d(g), kB2, 0, s>>>(g, J, V, ne, np, nek, npk, Se, Sp, ph, with_rhs ? 1 : 0);
 }
-void launch_block_rbgs(const Geom &g, const BOp &J, const double *f, double *x, int colour, hipStream_t s) {
-    k_block_rbgs<<<grid2d(g), kB2, 0, s>>>(g, J, f, x, colour);
+template <class T>
+void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s) {
+    k_block_rbgs<T><<<grid2d(g), kB2, 0, s>>>(g, J, f, x, colour);
 }
-void launch_block_residual(const Geom &g, const BOp &J, const double *f, const double *x, double *r, bool apply,
+template <class T>
+void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s) {
-    k_block_residual<<<grid2d(g), kB2, 0, s>>>(g, J, f, x, r, apply ? 1 : 0);
+    k_block_residual<T><<<grid2d(g), kB2, 0, s>>>(g, J, f, x, r, apply ? 1 : 0);
 }
-void launch_restrict3(const Geom &gf, const double *rf, int64_t pf, const Geom &gc, double *fc, int64_t pc,
-                      hipStream_t s) {
-    k_restrict3<<<grid2d(gc), kB2, 0, s>>>(gf, rf, pf, gc, fc, pc);
+template <class T>
+void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc, int64_t pc, hipStream_t s) {
+    k_restrict3<T><<<grid2d(gc), kB2, 0, s>>>(gf, rf, pf, gc, fc, pc);
 }
-void launch_prolong3(const Geom &gf, double *xf, int64_t pf, const Geom &gc, const double *xc, int64_t pc,
-                     hipStream_t s) {
-    k_prolong3<<<grid2d(gf), kB2, 0, s>>>(gf, xf, pf, gc, xc, pc);
+template <class T>
+void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s) {
+    k_prolong3<T><<<grid2d(gf), kB2, 0, s>>>(gf, xf, pf, gc, xc, pc);
 }
 void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
                     double *out, int64_t pc, hipStream_t s) {
@@ -742,11 +756,14 @@ void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, do
     else
         k_block_coarse_factor<<<1, 1024, 0, s>>>(g, J, scratch, invT);
 }
-void launch_block_coarse_solve(const Geom &g, const BOp &J, const double *f, const double *invT, double *x,
-                               hipStream_t s) {
-    k_block_coarse_solve<<<1, 1024, 0, s>>>(g, J, f, invT, x);
+template <class T>
+void launch_block_coarse_solve(const Geom &g, const BOpT<T> &J, const T *f, const T *invT, T *x, hipStream_t s) {
+    k_block_coarse_solve<T><<<1, 1024, 0, s>>>(g, J, f, invT, x);
 }
-void launch_block_subcycle(const FusedLevels &F, hipStream_t s) { k_block_subcycle<<<1, 1024, 0, s>>>(F); }
+template <class T>
+void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s) {
+    k_block_subcycle<T><<<1, 1024, 0, s>>>(F);
+}
 int block_vec_blocks(const Geom &g) {
     dim3 gr = grid2d(g);
     return (int)(gr.x * gr.y);
@@ -771,5 +788,83 @@ void launch_newton_update(const Geom &g, double *V, double *ne, double *np, cons
     k_newton_update<<<gr, kB2, 0, s>>>(g, V, ne, np, du, plane, partials);
     k_reduce_newton<<<1, 256, 0, s>>>(partials, (int)(gr.x * gr.y), out);
 }
+
+// FP32 copy of the block Jacobian: every plane rounded, except the diagonal
+// entries of the three five-point blocks (ee, pp, VV), which are rebuilt from
+// their exact FP64 column excess minus the rounded neighbour entries of the
+// same column (see k_op_to_f32 for the reason).
+__global__ void k_block_to_f32(Geom g, BOp J, BOpT<float> J32) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * kTY + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    int64_t p = at(g, i, j);
+    for (int k = 0; k < kBPlanes; ++k) J32.pl(k)[p] = (float)J.pl(k)[p];
+    if (j == 0 || j == g.nz) return;
+    const int kinds[3] = {kEE, kPP, kVV};
+    for (int t = 0; t < 3; ++t) {
+        const int K = kinds[t];
+        double ex = J.pl(K + 1)[p], r32 = 0.0;
+        if (i > 0) {
+            double v = J.pl(K + 2)[p - g.pitch];
+            ex += v;
+            r32 += (double)(float)v;
+        }
+        if (i < g.nr) {
+            double v = J.pl(K + 0)[p + g.pitch];
+            ex += v;
+            r32 += (double)(float)v;
+        }
+        if (j > 1) {
+            double v = J.pl(K + 4)[p - 1];
+            ex += v;
+            r32 += (double)(float)v;
+        }
+        if (j < g.nz - 1) {
+            double v = J.pl(K + 3)[p + 1];
+            ex += v;
+            r32 += (double)(float)v;
+        }
+        J32.pl(K + 1)[p] = (float)(ex - r32);
+    }
+}
+void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s) {
+    k_block_to_f32<<<grid2d(g), kB2, 0, s>>>(g, J, J32);
+}
+
+// planes -> FP32 copies (n planes of `plane` elements)
+__global__ void k_planes_to_f32(const double *__restrict__ src, float *__restrict__ dst, int64_t n) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; t < n; t += stride) dst[t] = (float)src[t];
+}
+__global__ void k_planes_to_f64(const float *__restrict__ src, double *__restrict__ dst, int64_t n) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; t < n; t += stride) dst[t] = (double)src[t];
+}
+void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    k_planes_to_f32<<<(unsigned)b, 256, 0, s>>>(src, dst, n);
+}
+void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    k_planes_to_f64<<<(unsigned)b, 256, 0, s>>>(src, dst, n);
+}
+
+#define MGF_INST(T)                                                                                          \
+    template void launch_block_rbgs<T>(const Geom &, const BOpT<T> &, const T *, T *, int, hipStream_t);     \
+    template void launch_block_residual<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
+                                           hipStream_t);                                                     \
+    template void launch_restrict3<T>(const Geom &, const T *, int64_t, const Geom &, T *, int64_t,          \
+                                      hipStream_t);                                                          \
+    template void launch_prolong3<T>(const Geom &, T *, int64_t, const Geom &, const T *, int64_t,           \
+                                     hipStream_t);                                                           \
+    template void launch_block_coarse_solve<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *,     \
+                                               hipStream_t);                                                 \
+    template void launch_block_subcycle<T>(const FusedLevelsT<T> &, hipStream_t);
+MGF_INST(double)
+MGF_INST(float)
 
 }  // namespace mgf

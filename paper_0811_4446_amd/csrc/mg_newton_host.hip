@@ -17,6 +17,23 @@ int64_t plane_of(const Level &L) { return (int64_t)(L.g.nr + 1) * L.g.pitch; }
 
 BOp bop(mg_ctx *c, int l) { return BOp{c->nw.lev[l].J, plane_of(c->lev[l])}; }
 
+template <class T>
+struct Prec;
+template <>
+struct Prec<double> {
+    static BOpT<double> op(mg_ctx *c, int l) { return BOpT<double>{c->nw.lev[l].J, plane_of(c->lev[l])}; }
+    static double *x(mg_ctx *c, int l) { return c->nw.lev[l].x; }
+    static double *r(mg_ctx *c, int l) { return c->nw.lev[l].r; }
+    static const double *inv(mg_ctx *c) { return c->nw.lev[c->nlev - 1].cinvT; }
+};
+template <>
+struct Prec<float> {
+    static BOpT<float> op(mg_ctx *c, int l) { return BOpT<float>{c->nw.lev[l].J32, plane_of(c->lev[l])}; }
+    static float *x(mg_ctx *c, int l) { return c->nw.lev[l].x32; }
+    static float *r(mg_ctx *c, int l) { return c->nw.lev[l].r32; }
+    static const float *inv(mg_ctx *c) { return c->nw.lev[c->nlev - 1].cinvT32; }
+};
+
 // Field weights of the inner product: Poisson rows are scaled by 1/k so that
 // all three equations are measured in density units.
 double3 field_weights(const mg_physics *ph) {
@@ -26,45 +43,46 @@ double3 field_weights(const mg_physics *ph) {
 // Levels at or below this size run in the single-workgroup sub-cycle.
 constexpr int kFuseMaxN = 32;
 
-void block_vcycle(mg_ctx *c, int l, const double *f, double *x, hipStream_t s) {
+template <class T>
+void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     const Level &L = c->lev[l];
-    BOp J = bop(c, l);
-    BLevel &B = c->nw.lev[l];
+    BOpT<T> J = Prec<T>::op(c, l);
     if (c->nw.fuse && L.g.nr <= kFuseMaxN && L.g.nz <= kFuseMaxN && c->nlev - l <= kMaxFused) {
-        FusedLevels F;
+        FusedLevelsT<T> F;
         memset(&F, 0, sizeof F);
         F.n = c->nlev - l;
         F.nu1 = c->desc.nu1;
         F.nu2 = c->desc.nu2;
         for (int q = 0; q < F.n; ++q) {
             F.g[q] = c->lev[l + q].g;
-            F.J[q] = c->nw.lev[l + q].J;
+            F.J[q] = Prec<T>::op(c, l + q).base;
             F.plane[q] = plane_of(c->lev[l + q]);
-            F.x[q] = (q == 0) ? x : c->nw.lev[l + q].x;
-            F.r[q] = c->nw.lev[l + q].r;
+            F.x[q] = (q == 0) ? x : Prec<T>::x(c, l + q);
+            F.r[q] = Prec<T>::r(c, l + q);
         }
         F.f0 = f;
-        F.invT = c->nw.lev[c->nlev - 1].cinvT;
-        launch_block_subcycle(F, s);
+        F.invT = Prec<T>::inv(c);
+        launch_block_subcycle<T>(F, s);
         return;
     }
     if (l == c->nlev - 1) {
-        launch_block_coarse_solve(L.g, J, f, B.cinvT, x, s);
+        launch_block_coarse_solve<T>(L.g, J, f, Prec<T>::inv(c), x, s);
         return;
     }
     for (int k = 0; k < c->desc.nu1; ++k)
-        for (int col = 0; col < 2; ++col) launch_block_rbgs(L.g, J, f, x, col, s);
-    launch_block_residual(L.g, J, f, x, B.r, false, s);
+        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(L.g, J, f, x, col, s);
+    T *r = Prec<T>::r(c, l);
+    launch_block_residual<T>(L.g, J, f, x, r, false, s);
     const Level &C = c->lev[l + 1];
-    BOp Jc = bop(c, l + 1);
-    double *fc = Jc.pl(kFe);
-    launch_restrict3(L.g, B.r, plane_of(L), C.g, fc, plane_of(C), s);
-    double *xc = c->nw.lev[l + 1].x;
-    launch_fill(xc, 3 * plane_of(C), 0.0, s);
-    block_vcycle(c, l + 1, fc, xc, s);
-    launch_prolong3(L.g, x, plane_of(L), C.g, xc, plane_of(C), s);
+    BOpT<T> Jc = Prec<T>::op(c, l + 1);
+    T *fc = Jc.pl(kFe);
+    launch_restrict3<T>(L.g, r, plane_of(L), C.g, fc, plane_of(C), s);
+    T *xc = Prec<T>::x(c, l + 1);
+    launch_fill(xc, 3 * plane_of(C), T(0), s);
+    block_vcycle<T>(c, l + 1, fc, xc, s);
+    launch_prolong3<T>(L.g, x, plane_of(L), C.g, xc, plane_of(C), s);
     for (int k = 0; k < c->desc.nu2; ++k)
-        for (int col = 0; col < 2; ++col) launch_block_rbgs(L.g, J, f, x, col, s);
+        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(L.g, J, f, x, col, s);
 }
 
 // Assemble the Jacobian on every level: level 0 at the current state with
@@ -95,6 +113,13 @@ void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt
     }
     const Level &Lc = c->lev[c->nlev - 1];
     launch_block_coarse_factor(Lc.g, bop(c, c->nlev - 1), c->nw.scratch, c->nw.lev[c->nlev - 1].cinvT, s);
+    if (c->nw.prec32) {
+        // FP32 copies of every level's Jacobian and of the coarsest inverse
+        for (int l = 0; l < c->nlev; ++l)
+            launch_block_to_f32(c->lev[l].g, bop(c, l), BOpT<float>{c->nw.lev[l].J32, plane_of(c->lev[l])}, s);
+        int64_t n = 3 * (int64_t)(Lc.g.nr + 1) * (Lc.g.nz - 1);
+        launch_planes_to_f32(c->nw.lev[c->nlev - 1].cinvT, c->nw.lev[c->nlev - 1].cinvT32, n * n, s);
+    }
 }
 
 // Givens-rotation least squares of the Arnoldi relation (host, small).
@@ -144,9 +169,18 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     const int m = W.m;
     double *dev = W.dev;
     double *vk = W.V + k * vs, *zk = W.Z + k * vs, *vk1 = W.V + (k + 1) * vs;
-    launch_fill(zk, vs, 0.0, s);
-    block_vcycle(c, 0, vk, zk, s);
-    launch_block_residual(g, J, nullptr, zk, W.w, true, s);  // w = J z_k
+    if (W.prec32) {
+        // preconditioner in FP32: z_k = M32 v_k (the Krylov space stays FP64)
+        float *x32 = W.lev[0].x32;
+        launch_planes_to_f32(vk, W.f32, vs, s);
+        launch_fill(x32, vs, 0.0f, s);
+        block_vcycle<float>(c, 0, W.f32, x32, s);
+        launch_planes_to_f64(x32, zk, vs, s);
+    } else {
+        launch_fill(zk, vs, 0.0, s);
+        block_vcycle<double>(c, 0, vk, zk, s);
+    }
+    launch_block_residual<double>(g, J, nullptr, zk, W.w, true, s);  // w = J z_k
     launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev, s);
     launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev, -1.0, s);
     launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev + (m + 1), s);
@@ -247,7 +281,7 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
         HIP_OK(hipMemcpyAsync(dev + 3 * m + 8, host, k * sizeof(double), hipMemcpyHostToDevice, s));
         launch_axpy_multi(g, W.delta, W.Z, vs, k, p0, dev + 3 * m + 8, 1.0, s);
         // true residual for the restart / final check
-        launch_block_residual(g, J, b, W.delta, W.w, false, s);
+        launch_block_residual<double>(g, J, b, W.delta, W.w, false, s);
         launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev, s);
         HIP_OK(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
@@ -353,9 +387,16 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
         B.x = cv.take<double>(3 * pl);
         B.r = cv.take<double>(3 * pl);
         B.st = (l > 0) ? cv.take<double>(3 * pl) : nullptr;
+        bool p32 = d->prec == MG_FP32_IR;
+        if (p32) {
+            B.J32 = cv.take<float>(kBPlanes * pl);
+            B.x32 = cv.take<float>(3 * pl);
+            B.r32 = cv.take<float>(3 * pl);
+        }
         if (l == nl - 1) {
             int64_t n = 3 * (int64_t)(nr + 1) * (nz - 1);
             B.cinvT = cv.take<double>(n * n);
+            if (p32) B.cinvT32 = cv.take<float>(n * n);
             double *scr = cv.take<double>(n * 2 * n);
             if (c) c->nw.scratch = scr;
         }
@@ -369,7 +410,10 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
     int nblk = ((d->nz + 1 + 63) / 64) * ((d->nr + 1 + 3) / 4);
     double *part = cv.take<double>((int64_t)nblk * (m + 2) + (int64_t)nblk * 8 + 64);
     double *dev = cv.take<double>(4 * kMaxKrylov + 64);
+    float *f32 = (d->prec == MG_FP32_IR) ? cv.take<float>(3 * p0) : nullptr;
     if (c) {
+        c->nw.f32 = f32;
+        c->nw.prec32 = d->prec == MG_FP32_IR;
         c->nw.V = V;
         c->nw.Z = Z;
         c->nw.w = w;
@@ -456,9 +500,9 @@ int time_block_smoother(mg_ctx *c, int reps, double *avg_ms) {
     hipEvent_t a, b;
     HIP_OK(hipEventCreate(&a));
     HIP_OK(hipEventCreate(&b));
-    launch_block_rbgs(L0.g, J, J.pl(kFe), x, 0, c->stream);
+    launch_block_rbgs<double>(L0.g, J, J.pl(kFe), x, 0, c->stream);
     HIP_OK(hipEventRecord(a, c->stream));
-    for (int r = 0; r < reps; ++r) launch_block_rbgs(L0.g, J, J.pl(kFe), x, r & 1, c->stream);
+    for (int r = 0; r < reps; ++r) launch_block_rbgs<double>(L0.g, J, J.pl(kFe), x, r & 1, c->stream);
     HIP_OK(hipEventRecord(b, c->stream));
     HIP_OK(hipEventSynchronize(b));
     float ms = 0;
