@@ -40,15 +40,16 @@ def schedule(M, lin_rtol):
                       newton_tol=1e-6)
 
 
-def chain_to(M, I, N_final, vtop, lin_rtol, seed=0, N0=64):
+def chain_to(M, I, N_final, vtop, lin_rtol, seed=0, N0=64, prec=None):
     """Steady runs N0 -> ... -> N_final/2, then prolong to N_final.  Returns
     the fine solver and its initial (V, ne, np, S) device fields."""
+    prec = M.FP64 if prec is None else prec
     phys = dict(I.PHYS)
     phys["V_top"] = vtop
     P = M.Physics.of(phys)
     N = N0
     z = I.z_cos(N)
-    sol = M.Solver(N, N, z, krylov_m=30, coarsest=4)
+    sol = M.Solver(N, N, z, krylov_m=30, coarsest=4, prec=prec)
     ne = I.initial_density(N, N, seed)
     t = [sol.upload(I.initial_potential(N, N, z, 0.0, vtop)), sol.upload(ne), sol.upload(ne),
          sol.upload(I.source(N, N, z))]
@@ -64,12 +65,12 @@ def chain_to(M, I, N_final, vtop, lin_rtol, seed=0, N0=64):
             break
         N2 = 2 * N
         z2 = I.z_cos(N2)
-        fine = M.Solver(N2, N2, z2, krylov_m=30, coarsest=4)
+        fine = M.Solver(N2, N2, z2, krylov_m=30, coarsest=4, prec=prec)
         t2 = [fine.field(), fine.field(), fine.field(), fine.upload(I.source(N2, N2, z2))]
         M.prolong_state(sol, st, fine, fine.state(t2[0], t2[1], t2[2], t2[3], t2[3]), P)
         sol, t, N = fine, t2, N2
     z2 = I.z_cos(N_final)
-    fine = M.Solver(N_final, N_final, z2, krylov_m=30, coarsest=4)
+    fine = M.Solver(N_final, N_final, z2, krylov_m=30, coarsest=4, prec=prec)
     t2 = [fine.field(), fine.field(), fine.field(), fine.upload(I.source(N_final, N_final, z2))]
     M.prolong_state(sol, sol.state(t[0], t[1], t[2], t[3], t[3]), fine,
                     fine.state(t2[0], t2[1], t2[2], t2[3], t2[3]), P)
@@ -104,6 +105,51 @@ def cpu_baseline(I, newton_its_gpu, vtop=1.0, N=256):
                                                                                  newton_its_gpu))
 
 
+def compare_precisions(args, M, I, N, vtops):
+    """Time-to-steady of the finest stage with the FP64 and the FP32 block
+    preconditioner (Newton residuals, FGMRES and the stop rules in FP64), from
+    the same prolonged state; reports both and their difference."""
+    import numpy as np
+    import torch
+    forms = ["fp64", "fp32"] if args.prec == "both" else [args.prec]
+    rows = []
+    for vt in vtops:
+        fine, t, P, info = chain_to(M, I, N, vt, args.lin_rtol)
+        log("prep V_top=%g: %s" % (vt, info))
+        init = [x.clone() for x in t[:3]]
+        finals = {}
+        for form in forms:
+            prec = M.FP64 if form == "fp64" else M.FP32_IR
+            sol = M.Solver(N, N, I.z_cos(N), krylov_m=30, coarsest=4, prec=prec)
+            tt = [x.clone() for x in init] + [t[3]]
+            torch.cuda.synchronize()
+            t0 = time.time()
+            code, rep = sol.steady(P, sol.state(tt[0], tt[1], tt[2], tt[3], tt[3]), schedule(M, args.lin_rtol))
+            torch.cuda.synchronize()
+            el = time.time() - t0
+            if code != 0:
+                raise RuntimeError("steady failed: %s" % M.lib().mg_last_error())
+            finals[form] = [sol.download(x) for x in tt[:3]]
+            rows.append(dict(V_top=vt, form=form, seconds=round(el, 3), steps=rep.steps, newton=rep.newton_its,
+                             fgmres=rep.vcycles))
+            log(rows[-1])
+            del sol
+        if len(forms) == 2:
+            d = [float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(finals["fp32"], finals["fp64"])]
+            rows.append(dict(V_top=vt, fp32_vs_fp64_maxrel=d))
+            log(rows[-1])
+    secs = {f: [r["seconds"] for r in rows if r.get("form") == f] for f in forms}
+    out = {"metric": METRIC, "value": round(float(np.mean(secs[forms[-1]])), 4), "unit": "s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64+f32" if "fp32" in forms else "f64", "data": "synthetic",
+           "config": {"workload": "steady %dx%d from the prolonged %dx%d steady state, coupled Newton BE, "
+                                  "block preconditioner precision comparison" % (N + 1, N + 1, N // 2 + 1, N // 2 + 1),
+                      "forms": forms, "lin_rtol": args.lin_rtol,
+                      "mean_seconds": {f: round(float(np.mean(v)), 4) for f, v in secs.items()},
+                      "runs": rows}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +158,9 @@ def main():
     ap.add_argument("--lin-rtol", type=float, default=1e-3)
     ap.add_argument("--vtops", type=str, default="0.5,1,2")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--grid", type=int, default=256, help="finest N (256: 257x257 workload; 1024 for 1025x1025)")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "both"], default="fp64",
+                    help="block preconditioner precision (FGMRES and Newton stay FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (asked for %d); the batch of "
@@ -123,7 +172,9 @@ def main():
     from paper_0811_4446_amd import mgfluid as M
 
     vtops = [float(v) for v in args.vtops.split(",")]
-    N = 256
+    N = args.grid
+    if args.prec != "fp64":
+        return compare_precisions(args, M, I, N, vtops)
     cases = []
     for vt in vtops:
         fine, t, P, info = chain_to(M, I, N, vt, args.lin_rtol)

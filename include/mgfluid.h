@@ -170,6 +170,30 @@ int solve_steady(mg_ctx *ctx, const mg_physics *phys, mg_state *st,
 int prolong_state(mg_ctx *coarse, const mg_state *src, mg_ctx *fine, mg_state *dst,
                   const mg_physics *phys);
 
+/* ---- batches of independent problems (a parameter sweep) ----
+ * A batch holds nprob problems of one grid shape (desc; krylov_m >= 1) in
+ * one workspace: problem p owns the p-th of nprob equal-stride regions
+ * (its solver workspace and its V, ne, np, Se, Sp fields), and every kernel
+ * launch advances all problems of the batch (problem index = blockIdx.z).
+ * Physics (mobilities, voltages) may differ per problem; k must not. */
+
+/* Stride between problem regions and total workspace bytes.  Pure host. */
+int mg_batch_query(const mg_grid_desc *desc, int32_t nprob, int64_t *stride_bytes, int64_t *workspace_bytes);
+
+/* Context over a caller-allocated batch workspace (256-byte aligned). */
+int mg_batch_setup(const mg_grid_desc *desc, int32_t nprob, void *workspace, int64_t workspace_bytes,
+                   void *stream, mg_ctx **out);
+
+/* Device pointers of problem p's fields inside the batch workspace (the
+ * caller writes the initial state and sources there). */
+int mg_batch_state(mg_ctx *batch, int32_t p, mg_state *out);
+
+/* Steady solves of every problem of the batch (Sec. 2 time-step rule,
+ * coupled Newton; the schedule is shared, dt and the step decisions are per
+ * problem); phys and reports are host arrays of nprob entries.  Returns the
+ * worst per-problem status. */
+int solve_steady_batch(mg_ctx *batch, const mg_physics *phys, const mg_schedule *sched, mg_report *reports);
+
 /* ---- introspection used by the tests (kernel-level parity) ---- */
 
 /* Number of levels and the size of level l. */

@@ -294,6 +294,30 @@ int one_cycle(mg_ctx *c, int eq, double *x) {
 
 }  // namespace
 
+int64_t mgf::carve_ctx(mg_ctx *c, const mg_grid_desc *d, char *base) { return carve(c, d, base); }
+int mgf::validate_desc(const mg_grid_desc *d) { return validate(d); }
+int64_t mgf::level_pitch_of(int nz) { return level_pitch(nz); }
+
+// Grid tables of every level (Sec. 2) into the context's workspace.
+int mgf::upload_tables(mg_ctx *c) {
+    std::vector<double> zl, wr, fr, dz, dzc, wl;
+    for (int l = 0; l < c->nlev; ++l) {
+        Level &L = c->lev[l];
+        zl.resize(L.g.nz + 1);
+        for (int j = 0; j <= L.g.nz; ++j) zl[j] = c->zhost[(size_t)j << l];
+        level_tables(&c->desc, zl.data(), L.g.nr, L.g.nz, wr, fr, dz, dzc, wl);
+        HIP_OK(hipMemcpyAsync((void *)L.g.wr, wr.data(), wr.size() * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_OK(hipMemcpyAsync((void *)L.g.fr, fr.data(), fr.size() * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_OK(hipMemcpyAsync((void *)L.g.z, zl.data(), zl.size() * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_OK(hipMemcpyAsync((void *)L.g.dz, dz.data(), dz.size() * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_OK(hipMemcpyAsync((void *)L.g.dzc, dzc.data(), dzc.size() * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_OK(hipMemcpyAsync((void *)L.g.wl, wl.data(), wl.size() * 8, hipMemcpyHostToDevice, c->stream));
+        // the host vectors are reused next level: wait for the copies
+        HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    return MG_OK;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -370,6 +394,8 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
 
 void mg_destroy(mg_ctx *ctx) {
     if (!ctx) return;
+    if (ctx->active_host) (void)hipHostFree(ctx->active_host);
+    if (ctx->bpinned) (void)hipHostFree(ctx->bpinned);
     for (int t = 0; t < 64; ++t)
         if (ctx->nw.exec[t]) (void)hipGraphExecDestroy(ctx->nw.exec[t]);
     if (ctx->nw.cap) (void)hipStreamDestroy(ctx->nw.cap);
@@ -632,6 +658,45 @@ int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
     (void)hipEventDestroy(b);
     *avg_ms = ms / reps;
     return MG_OK;
+}
+
+int mg_batch_query(const mg_grid_desc *desc, int32_t nprob, int64_t *stride_bytes, int64_t *workspace_bytes) {
+    if (int st = validate(desc)) return st;
+    if (desc->krylov_m < 1) return fail(MG_EINVAL, "a batch needs krylov_m >= 1 (Newton path)");
+    if (nprob < 1 || nprob > 65535) return fail(MG_EINVAL, "nprob = %d outside 1..65535", nprob);
+    int64_t ws = 0, so = 0, to = 0;
+    int64_t total = batch_layout(desc, nprob, &ws, &so, &to);
+    if (stride_bytes) *stride_bytes = to / nprob;
+    if (workspace_bytes) *workspace_bytes = total;
+    return MG_OK;
+}
+
+int mg_batch_setup(const mg_grid_desc *desc, int32_t nprob, void *workspace, int64_t workspace_bytes,
+                   void *stream, mg_ctx **out) {
+    if (int st = mg_batch_query(desc, nprob, nullptr, nullptr)) return st;
+    if (!workspace || !out) return fail(MG_EINVAL, "null workspace or output");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(MG_EINVAL, "workspace must be %d-byte aligned", (int)kAlign);
+    return batch_setup(desc, nprob, workspace, workspace_bytes, stream, out);
+}
+
+int mg_batch_state(mg_ctx *c, int32_t p, mg_state *out) {
+    if (int e = check_ctx(c)) return e;
+    if (!out) return fail(MG_EINVAL, "null output");
+    if (!c->ws_base) return fail(MG_EINVAL, "not a batch context");
+    return batch_state(c, p, out);
+}
+
+int solve_steady_batch(mg_ctx *c, const mg_physics *phys, const mg_schedule *sc, mg_report *reports) {
+    if (int e = check_ctx(c)) return e;
+    if (!phys || !sc) return fail(MG_EINVAL, "null physics or schedule");
+    if (!c->ws_base) return fail(MG_EINVAL, "not a batch context");
+    if (sc->coupling != MG_COUPLE_NEWTON) return fail(MG_EINVAL, "batched solves use the Newton coupling");
+    if (!(sc->dt0 > 0) || !(sc->growth >= 1.0) || !(sc->dt_max >= sc->dt0))
+        return fail(MG_EINVAL, "bad time-step schedule");
+    for (int p = 0; p < c->bt.n; ++p)
+        if (!(phys[p].D_e > 0) || !(phys[p].D_p > 0)) return fail(MG_EINVAL, "problem %d: need D > 0", p);
+    return batch_solve_steady(c, phys, sc, reports);
 }
 
 int prolong_state(mg_ctx *coarse, const mg_state *src, mg_ctx *fine, mg_state *dst, const mg_physics *ph) {

@@ -44,15 +44,43 @@ struct Level {
     int ncoarse;       // unknowns on the coarsest level
 };
 
+// A batch of same-shape problems stored in equal-stride regions of one
+// workspace: problem p's data is problem 0's address + p * stride bytes.
+// Kernels take the problem index from blockIdx.z and skip inactive problems.
+struct Batch {
+    int64_t stride = 0;
+    const int *active = nullptr;
+    int n = 1;
+};
+
+template <class T>
+__host__ __device__ inline T *boff(T *p, int64_t off) {
+    return p ? reinterpret_cast<T *>(reinterpret_cast<char *>(p) + off) : p;
+}
+template <class T>
+__host__ __device__ inline const T *boff(const T *p, int64_t off) {
+    return p ? reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + off) : p;
+}
+__host__ __device__ inline Geom geom_off(Geom g, int64_t off) {
+    g.wr = boff(g.wr, off);
+    g.fr = boff(g.fr, off);
+    g.z = boff(g.z, off);
+    g.dz = boff(g.dz, off);
+    g.dzc = boff(g.dzc, off);
+    g.wl = boff(g.wl, off);
+    return g;
+}
+
 // ---- kernel launchers (mg_kernels.hip) ----
 void launch_poisson_assemble(const Geom &g, Op<double> op, const double *ne, const double *np,
                              double k, bool charge, hipStream_t s);
 void launch_sg_assemble(const Geom &g, Op<double> op, const double *V, const double *nk,
                         const double *S, double q, double D, double dt_inv, hipStream_t s);
 void launch_inject(const Geom &gf, const double *vf, const Geom &gc, double *vc, hipStream_t s);
-void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s);
-void launch_fill(double *p, int64_t n, double v, hipStream_t s);
-void launch_fill(float *p, int64_t n, float v, hipStream_t s);
+void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s,
+                           const double *lohi = nullptr, const Batch &bt = Batch());
+void launch_fill(double *p, int64_t n, double v, hipStream_t s, const Batch &bt = Batch());
+void launch_fill(float *p, int64_t n, float v, hipStream_t s, const Batch &bt = Batch());
 template <class T>
 void launch_rbgs(const Geom &g, Op<T> op, T *x, int colour, hipStream_t s);
 template <class T>
@@ -69,11 +97,12 @@ void launch_coarse_factor(const Geom &g, Op<double> op, double *scratch, double 
                           hipStream_t s);
 template <class T>
 void launch_coarse_solve(const Geom &g, Op<T> op, const T *invT, T *x, hipStream_t s);
-void launch_sum_partials(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s);
+void launch_sum_partials(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s,
+                         const Batch &bt = Batch());
 void launch_diff_norms(const Geom &g, const double *a, const double *b, double *partials,
-                       int *nblocks_out, hipStream_t s);
+                       int *nblocks_out, hipStream_t s, const Batch &bt = Batch());
 int residual_blocks(const Geom &g);
-void launch_copy_field(const Geom &g, const double *src, double *dst, hipStream_t s);
+void launch_copy_field(const Geom &g, const double *src, double *dst, hipStream_t s, const Batch &bt = Batch());
 void launch_to_f32(const Geom &g, const double *src, float *dst, hipStream_t s);
 void launch_add_f32(const Geom &g, double *x, const float *e, hipStream_t s);
 void launch_op_to_f32(const Geom &g, Op<double> op, Op<float> o32, hipStream_t s);
@@ -153,6 +182,14 @@ struct mg_ctx {
     bool assembled[3] = {false, false, false};
     int64_t vcycles = 0;
     mgf::NewtonWork nw;
+    // batch of same-shape problems (n = 1: this context alone)
+    mgf::Batch bt;
+    void *php_dev = nullptr;      // device NewtonPhys[bt.n] in batch mode
+    double *lohi_dev = nullptr;   // device electrode values, 6 per problem
+    int *active_host = nullptr;   // pinned mirror of bt.active
+    double *bpinned = nullptr;    // pinned batch readback buffer
+    char *ws_base = nullptr;
+    int64_t ws_bytes = 0;         // bytes of one problem's solver workspace
 };
 
 namespace mgf {
@@ -162,4 +199,12 @@ int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double d
                          mg_report *rep, bool *converged);
 int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep);
 int time_block_smoother(mg_ctx *c, int reps, double *avg_ms);
+int64_t carve_ctx(mg_ctx *c, const mg_grid_desc *d, char *base);
+int upload_tables(mg_ctx *c);
+int validate_desc(const mg_grid_desc *d);
+int64_t batch_layout(const mg_grid_desc *d, int nprob, int64_t *ws_bytes, int64_t *state_off, int64_t *tail_off);
+int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes, void *stream, mg_ctx **out);
+int batch_state(mg_ctx *c, int p, mg_state *out);
+int batch_solve_steady(mg_ctx *c, const mg_physics *phys, const mg_schedule *sc, mg_report *reps);
+int64_t level_pitch_of(int nz);
 }  // namespace mgf

@@ -133,7 +133,15 @@ __global__ void k_inject(Geom gf, const double *__restrict__ vf, Geom gc, double
     vc[at(gc, I, J)] = vf[at(gf, 2 * I, 2 * J)];
 }
 
-__global__ void k_set_electrodes(Geom g, double *u, double lo, double hi) {
+__global__ void k_set_electrodes(Geom g, double *u, double lo, double hi, const double *lohi, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    u = boff(u, bo_);
+    if (lohi) {
+        lo = lohi[2 * blockIdx.z];
+        hi = lohi[2 * blockIdx.z + 1];
+    }
+
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > g.nr) return;
     u[at(g, i, 0)] = lo;
@@ -141,7 +149,11 @@ __global__ void k_set_electrodes(Geom g, double *u, double lo, double hi) {
 }
 
 template <class T>
-__global__ void k_fill(T *p, int64_t n, T v) {
+__global__ void k_fill(T *p, int64_t n, T v, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    p = boff(p, bo_);
+
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; t < n; t += stride) p[t] = v;
@@ -375,7 +387,12 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, Op<TA> op, const TX *_
 
 // Sum `ncomp`-component partials of nblocks blocks in a fixed order.
 __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part, int nblocks,
-                                                       int ncomp, double *__restrict__ out) {
+                                                       int ncomp, double *__restrict__ out, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    part = boff(part, bo_);
+    out = boff(out, bo_);
+
     __shared__ double sh[256 * 4];
     for (int c = 0; c < ncomp; ++c) {
         double acc = 0.0;
@@ -395,10 +412,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
 // Per-block sums of (a-b)^2 and a^2 over the unknown nodes (steady test).
 __global__ __launch_bounds__(256) void k_diff_norms(Geom g, const double *__restrict__ a,
                                                      const double *__restrict__ b,
-                                                     double *__restrict__ partials) {
+                                                     double *__restrict__ partials, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    a = boff(a, bo_);
+    b = boff(b, bo_);
+    partials = boff(partials, bo_);
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     double dd = 0.0, aa = 0.0;
+
     if (i <= g.nr && j >= 1 && j < g.nz) {
         int64_t p = at(g, i, j);
         double t = a[p] - b[p];
@@ -661,7 +684,12 @@ __global__ __launch_bounds__(256) void k_coarse_solve(Geom g, Op<T> op, const T 
     }
 }
 
-__global__ void k_copy_field(Geom g, const double *__restrict__ s, double *__restrict__ d) {
+__global__ void k_copy_field(Geom g, const double *__restrict__ s, double *__restrict__ d, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    s = boff(s, bo_);
+    d = boff(d, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
@@ -738,22 +766,23 @@ void launch_inject(const Geom &gf, const double *vf, const Geom &gc, double *vc,
     k_inject<<<grid2d(gc), kBlock2d, 0, s>>>(gf, vf, gc, vc);
 }
 
-void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s) {
-    k_set_electrodes<<<(g.nr + 1 + 255) / 256, 256, 0, s>>>(g, u, lo, hi);
+void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s, const double *lohi,
+                           const Batch &bt) {
+    k_set_electrodes<<<dim3((g.nr + 1 + 255) / 256, 1, bt.n), 256, 0, s>>>(g, u, lo, hi, lohi, bt);
 }
 
-void launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+void launch_fill(double *p, int64_t n, double v, hipStream_t s, const Batch &bt) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    k_fill<double><<<(unsigned)blocks, 256, 0, s>>>(p, n, v);
+    k_fill<double><<<dim3((unsigned)blocks, 1, bt.n), 256, 0, s>>>(p, n, v, bt);
 }
 
-void launch_fill(float *p, int64_t n, float v, hipStream_t s) {
+void launch_fill(float *p, int64_t n, float v, hipStream_t s, const Batch &bt) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    k_fill<float><<<(unsigned)blocks, 256, 0, s>>>(p, n, v);
+    k_fill<float><<<dim3((unsigned)blocks, 1, bt.n), 256, 0, s>>>(p, n, v, bt);
 }
 
 template <class T>
@@ -819,19 +848,20 @@ void launch_coarse_solve(const Geom &g, Op<T> op, const T *invT, T *x, hipStream
     k_coarse_solve<T><<<1, 256, 0, s>>>(g, op, invT, x);
 }
 
-void launch_sum_partials(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s) {
-    k_sum_partials<<<1, 256, 0, s>>>(partials, nblocks, ncomp, out);
+void launch_sum_partials(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s,
+                         const Batch &bt) {
+    k_sum_partials<<<dim3(1, 1, bt.n), 256, 0, s>>>(partials, nblocks, ncomp, out, bt);
 }
 
 void launch_diff_norms(const Geom &g, const double *a, const double *b, double *partials,
-                       int *nblocks_out, hipStream_t s) {
+                       int *nblocks_out, hipStream_t s, const Batch &bt) {
     dim3 gr = grid2d(g);
     if (nblocks_out) *nblocks_out = (int)(gr.x * gr.y);
-    k_diff_norms<<<gr, kBlock2d, 0, s>>>(g, a, b, partials);
+    k_diff_norms<<<dim3(gr.x, gr.y, bt.n), kBlock2d, 0, s>>>(g, a, b, partials, bt);
 }
 
-void launch_copy_field(const Geom &g, const double *src, double *dst, hipStream_t s) {
-    k_copy_field<<<grid2d(g), kBlock2d, 0, s>>>(g, src, dst);
+void launch_copy_field(const Geom &g, const double *src, double *dst, hipStream_t s, const Batch &bt) {
+    k_copy_field<<<dim3(grid2d(g).x, grid2d(g).y, bt.n), kBlock2d, 0, s>>>(g, src, dst, bt);
 }
 
 void launch_to_f32(const Geom &g, const double *src, float *dst, hipStream_t s) {

@@ -39,34 +39,42 @@ struct NewtonPhys {
 
 void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
                             const double *nek, const double *npk, const double *Se, const double *Sp,
-                            const NewtonPhys &ph, bool with_rhs, hipStream_t s);
+                            const NewtonPhys &ph, bool with_rhs, hipStream_t s, const NewtonPhys *php = nullptr,
+                            const Batch &bt = Batch());
 template <class T>
-void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s);
+void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s,
+                       const Batch &bt = Batch());
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
-                           hipStream_t s);
+                           hipStream_t s, const Batch &bt = Batch());
 template <class T>
-void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc, int64_t pc, hipStream_t s);
+void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc, int64_t pc, hipStream_t s,
+                      const Batch &bt = Batch());
 template <class T>
-void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s);
+void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s,
+                     const Batch &bt = Batch());
 void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
-                    double *out, int64_t pc, hipStream_t s);
-void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s);
+                    double *out, int64_t pc, hipStream_t s, const Batch &bt = Batch());
+void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s,
+                                const Batch &bt = Batch());
 template <class T>
-void launch_block_coarse_solve(const Geom &g, const BOpT<T> &J, const T *f, const T *invT, T *x, hipStream_t s);
+void launch_block_coarse_solve(const Geom &g, const BOpT<T> &J, const T *f, const T *invT, T *x, hipStream_t s,
+                               const Batch &bt = Batch());
 int block_vec_blocks(const Geom &g);
 template <class T>
-void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s);
-void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
-void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s);
-void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s);
+void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s, const Batch &bt = Batch());
+void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t s, const Batch &bt = Batch());
+void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s,
+                         const Batch &bt = Batch());
+void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s, const Batch &bt = Batch());
 void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
-                       int64_t plane, double3 cw, double *partials, double *out, hipStream_t s);
+                       int64_t plane, double3 cw, double *partials, double *out, hipStream_t s,
+                       const Batch &bt = Batch());
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
-                       const double *h, double sign, hipStream_t s);
+                       const double *h, double sign, hipStream_t s, const Batch &bt = Batch());
 void launch_scale_by_norm(const Geom &g, const double *src, double *dst, int64_t plane, const double *nrm2,
-                          hipStream_t s);
+                          hipStream_t s, const Batch &bt = Batch());
 void launch_newton_update(const Geom &g, double *V, double *ne, double *np, const double *du, int64_t plane,
-                          double *partials, double *out, hipStream_t s);
+                          double *partials, double *out, hipStream_t s, const Batch &bt = Batch());
 
 }  // namespace mgf

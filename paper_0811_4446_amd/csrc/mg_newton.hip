@@ -80,7 +80,21 @@ inline __device__ Face sg_face(bool plus, double q, double gd, double Vc, double
 __global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, const double *__restrict__ ne,
                                   const double *__restrict__ np, const double *__restrict__ nek,
                                   const double *__restrict__ npk, const double *__restrict__ Se,
-                                  const double *__restrict__ Sp, NewtonPhys ph, int with_rhs) {
+                                  const double *__restrict__ Sp, NewtonPhys ph, int with_rhs,
+                                  const NewtonPhys *__restrict__ php, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    V = boff(V, bo_);
+    ne = boff(ne, bo_);
+    np = boff(np, bo_);
+    nek = boff(nek, bo_);
+    npk = boff(npk, bo_);
+    Se = boff(Se, bo_);
+    Sp = boff(Sp, bo_);
+    if (php) ph = php[blockIdx.z];
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
@@ -197,7 +211,14 @@ inline __device__ void block_gs_node(const Geom &g, const BOpT<T> &J, const T *f
 // Red-black half-sweep: every unknown node with (i+j)%2 == colour.  Nodes of
 // one colour only read nodes of the other colour.
 template <class T>
-__global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__restrict__ x, int colour) {
+__global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__restrict__ x, int colour, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    f = boff(f, bo_);
+    x = boff(x, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j < 1 || j >= g.nz || ((i + j) & 1) != colour) return;
@@ -233,7 +254,15 @@ inline __device__ void block_residual_node(const Geom &g, const BOpT<T> &J, cons
 
 template <class T>
 __global__ void k_block_residual(Geom g, BOpT<T> J, const T *__restrict__ f, const T *__restrict__ x,
-                                 T *__restrict__ r, int apply) {
+                                 T *__restrict__ r, int apply, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    f = boff(f, bo_);
+    x = boff(x, bo_);
+    r = boff(r, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
@@ -270,7 +299,14 @@ inline __device__ void restrict3_node(const Geom &gf, const T *rf, int64_t pf, c
 
 template <class T>
 __global__ void k_restrict3(Geom gf, const T *__restrict__ rf, int64_t pf, Geom gc, T *__restrict__ fc,
-                            int64_t pc) {
+                            int64_t pc, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    gf = geom_off(gf, bo_);
+    gc = geom_off(gc, bo_);
+    rf = boff(rf, bo_);
+    fc = boff(fc, bo_);
+
     int J_ = blockIdx.x * kTX + threadIdx.x;
     int I = blockIdx.y * kTY + threadIdx.y;
     if (I > gc.nr || J_ > gc.nz) return;
@@ -302,7 +338,14 @@ inline __device__ void prolong3_node(const Geom &gf, T *xf, int64_t pf, const Ge
 
 template <class T>
 __global__ void k_prolong3(Geom gf, T *__restrict__ xf, int64_t pf, Geom gc, const T *__restrict__ xc,
-                           int64_t pc) {
+                           int64_t pc, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    gf = geom_off(gf, bo_);
+    gc = geom_off(gc, bo_);
+    xf = boff(xf, bo_);
+    xc = boff(xc, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > gf.nr || j < 1 || j >= gf.nz) return;
@@ -310,7 +353,16 @@ __global__ void k_prolong3(Geom gf, T *__restrict__ xf, int64_t pf, Geom gc, con
 }
 
 __global__ void k_inject3(Geom gf, const double *__restrict__ V, const double *__restrict__ ne,
-                          const double *__restrict__ np, Geom gc, double *__restrict__ out, int64_t pc) {
+                          const double *__restrict__ np, Geom gc, double *__restrict__ out, int64_t pc, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    gf = geom_off(gf, bo_);
+    gc = geom_off(gc, bo_);
+    V = boff(V, bo_);
+    ne = boff(ne, bo_);
+    np = boff(np, bo_);
+    out = boff(out, bo_);
+
     int J_ = blockIdx.x * kTX + threadIdx.x;
     int I = blockIdx.y * kTY + threadIdx.y;
     if (I > gc.nr || J_ > gc.nz) return;
@@ -324,7 +376,14 @@ __global__ void k_inject3(Geom gf, const double *__restrict__ V, const double *_
 // partial pivoting, one workgroup); unknown (i, j, field) has index
 // 3*(i*(nz-1) + j-1) + field.  Stored transposed.
 __global__ __launch_bounds__(1024) void k_block_coarse_factor(Geom g, BOp J, double *__restrict__ M,
-                                                              double *__restrict__ invT) {
+                                                              double *__restrict__ invT, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    M = boff(M, bo_);
+    invT = boff(invT, bo_);
+
     const int m = g.nz - 1;
     const int n = 3 * (g.nr + 1) * m;
     const int n2 = 2 * n;
@@ -395,7 +454,14 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor(Geom g, BOp J, dou
 
 // Same factorisation with the augmented matrix resident in LDS (n <= 63).
 constexpr int kLdsGJ = 63;
-__global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J, double *__restrict__ invT) {
+__global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J, double *__restrict__ invT,
+                                                                  Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    invT = boff(invT, bo_);
+
     const int m = g.nz - 1;
     const int n = 3 * (g.nr + 1) * m;
     const int n2 = 2 * n;
@@ -493,7 +559,15 @@ inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const
 template <class T>
 __global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOpT<T> J, const T *__restrict__ f,
                                                              const T *__restrict__ invT,
-                                                             T *__restrict__ x) {
+                                                             T *__restrict__ x, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    f = boff(f, bo_);
+    invT = boff(invT, bo_);
+    x = boff(x, bo_);
+
     __shared__ T rhs[3 * kMaxCoarseUnknowns];
     block_coarse_solve_wg(g, J.plane, f, invT, x, rhs);
 }
@@ -506,7 +580,18 @@ __global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOpT<T> J, 
 // between, node by node exactly as the per-level kernels do.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F) {
+__global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    for (int q = 0; q < F.n; ++q) {
+        F.g[q] = geom_off(F.g[q], bo_);
+        F.J[q] = boff(F.J[q], bo_);
+        F.x[q] = boff(F.x[q], bo_);
+        F.r[q] = boff(F.r[q], bo_);
+    }
+    F.f0 = boff(F.f0, bo_);
+    F.invT = boff(F.invT, bo_);
+
     __shared__ T rhs[3 * kMaxFusedCoarse];
     const int n = F.n;
     const int nt = blockDim.x;
@@ -579,7 +664,15 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F) {
 // <u, v>_W = sum over unknown nodes and fields of u v (c_f / vol)^2.
 __global__ __launch_bounds__(256) void k_wdot_multi(Geom g, const double *__restrict__ w,
                                                      const double *__restrict__ basis, int64_t vstride, int nv,
-                                                     int64_t plane, double3 cw, double *__restrict__ partials) {
+                                                     int64_t plane, double3 cw, double *__restrict__ partials,
+                                                     Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    w = boff(w, bo_);
+    basis = boff(basis, bo_);
+    partials = boff(partials, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     __shared__ double sh[kTY][kMaxKrylov + 1];
@@ -609,7 +702,12 @@ __global__ __launch_bounds__(256) void k_wdot_multi(Geom g, const double *__rest
 // out[c] = sum over blocks of partials[b*ncomp + c], fixed order (one
 // workgroup per component).
 __global__ __launch_bounds__(256) void k_sum_cols(const double *__restrict__ part, int nblocks, int ncomp,
-                                                   double *__restrict__ out) {
+                                                   double *__restrict__ out, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    part = boff(part, bo_);
+    out = boff(out, bo_);
+
     int c = blockIdx.x;
     __shared__ double sh[256];
     double acc = 0.0;
@@ -625,7 +723,14 @@ __global__ __launch_bounds__(256) void k_sum_cols(const double *__restrict__ par
 
 // w = alpha * (w - sum_v h[v] basis_v)   (alpha = 1, or 1/h_next on demand)
 __global__ void k_axpy_multi(Geom g, double *__restrict__ w, const double *__restrict__ basis, int64_t vstride,
-                             int nv, int64_t plane, const double *__restrict__ h, double sign) {
+                             int nv, int64_t plane, const double *__restrict__ h, double sign, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    w = boff(w, bo_);
+    basis = boff(basis, bo_);
+    h = boff(h, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j < 1 || j >= g.nz) return;
@@ -633,14 +738,22 @@ __global__ void k_axpy_multi(Geom g, double *__restrict__ w, const double *__res
     for (int f = 0; f < 3; ++f) {
         int64_t q = p + f * plane;
         double acc = w[q];
-        for (int v = 0; v < nv; ++v) acc += sign * h[v] * basis[v * vstride + q];
+        for (int v = 0; v < nv; ++v)
+            if (h[v] != 0.0) acc += sign * h[v] * basis[v * vstride + q];
         w[q] = acc;
     }
 }
 
 // dst = src * (1 / sqrt(*nrm2))
 __global__ void k_scale_by_norm(Geom g, const double *__restrict__ src, double *__restrict__ dst, int64_t plane,
-                                const double *__restrict__ nrm2) {
+                                const double *__restrict__ nrm2, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    src = boff(src, bo_);
+    dst = boff(dst, bo_);
+    nrm2 = boff(nrm2, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
@@ -654,7 +767,16 @@ __global__ void k_scale_by_norm(Geom g, const double *__restrict__ src, double *
 // |du_f| and |u_f| (l1) and the minima of the densities.
 __global__ __launch_bounds__(256) void k_newton_update(Geom g, double *__restrict__ V, double *__restrict__ ne,
                                                         double *__restrict__ np, const double *__restrict__ du,
-                                                        int64_t plane, double *__restrict__ partials) {
+                                                        int64_t plane, double *__restrict__ partials, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    V = boff(V, bo_);
+    ne = boff(ne, bo_);
+    np = boff(np, bo_);
+    du = boff(du, bo_);
+    partials = boff(partials, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     double s[8] = {0, 0, 0, 0, 0, 0, 1e300, 1e300};
@@ -698,7 +820,12 @@ __global__ __launch_bounds__(256) void k_newton_update(Geom g, double *__restric
 }
 
 __global__ __launch_bounds__(256) void k_reduce_newton(const double *__restrict__ part, int nblocks,
-                                                        double *__restrict__ out) {
+                                                        double *__restrict__ out, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    part = boff(part, bo_);
+    out = boff(out, bo_);
+
     __shared__ double sh[8][256];
     double o[8] = {0, 0, 0, 0, 0, 0, 1e300, 1e300};
     for (int b = threadIdx.x; b < nblocks; b += 256) {
@@ -722,78 +849,91 @@ __global__ __launch_bounds__(256) void k_reduce_newton(const double *__restrict_
 }  // namespace
 
 static const dim3 kB2(kTX, kTY);
+static dim3 gz(dim3 g, const Batch &bt) { return dim3(g.x, g.y, bt.n); }
 
 void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
                             const double *nek, const double *npk, const double *Se, const double *Sp,
-                            const NewtonPhys &ph, bool with_rhs, hipStream_t s) {
-    k_newton_assemble<<<grid2d(g), kB2, 0, s>>>(g, J, V, ne, np, nek, npk, Se, Sp, ph, with_rhs ? 1 : 0);
+                            const NewtonPhys &ph, bool with_rhs, hipStream_t s, const NewtonPhys *php,
+                            const Batch &bt) {
+    k_newton_assemble<<<gz(grid2d(g), bt), kB2, 0, s>>>(g, J, V, ne, np, nek, npk, Se, Sp, ph, with_rhs ? 1 : 0,
+                                                         php, bt);
 }
 template <class T>
-void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s) {
-    k_block_rbgs<T><<<grid2d(g), kB2, 0, s>>>(g, J, f, x, colour);
+void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s, const Batch &bt) {
+    k_block_rbgs<T><<<gz(grid2d(g), bt), kB2, 0, s>>>(g, J, f, x, colour, bt);
 }
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
-                           hipStream_t s) {
-    k_block_residual<T><<<grid2d(g), kB2, 0, s>>>(g, J, f, x, r, apply ? 1 : 0);
+                           hipStream_t s, const Batch &bt) {
+    k_block_residual<T><<<gz(grid2d(g), bt), kB2, 0, s>>>(g, J, f, x, r, apply ? 1 : 0, bt);
 }
 template <class T>
-void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc, int64_t pc, hipStream_t s) {
-    k_restrict3<T><<<grid2d(gc), kB2, 0, s>>>(gf, rf, pf, gc, fc, pc);
+void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc, int64_t pc, hipStream_t s,
+                      const Batch &bt) {
+    k_restrict3<T><<<gz(grid2d(gc), bt), kB2, 0, s>>>(gf, rf, pf, gc, fc, pc, bt);
 }
 template <class T>
-void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s) {
-    k_prolong3<T><<<grid2d(gf), kB2, 0, s>>>(gf, xf, pf, gc, xc, pc);
+void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s,
+                     const Batch &bt) {
+    k_prolong3<T><<<gz(grid2d(gf), bt), kB2, 0, s>>>(gf, xf, pf, gc, xc, pc, bt);
 }
 void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
-                    double *out, int64_t pc, hipStream_t s) {
-    k_inject3<<<grid2d(gc), kB2, 0, s>>>(gf, V, ne, np, gc, out, pc);
+                    double *out, int64_t pc, hipStream_t s, const Batch &bt) {
+    k_inject3<<<gz(grid2d(gc), bt), kB2, 0, s>>>(gf, V, ne, np, gc, out, pc, bt);
 }
-void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s) {
+void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s,
+                                const Batch &bt) {
     int n = 3 * (g.nr + 1) * (g.nz - 1);
     if (n <= kLdsGJ)
-        k_block_coarse_factor_lds<<<1, 1024, 0, s>>>(g, J, invT);
+        k_block_coarse_factor_lds<<<dim3(1, 1, bt.n), 1024, 0, s>>>(g, J, invT, bt);
     else
-        k_block_coarse_factor<<<1, 1024, 0, s>>>(g, J, scratch, invT);
+        k_block_coarse_factor<<<dim3(1, 1, bt.n), 1024, 0, s>>>(g, J, scratch, invT, bt);
 }
 template <class T>
-void launch_block_coarse_solve(const Geom &g, const BOpT<T> &J, const T *f, const T *invT, T *x, hipStream_t s) {
-    k_block_coarse_solve<T><<<1, 1024, 0, s>>>(g, J, f, invT, x);
+void launch_block_coarse_solve(const Geom &g, const BOpT<T> &J, const T *f, const T *invT, T *x, hipStream_t s,
+                               const Batch &bt) {
+    k_block_coarse_solve<T><<<dim3(1, 1, bt.n), 1024, 0, s>>>(g, J, f, invT, x, bt);
 }
 template <class T>
-void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s) {
-    k_block_subcycle<T><<<1, 1024, 0, s>>>(F);
+void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s, const Batch &bt) {
+    k_block_subcycle<T><<<dim3(1, 1, bt.n), 1024, 0, s>>>(F, bt);
 }
 int block_vec_blocks(const Geom &g) {
     dim3 gr = grid2d(g);
     return (int)(gr.x * gr.y);
 }
 void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
-                       int64_t plane, double3 cw, double *partials, double *out, hipStream_t s) {
+                       int64_t plane, double3 cw, double *partials, double *out, hipStream_t s, const Batch &bt) {
     dim3 gr = grid2d(g);
-    k_wdot_multi<<<gr, kB2, 0, s>>>(g, w, basis, vstride, nv, plane, cw, partials);
-    k_sum_cols<<<nv, 256, 0, s>>>(partials, (int)(gr.x * gr.y), nv, out);
+    k_wdot_multi<<<gz(gr, bt), kB2, 0, s>>>(g, w, basis, vstride, nv, plane, cw, partials, bt);
+    k_sum_cols<<<dim3(nv, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nv, out, bt);
 }
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
-                       const double *h, double sign, hipStream_t s) {
-    k_axpy_multi<<<grid2d(g), kB2, 0, s>>>(g, w, basis, vstride, nv, plane, h, sign);
+                       const double *h, double sign, hipStream_t s, const Batch &bt) {
+    k_axpy_multi<<<gz(grid2d(g), bt), kB2, 0, s>>>(g, w, basis, vstride, nv, plane, h, sign, bt);
 }
 void launch_scale_by_norm(const Geom &g, const double *src, double *dst, int64_t plane, const double *nrm2,
-                          hipStream_t s) {
-    k_scale_by_norm<<<grid2d(g), kB2, 0, s>>>(g, src, dst, plane, nrm2);
+                          hipStream_t s, const Batch &bt) {
+    k_scale_by_norm<<<gz(grid2d(g), bt), kB2, 0, s>>>(g, src, dst, plane, nrm2, bt);
 }
 void launch_newton_update(const Geom &g, double *V, double *ne, double *np, const double *du, int64_t plane,
-                          double *partials, double *out, hipStream_t s) {
+                          double *partials, double *out, hipStream_t s, const Batch &bt) {
     dim3 gr = grid2d(g);
-    k_newton_update<<<gr, kB2, 0, s>>>(g, V, ne, np, du, plane, partials);
-    k_reduce_newton<<<1, 256, 0, s>>>(partials, (int)(gr.x * gr.y), out);
+    k_newton_update<<<gz(gr, bt), kB2, 0, s>>>(g, V, ne, np, du, plane, partials, bt);
+    k_reduce_newton<<<dim3(1, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), out, bt);
 }
 
 // FP32 copy of the block Jacobian: every plane rounded, except the diagonal
 // entries of the three five-point blocks (ee, pp, VV), which are rebuilt from
 // their exact FP64 column excess minus the rounded neighbour entries of the
 // same column (see k_op_to_f32 for the reason).
-__global__ void k_block_to_f32(Geom g, BOp J, BOpT<float> J32) {
+__global__ void k_block_to_f32(Geom g, BOp J, BOpT<float> J32, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    J32.base = boff(J32.base, bo_);
+
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * kTY + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
@@ -827,43 +967,54 @@ __global__ void k_block_to_f32(Geom g, BOp J, BOpT<float> J32) {
         J32.pl(K + 1)[p] = (float)(ex - r32);
     }
 }
-void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s) {
-    k_block_to_f32<<<grid2d(g), kB2, 0, s>>>(g, J, J32);
+void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s, const Batch &bt) {
+    k_block_to_f32<<<gz(grid2d(g), bt), kB2, 0, s>>>(g, J, J32, bt);
 }
 
 // planes -> FP32 copies (n planes of `plane` elements)
-__global__ void k_planes_to_f32(const double *__restrict__ src, float *__restrict__ dst, int64_t n) {
+__global__ void k_planes_to_f32(const double *__restrict__ src, float *__restrict__ dst, int64_t n, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    src = boff(src, bo_);
+    dst = boff(dst, bo_);
+
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; t < n; t += stride) dst[t] = (float)src[t];
 }
-__global__ void k_planes_to_f64(const float *__restrict__ src, double *__restrict__ dst, int64_t n) {
+__global__ void k_planes_to_f64(const float *__restrict__ src, double *__restrict__ dst, int64_t n, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    src = boff(src, bo_);
+    dst = boff(dst, bo_);
+
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; t < n; t += stride) dst[t] = (double)src[t];
 }
-void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t s, const Batch &bt) {
     int64_t b = (n + 255) / 256;
     if (b > 8192) b = 8192;
-    k_planes_to_f32<<<(unsigned)b, 256, 0, s>>>(src, dst, n);
+    k_planes_to_f32<<<dim3((unsigned)b, 1, bt.n), 256, 0, s>>>(src, dst, n, bt);
 }
-void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s) {
+void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s, const Batch &bt) {
     int64_t b = (n + 255) / 256;
     if (b > 8192) b = 8192;
-    k_planes_to_f64<<<(unsigned)b, 256, 0, s>>>(src, dst, n);
+    k_planes_to_f64<<<dim3((unsigned)b, 1, bt.n), 256, 0, s>>>(src, dst, n, bt);
 }
 
 #define MGF_INST(T)                                                                                          \
-    template void launch_block_rbgs<T>(const Geom &, const BOpT<T> &, const T *, T *, int, hipStream_t);     \
+    template void launch_block_rbgs<T>(const Geom &, const BOpT<T> &, const T *, T *, int, hipStream_t,      \
+                                       const Batch &);                                                       \
     template void launch_block_residual<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
-                                           hipStream_t);                                                     \
+                                           hipStream_t, const Batch &);                                      \
     template void launch_restrict3<T>(const Geom &, const T *, int64_t, const Geom &, T *, int64_t,          \
-                                      hipStream_t);                                                          \
+                                      hipStream_t, const Batch &);                                           \
     template void launch_prolong3<T>(const Geom &, T *, int64_t, const Geom &, const T *, int64_t,           \
-                                     hipStream_t);                                                           \
+                                     hipStream_t, const Batch &);                                            \
     template void launch_block_coarse_solve<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *,     \
-                                               hipStream_t);                                                 \
-    template void launch_block_subcycle<T>(const FusedLevelsT<T> &, hipStream_t);
+                                               hipStream_t, const Batch &);                                  \
+    template void launch_block_subcycle<T>(const FusedLevelsT<T> &, hipStream_t, const Batch &);
 MGF_INST(double)
 MGF_INST(float)
 

@@ -3,9 +3,13 @@
 // V-cycle, weighted inner product), Newton iteration of one backward-Euler
 // step, and the steady driver with the paper's time-step rule.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <chrono>
+#include <new>
+#include <vector>
+#include <stdlib.h>
 
 #include "mg_newton.h"
 
@@ -62,27 +66,27 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         }
         F.f0 = f;
         F.invT = Prec<T>::inv(c);
-        launch_block_subcycle<T>(F, s);
+        launch_block_subcycle<T>(F, s, c->bt);
         return;
     }
     if (l == c->nlev - 1) {
-        launch_block_coarse_solve<T>(L.g, J, f, Prec<T>::inv(c), x, s);
+        launch_block_coarse_solve<T>(L.g, J, f, Prec<T>::inv(c), x, s, c->bt);
         return;
     }
     for (int k = 0; k < c->desc.nu1; ++k)
-        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(L.g, J, f, x, col, s);
+        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(L.g, J, f, x, col, s, c->bt);
     T *r = Prec<T>::r(c, l);
-    launch_block_residual<T>(L.g, J, f, x, r, false, s);
+    launch_block_residual<T>(L.g, J, f, x, r, false, s, c->bt);
     const Level &C = c->lev[l + 1];
     BOpT<T> Jc = Prec<T>::op(c, l + 1);
     T *fc = Jc.pl(kFe);
-    launch_restrict3<T>(L.g, r, plane_of(L), C.g, fc, plane_of(C), s);
+    launch_restrict3<T>(L.g, r, plane_of(L), C.g, fc, plane_of(C), s, c->bt);
     T *xc = Prec<T>::x(c, l + 1);
-    launch_fill(xc, 3 * plane_of(C), T(0), s);
+    launch_fill(xc, 3 * plane_of(C), T(0), s, c->bt);
     block_vcycle<T>(c, l + 1, fc, xc, s);
-    launch_prolong3<T>(L.g, x, plane_of(L), C.g, xc, plane_of(C), s);
+    launch_prolong3<T>(L.g, x, plane_of(L), C.g, xc, plane_of(C), s, c->bt);
     for (int k = 0; k < c->desc.nu2; ++k)
-        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(L.g, J, f, x, col, s);
+        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(L.g, J, f, x, col, s, c->bt);
 }
 
 // Assemble the Jacobian on every level: level 0 at the current state with
@@ -99,26 +103,26 @@ void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt
     const double *snap = c->nw.snap;
     int64_t p0 = plane_of(c->lev[0]);
     launch_newton_assemble(c->lev[0].g, bop(c, 0), st->V, st->ne, st->np, snap + p0, snap + 2 * p0, st->Se,
-                           st->Sp, np_, true, s);
+                           st->Sp, np_, true, s, static_cast<const NewtonPhys *>(c->php_dev), c->bt);
     const double *V = st->V, *ne = st->ne, *np = st->np;
     for (int l = 1; l < c->nlev; ++l) {
         const Level &F = c->lev[l - 1], &C = c->lev[l];
         int64_t pc = plane_of(C);
         double *out = c->nw.lev[l].st;
-        launch_inject3(F.g, V, ne, np, C.g, out, pc, s);
+        launch_inject3(F.g, V, ne, np, C.g, out, pc, s, c->bt);
         V = out;
         ne = out + pc;
         np = out + 2 * pc;
-        launch_newton_assemble(C.g, bop(c, l), V, ne, np, nullptr, nullptr, nullptr, nullptr, np_, false, s);
+        launch_newton_assemble(C.g, bop(c, l), V, ne, np, nullptr, nullptr, nullptr, nullptr, np_, false, s, static_cast<const NewtonPhys *>(c->php_dev), c->bt);
     }
     const Level &Lc = c->lev[c->nlev - 1];
-    launch_block_coarse_factor(Lc.g, bop(c, c->nlev - 1), c->nw.scratch, c->nw.lev[c->nlev - 1].cinvT, s);
+    launch_block_coarse_factor(Lc.g, bop(c, c->nlev - 1), c->nw.scratch, c->nw.lev[c->nlev - 1].cinvT, s, c->bt);
     if (c->nw.prec32) {
         // FP32 copies of every level's Jacobian and of the coarsest inverse
         for (int l = 0; l < c->nlev; ++l)
-            launch_block_to_f32(c->lev[l].g, bop(c, l), BOpT<float>{c->nw.lev[l].J32, plane_of(c->lev[l])}, s);
+            launch_block_to_f32(c->lev[l].g, bop(c, l), BOpT<float>{c->nw.lev[l].J32, plane_of(c->lev[l])}, s, c->bt);
         int64_t n = 3 * (int64_t)(Lc.g.nr + 1) * (Lc.g.nz - 1);
-        launch_planes_to_f32(c->nw.lev[c->nlev - 1].cinvT, c->nw.lev[c->nlev - 1].cinvT32, n * n, s);
+        launch_planes_to_f32(c->nw.lev[c->nlev - 1].cinvT, c->nw.lev[c->nlev - 1].cinvT32, n * n, s, c->bt);
     }
 }
 
@@ -157,6 +161,16 @@ struct Arnoldi {
     }
 };
 
+// Copy `count` device doubles at `dev` of every problem of the batch to
+// host[p * count ...] (one strided copy).
+void readback(mg_ctx *c, double *host, const double *dev, int count, hipStream_t s) {
+    if (c->bt.n <= 1)
+        (void)hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, s);
+    else
+        (void)hipMemcpy2DAsync(host, count * sizeof(double), dev, (size_t)c->bt.stride, count * sizeof(double),
+                               (size_t)c->bt.n, hipMemcpyDeviceToHost, s);
+}
+
 // One Arnoldi step k: z_k = M v_k (block V-cycle), w = J z_k, two passes of
 // classical Gram-Schmidt against v_0..v_k, v_{k+1} = w/|w|, and the
 // readback of the k+1 projections (twice) and |w|^2 to pinned memory.
@@ -172,22 +186,22 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     if (W.prec32) {
         // preconditioner in FP32: z_k = M32 v_k (the Krylov space stays FP64)
         float *x32 = W.lev[0].x32;
-        launch_planes_to_f32(vk, W.f32, vs, s);
-        launch_fill(x32, vs, 0.0f, s);
+        launch_planes_to_f32(vk, W.f32, vs, s, c->bt);
+        launch_fill(x32, vs, 0.0f, s, c->bt);
         block_vcycle<float>(c, 0, W.f32, x32, s);
-        launch_planes_to_f64(x32, zk, vs, s);
+        launch_planes_to_f64(x32, zk, vs, s, c->bt);
     } else {
-        launch_fill(zk, vs, 0.0, s);
+        launch_fill(zk, vs, 0.0, s, c->bt);
         block_vcycle<double>(c, 0, vk, zk, s);
     }
-    launch_block_residual<double>(g, J, nullptr, zk, W.w, true, s);  // w = J z_k
-    launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev, s);
-    launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev, -1.0, s);
-    launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev + (m + 1), s);
-    launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev + (m + 1), -1.0, s);
-    launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev + 2 * m + 2, s);
-    launch_scale_by_norm(g, W.w, vk1, p0, dev + 2 * m + 2, s);
-    (void)hipMemcpyAsync(c->pinned, dev, (2 * m + 3) * sizeof(double), hipMemcpyDeviceToHost, s);
+    launch_block_residual<double>(g, J, nullptr, zk, W.w, true, s, c->bt);  // w = J z_k
+    launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev, s, c->bt);
+    launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev, -1.0, s, c->bt);
+    launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev + (m + 1), s, c->bt);
+    launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev + (m + 1), -1.0, s, c->bt);
+    launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev + 2 * m + 2, s, c->bt);
+    launch_scale_by_norm(g, W.w, vk1, p0, dev + 2 * m + 2, s, c->bt);
+    readback(c, c->bt.n > 1 ? c->bpinned : c->pinned, dev, 2 * m + 3, s);
 }
 
 // Run Arnoldi step k on the context stream, from a captured graph when
@@ -299,17 +313,17 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
 void copy_state(mg_ctx *c, const mg_state *st, double *dst) {
     const Level &L0 = c->lev[0];
     int64_t p0 = plane_of(L0);
-    launch_copy_field(L0.g, st->V, dst, c->stream);
-    launch_copy_field(L0.g, st->ne, dst + p0, c->stream);
-    launch_copy_field(L0.g, st->np, dst + 2 * p0, c->stream);
+    launch_copy_field(L0.g, st->V, dst, c->stream, c->bt);
+    launch_copy_field(L0.g, st->ne, dst + p0, c->stream, c->bt);
+    launch_copy_field(L0.g, st->np, dst + 2 * p0, c->stream, c->bt);
 }
 
 void restore_state(mg_ctx *c, const double *src, mg_state *st) {
     const Level &L0 = c->lev[0];
     int64_t p0 = plane_of(L0);
-    launch_copy_field(L0.g, src, st->V, c->stream);
-    launch_copy_field(L0.g, src + p0, st->ne, c->stream);
-    launch_copy_field(L0.g, src + 2 * p0, st->np, c->stream);
+    launch_copy_field(L0.g, src, st->V, c->stream, c->bt);
+    launch_copy_field(L0.g, src + p0, st->ne, c->stream, c->bt);
+    launch_copy_field(L0.g, src + 2 * p0, st->np, c->stream, c->bt);
 }
 
 // Newton iterations of one BE step; the step's starting state is in W.snap.
@@ -490,6 +504,408 @@ int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_
     R->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (status == MG_ENOCONV) fail(MG_ENOCONV, "not steady after %d steps (change %.3e)", R->steps, R->last_change);
     return status;
+}
+
+
+// ===========================================================================
+// Batches of same-shape problems (one size class of a parameter sweep).
+// Every problem owns an equal-stride region of the workspace (solver
+// workspace + its five state fields); kernels index the problem by
+// blockIdx.z and skip problems whose active flag is 0, so one launch
+// advances the whole batch.  Time stepping, Newton and FGMRES run in
+// lockstep with per-problem control on the host: each problem keeps its
+// own dt, step count, Krylov recurrence and convergence decisions.
+// ===========================================================================
+namespace {
+
+struct BatchRun {
+    int n;
+    std::vector<int> act;   // host copy of the active flags
+};
+
+int set_active(mg_ctx *c, const std::vector<int> &act) {
+    for (int p = 0; p < c->bt.n; ++p) c->active_host[p] = act[p];
+    HIP_OK(hipMemcpyAsync((void *)c->bt.active, c->active_host, c->bt.n * sizeof(int), hipMemcpyHostToDevice,
+                          c->stream));
+    return MG_OK;
+}
+
+int any_of(const std::vector<int> &v) {
+    for (int x : v)
+        if (x) return 1;
+    return 0;
+}
+
+// Upload y coefficients (k per problem, zero-padded to kmax) into each
+// problem's device scalars at offset `off`.
+int upload_per_problem(mg_ctx *c, const std::vector<double> &vals, int count, double *dev_at) {
+    int n = c->bt.n;
+    double *h = c->bpinned;
+    for (int p = 0; p < n; ++p)
+        for (int i = 0; i < count; ++i) h[p * count + i] = vals[(size_t)p * count + i];
+    HIP_OK(hipMemcpy2DAsync(dev_at, (size_t)c->bt.stride, h, count * sizeof(double), count * sizeof(double),
+                            (size_t)n, hipMemcpyHostToDevice, c->stream));
+    return MG_OK;
+}
+
+// Lockstep FGMRES over the problems with act[p] = 1.  ok[p] = 1 when the
+// problem's weighted relative residual reached rtol.
+int fgmres_batch(mg_ctx *c, double3 cw, double rtol, int maxit, const std::vector<int> &act,
+                 std::vector<int> &ok, std::vector<int> &its) {
+    hipStream_t s = c->stream;
+    NewtonWork &W = c->nw;
+    const int n = c->bt.n, m = W.m;
+    const Level &L0 = c->lev[0];
+    const Geom &g = L0.g;
+    int64_t p0 = plane_of(L0), vs = 3 * p0;
+    BOp J = bop(c, 0);
+    const double *b = J.pl(kFe);
+    double *dev = W.dev;
+    double *host = c->bpinned;
+    std::vector<Arnoldi> A(n);
+    std::vector<double> beta0(n, 0.0), beta(n, 0.0), est(n, 0.0);
+    std::vector<int> live = act, kp(n, 0);
+    ok.assign(n, 0);
+    its.assign(n, 0);
+    int e = set_active(c, live);
+    if (e) return e;
+    launch_fill(W.delta, vs, 0.0, s, c->bt);
+    launch_wdot_multi(g, b, b, vs, 1, p0, cw, W.partials, dev, s, c->bt);
+    readback(c, host, dev, 1, s);
+    HIP_OK(hipStreamSynchronize(s));
+    for (int p = 0; p < n; ++p) {
+        if (!live[p]) continue;
+        beta0[p] = beta[p] = sqrt(host[p]);
+        if (!(beta0[p] > 0)) {  // zero right-hand side: delta = 0 is exact
+            ok[p] = isfinite(beta0[p]) ? 1 : 0;
+            live[p] = 0;
+        }
+    }
+    if ((e = set_active(c, live))) return e;
+    launch_scale_by_norm(g, b, W.V, p0, dev, s, c->bt);
+    std::vector<int> cycle_act;
+    while (any_of(live)) {
+        for (int p = 0; p < n; ++p)
+            if (live[p]) A[p].start(beta[p]);
+        cycle_act = live;  // problems taking part in this restart cycle
+        std::vector<int> iter = live;
+        int kmax = 0;
+        for (int k = 0; k < m && any_of(iter); ++k) {
+            if ((e = set_active(c, iter))) return e;
+            if ((e = run_arnoldi(c, k, cw))) return e;
+            HIP_OK(hipStreamSynchronize(s));
+            kmax = k + 1;
+            for (int p = 0; p < n; ++p) {
+                if (!iter[p]) continue;
+                const double *hp = host + (size_t)p * (2 * m + 3);
+                for (int i = 0; i <= k; ++i) A[p].H[i][k] = hp[i] + hp[m + 1 + i];
+                A[p].H[k + 1][k] = sqrt(hp[2 * m + 2]);
+                est[p] = A[p].add(k);
+                kp[p] = k + 1;
+                its[p]++;
+                if (!isfinite(est[p]) || est[p] <= rtol * beta0[p] || A[p].H[k][k] == 0.0 || its[p] >= maxit)
+                    iter[p] = 0;
+            }
+        }
+        // delta += Z y for every problem of the cycle (y zero-padded to kmax)
+        std::vector<double> Y((size_t)n * kmax, 0.0);
+        for (int p = 0; p < n; ++p) {
+            if (!cycle_act[p] || !isfinite(est[p])) continue;
+            double y[kMaxKrylov];
+            A[p].solve(kp[p], y);
+            for (int i = 0; i < kp[p]; ++i) Y[(size_t)p * kmax + i] = y[i];
+        }
+        if ((e = set_active(c, cycle_act))) return e;
+        if ((e = upload_per_problem(c, Y, kmax, dev + 3 * m + 8))) return e;
+        launch_axpy_multi(g, W.delta, W.Z, vs, kmax, p0, dev + 3 * m + 8, 1.0, s, c->bt);
+        launch_block_residual<double>(g, J, b, W.delta, W.w, false, s, c->bt);
+        launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev, s, c->bt);
+        readback(c, host, dev, 1, s);
+        HIP_OK(hipStreamSynchronize(s));
+        std::vector<int> restart(n, 0);
+        for (int p = 0; p < n; ++p) {
+            if (!cycle_act[p]) continue;
+            beta[p] = sqrt(host[p]);
+            live[p] = 0;
+            if (!isfinite(beta[p]) || !isfinite(est[p])) continue;  // ok stays 0
+            if (beta[p] <= rtol * beta0[p] * 1.0000001 || est[p] <= rtol * beta0[p]) {
+                ok[p] = 1;
+                continue;
+            }
+            if (its[p] >= maxit) continue;
+            restart[p] = 1;
+            live[p] = 1;
+        }
+        if (any_of(restart)) {
+            if ((e = set_active(c, restart))) return e;
+            launch_scale_by_norm(g, W.w, W.V, p0, dev, s, c->bt);
+        }
+    }
+    return MG_OK;
+}
+
+}  // namespace
+
+int64_t batch_layout(const mg_grid_desc *d, int nprob, int64_t *ws_bytes, int64_t *state_off, int64_t *tail_off) {
+    int64_t ws = carve_ctx(nullptr, d, nullptr);
+    int64_t nf0 = (int64_t)(d->nr + 1) * level_pitch_of(d->nz) * 8;
+    int64_t stride = round_up(ws + 5 * round_up(nf0, kAlign), kAlign);
+    if (ws_bytes) *ws_bytes = ws;
+    if (state_off) *state_off = ws;
+    int64_t tail = stride * nprob;
+    if (tail_off) *tail_off = tail;
+    int64_t tail_bytes = round_up(nprob * (int64_t)sizeof(NewtonPhys), kAlign) + round_up(nprob * 6 * 8, kAlign) +
+                         round_up(nprob * (int64_t)sizeof(int), kAlign);
+    return tail + tail_bytes;
+}
+
+int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes, void *stream, mg_ctx **out) {
+    int64_t wsb = 0, soff = 0, toff = 0;
+    int64_t need = batch_layout(d, nprob, &wsb, &soff, &toff);
+    if (bytes < need)
+        return fail(MG_ENOMEM, "batch workspace has %lld bytes, needs %lld", (long long)bytes, (long long)need);
+    mg_ctx *c = new (std::nothrow) mg_ctx();
+    if (!c) return fail(MG_ENOMEM, "host allocation failed");
+    c->desc = *d;
+    c->zhost.assign(d->z_host, d->z_host + d->nz + 1);
+    c->desc.z_host = c->zhost.data();
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    char *base = reinterpret_cast<char *>(workspace);
+    carve_ctx(c, d, base);
+    c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
+    c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
+    c->ws_base = base;
+    c->ws_bytes = wsb;
+    int64_t stride = toff / nprob;
+    char *tail = base + toff;
+    c->php_dev = tail;
+    c->lohi_dev = reinterpret_cast<double *>(tail + round_up(nprob * (int64_t)sizeof(NewtonPhys), kAlign));
+    int *act = reinterpret_cast<int *>(reinterpret_cast<char *>(c->lohi_dev) + round_up(nprob * 6 * 8, kAlign));
+    c->bt.stride = stride;
+    c->bt.active = act;
+    c->bt.n = nprob;
+    hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->active_host, nprob * sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->bpinned, (size_t)nprob * (2 * kMaxKrylov + 16) * sizeof(double),
+                          hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemsetAsync(workspace, 0, (size_t)need, c->stream);
+    if (e != hipSuccess) {
+        mg_destroy(c);
+        return fail(MG_EHIP, "batch setup: %s", hipGetErrorString(e));
+    }
+    int st = upload_tables(c);
+    if (st) {
+        mg_destroy(c);
+        return st;
+    }
+    // every problem gets the same grid tables: replicate problem 0's
+    // workspace (tables + zeros) into the other regions
+    for (int p = 1; p < nprob; ++p) {
+        e = hipMemcpyAsync(base + p * stride, base, (size_t)wsb, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) {
+            mg_destroy(c);
+            return fail(MG_EHIP, "batch setup copy: %s", hipGetErrorString(e));
+        }
+    }
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        mg_destroy(c);
+        return fail(MG_EHIP, "batch setup: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return MG_OK;
+}
+
+int batch_state(mg_ctx *c, int p, mg_state *out) {
+    if (p < 0 || p >= c->bt.n) return fail(MG_EINVAL, "problem %d outside 0..%d", p, c->bt.n - 1);
+    int64_t nf0 = round_up((int64_t)(c->desc.nr + 1) * level_pitch_of(c->desc.nz) * 8, kAlign);
+    char *r = c->ws_base + (int64_t)p * c->bt.stride + c->ws_bytes;
+    out->V = reinterpret_cast<double *>(r);
+    out->ne = reinterpret_cast<double *>(r + nf0);
+    out->np = reinterpret_cast<double *>(r + 2 * nf0);
+    out->Se = reinterpret_cast<const double *>(r + 3 * nf0);
+    out->Sp = reinterpret_cast<const double *>(r + 4 * nf0);
+    return MG_OK;
+}
+
+int batch_solve_steady(mg_ctx *c, const mg_physics *phys, const mg_schedule *sc, mg_report *reps) {
+    const int n = c->bt.n;
+    hipStream_t s = c->stream;
+    auto t0 = std::chrono::steady_clock::now();
+    mg_state st;
+    batch_state(c, 0, &st);
+    const Level &L0 = c->lev[0];
+    int64_t p0 = plane_of(L0);
+    for (int p = 1; p < n; ++p)
+        if (phys[p].k != phys[0].k) return fail(MG_EINVAL, "all problems of a batch need the same k");
+    double3 cw = field_weights(&phys[0]);
+    // the electrode kernel reads lohi[2p], lohi[2p+1]: pass per-field views
+    std::vector<double> lohi_e(2 * n), lohi_p(2 * n), lohi_v(2 * n);
+    for (int p = 0; p < n; ++p) {
+        lohi_v[2 * p] = phys[p].V_bottom;
+        lohi_v[2 * p + 1] = phys[p].V_top;
+        lohi_e[2 * p] = phys[p].ne_bottom;
+        lohi_e[2 * p + 1] = phys[p].ne_top;
+        lohi_p[2 * p] = phys[p].np_bottom;
+        lohi_p[2 * p + 1] = phys[p].np_top;
+    }
+    {
+        double *h = c->bpinned;
+        for (int q = 0; q < 2 * n; ++q) {
+            h[q] = lohi_v[q];
+            h[2 * n + q] = lohi_e[q];
+            h[4 * n + q] = lohi_p[q];
+        }
+        HIP_OK(hipMemcpyAsync(c->lohi_dev, h, 6 * n * sizeof(double), hipMemcpyHostToDevice, s));
+        std::vector<int> all(n, 1);
+        int e0 = set_active(c, all);
+        if (e0) return e0;
+        launch_set_electrodes(L0.g, st.V, 0, 0, s, c->lohi_dev, c->bt);
+        launch_set_electrodes(L0.g, st.ne, 0, 0, s, c->lohi_dev + 2 * n, c->bt);
+        launch_set_electrodes(L0.g, st.np, 0, 0, s, c->lohi_dev + 4 * n, c->bt);
+    }
+    std::vector<double> dt(n, sc->dt0), dt_acc(n, 0.0), tt(n, 0.0), change(n, 0.0), relres(n, 0.0);
+    std::vector<int> status(n, 0), steps(n, 0), rej(n, 0), newt(n, 0), fgm(n, 0), consec(n, 0);
+    std::vector<NewtonPhys> hp(n);
+    int maxn = sc->max_newton > 0 ? sc->max_newton : 10;
+    int maxit = sc->max_cycles > 0 ? sc->max_cycles : 200;
+    int rounds = 0;
+    const bool progress = getenv("MGF_PROGRESS") != nullptr;
+    while (true) {
+        std::vector<int> run(n, 0);
+        int nrun = 0;
+        for (int p = 0; p < n; ++p) {
+            run[p] = status[p] == 0 && steps[p] < sc->max_steps;
+            nrun += run[p];
+        }
+        if (!nrun) break;
+        ++rounds;
+        if (progress && rounds % 50 == 0) {
+            fprintf(stderr, "[mgfluid batch %dx%d] round %d: %d of %d problems still running\n", c->desc.nr + 1,
+                    c->desc.nz + 1, rounds, nrun, n);
+            fflush(stderr);
+        }
+        // per-problem physics with this round's dt
+        for (int p = 0; p < n; ++p) {
+            hp[p].qe = phys[p].mu_e / phys[p].D_e;
+            hp[p].qp = -phys[p].mu_p / phys[p].D_p;
+            hp[p].De = phys[p].D_e;
+            hp[p].Dp = phys[p].D_p;
+            hp[p].k = phys[p].k;
+            hp[p].dt_inv = 1.0 / dt[p];
+        }
+        HIP_OK(hipMemcpyAsync(c->php_dev, hp.data(), n * sizeof(NewtonPhys), hipMemcpyHostToDevice, s));
+        int e = set_active(c, run);
+        if (e) return e;
+        copy_state(c, &st, c->nw.snap);
+        // Newton iterations in lockstep
+        std::vector<int> nconv(n, 0), nfail(n, 0);
+        for (int it = 1; it <= maxn; ++it) {
+            std::vector<int> act(n, 0);
+            for (int p = 0; p < n; ++p) act[p] = run[p] && !nconv[p] && !nfail[p];
+            if (!any_of(act)) break;
+            if ((e = set_active(c, act))) return e;
+            mg_physics dummy = phys[0];
+            assemble_all(c, &dummy, &st, 0.0);
+            std::vector<int> ok, its;
+            if ((e = fgmres_batch(c, cw, sc->lin_rtol, maxit, act, ok, its))) return e;
+            std::vector<int> upd(n, 0);
+            for (int p = 0; p < n; ++p) {
+                if (!act[p]) continue;
+                newt[p]++;
+                fgm[p] += its[p];
+                if (!ok[p])
+                    nfail[p] = 1;
+                else
+                    upd[p] = 1;
+            }
+            if ((e = set_active(c, upd))) return e;
+            launch_newton_update(L0.g, st.V, st.ne, st.np, c->nw.delta, p0, c->nw.partials, c->scal, s, c->bt);
+            readback(c, c->bpinned, c->scal, 8, s);
+            HIP_OK(hipStreamSynchronize(s));
+            for (int p = 0; p < n; ++p) {
+                if (!upd[p]) continue;
+                const double *o = c->bpinned + 8 * p;
+                double re = o[0] / fmax(o[1], 1e-300), rp = o[2] / fmax(o[3], 1e-300), rv = o[4] / fmax(o[5], 1e-300);
+                double mx = fmax(re, fmax(rp, rv));
+                if (!isfinite(mx) || mx > sc->reject_limit) {
+                    nfail[p] = 1;
+                } else if (mx < sc->newton_tol) {
+                    double cnt = (double)(L0.g.nr + 1) * (L0.g.nz - 1);
+                    if (o[6] >= -1e-10 * o[1] / cnt && o[7] >= -1e-10 * o[3] / cnt)
+                        nconv[p] = 1;
+                    else
+                        nfail[p] = 1;
+                }
+            }
+        }
+        // accept or reject every running problem
+        std::vector<int> acc(n, 0), rejd(n, 0);
+        for (int p = 0; p < n; ++p) {
+            if (!run[p]) continue;
+            if (nconv[p])
+                acc[p] = 1;
+            else
+                rejd[p] = 1;
+        }
+        if (any_of(rejd)) {
+            if ((e = set_active(c, rejd))) return e;
+            restore_state(c, c->nw.snap, &st);
+        }
+        if (any_of(acc)) {
+            if ((e = set_active(c, acc))) return e;
+            int nb = 0;
+            launch_diff_norms(L0.g, st.ne, c->nw.snap + p0, c->partials, &nb, s, c->bt);
+            launch_sum_partials(c->partials, nb, 2, c->scal, s, c->bt);
+            launch_diff_norms(L0.g, st.np, c->nw.snap + 2 * p0, c->partials, &nb, s, c->bt);
+            launch_sum_partials(c->partials, nb, 2, c->scal + 2, s, c->bt);
+            readback(c, c->bpinned, c->scal, 4, s);
+            HIP_OK(hipStreamSynchronize(s));
+        }
+        for (int p = 0; p < n; ++p) {
+            if (rejd[p]) {
+                rej[p]++;
+                if (++consec[p] > 60) {
+                    status[p] = MG_EREJECT;
+                    continue;
+                }
+                dt[p] = (dt_acc[p] > 0 && dt[p] > dt_acc[p]) ? dt_acc[p] : 0.5 * dt[p];
+            } else if (acc[p]) {
+                consec[p] = 0;
+                steps[p]++;
+                tt[p] += dt[p];
+                const double *o = c->bpinned + 4 * p;
+                double ch = fmax(sqrt(o[0] / fmax(o[1], 1e-300)), sqrt(o[2] / fmax(o[3], 1e-300)));
+                change[p] = ch;
+                dt_acc[p] = dt[p];
+                if (!isfinite(ch))
+                    status[p] = MG_ENONFINITE;
+                else if (ch < sc->steady_tol)
+                    status[p] = 1;
+                else
+                    dt[p] = fmin(sc->growth * dt[p], sc->dt_max);
+            }
+        }
+    }
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = MG_OK;
+    for (int p = 0; p < n; ++p) {
+        if (reps) {
+            reps[p].steps = steps[p];
+            reps[p].rejected = rej[p];
+            reps[p].vcycles = fgm[p];
+            reps[p].newton_its = newt[p];
+            reps[p].last_change = change[p];
+            reps[p].final_relres = relres[p];
+            reps[p].seconds = secs;
+            reps[p].t_end = tt[p];
+        }
+        int code = status[p] == 1 ? MG_OK : (status[p] == 0 ? MG_ENOCONV : status[p]);
+        if (code < worst) worst = code;
+    }
+    if (worst) fail(worst, "batch: some problems did not reach steady state");
+    return worst;
 }
 
 int time_block_smoother(mg_ctx *c, int reps, double *avg_ms) {

@@ -87,6 +87,11 @@ SIGNATURES = {
     "mg_smooth_half": (ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int]),
     "mg_residual": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP]),
     "mg_time_kernel": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _I32, _PD]),
+    "mg_batch_query": (ctypes.c_int, [ctypes.POINTER(GridDesc), _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "mg_batch_setup": (ctypes.c_int, [ctypes.POINTER(GridDesc), _I32, _VP, _I64, _VP, ctypes.POINTER(_VP)]),
+    "mg_batch_state": (ctypes.c_int, [_VP, _I32, ctypes.POINTER(State)]),
+    "solve_steady_batch": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(Schedule),
+                                          ctypes.POINTER(Report)]),
     "mg_last_error": (ctypes.c_char_p, []),
 }
 
@@ -247,6 +252,65 @@ class Solver:
         code = lib().solve_steady(self.ctx, ctypes.byref(phys), ctypes.byref(state), ctypes.byref(sched),
                                   ctypes.byref(rep))
         return code, rep
+
+
+class Batch:
+    """nprob same-shape problems solved together (one size class)."""
+
+    def __init__(self, nr, nz, z, nprob, R=1.0, d=1.0, coarsest=4, nu1=2, nu2=2, prec=FP32_IR, krylov_m=20,
+                 device="cuda:0", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("mgfluid needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.nr, self.nz, self.n = nr, nz, nprob
+        self.z = np.ascontiguousarray(z, dtype=np.float64)
+        self.device = torch.device(device)
+        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, SMOOTH_ZEBRA, prec, krylov_m)
+        self.pitch, _ = query(self.desc)
+        stride, total = _I64(0), _I64(0)
+        _check(lib().mg_batch_query(ctypes.byref(self.desc), nprob, ctypes.byref(stride), ctypes.byref(total)))
+        self.stride, self.bytes = stride.value, total.value
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(self.bytes // 8 + 64, dtype=torch.float64, device=self.device)
+        h = _VP()
+        _check(lib().mg_batch_setup(ctypes.byref(self.desc), nprob, _ptr(self.workspace), self.bytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.ctx = h
+        base = self.workspace.data_ptr()
+        self.views = []
+        for p in range(nprob):
+            st = State()
+            _check(lib().mg_batch_state(self.ctx, p, ctypes.byref(st)))
+            v = {}
+            for name in ("V", "ne", "np", "Se", "Sp"):
+                off = (getattr(st, name) - base) // 8
+                v[name] = self.workspace[off: off + (nr + 1) * self.pitch].view(nr + 1, self.pitch)
+            self.views.append(v)
+
+    def set_problem(self, p, V, ne, np_, S):
+        for name, arr in (("V", V), ("ne", ne), ("np", np_), ("Se", S), ("Sp", S)):
+            t = self.views[p][name]
+            t[:, : self.nz + 1] = torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float64)).to(self.device)
+
+    def get(self, p, name):
+        torch.cuda.synchronize(self.device)
+        return self.views[p][name][:, : self.nz + 1].cpu().numpy().copy()
+
+    def steady(self, phys_list, sched):
+        P = (Physics * self.n)(*phys_list)
+        R = (Report * self.n)()
+        code = lib().solve_steady_batch(self.ctx, P, ctypes.byref(sched), R)
+        return code, [R[i].as_dict() for i in range(self.n)]
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().mg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def schedule(dt0=1e-4, growth=1.5, dt_max=0.1, steady_tol=1e-8, lin_rtol=1e-10, max_steps=100000,

@@ -1,0 +1,83 @@
+"""Batched steady solves: problems of one grid shape solved together (one
+launch per step of the whole batch, problem = blockIdx.z).  Every problem
+must end exactly where its own single-problem solve ends (same kernels,
+same per-problem decisions), and agree with the oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import newton as NW
+from paper_0811_4446_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+os.environ.setdefault("MGF_PROGRESS", "1")
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def M():
+    from paper_0811_4446_amd import mgfluid
+    return mgfluid
+
+
+def _draw(N, nprob, seed):
+    draws = I.sweep_draws(nprob, seed, sizes=(N,))
+    probs = []
+    for q, d in enumerate(draws):
+        phys = dict(I.PHYS)
+        phys.update(V_top=d["V_top"], mu_e=d["mu_e"], D_e=d["D_e"], mu_p=d["mu_p"], D_p=d["D_p"])
+        z = I.z_cos(N)
+        ne = I.initial_density(N, N, 1000 + q)
+        probs.append((phys, I.initial_potential(N, N, z, 0.0, phys["V_top"]), ne, ne.copy(), I.source(N, N, z)))
+    return probs
+
+
+@pytest.mark.parametrize("N,nprob,prec", [(16, 5, 1), (32, 4, 1), (32, 3, 0)])
+def test_batch_equals_single_problem_solves(N, nprob, prec):
+    _say("batch vs single", N, nprob, prec)
+    m = M()
+    z = I.z_cos(N)
+    probs = _draw(N, nprob, 12345)
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-3, max_cycles=200, newton_tol=1e-6, steady_tol=1e-8,
+                    max_steps=3000)
+    B = m.Batch(N, N, z, nprob, prec=prec, krylov_m=20)
+    for p, (phys, V, ne, np_, S) in enumerate(probs):
+        B.set_problem(p, V, ne, np_, S)
+    code, reps = B.steady([m.Physics.of(pr[0]) for pr in probs], sc)
+    assert code == 0, m.lib().mg_last_error()
+    for p, (phys, V, ne, np_, S) in enumerate(probs):
+        sol = m.Solver(N, N, z, krylov_m=20, coarsest=4, prec=prec)
+        t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)]
+        c1, rep = sol.steady(m.Physics.of(phys), sol.state(t[0], t[1], t[2], t[3], t[3]), sc)
+        assert c1 == 0
+        assert reps[p]["steps"] == rep.steps and reps[p]["newton_its"] == rep.newton_its, (p, reps[p], rep.as_dict())
+        assert reps[p]["vcycles"] == rep.vcycles
+        for name, tt in (("V", t[0]), ("ne", t[1]), ("np", t[2])):
+            assert np.array_equal(B.get(p, name), sol.download(tt)), (p, name)
+
+
+def test_batch_matches_oracle_17():
+    _say("batch vs oracle")
+    m = M()
+    N = 16
+    z = I.z_cos(N)
+    probs = _draw(N, 3, 777)
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-12, max_cycles=400, newton_tol=1e-10, steady_tol=1e-8,
+                    max_steps=3000)
+    B = m.Batch(N, N, z, len(probs), prec=m.FP32_IR, krylov_m=20)
+    for p, (phys, V, ne, np_, S) in enumerate(probs):
+        B.set_problem(p, V, ne, np_, S)
+    code, reps = B.steady([m.Physics.of(pr[0]) for pr in probs], sc)
+    assert code == 0
+    for p, (phys, V, ne, np_, S) in enumerate(probs):
+        cp = NW.Coupled(N, N, 1.0, z, phys)
+        Vo, neo, npo = V.copy(), ne.copy(), np_.copy()
+        acc, rej, seq = NW.steady(cp, Vo, neo, npo, S, S, tol=1e-8, newton_tol=1e-10)
+        assert reps[p]["steps"] == acc
+        for name, ref in (("V", Vo), ("ne", neo), ("np", npo)):
+            got = B.get(p, name)
+            assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max(), (p, name)
