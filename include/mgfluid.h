@@ -194,6 +194,13 @@ int mg_batch_state(mg_ctx *batch, int32_t p, mg_state *out);
  * worst per-problem status. */
 int solve_steady_batch(mg_ctx *batch, const mg_physics *phys, const mg_schedule *sched, mg_report *reports);
 
+/* Launch shape chosen by the autotuner: radial rows per workgroup of the 2D
+ * kernels (1, 2, 4, 8 or 16; the workgroup spans 64 axial nodes), and the
+ * largest level (nr, nz <= fuse_max_n) run inside the single-workgroup
+ * coarse sub-cycle of the Newton preconditioner (0 disables it).  Results
+ * change only by summation order.  Default 4 and 32. */
+int mg_set_tuning(mg_ctx *ctx, int32_t rows_per_block, int32_t fuse_max_n);
+
 /* ---- introspection used by the tests (kernel-level parity) ---- */
 
 /* Number of levels and the size of level l. */

@@ -95,6 +95,7 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
         memset(&L, 0, sizeof L);
         L.g.nr = nr;
         L.g.nz = nz;
+        L.g.ty = 4;
         L.g.pitch = pitch;
         L.g.dr = d->R / nr;
         L.g.wr = cv.take<double>(nr + 1);
@@ -144,7 +145,8 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
     Geom g0;
     g0.nr = d->nr;
     g0.nz = d->nz;
-    int nblk = ((d->nz + 1 + 63) / 64) * ((d->nr + 1 + 3) / 4);
+    // sized for one radial row per workgroup (the smallest launch shape)
+    int nblk = ((d->nz + 1 + 63) / 64) * (d->nr + 1);
     double *part = cv.take<double>(2 * (int64_t)nblk + 16);
     double *scal = cv.take<double>(64);
     double *sp[4];
@@ -657,6 +659,30 @@ int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     *avg_ms = ms / reps;
+    return MG_OK;
+}
+
+int mg_set_tuning(mg_ctx *c, int32_t rows_per_block, int32_t fuse_max_n) {
+    if (int e = check_ctx(c)) return e;
+    if (rows_per_block != 1 && rows_per_block != 2 && rows_per_block != 4 && rows_per_block != 8 &&
+        rows_per_block != 16)
+        return fail(MG_EINVAL, "rows_per_block must be 1, 2, 4, 8 or 16");
+    if (fuse_max_n < 0 || fuse_max_n > 128) return fail(MG_EINVAL, "fuse_max_n outside 0..128");
+    if (fuse_max_n > 0) {
+        // the fused range must hold at most kMaxFused levels and a coarsest
+        // grid small enough for its LDS
+        int first = c->nlev;
+        for (int l = 0; l < c->nlev; ++l)
+            if (c->lev[l].g.nr <= fuse_max_n && c->lev[l].g.nz <= fuse_max_n) {
+                first = l;
+                break;
+            }
+        if (c->nlev - first > 8) return fail(MG_EINVAL, "fuse_max_n = %d would fuse more than 8 levels", fuse_max_n);
+    }
+    for (int l = 0; l < c->nlev; ++l) c->lev[l].g.ty = rows_per_block;
+    c->nw.fuse = fuse_max_n > 0;
+    c->nw.fuse_max = fuse_max_n;
+    drop_graphs(c);
     return MG_OK;
 }
 

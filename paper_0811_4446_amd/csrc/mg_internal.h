@@ -12,10 +12,12 @@ namespace mgf {
 
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarseUnknowns = 1024;
+constexpr int kMaxTY = 16;  // largest rows-per-workgroup of the 2D kernels
 
 // Per-level grid tables and sizes, passed to kernels by value.
 struct Geom {
     int nr, nz;
+    int ty;             // radial rows per workgroup of the 2D kernels (tuning)
     int64_t pitch;
     double dr;
     const double *wr;   // radial width of node i (area of its z-faces), nr+1
@@ -164,6 +166,7 @@ struct NewtonWork {
     double cw_cap[3] = {0, 0, 0};
     bool use_graphs = true;
     bool fuse = true;  // single-workgroup coarse sub-cycle
+    int fuse_max = 32; // levels with nr, nz <= fuse_max run in it
 };
 
 }  // namespace mgf
@@ -199,6 +202,7 @@ int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double d
                          mg_report *rep, bool *converged);
 int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep);
 int time_block_smoother(mg_ctx *c, int reps, double *avg_ms);
+void drop_graphs(mg_ctx *c);
 int64_t carve_ctx(mg_ctx *c, const mg_grid_desc *d, char *base);
 int upload_tables(mg_ctx *c);
 int validate_desc(const mg_grid_desc *d);

@@ -14,12 +14,12 @@ namespace mgf {
 namespace {
 
 constexpr int kTX = 64;  // threads along z (one wavefront)
-constexpr int kTY = 4;   // radial rows per workgroup
 
 inline __device__ int64_t at(const Geom &g, int i, int j) { return (int64_t)i * g.pitch + j; }
 
+inline dim3 blk2d(const Geom &g) { return dim3(kTX, g.ty); }
 inline dim3 grid2d(const Geom &g) {
-    return dim3((g.nz + 1 + kTX - 1) / kTX, (g.nr + 1 + kTY - 1) / kTY);
+    return dim3((g.nz + 1 + kTX - 1) / kTX, (g.nr + 1 + g.ty - 1) / g.ty);
 }
 
 // Scharfetter-Gummel Bernoulli function F(x) = x/(exp(x)-1) (Sec. 2, after
@@ -44,7 +44,7 @@ inline __device__ double bern_F(double x) {
 __global__ void k_poisson_assemble(Geom g, Op<double> op, const double *__restrict__ ne,
                                    const double *__restrict__ np, double k, int charge) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     int64_t p = at(g, i, j);
     if (j == 0 || j == g.nz) {
@@ -76,7 +76,7 @@ __global__ void k_sg_assemble(Geom g, Op<double> op, const double *__restrict__ 
                               const double *__restrict__ nk, const double *__restrict__ S,
                               double q, double D, double dt_inv) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     int64_t p = at(g, i, j);
     if (j == 0 || j == g.nz) {
@@ -128,7 +128,7 @@ __global__ void k_sg_assemble(Geom g, Op<double> op, const double *__restrict__ 
 // Coarse potential = coincident fine value (nested grids).
 __global__ void k_inject(Geom gf, const double *__restrict__ vf, Geom gc, double *__restrict__ vc) {
     int J = blockIdx.x * kTX + threadIdx.x;
-    int I = blockIdx.y * kTY + threadIdx.y;
+    int I = blockIdx.y * blockDim.y + threadIdx.y;
     if (I > gc.nr || J > gc.nz) return;
     vc[at(gc, I, J)] = vf[at(gf, 2 * I, 2 * J)];
 }
@@ -167,7 +167,7 @@ __global__ void k_fill(T *p, int64_t n, T v, Batch bt) {
 template <class T>
 __global__ void k_rbgs(Geom g, Op<T> op, T *__restrict__ x, int colour) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j < 1 || j >= g.nz) return;
     if (((i + j) & 1) != colour) return;
     int64_t p = at(g, i, j);
@@ -333,11 +333,11 @@ __global__ __launch_bounds__(64) void k_zline(Geom g, Op<T> op, T *__restrict__ 
 // so they are deterministic.
 // ---------------------------------------------------------------------------
 template <class TA, class TX, class TR>
-__global__ __launch_bounds__(256) void k_residual(Geom g, Op<TA> op, const TX *__restrict__ fo,
+__global__ __launch_bounds__(1024) void k_residual(Geom g, Op<TA> op, const TX *__restrict__ fo,
                                                    const TX *__restrict__ x, TR *__restrict__ r,
                                                    double *__restrict__ partials) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     double rr = 0.0, bb = 0.0;
     if (i <= g.nr && j <= g.nz) {
         int64_t p = at(g, i, j);
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, Op<TA> op, const TX *_
         rr += __shfl_xor(rr, off);
         bb += __shfl_xor(bb, off);
     }
-    __shared__ double srr[kTY], sbb[kTY];
+    __shared__ double srr[kMaxTY], sbb[kMaxTY];
     if (threadIdx.x == 0) {
         srr[threadIdx.y] = rr;
         sbb[threadIdx.y] = bb;
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, Op<TA> op, const TX *_
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         double a = 0.0, b = 0.0;
-        for (int w = 0; w < kTY; ++w) {
+        for (int w = 0; w < (int)blockDim.y; ++w) {
             a += srr[w];
             b += sbb[w];
         }
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
 }
 
 // Per-block sums of (a-b)^2 and a^2 over the unknown nodes (steady test).
-__global__ __launch_bounds__(256) void k_diff_norms(Geom g, const double *__restrict__ a,
+__global__ __launch_bounds__(1024) void k_diff_norms(Geom g, const double *__restrict__ a,
                                                      const double *__restrict__ b,
                                                      double *__restrict__ partials, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(256) void k_diff_norms(Geom g, const double *__rest
     b = boff(b, bo_);
     partials = boff(partials, bo_);
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     double dd = 0.0, aa = 0.0;
 
     if (i <= g.nr && j >= 1 && j < g.nz) {
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(256) void k_diff_norms(Geom g, const double *__rest
         dd += __shfl_xor(dd, off);
         aa += __shfl_xor(aa, off);
     }
-    __shared__ double s1[kTY], s2[kTY];
+    __shared__ double s1[kMaxTY], s2[kMaxTY];
     if (threadIdx.x == 0) {
         s1[threadIdx.y] = dd;
         s2[threadIdx.y] = aa;
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) void k_diff_norms(Geom g, const double *__rest
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         double u = 0.0, v = 0.0;
-        for (int w = 0; w < kTY; ++w) {
+        for (int w = 0; w < (int)blockDim.y; ++w) {
             u += s1[w];
             v += s2[w];
         }
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256) void k_diff_norms(Geom g, const double *__rest
 template <class T>
 __global__ void k_restrict(Geom gf, const T *__restrict__ rf, Geom gc, T *__restrict__ fc) {
     int J = blockIdx.x * kTX + threadIdx.x;
-    int I = blockIdx.y * kTY + threadIdx.y;
+    int I = blockIdx.y * blockDim.y + threadIdx.y;
     if (I > gc.nr || J > gc.nz) return;
     int64_t pc = at(gc, I, J);
     if (J == 0 || J == gc.nz) {
@@ -484,7 +484,7 @@ __global__ void k_restrict(Geom gf, const T *__restrict__ rf, Geom gc, T *__rest
 template <class T>
 __global__ void k_prolong(Geom gf, T *__restrict__ xf, Geom gc, const T *__restrict__ xc) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > gf.nr || j < 1 || j >= gf.nz) return;
     int I0 = i >> 1, I1 = (i + 1) >> 1;
     T v0, v1;
@@ -506,7 +506,7 @@ __global__ void k_prolong(Geom gf, T *__restrict__ xf, Geom gc, const T *__restr
 // a whole state, electrode rows included).
 __global__ void k_prolong_state(Geom gf, double *__restrict__ xf, Geom gc, const double *__restrict__ xc) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > gf.nr || j > gf.nz) return;
     int I0 = i >> 1, I1 = (i + 1) >> 1;
     double v0, v1;
@@ -691,21 +691,21 @@ __global__ void k_copy_field(Geom g, const double *__restrict__ s, double *__res
     d = boff(d, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     d[at(g, i, j)] = s[at(g, i, j)];
 }
 
 __global__ void k_to_f32(Geom g, const double *__restrict__ s, float *__restrict__ d) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     d[at(g, i, j)] = (float)s[at(g, i, j)];
 }
 
 __global__ void k_add_f32(Geom g, double *__restrict__ x, const float *__restrict__ e) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j < 1 || j >= g.nz) return;
     x[at(g, i, j)] += (double)e[at(g, i, j)];
 }
@@ -729,7 +729,7 @@ __device__ inline double col_nb_sum(const Geom &g, const double *a, const double
 
 __global__ void k_op_to_f32(Geom g, Op<double> o, Op<float> o32) {
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     int64_t p = at(g, i, j);
     o32.a[p] = (float)o.a[p];
@@ -750,20 +750,19 @@ __global__ void k_op_to_f32(Geom g, Op<double> o, Op<float> o32) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-static const dim3 kBlock2d(kTX, kTY);
 
 void launch_poisson_assemble(const Geom &g, Op<double> op, const double *ne, const double *np,
                              double k, bool charge, hipStream_t s) {
-    k_poisson_assemble<<<grid2d(g), kBlock2d, 0, s>>>(g, op, ne, np, k, charge ? 1 : 0);
+    k_poisson_assemble<<<grid2d(g), blk2d(g), 0, s>>>(g, op, ne, np, k, charge ? 1 : 0);
 }
 
 void launch_sg_assemble(const Geom &g, Op<double> op, const double *V, const double *nk,
                         const double *S, double q, double D, double dt_inv, hipStream_t s) {
-    k_sg_assemble<<<grid2d(g), kBlock2d, 0, s>>>(g, op, V, nk, S, q, D, dt_inv);
+    k_sg_assemble<<<grid2d(g), blk2d(g), 0, s>>>(g, op, V, nk, S, q, D, dt_inv);
 }
 
 void launch_inject(const Geom &gf, const double *vf, const Geom &gc, double *vc, hipStream_t s) {
-    k_inject<<<grid2d(gc), kBlock2d, 0, s>>>(gf, vf, gc, vc);
+    k_inject<<<grid2d(gc), blk2d(gc), 0, s>>>(gf, vf, gc, vc);
 }
 
 void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s, const double *lohi,
@@ -787,7 +786,7 @@ void launch_fill(float *p, int64_t n, float v, hipStream_t s, const Batch &bt) {
 
 template <class T>
 void launch_rbgs(const Geom &g, Op<T> op, T *x, int colour, hipStream_t s) {
-    k_rbgs<T><<<grid2d(g), kBlock2d, 0, s>>>(g, op, x, colour);
+    k_rbgs<T><<<grid2d(g), blk2d(g), 0, s>>>(g, op, x, colour);
 }
 
 template <class T>
@@ -817,21 +816,21 @@ void launch_residual(const Geom &g, Op<TA> op, const TX *fo, const TX *x, TR *r,
                      int *nblocks_out, hipStream_t s) {
     dim3 gr = grid2d(g);
     if (nblocks_out) *nblocks_out = (int)(gr.x * gr.y);
-    k_residual<TA, TX, TR><<<gr, kBlock2d, 0, s>>>(g, op, fo, x, r, partials);
+    k_residual<TA, TX, TR><<<gr, blk2d(g), 0, s>>>(g, op, fo, x, r, partials);
 }
 
 template <class T>
 void launch_restrict(const Geom &gf, const T *rf, const Geom &gc, T *fc, hipStream_t s) {
-    k_restrict<T><<<grid2d(gc), kBlock2d, 0, s>>>(gf, rf, gc, fc);
+    k_restrict<T><<<grid2d(gc), blk2d(gc), 0, s>>>(gf, rf, gc, fc);
 }
 
 template <class T>
 void launch_prolong(const Geom &gf, T *xf, const Geom &gc, const T *xc, hipStream_t s) {
-    k_prolong<T><<<grid2d(gf), kBlock2d, 0, s>>>(gf, xf, gc, xc);
+    k_prolong<T><<<grid2d(gf), blk2d(gf), 0, s>>>(gf, xf, gc, xc);
 }
 
 void launch_prolong_state(const Geom &gf, double *xf, const Geom &gc, const double *xc, hipStream_t s) {
-    k_prolong_state<<<grid2d(gf), kBlock2d, 0, s>>>(gf, xf, gc, xc);
+    k_prolong_state<<<grid2d(gf), blk2d(gf), 0, s>>>(gf, xf, gc, xc);
 }
 
 void launch_coarse_factor(const Geom &g, Op<double> op, double *scratch, double *invT, float *invT32,
@@ -857,23 +856,23 @@ void launch_diff_norms(const Geom &g, const double *a, const double *b, double *
                        int *nblocks_out, hipStream_t s, const Batch &bt) {
     dim3 gr = grid2d(g);
     if (nblocks_out) *nblocks_out = (int)(gr.x * gr.y);
-    k_diff_norms<<<dim3(gr.x, gr.y, bt.n), kBlock2d, 0, s>>>(g, a, b, partials, bt);
+    k_diff_norms<<<dim3(gr.x, gr.y, bt.n), blk2d(g), 0, s>>>(g, a, b, partials, bt);
 }
 
 void launch_copy_field(const Geom &g, const double *src, double *dst, hipStream_t s, const Batch &bt) {
-    k_copy_field<<<dim3(grid2d(g).x, grid2d(g).y, bt.n), kBlock2d, 0, s>>>(g, src, dst, bt);
+    k_copy_field<<<dim3(grid2d(g).x, grid2d(g).y, bt.n), blk2d(g), 0, s>>>(g, src, dst, bt);
 }
 
 void launch_to_f32(const Geom &g, const double *src, float *dst, hipStream_t s) {
-    k_to_f32<<<grid2d(g), kBlock2d, 0, s>>>(g, src, dst);
+    k_to_f32<<<grid2d(g), blk2d(g), 0, s>>>(g, src, dst);
 }
 
 void launch_add_f32(const Geom &g, double *x, const float *e, hipStream_t s) {
-    k_add_f32<<<grid2d(g), kBlock2d, 0, s>>>(g, x, e);
+    k_add_f32<<<grid2d(g), blk2d(g), 0, s>>>(g, x, e);
 }
 
 void launch_op_to_f32(const Geom &g, Op<double> op, Op<float> o32, hipStream_t s) {
-    k_op_to_f32<<<grid2d(g), kBlock2d, 0, s>>>(g, op, o32);
+    k_op_to_f32<<<grid2d(g), blk2d(g), 0, s>>>(g, op, o32);
 }
 
 template void launch_rbgs<double>(const Geom &, Op<double>, double *, int, hipStream_t);

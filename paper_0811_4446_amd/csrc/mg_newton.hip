@@ -19,9 +19,9 @@ namespace mgf {
 namespace {
 
 constexpr int kTX = 64;
-constexpr int kTY = 4;
 
-inline dim3 grid2d(const Geom &g) { return dim3((g.nz + 1 + kTX - 1) / kTX, (g.nr + 1 + kTY - 1) / kTY); }
+inline dim3 grid2d(const Geom &g) { return dim3((g.nz + 1 + kTX - 1) / kTX, (g.nr + 1 + g.ty - 1) / g.ty); }
+inline dim3 blk2d(const Geom &g) { return dim3(kTX, g.ty); }
 inline __device__ int64_t at(const Geom &g, int i, int j) { return (int64_t)i * g.pitch + j; }
 
 inline __device__ double bF(double x) {
@@ -96,7 +96,7 @@ __global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, c
     if (php) ph = php[blockIdx.z];
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     int64_t p = at(g, i, j);
     if (j == 0 || j == g.nz) {
@@ -220,7 +220,7 @@ __global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__re
     x = boff(x, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j < 1 || j >= g.nz || ((i + j) & 1) != colour) return;
     block_gs_node(g, J, f, x, i, j);
 }
@@ -264,7 +264,7 @@ __global__ void k_block_residual(Geom g, BOpT<T> J, const T *__restrict__ f, con
     r = boff(r, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     block_residual_node(g, J, f, x, r, apply, i, j);
 }
@@ -308,7 +308,7 @@ __global__ void k_restrict3(Geom gf, const T *__restrict__ rf, int64_t pf, Geom 
     fc = boff(fc, bo_);
 
     int J_ = blockIdx.x * kTX + threadIdx.x;
-    int I = blockIdx.y * kTY + threadIdx.y;
+    int I = blockIdx.y * blockDim.y + threadIdx.y;
     if (I > gc.nr || J_ > gc.nz) return;
     restrict3_node(gf, rf, pf, gc, fc, pc, I, J_);
 }
@@ -347,7 +347,7 @@ __global__ void k_prolong3(Geom gf, T *__restrict__ xf, int64_t pf, Geom gc, con
     xc = boff(xc, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > gf.nr || j < 1 || j >= gf.nz) return;
     prolong3_node(gf, xf, pf, gc, xc, pc, i, j);
 }
@@ -364,7 +364,7 @@ __global__ void k_inject3(Geom gf, const double *__restrict__ V, const double *_
     out = boff(out, bo_);
 
     int J_ = blockIdx.x * kTX + threadIdx.x;
-    int I = blockIdx.y * kTY + threadIdx.y;
+    int I = blockIdx.y * blockDim.y + threadIdx.y;
     if (I > gc.nr || J_ > gc.nz) return;
     int64_t q = at(gc, I, J_), p = at(gf, 2 * I, 2 * J_);
     out[q] = V[p];
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
 
 // ---- FGMRES BLAS-1 (weighted inner product) ----
 // <u, v>_W = sum over unknown nodes and fields of u v (c_f / vol)^2.
-__global__ __launch_bounds__(256) void k_wdot_multi(Geom g, const double *__restrict__ w,
+__global__ __launch_bounds__(1024) void k_wdot_multi(Geom g, const double *__restrict__ w,
                                                      const double *__restrict__ basis, int64_t vstride, int nv,
                                                      int64_t plane, double3 cw, double *__restrict__ partials,
                                                      Batch bt) {
@@ -674,8 +674,8 @@ __global__ __launch_bounds__(256) void k_wdot_multi(Geom g, const double *__rest
     partials = boff(partials, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
-    __shared__ double sh[kTY][kMaxKrylov + 1];
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
+    __shared__ double sh[kMaxTY][kMaxKrylov + 1];
     bool ok = i <= g.nr && j >= 1 && j < g.nz;
     int64_t p = ok ? at(g, i, j) : 0;
     double iv = ok ? 1.0 / (g.wr[i] * g.dzc[j]) : 0.0;
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(256) void k_wdot_multi(Geom g, const double *__rest
     int t = threadIdx.y * kTX + threadIdx.x;
     if (t < nv) {
         double s = 0.0;
-        for (int y = 0; y < kTY; ++y) s += sh[y][t];
+        for (int y = 0; y < (int)blockDim.y; ++y) s += sh[y][t];
         partials[(int64_t)blk * nv + t] = s;
     }
 }
@@ -732,7 +732,7 @@ __global__ void k_axpy_multi(Geom g, double *__restrict__ w, const double *__res
     h = boff(h, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j < 1 || j >= g.nz) return;
     int64_t p = at(g, i, j);
     for (int f = 0; f < 3; ++f) {
@@ -755,7 +755,7 @@ __global__ void k_scale_by_norm(Geom g, const double *__restrict__ src, double *
     nrm2 = boff(nrm2, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     int64_t p = at(g, i, j);
     double s = 1.0 / sqrt(*nrm2);
@@ -765,7 +765,7 @@ __global__ void k_scale_by_norm(Geom g, const double *__restrict__ src, double *
 
 // Newton update u += du on the unknown nodes, with per-block sums of
 // |du_f| and |u_f| (l1) and the minima of the densities.
-__global__ __launch_bounds__(256) void k_newton_update(Geom g, double *__restrict__ V, double *__restrict__ ne,
+__global__ __launch_bounds__(1024) void k_newton_update(Geom g, double *__restrict__ V, double *__restrict__ ne,
                                                         double *__restrict__ np, const double *__restrict__ du,
                                                         int64_t plane, double *__restrict__ partials, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
@@ -778,7 +778,7 @@ __global__ __launch_bounds__(256) void k_newton_update(Geom g, double *__restric
     partials = boff(partials, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     double s[8] = {0, 0, 0, 0, 0, 0, 1e300, 1e300};
     if (i <= g.nr && j >= 1 && j < g.nz) {
         int64_t p = at(g, i, j);
@@ -803,13 +803,13 @@ __global__ __launch_bounds__(256) void k_newton_update(Geom g, double *__restric
         s[6] = fmin(s[6], __shfl_xor(s[6], off));
         s[7] = fmin(s[7], __shfl_xor(s[7], off));
     }
-    __shared__ double sh[kTY][8];
+    __shared__ double sh[kMaxTY][8];
     if (threadIdx.x == 0)
         for (int k = 0; k < 8; ++k) sh[threadIdx.y][k] = s[k];
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         double o[8] = {0, 0, 0, 0, 0, 0, 1e300, 1e300};
-        for (int y = 0; y < kTY; ++y) {
+        for (int y = 0; y < (int)blockDim.y; ++y) {
             for (int k = 0; k < 6; ++k) o[k] += sh[y][k];
             o[6] = fmin(o[6], sh[y][6]);
             o[7] = fmin(o[7], sh[y][7]);
@@ -848,38 +848,37 @@ __global__ __launch_bounds__(256) void k_reduce_newton(const double *__restrict_
 
 }  // namespace
 
-static const dim3 kB2(kTX, kTY);
 static dim3 gz(dim3 g, const Batch &bt) { return dim3(g.x, g.y, bt.n); }
 
 void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
                             const double *nek, const double *npk, const double *Se, const double *Sp,
                             const NewtonPhys &ph, bool with_rhs, hipStream_t s, const NewtonPhys *php,
                             const Batch &bt) {
-    k_newton_assemble<<<gz(grid2d(g), bt), kB2, 0, s>>>(g, J, V, ne, np, nek, npk, Se, Sp, ph, with_rhs ? 1 : 0,
+    k_newton_assemble<<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, V, ne, np, nek, npk, Se, Sp, ph, with_rhs ? 1 : 0,
                                                          php, bt);
 }
 template <class T>
 void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s, const Batch &bt) {
-    k_block_rbgs<T><<<gz(grid2d(g), bt), kB2, 0, s>>>(g, J, f, x, colour, bt);
+    k_block_rbgs<T><<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, f, x, colour, bt);
 }
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s, const Batch &bt) {
-    k_block_residual<T><<<gz(grid2d(g), bt), kB2, 0, s>>>(g, J, f, x, r, apply ? 1 : 0, bt);
+    k_block_residual<T><<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, f, x, r, apply ? 1 : 0, bt);
 }
 template <class T>
 void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc, int64_t pc, hipStream_t s,
                       const Batch &bt) {
-    k_restrict3<T><<<gz(grid2d(gc), bt), kB2, 0, s>>>(gf, rf, pf, gc, fc, pc, bt);
+    k_restrict3<T><<<gz(grid2d(gc), bt), blk2d(gc), 0, s>>>(gf, rf, pf, gc, fc, pc, bt);
 }
 template <class T>
 void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s,
                      const Batch &bt) {
-    k_prolong3<T><<<gz(grid2d(gf), bt), kB2, 0, s>>>(gf, xf, pf, gc, xc, pc, bt);
+    k_prolong3<T><<<gz(grid2d(gf), bt), blk2d(gf), 0, s>>>(gf, xf, pf, gc, xc, pc, bt);
 }
 void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
                     double *out, int64_t pc, hipStream_t s, const Batch &bt) {
-    k_inject3<<<gz(grid2d(gc), bt), kB2, 0, s>>>(gf, V, ne, np, gc, out, pc, bt);
+    k_inject3<<<gz(grid2d(gc), bt), blk2d(gc), 0, s>>>(gf, V, ne, np, gc, out, pc, bt);
 }
 void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s,
                                 const Batch &bt) {
@@ -905,21 +904,21 @@ int block_vec_blocks(const Geom &g) {
 void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
                        int64_t plane, double3 cw, double *partials, double *out, hipStream_t s, const Batch &bt) {
     dim3 gr = grid2d(g);
-    k_wdot_multi<<<gz(gr, bt), kB2, 0, s>>>(g, w, basis, vstride, nv, plane, cw, partials, bt);
+    k_wdot_multi<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, partials, bt);
     k_sum_cols<<<dim3(nv, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nv, out, bt);
 }
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                        const double *h, double sign, hipStream_t s, const Batch &bt) {
-    k_axpy_multi<<<gz(grid2d(g), bt), kB2, 0, s>>>(g, w, basis, vstride, nv, plane, h, sign, bt);
+    k_axpy_multi<<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, h, sign, bt);
 }
 void launch_scale_by_norm(const Geom &g, const double *src, double *dst, int64_t plane, const double *nrm2,
                           hipStream_t s, const Batch &bt) {
-    k_scale_by_norm<<<gz(grid2d(g), bt), kB2, 0, s>>>(g, src, dst, plane, nrm2, bt);
+    k_scale_by_norm<<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, src, dst, plane, nrm2, bt);
 }
 void launch_newton_update(const Geom &g, double *V, double *ne, double *np, const double *du, int64_t plane,
                           double *partials, double *out, hipStream_t s, const Batch &bt) {
     dim3 gr = grid2d(g);
-    k_newton_update<<<gz(gr, bt), kB2, 0, s>>>(g, V, ne, np, du, plane, partials, bt);
+    k_newton_update<<<gz(gr, bt), blk2d(g), 0, s>>>(g, V, ne, np, du, plane, partials, bt);
     k_reduce_newton<<<dim3(1, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), out, bt);
 }
 
@@ -935,7 +934,7 @@ __global__ void k_block_to_f32(Geom g, BOp J, BOpT<float> J32, Batch bt) {
     J32.base = boff(J32.base, bo_);
 
     int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * kTY + threadIdx.y;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     int64_t p = at(g, i, j);
     for (int k = 0; k < kBPlanes; ++k) J32.pl(k)[p] = (float)J.pl(k)[p];
@@ -968,7 +967,7 @@ __global__ void k_block_to_f32(Geom g, BOp J, BOpT<float> J32, Batch bt) {
     }
 }
 void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s, const Batch &bt) {
-    k_block_to_f32<<<gz(grid2d(g), bt), kB2, 0, s>>>(g, J, J32, bt);
+    k_block_to_f32<<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, J32, bt);
 }
 
 // planes -> FP32 copies (n planes of `plane` elements)

@@ -44,14 +44,11 @@ double3 field_weights(const mg_physics *ph) {
     return make_double3(1.0, 1.0, ph->k > 0 ? 1.0 / ph->k : 1.0);
 }
 
-// Levels at or below this size run in the single-workgroup sub-cycle.
-constexpr int kFuseMaxN = 32;
-
 template <class T>
 void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     const Level &L = c->lev[l];
     BOpT<T> J = Prec<T>::op(c, l);
-    if (c->nw.fuse && L.g.nr <= kFuseMaxN && L.g.nz <= kFuseMaxN && c->nlev - l <= kMaxFused) {
+    if (c->nw.fuse && L.g.nr <= c->nw.fuse_max && L.g.nz <= c->nw.fuse_max && c->nlev - l <= kMaxFused) {
         FusedLevelsT<T> F;
         memset(&F, 0, sizeof F);
         F.n = c->nlev - l;
@@ -421,7 +418,7 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
     double *w = cv.take<double>(3 * p0);
     double *delta = cv.take<double>(3 * p0);
     double *snap = cv.take<double>(3 * p0);
-    int nblk = ((d->nz + 1 + 63) / 64) * ((d->nr + 1 + 3) / 4);
+    int nblk = ((d->nz + 1 + 63) / 64) * (d->nr + 1);  // one row per workgroup at most
     double *part = cv.take<double>((int64_t)nblk * (m + 2) + (int64_t)nblk * 8 + 64);
     double *dev = cv.take<double>(4 * kMaxKrylov + 64);
     float *f32 = (d->prec == MG_FP32_IR) ? cv.take<float>(3 * p0) : nullptr;
@@ -906,6 +903,14 @@ int batch_solve_steady(mg_ctx *c, const mg_physics *phys, const mg_schedule *sc,
     }
     if (worst) fail(worst, "batch: some problems did not reach steady state");
     return worst;
+}
+
+void drop_graphs(mg_ctx *c) {
+    for (int t = 0; t < 64; ++t)
+        if (c->nw.exec[t]) {
+            (void)hipGraphExecDestroy(c->nw.exec[t]);
+            c->nw.exec[t] = nullptr;
+        }
 }
 
 int time_block_smoother(mg_ctx *c, int reps, double *avg_ms) {

@@ -92,6 +92,7 @@ SIGNATURES = {
     "mg_batch_state": (ctypes.c_int, [_VP, _I32, ctypes.POINTER(State)]),
     "solve_steady_batch": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(Schedule),
                                           ctypes.POINTER(Report)]),
+    "mg_set_tuning": (ctypes.c_int, [_VP, _I32, _I32]),
     "mg_last_error": (ctypes.c_char_p, []),
 }
 
@@ -242,6 +243,9 @@ class Solver:
         rep.code = code
         return rep
 
+    def tune(self, rows_per_block, fuse_max):
+        _check(lib().mg_set_tuning(self.ctx, rows_per_block, fuse_max))
+
     def time_kernel(self, which, eq=0, reps=50):
         ms = _D(0.0)
         _check(lib().mg_time_kernel(self.ctx, which, eq, reps, ctypes.byref(ms)))
@@ -294,6 +298,9 @@ class Batch:
     def get(self, p, name):
         torch.cuda.synchronize(self.device)
         return self.views[p][name][:, : self.nz + 1].cpu().numpy().copy()
+
+    def tune(self, rows_per_block, fuse_max):
+        _check(lib().mg_set_tuning(self.ctx, rows_per_block, fuse_max))
 
     def steady(self, phys_list, sched):
         P = (Physics * self.n)(*phys_list)

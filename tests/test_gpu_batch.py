@@ -81,3 +81,30 @@ def test_batch_matches_oracle_17():
         for name, ref in (("V", Vo), ("ne", neo), ("np", npo)):
             got = B.get(p, name)
             assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max(), (p, name)
+
+
+def test_every_launch_shape_gives_the_same_step():
+    """All autotuner candidates (rows per workgroup 1..16, fused coarse
+    sub-cycle off/16/32/64) give the same Newton step up to summation order."""
+    _say("launch shapes")
+    m = M()
+    N = 64
+    z = I.z_cos(N)
+    ne = I.initial_density(N, N, 0)
+    np_, V, S = ne.copy(), I.initial_potential(N, N, z), I.source(N, N, z)
+    ph = dict(I.PHYS)
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-12, max_cycles=400, newton_tol=1e-10)
+    ref = None
+    for ty in (4, 1, 2, 8, 16):
+        for fm in (32, 0, 16, 64):
+            sol = m.Solver(N, N, z, krylov_m=20, coarsest=4, prec=m.FP32_IR)
+            sol.tune(ty, fm)
+            t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)]
+            st = sol.state(t[0], t[1], t[2], t[3], t[3])
+            for dt in (1e-4, 1e-3):
+                sol.step(m.Physics.of(ph), st, dt, sc)
+            res = [sol.download(x) for x in t[:3]]
+            if ref is None:
+                ref = res
+            for a, b in zip(res, ref):
+                assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max(), (ty, fm)
