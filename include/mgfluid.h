@@ -194,6 +194,42 @@ int mg_batch_state(mg_ctx *batch, int32_t p, mg_state *out);
  * worst per-problem status. */
 int solve_steady_batch(mg_ctx *batch, const mg_physics *phys, const mg_schedule *sched, mg_report *reports);
 
+/* ---- learned warm start (replaces the coarse-to-fine extrapolation of the
+ * multilevel prolongation, Sec. 2) ----
+ * Network: four 3x3 convolutions with zero padding, 7 -> 32 -> 32 -> 32 -> 3
+ * channels, exact-erf GELU after the first three.  Parameters: one FP32
+ * device array of wn_param_count() values, per layer W[co][ci][3][3] then
+ * b[co].  Images are FP32 NCHW: inputs [B][7][H][W], outputs and targets
+ * [B][3][H][W], with H = nr+1 (radial nodes) and W = nz+1 (axial nodes).
+ * The convolutions run in bf16 on MFMA with FP32 accumulation.  `scratch`
+ * is caller-allocated device memory of wn_scratch_bytes(B, H, W) bytes.
+ * All calls are asynchronous on `stream` unless they return a loss. */
+int wn_param_count(void);
+int wn_scratch_bytes(int32_t B, int32_t H, int32_t W, int64_t *bytes);
+int wn_forward(const float *params, const float *in, float *out, int32_t B, int32_t H, int32_t W,
+               void *scratch, int64_t scratch_bytes, void *stream);
+/* Mean squared error over all outputs and its gradient w.r.t. params
+ * (grad_out: device, wn_param_count() floats; loss_out: host, synchronises). */
+int wn_grad(const float *params, const float *in, const float *target, int32_t B, int32_t H, int32_t W,
+            float *grad_out, double *loss_out, void *scratch, int64_t scratch_bytes, void *stream);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8; `step` counts from
+ * 1) on params with moments adam_m, adam_v (device, FP32, zero initially). */
+int wn_train_step(float *params, float *adam_m, float *adam_v, int32_t step, float lr, const float *in,
+                  const float *target, int32_t B, int32_t H, int32_t W, double *loss_out, void *scratch,
+                  int64_t scratch_bytes, void *stream);
+/* Input planes of one sample (out: [7][H][W]) from the prolonged coarse
+ * state `up` on the grid of `fine`: V/V_top, n_e/n_s, n_p/n_s, r/R, z/d,
+ * V_top/5, log10(ratio)/3, where n_s (written to nscale_dev, one device
+ * double) is the largest prolonged density. */
+int wn_features(mg_ctx *fine, const mg_state *up, double V_top, double ratio, float *out, double *nscale_dev);
+/* Training target: 100 x (steady - up) in the same units (out: [3][H][W]). */
+int wn_targets(mg_ctx *fine, const mg_state *up, const mg_state *steady, double V_top, const double *nscale_dev,
+               float *out);
+/* Initial state from the prediction: dst = up + prediction / 100 in
+ * physical units, densities clamped at zero, electrode rows from phys. */
+int wn_apply(mg_ctx *fine, const mg_state *up, const float *pred, double V_top, const double *nscale_dev,
+             const mg_physics *phys, mg_state *dst);
+
 /* Launch shape chosen by the autotuner: radial rows per workgroup of the 2D
  * kernels (1, 2, 4, 8 or 16; the workgroup spans 64 axial nodes), and the
  * largest level (nr, nz <= fuse_max_n) run inside the single-workgroup

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmgfluid.so")
-SOURCES = ["mg_kernels.hip", "mg_host.hip", "mg_newton.hip", "mg_newton_host.hip"]
+SOURCES = ["mg_kernels.hip", "mg_host.hip", "mg_newton.hip", "mg_newton_host.hip", "wn_net.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "mg_internal.h"
+#include "wn_net.h"
 
 namespace {
 constexpr int kMaxKrylovDesc = 40;
@@ -659,6 +660,77 @@ int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     *avg_ms = ms / reps;
+    return MG_OK;
+}
+
+int wn_param_count(void) { return kWnParams; }
+
+int wn_scratch_bytes(int32_t B, int32_t H, int32_t W, int64_t *bytes) {
+    if (B < 1 || H < 1 || W < 1 || !bytes) return fail(MG_EINVAL, "bad image batch shape");
+    *bytes = wn_scratch_size(B, H, W);
+    return MG_OK;
+}
+
+static int wn_check(const void *a, const void *b, int32_t B, int32_t H, int32_t W, const void *scratch,
+                    int64_t bytes) {
+    if (!a || !b || !scratch) return fail(MG_EINVAL, "null pointer");
+    if (B < 1 || H < 1 || W < 1) return fail(MG_EINVAL, "bad image batch shape %d x %d x %d", B, H, W);
+    if (bytes < wn_scratch_size(B, H, W)) return fail(MG_ENOMEM, "scratch too small");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256) return fail(MG_EINVAL, "scratch must be 256-byte aligned");
+    return MG_OK;
+}
+
+int wn_forward(const float *params, const float *in, float *out, int32_t B, int32_t H, int32_t W, void *scratch,
+               int64_t scratch_bytes, void *stream) {
+    if (int e = wn_check(params, in, B, H, W, scratch, scratch_bytes)) return e;
+    if (!out) return fail(MG_EINVAL, "null output");
+    return wn_forward_impl(params, in, out, B, H, W, scratch, reinterpret_cast<hipStream_t>(stream));
+}
+
+int wn_grad(const float *params, const float *in, const float *target, int32_t B, int32_t H, int32_t W,
+            float *grad_out, double *loss_out, void *scratch, int64_t scratch_bytes, void *stream) {
+    if (int e = wn_check(params, in, B, H, W, scratch, scratch_bytes)) return e;
+    if (!target) return fail(MG_EINVAL, "null target");
+    return wn_grad_impl(params, in, target, B, H, W, grad_out, loss_out, scratch,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
+int wn_train_step(float *params, float *adam_m, float *adam_v, int32_t step, float lr, const float *in,
+                  const float *target, int32_t B, int32_t H, int32_t W, double *loss_out, void *scratch,
+                  int64_t scratch_bytes, void *stream) {
+    if (int e = wn_check(params, in, B, H, W, scratch, scratch_bytes)) return e;
+    if (!target || !adam_m || !adam_v || step < 1) return fail(MG_EINVAL, "bad Adam state or target");
+    return wn_train_impl(params, adam_m, adam_v, step, lr, in, target, B, H, W, loss_out, scratch,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+int wn_features(mg_ctx *c, const mg_state *up, double V_top, double ratio, float *out, double *nscale_dev) {
+    if (int e = check_ctx(c)) return e;
+    if (!up || !up->V || !up->ne || !up->np || !out || !nscale_dev) return fail(MG_EINVAL, "null argument");
+    if (!(V_top != 0) || !(ratio > 0)) return fail(MG_EINVAL, "need V_top != 0 and ratio > 0");
+    launch_features(c->lev[0].g, up->V, up->ne, up->np, c->desc.R, c->desc.d, V_top, ratio, nscale_dev, out,
+                    c->stream);
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+int wn_targets(mg_ctx *c, const mg_state *up, const mg_state *steady, double V_top, const double *nscale_dev,
+               float *out) {
+    if (int e = check_ctx(c)) return e;
+    if (!up || !steady || !out || !nscale_dev) return fail(MG_EINVAL, "null argument");
+    launch_targets(c->lev[0].g, up->V, up->ne, up->np, steady->V, steady->ne, steady->np, V_top, nscale_dev, out,
+                   c->stream);
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+int wn_apply(mg_ctx *c, const mg_state *up, const float *pred, double V_top, const double *nscale_dev,
+             const mg_physics *phys, mg_state *dst) {
+    if (int e = check_ctx(c)) return e;
+    if (!up || !pred || !nscale_dev || !phys || !dst) return fail(MG_EINVAL, "null argument");
+    launch_apply(c->lev[0].g, up->V, up->ne, up->np, pred, V_top, nscale_dev, dst->V, dst->ne, dst->np, *phys,
+                 c->stream);
+    HIP_OK(hipGetLastError());
     return MG_OK;
 }
 

@@ -1,0 +1,489 @@
+// Learned warm start: a 4-layer 3x3 convolutional network (7 -> 32 -> 32 ->
+// 32 -> 3 channels, exact-erf GELU after the first three layers, zero
+// padding) that maps the prolonged coarse steady state (plus coordinate and
+// parameter planes) to a correction of it on the fine grid.  Forward and
+// input-gradient convolutions run on MFMA (v_mfma_f32_16x16x32_bf16: bf16
+// operands, FP32 accumulation) as implicit GEMMs; the weight gradient is an
+// FP32 reduction over pixels with deterministic partial sums; Adam keeps
+// FP32 master weights.
+//
+// Activations are NHWC bf16 with 32 channel slots (H = radial nodes, W =
+// axial nodes, so a row is one radial line of the solver's fields).
+#include <math.h>
+
+#include "wn_net.h"
+
+namespace mgf {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int kC = 32;  // channel slots of every activation
+
+struct LayerDims {
+    int ci, co;
+};
+__constant__ LayerDims kLayers[4] = {{7, 32}, {32, 32}, {32, 32}, {32, 3}};
+constexpr LayerDims kLayersH[4] = {{7, 32}, {32, 32}, {32, 32}, {32, 3}};
+
+inline __host__ __device__ int64_t param_offset(int l) {
+    int64_t off = 0;
+    for (int q = 0; q < l; ++q) off += (int64_t)kLayersH[q].co * kLayersH[q].ci * 9 + kLayersH[q].co;
+    return off;
+}
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// params (FP32, per layer W[co][ci][3][3] then b[co]) -> bf16 weight
+// tiles: WB[l][tap][co][ci] for the forward pass and WT[l][tap'][ci][co]
+// (taps mirrored) for the input gradient; biases copied to FP32 [l][32].
+__global__ void k_pack_weights(const float *__restrict__ params, __bf16 *__restrict__ WB, __bf16 *__restrict__ WT,
+                               float *__restrict__ bias) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;  // over 4 * 9 * 32 * 32
+    if (t >= 4 * 9 * kC * kC) return;
+    int l = t / (9 * kC * kC), r = t % (9 * kC * kC);
+    int tap = r / (kC * kC), co = (r / kC) % kC, ci = r % kC;
+    LayerDims d = kLayers[l];
+    const float *W = params + param_offset(l);
+    float w = (co < d.co && ci < d.ci) ? W[((int64_t)co * d.ci + ci) * 9 + tap] : 0.0f;
+    WB[(((int64_t)l * 9 + tap) * kC + co) * kC + ci] = (__bf16)w;
+    int tapm = 8 - tap;  // (ky, kx) -> (2-ky, 2-kx)
+    WT[(((int64_t)l * 9 + tapm) * kC + ci) * kC + co] = (__bf16)w;
+    if (tap == 0 && ci == 0) bias[l * kC + co] = (co < d.co) ? W[(int64_t)d.co * d.ci * 9 + co] : 0.0f;
+}
+
+// FP32 NCHW [B][7][H][W] -> bf16 NHWC with 32 channel slots (zeros beyond 7).
+__global__ void k_pack_input(const float *__restrict__ in, __bf16 *__restrict__ x, int B, int H, int W) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t npix = (int64_t)B * H * W;
+    if (t >= npix * kC) return;
+    int c = (int)(t % kC);
+    int64_t pix = t / kC;
+    int64_t b = pix / ((int64_t)H * W), hw = pix % ((int64_t)H * W);
+    x[t] = (__bf16)(c < 7 ? in[(b * 7 + c) * H * W + hw] : 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution as an implicit GEMM on MFMA.  One wavefront computes 16
+// consecutive pixels of one image row x 32 output channels: for each of the
+// 9 taps it multiplies the 16x32 bf16 input patch (pixels x input channels)
+// by the 32x32 weight tile (two 16x16x32 MFMAs, FP32 accumulators).
+// Operand layout of v_mfma_f32_16x16x32_bf16 (checked on the device):
+// lane l holds A[l%16][8*(l/16)..+7], B[8*(l/16)..+7][l%16] and returns
+// D[4*(l/16)+i][l%16], i = 0..3.
+// MODE 0: hidden layer   -> z (FP32) and gelu(z) (bf16)
+// MODE 1: last layer     -> FP32 NCHW output, channels < 3
+// MODE 2: input gradient -> (sum) * gelu'(zprev), bf16
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ in, const __bf16 *__restrict__ w,
+                                                 const float *__restrict__ bias, int B, int H, int W,
+                                                 __bf16 *__restrict__ out_act, float *__restrict__ out_z,
+                                                 float *__restrict__ out_f, const float *__restrict__ zprev) {
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int tiles_x = (W + 15) >> 4;
+    const int64_t ntiles = (int64_t)B * H * tiles_x;
+    if (tile >= ntiles) return;
+    const int xt = (int)(tile % tiles_x);
+    const int64_t by = tile / tiles_x;
+    const int y = (int)(by % H);
+    const int b = (int)(by / H);
+    const int x0 = xt * 16;
+    const int m = lane & 15, kg = lane >> 4;
+    f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const bf16x8 zero8 = {};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y + tap / 3 - 1, xx = x0 + m + tap % 3 - 1;
+        bf16x8 a = zero8;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+            a = *reinterpret_cast<const bf16x8 *>(in + (((int64_t)b * H + yy) * W + xx) * kC + 8 * kg);
+        const __bf16 *wt = w + (int64_t)tap * kC * kC;
+        bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(wt + (int64_t)m * kC + 8 * kg);
+        bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(wt + (int64_t)(16 + m) * kC + 8 * kg);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int px = x0 + 4 * kg + i;
+        if (px >= W) continue;
+        const int64_t pix = ((int64_t)b * H + y) * W + px;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int co = h * 16 + m;
+            float v = (h == 0) ? acc0[i] : acc1[i];
+            if (MODE == 0) {
+                v += bias[co];
+                out_z[pix * kC + co] = v;
+                out_act[pix * kC + co] = (__bf16)gelu(v);
+            } else if (MODE == 1) {
+                if (co < 3) out_f[(((int64_t)b * 3 + co) * H + y) * W + px] = v + bias[co];
+            } else {
+                out_act[pix * kC + co] = (__bf16)(v * gelu_grad(zprev[pix * kC + co]));
+            }
+        }
+    }
+}
+
+// MSE loss over B*3*H*W outputs: per-block partial sums of squared errors
+// and the output gradient 2 (out - target) / count as bf16 NHWC (3 of the
+// 32 channel slots).
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out, const float *__restrict__ tgt, int B,
+                                             int H, int W, __bf16 *__restrict__ dz, double *__restrict__ part) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t npix = (int64_t)B * H * W;
+    double s = 0.0;
+    if (t < npix) {
+        int64_t b = t / ((int64_t)H * W), hw = t % ((int64_t)H * W);
+        double inv = 2.0 / (3.0 * (double)npix);
+        for (int c = 0; c < kC; ++c) {
+            float g = 0.0f;
+            if (c < 3) {
+                int64_t q = (b * 3 + c) * H * W + hw;
+                float e = out[q] - tgt[q];
+                s += (double)e * e;
+                g = (float)(inv * e);
+            }
+            dz[t * kC + c] = (__bf16)g;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Weight and bias gradient of one layer:
+//   dW[co][ci][tap] = sum over pixels of dz[p][co] * a[p + tap offset][ci],
+//   db[co] = sum of dz[p][co].
+// Thread (tap, co) accumulates the 32 input channels over chunks of 32
+// pixels of one image row staged in LDS; every workgroup writes its partial
+// sums, reduced afterwards in a fixed order.
+constexpr int kWgChunk = 32;
+__global__ __launch_bounds__(320) void k_wgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ a, int B,
+                                               int H, int W, float *__restrict__ part) {
+    __shared__ float sdz[kWgChunk][kC];
+    __shared__ float sa[3][kWgChunk + 2][kC + 1];
+    const int t = threadIdx.x;
+    const bool owner = t < 9 * kC;
+    const int tap = t / kC, co = t % kC;
+    const int ky = tap / 3, kx = tap % 3;
+    float acc[kC];
+#pragma unroll
+    for (int c = 0; c < kC; ++c) acc[c] = 0.0f;
+    float accb = 0.0f;
+    const int chunks_x = (W + kWgChunk - 1) / kWgChunk;
+    const int64_t nchunks = (int64_t)B * H * chunks_x;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int cx = (int)(ch % chunks_x);
+        const int64_t by = ch / chunks_x;
+        const int y = (int)(by % H), b = (int)(by / H);
+        const int x0 = cx * kWgChunk;
+        __syncthreads();
+        for (int q = t; q < kWgChunk * kC; q += blockDim.x) {
+            int p = q / kC, c = q % kC;
+            int x = x0 + p;
+            sdz[p][c] = (x < W) ? (float)dz[(((int64_t)b * H + y) * W + x) * kC + c] : 0.0f;
+        }
+        for (int q = t; q < 3 * (kWgChunk + 2) * kC; q += blockDim.x) {
+            int r = q / ((kWgChunk + 2) * kC), p = (q / kC) % (kWgChunk + 2), c = q % kC;
+            int yy = y + r - 1, xx = x0 + p - 1;
+            sa[r][p][c] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                              ? (float)a[(((int64_t)b * H + yy) * W + xx) * kC + c]
+                              : 0.0f;
+        }
+        __syncthreads();
+        if (owner) {
+            for (int p = 0; p < kWgChunk; ++p) {
+                float g = sdz[p][co];
+                if (tap == 0) accb += g;
+#pragma unroll
+                for (int c = 0; c < kC; ++c) acc[c] += g * sa[ky][p + kx][c];
+            }
+        }
+    }
+    if (owner) {
+        float *o = part + (int64_t)blockIdx.x * (9 * kC * kC + kC);
+#pragma unroll
+        for (int c = 0; c < kC; ++c) o[((int64_t)co * kC + c) * 9 + tap] = acc[c];
+        if (tap == 0) o[9 * kC * kC + co] = accb;
+    }
+}
+
+// grad (param layout of layer l) = sum over workgroups of the partials.
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwg, int ci_real, int co_real,
+                               float *__restrict__ grad) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int E = 9 * kC * kC + kC;
+    if (e >= E) return;
+    float s = 0.0f;
+    for (int g = 0; g < nwg; ++g) s += part[(int64_t)g * E + e];
+    if (e < 9 * kC * kC) {
+        int co = e / (kC * 9), ci = (e / 9) % kC, tap = e % 9;
+        if (co < co_real && ci < ci_real) grad[((int64_t)co * ci_real + ci) * 9 + tap] = s;
+    } else {
+        int co = e - 9 * kC * kC;
+        if (co < co_real) grad[(int64_t)co_real * ci_real * 9 + co] = s;
+    }
+}
+
+__global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int n, float lr, float c1, float c2) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    float gt = g[t];
+    float mt = b1 * m[t] + (1.0f - b1) * gt;
+    float vt = b2 * v[t] + (1.0f - b2) * gt * gt;
+    m[t] = mt;
+    v[t] = vt;
+    p[t] -= lr * (mt / c1) / (sqrtf(vt / c2) + eps);
+}
+
+__global__ void k_sum_double(const double *__restrict__ part, int n, double *__restrict__ out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+struct Scratch {
+    __bf16 *WB, *WT, *X0, *A[3], *DZ[2];
+    float *bias, *Z[3], *OUT, *part, *grad;
+    double *lpart, *loss;
+    int nwg;
+};
+
+constexpr int kWgradBlocks = 512;
+
+Scratch carve_scratch(char *base, int B, int H, int W, int64_t *bytes) {
+    Scratch s;
+    int64_t off = 0;
+    auto take = [&](int64_t n) {
+        off = (off + 255) / 256 * 256;
+        char *p = base ? base + off : nullptr;
+        off += n;
+        return p;
+    };
+    int64_t npix = (int64_t)B * H * W;
+    s.WB = (__bf16 *)take(4 * 9 * kC * kC * 2);
+    s.WT = (__bf16 *)take(4 * 9 * kC * kC * 2);
+    s.bias = (float *)take(4 * kC * 4);
+    s.X0 = (__bf16 *)take(npix * kC * 2);
+    for (int i = 0; i < 3; ++i) s.A[i] = (__bf16 *)take(npix * kC * 2);
+    for (int i = 0; i < 3; ++i) s.Z[i] = (float *)take(npix * kC * 4);
+    for (int i = 0; i < 2; ++i) s.DZ[i] = (__bf16 *)take(npix * kC * 2);
+    s.OUT = (float *)take(npix * 3 * 4);
+    s.nwg = kWgradBlocks;
+    s.part = (float *)take((int64_t)kWgradBlocks * (9 * kC * kC + kC) * 4);
+    s.grad = (float *)take(kWnParams * 4);
+    s.lpart = (double *)take(((npix + 255) / 256 + 1) * 8);
+    s.loss = (double *)take(8);
+    if (bytes) *bytes = (off + 255) / 256 * 256;
+    return s;
+}
+
+void forward_pass(const Scratch &s, const float *params, const float *in, int B, int H, int W, hipStream_t st) {
+    int64_t npix = (int64_t)B * H * W;
+    k_pack_weights<<<(4 * 9 * kC * kC + 255) / 256, 256, 0, st>>>(params, s.WB, s.WT, s.bias);
+    k_pack_input<<<(unsigned)((npix * kC + 255) / 256), 256, 0, st>>>(in, s.X0, B, H, W);
+    int64_t tiles = (int64_t)B * H * ((W + 15) / 16);
+    unsigned g = (unsigned)((tiles + 3) / 4);
+    const __bf16 *x = s.X0;
+    for (int l = 0; l < 3; ++l) {
+        k_conv3x3<0><<<g, 256, 0, st>>>(x, s.WB + (int64_t)l * 9 * kC * kC, s.bias + l * kC, B, H, W, s.A[l], s.Z[l],
+                                          nullptr, nullptr);
+        x = s.A[l];
+    }
+    k_conv3x3<1><<<g, 256, 0, st>>>(x, s.WB + (int64_t)3 * 9 * kC * kC, s.bias + 3 * kC, B, H, W, nullptr, nullptr,
+                                      s.OUT, nullptr);
+}
+
+// Loss and gradient into s.grad (forward pass already run).
+void backward_pass(const Scratch &s, const float *target, int B, int H, int W, hipStream_t st) {
+    int64_t npix = (int64_t)B * H * W;
+    unsigned nb = (unsigned)((npix + 255) / 256);
+    k_mse<<<nb, 256, 0, st>>>(s.OUT, target, B, H, W, s.DZ[0], s.lpart);
+    k_sum_double<<<1, 256, 0, st>>>(s.lpart, (int)nb, s.loss);
+    int64_t tiles = (int64_t)B * H * ((W + 15) / 16);
+    unsigned g = (unsigned)((tiles + 3) / 4);
+    int cur = 0;
+    for (int l = 3; l >= 0; --l) {
+        const __bf16 *aprev = (l == 0) ? s.X0 : s.A[l - 1];
+        k_wgrad<<<s.nwg, 320, 0, st>>>(s.DZ[cur], aprev, B, H, W, s.part);
+        k_wgrad_reduce<<<(9 * kC * kC + kC + 255) / 256, 256, 0, st>>>(s.part, s.nwg, kLayersH[l].ci,
+                                                                        kLayersH[l].co, s.grad + param_offset(l));
+        if (l > 0) {
+            k_conv3x3<2><<<g, 256, 0, st>>>(s.DZ[cur], s.WT + (int64_t)l * 9 * kC * kC, nullptr, B, H, W,
+                                              s.DZ[cur ^ 1], nullptr, nullptr, s.Z[l - 1]);
+            cur ^= 1;
+        }
+    }
+}
+
+// Build the seven input planes of one sample from solver fields on the fine
+// grid: the prolonged coarse state (V, ne, np), r, z, V_top and the mobility
+// ratio.  Normalisation: V / V_top, n / n_scale, r / R, z / d, V_top / 5,
+// log10(ratio) / 3, where n_scale is the largest prolonged density.
+__global__ void k_features(Geom g, const double *__restrict__ V, const double *__restrict__ ne,
+                           const double *__restrict__ np, double R, double d, double vtop, double ratio,
+                           const double *__restrict__ nscale, float *__restrict__ out) {
+    int j = blockIdx.x * 64 + threadIdx.x;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    int64_t p = (int64_t)i * g.pitch + j;
+    int64_t HW = (int64_t)(g.nr + 1) * (g.nz + 1), q = (int64_t)i * (g.nz + 1) + j;
+    double ns = *nscale > 0 ? *nscale : 1.0;
+    out[0 * HW + q] = (float)(V[p] / vtop);
+    out[1 * HW + q] = (float)(ne[p] / ns);
+    out[2 * HW + q] = (float)(np[p] / ns);
+    out[3 * HW + q] = (float)(i * (g.dr) / R);
+    out[4 * HW + q] = (float)(g.z[j] / d);
+    out[5 * HW + q] = (float)(vtop / 5.0);
+    out[6 * HW + q] = (float)(log10(ratio) / 3.0);
+}
+
+// Largest density of the prolonged state (single workgroup, fixed order).
+__global__ void k_field_max(Geom g, const double *__restrict__ a, const double *__restrict__ b,
+                            double *__restrict__ out) {
+    __shared__ double sh[256];
+    double m = 0.0;
+    int64_t n = (int64_t)(g.nr + 1) * (g.nz + 1);
+    for (int64_t t = threadIdx.x; t < n; t += 256) {
+        int64_t p = (t / (g.nz + 1)) * g.pitch + t % (g.nz + 1);
+        m = fmax(m, fmax(a[p], b[p]));
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// Targets: the correction from the prolonged to the fine steady state in the
+// input's units, times kWnGain.  Apply: the inverse, with the densities
+// clamped at zero and the electrode rows set from the boundary values.
+__global__ void k_targets(Geom g, const double *__restrict__ Vu, const double *__restrict__ neu,
+                          const double *__restrict__ npu, const double *__restrict__ Vf,
+                          const double *__restrict__ nef, const double *__restrict__ npf, double vtop,
+                          const double *__restrict__ nscale, float *__restrict__ out) {
+    int j = blockIdx.x * 64 + threadIdx.x;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    int64_t p = (int64_t)i * g.pitch + j;
+    int64_t HW = (int64_t)(g.nr + 1) * (g.nz + 1), q = (int64_t)i * (g.nz + 1) + j;
+    double ns = *nscale > 0 ? *nscale : 1.0;
+    out[0 * HW + q] = (float)(kWnGain * (Vf[p] - Vu[p]) / vtop);
+    out[1 * HW + q] = (float)(kWnGain * (nef[p] - neu[p]) / ns);
+    out[2 * HW + q] = (float)(kWnGain * (npf[p] - npu[p]) / ns);
+}
+
+__global__ void k_apply(Geom g, const double *__restrict__ Vu, const double *__restrict__ neu,
+                        const double *__restrict__ npu, const float *__restrict__ corr, double vtop,
+                        const double *__restrict__ nscale, double *__restrict__ V, double *__restrict__ ne,
+                        double *__restrict__ np, double vb, double vt, double eb, double et, double pb, double pt) {
+    int j = blockIdx.x * 64 + threadIdx.x;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    int64_t p = (int64_t)i * g.pitch + j;
+    int64_t HW = (int64_t)(g.nr + 1) * (g.nz + 1), q = (int64_t)i * (g.nz + 1) + j;
+    double ns = *nscale > 0 ? *nscale : 1.0;
+    if (j == 0 || j == g.nz) {
+        V[p] = (j == 0) ? vb : vt;
+        ne[p] = (j == 0) ? eb : et;
+        np[p] = (j == 0) ? pb : pt;
+        return;
+    }
+    V[p] = Vu[p] + vtop * (double)corr[0 * HW + q] / kWnGain;
+    ne[p] = fmax(0.0, neu[p] + ns * (double)corr[1 * HW + q] / kWnGain);
+    np[p] = fmax(0.0, npu[p] + ns * (double)corr[2 * HW + q] / kWnGain);
+}
+
+}  // namespace
+
+int64_t wn_scratch_size(int B, int H, int W) {
+    int64_t bytes = 0;
+    carve_scratch(nullptr, B, H, W, &bytes);
+    return bytes;
+}
+
+int wn_forward_impl(const float *params, const float *in, float *out, int B, int H, int W, void *scratch,
+                    hipStream_t st) {
+    Scratch s = carve_scratch((char *)scratch, B, H, W, nullptr);
+    forward_pass(s, params, in, B, H, W, st);
+    HIP_OK(hipMemcpyAsync(out, s.OUT, (size_t)B * 3 * H * W * 4, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+int wn_grad_impl(const float *params, const float *in, const float *target, int B, int H, int W, float *grad_out,
+                 double *loss_host, void *scratch, hipStream_t st) {
+    Scratch s = carve_scratch((char *)scratch, B, H, W, nullptr);
+    forward_pass(s, params, in, B, H, W, st);
+    backward_pass(s, target, B, H, W, st);
+    if (grad_out) HIP_OK(hipMemcpyAsync(grad_out, s.grad, kWnParams * 4, hipMemcpyDeviceToDevice, st));
+    if (loss_host) {
+        HIP_OK(hipMemcpyAsync(loss_host, s.loss, 8, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        *loss_host /= 3.0 * (double)B * H * W;
+    }
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+int wn_train_impl(float *params, float *m, float *v, int step, float lr, const float *in, const float *target,
+                  int B, int H, int W, double *loss_host, void *scratch, hipStream_t st) {
+    Scratch s = carve_scratch((char *)scratch, B, H, W, nullptr);
+    forward_pass(s, params, in, B, H, W, st);
+    backward_pass(s, target, B, H, W, st);
+    float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    k_adam<<<(kWnParams + 255) / 256, 256, 0, st>>>(params, m, v, s.grad, kWnParams, lr, c1, c2);
+    if (loss_host) {
+        HIP_OK(hipMemcpyAsync(loss_host, s.loss, 8, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        *loss_host /= 3.0 * (double)B * H * W;
+    }
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}
+
+void launch_features(const Geom &g, const double *V, const double *ne, const double *np, double R, double d,
+                     double vtop, double ratio, double *nscale, float *out, hipStream_t s) {
+    k_field_max<<<1, 256, 0, s>>>(g, ne, np, nscale);
+    dim3 grid((g.nz + 64) / 64, (g.nr + 4) / 4);
+    k_features<<<grid, dim3(64, 4), 0, s>>>(g, V, ne, np, R, d, vtop, ratio, nscale, out);
+}
+
+void launch_targets(const Geom &g, const double *Vu, const double *neu, const double *npu, const double *Vf,
+                    const double *nef, const double *npf, double vtop, const double *nscale, float *out,
+                    hipStream_t s) {
+    dim3 grid((g.nz + 64) / 64, (g.nr + 4) / 4);
+    k_targets<<<grid, dim3(64, 4), 0, s>>>(g, Vu, neu, npu, Vf, nef, npf, vtop, nscale, out);
+}
+
+void launch_apply(const Geom &g, const double *Vu, const double *neu, const double *npu, const float *corr,
+                  double vtop, const double *nscale, double *V, double *ne, double *np, const mg_physics &ph,
+                  hipStream_t s) {
+    dim3 grid((g.nz + 64) / 64, (g.nr + 4) / 4);
+    k_apply<<<grid, dim3(64, 4), 0, s>>>(g, Vu, neu, npu, corr, vtop, nscale, V, ne, np, ph.V_bottom, ph.V_top,
+                                         ph.ne_bottom, ph.ne_top, ph.np_bottom, ph.np_top);
+}
+
+}  // namespace mgf

@@ -93,6 +93,16 @@ SIGNATURES = {
     "solve_steady_batch": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(Schedule),
                                           ctypes.POINTER(Report)]),
     "mg_set_tuning": (ctypes.c_int, [_VP, _I32, _I32]),
+    "wn_param_count": (ctypes.c_int, []),
+    "wn_scratch_bytes": (ctypes.c_int, [_I32, _I32, _I32, ctypes.POINTER(_I64)]),
+    "wn_forward": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _I64, _VP]),
+    "wn_grad": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _PD, _VP, _I64, _VP]),
+    "wn_train_step": (ctypes.c_int, [_VP, _VP, _VP, _I32, ctypes.c_float, _VP, _VP, _I32, _I32, _I32, _PD, _VP,
+                                     _I64, _VP]),
+    "wn_features": (ctypes.c_int, [_VP, ctypes.POINTER(State), _D, _D, _VP, _VP]),
+    "wn_targets": (ctypes.c_int, [_VP, ctypes.POINTER(State), ctypes.POINTER(State), _D, _VP, _VP]),
+    "wn_apply": (ctypes.c_int, [_VP, ctypes.POINTER(State), _VP, _D, _VP, ctypes.POINTER(Physics),
+                                ctypes.POINTER(State)]),
     "mg_last_error": (ctypes.c_char_p, []),
 }
 
@@ -318,6 +328,80 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """The warm-start network's parameters, Adam moments and scratch on one
+    device; every call runs the library's kernels."""
+
+    def __init__(self, params, device="cuda:0", stream=None):
+        self.device = torch.device(device)
+        self.P = lib().wn_param_count()
+        p = torch.as_tensor(np.asarray(params, dtype=np.float32))
+        assert p.numel() == self.P, (p.numel(), self.P)
+        self.params = p.to(self.device).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._scratch = {}
+
+    def scratch(self, B, H, W):
+        key = (B, H, W)
+        if key not in self._scratch:
+            n = _I64(0)
+            _check(lib().wn_scratch_bytes(B, H, W, ctypes.byref(n)))
+            self._scratch[key] = (torch.empty(n.value // 8 + 64, dtype=torch.float64, device=self.device), n.value)
+        return self._scratch[key]
+
+    def forward(self, x):
+        B, C, H, W = x.shape
+        out = torch.empty((B, 3, H, W), dtype=torch.float32, device=self.device)
+        s, n = self.scratch(B, H, W)
+        _check(lib().wn_forward(_ptr(self.params), _ptr(x), _ptr(out), B, H, W, _ptr(s), n,
+                                ctypes.c_void_p(self.stream.cuda_stream)))
+        return out
+
+    def grad(self, x, target):
+        B, C, H, W = x.shape
+        g = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        loss = _D(0.0)
+        s, n = self.scratch(B, H, W)
+        _check(lib().wn_grad(_ptr(self.params), _ptr(x), _ptr(target), B, H, W, _ptr(g), ctypes.byref(loss),
+                             _ptr(s), n, ctypes.c_void_p(self.stream.cuda_stream)))
+        return loss.value, g
+
+    def train_step(self, x, target, lr=1e-3):
+        B, C, H, W = x.shape
+        self.t += 1
+        loss = _D(0.0)
+        s, n = self.scratch(B, H, W)
+        _check(lib().wn_train_step(_ptr(self.params), _ptr(self.m), _ptr(self.v), self.t, lr, _ptr(x),
+                                   _ptr(target), B, H, W, ctypes.byref(loss), _ptr(s), n,
+                                   ctypes.c_void_p(self.stream.cuda_stream)))
+        return loss.value
+
+
+def features(sol, up_state, vtop, ratio):
+    """Input planes [7, H, W] of the prolonged coarse state on `sol`'s grid,
+    and the density scale (device double)."""
+    H, W = sol.nr + 1, sol.nz + 1
+    out = torch.empty((7, H, W), dtype=torch.float32, device=sol.device)
+    ns = torch.zeros(1, dtype=torch.float64, device=sol.device)
+    _check(lib().wn_features(sol.ctx, ctypes.byref(up_state), float(vtop), float(ratio), _ptr(out), _ptr(ns)))
+    return out, ns
+
+
+def targets(sol, up_state, steady_state, vtop, ns):
+    out = torch.empty((3, sol.nr + 1, sol.nz + 1), dtype=torch.float32, device=sol.device)
+    _check(lib().wn_targets(sol.ctx, ctypes.byref(up_state), ctypes.byref(steady_state), float(vtop), _ptr(ns),
+                            _ptr(out)))
+    return out
+
+
+def apply_prediction(sol, up_state, pred, vtop, ns, phys, dst_state):
+    _check(lib().wn_apply(sol.ctx, ctypes.byref(up_state), _ptr(pred), float(vtop), _ptr(ns),
+                          ctypes.byref(phys), ctypes.byref(dst_state)))
 
 
 def schedule(dt0=1e-4, growth=1.5, dt_max=0.1, steady_tol=1e-8, lin_rtol=1e-10, max_steps=100000,
