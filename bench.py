@@ -105,6 +105,90 @@ def cpu_baseline(I, newton_its_gpu, vtop=1.0, N=256):
                                                                                  newton_its_gpu))
 
 
+def roofline(sol, N, reps=200):
+    """Roofline entry of the dominant kernel, the one-launch collective
+    red-black block sweep (k_block_rb_sweep) on the finest level: its
+    average launch duration from HIP events recorded on the library's
+    stream around `reps` consecutive sweeps (the Jacobian of the last
+    solve), against the algorithmic bytes of one sweep: per unknown node 27
+    Jacobian entries, 3 right-hand-side values and 3 old unknowns read, 3
+    new unknowns written (FP64)."""
+    avg_ms = sol.time_kernel(4, 0, reps=reps)
+    nodes = (N + 1) * (N - 1)
+    bytes_launch = 8.0 * nodes * 36
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    return dict(bound="hbm", kernel="k_block_rb_sweep", level="%dx%d" % (N + 1, N + 1), achieved=round(achieved, 1),
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                avg_launch_us=round(avg_ms * 1e3, 3), algorithmic_bytes_per_launch=int(bytes_launch),
+                timed_launches=reps)
+
+
+def roofline_only(args, M, I):
+    """The roofline measurement alone (for counter runs): a 257x257 context,
+    one Newton step from the seeded start to assemble a Jacobian, the timed
+    half-sweeps, then a plain 512 MiB device copy whose bytes calibrate the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    N = args.grid
+    z = I.z_cos(N)
+    phys = dict(I.PHYS)
+    P = M.Physics.of(phys)
+    sol = M.Solver(N, N, z, krylov_m=30, coarsest=4, prec=M.FP64)
+    ne = I.initial_density(N, N, 0)
+    t = [sol.upload(I.initial_potential(N, N, z, 0.0, phys["V_top"])), sol.upload(ne), sol.upload(ne),
+         sol.upload(I.source(N, N, z))]
+    st = sol.state(t[0], t[1], t[2], t[3], t[3])
+    sol.step(P, st, 1e-3, schedule(M, args.lin_rtol))
+    roof = roofline(sol, N, reps=args.reps)
+    a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    roof["calibration_copy_bytes"] = a.numel() * 8
+    print(json.dumps({"roofline": roof}), flush=True)
+
+
+def trace_summary(path, top=25):
+    """Summary of a rocprofv3 CSV: a kernel trace (per kernel and grid
+    shape: calls, total and average duration) or a counter collection (per
+    kernel, grid shape and counter: dispatches and mean value)."""
+    import csv
+    import collections
+    agg = collections.OrderedDict()
+    kind = None
+    with open(path) as f:
+        rd = csv.DictReader(f)
+        cols = rd.fieldnames
+        kind = "counters" if "Counter_Name" in cols else "trace"
+        for row in rd:
+            name = row["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+            if "Grid_Size" in row:
+                grid = row["Grid_Size"]
+            else:
+                grid = "%sx%sx%s" % (row.get("Grid_Size_X"), row.get("Grid_Size_Y"), row.get("Grid_Size_Z"))
+            if kind == "trace":
+                key = (name[:70], grid)
+                d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+                e = agg.setdefault(key, [0, 0])
+                e[0] += 1
+                e[1] += d
+            else:
+                key = (name[:70], grid, row["Counter_Name"])
+                e = agg.setdefault(key, [0, 0.0])
+                e[0] += 1
+                e[1] += float(row["Counter_Value"])
+    if kind == "trace":
+        tot = sum(v[1] for v in agg.values())
+        print("%-70s %-16s %9s %12s %10s %7s" % ("kernel", "grid", "calls", "total_ms", "avg_us", "share"))
+        for (name, grid), (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+            print("%-70s %-16s %9d %12.3f %10.3f %6.2f%%" % (name, grid, c, t / 1e6, t / c / 1e3, 100.0 * t / tot))
+    else:
+        print("%-70s %-16s %-14s %9s %16s" % ("kernel", "grid", "counter", "dispatches", "mean_per_dispatch"))
+        for (name, grid, cn), (c, v) in agg.items():
+            print("%-70s %-16s %-14s %9d %16.1f" % (name, grid, cn, c, v / c))
+
+
 def compare_precisions(args, M, I, N, vtops):
     """Time-to-steady of the finest stage with the FP64 and the FP32 block
     preconditioner (Newton residuals, FGMRES and the stop rules in FP64), from
@@ -220,6 +304,40 @@ def sweep(args, M, I):
     print(json.dumps(out), flush=True)
 
 
+def learned(args, M, I):
+    """Learned warm start on 257x257: train the network on solver-generated
+    steady solutions, then compare time-to-steady from its prediction with
+    the plain prolongation start on held-out draws."""
+    import numpy as np
+    import torch
+    from paper_0811_4446_amd import warmstart as WS
+    os.environ.setdefault("MGF_PROGRESS", "1")
+    t0 = time.time()
+    tr = WS.generate(WS.draws(args.n_train, 2024), log=log)
+    va = WS.generate(WS.draws(args.n_val, 7), log=log)
+    te = WS.generate(WS.draws(args.n_test, 8), log=log)
+    tgen = time.time() - t0
+    t1 = time.time()
+    net, hist = WS.train(tr, va, epochs=args.epochs, log=log)
+    torch.cuda.synchronize()
+    ttrain = time.time() - t1
+    if args.save_weights:
+        np.save(args.save_weights, net.params.cpu().numpy())
+    summary = WS.compare(net, te, timed=args.n_timed, criterion=args.criterion, log=log)
+    summary = {k: v for k, v in summary.items() if not k.startswith("_")}
+    vals = summary["single_seconds_learned"]
+    out = {"metric": METRIC, "value": round(float(np.mean(vals)), 4) if vals else None, "unit": "s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64+bf16", "data": "synthetic",
+           "config": {"workload": "steady 257x257 from the learned warm start vs the plain prolongation of the "
+                                  "129x129 steady state (held-out draws)",
+                      "n_train": args.n_train, "n_val": args.n_val, "n_test": args.n_test, "epochs": args.epochs,
+                      "data_generation_s": round(tgen, 1), "training_s": round(ttrain, 1),
+                      "final_train_loss": hist[-1][1], "final_val_loss": hist[-1][2],
+                      "initial_val_loss": hist[0][2], "summary": summary}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,9 +349,23 @@ def main():
     ap.add_argument("--grid", type=int, default=256, help="finest N (256: 257x257 workload; 1024 for 1025x1025)")
     ap.add_argument("--sweep", action="store_true", help="batched parameter sweep instead of the chain")
     ap.add_argument("--nprob", type=int, default=512)
+    ap.add_argument("--learned", action="store_true", help="learned warm start: train and compare on 257x257")
+    ap.add_argument("--n-train", type=int, default=128)
+    ap.add_argument("--n-val", type=int, default=16)
+    ap.add_argument("--n-test", type=int, default=16)
+    ap.add_argument("--n-timed", type=int, default=6)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--save-weights", type=str, default="")
+    ap.add_argument("--criterion", choices=["run", "newton", "residual"], default="run",
+                    help="fallback test of the learned warm start")
+    ap.add_argument("--roofline-only", action="store_true", help="only the roofline timing (+ copy calibration)")
+    ap.add_argument("--reps", type=int, default=200, help="timed half-sweeps of the roofline measurement")
+    ap.add_argument("--trace-summary", type=str, default="", help="summarise a rocprofv3 CSV and exit")
     ap.add_argument("--prec", choices=["fp64", "fp32", "both"], default="fp64",
                     help="block preconditioner precision (FGMRES and Newton stay FP64)")
     args = ap.parse_args()
+    if args.trace_summary:
+        return trace_summary(args.trace_summary)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (asked for %d); the batch of "
               "independent solves would shard across GPUs, see the design notes" % args.gpus)
@@ -243,8 +375,12 @@ def main():
     from paper_0811_4446_amd import inputs as I
     from paper_0811_4446_amd import mgfluid as M
 
+    if args.roofline_only:
+        return roofline_only(args, M, I)
     if args.sweep:
         return sweep(args, M, I)
+    if args.learned:
+        return learned(args, M, I)
     vtops = [float(v) for v in args.vtops.split(",")]
     N = args.grid
     if args.prec != "fp64":
@@ -279,17 +415,7 @@ def main():
     for vt, rd in reps:
         log("V_top=%g steps=%d newton=%d fgmres=%d t=%.3f s" % (vt, rd["steps"], rd["newton_its"],
                                                               rd["vcycles"], rd["seconds"]))
-    # roofline of the dominant kernel: the collective red-black block smoother
-    fine = cases[-1][1]
-    avg_ms = fine.time_kernel(0, 0, reps=200)
-    nodes = (N + 1) * (N - 1)
-    # per half-sweep: the updated colour reads 27 Jacobian entries + 3 rhs and
-    # writes 3 unknowns; the other colour's 3 unknowns are read once
-    bytes_launch = 8.0 * nodes * (33 + 3) / 2.0
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    roof = dict(bound="hbm", kernel="k_block_rbgs", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                avg_launch_us=round(avg_ms * 1e3, 3), algorithmic_bytes_per_launch=int(bytes_launch))
+    roof = roofline(cases[-1][1], N)
     steps_mean = sum(rd["steps"] for _, rd in reps) / len(reps)
     newton_mean = sum(rd["newton_its"] for _, rd in reps) / len(reps)
     out = {

@@ -153,7 +153,9 @@ int mg_relres(mg_ctx *ctx, int eq, const double *x, double *relres_out);
 /* One backward-Euler step of length dt, Eq. (7).
  *   MG_COUPLE_DECOUPLED: Poisson with the densities of step k, then the SG
  *     electron and ion equations with the new potential.
- *   MG_COUPLE_NEWTON: Newton-Raphson on the coupled system (Eq. 14).
+ *   MG_COUPLE_NEWTON: Newton-Raphson on the coupled system (Eq. 14); the
+ *     report's last_change is the largest relative l1 size (per field) of
+ *     the last Newton correction.
  * st is updated in place; rep (optional) receives counts. */
 int implicit_step(mg_ctx *ctx, const mg_physics *phys, mg_state *st, double dt,
                   const mg_schedule *sched, mg_report *rep);
@@ -162,6 +164,11 @@ int implicit_step(mg_ctx *ctx, const mg_physics *phys, mg_state *st, double dt,
  * (Sec. 2, multilevel prolongation paragraph and the time-step rule). */
 int solve_steady(mg_ctx *ctx, const mg_physics *phys, mg_state *st,
                  const mg_schedule *sched, mg_report *rep);
+
+/* Weighted 2-norm of the steady residual F(u) of the coupled system
+ * (Eqs. 7-13 with dt = infinity; Poisson rows scaled by 1/k, every row by
+ * 1/vol) at the state st; needs krylov_m >= 1.  Synchronises. */
+int mg_steady_residual(mg_ctx *ctx, const mg_physics *phys, const mg_state *st, double *norm_out);
 
 /* Multilevel prolongation (Sec. 2): interpolate the state of the grid of
  * `coarse` onto the twice finer grid of `fine` (bilinear, the multigrid
@@ -234,7 +241,7 @@ int wn_apply(mg_ctx *fine, const mg_state *up, const float *pred, double V_top, 
  * kernels (1, 2, 4, 8 or 16; the workgroup spans 64 axial nodes), and the
  * largest level (nr, nz <= fuse_max_n) run inside the single-workgroup
  * coarse sub-cycle of the Newton preconditioner (0 disables it).  Results
- * change only by summation order.  Default 4 and 32. */
+ * change only by summation order.  Default 4 and 16. */
 int mg_set_tuning(mg_ctx *ctx, int32_t rows_per_block, int32_t fuse_max_n);
 
 /* ---- introspection used by the tests (kernel-level parity) ---- */
@@ -259,8 +266,9 @@ int mg_residual(mg_ctx *ctx, int eq, const double *x, double *r);
  * duration of one launch.  which: 0 collective red-black block smoother
  * half-sweep of the Newton system (level 0; needs an assembled Jacobian),
  * 1 zebra z-line half-sweep, 2 point red-black half-sweep, 3 residual
- * (scalar equation `eq`, assembled before).  Overwrites the level-0 work
- * vectors only.  Synchronises. */
+ * (scalar equation `eq`, assembled before), 4 full collective red-black
+ * sweep in one launch (both colours; level 0, assembled Jacobian).
+ * Overwrites the level-0 work vectors only.  Synchronises. */
 int mg_time_kernel(mg_ctx *ctx, int which, int eq, int32_t reps, double *avg_ms);
 
 /* Thread-local message of the last error. */

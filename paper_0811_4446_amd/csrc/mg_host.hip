@@ -359,6 +359,7 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     // sub-cycle, eager launches instead of captured graphs
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
     c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
+    c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
@@ -634,7 +635,7 @@ int solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedul
 int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
     if (int e = check_ctx(c)) return e;
     if (!avg_ms || reps < 1) return fail(MG_EINVAL, "bad reps or null output");
-    if (which == 0) return time_block_smoother(c, reps, avg_ms);
+    if (which == 0 || which == 4) return time_block_smoother(c, reps, which == 4, avg_ms);
     if (int e = check_eq(eq)) return e;
     if (!c->assembled[eq]) return fail(MG_EINVAL, "equation %d not assembled", eq);
     if (which < 1 || which > 3) return fail(MG_EINVAL, "bad kernel id %d", which);
@@ -661,6 +662,13 @@ int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
     (void)hipEventDestroy(b);
     *avg_ms = ms / reps;
     return MG_OK;
+}
+
+int mg_steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double *norm_out) {
+    if (int e = check_ctx(c)) return e;
+    if (!ph || !st || !norm_out || !st->V || !st->ne || !st->np || !st->Se || !st->Sp)
+        return fail(MG_EINVAL, "null argument");
+    return steady_residual(c, ph, st, norm_out);
 }
 
 int wn_param_count(void) { return kWnParams; }

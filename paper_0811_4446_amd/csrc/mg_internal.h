@@ -73,6 +73,34 @@ __host__ __device__ inline Geom geom_off(Geom g, int64_t off) {
     return g;
 }
 
+#ifdef __HIPCC__
+// Partial pivoting of the Gauss-Jordan factorisations: the first wavefront
+// finds the row r in [col, n) with the largest |M[r][col]| (the first such
+// row on ties, as a serial scan would) and stores it in *piv.  The caller
+// synchronises the workgroup afterwards.
+__device__ inline void pivot_search_wave0(const double *M, int64_t n2, int col, int n, int *piv) {
+    if (threadIdx.x >= 64) return;
+    int best = n;
+    double bv = -1.0;
+    for (int rr = col + (int)threadIdx.x; rr < n; rr += 64) {
+        double v = fabs(M[(int64_t)rr * n2 + col]);
+        if (v > bv) {
+            bv = v;
+            best = rr;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        double ov = __shfl_xor(bv, off);
+        int ob = __shfl_xor(best, off);
+        if (ov > bv || (ov == bv && ob < best)) {
+            bv = ov;
+            best = ob;
+        }
+    }
+    if (threadIdx.x == 0) *piv = best < n ? best : col;
+}
+#endif
+
 // ---- kernel launchers (mg_kernels.hip) ----
 void launch_poisson_assemble(const Geom &g, Op<double> op, const double *ne, const double *np,
                              double k, bool charge, hipStream_t s);
@@ -140,10 +168,11 @@ struct Carver {
 struct BLevel {
     double *J;      // kBPlanes planes
     double *x, *r;  // 3-field correction and residual
+    double *x2;     // partner of x for the fused red-black sweep (zero electrode rows)
     double *st;     // injected state (V, ne, np), levels >= 1
     double *cinvT;  // coarsest level: transposed inverse of the block matrix
     // FP32 copies for the mixed-precision preconditioner
-    float *J32, *x32, *r32, *cinvT32;
+    float *J32, *x32, *r32, *cinvT32, *x2_32;
 };
 
 struct NewtonWork {
@@ -165,8 +194,9 @@ struct NewtonWork {
     hipGraphExec_t exec[64] = {};
     double cw_cap[3] = {0, 0, 0};
     bool use_graphs = true;
+    bool rb_fused = true;      // full red-black sweeps in one launch (else two half-sweeps)
     bool fuse = true;  // single-workgroup coarse sub-cycle
-    int fuse_max = 32; // levels with nr, nz <= fuse_max run in it
+    int fuse_max = 16; // levels with nr, nz <= fuse_max run in it
 };
 
 }  // namespace mgf
@@ -201,8 +231,9 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl);
 int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
                          mg_report *rep, bool *converged);
 int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep);
-int time_block_smoother(mg_ctx *c, int reps, double *avg_ms);
+int time_block_smoother(mg_ctx *c, int reps, bool fused, double *avg_ms);
 void drop_graphs(mg_ctx *c);
+int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double *out);
 int64_t carve_ctx(mg_ctx *c, const mg_grid_desc *d, char *base);
 int upload_tables(mg_ctx *c);
 int validate_desc(const mg_grid_desc *d);

@@ -551,18 +551,7 @@ __global__ __launch_bounds__(256) void k_coarse_factor(Geom g, Op<double> op, do
     __shared__ int piv;
     __shared__ double fcol[kMaxCoarseUnknowns];
     for (int col = 0; col < n; ++col) {
-        if (threadIdx.x == 0) {
-            int best = col;
-            double bv = fabs(M[(int64_t)col * n2 + col]);
-            for (int rr = col + 1; rr < n; ++rr) {
-                double v = fabs(M[(int64_t)rr * n2 + col]);
-                if (v > bv) {
-                    bv = v;
-                    best = rr;
-                }
-            }
-            piv = best;
-        }
+        pivot_search_wave0(M, n2, col, n, &piv);
         __syncthreads();
         const int pv = piv;
         if (pv != col)
@@ -619,18 +608,7 @@ __global__ __launch_bounds__(256) void k_coarse_factor_lds(Geom g, Op<double> op
     }
     __syncthreads();
     for (int col = 0; col < n; ++col) {
-        if (threadIdx.x == 0) {
-            int best = col;
-            double bv = fabs(M[col * n2 + col]);
-            for (int rr = col + 1; rr < n; ++rr) {
-                double v = fabs(M[rr * n2 + col]);
-                if (v > bv) {
-                    bv = v;
-                    best = rr;
-                }
-            }
-            piv = best;
-        }
+        pivot_search_wave0(M, n2, col, n, &piv);
         __syncthreads();
         const int pv = piv;
         if (pv != col)

@@ -45,6 +45,9 @@ template <class T>
 void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s,
                        const Batch &bt = Batch());
 template <class T>
+void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, hipStream_t s,
+                           const Batch &bt = Batch());
+template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s, const Batch &bt = Batch());
 template <class T>

@@ -168,44 +168,87 @@ __global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, c
     }
 }
 
-// Sum over the four neighbours of B_nb x_nb for the three rows.
-template <class T>
-inline __device__ void nb_sum(const Geom &g, const BOpT<T> &J, const T *x, int64_t plane, int i, int64_t p,
-                              T &se, T &sp, T &sv) {
-    const T *xe = x, *xp = x + plane, *xv = x + 2 * plane;
-    int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
-    int dirs[4] = {0, 2, 3, 4};
-    bool has[4] = {i > 0, i < g.nr, true, true};
+// Sum over the four neighbours of B_nb x_nb for the three rows; xnb(t, c)
+// returns field c of neighbour t (0: i-1, 1: i+1, 2: j-1, 3: j+1).
+template <class T, class XNb>
+inline __device__ void nb_sum_of(const BOpT<T> &J, int64_t p, const bool (&has)[4], XNb xnb, T &se, T &sp, T &sv) {
+    const int dirs[4] = {0, 2, 3, 4};
     se = sp = sv = T(0);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         if (!has[t]) continue;
         int d = dirs[t];
-        int64_t q = nbp[t];
-        T v = xv[q];
-        se += J.pl(kEE + d)[p] * xe[q] + J.pl(kEV + d)[p] * v;
-        sp += J.pl(kPP + d)[p] * xp[q] + J.pl(kPV + d)[p] * v;
+        T v = xnb(t, 2);
+        se += J.pl(kEE + d)[p] * xnb(t, 0) + J.pl(kEV + d)[p] * v;
+        sp += J.pl(kPP + d)[p] * xnb(t, 1) + J.pl(kPV + d)[p] * v;
         sv += J.pl(kVV + d)[p] * v;
     }
 }
 
-// Collective Gauss-Seidel update of one node: the 3x3 centre block is
-// solved exactly for (n_e, n_p, V) with the neighbours held fixed.  The block
-// [[ee,0,eV],[0,pp,pV],[Ve,Vp,VV]] is reduced to the potential first.
+template <class T>
+inline __device__ void nb_sum(const Geom &g, const BOpT<T> &J, const T *x, int64_t plane, int i, int64_t p,
+                              T &se, T &sp, T &sv) {
+    const int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
+    const bool has[4] = {i > 0, i < g.nr, true, true};
+    nb_sum_of(J, p, has, [&](int t, int c) { return x[nbp[t] + c * plane]; }, se, sp, sv);
+}
+
+// The Jacobian row block and right-hand side of one node, held in registers.
+template <class T>
+struct NodeRow {
+    T ee[5], eV[5], pp[5], pV[5], VV[5], Ve, Vp, fe, fp, fv;
+};
+template <class T>
+inline __device__ void load_row(const BOpT<T> &J, const T *f, int64_t p, NodeRow<T> &R) {
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        R.ee[d] = J.pl(kEE + d)[p];
+        R.eV[d] = J.pl(kEV + d)[p];
+        R.pp[d] = J.pl(kPP + d)[p];
+        R.pV[d] = J.pl(kPV + d)[p];
+        R.VV[d] = J.pl(kVV + d)[p];
+    }
+    R.Ve = J.pl(kVe)[p];
+    R.Vp = J.pl(kVp)[p];
+    R.fe = f[p];
+    R.fp = f[p + J.plane];
+    R.fv = f[p + 2 * J.plane];
+}
+// Collective Gauss-Seidel update of one node: the neighbour sums of the
+// three rows, then the 3x3 centre block [[ee,0,eV],[0,pp,pV],[Ve,Vp,VV]]
+// solved exactly for (n_e, n_p, V), reduced to the potential first.
+template <class T, class XNb>
+inline __device__ void solve_row(const NodeRow<T> &R, const bool (&has)[4], XNb xnb, T &oe, T &op, T &ov) {
+    const int dirs[4] = {0, 2, 3, 4};
+    T se = T(0), sp = T(0), sv = T(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (!has[t]) continue;
+        int d = dirs[t];
+        T v = xnb(t, 2);
+        se += R.ee[d] * xnb(t, 0) + R.eV[d] * v;
+        sp += R.pp[d] * xnb(t, 1) + R.pV[d] * v;
+        sv += R.VV[d] * v;
+    }
+    T re = R.fe - se, rp = R.fp - sp, rv = R.fv - sv;
+    T a = R.Ve / R.ee[1], b = R.Vp / R.pp[1];
+    ov = (rv - a * re - b * rp) / (R.VV[1] - a * R.eV[1] - b * R.pV[1]);
+    oe = (re - R.eV[1] * ov) / R.ee[1];
+    op = (rp - R.pV[1] * ov) / R.pp[1];
+}
+
 template <class T>
 inline __device__ void block_gs_node(const Geom &g, const BOpT<T> &J, const T *f, T *x, int i, int j) {
-    int64_t p = at(g, i, j);
-    int64_t plane = J.plane;
-    T se, sp, sv;
-    nb_sum(g, J, x, plane, i, p, se, sp, sv);
-    T re = f[p] - se, rp = f[p + plane] - sp, rv = f[p + 2 * plane] - sv;
-    T ee = J.pl(kEE + 1)[p], eV = J.pl(kEV + 1)[p], pp = J.pl(kPP + 1)[p], pV = J.pl(kPV + 1)[p];
-    T VV = J.pl(kVV + 1)[p], Ve = J.pl(kVe)[p], Vp = J.pl(kVp)[p];
-    T a = Ve / ee, b = Vp / pp;
-    T xv = (rv - a * re - b * rp) / (VV - a * eV - b * pV);
-    x[p] = (re - eV * xv) / ee;
-    x[p + plane] = (rp - pV * xv) / pp;
-    x[p + 2 * plane] = xv;
+    const int64_t p = at(g, i, j), plane = J.plane;
+    NodeRow<T> R;
+    load_row(J, f, p, R);
+    const int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
+    const bool has[4] = {i > 0, i < g.nr, true, true};
+    T oe, op, ov;
+    solve_row(R, has, [&](int t, int c) { return x[nbp[t] + c * plane]; }, oe, op, ov);
+    x[p] = oe;
+    x[p + plane] = op;
+    x[p + 2 * plane] = ov;
 }
 
 // Red-black half-sweep: every unknown node with (i+j)%2 == colour.  Nodes of
@@ -223,6 +266,95 @@ __global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__re
     int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j < 1 || j >= g.nz || ((i + j) & 1) != colour) return;
     block_gs_node(g, J, f, x, i, j);
+}
+
+// One full collective red-black sweep (colour 0, then colour 1) from xin to
+// xout (distinct buffers whose electrode rows hold zeros).  A workgroup owns
+// a kSW x kSH tile (z by r); every thread first loads its node's Jacobian
+// row block into registers, so the tile's Jacobian is read once per sweep
+// in one batch.  The tile's colour-0 nodes and, from xin, the colour-0 nodes
+// of the ring around the tile (owned by the neighbouring workgroups) are
+// updated into LDS; the colour-1 update then reads its neighbours from LDS.
+// Every value equals what the two half-sweeps compute; the ring costs
+// (kSW + kSH) / (kSW kSH / 2) extra colour-0 updates.
+constexpr int kSW = 32, kSH = 16;
+template <class T>
+__global__ __launch_bounds__(kSW * kSH) void k_block_rb_sweep(Geom g, BOpT<T> J, const T *__restrict__ f,
+                                                              const T *__restrict__ xin, T *__restrict__ xout,
+                                                              Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    f = boff(f, bo_);
+    xin = boff(xin, bo_);
+    xout = boff(xout, bo_);
+
+    constexpr int W = kSW + 2;
+    __shared__ T lx[3][(kSH + 2) * W];
+    const int i0 = blockIdx.y * kSH, j0 = blockIdx.x * kSW;
+    const int64_t plane = J.plane;
+    const int ti = threadIdx.y, tj = threadIdx.x;
+    const int i = i0 + ti, j = j0 + tj;
+    const bool mine = i <= g.nr && j >= 1 && j < g.nz;
+    const int64_t p = at(g, i, j);
+    NodeRow<T> R;
+    if (mine) load_row(J, f, p, R);
+    // colour-0 update of node (ii, jj) from xin into LDS
+    auto red = [&](int ii, int jj, const NodeRow<T> &Q, T &oe, T &op, T &ov) {
+        const int64_t q = at(g, ii, jj);
+        const int64_t qnb[4] = {q - g.pitch, q + g.pitch, q - 1, q + 1};
+        const bool has[4] = {ii > 0, ii < g.nr, true, true};
+        solve_row(Q, has, [&](int t, int c) { return xin[qnb[t] + c * plane]; }, oe, op, ov);
+        const int l = (ii - i0 + 1) * W + (jj - j0 + 1);
+        lx[0][l] = oe;
+        lx[1][l] = op;
+        lx[2][l] = ov;
+    };
+    if (mine && ((i + j) & 1) == 0) {
+        T oe, op, ov;
+        red(i, j, R, oe, op, ov);
+        xout[p] = oe;
+        xout[p + plane] = op;
+        xout[p + 2 * plane] = ov;
+    }
+    {
+        const int k = ti * kSW + tj;
+        int ri = -1, rj = -1;
+        if (k < kSW) {
+            ri = i0 - 1;
+            rj = j0 + k;
+        } else if (k < 2 * kSW) {
+            ri = i0 + kSH;
+            rj = j0 + k - kSW;
+        } else if (k < 2 * kSW + kSH) {
+            ri = i0 + k - 2 * kSW;
+            rj = j0 - 1;
+        } else if (k < 2 * kSW + 2 * kSH) {
+            ri = i0 + k - 2 * kSW - kSH;
+            rj = j0 + kSW;
+        }
+        if (ri >= 0 && ri <= g.nr && rj >= 1 && rj < g.nz && ((ri + rj) & 1) == 0) {
+            NodeRow<T> Q;
+            load_row(J, f, at(g, ri, rj), Q);
+            T oe, op, ov;
+            red(ri, rj, Q, oe, op, ov);
+        }
+    }
+    __syncthreads();
+    if (!mine || ((i + j) & 1) != 1) return;
+    const int l = (ti + 1) * W + (tj + 1);
+    const int lnb[4] = {l - W, l + W, l - 1, l + 1};
+    const int64_t pnb[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
+    // electrode neighbours (j - 1 == 0 or j + 1 == nz) are not updated: read xin
+    const bool fixed[4] = {false, false, j - 1 == 0, j + 1 == g.nz};
+    const bool has[4] = {i > 0, i < g.nr, true, true};
+    T oe, op, ov;
+    solve_row(R, has, [&](int t, int c) { return fixed[t] ? xin[pnb[t] + c * plane] : lx[c][lnb[t]]; }, oe, op,
+              ov);
+    xout[p] = oe;
+    xout[p + plane] = op;
+    xout[p + 2 * plane] = ov;
 }
 
 // r = f - B x (apply == 0) or r = B x (apply == 1) at one node, 3 fields,
@@ -412,18 +544,7 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor(Geom g, BOp J, dou
     __shared__ int piv;
     __shared__ double fcol[3 * kMaxCoarseUnknowns];
     for (int col = 0; col < n; ++col) {
-        if (threadIdx.x == 0) {
-            int best = col;
-            double bv = fabs(M[(int64_t)col * n2 + col]);
-            for (int rr = col + 1; rr < n; ++rr) {
-                double v = fabs(M[(int64_t)rr * n2 + col]);
-                if (v > bv) {
-                    bv = v;
-                    best = rr;
-                }
-            }
-            piv = best;
-        }
+        pivot_search_wave0(M, n2, col, n, &piv);
         __syncthreads();
         const int pv = piv;
         if (pv != col)
@@ -491,18 +612,7 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
     }
     __syncthreads();
     for (int col = 0; col < n; ++col) {
-        if (threadIdx.x == 0) {
-            int best = col;
-            double bv = fabs(M[col * n2 + col]);
-            for (int rr = col + 1; rr < n; ++rr) {
-                double v = fabs(M[rr * n2 + col]);
-                if (v > bv) {
-                    bv = v;
-                    best = rr;
-                }
-            }
-            piv = best;
-        }
+        pivot_search_wave0(M, n2, col, n, &piv);
         __syncthreads();
         const int pv = piv;
         if (pv != col)
@@ -862,6 +972,13 @@ void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int co
     k_block_rbgs<T><<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, f, x, colour, bt);
 }
 template <class T>
+void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, hipStream_t s,
+                           const Batch &bt) {
+    static_assert(2 * kSW + 2 * kSH <= kSW * kSH, "one ring task per thread");
+    dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + kSH - 1) / kSH);
+    k_block_rb_sweep<T><<<gz(grid, bt), dim3(kSW, kSH), 0, s>>>(g, J, f, xin, xout, bt);
+}
+template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s, const Batch &bt) {
     k_block_residual<T><<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, f, x, r, apply ? 1 : 0, bt);
@@ -1005,6 +1122,8 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
 #define MGF_INST(T)                                                                                          \
     template void launch_block_rbgs<T>(const Geom &, const BOpT<T> &, const T *, T *, int, hipStream_t,      \
                                        const Batch &);                                                       \
+    template void launch_block_rb_sweep<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *,         \
+                                           hipStream_t, const Batch &);                                      \
     template void launch_block_residual<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
                                            hipStream_t, const Batch &);                                      \
     template void launch_restrict3<T>(const Geom &, const T *, int64_t, const Geom &, T *, int64_t,          \

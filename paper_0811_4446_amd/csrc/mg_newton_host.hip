@@ -28,6 +28,7 @@ struct Prec<double> {
     static BOpT<double> op(mg_ctx *c, int l) { return BOpT<double>{c->nw.lev[l].J, plane_of(c->lev[l])}; }
     static double *x(mg_ctx *c, int l) { return c->nw.lev[l].x; }
     static double *r(mg_ctx *c, int l) { return c->nw.lev[l].r; }
+    static double *x2(mg_ctx *c, int l) { return c->nw.lev[l].x2; }
     static const double *inv(mg_ctx *c) { return c->nw.lev[c->nlev - 1].cinvT; }
 };
 template <>
@@ -35,6 +36,7 @@ struct Prec<float> {
     static BOpT<float> op(mg_ctx *c, int l) { return BOpT<float>{c->nw.lev[l].J32, plane_of(c->lev[l])}; }
     static float *x(mg_ctx *c, int l) { return c->nw.lev[l].x32; }
     static float *r(mg_ctx *c, int l) { return c->nw.lev[l].r32; }
+    static float *x2(mg_ctx *c, int l) { return c->nw.lev[l].x2_32; }
     static const float *inv(mg_ctx *c) { return c->nw.lev[c->nlev - 1].cinvT32; }
 };
 
@@ -42,6 +44,23 @@ struct Prec<float> {
 // all three equations are measured in density units.
 double3 field_weights(const mg_physics *ph) {
     return make_double3(1.0, 1.0, ph->k > 0 ? 1.0 / ph->k : 1.0);
+}
+
+// nu collective red-black sweeps on level l: pairs of fused sweeps x -> x2 ->
+// x, and two half-sweeps for an odd last one.
+template <class T>
+void block_smooth(mg_ctx *c, int l, const BOpT<T> &J, const T *f, T *x, int nu, hipStream_t s) {
+    const Geom &g = c->lev[l].g;
+    int k = 0;
+    if (c->nw.rb_fused) {
+        T *x2 = Prec<T>::x2(c, l);
+        for (; k + 2 <= nu; k += 2) {
+            launch_block_rb_sweep<T>(g, J, f, x, x2, s, c->bt);
+            launch_block_rb_sweep<T>(g, J, f, x2, x, s, c->bt);
+        }
+    }
+    for (; k < nu; ++k)
+        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(g, J, f, x, col, s, c->bt);
 }
 
 template <class T>
@@ -70,8 +89,7 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         launch_block_coarse_solve<T>(L.g, J, f, Prec<T>::inv(c), x, s, c->bt);
         return;
     }
-    for (int k = 0; k < c->desc.nu1; ++k)
-        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(L.g, J, f, x, col, s, c->bt);
+    block_smooth<T>(c, l, J, f, x, c->desc.nu1, s);
     T *r = Prec<T>::r(c, l);
     launch_block_residual<T>(L.g, J, f, x, r, false, s, c->bt);
     const Level &C = c->lev[l + 1];
@@ -82,8 +100,7 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     launch_fill(xc, 3 * plane_of(C), T(0), s, c->bt);
     block_vcycle<T>(c, l + 1, fc, xc, s);
     launch_prolong3<T>(L.g, x, plane_of(L), C.g, xc, plane_of(C), s, c->bt);
-    for (int k = 0; k < c->desc.nu2; ++k)
-        for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(L.g, J, f, x, col, s, c->bt);
+    block_smooth<T>(c, l, J, f, x, c->desc.nu2, s);
 }
 
 // Assemble the Jacobian on every level: level 0 at the current state with
@@ -350,6 +367,7 @@ int newton_iterate(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, con
         const double *o = c->pinned;
         double re = o[0] / fmax(o[1], 1e-300), rp = o[2] / fmax(o[3], 1e-300), rv = o[4] / fmax(o[5], 1e-300);
         double mx = fmax(re, fmax(rp, rv));
+        if (rep) rep->last_change = mx;  // size of the last Newton correction
         if (!isfinite(mx)) return MG_OK;
         if (mx > sc->reject_limit) return MG_OK;
         if (mx < sc->newton_tol) {
@@ -396,12 +414,14 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
         memset(&B, 0, sizeof B);
         B.J = cv.take<double>(kBPlanes * pl);
         B.x = cv.take<double>(3 * pl);
+        B.x2 = cv.take<double>(3 * pl);
         B.r = cv.take<double>(3 * pl);
         B.st = (l > 0) ? cv.take<double>(3 * pl) : nullptr;
         bool p32 = d->prec == MG_FP32_IR;
         if (p32) {
             B.J32 = cv.take<float>(kBPlanes * pl);
             B.x32 = cv.take<float>(3 * pl);
+            B.x2_32 = cv.take<float>(3 * pl);
             B.r32 = cv.take<float>(3 * pl);
         }
         if (l == nl - 1) {
@@ -671,6 +691,7 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     carve_ctx(c, d, base);
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
     c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
+    c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     c->ws_base = base;
     c->ws_bytes = wsb;
     int64_t stride = toff / nprob;
@@ -913,17 +934,47 @@ void drop_graphs(mg_ctx *c) {
         }
 }
 
-int time_block_smoother(mg_ctx *c, int reps, double *avg_ms) {
+// Weighted norm of the steady residual F(u) (dt = infinity) at the state st:
+// the quantity the fallback test of the warm start compares.
+int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double *out) {
+    if (c->nw.m <= 0) return fail(MG_EINVAL, "no Newton workspace (krylov_m = 0)");
+    hipStream_t s = c->stream;
+    NewtonPhys np_;
+    np_.qe = ph->mu_e / ph->D_e;
+    np_.qp = -ph->mu_p / ph->D_p;
+    np_.De = ph->D_e;
+    np_.Dp = ph->D_p;
+    np_.k = ph->k;
+    np_.dt_inv = 0.0;
+    const Level &L0 = c->lev[0];
+    int64_t p0 = plane_of(L0);
+    BOp J = bop(c, 0);
+    launch_newton_assemble(L0.g, J, st->V, st->ne, st->np, st->ne, st->np, st->Se, st->Sp, np_, true, s);
+    launch_wdot_multi(L0.g, J.pl(kFe), J.pl(kFe), 3 * p0, 1, p0, field_weights(ph), c->nw.partials, c->nw.dev, s);
+    HIP_OK(hipMemcpyAsync(c->pinned, c->nw.dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    *out = sqrt(c->pinned[0]);
+    return MG_OK;
+}
+
+int time_block_smoother(mg_ctx *c, int reps, bool fused, double *avg_ms) {
     if (c->nw.m <= 0) return fail(MG_EINVAL, "no Newton workspace (krylov_m = 0)");
     const Level &L0 = c->lev[0];
     BOp J = bop(c, 0);
-    double *x = c->nw.lev[0].x;
+    double *x = c->nw.lev[0].x, *x2 = c->nw.lev[0].x2;
+    auto one = [&](int r) {
+        if (fused)
+            launch_block_rb_sweep<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, c->stream);
+        else
+            launch_block_rbgs<double>(L0.g, J, J.pl(kFe), x, r & 1, c->stream);
+    };
     hipEvent_t a, b;
     HIP_OK(hipEventCreate(&a));
     HIP_OK(hipEventCreate(&b));
-    launch_block_rbgs<double>(L0.g, J, J.pl(kFe), x, 0, c->stream);
+    one(0);
+    one(1);
     HIP_OK(hipEventRecord(a, c->stream));
-    for (int r = 0; r < reps; ++r) launch_block_rbgs<double>(L0.g, J, J.pl(kFe), x, r & 1, c->stream);
+    for (int r = 0; r < reps; ++r) one(r);
     HIP_OK(hipEventRecord(b, c->stream));
     HIP_OK(hipEventSynchronize(b));
     float ms = 0;

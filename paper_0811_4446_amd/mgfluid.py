@@ -93,6 +93,7 @@ SIGNATURES = {
     "solve_steady_batch": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(Schedule),
                                           ctypes.POINTER(Report)]),
     "mg_set_tuning": (ctypes.c_int, [_VP, _I32, _I32]),
+    "mg_steady_residual": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _PD]),
     "wn_param_count": (ctypes.c_int, []),
     "wn_scratch_bytes": (ctypes.c_int, [_I32, _I32, _I32, ctypes.POINTER(_I64)]),
     "wn_forward": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _I64, _VP]),
@@ -255,6 +256,11 @@ class Solver:
 
     def tune(self, rows_per_block, fuse_max):
         _check(lib().mg_set_tuning(self.ctx, rows_per_block, fuse_max))
+
+    def steady_residual(self, phys, state):
+        r = _D(0.0)
+        _check(lib().mg_steady_residual(self.ctx, ctypes.byref(phys), ctypes.byref(state), ctypes.byref(r)))
+        return r.value
 
     def time_kernel(self, which, eq=0, reps=50):
         ms = _D(0.0)

@@ -26,10 +26,10 @@ def relmax(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def _gpu(N, V, ne, np_, S, krylov_m=20, smoother=1):
+def _gpu(N, V, ne, np_, S, krylov_m=20, smoother=1, prec=None):
     m = M()
     z = I.z_cos(N)
-    sol = m.Solver(N, N, z, smoother=smoother, krylov_m=krylov_m)
+    sol = m.Solver(N, N, z, smoother=smoother, krylov_m=krylov_m, prec=m.FP64 if prec is None else prec)
     t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)]
     st = sol.state(t[0], t[1], t[2], t[3], t[3])
     return sol, t, st
@@ -115,3 +115,33 @@ def test_fused_subcycle_and_graphs_match_eager(N, monkeypatch):
     for key, res in results.items():
         for a, b in zip(res, base):
             assert np.array_equal(a, b), key
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_fused_rb_sweep_matches_half_sweeps(N, monkeypatch):
+    """One-launch red-black sweeps (tile + recomputed ring in LDS, ping-pong
+    buffers) give bitwise the Newton steps of two half-sweep launches, for
+    every tile height (the reductions' order depends on the tile height, so
+    each height is compared with itself) and in the FP32 preconditioner."""
+    _say("fused rb sweep", N)
+    m = M()
+    z, V, ne, np_, S = _start(N)
+    ph = dict(I.PHYS)
+    cp = NW.Coupled(N, N, 1.0, z, ph)
+    NW.steady(cp, V, ne, np_, S, S, max_steps=15)
+    for prec in (m.FP64, m.FP32_IR):
+        for rows in (1, 2, 4, 16):
+            results = {}
+            for half in (1, 0):
+                if half:
+                    monkeypatch.setenv("MGF_HALF_SWEEPS", "1")
+                else:
+                    monkeypatch.delenv("MGF_HALF_SWEEPS", raising=False)
+                sol, t, st = _gpu(N, V, ne, np_, S, krylov_m=20, prec=prec)
+                sol.tune(rows, 32)
+                sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-10, max_cycles=400, newton_tol=1e-10)
+                for dt in (1e-3, 1e-2, 0.1):
+                    sol.step(m.Physics.of(ph), st, dt, sc)
+                results[half] = [sol.download(x) for x in t[:3]]
+            for a, b in zip(results[0], results[1]):
+                assert np.array_equal(a, b), (prec, rows)

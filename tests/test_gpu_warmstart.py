@@ -117,3 +117,45 @@ def test_features_targets_apply_roundtrip():
     for k in range(3):
         got = sol.download(dst[k])
         assert np.abs(got - st[k]).max() <= 1e-6 * np.abs(st[k]).max()
+
+
+@pytest.fixture(scope="module")
+def small_warmstart():
+    """A network trained on the 33 -> 65 -> 129 chain (few draws, few
+    epochs) and held-out test data: enough to show the mechanism."""
+    _say("warm start: data 129x129 + training")
+    from paper_0811_4446_amd import warmstart as WS
+    log = lambda *a: print(*a)
+    tr = WS.generate(WS.draws(24, 2024), log=log, N=128)
+    va = WS.generate(WS.draws(4, 7), log=log, N=128)
+    te = WS.generate(WS.draws(6, 8), log=log, N=128)
+    net, hist = WS.train(tr, va, epochs=40, log=log)
+    return WS, net, te, hist
+
+
+def test_warm_start_gain_on_held_out_draws(small_warmstart):
+    """The network's start needs fewer time steps than the plain
+    prolongation on most held-out draws, and both runs end at the same
+    discrete steady solution once polished by steady Newton."""
+    _say("warm start gain 129x129")
+    WS, net, te, hist = small_warmstart
+    assert hist[-1][2] < 0.5 * hist[0][2]
+    s = WS.compare(net, te, timed=0, log=lambda *a: print(*a))
+    print({k: v for k, v in s.items() if not k.startswith("_")})
+    assert s["fallbacks"] == 0
+    assert s["network_start_steps_ratio_median"] < 1.0
+    assert s["steps_learned_mean"] < s["steps_plain_mean"]
+    assert s["polished_states_maxrel_diff_max"] < 1e-9
+
+
+def test_warm_start_forced_fallback(small_warmstart):
+    """A run from the network's start that cannot finish (step cap of 3)
+    falls back to the plain prolongation, whose result it then returns
+    bitwise."""
+    _say("warm start forced fallback 129x129")
+    WS, net, te, hist = small_warmstart
+    s = WS.compare(net, te, timed=0, attempt_steps=3, log=lambda *a: print(*a))
+    assert s["fallbacks"] == len(te["draws"])
+    for a, b in zip(s["_chosen_finals"], s["_plain_finals"]):
+        for k in ("V", "ne", "np"):
+            assert torch.equal(a[k], b[k])
