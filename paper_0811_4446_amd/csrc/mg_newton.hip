@@ -587,7 +587,7 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
     const int n = 3 * (g.nr + 1) * m;
     const int n2 = 2 * n;
     __shared__ double M[kLdsGJ * 2 * kLdsGJ];
-    __shared__ double fcol[kLdsGJ];
+    __shared__ double fcol[kLdsGJ], prow[2 * kLdsGJ], orow[2 * kLdsGJ];
     __shared__ int piv;
     for (int t = threadIdx.x; t < n * n2; t += blockDim.x) M[t] = 0.0;
     __syncthreads();
@@ -611,27 +611,33 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
         for (int f = 0; f < 3; ++f) M[(rowb + f) * n2 + n + rowb + f] = 1.0;
     }
     __syncthreads();
+    // Gauss-Jordan with partial pivoting, three barriers per column: the
+    // pivot row (scaled) and the row it replaces are staged, then every
+    // other row is eliminated against the staged pivot row.  Waves own rows,
+    // lanes own columns.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     for (int col = 0; col < n; ++col) {
         pivot_search_wave0(M, n2, col, n, &piv);
         __syncthreads();
         const int pv = piv;
-        if (pv != col)
-            for (int t = threadIdx.x; t < n2; t += blockDim.x) {
-                double tmp = M[col * n2 + t];
-                M[col * n2 + t] = M[pv * n2 + t];
-                M[pv * n2 + t] = tmp;
+        const double pinv = 1.0 / M[pv * n2 + col];
+        for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+            prow[t] = M[pv * n2 + t] * pinv;
+            orow[t] = M[col * n2 + t];
+        }
+        for (int rr = threadIdx.x; rr < n; rr += blockDim.x)
+            fcol[rr] = (rr == col) ? 0.0 : (rr == pv ? M[col * n2 + col] : M[rr * n2 + col]);
+        __syncthreads();
+        for (int rr = wave; rr < n; rr += nwave) {
+            const double fct = fcol[rr];
+            for (int cc = lane; cc < n2; cc += 64) {
+                if (rr == col) {
+                    M[rr * n2 + cc] = prow[cc];
+                } else {
+                    double v = (rr == pv) ? orow[cc] : M[rr * n2 + cc];
+                    M[rr * n2 + cc] = (fct != 0.0) ? v - fct * prow[cc] : v;
+                }
             }
-        __syncthreads();
-        const double pinv = 1.0 / M[col * n2 + col];
-        __syncthreads();
-        for (int t = threadIdx.x; t < n2; t += blockDim.x) M[col * n2 + t] *= pinv;
-        for (int rr = threadIdx.x; rr < n; rr += blockDim.x) fcol[rr] = M[rr * n2 + col];
-        __syncthreads();
-        for (int t = threadIdx.x; t < n * n2; t += blockDim.x) {
-            int rr = t / n2, cc = t % n2;
-            if (rr == col) continue;
-            double fct = fcol[rr];
-            if (fct != 0.0) M[rr * n2 + cc] -= fct * M[col * n2 + cc];
         }
         __syncthreads();
     }
@@ -693,23 +699,24 @@ template <class T>
 __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
-    for (int q = 0; q < F.n; ++q) {
-        F.g[q] = geom_off(F.g[q], bo_);
-        F.J[q] = boff(F.J[q], bo_);
-        F.x[q] = boff(F.x[q], bo_);
-        F.r[q] = boff(F.r[q], bo_);
-    }
-    F.f0 = boff(F.f0, bo_);
-    F.invT = boff(F.invT, bo_);
+    // F stays in the kernel-argument segment (read-only, indexed by level);
+    // the problem offset is applied to local copies
+    auto geom = [&](int q) { return geom_off(F.g[q], bo_); };
+    auto jac = [&](int q) { return BOpT<T>{boff(F.J[q], bo_), F.plane[q]}; };
+    auto xof = [&](int q) { return boff(F.x[q], bo_); };
+    auto rof = [&](int q) { return boff(F.r[q], bo_); };
+    const T *f0 = boff(F.f0, bo_);
+    const T *invT = boff(F.invT, bo_);
 
     __shared__ T rhs[3 * kMaxFusedCoarse];
     const int n = F.n;
     const int nt = blockDim.x;
     for (int q = 0; q < n - 1; ++q) {
-        const Geom &g = F.g[q];
-        BOpT<T> J{F.J[q], F.plane[q]};
-        const T *f = (q == 0) ? F.f0 : J.pl(kFe);
-        T *x = F.x[q];
+        const Geom g = geom(q);
+        const BOpT<T> J = jac(q);
+        const T *f = (q == 0) ? f0 : J.pl(kFe);
+        T *x = xof(q);
+        T *r = rof(q);
         const int nodes = (g.nr + 1) * (g.nz + 1);
         if (q > 0) {
             for (int t = threadIdx.x; t < nodes; t += nt) {
@@ -729,34 +736,36 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
             }
         for (int t = threadIdx.x; t < nodes; t += nt) {
             int i = t / (g.nz + 1), j = t % (g.nz + 1);
-            block_residual_node(g, J, f, x, F.r[q], 0, i, j);
+            block_residual_node(g, J, f, x, r, 0, i, j);
         }
         __syncthreads();
-        const Geom &gc = F.g[q + 1];
-        BOpT<T> Jc{F.J[q + 1], F.plane[q + 1]};
+        const Geom gc = geom(q + 1);
+        const BOpT<T> Jc = jac(q + 1);
         const int cnodes = (gc.nr + 1) * (gc.nz + 1);
         for (int t = threadIdx.x; t < cnodes; t += nt) {
             int I = t / (gc.nz + 1), J_ = t % (gc.nz + 1);
-            restrict3_node(g, F.r[q], J.plane, gc, Jc.pl(kFe), Jc.plane, I, J_);
+            restrict3_node(g, r, J.plane, gc, Jc.pl(kFe), Jc.plane, I, J_);
         }
         __syncthreads();
     }
     {
         const int q = n - 1;
-        BOpT<T> J{F.J[q], F.plane[q]};
-        const T *f = (q == 0) ? F.f0 : J.pl(kFe);
-        block_coarse_solve_wg(F.g[q], J.plane, f, F.invT, F.x[q], rhs);
+        const BOpT<T> J = jac(q);
+        const T *f = (q == 0) ? f0 : J.pl(kFe);
+        block_coarse_solve_wg(geom(q), J.plane, f, invT, xof(q), rhs);
         __syncthreads();
     }
     for (int q = n - 2; q >= 0; --q) {
-        const Geom &g = F.g[q];
-        BOpT<T> J{F.J[q], F.plane[q]};
-        const T *f = (q == 0) ? F.f0 : J.pl(kFe);
-        T *x = F.x[q];
+        const Geom g = geom(q);
+        const BOpT<T> J = jac(q);
+        const T *f = (q == 0) ? f0 : J.pl(kFe);
+        T *x = xof(q);
+        const Geom gc = geom(q + 1);
+        const T *xc = xof(q + 1);
         const int nodes = (g.nr + 1) * (g.nz + 1);
         for (int t = threadIdx.x; t < nodes; t += nt) {
             int i = t / (g.nz + 1), j = t % (g.nz + 1);
-            if (j >= 1 && j < g.nz) prolong3_node(g, x, J.plane, F.g[q + 1], F.x[q + 1], F.plane[q + 1], i, j);
+            if (j >= 1 && j < g.nz) prolong3_node(g, x, J.plane, gc, xc, F.plane[q + 1], i, j);
         }
         __syncthreads();
         for (int s = 0; s < F.nu2; ++s)
