@@ -45,8 +45,8 @@ template <class T>
 void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s,
                        const Batch &bt = Batch());
 template <class T>
-void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, hipStream_t s,
-                           const Batch &bt = Batch());
+void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
+                           hipStream_t s, const Batch &bt = Batch());
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s, const Batch &bt = Batch());
@@ -73,6 +73,15 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
 void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
                        int64_t plane, double3 cw, double *partials, double *out, hipStream_t s,
                        const Batch &bt = Batch());
+// Gram-Schmidt pass: w -= sum_v h_sub[v] basis_v (if h_sub), then the
+// partial sums of the weighted (w, basis_v), v < nv, or of (w, w) when
+// self_norm; with out != nullptr a second launch adds them into out[].
+void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
+                     double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
+                     const Batch &bt = Batch());
+// dst = src / |.| from the norm partials of a self_norm pass; out[0] = |.|^2.
+void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
+                         double *out, hipStream_t s, const Batch &bt = Batch());
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                        const double *h, double sign, hipStream_t s, const Batch &bt = Batch());
 void launch_scale_by_norm(const Geom &g, const double *src, double *dst, int64_t plane, const double *nrm2,

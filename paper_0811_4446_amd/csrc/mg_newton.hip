@@ -269,7 +269,8 @@ __global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__re
 }
 
 // One full collective red-black sweep (colour 0, then colour 1) from xin to
-// xout (distinct buffers whose electrode rows hold zeros).  A workgroup owns
+// xout (distinct buffers whose electrode rows hold zeros); zin != 0 takes
+// xin as zero without reading it (first sweep from a zero guess).  A workgroup owns
 // a kSW x kSH tile (z by r); every thread first loads its node's Jacobian
 // row block into registers, so the tile's Jacobian is read once per sweep
 // in one batch.  The tile's colour-0 nodes and, from xin, the colour-0 nodes
@@ -281,7 +282,7 @@ constexpr int kSW = 32, kSH = 16;
 template <class T>
 __global__ __launch_bounds__(kSW * kSH) void k_block_rb_sweep(Geom g, BOpT<T> J, const T *__restrict__ f,
                                                               const T *__restrict__ xin, T *__restrict__ xout,
-                                                              Batch bt) {
+                                                              int zin, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     g = geom_off(g, bo_);
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(kSW * kSH) void k_block_rb_sweep(Geom g, BOpT<T> J,
         const int64_t q = at(g, ii, jj);
         const int64_t qnb[4] = {q - g.pitch, q + g.pitch, q - 1, q + 1};
         const bool has[4] = {ii > 0, ii < g.nr, true, true};
-        solve_row(Q, has, [&](int t, int c) { return xin[qnb[t] + c * plane]; }, oe, op, ov);
+        solve_row(Q, has, [&](int t, int c) { return zin ? T(0) : xin[qnb[t] + c * plane]; }, oe, op, ov);
         const int l = (ii - i0 + 1) * W + (jj - j0 + 1);
         lx[0][l] = oe;
         lx[1][l] = op;
@@ -350,8 +351,9 @@ __global__ __launch_bounds__(kSW * kSH) void k_block_rb_sweep(Geom g, BOpT<T> J,
     const bool fixed[4] = {false, false, j - 1 == 0, j + 1 == g.nz};
     const bool has[4] = {i > 0, i < g.nr, true, true};
     T oe, op, ov;
-    solve_row(R, has, [&](int t, int c) { return fixed[t] ? xin[pnb[t] + c * plane] : lx[c][lnb[t]]; }, oe, op,
-              ov);
+    solve_row(R, has,
+              [&](int t, int c) { return fixed[t] ? (zin ? T(0) : xin[pnb[t] + c * plane]) : lx[c][lnb[t]]; }, oe,
+              op, ov);
     xout[p] = oe;
     xout[p + plane] = op;
     xout[p + 2 * plane] = ov;
@@ -718,14 +720,13 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
         T *x = xof(q);
         T *r = rof(q);
         const int nodes = (g.nr + 1) * (g.nz + 1);
-        if (q > 0) {
-            for (int t = threadIdx.x; t < nodes; t += nt) {
-                int i = t / (g.nz + 1), j = t % (g.nz + 1);
-                int64_t p = at(g, i, j);
-                x[p] = x[p + J.plane] = x[p + 2 * J.plane] = T(0);
-            }
-            __syncthreads();
+        // every level's correction starts from zero (x is not read on entry)
+        for (int t = threadIdx.x; t < nodes; t += nt) {
+            int i = t / (g.nz + 1), j = t % (g.nz + 1);
+            int64_t p = at(g, i, j);
+            x[p] = x[p + J.plane] = x[p + 2 * J.plane] = T(0);
         }
+        __syncthreads();
         for (int s = 0; s < F.nu1; ++s)
             for (int col = 0; col < 2; ++col) {
                 for (int t = threadIdx.x; t < nodes; t += nt) {
@@ -816,6 +817,103 @@ __global__ __launch_bounds__(1024) void k_wdot_multi(Geom g, const double *__res
         for (int y = 0; y < (int)blockDim.y; ++y) s += sh[y][t];
         partials[(int64_t)blk * nv + t] = s;
     }
+}
+
+// One pass of classical Gram-Schmidt: optionally w -= sum_v h_sub[v]
+// basis_v at every unknown node, then the per-workgroup partial sums of the
+// weighted dot products of (the updated) w with basis_0..basis_{nv-1}, or
+// with w itself (self_norm).  The grid-wide sums are formed by a following
+// launch (k_sum_cols or k_scale_reduce) in a fixed order.
+__global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ w, const double *__restrict__ basis,
+                                                   int64_t vstride, int nv, int64_t plane, double3 cw,
+                                                   const double *__restrict__ h_sub, int self_norm,
+                                                   double *__restrict__ partials, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    w = boff(w, bo_);
+    basis = boff(basis, bo_);
+    h_sub = boff(h_sub, bo_);
+    partials = boff(partials, bo_);
+
+    const int j = blockIdx.x * kTX + threadIdx.x;
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    __shared__ double sh[kMaxTY][kMaxKrylov + 1];
+    const bool ok = i <= g.nr && j >= 1 && j < g.nz;
+    const int64_t p = ok ? at(g, i, j) : 0;
+    double wf[3] = {0.0, 0.0, 0.0};
+    if (ok) {
+        for (int f = 0; f < 3; ++f) {
+            const int64_t q = p + f * plane;
+            double acc = w[q];
+            if (h_sub) {
+                for (int v = 0; v < nv; ++v)
+                    if (h_sub[v] != 0.0) acc += -1.0 * h_sub[v] * basis[v * vstride + q];
+                w[q] = acc;
+            }
+            wf[f] = acc;
+        }
+    }
+    const double iv = ok ? 1.0 / (g.wr[i] * g.dzc[j]) : 0.0;
+    const double we = wf[0] * cw.x * cw.x * iv * iv;
+    const double wp = wf[1] * cw.y * cw.y * iv * iv;
+    const double wv = wf[2] * cw.z * cw.z * iv * iv;
+    const int nd = self_norm ? 1 : nv;
+    for (int v = 0; v < nd; ++v) {
+        double s = 0.0;
+        if (ok) {
+            if (self_norm) {
+                s = we * wf[0] + wp * wf[1] + wv * wf[2];
+            } else {
+                const double *b = basis + v * vstride;
+                s = we * b[p] + wp * b[p + plane] + wv * b[p + 2 * plane];
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
+    }
+    __syncthreads();
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const int t = threadIdx.y * kTX + threadIdx.x;
+    if (t < nd) {
+        double s = 0.0;
+        for (int y = 0; y < (int)blockDim.y; ++y) s += sh[y][t];
+        partials[(int64_t)blk * nd + t] = s;
+    }
+}
+
+// dst = src / sqrt(n2) with n2 the sum of the nblk norm partials (formed in
+// the same fixed order by every workgroup; workgroup 0 also stores it).
+__global__ void k_scale_reduce(Geom g, const double *__restrict__ src, double *__restrict__ dst, int64_t plane,
+                               const double *__restrict__ partials, int nblk, double *__restrict__ out, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    src = boff(src, bo_);
+    dst = boff(dst, bo_);
+    partials = boff(partials, bo_);
+    out = boff(out, bo_);
+
+    __shared__ double n2s;
+    if (threadIdx.y == 0) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kTX) a += partials[b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        if (threadIdx.x == 0) {
+            n2s = a;
+            if (blockIdx.x == 0 && blockIdx.y == 0) out[0] = a;
+        }
+    }
+    __syncthreads();
+    const int j = blockIdx.x * kTX + threadIdx.x;
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    const int64_t p = at(g, i, j);
+    const double s = 1.0 / sqrt(n2s);
+    const bool un = j >= 1 && j < g.nz;
+    for (int f = 0; f < 3; ++f) dst[p + f * plane] = un ? src[p + f * plane] * s : 0.0;
 }
 
 // out[c] = sum over blocks of partials[b*ncomp + c], fixed order (one
@@ -981,11 +1079,11 @@ void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int co
     k_block_rbgs<T><<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, f, x, colour, bt);
 }
 template <class T>
-void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, hipStream_t s,
-                           const Batch &bt) {
+void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
+                           hipStream_t s, const Batch &bt) {
     static_assert(2 * kSW + 2 * kSH <= kSW * kSH, "one ring task per thread");
     dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + kSH - 1) / kSH);
-    k_block_rb_sweep<T><<<gz(grid, bt), dim3(kSW, kSH), 0, s>>>(g, J, f, xin, xout, bt);
+    k_block_rb_sweep<T><<<gz(grid, bt), dim3(kSW, kSH), 0, s>>>(g, J, f, xin, xout, zin ? 1 : 0, bt);
 }
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
@@ -1032,6 +1130,22 @@ void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int6
     dim3 gr = grid2d(g);
     k_wdot_multi<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, partials, bt);
     k_sum_cols<<<dim3(nv, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nv, out, bt);
+}
+void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
+                     double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
+                     const Batch &bt) {
+    dim3 gr = grid2d(g);
+    k_cgs_pass<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, h_sub, self_norm ? 1 : 0,
+                                               partials, bt);
+    if (out) {
+        int nd = self_norm ? 1 : nv;
+        k_sum_cols<<<dim3(nd, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nd, out, bt);
+    }
+}
+void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
+                         double *out, hipStream_t s, const Batch &bt) {
+    dim3 gr = grid2d(g);
+    k_scale_reduce<<<gz(gr, bt), blk2d(g), 0, s>>>(g, src, dst, plane, partials, (int)(gr.x * gr.y), out, bt);
 }
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                        const double *h, double sign, hipStream_t s, const Batch &bt) {
@@ -1131,7 +1245,7 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
 #define MGF_INST(T)                                                                                          \
     template void launch_block_rbgs<T>(const Geom &, const BOpT<T> &, const T *, T *, int, hipStream_t,      \
                                        const Batch &);                                                       \
-    template void launch_block_rb_sweep<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *,         \
+    template void launch_block_rb_sweep<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
                                            hipStream_t, const Batch &);                                      \
     template void launch_block_residual<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
                                            hipStream_t, const Batch &);                                      \

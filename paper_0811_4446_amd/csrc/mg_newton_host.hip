@@ -47,22 +47,25 @@ double3 field_weights(const mg_physics *ph) {
 }
 
 // nu collective red-black sweeps on level l: pairs of fused sweeps x -> x2 ->
-// x, and two half-sweeps for an odd last one.
+// x, and two half-sweeps for an odd last one.  x_zero: x is zero on entry
+// (the first fused sweep then does not read it).
 template <class T>
-void block_smooth(mg_ctx *c, int l, const BOpT<T> &J, const T *f, T *x, int nu, hipStream_t s) {
+void block_smooth(mg_ctx *c, int l, const BOpT<T> &J, const T *f, T *x, int nu, bool x_zero, hipStream_t s) {
     const Geom &g = c->lev[l].g;
     int k = 0;
     if (c->nw.rb_fused) {
         T *x2 = Prec<T>::x2(c, l);
         for (; k + 2 <= nu; k += 2) {
-            launch_block_rb_sweep<T>(g, J, f, x, x2, s, c->bt);
-            launch_block_rb_sweep<T>(g, J, f, x2, x, s, c->bt);
+            launch_block_rb_sweep<T>(g, J, f, x, x2, x_zero && k == 0, s, c->bt);
+            launch_block_rb_sweep<T>(g, J, f, x2, x, false, s, c->bt);
         }
     }
     for (; k < nu; ++k)
         for (int col = 0; col < 2; ++col) launch_block_rbgs<T>(g, J, f, x, col, s, c->bt);
 }
 
+// One block V(nu1, nu2) cycle for B x = f on level l from a zero initial
+// guess; x is not read on entry (its electrode rows hold zeros).
 template <class T>
 void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     const Level &L = c->lev[l];
@@ -89,7 +92,10 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         launch_block_coarse_solve<T>(L.g, J, f, Prec<T>::inv(c), x, s, c->bt);
         return;
     }
-    block_smooth<T>(c, l, J, f, x, c->desc.nu1, s);
+    // without a fused first sweep the zero guess has to be written
+    const bool zero_sweep = c->nw.rb_fused && c->desc.nu1 >= 2;
+    if (!zero_sweep) launch_fill(x, 3 * plane_of(L), T(0), s, c->bt);
+    block_smooth<T>(c, l, J, f, x, c->desc.nu1, zero_sweep, s);
     T *r = Prec<T>::r(c, l);
     launch_block_residual<T>(L.g, J, f, x, r, false, s, c->bt);
     const Level &C = c->lev[l + 1];
@@ -97,10 +103,9 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     T *fc = Jc.pl(kFe);
     launch_restrict3<T>(L.g, r, plane_of(L), C.g, fc, plane_of(C), s, c->bt);
     T *xc = Prec<T>::x(c, l + 1);
-    launch_fill(xc, 3 * plane_of(C), T(0), s, c->bt);
     block_vcycle<T>(c, l + 1, fc, xc, s);
     launch_prolong3<T>(L.g, x, plane_of(L), C.g, xc, plane_of(C), s, c->bt);
-    block_smooth<T>(c, l, J, f, x, c->desc.nu2, s);
+    block_smooth<T>(c, l, J, f, x, c->desc.nu2, false, s);
 }
 
 // Assemble the Jacobian on every level: level 0 at the current state with
@@ -201,20 +206,17 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
         // preconditioner in FP32: z_k = M32 v_k (the Krylov space stays FP64)
         float *x32 = W.lev[0].x32;
         launch_planes_to_f32(vk, W.f32, vs, s, c->bt);
-        launch_fill(x32, vs, 0.0f, s, c->bt);
         block_vcycle<float>(c, 0, W.f32, x32, s);
         launch_planes_to_f64(x32, zk, vs, s, c->bt);
     } else {
-        launch_fill(zk, vs, 0.0, s, c->bt);
         block_vcycle<double>(c, 0, vk, zk, s);
     }
     launch_block_residual<double>(g, J, nullptr, zk, W.w, true, s, c->bt);  // w = J z_k
-    launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev, s, c->bt);
-    launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev, -1.0, s, c->bt);
-    launch_wdot_multi(g, W.w, W.V, vs, k + 1, p0, cw, W.partials, dev + (m + 1), s, c->bt);
-    launch_axpy_multi(g, W.w, W.V, vs, k + 1, p0, dev + (m + 1), -1.0, s, c->bt);
-    launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev + 2 * m + 2, s, c->bt);
-    launch_scale_by_norm(g, W.w, vk1, p0, dev + 2 * m + 2, s, c->bt);
+    // classical Gram-Schmidt twice: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2, |w|^2
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, W.partials, dev, s, c->bt);
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev, false, W.partials, dev + (m + 1), s, c->bt);
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev + (m + 1), true, W.partials, nullptr, s, c->bt);
+    launch_scale_reduce(g, W.w, vk1, p0, W.partials, dev + 2 * m + 2, s, c->bt);
     readback(c, c->bt.n > 1 ? c->bpinned : c->pinned, dev, 2 * m + 3, s);
 }
 
@@ -271,7 +273,7 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
     Arnoldi A;
     launch_fill(W.delta, vs, 0.0, s);
     // r0 = b
-    launch_wdot_multi(g, b, b, vs, 1, p0, cw, W.partials, dev, s);
+    launch_cgs_pass(g, const_cast<double *>(b), b, vs, 1, p0, cw, nullptr, true, W.partials, dev, s);
     HIP_OK(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     double beta0 = sqrt(host[0]);
@@ -310,7 +312,7 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
         launch_axpy_multi(g, W.delta, W.Z, vs, k, p0, dev + 3 * m + 8, 1.0, s);
         // true residual for the restart / final check
         launch_block_residual<double>(g, J, b, W.delta, W.w, false, s);
-        launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev, s);
+        launch_cgs_pass(g, W.w, W.w, vs, 1, p0, cw, nullptr, true, W.partials, dev, s);
         HIP_OK(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         beta = sqrt(host[0]);
@@ -587,7 +589,7 @@ int fgmres_batch(mg_ctx *c, double3 cw, double rtol, int maxit, const std::vecto
     int e = set_active(c, live);
     if (e) return e;
     launch_fill(W.delta, vs, 0.0, s, c->bt);
-    launch_wdot_multi(g, b, b, vs, 1, p0, cw, W.partials, dev, s, c->bt);
+    launch_cgs_pass(g, const_cast<double *>(b), b, vs, 1, p0, cw, nullptr, true, W.partials, dev, s, c->bt);
     readback(c, host, dev, 1, s);
     HIP_OK(hipStreamSynchronize(s));
     for (int p = 0; p < n; ++p) {
@@ -636,7 +638,7 @@ int fgmres_batch(mg_ctx *c, double3 cw, double rtol, int maxit, const std::vecto
         if ((e = upload_per_problem(c, Y, kmax, dev + 3 * m + 8))) return e;
         launch_axpy_multi(g, W.delta, W.Z, vs, kmax, p0, dev + 3 * m + 8, 1.0, s, c->bt);
         launch_block_residual<double>(g, J, b, W.delta, W.w, false, s, c->bt);
-        launch_wdot_multi(g, W.w, W.w, vs, 1, p0, cw, W.partials, dev, s, c->bt);
+        launch_cgs_pass(g, W.w, W.w, vs, 1, p0, cw, nullptr, true, W.partials, dev, s, c->bt);
         readback(c, host, dev, 1, s);
         HIP_OK(hipStreamSynchronize(s));
         std::vector<int> restart(n, 0);
@@ -950,7 +952,8 @@ int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double 
     int64_t p0 = plane_of(L0);
     BOp J = bop(c, 0);
     launch_newton_assemble(L0.g, J, st->V, st->ne, st->np, st->ne, st->np, st->Se, st->Sp, np_, true, s);
-    launch_wdot_multi(L0.g, J.pl(kFe), J.pl(kFe), 3 * p0, 1, p0, field_weights(ph), c->nw.partials, c->nw.dev, s);
+    launch_cgs_pass(L0.g, J.pl(kFe), J.pl(kFe), 3 * p0, 1, p0, field_weights(ph), nullptr, true, c->nw.partials,
+                    c->nw.dev, s);
     HIP_OK(hipMemcpyAsync(c->pinned, c->nw.dev, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     *out = sqrt(c->pinned[0]);
@@ -964,7 +967,7 @@ int time_block_smoother(mg_ctx *c, int reps, bool fused, double *avg_ms) {
     double *x = c->nw.lev[0].x, *x2 = c->nw.lev[0].x2;
     auto one = [&](int r) {
         if (fused)
-            launch_block_rb_sweep<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, c->stream);
+            launch_block_rb_sweep<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, false, c->stream);
         else
             launch_block_rbgs<double>(L0.g, J, J.pl(kFe), x, r & 1, c->stream);
     };
