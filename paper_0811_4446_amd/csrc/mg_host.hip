@@ -398,10 +398,11 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
 
 void mg_destroy(mg_ctx *ctx) {
     if (!ctx) return;
+    // work still queued (a speculative Arnoldi step) may copy into pinned memory
+    (void)hipStreamSynchronize(ctx->stream);
     if (ctx->active_host) (void)hipHostFree(ctx->active_host);
     if (ctx->bpinned) (void)hipHostFree(ctx->bpinned);
-    for (int t = 0; t < 64; ++t)
-        if (ctx->nw.exec[t]) (void)hipGraphExecDestroy(ctx->nw.exec[t]);
+    drop_graphs(ctx);
     if (ctx->nw.cap) (void)hipStreamDestroy(ctx->nw.cap);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;

@@ -195,6 +195,8 @@ struct NewtonWork {
     double cw_cap[3] = {0, 0, 0};
     bool use_graphs = true;
     bool rb_fused = true;      // full red-black sweeps in one launch (else two half-sweeps)
+    hipEvent_t ev[2] = {nullptr, nullptr};  // readback of Arnoldi steps k (even / odd)
+    int last_its = 0;          // FGMRES iterations of the previous solve
     bool fuse = true;  // single-workgroup coarse sub-cycle
     int fuse_max = 16; // levels with nr, nz <= fuse_max run in it
 };

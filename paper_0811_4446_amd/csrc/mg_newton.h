@@ -5,6 +5,10 @@
 namespace mgf {
 
 constexpr int kMaxKrylov = 40;
+// pinned host doubles per Arnoldi readback slot (2 m + 3 used); the context's
+// 512 pinned doubles hold two slots, the least-squares solution and scalars
+constexpr int kSlot = 128;
+static_assert(2 * kSlot + 2 * kMaxKrylov + 16 <= 512, "pinned layout");
 constexpr int kBPlanes = 30;
 constexpr int kEE = 0, kEV = 5, kPP = 10, kPV = 15, kVV = 20, kVe = 25, kVp = 26, kFe = 27, kFp = 28, kFV = 29;
 
@@ -44,9 +48,11 @@ void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const 
 template <class T>
 void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s,
                        const Batch &bt = Batch());
+// One full red-black sweep xin -> xout; zin: input zero; gc/xc/pc: input is
+// xin plus the prolongation of the coarse correction xc (level gc, plane pc).
 template <class T>
 void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
-                           hipStream_t s, const Batch &bt = Batch());
+                           const Geom *gc, const T *xc, int64_t pc, hipStream_t s, const Batch &bt = Batch());
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s, const Batch &bt = Batch());

@@ -193,6 +193,36 @@ inline __device__ void nb_sum(const Geom &g, const BOpT<T> &J, const T *x, int64
     nb_sum_of(J, p, has, [&](int t, int c) { return x[nbp[t] + c * plane]; }, se, sp, sv);
 }
 
+// Bilinear prolongation (z-distance weights) of one coarse field c at fine
+// node (i, j) of an unknown row.
+template <class T>
+inline __device__ T prolong_val(const Geom &gf, const Geom &gc, const T *c, int i, int j) {
+    int I0 = i >> 1, I1 = (i + 1) >> 1;
+    T v0, v1;
+    if ((j & 1) == 0) {
+        v0 = c[at(gc, I0, j >> 1)];
+        v1 = c[at(gc, I1, j >> 1)];
+    } else {
+        int J_ = j >> 1;
+        T wl = gf.wl[J_], wu = T(1) - wl;
+        v0 = wl * c[at(gc, I0, J_)] + wu * c[at(gc, I0, J_ + 1)];
+        v1 = wl * c[at(gc, I1, J_)] + wu * c[at(gc, I1, J_ + 1)];
+    }
+    return (i & 1) ? T(0.5) * (v0 + v1) : v0;
+}
+
+template <class T>
+inline __device__ void prolong3_node(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc,
+                                     int64_t pc, int i, int j) {
+    int64_t p = at(gf, i, j);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        T v = xf[p + f * pf];
+        v += prolong_val(gf, gc, xc + f * pc, i, j);
+        xf[p + f * pf] = v;
+    }
+}
+
 // The Jacobian row block and right-hand side of one node, held in registers.
 template <class T>
 struct NodeRow {
@@ -268,21 +298,28 @@ __global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__re
     block_gs_node(g, J, f, x, i, j);
 }
 
-// One full collective red-black sweep (colour 0, then colour 1) from xin to
-// xout (distinct buffers whose electrode rows hold zeros); zin != 0 takes
-// xin as zero without reading it (first sweep from a zero guess).  A workgroup owns
-// a kSW x kSH tile (z by r); every thread first loads its node's Jacobian
-// row block into registers, so the tile's Jacobian is read once per sweep
-// in one batch.  The tile's colour-0 nodes and, from xin, the colour-0 nodes
-// of the ring around the tile (owned by the neighbouring workgroups) are
-// updated into LDS; the colour-1 update then reads its neighbours from LDS.
-// Every value equals what the two half-sweeps compute; the ring costs
-// (kSW + kSH) / (kSW kSH / 2) extra colour-0 updates.
-constexpr int kSW = 32, kSH = 16;
+// One full collective red-black sweep (colour 0, then colour 1) from the
+// input to xout (xin and xout distinct, electrode rows zero).  The input is
+// xin, or zero (zin != 0, xin not read), or xin plus the bilinear
+// prolongation of the coarse correction xc (xc != nullptr: the coarse-grid
+// correction applied on the fly, never stored).
+//
+// A workgroup owns a kSW x kSH tile (z by r) and kSR more thread rows for
+// the ring.  Phase 0 stages the input over the tile and a 2-node ring in LDS
+// while every thread loads its node's Jacobian row block into registers
+// (tile threads: their own node; ring threads: one colour-0 node of the
+// 1-node ring, owned by a neighbouring workgroup).  Phase 1 updates the
+// colour-0 nodes of tile and ring into LDS, phase 2 the tile's colour-1
+// nodes.  Every value equals what two half-sweep launches compute, with one
+// launch and one pass over the Jacobian; the ring costs (kSW + kSH) /
+// (kSW kSH / 2) extra colour-0 updates.
+constexpr int kSW = 32, kSH = 16, kSR = 3;
+static_assert(kSR * kSW == 2 * kSW + 2 * kSH, "one ring node per ring thread");
 template <class T>
-__global__ __launch_bounds__(kSW * kSH) void k_block_rb_sweep(Geom g, BOpT<T> J, const T *__restrict__ f,
-                                                              const T *__restrict__ xin, T *__restrict__ xout,
-                                                              int zin, Batch bt) {
+__global__ __launch_bounds__(kSW *(kSH + kSR)) void k_block_rb_sweep(Geom g, BOpT<T> J, const T *__restrict__ f,
+                                                                     const T *__restrict__ xin, T *__restrict__ xout,
+                                                                     int zin, Geom gc, const T *__restrict__ xc,
+                                                                     int64_t pc, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     g = geom_off(g, bo_);
@@ -290,70 +327,86 @@ __global__ __launch_bounds__(kSW * kSH) void k_block_rb_sweep(Geom g, BOpT<T> J,
     f = boff(f, bo_);
     xin = boff(xin, bo_);
     xout = boff(xout, bo_);
+    if (xc) {
+        gc = geom_off(gc, bo_);
+        xc = boff(xc, bo_);
+    }
 
-    constexpr int W = kSW + 2;
+    constexpr int W = kSW + 2, W2 = kSW + 4;
     __shared__ T lx[3][(kSH + 2) * W];
+    __shared__ T lin[3][(kSH + 4) * W2];
     const int i0 = blockIdx.y * kSH, j0 = blockIdx.x * kSW;
     const int64_t plane = J.plane;
     const int ti = threadIdx.y, tj = threadIdx.x;
-    const int i = i0 + ti, j = j0 + tj;
-    const bool mine = i <= g.nr && j >= 1 && j < g.nz;
-    const int64_t p = at(g, i, j);
-    NodeRow<T> R;
-    if (mine) load_row(J, f, p, R);
-    // colour-0 update of node (ii, jj) from xin into LDS
-    auto red = [&](int ii, int jj, const NodeRow<T> &Q, T &oe, T &op, T &ov) {
+    const int tid = ti * kSW + tj;
+    // phase 0: input over the window rows i0-2 .. i0+kSH+1, columns j0-2 .. j0+kSW+1
+    for (int t = tid; t < (kSH + 4) * W2; t += kSW * (kSH + kSR)) {
+        const int ii = i0 - 2 + t / W2, jj = j0 - 2 + t % W2;
+        if (ii < 0 || ii > g.nr || jj < 0 || jj > g.nz) continue;
         const int64_t q = at(g, ii, jj);
-        const int64_t qnb[4] = {q - g.pitch, q + g.pitch, q - 1, q + 1};
-        const bool has[4] = {ii > 0, ii < g.nr, true, true};
-        solve_row(Q, has, [&](int t, int c) { return zin ? T(0) : xin[qnb[t] + c * plane]; }, oe, op, ov);
-        const int l = (ii - i0 + 1) * W + (jj - j0 + 1);
+        const bool un = jj >= 1 && jj < g.nz;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T v = zin ? T(0) : xin[q + c * plane];
+            if (xc && un) v += prolong_val(g, gc, xc + c * pc, ii, jj);
+            lin[c][t] = v;
+        }
+    }
+    // the node this thread updates in phase 1 or 2
+    int ni, nj;
+    if (ti < kSH) {
+        ni = i0 + ti;
+        nj = j0 + tj;
+    } else {
+        const int k = (ti - kSH) * kSW + tj;
+        if (k < kSW) {
+            ni = i0 - 1;
+            nj = j0 + k;
+        } else if (k < 2 * kSW) {
+            ni = i0 + kSH;
+            nj = j0 + k - kSW;
+        } else if (k < 2 * kSW + kSH) {
+            ni = i0 + k - 2 * kSW;
+            nj = j0 - 1;
+        } else {
+            ni = i0 + k - 2 * kSW - kSH;
+            nj = j0 + kSW;
+        }
+    }
+    const bool valid = ni >= 0 && ni <= g.nr && nj >= 1 && nj < g.nz;
+    const bool red = ((ni + nj) & 1) == 0;
+    const bool tile = ti < kSH;
+    const int64_t p = at(g, ni, nj);
+    NodeRow<T> R;
+    if (valid && (tile || red)) load_row(J, f, p, R);
+    __syncthreads();
+    auto in_at = [&](int ii, int jj, int c) { return lin[c][(ii - i0 + 2) * W2 + (jj - j0 + 2)]; };
+    const bool has[4] = {ni > 0, ni < g.nr, true, true};
+    const int dni[4] = {-1, 1, 0, 0}, dnj[4] = {0, 0, -1, 1};
+    if (valid && red) {
+        T oe, op, ov;
+        solve_row(R, has, [&](int t, int c) { return in_at(ni + dni[t], nj + dnj[t], c); }, oe, op, ov);
+        const int l = (ni - i0 + 1) * W + (nj - j0 + 1);
         lx[0][l] = oe;
         lx[1][l] = op;
         lx[2][l] = ov;
-    };
-    if (mine && ((i + j) & 1) == 0) {
-        T oe, op, ov;
-        red(i, j, R, oe, op, ov);
-        xout[p] = oe;
-        xout[p + plane] = op;
-        xout[p + 2 * plane] = ov;
-    }
-    {
-        const int k = ti * kSW + tj;
-        int ri = -1, rj = -1;
-        if (k < kSW) {
-            ri = i0 - 1;
-            rj = j0 + k;
-        } else if (k < 2 * kSW) {
-            ri = i0 + kSH;
-            rj = j0 + k - kSW;
-        } else if (k < 2 * kSW + kSH) {
-            ri = i0 + k - 2 * kSW;
-            rj = j0 - 1;
-        } else if (k < 2 * kSW + 2 * kSH) {
-            ri = i0 + k - 2 * kSW - kSH;
-            rj = j0 + kSW;
-        }
-        if (ri >= 0 && ri <= g.nr && rj >= 1 && rj < g.nz && ((ri + rj) & 1) == 0) {
-            NodeRow<T> Q;
-            load_row(J, f, at(g, ri, rj), Q);
-            T oe, op, ov;
-            red(ri, rj, Q, oe, op, ov);
+        if (tile) {
+            xout[p] = oe;
+            xout[p + plane] = op;
+            xout[p + 2 * plane] = ov;
         }
     }
     __syncthreads();
-    if (!mine || ((i + j) & 1) != 1) return;
-    const int l = (ti + 1) * W + (tj + 1);
-    const int lnb[4] = {l - W, l + W, l - 1, l + 1};
-    const int64_t pnb[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
-    // electrode neighbours (j - 1 == 0 or j + 1 == nz) are not updated: read xin
-    const bool fixed[4] = {false, false, j - 1 == 0, j + 1 == g.nz};
-    const bool has[4] = {i > 0, i < g.nr, true, true};
+    if (!tile || !valid || red) return;
+    // electrode neighbours (j - 1 == 0 or j + 1 == nz) are not updated: input value
+    const bool fixed[4] = {false, false, nj - 1 == 0, nj + 1 == g.nz};
     T oe, op, ov;
     solve_row(R, has,
-              [&](int t, int c) { return fixed[t] ? (zin ? T(0) : xin[pnb[t] + c * plane]) : lx[c][lnb[t]]; }, oe,
-              op, ov);
+              [&](int t, int c) {
+                  const int ii = ni + dni[t], jj = nj + dnj[t];
+                  return fixed[t] ? in_at(ii, jj, c) : lx[c][(ii - i0 + 1) * W + (jj - j0 + 1)];
+              },
+              oe, op, ov);
     xout[p] = oe;
     xout[p + plane] = op;
     xout[p + 2 * plane] = ov;
@@ -448,27 +501,6 @@ __global__ void k_restrict3(Geom gf, const T *__restrict__ rf, int64_t pf, Geom 
 }
 
 // Bilinear prolongation of the coarse correction, added at fine node (i, j).
-template <class T>
-inline __device__ void prolong3_node(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc,
-                                     int64_t pc, int i, int j) {
-    int I0 = i >> 1, I1 = (i + 1) >> 1;
-    int64_t p = at(gf, i, j);
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        const T *c = xc + f * pc;
-        T v0, v1;
-        if ((j & 1) == 0) {
-            v0 = c[at(gc, I0, j >> 1)];
-            v1 = c[at(gc, I1, j >> 1)];
-        } else {
-            int J_ = j >> 1;
-            T wl = gf.wl[J_], wu = T(1) - wl;
-            v0 = wl * c[at(gc, I0, J_)] + wu * c[at(gc, I0, J_ + 1)];
-            v1 = wl * c[at(gc, I1, J_)] + wu * c[at(gc, I1, J_ + 1)];
-        }
-        xf[p + f * pf] += (i & 1) ? T(0.5) * (v0 + v1) : v0;
-    }
-}
 
 template <class T>
 __global__ void k_prolong3(Geom gf, T *__restrict__ xf, int64_t pf, Geom gc, const T *__restrict__ xc,
@@ -1080,10 +1112,10 @@ void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int co
 }
 template <class T>
 void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
-                           hipStream_t s, const Batch &bt) {
-    static_assert(2 * kSW + 2 * kSH <= kSW * kSH, "one ring task per thread");
+                           const Geom *gc, const T *xc, int64_t pc, hipStream_t s, const Batch &bt) {
     dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + kSH - 1) / kSH);
-    k_block_rb_sweep<T><<<gz(grid, bt), dim3(kSW, kSH), 0, s>>>(g, J, f, xin, xout, zin ? 1 : 0, bt);
+    k_block_rb_sweep<T><<<gz(grid, bt), dim3(kSW, kSH + kSR), 0, s>>>(g, J, f, xin, xout, zin ? 1 : 0,
+                                                                       gc ? *gc : g, xc, pc, bt);
 }
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
@@ -1246,7 +1278,7 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
     template void launch_block_rbgs<T>(const Geom &, const BOpT<T> &, const T *, T *, int, hipStream_t,      \
                                        const Batch &);                                                       \
     template void launch_block_rb_sweep<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
-                                           hipStream_t, const Batch &);                                      \
+                                           const Geom *, const T *, int64_t, hipStream_t, const Batch &);     \
     template void launch_block_residual<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
                                            hipStream_t, const Batch &);                                      \
     template void launch_restrict3<T>(const Geom &, const T *, int64_t, const Geom &, T *, int64_t,          \

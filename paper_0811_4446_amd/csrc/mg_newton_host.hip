@@ -48,16 +48,27 @@ double3 field_weights(const mg_physics *ph) {
 
 // nu collective red-black sweeps on level l: pairs of fused sweeps x -> x2 ->
 // x, and two half-sweeps for an odd last one.  x_zero: x is zero on entry
-// (the first fused sweep then does not read it).
+// (the first fused sweep then does not read it).  xc (level l+1): the coarse
+// correction still to be prolonged and added to x, which the first fused
+// sweep does on the fly; the caller guarantees a fused sweep when x_zero or
+// xc is set (fused_ok).
 template <class T>
-void block_smooth(mg_ctx *c, int l, const BOpT<T> &J, const T *f, T *x, int nu, bool x_zero, hipStream_t s) {
+bool fused_ok(mg_ctx *c, int nu) { return c->nw.rb_fused && nu >= 2; }
+
+template <class T>
+void block_smooth(mg_ctx *c, int l, const BOpT<T> &J, const T *f, T *x, int nu, bool x_zero, const T *xc,
+                  hipStream_t s) {
     const Geom &g = c->lev[l].g;
     int k = 0;
-    if (c->nw.rb_fused) {
+    if (fused_ok<T>(c, nu)) {
         T *x2 = Prec<T>::x2(c, l);
+        const Geom *gc = xc ? &c->lev[l + 1].g : nullptr;
+        const int64_t pc = xc ? plane_of(c->lev[l + 1]) : 0;
         for (; k + 2 <= nu; k += 2) {
-            launch_block_rb_sweep<T>(g, J, f, x, x2, x_zero && k == 0, s, c->bt);
-            launch_block_rb_sweep<T>(g, J, f, x2, x, false, s, c->bt);
+            const bool first = k == 0;
+            launch_block_rb_sweep<T>(g, J, f, x, x2, x_zero && first, first ? gc : nullptr, first ? xc : nullptr,
+                                     pc, s, c->bt);
+            launch_block_rb_sweep<T>(g, J, f, x2, x, false, nullptr, nullptr, 0, s, c->bt);
         }
     }
     for (; k < nu; ++k)
@@ -93,9 +104,9 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         return;
     }
     // without a fused first sweep the zero guess has to be written
-    const bool zero_sweep = c->nw.rb_fused && c->desc.nu1 >= 2;
+    const bool zero_sweep = fused_ok<T>(c, c->desc.nu1);
     if (!zero_sweep) launch_fill(x, 3 * plane_of(L), T(0), s, c->bt);
-    block_smooth<T>(c, l, J, f, x, c->desc.nu1, zero_sweep, s);
+    block_smooth<T>(c, l, J, f, x, c->desc.nu1, zero_sweep, nullptr, s);
     T *r = Prec<T>::r(c, l);
     launch_block_residual<T>(L.g, J, f, x, r, false, s, c->bt);
     const Level &C = c->lev[l + 1];
@@ -104,8 +115,14 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     launch_restrict3<T>(L.g, r, plane_of(L), C.g, fc, plane_of(C), s, c->bt);
     T *xc = Prec<T>::x(c, l + 1);
     block_vcycle<T>(c, l + 1, fc, xc, s);
-    launch_prolong3<T>(L.g, x, plane_of(L), C.g, xc, plane_of(C), s, c->bt);
-    block_smooth<T>(c, l, J, f, x, c->desc.nu2, false, s);
+    // the coarse-grid correction: added by the first post-smoothing sweep, or
+    // by its own launch
+    if (fused_ok<T>(c, c->desc.nu2)) {
+        block_smooth<T>(c, l, J, f, x, c->desc.nu2, false, xc, s);
+    } else {
+        launch_prolong3<T>(L.g, x, plane_of(L), C.g, xc, plane_of(C), s, c->bt);
+        block_smooth<T>(c, l, J, f, x, c->desc.nu2, false, nullptr, s);
+    }
 }
 
 // Assemble the Jacobian on every level: level 0 at the current state with
@@ -217,7 +234,24 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev, false, W.partials, dev + (m + 1), s, c->bt);
     launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev + (m + 1), true, W.partials, nullptr, s, c->bt);
     launch_scale_reduce(g, W.w, vk1, p0, W.partials, dev + 2 * m + 2, s, c->bt);
-    readback(c, c->bt.n > 1 ? c->bpinned : c->pinned, dev, 2 * m + 3, s);
+    // single problem: alternate between two pinned slots, so that step k+1
+    // can run while the host reads step k
+    readback(c, c->bt.n > 1 ? c->bpinned : c->pinned + kSlot * (k & 1), dev, 2 * m + 3, s);
+}
+
+int run_arnoldi(mg_ctx *c, int k, double3 cw);
+
+// Launch Arnoldi step k (run_arnoldi) and record the event that marks its
+// readback.
+int launch_step(mg_ctx *c, int k, double3 cw) {
+    NewtonWork &W = c->nw;
+    if (!W.ev[0]) {
+        HIP_OK(hipEventCreateWithFlags(&W.ev[0], hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&W.ev[1], hipEventDisableTiming));
+    }
+    if (int e = run_arnoldi(c, k, cw)) return e;
+    HIP_OK(hipEventRecord(W.ev[k & 1], c->stream));
+    return MG_OK;
 }
 
 // Run Arnoldi step k on the context stream, from a captured graph when
@@ -258,6 +292,11 @@ int run_arnoldi(mg_ctx *c, int k, double3 cw) {
 
 // Solve J delta = b (b = the Newton right-hand side planes of level 0) to
 // weighted relative residual rtol.  Returns the iteration count in *its.
+// Step k+1 is launched before the host has read step k when the residual
+// estimates predict that step k will not converge (or, for k = 0, when the
+// previous solve needed more than one step): the GPU then never waits for
+// the host's Givens update, at the price of a discarded step when the
+// prediction fails.
 int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, double *relres) {
     hipStream_t s = c->stream;
     NewtonWork &W = c->nw;
@@ -269,14 +308,14 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
     double3 cw = field_weights(ph);
     double *dev = W.dev;  // [0..m] dots, [m+1..2m+1] second pass, [2m+2] norm^2, y at [3m+8..]
     const int m = W.m;
-    double *host = c->pinned;
+    double *ybuf = c->pinned + 2 * kSlot, *sbuf = c->pinned + 2 * kSlot + kMaxKrylov + 8;
     Arnoldi A;
     launch_fill(W.delta, vs, 0.0, s);
     // r0 = b
     launch_cgs_pass(g, const_cast<double *>(b), b, vs, 1, p0, cw, nullptr, true, W.partials, dev, s);
-    HIP_OK(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(sbuf, dev, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    double beta0 = sqrt(host[0]);
+    double beta0 = sqrt(sbuf[0]);
     *its = 0;
     *relres = 0.0;
     if (!(beta0 > 0)) {
@@ -286,37 +325,62 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
     launch_scale_by_norm(g, b, W.V, p0, dev, s);
     double beta = beta0;
     int total = 0;
+    const int prev = W.last_its;
     while (true) {
         A.start(beta);
         int k = 0;
-        double est = beta;
+        double est = beta, est_prev = beta;
+        bool next_launched = false;
+        if (int e = launch_step(c, 0, cw)) return e;
         for (; k < m && total < maxit; ++k) {
-            int e = run_arnoldi(c, k, cw);
-            if (e) return e;
-            HIP_OK(hipStreamSynchronize(s));
+            // speculative launch of step k+1
+            bool more = k + 1 < m && total + 1 < maxit;
+            if (more) {
+                bool spec;
+                if (k == 0)
+                    spec = prev != 1;
+                else {
+                    double pred = est * (est / est_prev);
+                    spec = pred > 1.5 * rtol * beta0;
+                }
+                next_launched = spec;
+                if (spec)
+                    if (int e = launch_step(c, k + 1, cw)) return e;
+            } else {
+                next_launched = false;
+            }
+            HIP_OK(hipEventSynchronize(W.ev[k & 1]));
+            const double *host = c->pinned + kSlot * (k & 1);
             for (int i = 0; i <= k; ++i) A.H[i][k] = host[i] + host[m + 1 + i];
             A.H[k + 1][k] = sqrt(host[2 * m + 2]);
             ++total;
             c->vcycles++;
+            est_prev = est;
             est = A.add(k);
-            if (!isfinite(est)) return fail(MG_ENONFINITE, "FGMRES breakdown (non-finite)");
+            if (!isfinite(est)) {
+                HIP_OK(hipStreamSynchronize(s));
+                return fail(MG_ENONFINITE, "FGMRES breakdown (non-finite)");
+            }
             if (est <= rtol * beta0 || A.H[k][k] == 0.0) {
                 ++k;
                 break;
             }
+            if (more && !next_launched)
+                if (int e = launch_step(c, k + 1, cw)) return e;
         }
         double y[kMaxKrylov];
         A.solve(k, y);
-        for (int i = 0; i < k; ++i) host[i] = y[i];
-        HIP_OK(hipMemcpyAsync(dev + 3 * m + 8, host, k * sizeof(double), hipMemcpyHostToDevice, s));
+        for (int i = 0; i < k; ++i) ybuf[i] = y[i];
+        HIP_OK(hipMemcpyAsync(dev + 3 * m + 8, ybuf, k * sizeof(double), hipMemcpyHostToDevice, s));
         launch_axpy_multi(g, W.delta, W.Z, vs, k, p0, dev + 3 * m + 8, 1.0, s);
         // true residual for the restart / final check
         launch_block_residual<double>(g, J, b, W.delta, W.w, false, s);
         launch_cgs_pass(g, W.w, W.w, vs, 1, p0, cw, nullptr, true, W.partials, dev, s);
-        HIP_OK(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(sbuf, dev, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        beta = sqrt(host[0]);
+        beta = sqrt(sbuf[0]);
         *its = total;
+        W.last_its = total;
         *relres = beta / beta0;
         if (!isfinite(beta)) return fail(MG_ENONFINITE, "FGMRES residual is not finite");
         if (beta <= rtol * beta0 * 1.0000001 || est <= rtol * beta0) return MG_OK;
@@ -934,10 +998,15 @@ void drop_graphs(mg_ctx *c) {
             (void)hipGraphExecDestroy(c->nw.exec[t]);
             c->nw.exec[t] = nullptr;
         }
+    for (int t = 0; t < 2; ++t)
+        if (c->nw.ev[t]) {
+            (void)hipEventDestroy(c->nw.ev[t]);
+            c->nw.ev[t] = nullptr;
+        }
 }
 
-// Weighted norm of the steady residual F(u) (dt = infinity) at the state st:
-// the quantity the fallback test of the warm start compares.
+// Weighted norm of the steady residual F(u) (dt = infinity) at the state st
+// (a diagnostic of how far a state is from steady).
 int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double *out) {
     if (c->nw.m <= 0) return fail(MG_EINVAL, "no Newton workspace (krylov_m = 0)");
     hipStream_t s = c->stream;
@@ -967,7 +1036,8 @@ int time_block_smoother(mg_ctx *c, int reps, bool fused, double *avg_ms) {
     double *x = c->nw.lev[0].x, *x2 = c->nw.lev[0].x2;
     auto one = [&](int r) {
         if (fused)
-            launch_block_rb_sweep<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, false, c->stream);
+            launch_block_rb_sweep<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, false, nullptr,
+                                          nullptr, 0, c->stream);
         else
             launch_block_rbgs<double>(L0.g, J, J.pl(kFe), x, r & 1, c->stream);
     };
