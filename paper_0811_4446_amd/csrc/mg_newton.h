@@ -59,6 +59,10 @@ void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T 
 template <class T>
 void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T *fc, int64_t pc, hipStream_t s,
                       const Batch &bt = Batch());
+// Coarse right-hand side fc = R (f - B x) in one launch (no fine residual stored).
+template <class T>
+void launch_residual_restrict(const Geom &gf, const BOpT<T> &J, const T *f, const T *x, const Geom &gc, T *fc,
+                              int64_t pc, hipStream_t s, const Batch &bt = Batch());
 template <class T>
 void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s,
                      const Batch &bt = Batch());
@@ -79,12 +83,13 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
 void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
                        int64_t plane, double3 cw, double *partials, double *out, hipStream_t s,
                        const Batch &bt = Batch());
-// Gram-Schmidt pass: w -= sum_v h_sub[v] basis_v (if h_sub), then the
-// partial sums of the weighted (w, basis_v), v < nv, or of (w, w) when
-// self_norm; with out != nullptr a second launch adds them into out[].
+// Gram-Schmidt pass: w = J z (if J and z) or w -= sum_v h_sub[v] basis_v
+// (if h_sub), then the partial sums of the weighted (w, basis_v), v < nv,
+// or of (w, w) when self_norm; with out != nullptr a second launch adds them
+// into out[].
 void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                      double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
-                     const Batch &bt = Batch());
+                     const Batch &bt = Batch(), const BOp *J = nullptr, const double *z = nullptr);
 // dst = src / |.| from the norm partials of a self_norm pass; out[0] = |.|^2.
 void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
                          double *out, hipStream_t s, const Batch &bt = Batch());

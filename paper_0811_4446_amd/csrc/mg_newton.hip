@@ -415,6 +415,17 @@ __global__ __launch_bounds__(kSW *(kSH + kSR)) void k_block_rb_sweep(Geom g, BOp
 // r = f - B x (apply == 0) or r = B x (apply == 1) at one node, 3 fields,
 // 0 on the electrode rows.
 template <class T>
+inline __device__ void block_apply_node(const Geom &g, const BOpT<T> &J, const T *x, int i, int64_t p, T &se, T &sp,
+                                        T &sv) {
+    const int64_t plane = J.plane;
+    nb_sum(g, J, x, plane, i, p, se, sp, sv);
+    T xe = x[p], xp = x[p + plane], xv = x[p + 2 * plane];
+    se += J.pl(kEE + 1)[p] * xe + J.pl(kEV + 1)[p] * xv;
+    sp += J.pl(kPP + 1)[p] * xp + J.pl(kPV + 1)[p] * xv;
+    sv += J.pl(kVV + 1)[p] * xv + J.pl(kVe)[p] * xe + J.pl(kVp)[p] * xp;
+}
+
+template <class T>
 inline __device__ void block_residual_node(const Geom &g, const BOpT<T> &J, const T *f, const T *x,
                                            T *r, int apply, int i, int j) {
     int64_t p = at(g, i, j), plane = J.plane;
@@ -423,11 +434,7 @@ inline __device__ void block_residual_node(const Geom &g, const BOpT<T> &J, cons
         return;
     }
     T se, sp, sv;
-    nb_sum(g, J, x, plane, i, p, se, sp, sv);
-    T xe = x[p], xp = x[p + plane], xv = x[p + 2 * plane];
-    se += J.pl(kEE + 1)[p] * xe + J.pl(kEV + 1)[p] * xv;
-    sp += J.pl(kPP + 1)[p] * xp + J.pl(kPV + 1)[p] * xv;
-    sv += J.pl(kVV + 1)[p] * xv + J.pl(kVe)[p] * xe + J.pl(kVp)[p] * xp;
+    block_apply_node(g, J, x, i, p, se, sp, sv);
     if (apply) {
         r[p] = se;
         r[p + plane] = sp;
@@ -500,8 +507,69 @@ __global__ void k_restrict3(Geom gf, const T *__restrict__ rf, int64_t pf, Geom 
     restrict3_node(gf, rf, pf, gc, fc, pc, I, J_);
 }
 
-// Bilinear prolongation of the coarse correction, added at fine node (i, j).
+// Residual and restriction in one launch: a workgroup owns a kCW x kCH
+// tile of coarse nodes, forms the fine residual r = f - B x over the fine
+// window those nodes restrict from (2 kCH + 1 rows, 2 kCW + 1 columns) in
+// LDS, then restricts it.  Bitwise the values of k_block_residual followed
+// by k_restrict3; the fine residual itself is not stored.
+constexpr int kCW = 32, kCH = 8;
+template <class T>
+__global__ __launch_bounds__(1024) void k_block_residual_restrict(Geom gf, BOpT<T> J, const T *__restrict__ f,
+                                                                  const T *__restrict__ x, Geom gc,
+                                                                  T *__restrict__ fc, int64_t pc, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    gf = geom_off(gf, bo_);
+    gc = geom_off(gc, bo_);
+    J.base = boff(J.base, bo_);
+    f = boff(f, bo_);
+    x = boff(x, bo_);
+    fc = boff(fc, bo_);
 
+    constexpr int FW = 2 * kCW + 1, FH = 2 * kCH + 1;
+    __shared__ T lr[3][FH * FW];
+    const int I0 = blockIdx.y * kCH, J0 = blockIdx.x * kCW;
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x, nth = blockDim.x * blockDim.y;
+    for (int t = tid; t < FH * FW; t += nth) {
+        const int i = fi0 + t / FW, j = fj0 + t % FW;
+        if (i < 0 || i > gf.nr || j < 0 || j > gf.nz) continue;
+        if (j == 0 || j == gf.nz) {
+            lr[0][t] = lr[1][t] = lr[2][t] = T(0);
+            continue;
+        }
+        const int64_t p = at(gf, i, j);
+        T se, sp, sv;
+        block_apply_node(gf, J, x, i, p, se, sp, sv);
+        lr[0][t] = f[p] - se;
+        lr[1][t] = f[p + J.plane] - sp;
+        lr[2][t] = f[p + 2 * J.plane] - sv;
+    }
+    __syncthreads();
+    if (tid >= kCW * kCH) return;
+    const int I = I0 + tid / kCW, J_ = J0 + tid % kCW;
+    if (I > gc.nr || J_ > gc.nz) return;
+    const int64_t q = at(gc, I, J_);
+    if (J_ == 0 || J_ == gc.nz) {
+        fc[q] = fc[q + pc] = fc[q + 2 * pc] = T(0);
+        return;
+    }
+    T wdn = T(1) - gf.wl[J_ - 1], wup = gf.wl[J_];
+    T acc[3] = {0, 0, 0};
+    for (int di = -1; di <= 1; ++di) {
+        int i = 2 * I + di;
+        if (i < 0 || i > gf.nr) continue;
+        T wi = (di == 0) ? T(1) : T(0.5);
+        const int l = (i - fi0) * FW + (2 * J_ - fj0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += wi * (wdn * lr[c][l - 1] + lr[c][l] + wup * lr[c][l + 1]);
+    }
+    fc[q] = acc[0];
+    fc[q + pc] = acc[1];
+    fc[q + 2 * pc] = acc[2];
+}
+
+// x += P xc on the unknown rows (bilinear, z-distance weights).
 template <class T>
 __global__ void k_prolong3(Geom gf, T *__restrict__ xf, int64_t pf, Geom gc, const T *__restrict__ xc,
                            int64_t pc, Batch bt) {
@@ -851,15 +919,17 @@ __global__ __launch_bounds__(1024) void k_wdot_multi(Geom g, const double *__res
     }
 }
 
-// One pass of classical Gram-Schmidt: optionally w -= sum_v h_sub[v]
-// basis_v at every unknown node, then the per-workgroup partial sums of the
+// One pass of classical Gram-Schmidt: w = B z (if z: the operator applied
+// to the new preconditioned direction), or w -= sum_v h_sub[v] basis_v (if
+// h_sub), at every unknown node, then the per-workgroup partial sums of the
 // weighted dot products of (the updated) w with basis_0..basis_{nv-1}, or
 // with w itself (self_norm).  The grid-wide sums are formed by a following
 // launch (k_sum_cols or k_scale_reduce) in a fixed order.
 __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ w, const double *__restrict__ basis,
                                                    int64_t vstride, int nv, int64_t plane, double3 cw,
-                                                   const double *__restrict__ h_sub, int self_norm,
-                                                   double *__restrict__ partials, Batch bt) {
+                                                   const double *__restrict__ h_sub, int self_norm, BOp Jop,
+                                                   const double *__restrict__ z, double *__restrict__ partials,
+                                                   Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     g = geom_off(g, bo_);
@@ -867,6 +937,8 @@ __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ 
     basis = boff(basis, bo_);
     h_sub = boff(h_sub, bo_);
     partials = boff(partials, bo_);
+    z = boff(z, bo_);
+    Jop.base = boff(Jop.base, bo_);
 
     const int j = blockIdx.x * kTX + threadIdx.x;
     const int i = blockIdx.y * blockDim.y + threadIdx.y;
@@ -874,7 +946,16 @@ __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ 
     const bool ok = i <= g.nr && j >= 1 && j < g.nz;
     const int64_t p = ok ? at(g, i, j) : 0;
     double wf[3] = {0.0, 0.0, 0.0};
-    if (ok) {
+    if (z && i <= g.nr && (j == 0 || j == g.nz)) {
+        const int64_t pb = at(g, i, j);
+        w[pb] = w[pb + plane] = w[pb + 2 * plane] = 0.0;
+    }
+    if (ok && z) {
+        block_apply_node(g, Jop, z, i, p, wf[0], wf[1], wf[2]);
+        w[p] = wf[0];
+        w[p + plane] = wf[1];
+        w[p + 2 * plane] = wf[2];
+    } else if (ok) {
         for (int f = 0; f < 3; ++f) {
             const int64_t q = p + f * plane;
             double acc = w[q];
@@ -1128,6 +1209,12 @@ void launch_restrict3(const Geom &gf, const T *rf, int64_t pf, const Geom &gc, T
     k_restrict3<T><<<gz(grid2d(gc), bt), blk2d(gc), 0, s>>>(gf, rf, pf, gc, fc, pc, bt);
 }
 template <class T>
+void launch_residual_restrict(const Geom &gf, const BOpT<T> &J, const T *f, const T *x, const Geom &gc, T *fc,
+                              int64_t pc, hipStream_t s, const Batch &bt) {
+    dim3 grid((gc.nz + 1 + kCW - 1) / kCW, (gc.nr + 1 + kCH - 1) / kCH);
+    k_block_residual_restrict<T><<<gz(grid, bt), dim3(64, 16), 0, s>>>(gf, J, f, x, gc, fc, pc, bt);
+}
+template <class T>
 void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s,
                      const Batch &bt) {
     k_prolong3<T><<<gz(grid2d(gf), bt), blk2d(gf), 0, s>>>(gf, xf, pf, gc, xc, pc, bt);
@@ -1165,10 +1252,10 @@ void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int6
 }
 void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                      double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
-                     const Batch &bt) {
+                     const Batch &bt, const BOp *J, const double *z) {
     dim3 gr = grid2d(g);
     k_cgs_pass<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, h_sub, self_norm ? 1 : 0,
-                                               partials, bt);
+                                               J ? *J : BOp{nullptr, 0}, z, partials, bt);
     if (out) {
         int nd = self_norm ? 1 : nv;
         k_sum_cols<<<dim3(nd, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nd, out, bt);
@@ -1283,6 +1370,8 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
                                            hipStream_t, const Batch &);                                      \
     template void launch_restrict3<T>(const Geom &, const T *, int64_t, const Geom &, T *, int64_t,          \
                                       hipStream_t, const Batch &);                                           \
+    template void launch_residual_restrict<T>(const Geom &, const BOpT<T> &, const T *, const T *,          \
+                                              const Geom &, T *, int64_t, hipStream_t, const Batch &);        \
     template void launch_prolong3<T>(const Geom &, T *, int64_t, const Geom &, const T *, int64_t,           \
                                      hipStream_t, const Batch &);                                            \
     template void launch_block_coarse_solve<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *,     \

@@ -107,12 +107,16 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     const bool zero_sweep = fused_ok<T>(c, c->desc.nu1);
     if (!zero_sweep) launch_fill(x, 3 * plane_of(L), T(0), s, c->bt);
     block_smooth<T>(c, l, J, f, x, c->desc.nu1, zero_sweep, nullptr, s);
-    T *r = Prec<T>::r(c, l);
-    launch_block_residual<T>(L.g, J, f, x, r, false, s, c->bt);
     const Level &C = c->lev[l + 1];
     BOpT<T> Jc = Prec<T>::op(c, l + 1);
     T *fc = Jc.pl(kFe);
-    launch_restrict3<T>(L.g, r, plane_of(L), C.g, fc, plane_of(C), s, c->bt);
+    if (c->nw.rb_fused) {
+        launch_residual_restrict<T>(L.g, J, f, x, C.g, fc, plane_of(C), s, c->bt);
+    } else {
+        T *r = Prec<T>::r(c, l);
+        launch_block_residual<T>(L.g, J, f, x, r, false, s, c->bt);
+        launch_restrict3<T>(L.g, r, plane_of(L), C.g, fc, plane_of(C), s, c->bt);
+    }
     T *xc = Prec<T>::x(c, l + 1);
     block_vcycle<T>(c, l + 1, fc, xc, s);
     // the coarse-grid correction: added by the first post-smoothing sweep, or
@@ -228,9 +232,9 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     } else {
         block_vcycle<double>(c, 0, vk, zk, s);
     }
-    launch_block_residual<double>(g, J, nullptr, zk, W.w, true, s, c->bt);  // w = J z_k
-    // classical Gram-Schmidt twice: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2, |w|^2
-    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, W.partials, dev, s, c->bt);
+    // w = J z_k, then classical Gram-Schmidt twice: h1 = V^T w; w -= V h1,
+    // h2 = V^T w; w -= V h2, |w|^2
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, W.partials, dev, s, c->bt, &J, zk);
     launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev, false, W.partials, dev + (m + 1), s, c->bt);
     launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev + (m + 1), true, W.partials, nullptr, s, c->bt);
     launch_scale_reduce(g, W.w, vk1, p0, W.partials, dev + 2 * m + 2, s, c->bt);
