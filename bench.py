@@ -28,6 +28,13 @@ sys.path.insert(0, ROOT)
 METRIC = ("time-to-steady at 257² & 1025² (s), V-cycle HBM GB/s; "
           "plain FP64 vs chosen forms")
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the finest-level sweep, from FETCH_SIZE and
+# WRITE_SIZE counter runs (x2.0 and x1.0 by a 512 MiB copy's counters; the
+# runs and tables are kept under profiles/).  Valid only for the kernel
+# source they were taken with: any change to it reports traffic as null.
+MEASURED_TRAFFIC = {"source": "paper_0811_4446_amd/csrc/mg_newton.hip",
+                    "sha1": "f706b2c9220e198f7d07c2af49ed6c28c2d1b24d",
+                    "bytes": {256: 29218304, 1024: 469636301}}
 
 
 def log(*a):
@@ -113,12 +120,16 @@ def roofline(sol, N, reps=200):
     solve), against the algorithmic bytes of one sweep: per unknown node 27
     Jacobian entries, 3 right-hand-side values and 3 old unknowns read, 3
     new unknowns written (FP64)."""
+    import hashlib
     avg_ms = sol.time_kernel(4, 0, reps=reps)
     nodes = (N + 1) * (N - 1)
+    with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"]), "rb") as fh:
+        same = hashlib.sha1(fh.read()).hexdigest() == MEASURED_TRAFFIC["sha1"]
+    traffic = MEASURED_TRAFFIC["bytes"].get(N) if same else None
     bytes_launch = 8.0 * nodes * 36
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     return dict(bound="hbm", kernel="k_block_rb_sweep", level="%dx%d" % (N + 1, N + 1), achieved=round(achieved, 1),
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 avg_launch_us=round(avg_ms * 1e3, 3), algorithmic_bytes_per_launch=int(bytes_launch),
                 timed_launches=reps)
 
