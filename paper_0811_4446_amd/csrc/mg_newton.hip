@@ -797,17 +797,81 @@ __global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOpT<T> J, 
 // residual, restriction, coarse solve and prolongation with barriers in
 // between, node by node exactly as the per-level kernels do.
 // ---------------------------------------------------------------------------
+// Where the sub-cycle keeps its levels.  Global: the levels' own workspace.
+// LDS: every level's Jacobian planes, correction and residual, and the top
+// level's right-hand side, copied into LDS in a compact layout (pitch nz+1)
+// when they fit, so that the barrier phases read no global memory; the top
+// level's correction is written back at the end.
+constexpr int kSubPool = 15360;  // LDS elements of the staged levels
+template <class T, bool kLds>
+struct SubMem;
 template <class T>
+struct SubMem<T, false> {
+    const FusedLevelsT<T> &F;
+    int64_t bo;
+    __device__ Geom geom(int q) const { return geom_off(F.g[q], bo); }
+    __device__ BOpT<T> jac(int q) const { return BOpT<T>{boff(F.J[q], bo), F.plane[q]}; }
+    __device__ T *x(int q) const { return boff(F.x[q], bo); }
+    __device__ T *r(int q) const { return boff(F.r[q], bo); }
+    __device__ const T *f0() const { return boff(F.f0, bo); }
+    __device__ int64_t xplane(int q) const { return F.plane[q]; }
+};
+template <class T>
+struct SubMem<T, true> {
+    const FusedLevelsT<T> &F;
+    int64_t bo;
+    T *pool;
+    __device__ int nodes(int q) const { return (F.g[q].nr + 1) * (F.g[q].nz + 1); }
+    __device__ int off(int q) const {
+        int o = 0;
+        for (int t = 0; t < q; ++t) o += (kBPlanes + 6) * nodes(t);
+        return o;
+    }
+    __device__ Geom geom(int q) const {
+        Geom g = geom_off(F.g[q], bo);
+        g.pitch = g.nz + 1;
+        return g;
+    }
+    __device__ BOpT<T> jac(int q) const { return BOpT<T>{pool + off(q), nodes(q)}; }
+    __device__ T *x(int q) const { return pool + off(q) + kBPlanes * nodes(q); }
+    __device__ T *r(int q) const { return pool + off(q) + (kBPlanes + 3) * nodes(q); }
+    __device__ const T *f0() const { return pool + off(F.n); }
+    __device__ int64_t xplane(int q) const { return nodes(q); }
+    // compact copy of planes [0, np) of a global level array into LDS
+    __device__ void stage(const Geom &gg, const T *src, int64_t gplane, T *dst, int np) const {
+        const int w = gg.nz + 1, nn = (gg.nr + 1) * w;
+        for (int t = threadIdx.x; t < np * nn; t += blockDim.x) {
+            const int k = t / nn, node = t % nn;
+            dst[t] = src[k * gplane + (int64_t)(node / w) * gg.pitch + node % w];
+        }
+    }
+};
+
+// The coarse end of the block V-cycle in one workgroup: levels 0..n-1 of
+// `F` (the last is the coarsest) are small enough that per-level launches
+// would cost more than the work, so one workgroup runs their smoothing,
+// residual, restriction, coarse solve and prolongation with barriers in
+// between, node by node exactly as the per-level kernels do.
+template <class T, bool kLds>
 __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
-    // F stays in the kernel-argument segment (read-only, indexed by level);
-    // the problem offset is applied to local copies
-    auto geom = [&](int q) { return geom_off(F.g[q], bo_); };
-    auto jac = [&](int q) { return BOpT<T>{boff(F.J[q], bo_), F.plane[q]}; };
-    auto xof = [&](int q) { return boff(F.x[q], bo_); };
-    auto rof = [&](int q) { return boff(F.r[q], bo_); };
-    const T *f0 = boff(F.f0, bo_);
+    __shared__ T pool[kLds ? kSubPool : 1];
+    SubMem<T, kLds> M{F, bo_};
+    if constexpr (kLds) {
+        M.pool = pool;
+        for (int q = 0; q < F.n; ++q) {
+            const Geom gg = geom_off(F.g[q], bo_);
+            M.stage(gg, boff(F.J[q], bo_), F.plane[q], M.jac(q).base, kBPlanes);
+        }
+        M.stage(geom_off(F.g[0], bo_), boff(F.f0, bo_), F.plane[0], const_cast<T *>(M.f0()), 3);
+        __syncthreads();
+    }
+    auto geom = [&](int q) { return M.geom(q); };
+    auto jac = [&](int q) { return M.jac(q); };
+    auto xof = [&](int q) { return M.x(q); };
+    auto rof = [&](int q) { return M.r(q); };
+    const T *f0 = M.f0();
     const T *invT = boff(F.invT, bo_);
 
     __shared__ T rhs[3 * kMaxFusedCoarse];
@@ -853,6 +917,14 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
         const int q = n - 1;
         const BOpT<T> J = jac(q);
         const T *f = (q == 0) ? f0 : J.pl(kFe);
+        if constexpr (kLds) {
+            // the staged coarsest correction needs its electrode rows zero
+            const Geom g = geom(q);
+            const int nodes = (g.nr + 1) * (g.nz + 1);
+            T *x = xof(q);
+            for (int t = threadIdx.x; t < 3 * nodes; t += nt) x[t] = T(0);
+            __syncthreads();
+        }
         block_coarse_solve_wg(geom(q), J.plane, f, invT, xof(q), rhs);
         __syncthreads();
     }
@@ -866,7 +938,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
         const int nodes = (g.nr + 1) * (g.nz + 1);
         for (int t = threadIdx.x; t < nodes; t += nt) {
             int i = t / (g.nz + 1), j = t % (g.nz + 1);
-            if (j >= 1 && j < g.nz) prolong3_node(g, x, J.plane, gc, xc, F.plane[q + 1], i, j);
+            if (j >= 1 && j < g.nz) prolong3_node(g, x, J.plane, gc, xc, M.xplane(q + 1), i, j);
         }
         __syncthreads();
         for (int s = 0; s < F.nu2; ++s)
@@ -877,6 +949,18 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
                 }
                 __syncthreads();
             }
+    }
+    if constexpr (kLds) {
+        __syncthreads();
+        const Geom gg = geom_off(F.g[0], bo_), gl = geom(0);
+        T *dst = boff(F.x[0], bo_);
+        const T *src = xof(0);
+        const int w = gg.nz + 1, nn = (gg.nr + 1) * w;
+        for (int t = threadIdx.x; t < 3 * nn; t += blockDim.x) {
+            const int k = t / nn, node = t % nn;
+            dst[k * F.plane[0] + (int64_t)(node / w) * gg.pitch + node % w] = src[k * (int64_t)nn + node];
+        }
+        (void)gl;
     }
 }
 
@@ -1238,7 +1322,13 @@ void launch_block_coarse_solve(const Geom &g, const BOpT<T> &J, const T *f, cons
 }
 template <class T>
 void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s, const Batch &bt) {
-    k_block_subcycle<T><<<dim3(1, 1, bt.n), 1024, 0, s>>>(F, bt);
+    int64_t need = 0;
+    for (int q = 0; q < F.n; ++q) need += (int64_t)(kBPlanes + 6) * (F.g[q].nr + 1) * (F.g[q].nz + 1);
+    need += 3 * (int64_t)(F.g[0].nr + 1) * (F.g[0].nz + 1);
+    if (need <= kSubPool)
+        k_block_subcycle<T, true><<<dim3(1, 1, bt.n), 1024, 0, s>>>(F, bt);
+    else
+        k_block_subcycle<T, false><<<dim3(1, 1, bt.n), 1024, 0, s>>>(F, bt);
 }
 int block_vec_blocks(const Geom &g) {
     dim3 gr = grid2d(g);
