@@ -31,9 +31,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the finest-level sweep, from FETCH_SIZE and
 # WRITE_SIZE counter runs (x2.0 and x1.0 by a 512 MiB copy's counters; the
 # runs and tables are kept under profiles/).  Valid only for the kernel
-# source they were taken with: any change to it reports traffic as null.
+# source they were taken with (the text between the two markers, which holds
+# the sweep kernel and its device helpers): any change to it reports null.
 MEASURED_TRAFFIC = {"source": "paper_0811_4446_amd/csrc/mg_newton.hip",
-                    "sha1": "f706b2c9220e198f7d07c2af49ed6c28c2d1b24d",
+                    "begin": "// Bilinear prolongation (z-distance weights) of one coarse field",
+                    "end": "// r = f - B x (apply == 0) or r = B x (apply == 1) at one node, 3 fields,",
+                    "sha1": "447a586191e5b33f68e63f0c177018882a867d91",
                     "bytes": {256: 29218304, 1024: 469636301}}
 
 
@@ -123,8 +126,10 @@ def roofline(sol, N, reps=200):
     import hashlib
     avg_ms = sol.time_kernel(4, 0, reps=reps)
     nodes = (N + 1) * (N - 1)
-    with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"]), "rb") as fh:
-        same = hashlib.sha1(fh.read()).hexdigest() == MEASURED_TRAFFIC["sha1"]
+    with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"])) as fh:
+        src = fh.read()
+    a, e = src.find(MEASURED_TRAFFIC["begin"]), src.find(MEASURED_TRAFFIC["end"])
+    same = 0 <= a < e and hashlib.sha1(src[a:e].encode()).hexdigest() == MEASURED_TRAFFIC["sha1"]
     traffic = MEASURED_TRAFFIC["bytes"].get(N) if same else None
     bytes_launch = 8.0 * nodes * 36
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
@@ -245,6 +250,44 @@ def compare_precisions(args, M, I, N, vtops):
     print(json.dumps(out), flush=True)
 
 
+def sweep_reference(args, M, I):
+    """The first `--sweep-ref` problems of every size class of the sweep,
+    solved one at a time (single-problem contexts, same FP32 preconditioner
+    and schedule): the per problem-step cost the batch is compared with."""
+    import numpy as np
+    import torch
+    draws = I.sweep_draws(args.nprob, 12345)
+    classes = {}
+    for q, d in enumerate(draws):
+        classes.setdefault(d["N"], []).append((q, d))
+    sched = schedule(M, args.lin_rtol)
+    rows = []
+    for N in sorted(classes):
+        z = I.z_cos(N)
+        sol = M.Solver(N, N, z, krylov_m=20, coarsest=4, prec=M.FP32_IR)
+        for q, d in classes[N][:args.sweep_ref]:
+            ph = dict(I.PHYS)
+            ph.update(V_top=d["V_top"], mu_e=d["mu_e"], D_e=d["D_e"], mu_p=d["mu_p"], D_p=d["D_p"])
+            ne = I.initial_density(N, N, 1000 + q)
+            t = [sol.upload(I.initial_potential(N, N, z, 0.0, ph["V_top"])), sol.upload(ne), sol.upload(ne),
+                 sol.upload(I.source(N, N, z))]
+            torch.cuda.synchronize()
+            t0 = time.time()
+            code, rep = sol.steady(M.Physics.of(ph), sol.state(t[0], t[1], t[2], t[3], t[3]), sched)
+            torch.cuda.synchronize()
+            el = time.time() - t0
+            rows.append(dict(grid="%dx%d" % (N + 1, N + 1), problem=q, code=code, seconds=round(el, 3),
+                             steps=rep.steps, ms_per_step=round(1e3 * el / max(rep.steps, 1), 3)))
+            log(rows[-1])
+        del sol
+    out = {"metric": METRIC, "value": None, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+           "data": "synthetic",
+           "config": {"workload": "reference for the parameter sweep: its first problems of each size solved "
+                                  "one at a time", "runs": rows}}
+    print(json.dumps(out), flush=True)
+
+
 def sweep(args, M, I):
     """Parameter sweep: independent steady solves from their own seeded
     random starts, grid sizes drawn from {65, 129, 257, 513}^2, V_top ~
@@ -299,6 +342,7 @@ def sweep(args, M, I):
         rows.append(dict(grid="%dx%d" % (N + 1, N + 1), problems=len(items), converged=ok, code=code,
                          seconds=round(el, 3), tuning=dict(rows_per_block=choice[0], fuse_max=choice[1]),
                          steps_mean=float(np.mean([r["steps"] for r in reps])),
+                         ms_per_problem_step=round(1e3 * el / max(1, sum(r["steps"] for r in reps)), 4),
                          fgmres_total=int(cyc), newton_total=int(sum(r["newton_its"] for r in reps))))
         log(rows[-1])
         del B
@@ -360,6 +404,8 @@ def main():
     ap.add_argument("--grid", type=int, default=256, help="finest N (256: 257x257 workload; 1024 for 1025x1025)")
     ap.add_argument("--sweep", action="store_true", help="batched parameter sweep instead of the chain")
     ap.add_argument("--nprob", type=int, default=512)
+    ap.add_argument("--sweep-ref", type=int, default=0, help="solve this many problems per size class of the "
+                                                              "sweep one at a time (reference for the batch)")
     ap.add_argument("--learned", action="store_true", help="learned warm start: train and compare on 257x257")
     ap.add_argument("--n-train", type=int, default=128)
     ap.add_argument("--n-val", type=int, default=16)
@@ -388,6 +434,8 @@ def main():
 
     if args.roofline_only:
         return roofline_only(args, M, I)
+    if args.sweep_ref:
+        return sweep_reference(args, M, I)
     if args.sweep:
         return sweep(args, M, I)
     if args.learned:

@@ -279,17 +279,32 @@ def compare(net, data, timed=8, criterion="run", log=print, prec=M.FP32_IR, atte
         pb, rb = polish(sol, P[p], b, S)
         d_pol.append(maxrel(pa, pb))
         d_to_pol.append(max(maxrel(a, pa), maxrel(b, pb)))
-    # single-problem wall clock, FP64 preconditioner
+    # single-problem wall clock, FP64 preconditioner; the learned start's time
+    # includes computing its input planes, the network and applying its output
     sol64 = M.Solver(Nf, Nf, z, krylov_m=30, coarsest=4, prec=M.FP64)
     single = {"plain": [], "learned": []}
     for p in range(min(timed, n)):
         for name in ("plain", "learned"):
             use_plain = name == "plain" or (fb[p] and criterion != "run")
             src = data["up"][p] if use_plain else starts[p]["raw"]
+            t_inf = 0.0
+            if not use_plain:
+                up, ph = data["up"][p], data["phys"][p]
+                su = sol64.state(up["V"], up["ne"], up["np"], up["Se"], up["Se"])
+                g = {k: sol64.field() for k in ("V", "ne", "np")}
+                torch.cuda.synchronize()
+                ti = time.time()
+                feat, ns = M.features(sol64, su, ph["V_top"], data["draws"][p]["ratio"])
+                pred = net.forward(feat.unsqueeze(0).contiguous())[0].contiguous()
+                M.apply_prediction(sol64, su, pred, ph["V_top"], ns, P[p], sol64.state(g["V"], g["ne"], g["np"],
+                                                                                     up["Se"], up["Se"]))
+                torch.cuda.synchronize()
+                t_inf = time.time() - ti
+                src = g
             t = [src["V"].clone(), src["ne"].clone(), src["np"].clone(), data["up"][p]["Se"]]
             st = sol64.state(t[0], t[1], t[2], t[3], t[3])
             torch.cuda.synchronize()
-            t0 = time.time()
+            t0 = time.time() - t_inf
             cap = attempt_steps if (name == "learned" and attempt_steps) else 20000
             code, rep = sol64.steady(P[p], st, _sched(max_steps=cap))
             if name == "learned" and criterion == "run" and (code != 0 or rep.last_change >= 1e-8):
@@ -298,7 +313,7 @@ def compare(net, data, timed=8, criterion="run", log=print, prec=M.FP32_IR, atte
                 st = sol64.state(t[0], t[1], t[2], t[3], t[3])
                 code, rep = sol64.steady(P[p], st, _sched())
             torch.cuda.synchronize()
-            single[name].append(dict(seconds=time.time() - t0, steps=rep.steps, code=code))
+            single[name].append(dict(seconds=time.time() - t0, steps=rep.steps, code=code, inference=t_inf))
     summary = dict(test_draws=n, criterion=criterion, fallbacks=int(fb.sum()),
                    steps_plain_mean=float(sp.mean()), steps_learned_mean=float(sl.mean()),
                    steps_network_start_mean=float(sr.mean()),
@@ -315,6 +330,7 @@ def compare(net, data, timed=8, criterion="run", log=print, prec=M.FP32_IR, atte
                    final_to_polished_maxrel_max=float(max(d_to_pol)),
                    single_seconds_plain=[round(s["seconds"], 3) for s in single["plain"]],
                    single_seconds_learned=[round(s["seconds"], 3) for s in single["learned"]],
+                   single_inference_seconds=[round(s["inference"], 4) for s in single["learned"]],
                    single_steps_plain=[s["steps"] for s in single["plain"]],
                    single_steps_learned=[s["steps"] for s in single["learned"]],
                    time_ratio_median=float(np.median([l["seconds"] / p_["seconds"]
