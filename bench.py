@@ -380,6 +380,8 @@ def learned(args, M, I):
         np.save(args.save_weights, net.params.cpu().numpy())
     summary = WS.compare(net, te, timed=args.n_timed, criterion=args.criterion, log=log)
     summary = {k: v for k, v in summary.items() if not k.startswith("_")}
+    thr = WS.network_throughput(net)
+    log("network throughput: %s" % thr)
     vals = summary["single_seconds_learned"]
     out = {"metric": METRIC, "value": round(float(np.mean(vals)), 4) if vals else None, "unit": "s", "n_gpus": 1,
            "steps": 1, "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -389,7 +391,7 @@ def learned(args, M, I):
                       "n_train": args.n_train, "n_val": args.n_val, "n_test": args.n_test, "epochs": args.epochs,
                       "data_generation_s": round(tgen, 1), "training_s": round(ttrain, 1),
                       "final_train_loss": hist[-1][1], "final_val_loss": hist[-1][2],
-                      "initial_val_loss": hist[0][2], "summary": summary}}
+                      "initial_val_loss": hist[0][2], "summary": summary, "network_throughput": thr}}
     print(json.dumps(out), flush=True)
 
 

@@ -340,3 +340,34 @@ def compare(net, data, timed=8, criterion="run", log=print, prec=M.FP32_IR, atte
     summary["_chosen_finals"] = chosen
     summary["_plain_finals"] = res["plain"]["finals"]
     return summary
+
+
+def network_throughput(net, B=8, H=257, W=257, reps=20, peak_tflops=2500.0):
+    """Timed forward passes and gradient evaluations of the network on a
+    B x 7 x H x W batch: milliseconds, achieved TFLOP/s and the fraction of
+    the dense bf16 MFMA peak.  Flops per pixel: forward 2*9*(7*32 + 32*32 +
+    32*32 + 32*3) = 42,624; gradient = forward + input gradients of layers
+    2-4 (38,592) + weight gradients (42,624)."""
+    x = torch.randn((B, 7, H, W), dtype=torch.float32, device=net.device)
+    t = torch.randn((B, 3, H, W), dtype=torch.float32, device=net.device)
+    px = B * H * W
+    f_fwd, f_grad = 42624.0 * px, (42624.0 + 38592.0 + 42624.0) * px
+    net.forward(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(net.stream)
+    for _ in range(reps):
+        net.forward(x)
+    b.record(net.stream)
+    b.synchronize()
+    fwd_ms = a.elapsed_time(b) / reps
+    net.grad(x, t)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(reps):
+        net.grad(x, t)
+    torch.cuda.synchronize()
+    grad_ms = (time.time() - t0) * 1e3 / reps
+    return dict(batch=B, H=H, W=W, forward_ms=round(fwd_ms, 3), forward_tflops=round(f_fwd / fwd_ms / 1e9, 2),
+                forward_mfma_frac=round(f_fwd / fwd_ms / 1e9 / peak_tflops, 5), grad_ms=round(grad_ms, 3),
+                grad_tflops=round(f_grad / grad_ms / 1e9, 2), grad_mfma_frac=round(f_grad / grad_ms / 1e9 / peak_tflops, 5))
