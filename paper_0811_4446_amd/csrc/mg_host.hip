@@ -97,6 +97,7 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
         L.g.nr = nr;
         L.g.nz = nz;
         L.g.ty = 4;
+        L.g.sh = 8;
         L.g.pitch = pitch;
         L.g.dr = d->R / nr;
         L.g.wr = cv.take<double>(nr + 1);
@@ -360,6 +361,8 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
     c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
+    if (const char *e = getenv("MGF_SWEEP_ROWS"))
+        for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(e) == 16 ? 16 : 8;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;

@@ -18,6 +18,7 @@ constexpr int kMaxTY = 16;  // largest rows-per-workgroup of the 2D kernels
 struct Geom {
     int nr, nz;
     int ty;             // radial rows per workgroup of the 2D kernels (tuning)
+    int sh;             // radial rows of a red-black sweep tile: 8 (default) or 16
     int64_t pitch;
     double dr;
     const double *wr;   // radial width of node i (area of its z-faces), nr+1

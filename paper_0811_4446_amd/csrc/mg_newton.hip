@@ -313,13 +313,17 @@ __global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__re
 // nodes.  Every value equals what two half-sweep launches compute, with one
 // launch and one pass over the Jacobian; the ring costs (kSW + kSH) /
 // (kSW kSH / 2) extra colour-0 updates.
-constexpr int kSW = 32, kSH = 16, kSR = 3;
-static_assert(kSR * kSW == 2 * kSW + 2 * kSH, "one ring node per ring thread");
-template <class T>
-__global__ __launch_bounds__(kSW *(kSH + kSR)) void k_block_rb_sweep(Geom g, BOpT<T> J, const T *__restrict__ f,
-                                                                     const T *__restrict__ xin, T *__restrict__ xout,
-                                                                     int zin, Geom gc, const T *__restrict__ xc,
-                                                                     int64_t pc, Batch bt) {
+constexpr int kSW = 32;
+template <int SH>
+struct SweepTile {
+    static constexpr int kSH = SH;                                // tile rows
+    static constexpr int kSR = (2 * kSW + 2 * SH + kSW - 1) / kSW;  // ring thread rows
+};
+template <class T, int SH>
+__global__ __launch_bounds__(kSW *(SH + SweepTile<SH>::kSR)) void k_block_rb_sweep(
+    Geom g, BOpT<T> J, const T *__restrict__ f, const T *__restrict__ xin, T *__restrict__ xout, int zin, Geom gc,
+    const T *__restrict__ xc, int64_t pc, Batch bt) {
+    constexpr int kSH = SH, kSR = SweepTile<SH>::kSR;
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     g = geom_off(g, bo_);
@@ -368,9 +372,12 @@ __global__ __launch_bounds__(kSW *(kSH + kSR)) void k_block_rb_sweep(Geom g, BOp
         } else if (k < 2 * kSW + kSH) {
             ni = i0 + k - 2 * kSW;
             nj = j0 - 1;
-        } else {
+        } else if (k < 2 * kSW + 2 * kSH) {
             ni = i0 + k - 2 * kSW - kSH;
             nj = j0 + kSW;
+        } else {
+            ni = -1;  // spare ring thread
+            nj = 0;
         }
     }
     const bool valid = ni >= 0 && ni <= g.nr && nj >= 1 && nj < g.nz;
@@ -1278,9 +1285,18 @@ void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int co
 template <class T>
 void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
                            const Geom *gc, const T *xc, int64_t pc, hipStream_t s, const Batch &bt) {
-    dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + kSH - 1) / kSH);
-    k_block_rb_sweep<T><<<gz(grid, bt), dim3(kSW, kSH + kSR), 0, s>>>(g, J, f, xin, xout, zin ? 1 : 0,
-                                                                       gc ? *gc : g, xc, pc, bt);
+    const Geom &gcc = gc ? *gc : g;
+    if (g.sh == 8) {
+        using Tl = SweepTile<8>;
+        dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + Tl::kSH - 1) / Tl::kSH);
+        k_block_rb_sweep<T, 8><<<gz(grid, bt), dim3(kSW, Tl::kSH + Tl::kSR), 0, s>>>(g, J, f, xin, xout, zin ? 1 : 0,
+                                                                                    gcc, xc, pc, bt);
+    } else {
+        using Tl = SweepTile<16>;
+        dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + Tl::kSH - 1) / Tl::kSH);
+        k_block_rb_sweep<T, 16><<<gz(grid, bt), dim3(kSW, Tl::kSH + Tl::kSR), 0, s>>>(g, J, f, xin, xout,
+                                                                                      zin ? 1 : 0, gcc, xc, pc, bt);
+    }
 }
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,

@@ -762,6 +762,8 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
     c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
+    if (const char *sr = getenv("MGF_SWEEP_ROWS"))
+        for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(sr) == 16 ? 16 : 8;
     c->ws_base = base;
     c->ws_bytes = wsb;
     int64_t stride = toff / nprob;

@@ -145,3 +145,12 @@ def test_fused_rb_sweep_matches_half_sweeps(N, monkeypatch):
                 results[half] = [sol.download(x) for x in t[:3]]
             for a, b in zip(results[0], results[1]):
                 assert np.array_equal(a, b), (prec, rows)
+        # the 16-row sweep tile gives the same bits as the default 8-row one
+        monkeypatch.setenv("MGF_SWEEP_ROWS", "16")
+        sol, t, st = _gpu(N, V, ne, np_, S, krylov_m=20, prec=prec)
+        sol.tune(16, 32)
+        for dt in (1e-3, 1e-2, 0.1):
+            sol.step(m.Physics.of(ph), st, dt, sc)
+        monkeypatch.delenv("MGF_SWEEP_ROWS", raising=False)
+        for a, b in zip([sol.download(x) for x in t[:3]], results[0]):
+            assert np.array_equal(a, b), (prec, "sweep rows 16")
