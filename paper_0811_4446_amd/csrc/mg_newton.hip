@@ -519,7 +519,8 @@ __global__ void k_restrict3(Geom gf, const T *__restrict__ rf, int64_t pf, Geom 
 // window those nodes restrict from (2 kCH + 1 rows, 2 kCW + 1 columns) in
 // LDS, then restricts it.  Bitwise the values of k_block_residual followed
 // by k_restrict3; the fine residual itself is not stored.
-constexpr int kCW = 32, kCH = 8;
+constexpr int kCW = 32, kCH = 4;  // fine window 9 x 65: one node per thread of a 64 x 10 workgroup
+static_assert((2 * kCW + 1) * (2 * kCH + 1) <= 64 * 10, "one fine node per thread");
 template <class T>
 __global__ __launch_bounds__(1024) void k_block_residual_restrict(Geom gf, BOpT<T> J, const T *__restrict__ f,
                                                                   const T *__restrict__ x, Geom gc,
@@ -1312,7 +1313,7 @@ template <class T>
 void launch_residual_restrict(const Geom &gf, const BOpT<T> &J, const T *f, const T *x, const Geom &gc, T *fc,
                               int64_t pc, hipStream_t s, const Batch &bt) {
     dim3 grid((gc.nz + 1 + kCW - 1) / kCW, (gc.nr + 1 + kCH - 1) / kCH);
-    k_block_residual_restrict<T><<<gz(grid, bt), dim3(64, 16), 0, s>>>(gf, J, f, x, gc, fc, pc, bt);
+    k_block_residual_restrict<T><<<gz(grid, bt), dim3(64, 10), 0, s>>>(gf, J, f, x, gc, fc, pc, bt);
 }
 template <class T>
 void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s,
