@@ -696,9 +696,10 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
     const int m = g.nz - 1;
     const int n = 3 * (g.nr + 1) * m;
     const int n2 = 2 * n;
-    __shared__ double M[kLdsGJ * 2 * kLdsGJ];
-    __shared__ double fcol[kLdsGJ], prow[2 * kLdsGJ], orow[2 * kLdsGJ];
+    // two copies of the augmented matrix: column step k reads one, writes the other
+    __shared__ double Mb[2][kLdsGJ * 2 * kLdsGJ];
     __shared__ int piv;
+    double *M = Mb[0];
     for (int t = threadIdx.x; t < n * n2; t += blockDim.x) M[t] = 0.0;
     __syncthreads();
     for (int node = threadIdx.x; node < (g.nr + 1) * m; node += blockDim.x) {
@@ -721,36 +722,46 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
         for (int f = 0; f < 3; ++f) M[(rowb + f) * n2 + n + rowb + f] = 1.0;
     }
     __syncthreads();
-    // Gauss-Jordan with partial pivoting, three barriers per column: the
-    // pivot row (scaled) and the row it replaces are staged, then every
-    // other row is eliminated against the staged pivot row.  Waves own rows,
-    // lanes own columns.
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    // Gauss-Jordan with partial pivoting, two barriers per column: the pivot
+    // search, then every element of the next copy in one pass (scaled pivot
+    // row, exchanged row, other rows eliminated against the scaled pivot row),
+    // each thread's elements loaded before any is stored.
+    constexpr int kPer = (kLdsGJ * 2 * kLdsGJ + 1023) / 1024;
+    const int total = n * n2;
+    int cur = 0;
     for (int col = 0; col < n; ++col) {
-        pivot_search_wave0(M, n2, col, n, &piv);
+        const double *A = Mb[cur];
+        double *B = Mb[cur ^ 1];
+        pivot_search_wave0(A, n2, col, n, &piv);
         __syncthreads();
         const int pv = piv;
-        const double pinv = 1.0 / M[pv * n2 + col];
-        for (int t = threadIdx.x; t < n2; t += blockDim.x) {
-            prow[t] = M[pv * n2 + t] * pinv;
-            orow[t] = M[col * n2 + t];
-        }
-        for (int rr = threadIdx.x; rr < n; rr += blockDim.x)
-            fcol[rr] = (rr == col) ? 0.0 : (rr == pv ? M[col * n2 + col] : M[rr * n2 + col]);
-        __syncthreads();
-        for (int rr = wave; rr < n; rr += nwave) {
-            const double fct = fcol[rr];
-            for (int cc = lane; cc < n2; cc += 64) {
-                if (rr == col) {
-                    M[rr * n2 + cc] = prow[cc];
-                } else {
-                    double v = (rr == pv) ? orow[cc] : M[rr * n2 + cc];
-                    M[rr * n2 + cc] = (fct != 0.0) ? v - fct * prow[cc] : v;
-                }
+        const double pinv = 1.0 / A[pv * n2 + col];
+        const double fpv = A[col * n2 + col];
+        double v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int t = threadIdx.x + k * 1024;
+            if (t >= total) break;
+            const int rr = t / n2, cc = t - rr * n2;
+            const double prc = A[pv * n2 + cc] * pinv;
+            if (rr == col) {
+                v[k] = prc;
+            } else {
+                const double src = (rr == pv) ? A[col * n2 + cc] : A[rr * n2 + cc];
+                const double fct = (rr == pv) ? fpv : A[rr * n2 + col];
+                v[k] = (fct != 0.0) ? src - fct * prc : src;
             }
         }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int t = threadIdx.x + k * 1024;
+            if (t >= total) break;
+            B[t] = v[k];
+        }
         __syncthreads();
+        cur ^= 1;
     }
+    M = Mb[cur];
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
         int row = t / n, k = t % n;
         invT[(int64_t)k * n + row] = M[row * n2 + n + k];
