@@ -89,3 +89,24 @@ def test_setup_rejects_small_workspace_without_touching_it():
     # a fake aligned address: the size check fails first, nothing is dereferenced
     code = M.lib().mg_setup(ctypes.byref(d), ctypes.c_void_p(1 << 20), ws - 8, None, ctypes.byref(h))
     assert code == -6
+
+
+@pytest.mark.parametrize("nprob,krylov,msg", [(0, 20, "nprob"), (-3, 20, "nprob"), (70000, 20, "nprob"),
+                                              (4, 0, "krylov_m")])
+def test_batch_query_rejects_empty_and_oversized_batches(nprob, krylov, msg):
+    import ctypes
+    d = M.make_desc(64, 64, inputs.z_cos(64), krylov_m=krylov, coarsest=4)
+    stride, total = ctypes.c_int64(0), ctypes.c_int64(0)
+    code = M.lib().mg_batch_query(ctypes.byref(d), nprob, ctypes.byref(stride), ctypes.byref(total))
+    assert code == -1  # MG_EINVAL
+    assert msg in M.lib().mg_last_error().decode()
+
+
+def test_batch_query_stride_covers_one_problem():
+    import ctypes
+    d = M.make_desc(64, 64, inputs.z_cos(64), krylov_m=20, coarsest=4)
+    _, ws1 = M.query(d)
+    stride, total = ctypes.c_int64(0), ctypes.c_int64(0)
+    assert M.lib().mg_batch_query(ctypes.byref(d), 5, ctypes.byref(stride), ctypes.byref(total)) == 0
+    assert stride.value >= ws1 and stride.value % 256 == 0
+    assert total.value >= 5 * stride.value

@@ -154,3 +154,31 @@ def test_fused_rb_sweep_matches_half_sweeps(N, monkeypatch):
         monkeypatch.delenv("MGF_SWEEP_ROWS", raising=False)
         for a, b in zip([sol.download(x) for x in t[:3]], results[0]):
             assert np.array_equal(a, b), (prec, "sweep rows 16")
+
+
+@pytest.mark.parametrize("nr,nz,prec_name", [(32, 64, "FP64"), (64, 32, "FP64"), (32, 64, "FP32_IR")])
+def test_newton_step_rectangular_grid(nr, nz, prec_name):
+    """N_r != N_z (ragged sweep tiles and a rectangular coarsest grid): one
+    BE step after 10 oracle steps of the steady schedule matches the oracle's
+    Newton iterates (FP64 preconditioner: 1e-11; FP32 preconditioner inside
+    FP64 FGMRES, converged to the same tolerance: 1e-9)."""
+    _say("newton step rectangular", nr, nz, prec_name)
+    m = M()
+    z = I.z_cos(nz)
+    ne = I.initial_density(nr, nz, 3)
+    np_, V, S = ne.copy(), I.initial_potential(nr, nz, z), I.source(nr, nz, z)
+    ph = dict(I.PHYS)
+    cp = NW.Coupled(nr, nz, 1.0, z, ph)
+    NW.steady(cp, V, ne, np_, S, S, max_steps=10)
+    sol = m.Solver(nr, nz, z, krylov_m=20, coarsest=4, prec=getattr(m, prec_name))
+    t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)]
+    st = sol.state(t[0], t[1], t[2], t[3], t[3])
+    dt = 1e-2
+    ok, its = NW.newton_step(cp, V, ne, np_, S, S, dt, max_newton=20, tol=1e-11)
+    assert ok
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-13, max_cycles=400, max_newton=20, newton_tol=1e-11)
+    rep = sol.step(m.Physics.of(ph), st, dt, sc)
+    assert rep.newton_its == its, (rep.newton_its, its)
+    tol = 1e-11 if prec_name == "FP64" else 1e-9
+    for tt, ref in zip(t[:3], (V, ne, np_)):
+        assert relmax(sol.download(tt), ref) <= tol
