@@ -205,6 +205,92 @@ def trace_summary(path, top=25):
             print("%-70s %-16s %-14s %9d %16.1f" % (name, grid, cn, c, v / c))
 
 
+def vcycle_bench(args, M, I):
+    """The scalar path: (1) one decoupled backward-Euler step at 65x65 (dt
+    1e-4): Poisson with n^k, then the SG electron and ion equations, each by
+    V(2,2) red-black cycles to relative residual 1e-10, timed beside the
+    oracle's same step on one host core; (2) V-cycle throughput: back-to-back
+    V(2,2) cycles on the assembled Poisson and electron operators at 257x257
+    and 1025x1025, for both smoothers, on one context and (1025x1025) on four
+    contexts in turn, whose working set exceeds the 256 MB Infinity Cache.
+    Algorithmic bytes of one FP64 V(2,2) cycle per fine node: 4 sweeps x 8
+    values + residual 8 + restriction 1.25 + prolongation 2.25 = 43.5 values
+    on the fine level, x 4/3 for the coarser levels = 58 values = 464 B."""
+    import numpy as np
+    import torch
+    import oracle as O
+    out_rows = {}
+    N = 64
+    z = I.z_cos(N)
+    ne0 = I.initial_density(N, N, 0)
+    S = I.source(N, N, z)
+    V0 = I.initial_potential(N, N, z, 0.0, 1.0)
+    phys = dict(I.PHYS)
+    sol = M.Solver(N, N, z, smoother=M.SMOOTH_RB)
+    sched = M.schedule(lin_rtol=1e-10, max_cycles=500)
+    tS = sol.upload(S)
+    times, cycles = [], None
+    for k in range(6):
+        t = [sol.upload(V0), sol.upload(ne0), sol.upload(ne0.copy())]
+        st = sol.state(t[0], t[1], t[2], tS, tS)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        rep = sol.step(M.Physics.of(phys), st, 1e-4, sched)
+        torch.cuda.synchronize()
+        if k:
+            times.append(time.time() - t0)
+        cycles = rep.vcycles
+    Vo, neo, npo = V0.copy(), ne0.copy(), ne0.copy()
+    t0 = time.time()
+    code, cyc, rr = O.step_decoupled(1.0, z, O.Phys(**phys), Vo, neo, npo, S, S, 1e-4, smoother=O.SMOOTH_RB,
+                                     rtol=1e-10)
+    t_or = time.time() - t0
+    out_rows["step_65"] = dict(gpu_ms_median=round(1e3 * float(np.median(times)), 3), vcycles=cycles,
+                               oracle_ms=round(1e3 * t_or, 1), oracle_cycles=list(cyc), oracle_cores=1)
+    log(out_rows["step_65"])
+    # V-cycle throughput
+    vrows = []
+    for N, nctx in ((256, 1), (1024, 1), (1024, 4)):
+        for smoother, sname in ((M.SMOOTH_RB, "red-black"), (M.SMOOTH_ZEBRA, "zebra")):
+            z = I.z_cos(N)
+            ctxs = []
+            for c in range(nctx):
+                s = M.Solver(N, N, z, smoother=smoother)
+                ne = I.initial_density(N, N, c)
+                t = [s.upload(I.initial_potential(N, N, z, 0.0, 1.0)), s.upload(ne), s.upload(ne.copy()),
+                     s.upload(I.source(N, N, z))]
+                st = s.state(t[0], t[1], t[2], t[3], t[3])
+                for eq in (0, 1):
+                    s.assemble(eq, M.Physics.of(phys), st, 1e-4)
+                ctxs.append((s, [s.field(), s.field()], t))
+            for eq, ename in ((0, "poisson"), (1, "electron")):
+                for s, xs, _ in ctxs:
+                    s.vcycle(eq, xs[eq], 2)
+                torch.cuda.synchronize()
+                reps = 20
+                t0 = time.time()
+                for r in range(reps):
+                    for s, xs, _ in ctxs:
+                        s.vcycle(eq, xs[eq], 1)
+                torch.cuda.synchronize()
+                per = (time.time() - t0) / (reps * nctx)
+                nodes = (N + 1) * (N + 1)
+                gbs = 464.0 * nodes / per / 1e9
+                vrows.append(dict(grid="%dx%d" % (N + 1, N + 1), contexts=nctx, smoother=sname, eq=ename,
+                                  ms_per_cycle=round(per * 1e3, 4), algorithmic_GBps=round(gbs, 1),
+                                  frac_of_8TBps=round(gbs / HBM_PEAK_GBS, 3)))
+                log(vrows[-1])
+            del ctxs
+            torch.cuda.empty_cache()
+    out = {"metric": METRIC, "value": out_rows["step_65"]["gpu_ms_median"] / 1e3, "unit": "s", "n_gpus": 1,
+           "steps": 5, "warmup": 1, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "decoupled BE step at 65x65 (dt 1e-4, V(2,2) red-black to 1e-10 per equation) "
+                                  "and scalar V-cycle throughput at 257x257 and 1025x1025",
+                      "step_65": out_rows["step_65"], "vcycle": vrows}}
+    print(json.dumps(out), flush=True)
+
+
 def compare_precisions(args, M, I, N, vtops):
     """Time-to-steady of the finest stage with the FP64 and the FP32 block
     preconditioner (Newton residuals, FGMRES and the stop rules in FP64), from
@@ -418,6 +504,7 @@ def main():
     ap.add_argument("--criterion", choices=["run", "newton", "residual"], default="run",
                     help="fallback test of the learned warm start")
     ap.add_argument("--roofline-only", action="store_true", help="only the roofline timing (+ copy calibration)")
+    ap.add_argument("--vcycle", action="store_true", help="scalar path: 65x65 decoupled step and V-cycle GB/s")
     ap.add_argument("--reps", type=int, default=200, help="timed half-sweeps of the roofline measurement")
     ap.add_argument("--trace-summary", type=str, default="", help="summarise a rocprofv3 CSV and exit")
     ap.add_argument("--prec", choices=["fp64", "fp32", "both"], default="fp64",
@@ -436,6 +523,8 @@ def main():
 
     if args.roofline_only:
         return roofline_only(args, M, I)
+    if args.vcycle:
+        return vcycle_bench(args, M, I)
     if args.sweep_ref:
         return sweep_reference(args, M, I)
     if args.sweep:

@@ -125,10 +125,12 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
             }
         }
         L.x = cv.take<double>(nf);
+        L.x2 = cv.take<double>(nf);
         L.r = cv.take<double>(nf);
         L.vinj = cv.take<double>(nf);
         if (ir) {
             L.x32 = cv.take<float>(nf);
+            L.x2_32 = cv.take<float>(nf);
             L.r32 = cv.take<float>(nf);
         }
         if (l == nl - 1) {
@@ -232,10 +234,37 @@ template <>
 const float *cinv_of<float>(mg_ctx *c, int eq) { return c->lev[c->nlev - 1].cinv32[eq]; }
 
 template <class T>
-void smooth(mg_ctx *c, int l, int eq, T *x, int sweeps) {
+T *x2_of(mg_ctx *c, int l);
+template <>
+double *x2_of<double>(mg_ctx *c, int l) { return c->lev[l].x2; }
+template <>
+float *x2_of<float>(mg_ctx *c, int l) { return c->lev[l].x2_32; }
+
+// Red-black sweeps in one launch each (with the fused residual-restriction,
+// zero-guess first sweep, prolongation on read and the LDS coarse sub-cycle).
+bool fused_rb(const mg_ctx *c) { return c->nw.rb_fused && c->desc.smoother == MG_SMOOTH_RB; }
+
+// `sweeps` sweeps on level l: pairs of one-launch sweeps x -> x2 -> x, then
+// half-sweeps (or zebra sweeps) for the rest.  x_zero: x is zero on entry and
+// is not read; xc: the coarse correction (level l+1) still to be prolonged
+// and added, which the first one-launch sweep does while staging its input.
+// Callers set x_zero or xc only when fused_rb(c) and sweeps >= 2.
+template <class T>
+void smooth(mg_ctx *c, int l, int eq, T *x, int sweeps, bool x_zero = false, const T *xc = nullptr) {
     const Geom &g = c->lev[l].g;
     Op<T> op = op_of<T>(c, l, eq);
-    for (int s = 0; s < sweeps; ++s)
+    int k = 0;
+    if (fused_rb(c) && sweeps >= 2) {
+        T *x2 = x2_of<T>(c, l);
+        const Geom *gc = xc ? &c->lev[l + 1].g : nullptr;
+        for (; k + 2 <= sweeps; k += 2) {
+            const bool first = k == 0;
+            launch_rb_sweep<T>(g, op, x, x2, x_zero && first, first ? gc : nullptr, first ? xc : nullptr,
+                               c->stream);
+            launch_rb_sweep<T>(g, op, x2, x, false, nullptr, nullptr, c->stream);
+        }
+    }
+    for (; k < sweeps; ++k)
         for (int col = 0; col < 2; ++col) {
             if (c->desc.smoother == MG_SMOOTH_RB)
                 launch_rbgs<T>(g, op, x, col, c->stream);
@@ -244,7 +273,11 @@ void smooth(mg_ctx *c, int l, int eq, T *x, int sweeps) {
         }
 }
 
-// V(nu1, nu2) on level l for the field x (level l layout).
+// Largest level (nr, nz) of the scalar coarse sub-cycle (LDS capacity).
+constexpr int kFuseMaxS = 32;
+
+// V(nu1, nu2) on level l for the field x (level l layout).  On levels l >= 1
+// x is a correction that starts from zero (x is not read on entry).
 template <class T>
 void vcycle_level(mg_ctx *c, int l, int eq, T *x) {
     hipStream_t s = c->stream;
@@ -253,17 +286,41 @@ void vcycle_level(mg_ctx *c, int l, int eq, T *x) {
         launch_coarse_solve<T>(L.g, op_of<T>(c, l, eq), cinv_of<T>(c, eq), x, s);
         return;
     }
-    smooth<T>(c, l, eq, x, c->desc.nu1);
-    T *r = r_of<T>(c, l);
-    launch_residual<T, T, T>(L.g, op_of<T>(c, l, eq), nullptr, x, r, nullptr, nullptr, s);
+    if (l >= 1 && fused_rb(c) && c->nw.fuse && c->nlev - l <= kMaxFusedS && L.g.nr <= kFuseMaxS &&
+        L.g.nz <= kFuseMaxS) {
+        FusedScalar<T> F;
+        memset(&F, 0, sizeof F);
+        F.n = c->nlev - l;
+        F.nu1 = c->desc.nu1;
+        F.nu2 = c->desc.nu2;
+        for (int q = 0; q < F.n; ++q) {
+            F.g[q] = c->lev[l + q].g;
+            F.op[q] = op_of<T>(c, l + q, eq);
+        }
+        F.invT = cinv_of<T>(c, eq);
+        F.x0 = x;
+        if (launch_subcycle_s<T>(F, s)) return;
+    }
+    const bool zero_sweep = l >= 1 && fused_rb(c) && c->desc.nu1 >= 2;
+    if (l >= 1 && !zero_sweep) launch_fill(x, (int64_t)(L.g.nr + 1) * L.g.pitch, T(0), s);
+    smooth<T>(c, l, eq, x, c->desc.nu1, zero_sweep);
     const Level &C = c->lev[l + 1];
     Op<T> oc = op_of<T>(c, l + 1, eq);
-    launch_restrict<T>(L.g, r, C.g, oc.f, s);
+    if (fused_rb(c)) {
+        launch_residual_restrict_s<T>(L.g, op_of<T>(c, l, eq), x, C.g, oc.f, s);
+    } else {
+        T *r = r_of<T>(c, l);
+        launch_residual<T, T, T>(L.g, op_of<T>(c, l, eq), nullptr, x, r, nullptr, nullptr, s);
+        launch_restrict<T>(L.g, r, C.g, oc.f, s);
+    }
     T *xc = x_of<T>(c, l + 1);
-    launch_fill(xc, (int64_t)(C.g.nr + 1) * C.g.pitch, T(0), s);
     vcycle_level<T>(c, l + 1, eq, xc);
-    launch_prolong<T>(L.g, x, C.g, xc, s);
-    smooth<T>(c, l, eq, x, c->desc.nu2);
+    if (fused_rb(c) && c->desc.nu2 >= 2) {
+        smooth<T>(c, l, eq, x, c->desc.nu2, false, xc);
+    } else {
+        launch_prolong<T>(L.g, x, C.g, xc, s);
+        smooth<T>(c, l, eq, x, c->desc.nu2);
+    }
 }
 
 // Strong-form relative residual of the FP64 system (synchronises).

@@ -41,7 +41,8 @@ struct Level {
     Op<double> op[3];
     Op<float> op32[3];
     double *x, *r, *vinj;
-    float *x32, *r32;
+    double *x2;        // partner of the level's field for one-launch sweeps
+    float *x32, *r32, *x2_32;
     double *cinv[3];   // coarsest level only: transposed inverse, n x n
     float *cinv32[3];
     int ncoarse;       // unknowns on the coarsest level
@@ -128,6 +129,27 @@ void launch_coarse_factor(const Geom &g, Op<double> op, double *scratch, double 
                           hipStream_t s);
 template <class T>
 void launch_coarse_solve(const Geom &g, Op<T> op, const T *invT, T *x, hipStream_t s);
+// One full red-black sweep xin -> xout (xout a whole field); zin: input zero;
+// gc/xc: input is xin plus the prolongation of the coarse correction xc.
+template <class T>
+void launch_rb_sweep(const Geom &g, Op<T> op, const T *xin, T *xout, bool zin, const Geom *gc, const T *xc,
+                     hipStream_t s);
+// Coarse right-hand side fc = R (f - A x) in one launch.
+template <class T>
+void launch_residual_restrict_s(const Geom &gf, Op<T> op, const T *x, const Geom &gc, T *fc, hipStream_t s);
+// Levels of the coarse end of the scalar V-cycle run by one workgroup.
+constexpr int kMaxFusedS = 8;
+template <class T>
+struct FusedScalar {
+    int n, nu1, nu2;
+    Geom g[kMaxFusedS];
+    Op<T> op[kMaxFusedS];
+    const T *invT;
+    T *x0;
+};
+// Returns false (nothing launched) when the levels do not fit in LDS.
+template <class T>
+bool launch_subcycle_s(const FusedScalar<T> &F, hipStream_t s);
 void launch_sum_partials(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s,
                          const Batch &bt = Batch());
 void launch_diff_norms(const Geom &g, const double *a, const double *b, double *partials,

@@ -164,6 +164,30 @@ __global__ void k_fill(T *p, int64_t n, T v, Batch bt) {
 // Nodes of one colour only read nodes of the other colour, so the order of
 // updates inside a half-sweep does not matter.
 // ---------------------------------------------------------------------------
+// The five coefficients and right-hand side of one node, in registers.
+template <class T>
+struct SRow {
+    T a, b, c, d, e, f;
+};
+template <class T>
+inline __device__ void load_srow(const Op<T> &op, int64_t p, SRow<T> &R) {
+    R.a = op.a[p];
+    R.b = op.b[p];
+    R.c = op.c[p];
+    R.d = op.d[p];
+    R.e = op.e[p];
+    R.f = op.f[p];
+}
+// Gauss-Seidel value of one node; xnb(t): neighbour t (0: i-1, 1: i+1,
+// 2: j-1, 3: j+1).
+template <class T, class XNb>
+inline __device__ T solve_srow(const SRow<T> &R, bool has_im, bool has_ip, XNb xnb) {
+    T s = R.f - R.d * xnb(2) - R.e * xnb(3);
+    if (has_im) s -= R.a * xnb(0);
+    if (has_ip) s -= R.c * xnb(1);
+    return s / R.b;
+}
+
 template <class T>
 __global__ void k_rbgs(Geom g, Op<T> op, T *__restrict__ x, int colour) {
     int j = blockIdx.x * kTX + threadIdx.x;
@@ -171,10 +195,10 @@ __global__ void k_rbgs(Geom g, Op<T> op, T *__restrict__ x, int colour) {
     if (i > g.nr || j < 1 || j >= g.nz) return;
     if (((i + j) & 1) != colour) return;
     int64_t p = at(g, i, j);
-    T s = op.f[p] - op.d[p] * x[p - 1] - op.e[p] * x[p + 1];
-    if (i > 0) s -= op.a[p] * x[p - g.pitch];
-    if (i < g.nr) s -= op.c[p] * x[p + g.pitch];
-    x[p] = s / op.b[p];
+    SRow<T> R;
+    load_srow(op, p, R);
+    const int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
+    x[p] = solve_srow(R, i > 0, i < g.nr, [&](int t) { return x[nbp[t]]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -482,10 +506,7 @@ __global__ void k_restrict(Geom gf, const T *__restrict__ rf, Geom gc, T *__rest
 
 // Bilinear prolongation of the coarse correction, added on fine unknowns.
 template <class T>
-__global__ void k_prolong(Geom gf, T *__restrict__ xf, Geom gc, const T *__restrict__ xc) {
-    int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i > gf.nr || j < 1 || j >= gf.nz) return;
+inline __device__ T prolong_s(const Geom &gf, const Geom &gc, const T *xc, int i, int j) {
     int I0 = i >> 1, I1 = (i + 1) >> 1;
     T v0, v1;
     if ((j & 1) == 0) {
@@ -498,8 +519,292 @@ __global__ void k_prolong(Geom gf, T *__restrict__ xf, Geom gc, const T *__restr
         v0 = wl * xc[at(gc, I0, J)] + wu * xc[at(gc, I0, J + 1)];
         v1 = wl * xc[at(gc, I1, J)] + wu * xc[at(gc, I1, J + 1)];
     }
-    T v = (i & 1) ? T(0.5) * (v0 + v1) : v0;
-    xf[at(gf, i, j)] += v;
+    return (i & 1) ? T(0.5) * (v0 + v1) : v0;
+}
+
+template <class T>
+__global__ void k_prolong(Geom gf, T *__restrict__ xf, Geom gc, const T *__restrict__ xc) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > gf.nr || j < 1 || j >= gf.nz) return;
+    T v = xf[at(gf, i, j)];
+    v += prolong_s(gf, gc, xc, i, j);
+    xf[at(gf, i, j)] = v;
+}
+
+// ---------------------------------------------------------------------------
+// One full red-black sweep in one launch (scalar operator), from the input to
+// xout (distinct buffers).  The input is xin, or zero (zin != 0, xin not
+// read), or xin plus the bilinear prolongation of the coarse correction xc
+// (xc != nullptr).  A workgroup owns a kSWs x SH tile and ring threads; the
+// input over the tile and a 2-node ring is staged in LDS, every thread holds
+// its node's coefficients in registers, the colour-0 nodes of tile and
+// 1-node ring are updated into LDS, then the tile's colour-1 nodes.  The
+// electrode rows of the tile are copied from the input, so xout is a whole
+// field.  Values equal two k_rbgs launches (after k_prolong).
+// ---------------------------------------------------------------------------
+constexpr int kSWs = 32;
+template <int SH>
+struct STile {
+    static constexpr int kSR = (2 * kSWs + 2 * SH + kSWs - 1) / kSWs;
+};
+template <class T, int SH>
+__global__ __launch_bounds__(kSWs *(SH + STile<SH>::kSR)) void k_rb_sweep_s(Geom g, Op<T> op,
+                                                                           const T *__restrict__ xin,
+                                                                           T *__restrict__ xout, int zin, Geom gc,
+                                                                           const T *__restrict__ xc) {
+    constexpr int kSH = SH, kSR = STile<SH>::kSR;
+    constexpr int W = kSWs + 2, W2 = kSWs + 4;
+    __shared__ T lx[(kSH + 2) * W];
+    __shared__ T lin[(kSH + 4) * W2];
+    const int i0 = blockIdx.y * kSH, j0 = blockIdx.x * kSWs;
+    const int ti = threadIdx.y, tj = threadIdx.x, tid = ti * kSWs + tj;
+    for (int t = tid; t < (kSH + 4) * W2; t += kSWs * (kSH + kSR)) {
+        const int ii = i0 - 2 + t / W2, jj = j0 - 2 + t % W2;
+        if (ii < 0 || ii > g.nr || jj < 0 || jj > g.nz) continue;
+        T v = zin ? T(0) : xin[at(g, ii, jj)];
+        if (xc && jj >= 1 && jj < g.nz) v += prolong_s(g, gc, xc, ii, jj);
+        lin[t] = v;
+    }
+    int ni, nj;
+    if (ti < kSH) {
+        ni = i0 + ti;
+        nj = j0 + tj;
+    } else {
+        const int k = (ti - kSH) * kSWs + tj;
+        if (k < kSWs) {
+            ni = i0 - 1;
+            nj = j0 + k;
+        } else if (k < 2 * kSWs) {
+            ni = i0 + kSH;
+            nj = j0 + k - kSWs;
+        } else if (k < 2 * kSWs + kSH) {
+            ni = i0 + k - 2 * kSWs;
+            nj = j0 - 1;
+        } else if (k < 2 * kSWs + 2 * kSH) {
+            ni = i0 + k - 2 * kSWs - kSH;
+            nj = j0 + kSWs;
+        } else {
+            ni = -1;  // spare ring thread
+            nj = 0;
+        }
+    }
+    const bool tile = ti < kSH;
+    const bool valid = ni >= 0 && ni <= g.nr && nj >= 1 && nj < g.nz;
+    const bool red = ((ni + nj) & 1) == 0;
+    const int64_t p = at(g, ni, nj);
+    SRow<T> R;
+    if (valid && (tile || red)) load_srow(op, p, R);
+    __syncthreads();
+    auto in_at = [&](int ii, int jj) { return lin[(ii - i0 + 2) * W2 + (jj - j0 + 2)]; };
+    const int dni[4] = {-1, 1, 0, 0}, dnj[4] = {0, 0, -1, 1};
+    if (tile && ni <= g.nr && (nj == 0 || nj == g.nz)) xout[p] = in_at(ni, nj);  // electrode rows
+    if (valid && red) {
+        const T v = solve_srow(R, ni > 0, ni < g.nr, [&](int t) { return in_at(ni + dni[t], nj + dnj[t]); });
+        lx[(ni - i0 + 1) * W + (nj - j0 + 1)] = v;
+        if (tile) xout[p] = v;
+    }
+    __syncthreads();
+    if (!tile || !valid || red) return;
+    const bool fixed[4] = {false, false, nj - 1 == 0, nj + 1 == g.nz};
+    xout[p] = solve_srow(R, ni > 0, ni < g.nr, [&](int t) {
+        const int ii = ni + dni[t], jj = nj + dnj[t];
+        return fixed[t] ? in_at(ii, jj) : lx[(ii - i0 + 1) * W + (jj - j0 + 1)];
+    });
+}
+
+// Fine residual (as k_residual: FP64 arithmetic, stored as T) at node (i, j).
+template <class T>
+inline __device__ T residual_s(const Geom &g, const Op<T> &op, const T *x, int i, int j) {
+    const int64_t p = at(g, i, j);
+    double f = (double)op.f[p];
+    double xd = (double)x[p - 1], xu = (double)x[p + 1];
+    double ax = (double)op.b[p] * (double)x[p] + (double)op.d[p] * xd + (double)op.e[p] * xu;
+    if (i > 0) ax += (double)op.a[p] * (double)x[p - g.pitch];
+    if (i < g.nr) ax += (double)op.c[p] * (double)x[p + g.pitch];
+    return (T)(f - ax);
+}
+
+// Restriction of a fine residual held in LDS (window origin fi0, fj0, row
+// length FW) to coarse node (I, J), as k_restrict.
+template <class T>
+inline __device__ T restrict_s(const Geom &gf, const Geom &gc, const T *lr, int fi0, int fj0, int FW, int I, int J) {
+    if (J == 0 || J == gc.nz) return T(0);
+    T wdn = T(1) - (T)gf.wl[J - 1];
+    T wup = (T)gf.wl[J];
+    T acc = 0;
+    for (int di = -1; di <= 1; ++di) {
+        int i = 2 * I + di;
+        if (i < 0 || i > gf.nr) continue;
+        T wi = (di == 0) ? T(1) : T(0.5);
+        const int l = (i - fi0) * FW + (2 * J - fj0);
+        acc += wi * (wdn * lr[l - 1] + lr[l] + wup * lr[l + 1]);
+    }
+    return acc;
+}
+
+// Residual and restriction in one launch: coarse tile kCWs x kCHs, fine
+// window (2 kCHs + 1) x (2 kCWs + 1) of residuals in LDS, one fine node per
+// thread of a 64 x 10 workgroup.  Values equal k_residual + k_restrict.
+constexpr int kCWs = 32, kCHs = 4;
+static_assert((2 * kCWs + 1) * (2 * kCHs + 1) <= 64 * 10, "one fine node per thread");
+template <class T>
+__global__ __launch_bounds__(640) void k_residual_restrict_s(Geom gf, Op<T> op, const T *__restrict__ x, Geom gc,
+                                                             T *__restrict__ fc) {
+    constexpr int FW = 2 * kCWs + 1, FH = 2 * kCHs + 1;
+    __shared__ T lr[FH * FW];
+    const int I0 = blockIdx.y * kCHs, J0 = blockIdx.x * kCWs;
+    const int fi0 = 2 * I0 - 1, fj0 = 2 * J0 - 1;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    if (tid < FH * FW) {
+        const int i = fi0 + tid / FW, j = fj0 + tid % FW;
+        if (i >= 0 && i <= gf.nr && j >= 0 && j <= gf.nz)
+            lr[tid] = (j == 0 || j == gf.nz) ? T(0) : residual_s(gf, op, x, i, j);
+    }
+    __syncthreads();
+    if (tid >= kCWs * kCHs) return;
+    const int I = I0 + tid / kCWs, J = J0 + tid % kCWs;
+    if (I > gc.nr || J > gc.nz) return;
+    fc[at(gc, I, J)] = restrict_s(gf, gc, lr, fi0, fj0, FW, I, J);
+}
+
+// ---------------------------------------------------------------------------
+// The coarse end of the scalar V-cycle (levels 0..n-1 of F, the last the
+// coarsest) in one workgroup, every level's coefficients, right-hand side,
+// correction and residual staged in LDS (compact, pitch nz+1); the top
+// level's correction is written back.  Node by node the arithmetic of the
+// per-level kernels (red-black half-sweeps, residual, restriction, explicit
+// coarsest inverse, prolongation).  Corrections start from zero.
+// ---------------------------------------------------------------------------
+constexpr int kSubPoolS = 15360;
+template <class T>
+__global__ __launch_bounds__(1024) void k_subcycle_s(FusedScalar<T> F) {
+    __shared__ T pool[kSubPoolS];
+    __shared__ T rhs[kMaxCoarseUnknowns];
+    const int n = F.n, nt = blockDim.x;
+    auto nodes = [&](int q) { return (F.g[q].nr + 1) * (F.g[q].nz + 1); };
+    auto off = [&](int q) {
+        int o = 0;
+        for (int t = 0; t < q; ++t) o += 8 * nodes(t);
+        return o;
+    };
+    auto geom = [&](int q) {
+        Geom g = F.g[q];
+        g.pitch = g.nz + 1;
+        return g;
+    };
+    auto opq = [&](int q) {
+        T *b = pool + off(q);
+        const int nn = nodes(q);
+        return Op<T>{b, b + nn, b + 2 * nn, b + 3 * nn, b + 4 * nn, b + 5 * nn};
+    };
+    auto xq = [&](int q) { return pool + off(q) + 6 * nodes(q); };
+    auto rq = [&](int q) { return pool + off(q) + 7 * nodes(q); };
+    // stage coefficients and right-hand sides; zero the corrections
+    for (int q = 0; q < n; ++q) {
+        const Geom &gg = F.g[q];
+        const int w = gg.nz + 1, nn = nodes(q);
+        const Op<T> &src = F.op[q];
+        const T *arr[6] = {src.a, src.b, src.c, src.d, src.e, src.f};
+        T *dst = pool + off(q);
+        for (int t = threadIdx.x; t < 6 * nn; t += nt) {
+            const int k = t / nn, node = t % nn;
+            dst[t] = arr[k][(int64_t)(node / w) * gg.pitch + node % w];
+        }
+        T *x = xq(q);
+        for (int t = threadIdx.x; t < nn; t += nt) x[t] = T(0);
+    }
+    __syncthreads();
+    for (int q = 0; q < n - 1; ++q) {
+        const Geom g = geom(q);
+        const Op<T> op = opq(q);
+        T *x = xq(q);
+        T *r = rq(q);
+        const int nn = nodes(q);
+        for (int s = 0; s < F.nu1; ++s)
+            for (int col = 0; col < 2; ++col) {
+                for (int t = threadIdx.x; t < nn; t += nt) {
+                    const int i = t / (g.nz + 1), j = t % (g.nz + 1);
+                    if (j < 1 || j >= g.nz || ((i + j) & 1) != col) continue;
+                    const int64_t p = at(g, i, j);
+                    SRow<T> R;
+                    load_srow(op, p, R);
+                    const int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
+                    x[p] = solve_srow(R, i > 0, i < g.nr, [&](int k) { return x[nbp[k]]; });
+                }
+                __syncthreads();
+            }
+        for (int t = threadIdx.x; t < nn; t += nt) {
+            const int i = t / (g.nz + 1), j = t % (g.nz + 1);
+            r[t] = (j == 0 || j == g.nz) ? T(0) : residual_s(g, op, x, i, j);
+        }
+        __syncthreads();
+        const Geom gc = geom(q + 1);
+        const Op<T> oc = opq(q + 1);
+        for (int t = threadIdx.x; t < nodes(q + 1); t += nt) {
+            const int I = t / (gc.nz + 1), J = t % (gc.nz + 1);
+            // the fine residual window is the whole level: origin (0, 0), row length nz + 1
+            oc.f[t] = (J == 0 || J == gc.nz) ? T(0) : restrict_s(g, gc, r, 0, 0, g.nz + 1, I, J);
+        }
+        __syncthreads();
+    }
+    {
+        // coarsest level: x = A^{-1} f (electrode terms with the zero correction)
+        const int q = n - 1;
+        const Geom g = geom(q);
+        const Op<T> op = opq(q);
+        T *x = xq(q);
+        const int m = g.nz - 1, nc = (g.nr + 1) * m;
+        for (int row = threadIdx.x; row < nc; row += nt) {
+            const int i = row / m, j = row % m + 1;
+            const int64_t p = at(g, i, j);
+            T v = op.f[p];
+            if (j == 1) v -= op.d[p] * x[p - 1];
+            if (j == m) v -= op.e[p] * x[p + 1];
+            rhs[row] = v;
+        }
+        __syncthreads();
+        for (int row = threadIdx.x; row < nc; row += nt) {
+            T acc = 0;
+            for (int k = 0; k < nc; ++k) acc += F.invT[(int64_t)k * nc + row] * rhs[k];
+            const int i = row / m, j = row % m + 1;
+            x[at(g, i, j)] = acc;
+        }
+        __syncthreads();
+    }
+    for (int q = n - 2; q >= 0; --q) {
+        const Geom g = geom(q), gc = geom(q + 1);
+        const Op<T> op = opq(q);
+        T *x = xq(q);
+        const T *xcq = xq(q + 1);
+        const int nn = nodes(q);
+        for (int t = threadIdx.x; t < nn; t += nt) {
+            const int i = t / (g.nz + 1), j = t % (g.nz + 1);
+            if (j < 1 || j >= g.nz) continue;
+            T v = x[t];
+            v += prolong_s(g, gc, xcq, i, j);
+            x[t] = v;
+        }
+        __syncthreads();
+        for (int s = 0; s < F.nu2; ++s)
+            for (int col = 0; col < 2; ++col) {
+                for (int t = threadIdx.x; t < nn; t += nt) {
+                    const int i = t / (g.nz + 1), j = t % (g.nz + 1);
+                    if (j < 1 || j >= g.nz || ((i + j) & 1) != col) continue;
+                    const int64_t p = at(g, i, j);
+                    SRow<T> R;
+                    load_srow(op, p, R);
+                    const int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
+                    x[p] = solve_srow(R, i > 0, i < g.nr, [&](int k) { return x[nbp[k]]; });
+                }
+                __syncthreads();
+            }
+    }
+    // the top level's correction back to its field (whole field, electrode rows zero)
+    const Geom &g0 = F.g[0];
+    const int w = g0.nz + 1, nn = nodes(0);
+    const T *x0 = xq(0);
+    for (int t = threadIdx.x; t < nn; t += nt) F.x0[(int64_t)(t / w) * g0.pitch + t % w] = x0[t];
 }
 
 // Full-field bilinear interpolation (used for the multilevel prolongation of
@@ -803,6 +1108,35 @@ void launch_restrict(const Geom &gf, const T *rf, const Geom &gc, T *fc, hipStre
 }
 
 template <class T>
+void launch_rb_sweep(const Geom &g, Op<T> op, const T *xin, T *xout, bool zin, const Geom *gc, const T *xc,
+                     hipStream_t s) {
+    const Geom &gcc = gc ? *gc : g;
+    if (g.sh == 16) {
+        dim3 grid((g.nz + 1 + kSWs - 1) / kSWs, (g.nr + 1 + 15) / 16);
+        k_rb_sweep_s<T, 16><<<grid, dim3(kSWs, 16 + STile<16>::kSR), 0, s>>>(g, op, xin, xout, zin ? 1 : 0, gcc, xc);
+    } else {
+        dim3 grid((g.nz + 1 + kSWs - 1) / kSWs, (g.nr + 1 + 7) / 8);
+        k_rb_sweep_s<T, 8><<<grid, dim3(kSWs, 8 + STile<8>::kSR), 0, s>>>(g, op, xin, xout, zin ? 1 : 0, gcc, xc);
+    }
+}
+
+template <class T>
+void launch_residual_restrict_s(const Geom &gf, Op<T> op, const T *x, const Geom &gc, T *fc, hipStream_t s) {
+    dim3 grid((gc.nz + 1 + kCWs - 1) / kCWs, (gc.nr + 1 + kCHs - 1) / kCHs);
+    k_residual_restrict_s<T><<<grid, dim3(64, 10), 0, s>>>(gf, op, x, gc, fc);
+}
+
+template <class T>
+bool launch_subcycle_s(const FusedScalar<T> &F, hipStream_t s) {
+    int64_t need = 0;
+    for (int q = 0; q < F.n; ++q) need += 8 * (int64_t)(F.g[q].nr + 1) * (F.g[q].nz + 1);
+    const Geom &gl = F.g[F.n - 1];
+    if (need > kSubPoolS || (int64_t)(gl.nr + 1) * (gl.nz - 1) > kMaxCoarseUnknowns) return false;
+    k_subcycle_s<T><<<1, 1024, 0, s>>>(F);
+    return true;
+}
+
+template <class T>
 void launch_prolong(const Geom &gf, T *xf, const Geom &gc, const T *xc, hipStream_t s) {
     k_prolong<T><<<grid2d(gf), blk2d(gf), 0, s>>>(gf, xf, gc, xc);
 }
@@ -868,6 +1202,16 @@ template void launch_residual<float, float, float>(const Geom &, Op<float>, cons
 template void launch_restrict<double>(const Geom &, const double *, const Geom &, double *, hipStream_t);
 template void launch_restrict<float>(const Geom &, const float *, const Geom &, float *, hipStream_t);
 template void launch_prolong<double>(const Geom &, double *, const Geom &, const double *, hipStream_t);
+template void launch_rb_sweep<double>(const Geom &, Op<double>, const double *, double *, bool, const Geom *,
+                                      const double *, hipStream_t);
+template void launch_rb_sweep<float>(const Geom &, Op<float>, const float *, float *, bool, const Geom *,
+                                     const float *, hipStream_t);
+template void launch_residual_restrict_s<double>(const Geom &, Op<double>, const double *, const Geom &, double *,
+                                                 hipStream_t);
+template void launch_residual_restrict_s<float>(const Geom &, Op<float>, const float *, const Geom &, float *,
+                                                hipStream_t);
+template bool launch_subcycle_s<double>(const FusedScalar<double> &, hipStream_t);
+template bool launch_subcycle_s<float>(const FusedScalar<float> &, hipStream_t);
 template void launch_prolong<float>(const Geom &, float *, const Geom &, const float *, hipStream_t);
 template void launch_coarse_solve<double>(const Geom &, Op<double>, const double *, double *, hipStream_t);
 template void launch_coarse_solve<float>(const Geom &, Op<float>, const float *, float *, hipStream_t);

@@ -208,3 +208,34 @@ def test_small_grids_direct_and_dense(N, coarsest):
     O.direct_solve(mg.coef(0), ref)
     cyc, rr = sol.solve(1, tne, rtol=1e-14, max_cycles=60)
     assert relmax(sol.download(tne), ref) <= TOL
+
+
+@pytest.mark.parametrize("name,eq", EQS)
+@pytest.mark.parametrize("nr,nz,prec", [(64, 64, 0), (256, 256, 0), (128, 32, 0), (128, 128, 1)])
+def test_fused_scalar_vcycle_matches_half_sweeps(name, eq, nr, nz, prec, monkeypatch):
+    """Red-black V(2,2) cycles built from one-launch sweeps (zero-guess first
+    sweep, prolongation on read, residual + restriction in one launch, the
+    coarse levels in one workgroup staged in LDS) give bitwise the iterates
+    of the per-step launches (half-sweeps, residual, restriction, fill,
+    prolongation, per-level coarse end), in FP64 and in FP32 refinement."""
+    m = M()
+    _say("fused scalar vcycle", name, nr, nz, prec)
+    z, V, ne, np_, S, phys = _problem(nr, nz, seed=4, vtop=1.0, pert=0.02)
+    out = {}
+    for half in (1, 0):
+        if half:
+            monkeypatch.setenv("MGF_HALF_SWEEPS", "1")
+        else:
+            monkeypatch.delenv("MGF_HALF_SWEEPS", raising=False)
+        sol = m.Solver(nr, nz, z, smoother=0, prec=prec)
+        tV, tne, tnp, tS = sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)
+        st = sol.state(tV, tne, tnp, tS, tS)
+        sol.assemble(eq, m.Physics.of(phys), st, 1e-3)
+        x = (tV, tne, tnp)[eq].clone()
+        its = []
+        for k in range(4):
+            sol.vcycle(eq, x, 1)
+            its.append(sol.download(x))
+        out[half] = its
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
