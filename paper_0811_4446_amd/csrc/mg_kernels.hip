@@ -890,14 +890,15 @@ __global__ __launch_bounds__(256) void k_coarse_factor(Geom g, Op<double> op, do
 
 // Same factorisation with the augmented matrix resident in LDS (n <= 63).
 constexpr int kLdsGJ = 63;
-__global__ __launch_bounds__(256) void k_coarse_factor_lds(Geom g, Op<double> op, double *__restrict__ invT,
-                                                            float *__restrict__ invT32) {
+__global__ __launch_bounds__(1024) void k_coarse_factor_lds(Geom g, Op<double> op, double *__restrict__ invT,
+                                                             float *__restrict__ invT32) {
     const int m = g.nz - 1;
     const int n = (g.nr + 1) * m;
     const int n2 = 2 * n;
-    __shared__ double M[kLdsGJ * 2 * kLdsGJ];
-    __shared__ double fcol[kLdsGJ];
+    // two copies of the augmented matrix: column step k reads one, writes the other
+    __shared__ double Mb[2][kLdsGJ * 2 * kLdsGJ];
     __shared__ int piv;
+    double *M = Mb[0];
     for (int t = threadIdx.x; t < n * n2; t += blockDim.x) M[t] = 0.0;
     __syncthreads();
     for (int row = threadIdx.x; row < n; row += blockDim.x) {
@@ -912,30 +913,45 @@ __global__ __launch_bounds__(256) void k_coarse_factor_lds(Geom g, Op<double> op
         Mr[n + row] = 1.0;
     }
     __syncthreads();
+    // Gauss-Jordan with partial pivoting, two barriers per column: the pivot
+    // search, then every element of the next copy in one pass (scaled pivot
+    // row, exchanged row, other rows eliminated against the scaled pivot row).
+    constexpr int kPer = (kLdsGJ * 2 * kLdsGJ + 1023) / 1024;
+    const int total = n * n2;
+    int cur = 0;
     for (int col = 0; col < n; ++col) {
-        pivot_search_wave0(M, n2, col, n, &piv);
+        const double *A = Mb[cur];
+        double *B = Mb[cur ^ 1];
+        pivot_search_wave0(A, n2, col, n, &piv);
         __syncthreads();
         const int pv = piv;
-        if (pv != col)
-            for (int t = threadIdx.x; t < n2; t += blockDim.x) {
-                double tmp = M[col * n2 + t];
-                M[col * n2 + t] = M[pv * n2 + t];
-                M[pv * n2 + t] = tmp;
+        const double pinv = 1.0 / A[pv * n2 + col];
+        const double fpv = A[col * n2 + col];
+        double v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int t = threadIdx.x + k * 1024;
+            if (t >= total) break;
+            const int rr = t / n2, cc = t - rr * n2;
+            const double prc = A[pv * n2 + cc] * pinv;
+            if (rr == col) {
+                v[k] = prc;
+            } else {
+                const double src = (rr == pv) ? A[col * n2 + cc] : A[rr * n2 + cc];
+                const double fct = (rr == pv) ? fpv : A[rr * n2 + col];
+                v[k] = (fct != 0.0) ? src - fct * prc : src;
             }
-        __syncthreads();
-        const double pinv = 1.0 / M[col * n2 + col];
-        __syncthreads();
-        for (int t = threadIdx.x; t < n2; t += blockDim.x) M[col * n2 + t] *= pinv;
-        for (int rr = threadIdx.x; rr < n; rr += blockDim.x) fcol[rr] = M[rr * n2 + col];
-        __syncthreads();
-        for (int t = threadIdx.x; t < n * n2; t += blockDim.x) {
-            int rr = t / n2, cc = t % n2;
-            if (rr == col) continue;
-            double fct = fcol[rr];
-            if (fct != 0.0) M[rr * n2 + cc] -= fct * M[col * n2 + cc];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int t = threadIdx.x + k * 1024;
+            if (t >= total) break;
+            B[t] = v[k];
         }
         __syncthreads();
+        cur ^= 1;
     }
+    M = Mb[cur];
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
         int row = t / n, k = t % n;
         double v = M[row * n2 + n + k];
@@ -1149,7 +1165,7 @@ void launch_coarse_factor(const Geom &g, Op<double> op, double *scratch, double 
                           hipStream_t s) {
     int n = (g.nr + 1) * (g.nz - 1);
     if (n <= kLdsGJ)
-        k_coarse_factor_lds<<<1, 256, 0, s>>>(g, op, invT, invT32);
+        k_coarse_factor_lds<<<1, 1024, 0, s>>>(g, op, invT, invT32);
     else
         k_coarse_factor<<<1, 256, 0, s>>>(g, op, scratch, invT, invT32);
 }
