@@ -80,9 +80,6 @@ void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t 
 void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s,
                          const Batch &bt = Batch());
 void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s, const Batch &bt = Batch());
-void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
-                       int64_t plane, double3 cw, double *partials, double *out, hipStream_t s,
-                       const Batch &bt = Batch());
 // Gram-Schmidt pass: w = J z (if J and z) or w -= sum_v h_sub[v] basis_v
 // (if h_sub), then the partial sums of the weighted (w, basis_v), v < nv,
 // or of (w, w) when self_norm; with out != nullptr a second launch adds them

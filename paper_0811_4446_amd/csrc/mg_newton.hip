@@ -971,7 +971,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
     }
     if constexpr (kLds) {
         __syncthreads();
-        const Geom gg = geom_off(F.g[0], bo_), gl = geom(0);
+        const Geom gg = geom_off(F.g[0], bo_);
         T *dst = boff(F.x[0], bo_);
         const T *src = xof(0);
         const int w = gg.nz + 1, nn = (gg.nr + 1) * w;
@@ -979,48 +979,12 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
             const int k = t / nn, node = t % nn;
             dst[k * F.plane[0] + (int64_t)(node / w) * gg.pitch + node % w] = src[k * (int64_t)nn + node];
         }
-        (void)gl;
     }
 }
 
 // ---- FGMRES BLAS-1 (weighted inner product) ----
-// <u, v>_W = sum over unknown nodes and fields of u v (c_f / vol)^2.
-__global__ __launch_bounds__(1024) void k_wdot_multi(Geom g, const double *__restrict__ w,
-                                                     const double *__restrict__ basis, int64_t vstride, int nv,
-                                                     int64_t plane, double3 cw, double *__restrict__ partials,
-                                                     Batch bt) {
-    if (bt.active && !bt.active[blockIdx.z]) return;
-    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
-    g = geom_off(g, bo_);
-    w = boff(w, bo_);
-    basis = boff(basis, bo_);
-    partials = boff(partials, bo_);
-
-    int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * blockDim.y + threadIdx.y;
-    __shared__ double sh[kMaxTY][kMaxKrylov + 1];
-    bool ok = i <= g.nr && j >= 1 && j < g.nz;
-    int64_t p = ok ? at(g, i, j) : 0;
-    double iv = ok ? 1.0 / (g.wr[i] * g.dzc[j]) : 0.0;
-    double we = ok ? w[p] * cw.x * cw.x * iv * iv : 0.0;
-    double wp = ok ? w[p + plane] * cw.y * cw.y * iv * iv : 0.0;
-    double wv = ok ? w[p + 2 * plane] * cw.z * cw.z * iv * iv : 0.0;
-    for (int v = 0; v < nv; ++v) {
-        const double *b = basis + v * vstride;
-        double s = ok ? (we * b[p] + wp * b[p + plane] + wv * b[p + 2 * plane]) : 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
-    }
-    __syncthreads();
-    int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    int t = threadIdx.y * kTX + threadIdx.x;
-    if (t < nv) {
-        double s = 0.0;
-        for (int y = 0; y < (int)blockDim.y; ++y) s += sh[y][t];
-        partials[(int64_t)blk * nv + t] = s;
-    }
-}
+// <u, v>_W = sum over unknown nodes and fields of u v (c_f / vol)^2, with
+// c_f = 1 for the densities and 1/k for the Poisson rows.
 
 // One pass of classical Gram-Schmidt: w = B z (if z: the operator applied
 // to the new preconditioned direction), or w -= sum_v h_sub[v] basis_v (if
@@ -1361,12 +1325,6 @@ void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s, const Batch 
 int block_vec_blocks(const Geom &g) {
     dim3 gr = grid2d(g);
     return (int)(gr.x * gr.y);
-}
-void launch_wdot_multi(const Geom &g, const double *w, const double *basis, int64_t vstride, int nv,
-                       int64_t plane, double3 cw, double *partials, double *out, hipStream_t s, const Batch &bt) {
-    dim3 gr = grid2d(g);
-    k_wdot_multi<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, partials, bt);
-    k_sum_cols<<<dim3(nv, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nv, out, bt);
 }
 void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                      double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
