@@ -3,9 +3,9 @@
 // padding) that maps the prolonged coarse steady state (plus coordinate and
 // parameter planes) to a correction of it on the fine grid.  Forward and
 // input-gradient convolutions run on MFMA (v_mfma_f32_16x16x32_bf16: bf16
-// operands, FP32 accumulation) as implicit GEMMs; the weight gradient is an
-// FP32 reduction over pixels with deterministic partial sums; Adam keeps
-// FP32 master weights.
+// operands, FP32 accumulation) as implicit GEMMs, and so does the weight
+// gradient (a GEMM over pixels per tap, deterministic partial sums); Adam
+// keeps FP32 master weights.
 //
 // Activations are NHWC bf16 with 32 channel slots (H = radial nodes, W =
 // axial nodes, so a row is one radial line of the solver's fields).
@@ -162,61 +162,93 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out, cons
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// Weight and bias gradient of one layer:
-//   dW[co][ci][tap] = sum over pixels of dz[p][co] * a[p + tap offset][ci],
-//   db[co] = sum of dz[p][co].
-// Thread (tap, co) accumulates the 32 input channels over chunks of 32
-// pixels of one image row staged in LDS; every workgroup writes its partial
-// sums, reduced afterwards in a fixed order.
+// Pixels per weight-gradient chunk (one MFMA K step).
 constexpr int kWgChunk = 32;
-__global__ __launch_bounds__(320) void k_wgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ a, int B,
-                                               int H, int W, float *__restrict__ part) {
-    __shared__ float sdz[kWgChunk][kC];
-    __shared__ float sa[3][kWgChunk + 2][kC + 1];
-    const int t = threadIdx.x;
-    const bool owner = t < 9 * kC;
-    const int tap = t / kC, co = t % kC;
-    const int ky = tap / 3, kx = tap % 3;
-    float acc[kC];
+
+// Weight and bias gradient of one layer on MFMA.  Per tap (dy, dx) the
+// gradient is a GEMM over pixels: dW_tap[co][ci] = sum_p dz[p][co] *
+// a[p + (dy, dx)][ci], i.e. D (co x ci) += A (co x 32 pixels) * B (32
+// pixels x ci) per chunk of 32 consecutive pixels of one image row, two by
+// two 16x16x32 bf16 tiles with FP32 accumulators.  Wave `tap` of the
+// 9-wave workgroup owns one tap; the chunk's dz (transposed, [co][pixel]) and
+// the nine shifted input windows (transposed, [tap][ci][pixel]) are staged
+// in LDS so every operand is one aligned 16-byte LDS read.  Wave 0 also sums
+// dz for the bias gradient.  Every workgroup writes its partial sums in the
+// layout k_wgrad_reduce adds in a fixed order.
+constexpr int kWgPad = 40;  // LDS row length (pixels) of the transposed tiles
+__global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ a,
+                                                    int B, int H, int W, float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) __bf16 sdz[kC][kWgPad];
+    __shared__ __attribute__((aligned(16))) __bf16 sa[9][kC][kWgPad];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int m = lane & 15, kg = lane >> 4;
+    const int tap = wave, ky = tap / 3, kx = tap % 3;
+    f32x4 acc[2][2];
 #pragma unroll
-    for (int c = 0; c < kC; ++c) acc[c] = 0.0f;
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) acc[h][h2] = f32x4{0, 0, 0, 0};
     float accb = 0.0f;
     const int chunks_x = (W + kWgChunk - 1) / kWgChunk;
     const int64_t nchunks = (int64_t)B * H * chunks_x;
+    const __bf16 zero = (__bf16)0.0f;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int cx = (int)(ch % chunks_x);
         const int64_t by = ch / chunks_x;
         const int y = (int)(by % H), b = (int)(by / H);
         const int x0 = cx * kWgChunk;
         __syncthreads();
-        for (int q = t; q < kWgChunk * kC; q += blockDim.x) {
-            int p = q / kC, c = q % kC;
-            int x = x0 + p;
-            sdz[p][c] = (x < W) ? (float)dz[(((int64_t)b * H + y) * W + x) * kC + c] : 0.0f;
-        }
-        for (int q = t; q < 3 * (kWgChunk + 2) * kC; q += blockDim.x) {
-            int r = q / ((kWgChunk + 2) * kC), p = (q / kC) % (kWgChunk + 2), c = q % kC;
-            int yy = y + r - 1, xx = x0 + p - 1;
-            sa[r][p][c] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                              ? (float)a[(((int64_t)b * H + yy) * W + xx) * kC + c]
-                              : 0.0f;
-        }
-        __syncthreads();
-        if (owner) {
-            for (int p = 0; p < kWgChunk; ++p) {
-                float g = sdz[p][co];
-                if (tap == 0) accb += g;
+        // dz: 32 pixels x 4 groups of 8 channels, one 16-byte load each
+        for (int q = t; q < kWgChunk * (kC / 8); q += blockDim.x) {
+            const int p = q / (kC / 8), c8 = (q % (kC / 8)) * 8, x = x0 + p;
+            bf16x8 v = {};
+            if (x < W) v = *reinterpret_cast<const bf16x8 *>(dz + (((int64_t)b * H + y) * W + x) * kC + c8);
 #pragma unroll
-                for (int c = 0; c < kC; ++c) acc[c] += g * sa[ky][p + kx][c];
+            for (int u = 0; u < 8; ++u) sdz[c8 + u][p] = v[u];
+        }
+        // the three input rows y-1..y+1 over pixels x0-1..x0+32, each value
+        // written to the (up to three) shifted copies of the taps that read it
+        for (int q = t; q < 3 * (kWgChunk + 2) * (kC / 8); q += blockDim.x) {
+            const int r = q / ((kWgChunk + 2) * (kC / 8)), P = (q / (kC / 8)) % (kWgChunk + 2);
+            const int c8 = (q % (kC / 8)) * 8;
+            const int yy = y + r - 1, xx = x0 + P - 1;
+            bf16x8 v = {};
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                v = *reinterpret_cast<const bf16x8 *>(a + (((int64_t)b * H + yy) * W + xx) * kC + c8);
+#pragma unroll
+            for (int kxx = 0; kxx < 3; ++kxx) {
+                const int p = P - kxx;
+                if (p < 0 || p >= kWgChunk) continue;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sa[r * 3 + kxx][c8 + u][p] = v[u];
             }
         }
-    }
-    if (owner) {
-        float *o = part + (int64_t)blockIdx.x * (9 * kC * kC + kC);
+        __syncthreads();
+        bf16x8 A[2], Bm[2];
 #pragma unroll
-        for (int c = 0; c < kC; ++c) o[((int64_t)co * kC + c) * 9 + tap] = acc[c];
-        if (tap == 0) o[9 * kC * kC + co] = accb;
+        for (int h = 0; h < 2; ++h) {
+            A[h] = *reinterpret_cast<const bf16x8 *>(&sdz[h * 16 + m][8 * kg]);
+            Bm[h] = *reinterpret_cast<const bf16x8 *>(&sa[tap][h * 16 + m][8 * kg]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2)
+                acc[h][h2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], Bm[h2], acc[h][h2], 0, 0, 0);
+        if (wave == 0 && lane < kC)
+            for (int p = 0; p < kWgChunk; ++p) accb += (float)sdz[lane][p];
     }
+    float *o = part + (int64_t)blockIdx.x * (9 * kC * kC + kC);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = h * 16 + 4 * kg + i, ci = h2 * 16 + m;
+                o[((int64_t)co * kC + ci) * 9 + tap] = acc[h][h2][i];
+            }
+    if (wave == 0 && lane < kC) o[9 * kC * kC + lane] = accb;
 }
 
 // grad (param layout of layer l) = sum over workgroups of the partials.
@@ -225,8 +257,15 @@ __global__ void k_wgrad_reduce(const float *__restrict__ part, int nwg, int ci_r
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     const int E = 9 * kC * kC + kC;
     if (e >= E) return;
-    float s = 0.0f;
-    for (int g = 0; g < nwg; ++g) s += part[(int64_t)g * E + e];
+    // eight independent running sums (workgroups g = k mod 8), combined in a
+    // fixed order: the loads overlap instead of waiting on one add chain
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int g = 0;
+    for (; g + 8 <= nwg; g += 8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += part[(int64_t)(g + k) * E + e];
+    for (int k = 0; g < nwg; ++g, ++k) acc[k] += part[(int64_t)g * E + e];
+    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     if (e < 9 * kC * kC) {
         int co = e / (kC * 9), ci = (e / 9) % kC, tap = e % 9;
         if (co < co_real && ci < ci_real) grad[((int64_t)co * ci_real + ci) * 9 + tap] = s;
@@ -325,7 +364,7 @@ void backward_pass(const Scratch &s, const float *target, int B, int H, int W, h
     int cur = 0;
     for (int l = 3; l >= 0; --l) {
         const __bf16 *aprev = (l == 0) ? s.X0 : s.A[l - 1];
-        k_wgrad<<<s.nwg, 320, 0, st>>>(s.DZ[cur], aprev, B, H, W, s.part);
+        k_wgrad_mfma<<<s.nwg, 576, 0, st>>>(s.DZ[cur], aprev, B, H, W, s.part);
         k_wgrad_reduce<<<(9 * kC * kC + kC + 255) / 256, 256, 0, st>>>(s.part, s.nwg, kLayersH[l].ci,
                                                                         kLayersH[l].co, s.grad + param_offset(l));
         if (l > 0) {
