@@ -192,7 +192,6 @@ struct BLevel {
     double *J;      // kBPlanes planes
     double *x, *r;  // 3-field correction and residual
     double *x2;     // partner of x for the fused red-black sweep (zero electrode rows)
-    double *st;     // injected state (V, ne, np), levels >= 1
     double *cinvT;  // coarsest level: transposed inverse of the block matrix
     // FP32 copies for the mixed-precision preconditioner
     float *J32, *x32, *r32, *cinvT32, *x2_32;

@@ -41,6 +41,20 @@ struct NewtonPhys {
     double De, Dp, k, dt_inv;
 };
 
+// Several levels of the hierarchy in one launch of a 2D kernel: blocks of
+// 64 x kLevTabTY threads; level k of the table owns the row blocks
+// blockIdx.y in [y0[k], y0[k+1]) (filled by the launcher).
+constexpr int kLevTabTY = 4;
+constexpr int kMaxLevTab = 16;  // callers keep 1 <= n <= kMaxLevTab
+struct LevTab {
+    int n = 0;
+    int y0[kMaxLevTab + 1];
+    int shift[kMaxLevTab];  // levels below the finest grid
+    Geom g[kMaxLevTab];
+    BOp J[kMaxLevTab];
+    BOpT<float> J32[kMaxLevTab];
+};
+
 void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
                             const double *nek, const double *npk, const double *Se, const double *Sp,
                             const NewtonPhys &ph, bool with_rhs, hipStream_t s, const NewtonPhys *php = nullptr,
@@ -66,8 +80,13 @@ void launch_residual_restrict(const Geom &gf, const BOpT<T> &J, const T *f, cons
 template <class T>
 void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T *xc, int64_t pc, hipStream_t s,
                      const Batch &bt = Batch());
-void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
-                    double *out, int64_t pc, hipStream_t s, const Batch &bt = Batch());
+// Jacobians of levels t.g[k] (no rhs) at the finest state injected to them
+// (node (i, j) of level shift[k] reads the finest node (i, j) << shift[k]).
+void launch_newton_assemble_coarse(LevTab t, const double *V, const double *ne, const double *np, int64_t pitch0,
+                                   const NewtonPhys &ph, hipStream_t s, const NewtonPhys *php = nullptr,
+                                   const Batch &bt = Batch());
+// FP32 copies t.J32[k] of every level's Jacobian t.J[k].
+void launch_block_to_f32_levels(LevTab t, hipStream_t s, const Batch &bt = Batch());
 void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s,
                                 const Batch &bt = Batch());
 template <class T>
@@ -77,8 +96,6 @@ int block_vec_blocks(const Geom &g);
 template <class T>
 void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s, const Batch &bt = Batch());
 void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t s, const Batch &bt = Batch());
-void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s,
-                         const Batch &bt = Batch());
 void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s, const Batch &bt = Batch());
 // Gram-Schmidt pass: w = J z (if J and z) or w -= sum_v h_sub[v] basis_v
 // (if h_sub), then the partial sums of the weighted (w, basis_v), v < nv,

@@ -77,37 +77,25 @@ inline __device__ Face sg_face(bool plus, double q, double gd, double Vc, double
 // Continuity rows: F = sum over faces area*phi_out + vol (n - n^k)/dt - vol S
 // (Eqs. 7-11); Poisson row: F = A_P V - vol k (n_p - n_e) (Eqs. 12-13).
 // ---------------------------------------------------------------------------
-__global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, const double *__restrict__ ne,
-                                  const double *__restrict__ np, const double *__restrict__ nek,
-                                  const double *__restrict__ npk, const double *__restrict__ Se,
-                                  const double *__restrict__ Sp, NewtonPhys ph, int with_rhs,
-                                  const NewtonPhys *__restrict__ php, Batch bt) {
-    if (bt.active && !bt.active[blockIdx.z]) return;
-    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
-    g = geom_off(g, bo_);
-    J.base = boff(J.base, bo_);
-    V = boff(V, bo_);
-    ne = boff(ne, bo_);
-    np = boff(np, bo_);
-    nek = boff(nek, bo_);
-    npk = boff(npk, bo_);
-    Se = boff(Se, bo_);
-    Sp = boff(Sp, bo_);
-    if (php) ph = php[blockIdx.z];
-
-    int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i > g.nr || j > g.nz) return;
+// One node (i, j) of a level's Jacobian and, with_rhs, of -F.  The state
+// (V, ne, np) and the rhs inputs are read at sidx(i', j') for node (i', j')
+// of this level: the level's own layout on the finest grid, and the finest
+// grid's node (i' 2^l, j' 2^l) on level l (repeated injection).
+template <class Ix>
+inline __device__ void assemble_node(const Geom &g, const BOp &J, int i, int j, Ix sidx, const double *V,
+                                     const double *ne, const double *np, const double *nek, const double *npk,
+                                     const double *Se, const double *Sp, const NewtonPhys &ph, bool with_rhs) {
     int64_t p = at(g, i, j);
     if (j == 0 || j == g.nz) {
         for (int k = 0; k < kBPlanes; ++k) J.pl(k)[p] = 0.0;
         return;
     }
+    int64_t s = sidx(i, j);
     double w = g.wr[i], dzc = g.dzc[j], vol = w * dzc;
-    double Vc = V[p], ec = ne[p], pc = np[p];
+    double Vc = V[s], ec = ne[s], pc = np[s];
     double ee[5] = {0, 0, 0, 0, 0}, eV[5] = {0, 0, 0, 0, 0}, pp[5] = {0, 0, 0, 0, 0}, pV[5] = {0, 0, 0, 0, 0},
            VV[5] = {0, 0, 0, 0, 0};
-    int64_t nbp[5] = {p - g.pitch, p, p + g.pitch, p - 1, p + 1};
+    int64_t nbp[5] = {sidx(i - 1, j), s, sidx(i + 1, j), sidx(i, j - 1), sidx(i, j + 1)};
     bool has[5] = {i > 0, false, i < g.nr, true, true};
     double geo[5];
     geo[0] = (i > 0) ? g.fr[i - 1] * dzc / g.dr : 0.0;
@@ -147,8 +135,8 @@ __global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, c
     J.pl(kVe)[p] = kv;
     J.pl(kVp)[p] = -kv;
     if (with_rhs) {
-        double Fe = ee[1] * ec - vol * (Se[p] + nek[p] * ph.dt_inv);
-        double Fp = pp[1] * pc - vol * (Sp[p] + npk[p] * ph.dt_inv);
+        double Fe = ee[1] * ec - vol * (Se[s] + nek[s] * ph.dt_inv);
+        double Fp = pp[1] * pc - vol * (Sp[s] + npk[s] * ph.dt_inv);
         double FV = VV[1] * Vc - kv * (pc - ec);
 #pragma unroll
         for (int d = 0; d < 5; ++d) {
@@ -166,6 +154,62 @@ __global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, c
         J.pl(kFp)[p] = 0.0;
         J.pl(kFV)[p] = 0.0;
     }
+}
+
+__global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, const double *__restrict__ ne,
+                                  const double *__restrict__ np, const double *__restrict__ nek,
+                                  const double *__restrict__ npk, const double *__restrict__ Se,
+                                  const double *__restrict__ Sp, NewtonPhys ph, int with_rhs,
+                                  const NewtonPhys *__restrict__ php, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    V = boff(V, bo_);
+    ne = boff(ne, bo_);
+    np = boff(np, bo_);
+    nek = boff(nek, bo_);
+    npk = boff(npk, bo_);
+    Se = boff(Se, bo_);
+    Sp = boff(Sp, bo_);
+    if (php) ph = php[blockIdx.z];
+
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    const int64_t pitch = g.pitch;
+    assemble_node(g, J, i, j, [pitch](int a, int b) { return (int64_t)a * pitch + b; }, V, ne, np, nek, npk, Se, Sp,
+                  ph, with_rhs != 0);
+}
+
+// Levels 1..n of the hierarchy in one launch: blockIdx.y ranges over the
+// row blocks of every level in turn (LevTab::y0), and level l reads the
+// finest state at (i 2^l, j 2^l), the node that repeated injection
+// carries to its node (i, j).
+__global__ __launch_bounds__(kTX *kLevTabTY) void k_newton_assemble_coarse(LevTab t, const double *__restrict__ V,
+                                                                          const double *__restrict__ ne,
+                                                                          const double *__restrict__ np,
+                                                                          int64_t pitch0, NewtonPhys ph,
+                                                                          const NewtonPhys *__restrict__ php,
+                                                                          Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    int l = 0;
+    while (l + 1 < t.n && (int)blockIdx.y >= t.y0[l + 1]) ++l;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    Geom g = geom_off(t.g[l], bo_);
+    BOp J = t.J[l];
+    J.base = boff(J.base, bo_);
+    V = boff(V, bo_);
+    ne = boff(ne, bo_);
+    np = boff(np, bo_);
+    if (php) ph = php[blockIdx.z];
+
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = (blockIdx.y - t.y0[l]) * kLevTabTY + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    const int64_t si = pitch0 << t.shift[l], sj = int64_t(1) << t.shift[l];
+    assemble_node(g, J, i, j, [si, sj](int a, int b) { return (int64_t)a * si + (int64_t)b * sj; }, V, ne, np,
+                  nullptr, nullptr, nullptr, nullptr, ph, false);
 }
 
 // Sum over the four neighbours of B_nb x_nb for the three rows; xnb(t, c)
@@ -592,26 +636,6 @@ __global__ void k_prolong3(Geom gf, T *__restrict__ xf, int64_t pf, Geom gc, con
     int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > gf.nr || j < 1 || j >= gf.nz) return;
     prolong3_node(gf, xf, pf, gc, xc, pc, i, j);
-}
-
-__global__ void k_inject3(Geom gf, const double *__restrict__ V, const double *__restrict__ ne,
-                          const double *__restrict__ np, Geom gc, double *__restrict__ out, int64_t pc, Batch bt) {
-    if (bt.active && !bt.active[blockIdx.z]) return;
-    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
-    gf = geom_off(gf, bo_);
-    gc = geom_off(gc, bo_);
-    V = boff(V, bo_);
-    ne = boff(ne, bo_);
-    np = boff(np, bo_);
-    out = boff(out, bo_);
-
-    int J_ = blockIdx.x * kTX + threadIdx.x;
-    int I = blockIdx.y * blockDim.y + threadIdx.y;
-    if (I > gc.nr || J_ > gc.nz) return;
-    int64_t q = at(gc, I, J_), p = at(gf, 2 * I, 2 * J_);
-    out[q] = V[p];
-    out[q + pc] = ne[p];
-    out[q + 2 * pc] = np[p];
 }
 
 // Coarsest grid: explicit inverse of the dense block matrix (Gauss-Jordan,
@@ -1295,10 +1319,6 @@ void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T 
                      const Batch &bt) {
     k_prolong3<T><<<gz(grid2d(gf), bt), blk2d(gf), 0, s>>>(gf, xf, pf, gc, xc, pc, bt);
 }
-void launch_inject3(const Geom &gf, const double *V, const double *ne, const double *np, const Geom &gc,
-                    double *out, int64_t pc, hipStream_t s, const Batch &bt) {
-    k_inject3<<<gz(grid2d(gc), bt), blk2d(gc), 0, s>>>(gf, V, ne, np, gc, out, pc, bt);
-}
 void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s,
                                 const Batch &bt) {
     int n = 3 * (g.nr + 1) * (g.nz - 1);
@@ -1361,16 +1381,11 @@ void launch_newton_update(const Geom &g, double *V, double *ne, double *np, cons
 // entries of the three five-point blocks (ee, pp, VV), which are rebuilt from
 // their exact FP64 column excess minus the rounded neighbour entries of the
 // same column (see k_op_to_f32 for the reason).
-__global__ void k_block_to_f32(Geom g, BOp J, BOpT<float> J32, Batch bt) {
-    if (bt.active && !bt.active[blockIdx.z]) return;
-    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
-    g = geom_off(g, bo_);
-    J.base = boff(J.base, bo_);
-    J32.base = boff(J32.base, bo_);
-
-    int j = blockIdx.x * kTX + threadIdx.x;
-    int i = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i > g.nr || j > g.nz) return;
+namespace {
+// FP32 copy of one node's planes.  The diagonal centre entries are
+// re-rounded so that each FP32 row keeps the FP64 row's excess of the
+// centre over the neighbour couplings of its own field.
+inline __device__ void block_to_f32_node(const Geom &g, const BOp &J, const BOpT<float> &J32, int i, int j) {
     int64_t p = at(g, i, j);
     for (int k = 0; k < kBPlanes; ++k) J32.pl(k)[p] = (float)J.pl(k)[p];
     if (j == 0 || j == g.nz) return;
@@ -1401,8 +1416,46 @@ __global__ void k_block_to_f32(Geom g, BOp J, BOpT<float> J32, Batch bt) {
         J32.pl(K + 1)[p] = (float)(ex - r32);
     }
 }
-void launch_block_to_f32(const Geom &g, const BOp &J, const BOpT<float> &J32, hipStream_t s, const Batch &bt) {
-    k_block_to_f32<<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, J32, bt);
+
+__global__ __launch_bounds__(kTX *kLevTabTY) void k_block_to_f32_levels(LevTab t, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    int l = 0;
+    while (l + 1 < t.n && (int)blockIdx.y >= t.y0[l + 1]) ++l;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    Geom g = geom_off(t.g[l], bo_);
+    BOp J = t.J[l];
+    J.base = boff(J.base, bo_);
+    BOpT<float> J32 = t.J32[l];
+    J32.base = boff(J32.base, bo_);
+
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = (blockIdx.y - t.y0[l]) * kLevTabTY + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    block_to_f32_node(g, J, J32, i, j);
+}
+
+// Row-block starts of every level of the table; returns the launch grid.
+dim3 levtab_grid(LevTab &t, const Batch &bt) {
+    int y = 0, x = 0;
+    for (int k = 0; k < t.n; ++k) {
+        t.y0[k] = y;
+        y += (t.g[k].nr + 1 + kLevTabTY - 1) / kLevTabTY;
+        int bx = (t.g[k].nz + 1 + kTX - 1) / kTX;
+        x = bx > x ? bx : x;
+    }
+    t.y0[t.n] = y;
+    return dim3(x, y, bt.n);
+}
+}  // namespace
+
+void launch_block_to_f32_levels(LevTab t, hipStream_t s, const Batch &bt) {
+    dim3 grid = levtab_grid(t, bt);
+    k_block_to_f32_levels<<<grid, dim3(kTX, kLevTabTY), 0, s>>>(t, bt);
+}
+void launch_newton_assemble_coarse(LevTab t, const double *V, const double *ne, const double *np, int64_t pitch0,
+                                   const NewtonPhys &ph, hipStream_t s, const NewtonPhys *php, const Batch &bt) {
+    dim3 grid = levtab_grid(t, bt);
+    k_newton_assemble_coarse<<<grid, dim3(kTX, kLevTabTY), 0, s>>>(t, V, ne, np, pitch0, ph, php, bt);
 }
 
 // planes -> FP32 copies (n planes of `plane` elements)

@@ -131,6 +131,8 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
 
 // Assemble the Jacobian on every level: level 0 at the current state with
 // the Newton right-hand side; coarser levels at the injected state.
+static_assert(kMaxLevTab >= kMaxLevels, "one level-table launch covers the hierarchy");
+
 void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt_inv) {
     hipStream_t s = c->stream;
     NewtonPhys np_;
@@ -144,23 +146,31 @@ void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt
     int64_t p0 = plane_of(c->lev[0]);
     launch_newton_assemble(c->lev[0].g, bop(c, 0), st->V, st->ne, st->np, snap + p0, snap + 2 * p0, st->Se,
                            st->Sp, np_, true, s, static_cast<const NewtonPhys *>(c->php_dev), c->bt);
-    const double *V = st->V, *ne = st->ne, *np = st->np;
-    for (int l = 1; l < c->nlev; ++l) {
-        const Level &F = c->lev[l - 1], &C = c->lev[l];
-        int64_t pc = plane_of(C);
-        double *out = c->nw.lev[l].st;
-        launch_inject3(F.g, V, ne, np, C.g, out, pc, s, c->bt);
-        V = out;
-        ne = out + pc;
-        np = out + 2 * pc;
-        launch_newton_assemble(C.g, bop(c, l), V, ne, np, nullptr, nullptr, nullptr, nullptr, np_, false, s, static_cast<const NewtonPhys *>(c->php_dev), c->bt);
+    if (c->nlev > 1) {
+        // every coarser level at once, each at the finest state injected to it
+        LevTab t;
+        t.n = c->nlev - 1;
+        for (int l = 1; l < c->nlev; ++l) {
+            t.shift[l - 1] = l;
+            t.g[l - 1] = c->lev[l].g;
+            t.J[l - 1] = bop(c, l);
+        }
+        launch_newton_assemble_coarse(t, st->V, st->ne, st->np, c->lev[0].g.pitch, np_, s,
+                                      static_cast<const NewtonPhys *>(c->php_dev), c->bt);
     }
     const Level &Lc = c->lev[c->nlev - 1];
     launch_block_coarse_factor(Lc.g, bop(c, c->nlev - 1), c->nw.scratch, c->nw.lev[c->nlev - 1].cinvT, s, c->bt);
     if (c->nw.prec32) {
         // FP32 copies of every level's Jacobian and of the coarsest inverse
-        for (int l = 0; l < c->nlev; ++l)
-            launch_block_to_f32(c->lev[l].g, bop(c, l), BOpT<float>{c->nw.lev[l].J32, plane_of(c->lev[l])}, s, c->bt);
+        LevTab t;
+        t.n = c->nlev;
+        for (int l = 0; l < c->nlev; ++l) {
+            t.shift[l] = l;
+            t.g[l] = c->lev[l].g;
+            t.J[l] = bop(c, l);
+            t.J32[l] = BOpT<float>{c->nw.lev[l].J32, plane_of(c->lev[l])};
+        }
+        launch_block_to_f32_levels(t, s, c->bt);
         int64_t n = 3 * (int64_t)(Lc.g.nr + 1) * (Lc.g.nz - 1);
         launch_planes_to_f32(c->nw.lev[c->nlev - 1].cinvT, c->nw.lev[c->nlev - 1].cinvT32, n * n, s, c->bt);
     }
@@ -486,7 +496,6 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
         B.x = cv.take<double>(3 * pl);
         B.x2 = cv.take<double>(3 * pl);
         B.r = cv.take<double>(3 * pl);
-        B.st = (l > 0) ? cv.take<double>(3 * pl) : nullptr;
         bool p32 = d->prec == MG_FP32_IR;
         if (p32) {
             B.J32 = cv.take<float>(kBPlanes * pl);
