@@ -267,7 +267,9 @@ int mg_residual(mg_ctx *ctx, int eq, const double *x, double *r);
  * half-sweep of the Newton system (level 0; needs an assembled Jacobian),
  * 1 zebra z-line half-sweep, 2 point red-black half-sweep, 3 residual
  * (scalar equation `eq`, assembled before), 4 full collective red-black
- * sweep in one launch (both colours; level 0, assembled Jacobian).
+ * sweep in one launch (both colours; level 0, assembled Jacobian), 5 two
+ * full collective red-black sweeps in one launch (level 0, assembled
+ * Jacobian; what the block V-cycle launches when nu1 and nu2 are even).
  * Overwrites the level-0 work vectors only.  Synchronises. */
 int mg_time_kernel(mg_ctx *ctx, int which, int eq, int32_t reps, double *avg_ms);
 

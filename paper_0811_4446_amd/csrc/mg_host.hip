@@ -418,6 +418,8 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
     c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
+    if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
+    if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
     if (const char *e = getenv("MGF_SWEEP_ROWS"))
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(e) == 16 ? 16 : 8;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
@@ -696,7 +698,8 @@ int solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedul
 int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
     if (int e = check_ctx(c)) return e;
     if (!avg_ms || reps < 1) return fail(MG_EINVAL, "bad reps or null output");
-    if (which == 0 || which == 4) return time_block_smoother(c, reps, which == 4, avg_ms);
+    if (which == 0 || which == 4 || which == 5)
+        return time_block_smoother(c, reps, which == 5 ? 2 : which == 4 ? 1 : 0, avg_ms);
     if (int e = check_eq(eq)) return e;
     if (!c->assembled[eq]) return fail(MG_EINVAL, "equation %d not assembled", eq);
     if (which < 1 || which > 3) return fail(MG_EINVAL, "bad kernel id %d", which);

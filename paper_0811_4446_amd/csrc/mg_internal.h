@@ -217,6 +217,10 @@ struct NewtonWork {
     double cw_cap[3] = {0, 0, 0};
     bool use_graphs = true;
     bool rb_fused = true;      // full red-black sweeps in one launch (else two half-sweeps)
+    // two full sweeps per launch (nu1 and nu2 even) on levels of at most this
+    // many nodes; larger levels launch one sweep at a time, which is faster
+    // there (measured crossover between 129^2 and 257^2)
+    int64_t sweep2_max_nodes = 129 * 129;
     hipEvent_t ev[2] = {nullptr, nullptr};  // readback of Arnoldi steps k (even / odd)
     int last_its = 0;          // FGMRES iterations of the previous solve
     bool fuse = true;  // single-workgroup coarse sub-cycle
@@ -255,7 +259,8 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl);
 int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
                          mg_report *rep, bool *converged);
 int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep);
-int time_block_smoother(mg_ctx *c, int reps, bool fused, double *avg_ms);
+// mode 0: half-sweep, 1: one full sweep per launch, 2: two full sweeps per launch
+int time_block_smoother(mg_ctx *c, int reps, int mode, double *avg_ms);
 void drop_graphs(mg_ctx *c);
 int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double *out);
 int64_t carve_ctx(mg_ctx *c, const mg_grid_desc *d, char *base);

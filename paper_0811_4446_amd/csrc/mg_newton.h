@@ -67,6 +67,10 @@ void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int co
 template <class T>
 void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
                            const Geom *gc, const T *xc, int64_t pc, hipStream_t s, const Batch &bt = Batch());
+// Two full red-black sweeps xin -> xout in one launch (same input options).
+template <class T>
+void launch_block_rb_sweep2(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
+                            const Geom *gc, const T *xc, int64_t pc, hipStream_t s, const Batch &bt = Batch());
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s, const Batch &bt = Batch());

@@ -497,6 +497,107 @@ inline __device__ void block_residual_node(const Geom &g, const BOpT<T> &J, cons
     }
 }
 
+// Two full collective red-black sweeps in one launch, xin -> xout (distinct
+// buffers, electrode rows zero), input as for k_block_rb_sweep.  Each
+// workgroup owns a kSW x SH tile T and keeps the window T+4 (every node
+// within 4 rows / columns of T) in LDS, updated in place:
+//   A: colour 0 on T+3 (first sweep), B: colour 1 on T+2,
+//   C: colour 0 on T+1 (second sweep), D: colour 1 on T,
+// so each phase reads only values the previous phases made current.  Each
+// thread holds the Jacobian rows of one colour-0 node of T+3 and one
+// colour-1 node of T+2 in registers; the arithmetic of every update is
+// that of the per-node block solve, so the result equals four half-sweeps
+// bit for bit, with one launch and one pass over the Jacobian.
+template <int SH>
+struct Sweep2Tile {
+    static constexpr int kR3 = SH + 6, kC3 = (kSW + 6) / 2;  // colour-0 nodes of T+3: rows x per row
+    static constexpr int kR2 = SH + 4, kC2 = (kSW + 4) / 2;  // colour-1 nodes of T+2
+    static constexpr int kN = (kR3 * kC3 > kR2 * kC2) ? kR3 * kC3 : kR2 * kC2;
+    static constexpr int kThreads = (kN + 63) / 64 * 64;
+    static constexpr int kWR = SH + 8, kWC = kSW + 8;  // window T+4
+};
+template <class T, int SH>
+__global__ __launch_bounds__(Sweep2Tile<SH>::kThreads) void k_block_rb_sweep2(
+    Geom g, BOpT<T> J, const T *__restrict__ f, const T *__restrict__ xin, T *__restrict__ xout, int zin, Geom gc,
+    const T *__restrict__ xc, int64_t pc, Batch bt) {
+    using Tl = Sweep2Tile<SH>;
+    constexpr int kWR = Tl::kWR, kWC = Tl::kWC;
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    f = boff(f, bo_);
+    xin = boff(xin, bo_);
+    xout = boff(xout, bo_);
+    if (xc) {
+        gc = geom_off(gc, bo_);
+        xc = boff(xc, bo_);
+    }
+
+    __shared__ T w[3][kWR * kWC];
+    const int i0 = blockIdx.y * SH, j0 = blockIdx.x * kSW;
+    const int64_t plane = J.plane;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < kWR * kWC; t += Tl::kThreads) {
+        const int ii = i0 - 4 + t / kWC, jj = j0 - 4 + t % kWC;
+        if (ii < 0 || ii > g.nr || jj < 0 || jj > g.nz) continue;
+        const int64_t q = at(g, ii, jj);
+        const bool un = jj >= 1 && jj < g.nz;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T v = zin ? T(0) : xin[q + c * plane];
+            if (xc && un) v += prolong_val(g, gc, xc + c * pc, ii, jj);
+            w[c][t] = v;
+        }
+    }
+    // this thread's colour-0 node of T+3 (a) and colour-1 node of T+2 (b)
+    int ai = -1, aj = 0, bi = -1, bj = 0;
+    if (tid < Tl::kR3 * Tl::kC3) {
+        const int r = tid / Tl::kC3, k = tid % Tl::kC3;
+        ai = i0 - 3 + r;
+        aj = j0 - 3 + 2 * k + ((i0 + j0 + r) & 1);
+    }
+    if (tid < Tl::kR2 * Tl::kC2) {
+        const int r = tid / Tl::kC2, k = tid % Tl::kC2;
+        bi = i0 - 2 + r;
+        bj = j0 - 2 + 2 * k + ((i0 + j0 + r + 1) & 1);
+    }
+    const bool va = ai >= 0 && ai <= g.nr && aj >= 1 && aj < g.nz;
+    const bool vb = bi >= 0 && bi <= g.nr && bj >= 1 && bj < g.nz;
+    const int64_t pa = at(g, ai, aj), pb = at(g, bi, bj);
+    NodeRow<T> Ra, Rb;
+    if (va) load_row(J, f, pa, Ra);
+    if (vb) load_row(J, f, pb, Rb);
+    const int dni[4] = {-1, 1, 0, 0}, dnj[4] = {0, 0, -1, 1};
+    auto widx = [&](int ii, int jj) { return (ii - i0 + 4) * kWC + (jj - j0 + 4); };
+    auto update = [&](const NodeRow<T> &R, int ni, int nj, bool write) {
+        const bool has[4] = {ni > 0, ni < g.nr, true, true};
+        T oe, op, ov;
+        solve_row(R, has, [&](int t, int c) { return w[c][widx(ni + dni[t], nj + dnj[t])]; }, oe, op, ov);
+        const int l = widx(ni, nj);
+        w[0][l] = oe;
+        w[1][l] = op;
+        w[2][l] = ov;
+        if (write) {
+            const int64_t q = at(g, ni, nj);
+            xout[q] = oe;
+            xout[q + plane] = op;
+            xout[q + 2 * plane] = ov;
+        }
+    };
+    auto in_ring = [&](int ni, int nj, int d) {
+        return ni >= i0 - d && ni < i0 + SH + d && nj >= j0 - d && nj < j0 + kSW + d;
+    };
+    __syncthreads();
+    if (va) update(Ra, ai, aj, false);  // A
+    __syncthreads();
+    if (vb) update(Rb, bi, bj, false);  // B
+    __syncthreads();
+    if (va && in_ring(ai, aj, 1)) update(Ra, ai, aj, in_ring(ai, aj, 0));  // C
+    __syncthreads();
+    if (vb && in_ring(bi, bj, 0)) update(Rb, bi, bj, true);  // D
+}
+
 template <class T>
 __global__ void k_block_residual(Geom g, BOpT<T> J, const T *__restrict__ f, const T *__restrict__ x,
                                  T *__restrict__ r, int apply, Batch bt) {
@@ -1299,6 +1400,15 @@ void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T 
     }
 }
 template <class T>
+void launch_block_rb_sweep2(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
+                            const Geom *gc, const T *xc, int64_t pc, hipStream_t s, const Batch &bt) {
+    const Geom &gcc = gc ? *gc : g;
+    using Tl = Sweep2Tile<8>;
+    dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + 8 - 1) / 8);
+    k_block_rb_sweep2<T, 8><<<gz(grid, bt), Tl::kThreads, 0, s>>>(g, J, f, xin, xout, zin ? 1 : 0, gcc, xc, pc,
+                                                                   bt);
+}
+template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s, const Batch &bt) {
     k_block_residual<T><<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, f, x, r, apply ? 1 : 0, bt);
@@ -1495,6 +1605,8 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
                                        const Batch &);                                                       \
     template void launch_block_rb_sweep<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
                                            const Geom *, const T *, int64_t, hipStream_t, const Batch &);     \
+    template void launch_block_rb_sweep2<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,  \
+                                            const Geom *, const T *, int64_t, hipStream_t, const Batch &);    \
     template void launch_block_residual<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
                                            hipStream_t, const Batch &);                                      \
     template void launch_restrict3<T>(const Geom &, const T *, int64_t, const Geom &, T *, int64_t,          \

@@ -54,6 +54,13 @@ double3 field_weights(const mg_physics *ph) {
 // xc is set (fused_ok).
 template <class T>
 bool fused_ok(mg_ctx *c, int nu) { return c->nw.rb_fused && nu >= 2; }
+// Pairs of sweeps per launch on level l: every pre- and post-smoothing
+// count even and the level small enough.
+bool sweep2_ok(const mg_ctx *c, int l) {
+    const Geom &g = c->lev[l].g;
+    return c->nw.rb_fused && (int64_t)(g.nr + 1) * (g.nz + 1) <= c->nw.sweep2_max_nodes && c->desc.nu1 >= 2 &&
+           c->desc.nu2 >= 2 && c->desc.nu1 % 2 == 0 && c->desc.nu2 % 2 == 0;
+}
 
 template <class T>
 void block_smooth(mg_ctx *c, int l, const BOpT<T> &J, const T *f, T *x, int nu, bool x_zero, const T *xc,
@@ -103,13 +110,38 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         launch_block_coarse_solve<T>(L.g, J, f, Prec<T>::inv(c), x, s, c->bt);
         return;
     }
+    const Level &C = c->lev[l + 1];
+    BOpT<T> Jc = Prec<T>::op(c, l + 1);
+    T *fc = Jc.pl(kFe);
+    T *xc = Prec<T>::x(c, l + 1);
+    if (sweep2_ok(c, l)) {
+        // sweeps in pairs, alternating between x and x2: the first from a zero
+        // guess, the first post-smoothing pair adding the prolonged correction
+        // as it stages its input; the buffer order makes the last pair land in x
+        T *x2 = Prec<T>::x2(c, l);
+        const int n1 = c->desc.nu1 / 2, n2 = c->desc.nu2 / 2;
+        T *mid = (n2 & 1) ? x2 : x;  // iterate between pre- and post-smoothing
+        auto other = [&](T *b) { return b == x ? x2 : x; };
+        T *cur = (n1 & 1) ? mid : other(mid);
+        launch_block_rb_sweep2<T>(L.g, J, f, nullptr, cur, true, nullptr, nullptr, 0, s, c->bt);
+        for (int k = 1; k < n1; ++k) {
+            launch_block_rb_sweep2<T>(L.g, J, f, cur, other(cur), false, nullptr, nullptr, 0, s, c->bt);
+            cur = other(cur);
+        }
+        launch_residual_restrict<T>(L.g, J, f, cur, C.g, fc, plane_of(C), s, c->bt);
+        block_vcycle<T>(c, l + 1, fc, xc, s);
+        for (int k = 0; k < n2; ++k) {
+            const bool first = k == 0;
+            launch_block_rb_sweep2<T>(L.g, J, f, cur, other(cur), false, first ? &C.g : nullptr,
+                                      first ? xc : nullptr, plane_of(C), s, c->bt);
+            cur = other(cur);
+        }
+        return;
+    }
     // without a fused first sweep the zero guess has to be written
     const bool zero_sweep = fused_ok<T>(c, c->desc.nu1);
     if (!zero_sweep) launch_fill(x, 3 * plane_of(L), T(0), s, c->bt);
     block_smooth<T>(c, l, J, f, x, c->desc.nu1, zero_sweep, nullptr, s);
-    const Level &C = c->lev[l + 1];
-    BOpT<T> Jc = Prec<T>::op(c, l + 1);
-    T *fc = Jc.pl(kFe);
     if (c->nw.rb_fused) {
         launch_residual_restrict<T>(L.g, J, f, x, C.g, fc, plane_of(C), s, c->bt);
     } else {
@@ -117,7 +149,6 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         launch_block_residual<T>(L.g, J, f, x, r, false, s, c->bt);
         launch_restrict3<T>(L.g, r, plane_of(L), C.g, fc, plane_of(C), s, c->bt);
     }
-    T *xc = Prec<T>::x(c, l + 1);
     block_vcycle<T>(c, l + 1, fc, xc, s);
     // the coarse-grid correction: added by the first post-smoothing sweep, or
     // by its own launch
@@ -771,6 +802,8 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
     c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
+    if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
+    if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
     if (const char *sr = getenv("MGF_SWEEP_ROWS"))
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(sr) == 16 ? 16 : 8;
     c->ws_base = base;
@@ -1044,13 +1077,16 @@ int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double 
     return MG_OK;
 }
 
-int time_block_smoother(mg_ctx *c, int reps, bool fused, double *avg_ms) {
+int time_block_smoother(mg_ctx *c, int reps, int mode, double *avg_ms) {
     if (c->nw.m <= 0) return fail(MG_EINVAL, "no Newton workspace (krylov_m = 0)");
     const Level &L0 = c->lev[0];
     BOp J = bop(c, 0);
     double *x = c->nw.lev[0].x, *x2 = c->nw.lev[0].x2;
     auto one = [&](int r) {
-        if (fused)
+        if (mode == 2)
+            launch_block_rb_sweep2<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, false, nullptr,
+                                           nullptr, 0, c->stream);
+        else if (mode == 1)
             launch_block_rb_sweep<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, false, nullptr,
                                           nullptr, 0, c->stream);
         else

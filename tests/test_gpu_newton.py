@@ -120,39 +120,50 @@ def test_fused_subcycle_and_graphs_match_eager(N, monkeypatch):
 @pytest.mark.parametrize("N", [64, 128])
 def test_fused_rb_sweep_matches_half_sweeps(N, monkeypatch):
     """One-launch red-black sweeps (tile + recomputed ring in LDS, ping-pong
-    buffers) give bitwise the Newton steps of two half-sweep launches, for
-    every tile height (the reductions' order depends on the tile height, so
-    each height is compared with itself) and in the FP32 preconditioner."""
+    buffers), one or two full sweeps per launch, give bitwise the Newton
+    steps of half-sweep launches, for every tile height of the other kernels
+    (the reductions' order depends on it, so each height is compared with
+    itself) and in the FP32 preconditioner."""
     _say("fused rb sweep", N)
     m = M()
     z, V, ne, np_, S = _start(N)
     ph = dict(I.PHYS)
     cp = NW.Coupled(N, N, 1.0, z, ph)
     NW.steady(cp, V, ne, np_, S, S, max_steps=15)
+    # two: pairs of sweeps per launch on every launched level; mixed: only on
+    # levels of at most 5000 nodes (65^2 and 33^2), single sweeps above
+    modes = {"half": {"MGF_HALF_SWEEPS": "1"}, "one": {"MGF_ONE_SWEEP": "1"},
+             "two": {"MGF_TWO_SWEEP_NODES": str(10 ** 9)}, "mixed": {"MGF_TWO_SWEEP_NODES": "5000"}}
     for prec in (m.FP64, m.FP32_IR):
         for rows in (1, 2, 4, 16):
             results = {}
-            for half in (1, 0):
-                if half:
-                    monkeypatch.setenv("MGF_HALF_SWEEPS", "1")
-                else:
-                    monkeypatch.delenv("MGF_HALF_SWEEPS", raising=False)
+            for mode, env in modes.items():
+                for k in ("MGF_HALF_SWEEPS", "MGF_ONE_SWEEP", "MGF_TWO_SWEEP_NODES"):
+                    if k in env:
+                        monkeypatch.setenv(k, env[k])
+                    else:
+                        monkeypatch.delenv(k, raising=False)
                 sol, t, st = _gpu(N, V, ne, np_, S, krylov_m=20, prec=prec)
                 sol.tune(rows, 32)
                 sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-10, max_cycles=400, newton_tol=1e-10)
                 for dt in (1e-3, 1e-2, 0.1):
                     sol.step(m.Physics.of(ph), st, dt, sc)
-                results[half] = [sol.download(x) for x in t[:3]]
-            for a, b in zip(results[0], results[1]):
-                assert np.array_equal(a, b), (prec, rows)
-        # the 16-row sweep tile gives the same bits as the default 8-row one
+                results[mode] = [sol.download(x) for x in t[:3]]
+            for mode in ("one", "two", "mixed"):
+                for a, b in zip(results[mode], results["half"]):
+                    assert np.array_equal(a, b), (prec, rows, mode)
+        # the 16-row one-sweep tile gives the same bits as the default 8-row one
+        monkeypatch.delenv("MGF_HALF_SWEEPS", raising=False)
+        monkeypatch.delenv("MGF_TWO_SWEEP_NODES", raising=False)
+        monkeypatch.setenv("MGF_ONE_SWEEP", "1")
         monkeypatch.setenv("MGF_SWEEP_ROWS", "16")
         sol, t, st = _gpu(N, V, ne, np_, S, krylov_m=20, prec=prec)
         sol.tune(16, 32)
         for dt in (1e-3, 1e-2, 0.1):
             sol.step(m.Physics.of(ph), st, dt, sc)
         monkeypatch.delenv("MGF_SWEEP_ROWS", raising=False)
-        for a, b in zip([sol.download(x) for x in t[:3]], results[0]):
+        monkeypatch.delenv("MGF_ONE_SWEEP", raising=False)
+        for a, b in zip([sol.download(x) for x in t[:3]], results["half"]):
             assert np.array_equal(a, b), (prec, "sweep rows 16")
 
 
