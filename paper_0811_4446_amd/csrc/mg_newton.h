@@ -34,6 +34,7 @@ struct FusedLevelsT {
     T *r[kMaxFused];
     const T *f0;
     const T *invT;
+    uint32_t wmagic[kMaxFused];  // set by the launcher: ceil(2^32 / (nz + 1)) per level
 };
 
 struct NewtonPhys {

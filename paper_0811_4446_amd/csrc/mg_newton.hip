@@ -305,10 +305,11 @@ inline __device__ void solve_row(const NodeRow<T> &R, const bool (&has)[4], XNb 
         sv += R.VV[d] * v;
     }
     T re = R.fe - se, rp = R.fp - sp, rv = R.fv - sv;
-    T a = R.Ve / R.ee[1], b = R.Vp / R.pp[1];
+    const T ie = T(1) / R.ee[1], ip = T(1) / R.pp[1];
+    T a = R.Ve * ie, b = R.Vp * ip;
     ov = (rv - a * re - b * rp) / (R.VV[1] - a * R.eV[1] - b * R.pV[1]);
-    oe = (re - R.eV[1] * ov) / R.ee[1];
-    op = (rp - R.pV[1] * ov) / R.pp[1];
+    oe = (re - R.eV[1] * ov) * ie;
+    op = (rp - R.pV[1] * ov) * ip;
 }
 
 template <class T>
@@ -893,11 +894,17 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
     }
 }
 
-// x = A^{-1} f on the coarsest grid by the whole workgroup (rhs staged in
-// `rhs`, at least 3 * nodes doubles of LDS).
+// x = A^{-1} f on the coarsest grid by one workgroup of 1024 threads (rhs
+// staged in `rhs`, at least 3 * nodes values of LDS; `red` 16 x 64 values of
+// LDS).  Rows go in blocks of 64, one per lane; the 16 wavefronts split the
+// columns (wavefront w takes k = w, w + 16, ...) and the partial sums are
+// added in wavefront order.  use_pre (n <= 64 only): pre holds this thread's
+// matrix entries, k = w + 16 u for u < kCsPre, already loaded.
+constexpr int kCsParts = 16;
+constexpr int kCsPre = 4;  // kCsParts * kCsPre >= 64
 template <class T>
-inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const T *f, const T *invT,
-                                             T *x, T *rhs) {
+inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const T *f, const T *invT, T *x, T *rhs,
+                                             T (*red)[64], bool use_pre, const T (&pre)[kCsPre]) {
     const int m = g.nz - 1;
     const int nn = (g.nr + 1) * m;
     const int n = 3 * nn;
@@ -909,12 +916,31 @@ inline __device__ void block_coarse_solve_wg(const Geom &g, int64_t plane, const
         rhs[3 * node + 2] = f[p + 2 * plane];
     }
     __syncthreads();
-    for (int row = threadIdx.x; row < n; row += blockDim.x) {
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    for (int rb = 0; rb < n; rb += 64) {
+        const int row = rb + lane;
         T acc = T(0);
-        for (int k = 0; k < n; ++k) acc += invT[(int64_t)k * n + row] * rhs[k];
-        int node = row / 3, fl = row % 3;
-        int i = node / m, j = node % m + 1;
-        x[at(g, i, j) + fl * plane] = acc;
+        if (row < n) {
+            if (use_pre) {
+#pragma unroll
+                for (int u = 0; u < kCsPre; ++u) {
+                    const int k = part + kCsParts * u;
+                    if (k < n) acc += pre[u] * rhs[k];
+                }
+            } else {
+                for (int k = part; k < n; k += kCsParts) acc += invT[(int64_t)k * n + row] * rhs[k];
+            }
+        }
+        red[part][lane] = acc;
+        __syncthreads();
+        if (threadIdx.x < 64 && row < n) {
+            T sum = T(0);
+            for (int q = 0; q < kCsParts; ++q) sum += red[q][lane];
+            const int node = row / 3, fl = row % 3;
+            const int i = node / m, j = node % m + 1;
+            x[at(g, i, j) + fl * plane] = sum;
+        }
+        __syncthreads();
     }
 }
 
@@ -931,7 +957,9 @@ __global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOpT<T> J, 
     x = boff(x, bo_);
 
     __shared__ T rhs[3 * kMaxCoarseUnknowns];
-    block_coarse_solve_wg(g, J.plane, f, invT, x, rhs);
+    __shared__ T red[kCsParts][64];
+    const T none[kCsPre] = {};
+    block_coarse_solve_wg(g, J.plane, f, invT, x, rhs, red, false, none);
 }
 
 // ---------------------------------------------------------------------------
@@ -947,6 +975,8 @@ __global__ __launch_bounds__(1024) void k_block_coarse_solve(Geom g, BOpT<T> J, 
 // when they fit, so that the barrier phases read no global memory; the top
 // level's correction is written back at the end.
 constexpr int kSubPool = 15360;  // LDS elements of the staged levels
+constexpr int kStaged = kFe;     // matrix planes 0 .. kFe-1 (the rhs planes kFe.. come last)
+static_assert(kFe == kBPlanes - 3, "the three rhs planes are the last ones");
 template <class T, bool kLds>
 struct SubMem;
 template <class T>
@@ -981,12 +1011,57 @@ struct SubMem<T, true> {
     __device__ T *r(int q) const { return pool + off(q) + (kBPlanes + 3) * nodes(q); }
     __device__ const T *f0() const { return pool + off(F.n); }
     __device__ int64_t xplane(int q) const { return nodes(q); }
-    // compact copy of planes [0, np) of a global level array into LDS
-    __device__ void stage(const Geom &gg, const T *src, int64_t gplane, T *dst, int np) const {
-        const int w = gg.nz + 1, nn = (gg.nr + 1) * w;
-        for (int t = threadIdx.x; t < np * nn; t += blockDim.x) {
-            const int k = t / nn, node = t % nn;
-            dst[t] = src[k * gplane + (int64_t)(node / w) * gg.pitch + node % w];
+    // Compact copies of every level's Jacobian planes and of the top level's
+    // right-hand side into LDS, and zero corrections on every level.  Segment
+    // q < n is level q's kStaged matrix planes (a level's right-hand-side
+    // planes are written by the restriction before they are read, and the
+    // top level uses f0), segment n the 3 planes of f0; value
+    // e of a segment is row R = e / (nz + 1) (R = plane * (nr + 1) + i, which
+    // starts R * pitch values into the array since planes are (nr + 1) *
+    // pitch apart), column e % (nz + 1).  One segment is at most kB values
+    // per thread (the pool bound); the next segment's loads are issued before
+    // the current segment's stores, so the latencies overlap.
+    __device__ void stage_all() const {
+        const int n = F.n;
+        constexpr int kB = (kSubPool + 1023) / 1024;
+        auto load = [&](int q, T(&v)[kB]) {
+            const int qq = q < n ? q : 0;
+            const int w = F.g[qq].nz + 1, size = (q < n ? kStaged : 3) * (F.g[qq].nr + 1) * w;
+            const uint32_t mg = F.wmagic[qq];
+            const int64_t pitch = F.g[qq].pitch;
+            const T *src = boff(q < n ? F.J[q] : F.f0, bo);
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int e = threadIdx.x + u * 1024;
+                if (e < size) {
+                    const int R = (int)__umulhi((uint32_t)e, mg);
+                    v[u] = src[(int64_t)R * pitch + (e - R * w)];
+                }
+            }
+        };
+        auto store = [&](int q, const T(&v)[kB]) {
+            const int qq = q < n ? q : 0;
+            const int size = (q < n ? kStaged : 3) * nodes(qq);
+            T *dst = pool + (q < n ? off(q) : off(n));
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int e = threadIdx.x + u * 1024;
+                if (e < size) dst[e] = v[u];
+            }
+        };
+        T va[kB], vb[kB];
+        load(0, va);
+        for (int q = 0; q <= n; q += 2) {
+            if (q + 1 <= n) load(q + 1, vb);
+            store(q, va);
+            if (q + 1 <= n) {
+                if (q + 2 <= n) load(q + 2, va);
+                store(q + 1, vb);
+            }
+        }
+        for (int q = 0; q < n; ++q) {
+            T *xq = x(q);
+            for (int t = threadIdx.x; t < 3 * nodes(q); t += blockDim.x) xq[t] = T(0);
         }
     }
 };
@@ -1002,23 +1077,44 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     __shared__ T pool[kLds ? kSubPool : 1];
     SubMem<T, kLds> M{F, bo_};
+    // the coarsest inverse's entries this thread multiplies, loaded first
+    // (n <= 64) so that their latency hides behind the staging and the
+    // finer levels
+    const T *invT = boff(F.invT, bo_);
+    const Geom gl = geom_off(F.g[F.n - 1], bo_);
+    const int nco = 3 * (gl.nr + 1) * (gl.nz - 1);
+    T pre[kCsPre];
+    {
+        const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+#pragma unroll
+        for (int u = 0; u < kCsPre; ++u) {
+            const int k = part + kCsParts * u;
+            pre[u] = (nco <= 64 && k < nco && lane < nco) ? invT[(int64_t)k * nco + lane] : T(0);
+        }
+    }
     if constexpr (kLds) {
         M.pool = pool;
+        M.stage_all();
+    } else {
         for (int q = 0; q < F.n; ++q) {
-            const Geom gg = geom_off(F.g[q], bo_);
-            M.stage(gg, boff(F.J[q], bo_), F.plane[q], M.jac(q).base, kBPlanes);
+            const Geom g = geom_off(F.g[q], bo_);
+            T *xq = M.x(q);
+            const int nodes = (g.nr + 1) * (g.nz + 1);
+            for (int t = threadIdx.x; t < nodes; t += blockDim.x) {
+                int64_t p = at(g, t / (g.nz + 1), t % (g.nz + 1));
+                xq[p] = xq[p + F.plane[q]] = xq[p + 2 * F.plane[q]] = T(0);
+            }
         }
-        M.stage(geom_off(F.g[0], bo_), boff(F.f0, bo_), F.plane[0], const_cast<T *>(M.f0()), 3);
-        __syncthreads();
     }
+    __syncthreads();
     auto geom = [&](int q) { return M.geom(q); };
     auto jac = [&](int q) { return M.jac(q); };
     auto xof = [&](int q) { return M.x(q); };
     auto rof = [&](int q) { return M.r(q); };
     const T *f0 = M.f0();
-    const T *invT = boff(F.invT, bo_);
 
     __shared__ T rhs[3 * kMaxFusedCoarse];
+    __shared__ T red[kCsParts][64];
     const int n = F.n;
     const int nt = blockDim.x;
     for (int q = 0; q < n - 1; ++q) {
@@ -1028,13 +1124,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
         T *x = xof(q);
         T *r = rof(q);
         const int nodes = (g.nr + 1) * (g.nz + 1);
-        // every level's correction starts from zero (x is not read on entry)
-        for (int t = threadIdx.x; t < nodes; t += nt) {
-            int i = t / (g.nz + 1), j = t % (g.nz + 1);
-            int64_t p = at(g, i, j);
-            x[p] = x[p + J.plane] = x[p + 2 * J.plane] = T(0);
-        }
-        __syncthreads();
+        // every level's correction starts from zero (set while staging)
         for (int s = 0; s < F.nu1; ++s)
             for (int col = 0; col < 2; ++col) {
                 for (int t = threadIdx.x; t < nodes; t += nt) {
@@ -1061,15 +1151,8 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
         const int q = n - 1;
         const BOpT<T> J = jac(q);
         const T *f = (q == 0) ? f0 : J.pl(kFe);
-        if constexpr (kLds) {
-            // the staged coarsest correction needs its electrode rows zero
-            const Geom g = geom(q);
-            const int nodes = (g.nr + 1) * (g.nz + 1);
-            T *x = xof(q);
-            for (int t = threadIdx.x; t < 3 * nodes; t += nt) x[t] = T(0);
-            __syncthreads();
-        }
-        block_coarse_solve_wg(geom(q), J.plane, f, invT, xof(q), rhs);
+        // (the coarsest correction's electrode rows were zeroed while staging)
+        block_coarse_solve_wg(geom(q), J.plane, f, invT, xof(q), rhs, red, nco <= 64, pre);
         __syncthreads();
     }
     for (int q = n - 2; q >= 0; --q) {
@@ -1447,8 +1530,18 @@ void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s, const Batch 
     int64_t need = 0;
     for (int q = 0; q < F.n; ++q) need += (int64_t)(kBPlanes + 6) * (F.g[q].nr + 1) * (F.g[q].nz + 1);
     need += 3 * (int64_t)(F.g[0].nr + 1) * (F.g[0].nz + 1);
-    if (need <= kSubPool)
-        k_block_subcycle<T, true><<<dim3(1, 1, bt.n), 1024, 0, s>>>(F, bt);
+    // the LDS copy reads rows of planes (nr + 1) * pitch apart; row index
+    // e / (nz + 1) by a multiply-high with ceil(2^32 / (nz + 1)) (exact for
+    // e (nz + 1) < 2^32)
+    bool rows_ok = true;
+    FusedLevelsT<T> G = F;
+    for (int q = 0; q < F.n; ++q) {
+        const uint64_t w = (uint64_t)F.g[q].nz + 1;
+        rows_ok = rows_ok && F.plane[q] == (int64_t)(F.g[q].nr + 1) * F.g[q].pitch && w * kSubPool < (1ull << 32);
+        G.wmagic[q] = (uint32_t)(((1ull << 32) + w - 1) / w);
+    }
+    if (need <= kSubPool && rows_ok)
+        k_block_subcycle<T, true><<<dim3(1, 1, bt.n), 1024, 0, s>>>(G, bt);
     else
         k_block_subcycle<T, false><<<dim3(1, 1, bt.n), 1024, 0, s>>>(F, bt);
 }
