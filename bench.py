@@ -481,6 +481,82 @@ def learned(args, M, I):
     print(json.dumps(out), flush=True)
 
 
+def fig1(args, M, I):
+    """Sec. 3, Fig. 1 re-measured on this GPU: time to the steady state against N for plain relaxation
+    (R: the coupled Newton path with its preconditioner reduced to V(2,2)'s four red-black sweeps on the
+    finest grid, no coarse correction), multigrid from the random start (M), and multigrid with
+    multilevel prolongation (M+L: steady runs 17x17 -> 33x33 -> ... -> N, each prolonged to the next).
+    Same physics, schedule and stop rule as the default benchmark (V_top = 1); slopes are d log t /
+    d log N between consecutive grids."""
+    import math
+    import numpy as np
+    import torch
+    Ns = [int(v) for v in args.fig1_grids.split(",")]
+    if min(Ns) <= 16 or any(n & (n - 1) for n in Ns):
+        raise SystemExit("--fig1-grids: powers of two above 16 (the chain starts at 17x17)")
+    phys = dict(I.PHYS)
+    P = M.Physics.of(phys)
+
+    def from_random(N, relax):
+        if relax:
+            os.environ["MGF_SMOOTHER_ONLY"] = "1"
+        try:
+            z = I.z_cos(N)
+            sol = M.Solver(N, N, z, krylov_m=30, coarsest=4, prec=M.FP64)
+        finally:
+            os.environ.pop("MGF_SMOOTHER_ONLY", None)
+        ne = I.initial_density(N, N, 0)
+        t = [sol.upload(I.initial_potential(N, N, z, 0.0, phys["V_top"])), sol.upload(ne), sol.upload(ne),
+             sol.upload(I.source(N, N, z))]
+        sc = schedule(M, args.lin_rtol)
+        if relax:
+            sc = M.schedule(dt0=1e-4, growth=1.5, dt_max=0.1, steady_tol=1e-8, lin_rtol=args.lin_rtol,
+                            max_steps=20000, max_cycles=args.fig1_rmax_cycles, coupling=M.NEWTON, max_newton=10,
+                            newton_tol=1e-6)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        code, rep = sol.steady(P, sol.state(t[0], t[1], t[2], t[3], t[3]), sc)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        fields = [sol.download(x) for x in t[:3]]
+        return dict(seconds=round(dt, 4), ok=code == 0, steps=rep.steps, newton=rep.newton_its,
+                    fgmres=rep.vcycles), fields
+
+    def chained(N):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        fine, t, P2, info = chain_to(M, I, N, phys["V_top"], args.lin_rtol, N0=16)
+        code, rep = fine.steady(P2, fine.state(t[0], t[1], t[2], t[3], t[3]), schedule(M, args.lin_rtol))
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        fields = [fine.download(x) for x in t[:3]]
+        return dict(seconds=round(dt, 4), ok=code == 0, steps_final=rep.steps,
+                    stages=[s_["N"] for s_ in info] + [N]), fields
+
+    def rel(a, b):
+        return max(float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300)) for x, y in zip(a, b))
+
+    from_random(16, False)  # first-use costs (library load, graph capture) outside the timings
+    rows = []
+    for N in Ns:
+        m, fm = from_random(N, False)
+        ml, fml = chained(N)
+        row = dict(N=N + 1, M=m, ML=ml, ML_vs_M=rel(fml, fm))
+        if N <= args.fig1_rmax:
+            r, fr = from_random(N, True)
+            row["R"] = r
+            row["R_vs_M"] = rel(fr, fm)
+        rows.append(row)
+        log("fig1 %dx%d: %s" % (N + 1, N + 1, row))
+    slopes = {}
+    for key in ("R", "M", "ML"):
+        pts = [(r["N"], r[key]["seconds"]) for r in rows if key in r and r[key]["ok"]]
+        slopes[key] = [round(math.log(t2 / t1) / math.log(n2 / n1), 2)
+                       for (n1, t1), (n2, t2) in zip(pts, pts[1:])]
+    print(json.dumps({"fig1": rows, "slopes": slopes, "V_top": phys["V_top"], "lin_rtol": args.lin_rtol}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -507,6 +583,10 @@ def main():
     ap.add_argument("--vcycle", action="store_true", help="scalar path: 65x65 decoupled step and V-cycle GB/s")
     ap.add_argument("--reps", type=int, default=200, help="timed half-sweeps of the roofline measurement")
     ap.add_argument("--trace-summary", type=str, default="", help="summarise a rocprofv3 CSV and exit")
+    ap.add_argument("--fig1", action="store_true", help="Sec. 3 Fig. 1 re-measured: R / M / M+L time vs N")
+    ap.add_argument("--fig1-grids", type=str, default="32,64,128,256", help="N values, each > 16")
+    ap.add_argument("--fig1-rmax", type=int, default=64, help="largest N of the relaxation-only runs")
+    ap.add_argument("--fig1-rmax-cycles", type=int, default=20000, help="FGMRES iterations per Newton, R runs")
     ap.add_argument("--prec", choices=["fp64", "fp32", "both"], default="fp64",
                     help="block preconditioner precision (FGMRES and Newton stay FP64)")
     args = ap.parse_args()
@@ -531,6 +611,8 @@ def main():
         return sweep(args, M, I)
     if args.learned:
         return learned(args, M, I)
+    if args.fig1:
+        return fig1(args, M, I)
     vtops = [float(v) for v in args.vtops.split(",")]
     N = args.grid
     if args.prec != "fp64":

@@ -417,6 +417,7 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     // sub-cycle, eager launches instead of captured graphs
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
     c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
+    c->nw.smoother_only = getenv("MGF_SMOOTHER_ONLY") != nullptr;
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
     if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);

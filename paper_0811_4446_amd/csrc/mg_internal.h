@@ -216,12 +216,21 @@ struct NewtonWork {
     hipGraphExec_t exec[64] = {};
     double cw_cap[3] = {0, 0, 0};
     bool use_graphs = true;
+    // preconditioner reduced to nu1 + nu2 red-black sweeps on the finest grid
+    // (no coarse correction): plain relaxation, measured against multigrid
+    bool smoother_only = false;
     bool rb_fused = true;      // full red-black sweeps in one launch (else two half-sweeps)
     // two full sweeps per launch (nu1 and nu2 even) on levels of at most this
     // many nodes; larger levels launch one sweep at a time, which is faster
     // there (measured crossover between 129^2 and 257^2)
     int64_t sweep2_max_nodes = 129 * 129;
     hipEvent_t ev[2] = {nullptr, nullptr};  // readback of Arnoldi steps k (even / odd)
+    // the coarsest factorisation runs on `side` as a branch of Arnoldi step 0
+    // (fork: evf[0] on the step's stream; join: evf[1], awaited before the
+    // first use of the inverse)
+    hipStream_t side = nullptr;
+    hipEvent_t evf[2] = {nullptr, nullptr};
+    bool join_pending = false;
     int last_its = 0;          // FGMRES iterations of the previous solve
     bool fuse = true;  // single-workgroup coarse sub-cycle
     int fuse_max = 16; // levels with nr, nz <= fuse_max run in it

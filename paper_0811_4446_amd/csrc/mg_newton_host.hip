@@ -52,6 +52,8 @@ double3 field_weights(const mg_physics *ph) {
 // correction still to be prolonged and added to x, which the first fused
 // sweep does on the fly; the caller guarantees a fused sweep when x_zero or
 // xc is set (fused_ok).
+void join_factor(mg_ctx *c, hipStream_t s);
+
 template <class T>
 bool fused_ok(mg_ctx *c, int nu) { return c->nw.rb_fused && nu >= 2; }
 // Pairs of sweeps per launch on level l: every pre- and post-smoothing
@@ -88,6 +90,14 @@ template <class T>
 void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     const Level &L = c->lev[l];
     BOpT<T> J = Prec<T>::op(c, l);
+    if (l == 0 && c->nw.smoother_only) {
+        // relaxation only: nu1 + nu2 collective red-black sweeps from zero
+        const int nu = c->desc.nu1 + c->desc.nu2;
+        const bool zs = fused_ok<T>(c, nu);
+        if (!zs) launch_fill(x, 3 * plane_of(L), T(0), s, c->bt);
+        block_smooth<T>(c, 0, J, f, x, nu, zs, nullptr, s);
+        return;
+    }
     if (c->nw.fuse && L.g.nr <= c->nw.fuse_max && L.g.nz <= c->nw.fuse_max && c->nlev - l <= kMaxFused) {
         FusedLevelsT<T> F;
         memset(&F, 0, sizeof F);
@@ -103,10 +113,12 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         }
         F.f0 = f;
         F.invT = Prec<T>::inv(c);
+        join_factor(c, s);
         launch_block_subcycle<T>(F, s, c->bt);
         return;
     }
     if (l == c->nlev - 1) {
+        join_factor(c, s);
         launch_block_coarse_solve<T>(L.g, J, f, Prec<T>::inv(c), x, s, c->bt);
         return;
     }
@@ -189,10 +201,9 @@ void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt
         launch_newton_assemble_coarse(t, st->V, st->ne, st->np, c->lev[0].g.pitch, np_, s,
                                       static_cast<const NewtonPhys *>(c->php_dev), c->bt);
     }
-    const Level &Lc = c->lev[c->nlev - 1];
-    launch_block_coarse_factor(Lc.g, bop(c, c->nlev - 1), c->nw.scratch, c->nw.lev[c->nlev - 1].cinvT, s, c->bt);
     if (c->nw.prec32) {
-        // FP32 copies of every level's Jacobian and of the coarsest inverse
+        // FP32 copies of every level's Jacobian (the coarsest inverse's copy
+        // follows its factorisation, coarse_factor)
         LevTab t;
         t.n = c->nlev;
         for (int l = 0; l < c->nlev; ++l) {
@@ -202,9 +213,25 @@ void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt
             t.J32[l] = BOpT<float>{c->nw.lev[l].J32, plane_of(c->lev[l])};
         }
         launch_block_to_f32_levels(t, s, c->bt);
+    }
+}
+
+// Explicit inverse of the coarsest Jacobian (and its FP32 copy) on stream s.
+void coarse_factor(mg_ctx *c, hipStream_t s) {
+    const Level &Lc = c->lev[c->nlev - 1];
+    launch_block_coarse_factor(Lc.g, bop(c, c->nlev - 1), c->nw.scratch, c->nw.lev[c->nlev - 1].cinvT, s, c->bt);
+    if (c->nw.prec32) {
         int64_t n = 3 * (int64_t)(Lc.g.nr + 1) * (Lc.g.nz - 1);
         launch_planes_to_f32(c->nw.lev[c->nlev - 1].cinvT, c->nw.lev[c->nlev - 1].cinvT32, n * n, s, c->bt);
     }
+}
+
+// Stream s waits for the coarsest factorisation if it is still a pending
+// branch (the first V-cycle after a fork reaches the coarse end).
+void join_factor(mg_ctx *c, hipStream_t s) {
+    if (!c->nw.join_pending) return;
+    (void)hipStreamWaitEvent(s, c->nw.evf[1], 0);
+    c->nw.join_pending = false;
 }
 
 // Givens-rotation least squares of the Arnoldi relation (host, small).
@@ -264,6 +291,15 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     const int m = W.m;
     double *dev = W.dev;
     double *vk = W.V + k * vs, *zk = W.Z + k * vs, *vk1 = W.V + (k + 1) * vs;
+    if (k == 0) {
+        // the coarsest factorisation (of the Jacobian assembled before this
+        // solve) overlaps the fine-level part of the first V-cycle
+        (void)hipEventRecord(W.evf[0], s);
+        (void)hipStreamWaitEvent(W.side, W.evf[0], 0);
+        coarse_factor(c, W.side);
+        (void)hipEventRecord(W.evf[1], W.side);
+        W.join_pending = true;
+    }
     if (W.prec32) {
         // preconditioner in FP32: z_k = M32 v_k (the Krylov space stays FP64)
         float *x32 = W.lev[0].x32;
@@ -273,6 +309,7 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     } else {
         block_vcycle<double>(c, 0, vk, zk, s);
     }
+    join_factor(c, s);  // (already joined by the V-cycle's coarse end)
     // w = J z_k, then classical Gram-Schmidt twice: h1 = V^T w; w -= V h1,
     // h2 = V^T w; w -= V h2, |w|^2
     launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, W.partials, dev, s, c->bt, &J, zk);
@@ -304,6 +341,11 @@ int launch_step(mg_ctx *c, int k, double3 cw) {
 // of the inner-product weights recaptures).
 int run_arnoldi(mg_ctx *c, int k, double3 cw) {
     NewtonWork &W = c->nw;
+    if (!W.side) {  // created outside any capture
+        HIP_OK(hipStreamCreateWithFlags(&W.side, hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&W.evf[0], hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&W.evf[1], hipEventDisableTiming));
+    }
     if (!W.use_graphs) {
         arnoldi_step(c, k, cw, c->stream);
         return MG_OK;
@@ -801,6 +843,7 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     carve_ctx(c, d, base);
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;
     c->nw.use_graphs = getenv("MGF_NO_GRAPHS") == nullptr;
+    c->nw.smoother_only = getenv("MGF_SMOOTHER_ONLY") != nullptr;
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
     if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
@@ -1046,11 +1089,21 @@ void drop_graphs(mg_ctx *c) {
             (void)hipGraphExecDestroy(c->nw.exec[t]);
             c->nw.exec[t] = nullptr;
         }
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t) {
         if (c->nw.ev[t]) {
             (void)hipEventDestroy(c->nw.ev[t]);
             c->nw.ev[t] = nullptr;
         }
+        if (c->nw.evf[t]) {
+            (void)hipEventDestroy(c->nw.evf[t]);
+            c->nw.evf[t] = nullptr;
+        }
+    }
+    if (c->nw.side) {
+        (void)hipStreamDestroy(c->nw.side);
+        c->nw.side = nullptr;
+    }
+    c->nw.join_pending = false;
 }
 
 // Weighted norm of the steady residual F(u) (dt = infinity) at the state st

@@ -63,6 +63,33 @@ def test_newton_step_matches_oracle(N, dt, pre):
         assert relmax(sol.download(tt), ref) <= 1e-11
 
 
+def test_relaxation_only_preconditioner_matches_oracle(monkeypatch):
+    """The relaxation-only preconditioner (red-black sweeps on the finest
+    grid, no coarse correction; the plain-relaxation curve of the Fig. 1
+    measurement) changes the linear-solver path, not the Newton iterates:
+    one BE step at 33x33 equals the oracle's within FP64 rounding."""
+    _say("relaxation-only preconditioner", 32)
+    m = M()
+    N, dt = 32, 1e-3
+    z, V, ne, np_, S = _start(N)
+    ph = dict(I.PHYS)
+    cp = NW.Coupled(N, N, 1.0, z, ph)
+    monkeypatch.setenv("MGF_SMOOTHER_ONLY", "1")
+    sol, t, st = _gpu(N, V, ne, np_, S, krylov_m=30)
+    monkeypatch.delenv("MGF_SMOOTHER_ONLY", raising=False)
+    ok, its = NW.newton_step(cp, V, ne, np_, S, S, dt, max_newton=20, tol=1e-11)
+    assert ok
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-13, max_cycles=20000, max_newton=20, newton_tol=1e-11)
+    rep = sol.step(m.Physics.of(ph), st, dt, sc)
+    assert rep.newton_its == its, (rep.newton_its, its)
+    for tt, ref in zip(t[:3], (V, ne, np_)):
+        assert relmax(sol.download(tt), ref) <= 1e-11
+    # without the coarse correction the linear solves need more iterations
+    base, tb, stb = _gpu(N, *_start(N)[1:], krylov_m=30)
+    rb = base.step(m.Physics.of(ph), stb, dt, sc)
+    assert rep.vcycles > rb.vcycles, (rep.vcycles, rb.vcycles)
+
+
 def test_steady_run_matches_oracle_33():
     """The whole steady run at 33x33 from the random start: the library's
     solve_steady takes the same accepted steps (dt x1.5 up to 0.1, stop at
