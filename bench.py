@@ -492,12 +492,14 @@ def fig1(args, M, I):
     import numpy as np
     import torch
     Ns = [int(v) for v in args.fig1_grids.split(",")]
-    if min(Ns) <= 16 or any(n & (n - 1) for n in Ns):
+    Rs = [int(v) for v in args.fig1_rgrids.split(",")] if args.fig1_rgrids else []
+    if min(Ns) <= 16 or any(n & (n - 1) for n in Ns + Rs):
         raise SystemExit("--fig1-grids: powers of two above 16 (the chain starts at 17x17)")
     phys = dict(I.PHYS)
     P = M.Physics.of(phys)
 
     def from_random(N, relax):
+        log("fig1: %s from the random start at %dx%d" % ("R" if relax else "M", N + 1, N + 1))
         if relax:
             os.environ["MGF_SMOOTHER_ONLY"] = "1"
         try:
@@ -511,7 +513,7 @@ def fig1(args, M, I):
         sc = schedule(M, args.lin_rtol)
         if relax:
             sc = M.schedule(dt0=1e-4, growth=1.5, dt_max=0.1, steady_tol=1e-8, lin_rtol=args.lin_rtol,
-                            max_steps=20000, max_cycles=args.fig1_rmax_cycles, coupling=M.NEWTON, max_newton=10,
+                            max_steps=2000, max_cycles=args.fig1_rmax_cycles, coupling=M.NEWTON, max_newton=10,
                             newton_tol=1e-6)
         torch.cuda.synchronize()
         t0 = time.time()
@@ -523,6 +525,7 @@ def fig1(args, M, I):
                     fgmres=rep.vcycles), fields
 
     def chained(N):
+        log("fig1: M+L chain 17x17 -> %dx%d" % (N + 1, N + 1))
         torch.cuda.synchronize()
         t0 = time.time()
         fine, t, P2, info = chain_to(M, I, N, phys["V_top"], args.lin_rtol, N0=16)
@@ -538,11 +541,14 @@ def fig1(args, M, I):
 
     from_random(16, False)  # first-use costs (library load, graph capture) outside the timings
     rows = []
-    for N in Ns:
+    for N in sorted(set(Ns) | set(n for n in Rs)):
         m, fm = from_random(N, False)
-        ml, fml = chained(N)
-        row = dict(N=N + 1, M=m, ML=ml, ML_vs_M=rel(fml, fm))
-        if N <= args.fig1_rmax:
+        row = dict(N=N + 1, M=m)
+        if N in Ns:
+            ml, fml = chained(N)
+            row["ML"] = ml
+            row["ML_vs_M"] = rel(fml, fm)
+        if N in Rs:
             r, fr = from_random(N, True)
             row["R"] = r
             row["R_vs_M"] = rel(fr, fm)
@@ -585,7 +591,8 @@ def main():
     ap.add_argument("--trace-summary", type=str, default="", help="summarise a rocprofv3 CSV and exit")
     ap.add_argument("--fig1", action="store_true", help="Sec. 3 Fig. 1 re-measured: R / M / M+L time vs N")
     ap.add_argument("--fig1-grids", type=str, default="32,64,128,256", help="N values, each > 16")
-    ap.add_argument("--fig1-rmax", type=int, default=64, help="largest N of the relaxation-only runs")
+    ap.add_argument("--fig1-rgrids", type=str, default="16,32",
+                    help="N values of the relaxation-only runs (65x65 and above take minutes)")
     ap.add_argument("--fig1-rmax-cycles", type=int, default=20000, help="FGMRES iterations per Newton, R runs")
     ap.add_argument("--prec", choices=["fp64", "fp32", "both"], default="fp64",
                     help="block preconditioner precision (FGMRES and Newton stay FP64)")

@@ -424,7 +424,9 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     if (const char *e = getenv("MGF_SWEEP_ROWS"))
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(e) == 16 ? 16 : 8;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->pinned_dev, c->pinned, 0);
     if (e != hipSuccess) {
+        if (c->pinned) (void)hipHostFree(c->pinned);
         delete c;
         return fail(MG_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
     }

@@ -206,6 +206,7 @@ struct NewtonWork {
     double *delta = nullptr;   // Newton correction
     double *snap = nullptr;    // state at the start of the step (V, ne, np)
     double *partials = nullptr;
+    double *partials2 = nullptr;  // second buffer: a pass reads one while writing the other
     double *dev = nullptr;     // device scalars (dots, norms, y)
     double *scratch = nullptr; // coarsest factorisation workspace
     float *f32 = nullptr;      // FP32 right-hand side of the preconditioner (level 0)
@@ -248,6 +249,7 @@ struct mg_ctx {
     double *scal = nullptr;      // device scalars
     double *coarse_scratch = nullptr;
     double *pinned = nullptr;    // host-pinned readback
+    double *pinned_dev = nullptr;  // the same memory as kernels address it
     double *spare[4] = {nullptr, nullptr, nullptr, nullptr};
     bool assembled[3] = {false, false, false};
     int64_t vcycles = 0;

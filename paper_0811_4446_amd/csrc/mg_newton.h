@@ -109,9 +109,17 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
 void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                      double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
                      const Batch &bt = Batch(), const BOp *J = nullptr, const double *z = nullptr);
-// dst = src / |.| from the norm partials of a self_norm pass; out[0] = |.|^2.
+// dst = src / |.| from the norm partials of a self_norm pass; out[0] = |.|^2
+// (also to out_host, pinned host memory, when given).
 void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
-                         double *out, hipStream_t s, const Batch &bt = Batch());
+                         double *out, hipStream_t s, const Batch &bt = Batch(), double *out_host = nullptr);
+// A Gram-Schmidt pass that first forms the projections h = V^T w of the
+// previous pass from that pass's workgroup partials h_part (same launch
+// grid; the result also to h_out and, when given, to pinned h_host), then
+// w -= V h and its own partials (partials must not alias h_part).
+void launch_cgs_pass_chained(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
+                             double3 cw, bool self_norm, const double *h_part, double *h_out, double *h_host,
+                             double *partials, hipStream_t s, const Batch &bt = Batch());
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                        const double *h, double sign, hipStream_t s, const Batch &bt = Batch());
 void launch_scale_by_norm(const Geom &g, const double *src, double *dst, int64_t plane, const double *nrm2,

@@ -1200,10 +1200,37 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
 // weighted dot products of (the updated) w with basis_0..basis_{nv-1}, or
 // with w itself (self_norm).  The grid-wide sums are formed by a following
 // launch (k_sum_cols or k_scale_reduce) in a fixed order.
+// Projections h_v = sum over the nblk workgroup partials (partial b of
+// column v at part[b * nv + v]) in a fixed order: lane l adds the partials b
+// = l, l + 64, ... in turn, then the 64 lane sums are combined by an xor
+// butterfly and lane 0's total is taken (the same bits in every workgroup).
+// One wavefront per column; the result goes to LDS hs[v], and workgroup
+// (0, 0) also stores it to out (device) and out_host (pinned host memory).
+inline __device__ void reduce_projections(const double *__restrict__ part, int nblk, int nv, double *hs,
+                                          double *out, double *out_host) {
+    for (int v = threadIdx.y; v < nv; v += blockDim.y) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kTX) a += part[(int64_t)b * nv + v];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        a = __shfl(a, 0);
+        if (threadIdx.x == 0) {
+            hs[v] = a;
+            if (blockIdx.x == 0 && blockIdx.y == 0) {
+                if (out) out[v] = a;
+                if (out_host) out_host[v] = a;
+            }
+        }
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ w, const double *__restrict__ basis,
                                                    int64_t vstride, int nv, int64_t plane, double3 cw,
                                                    const double *__restrict__ h_sub, int self_norm, BOp Jop,
                                                    const double *__restrict__ z, double *__restrict__ partials,
+                                                   const double *__restrict__ h_part, int h_nblk,
+                                                   double *__restrict__ h_out, double *__restrict__ h_host,
                                                    Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
@@ -1218,6 +1245,12 @@ __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ 
     const int j = blockIdx.x * kTX + threadIdx.x;
     const int i = blockIdx.y * blockDim.y + threadIdx.y;
     __shared__ double sh[kMaxTY][kMaxKrylov + 1];
+    __shared__ double hs[kMaxKrylov + 1];
+    if (h_part) {
+        // the previous pass's projections, formed here instead of by a launch of their own
+        reduce_projections(boff(h_part, bo_), h_nblk, nv, hs, boff(h_out, bo_), h_host);
+        h_sub = hs;
+    }
     const bool ok = i <= g.nr && j >= 1 && j < g.nz;
     const int64_t p = ok ? at(g, i, j) : 0;
     double wf[3] = {0.0, 0.0, 0.0};
@@ -1274,7 +1307,8 @@ __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ 
 // dst = src / sqrt(n2) with n2 the sum of the nblk norm partials (formed in
 // the same fixed order by every workgroup; workgroup 0 also stores it).
 __global__ void k_scale_reduce(Geom g, const double *__restrict__ src, double *__restrict__ dst, int64_t plane,
-                               const double *__restrict__ partials, int nblk, double *__restrict__ out, Batch bt) {
+                               const double *__restrict__ partials, int nblk, double *__restrict__ out,
+                               double *__restrict__ out_host, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     g = geom_off(g, bo_);
@@ -1291,7 +1325,10 @@ __global__ void k_scale_reduce(Geom g, const double *__restrict__ src, double *_
         for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
         if (threadIdx.x == 0) {
             n2s = a;
-            if (blockIdx.x == 0 && blockIdx.y == 0) out[0] = a;
+            if (blockIdx.x == 0 && blockIdx.y == 0) {
+                out[0] = a;
+                if (out_host) out_host[0] = a;
+            }
         }
     }
     __syncthreads();
@@ -1554,16 +1591,26 @@ void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstr
                      const Batch &bt, const BOp *J, const double *z) {
     dim3 gr = grid2d(g);
     k_cgs_pass<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, h_sub, self_norm ? 1 : 0,
-                                               J ? *J : BOp{nullptr, 0}, z, partials, bt);
+                                               J ? *J : BOp{nullptr, 0}, z, partials, nullptr, 0, nullptr,
+                                               nullptr, bt);
     if (out) {
         int nd = self_norm ? 1 : nv;
         k_sum_cols<<<dim3(nd, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nd, out, bt);
     }
 }
 void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
-                         double *out, hipStream_t s, const Batch &bt) {
+                         double *out, hipStream_t s, const Batch &bt, double *out_host) {
     dim3 gr = grid2d(g);
-    k_scale_reduce<<<gz(gr, bt), blk2d(g), 0, s>>>(g, src, dst, plane, partials, (int)(gr.x * gr.y), out, bt);
+    k_scale_reduce<<<gz(gr, bt), blk2d(g), 0, s>>>(g, src, dst, plane, partials, (int)(gr.x * gr.y), out,
+                                                   out_host, bt);
+}
+void launch_cgs_pass_chained(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
+                             double3 cw, bool self_norm, const double *h_part, double *h_out, double *h_host,
+                             double *partials, hipStream_t s, const Batch &bt) {
+    dim3 gr = grid2d(g);
+    k_cgs_pass<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, nullptr, self_norm ? 1 : 0,
+                                               BOp{nullptr, 0}, nullptr, partials, h_part, (int)(gr.x * gr.y),
+                                               h_out, h_host, bt);
 }
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                        const double *h, double sign, hipStream_t s, const Batch &bt) {

@@ -311,14 +311,19 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     }
     join_factor(c, s);  // (already joined by the V-cycle's coarse end)
     // w = J z_k, then classical Gram-Schmidt twice: h1 = V^T w; w -= V h1,
-    // h2 = V^T w; w -= V h2, |w|^2
-    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, W.partials, dev, s, c->bt, &J, zk);
-    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev, false, W.partials, dev + (m + 1), s, c->bt);
-    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev + (m + 1), true, W.partials, nullptr, s, c->bt);
-    launch_scale_reduce(g, W.w, vk1, p0, W.partials, dev + 2 * m + 2, s, c->bt);
-    // single problem: alternate between two pinned slots, so that step k+1
-    // can run while the host reads step k
-    readback(c, c->bt.n > 1 ? c->bpinned : c->pinned + kSlot * (k & 1), dev, 2 * m + 3, s);
+    // h2 = V^T w; w -= V h2, |w|^2.  Each pass forms the previous pass's
+    // projections from its workgroup partials (two partial buffers in turn).
+    // A single problem's projections and |w|^2 go straight to one of two
+    // pinned slots (step k+1 can run while the host reads step k); a batch's
+    // are copied afterwards.
+    double *P0 = W.partials, *P1 = W.partials2;
+    double *host = c->bt.n > 1 ? nullptr : c->pinned_dev + kSlot * (k & 1);
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, nullptr, s, c->bt, &J, zk);
+    launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, false, P0, dev, host, P1, s, c->bt);
+    launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, true, P1, dev + (m + 1), host ? host + (m + 1) : nullptr,
+                            P0, s, c->bt);
+    launch_scale_reduce(g, W.w, vk1, p0, P0, dev + 2 * m + 2, s, c->bt, host ? host + 2 * m + 2 : nullptr);
+    if (c->bt.n > 1) readback(c, c->bpinned, dev, 2 * m + 3, s);
 }
 
 int run_arnoldi(mg_ctx *c, int k, double3 cw);
@@ -592,6 +597,7 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
     double *snap = cv.take<double>(3 * p0);
     int nblk = ((d->nz + 1 + 63) / 64) * (d->nr + 1);  // one row per workgroup at most
     double *part = cv.take<double>((int64_t)nblk * (m + 2) + (int64_t)nblk * 8 + 64);
+    double *part2 = cv.take<double>((int64_t)nblk * (m + 2) + 64);
     double *dev = cv.take<double>(4 * kMaxKrylov + 64);
     float *f32 = (d->prec == MG_FP32_IR) ? cv.take<float>(3 * p0) : nullptr;
     if (c) {
@@ -603,6 +609,7 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
         c->nw.delta = delta;
         c->nw.snap = snap;
         c->nw.partials = part;
+        c->nw.partials2 = part2;
         c->nw.dev = dev;
     }
 }
@@ -860,6 +867,7 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     c->bt.active = act;
     c->bt.n = nprob;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->pinned_dev, c->pinned, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->active_host, nprob * sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&c->bpinned, (size_t)nprob * (2 * kMaxKrylov + 16) * sizeof(double),
