@@ -54,6 +54,11 @@ double3 field_weights(const mg_physics *ph) {
 // xc is set (fused_ok).
 void join_factor(mg_ctx *c, hipStream_t s);
 
+// Largest launch grid (workgroups) whose Gram-Schmidt passes form the
+// previous pass's projections themselves (measured: 325 workgroups at
+// 257x257 gain, several thousand at 1025x1025 lose).
+constexpr int kChainMaxBlocks = 512;
+
 template <class T>
 bool fused_ok(mg_ctx *c, int nu) { return c->nw.rb_fused && nu >= 2; }
 // Pairs of sweeps per launch on level l: every pre- and post-smoothing
@@ -316,14 +321,24 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     // A single problem's projections and |w|^2 go straight to one of two
     // pinned slots (step k+1 can run while the host reads step k); a batch's
     // are copied afterwards.
+    // Every workgroup of a chained pass reads all partials of the previous
+    // one, so large grids (many workgroups) sum them in launches of their own.
     double *P0 = W.partials, *P1 = W.partials2;
-    double *host = c->bt.n > 1 ? nullptr : c->pinned_dev + kSlot * (k & 1);
-    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, nullptr, s, c->bt, &J, zk);
-    launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, false, P0, dev, host, P1, s, c->bt);
-    launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, true, P1, dev + (m + 1), host ? host + (m + 1) : nullptr,
-                            P0, s, c->bt);
-    launch_scale_reduce(g, W.w, vk1, p0, P0, dev + 2 * m + 2, s, c->bt, host ? host + 2 * m + 2 : nullptr);
-    if (c->bt.n > 1) readback(c, c->bpinned, dev, 2 * m + 3, s);
+    if (block_vec_blocks(g) <= kChainMaxBlocks) {
+        double *host = c->bt.n > 1 ? nullptr : c->pinned_dev + kSlot * (k & 1);
+        launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, nullptr, s, c->bt, &J, zk);
+        launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, false, P0, dev, host, P1, s, c->bt);
+        launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, true, P1, dev + (m + 1),
+                                host ? host + (m + 1) : nullptr, P0, s, c->bt);
+        launch_scale_reduce(g, W.w, vk1, p0, P0, dev + 2 * m + 2, s, c->bt, host ? host + 2 * m + 2 : nullptr);
+        if (c->bt.n > 1) readback(c, c->bpinned, dev, 2 * m + 3, s);
+        return;
+    }
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, dev, s, c->bt, &J, zk);
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev, false, P0, dev + (m + 1), s, c->bt);
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev + (m + 1), true, P0, nullptr, s, c->bt);
+    launch_scale_reduce(g, W.w, vk1, p0, P0, dev + 2 * m + 2, s, c->bt);
+    readback(c, c->bt.n > 1 ? c->bpinned : c->pinned + kSlot * (k & 1), dev, 2 * m + 3, s);
 }
 
 int run_arnoldi(mg_ctx *c, int k, double3 cw);
