@@ -165,13 +165,17 @@ def roofline_only(args, M, I):
     print(json.dumps({"roofline": roof}), flush=True)
 
 
-def trace_summary(path, top=25):
+def trace_summary(path, top=25, tail_kernel="k_block_rb_sweep<", tail=200):
     """Summary of a rocprofv3 CSV: a kernel trace (per kernel and grid
     shape: calls, total and average duration) or a counter collection (per
-    kernel, grid shape and counter: dispatches and mean value)."""
+    kernel, grid shape and counter: dispatches and mean value).  For a
+    trace, also the mean duration of the last `tail` dispatches of
+    `tail_kernel` on its largest grid: the roofline loop's launches, which
+    come last in the benchmark."""
     import csv
     import collections
     agg = collections.OrderedDict()
+    tails = collections.defaultdict(list)
     kind = None
     with open(path) as f:
         rd = csv.DictReader(f)
@@ -189,6 +193,8 @@ def trace_summary(path, top=25):
                 e = agg.setdefault(key, [0, 0])
                 e[0] += 1
                 e[1] += d
+                if tail_kernel in name:
+                    tails[grid].append((int(row["Start_Timestamp"]), d))
             else:
                 key = (name[:70], grid, row["Counter_Name"])
                 e = agg.setdefault(key, [0, 0.0])
@@ -199,6 +205,16 @@ def trace_summary(path, top=25):
         print("%-70s %-16s %9s %12s %10s %7s" % ("kernel", "grid", "calls", "total_ms", "avg_us", "share"))
         for (name, grid), (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
             print("%-70s %-16s %9d %12.3f %10.3f %6.2f%%" % (name, grid, c, t / 1e6, t / c / 1e3, 100.0 * t / tot))
+        if tails:
+            def size(g):
+                n = 1
+                for v in g.split("x"):
+                    n *= int(v)
+                return n
+            grid = max(tails, key=size)
+            last = [d for _, d in sorted(tails[grid])[-tail:]]
+            print("last %d dispatches of %s on grid %s: mean %.3f us" % (len(last), tail_kernel.rstrip("<"), grid,
+                                                                        sum(last) / len(last) / 1e3))
     else:
         print("%-70s %-16s %-14s %9s %16s" % ("kernel", "grid", "counter", "dispatches", "mean_per_dispatch"))
         for (name, grid, cn), (c, v) in agg.items():

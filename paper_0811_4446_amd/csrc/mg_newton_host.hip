@@ -56,17 +56,20 @@ void join_factor(mg_ctx *c, hipStream_t s);
 
 // Largest launch grid (workgroups) whose Gram-Schmidt passes form the
 // previous pass's projections themselves (measured: 325 workgroups at
-// 257x257 gain, several thousand at 1025x1025 lose).
+// 257x257 gain, several thousand at 1025x1025 lose); single problems only,
+// a batch's column sums cover all its problems in one launch.
 constexpr int kChainMaxBlocks = 512;
 
 template <class T>
 bool fused_ok(mg_ctx *c, int nu) { return c->nw.rb_fused && nu >= 2; }
 // Pairs of sweeps per launch on level l: every pre- and post-smoothing
-// count even and the level small enough.
+// count even and the launch small enough to be latency-bound (nodes of all
+// problems of a batch counted; larger launches are throughput-bound, where
+// two one-sweep launches are faster).
 bool sweep2_ok(const mg_ctx *c, int l) {
     const Geom &g = c->lev[l].g;
-    return c->nw.rb_fused && (int64_t)(g.nr + 1) * (g.nz + 1) <= c->nw.sweep2_max_nodes && c->desc.nu1 >= 2 &&
-           c->desc.nu2 >= 2 && c->desc.nu1 % 2 == 0 && c->desc.nu2 % 2 == 0;
+    return c->nw.rb_fused && (int64_t)(g.nr + 1) * (g.nz + 1) * c->bt.n <= c->nw.sweep2_max_nodes &&
+           c->desc.nu1 >= 2 && c->desc.nu2 >= 2 && c->desc.nu1 % 2 == 0 && c->desc.nu2 % 2 == 0;
 }
 
 template <class T>
@@ -324,7 +327,7 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     // Every workgroup of a chained pass reads all partials of the previous
     // one, so large grids (many workgroups) sum them in launches of their own.
     double *P0 = W.partials, *P1 = W.partials2;
-    if (block_vec_blocks(g) <= kChainMaxBlocks) {
+    if (c->bt.n == 1 && block_vec_blocks(g) <= kChainMaxBlocks) {
         double *host = c->bt.n > 1 ? nullptr : c->pinned_dev + kSlot * (k & 1);
         launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, nullptr, s, c->bt, &J, zk);
         launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, false, P0, dev, host, P1, s, c->bt);
