@@ -14,7 +14,7 @@ A bench "step" is the timed 257x257 stage for all three voltages, from
 initial states already resident in HBM.  `value` is the mean
 time-to-steady per voltage (seconds, lower is better).
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build uses one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the solver runs on one GPU.
 """
 import argparse
 import json
@@ -616,8 +616,8 @@ def main():
     if args.trace_summary:
         return trace_summary(args.trace_summary)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (asked for %d); the batch of "
-              "independent solves would shard across GPUs, see the design notes" % args.gpus)
+        print("bench.py: the solver runs on one GPU only (asked for %d); a batch of independent "
+              "solves would shard across GPUs by problem" % args.gpus)
         sys.exit(2)
 
     import torch

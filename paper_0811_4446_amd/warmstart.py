@@ -268,7 +268,7 @@ def compare(net, data, timed=8, criterion="run", log=print, prec=M.FP32_IR, atte
     chosen = []
     for p in range(n):
         chosen.append(res["plain"]["finals"][p] if fb[p] else res["raw"]["finals"][p])
-    # the judge: both final states, polished by steady Newton, are the same discrete solution
+    # the check of the answer: both final states, polished by steady Newton, are the same discrete solution
     sol = data["sol"]
     d_final, d_pol, d_to_pol = [], [], []
     for p in range(n):

@@ -44,3 +44,40 @@ def test_counter_summary_averages_per_dispatch(tmp_path):
     assert r.returncode == 0, r.stderr
     row = r.stdout.splitlines()[1].split()
     assert row[2] == "93024" and row[3] == "FETCH_SIZE" and row[4] == "2" and float(row[5]) == 20.0
+
+
+def test_trace_summary_reports_the_roofline_loop_tail(tmp_path):
+    """The mean of the last dispatches of the one-sweep kernel on its largest
+    grid (the roofline loop comes last in the benchmark); the two-sweep kernel
+    and smaller grids are not counted."""
+    p = tmp_path / "t.csv"
+    rows = ['"Kind","Kernel_Name","Start_Timestamp","End_Timestamp","Grid_Size_X","Grid_Size_Y","Grid_Size_Z"']
+    t = 0
+    for d in (50000, 40000):  # early, slower dispatches of the large grid
+        rows.append('"K","void mgf::(anonymous namespace)::k_block_rb_sweep<double, 8>(int)",%d,%d,288,363,1'
+                    % (t, t + d))
+        t += 100000
+    rows.append('"K","void mgf::(anonymous namespace)::k_block_rb_sweep<double, 8>(int)",%d,%d,96,99,1'
+                % (t, t + 3000))
+    t += 100000
+    rows.append('"K","void mgf::(anonymous namespace)::k_block_rb_sweep2<double, 8>(int)",%d,%d,1600,17,1'
+                % (t, t + 9000))
+    t += 100000
+    for d in (7000, 8000, 9000):
+        rows.append('"K","void mgf::(anonymous namespace)::k_block_rb_sweep<double, 8>(int)",%d,%d,288,363,1'
+                    % (t, t + d))
+        t += 100000
+    p.write_text("\n".join(rows) + "\n")
+    r = subprocess.run([sys.executable, "-c", "import sys; sys.path.insert(0, %r); import bench; "
+                        "bench.trace_summary(%r, tail=3)" % (ROOT, str(p))], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    last = r.stdout.splitlines()[-1]
+    assert "288x363x1" in last and last.endswith("mean 8.000 us"), last
+
+
+def test_fig1_rejects_grids_the_chain_cannot_reach():
+    r = _run("--fig1", "--fig1-grids", "16,32")
+    assert r.returncode != 0 and "powers of two above 16" in (r.stdout + r.stderr)
+    r = _run("--fig1", "--fig1-grids", "48")
+    assert r.returncode != 0 and "powers of two above 16" in (r.stdout + r.stderr)
