@@ -1206,11 +1206,24 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
 // butterfly and lane 0's total is taken (the same bits in every workgroup).
 // One wavefront per column; the result goes to LDS hs[v], and workgroup
 // (0, 0) also stores it to out (device) and out_host (pinned host memory).
+// The loads of a lane's partials are issued together (kChainLoads per pass:
+// one pass for the grids that chain their passes), then added in order.
+constexpr int kChainLoads = 8;
 inline __device__ void reduce_projections(const double *__restrict__ part, int nblk, int nv, double *hs,
                                           double *out, double *out_host) {
     for (int v = threadIdx.y; v < nv; v += blockDim.y) {
         double a = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kTX) a += part[(int64_t)b * nv + v];
+        for (int b0 = threadIdx.x; b0 < nblk; b0 += kTX * kChainLoads) {
+            double q[kChainLoads];
+#pragma unroll
+            for (int u = 0; u < kChainLoads; ++u) {
+                const int b = b0 + u * kTX;
+                q[u] = b < nblk ? part[(int64_t)b * nv + v] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kChainLoads; ++u)
+                if (b0 + u * kTX < nblk) a += q[u];
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
         a = __shfl(a, 0);
