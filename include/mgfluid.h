@@ -170,6 +170,21 @@ int solve_steady(mg_ctx *ctx, const mg_physics *phys, mg_state *st,
  * 1/vol) at the state st; needs krylov_m >= 1.  Synchronises. */
 int mg_steady_residual(mg_ctx *ctx, const mg_physics *phys, const mg_state *st, double *norm_out);
 
+/* The preconditioner of the Newton linear solves on its own (Sec. 2: the
+ * Jacobian system of Eq. (14) solved by multigrid): assembles the 3x3-block
+ * Jacobian at the state st on every level (coarse levels at the injected
+ * state) for a backward-Euler step of size dt (dt = +inf: the steady
+ * Jacobian), factors the coarsest level, and applies one collective
+ * red-black block V(nu1, nu2) cycle from a zero guess: z = M r.  r and z are
+ * device pointers to three consecutive planes (n_e, n_p, V rows), each
+ * (nr+1) x pitch FP64, caller-owned; r's electrode rows are ignored, z's are
+ * written as zero.  The block V-cycle runs in FP32 when the context was
+ * built with MG_FP32_IR (r and z stay FP64).  Needs krylov_m >= 1 and a
+ * single-problem context; overwrites the context's Newton work arrays.
+ * MG_EINVAL: null pointers, dt <= 0 or NaN, batch context.  Synchronises. */
+int mg_newton_precond(mg_ctx *ctx, const mg_physics *phys, const mg_state *st, double dt, const double *r,
+                      double *z);
+
 /* Multilevel prolongation (Sec. 2): interpolate the state of the grid of
  * `coarse` onto the twice finer grid of `fine` (bilinear, the multigrid
  * prolongation), electrode rows set from phys.  Both contexts must share R,

@@ -182,3 +182,85 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
             break
         dt = min(growth * dt, dt_max)
     return acc, rej, seq
+
+
+# ---------------------------------------------------------------------------
+# Block multigrid for the Newton system (Sec. 2: Eq. (14) solved by the
+# multigrid method).  Hierarchy: the grid halved in r and z until the
+# oracle's level rule stops (coarse z nodes are every second fine node),
+# the Jacobian rediscretised on every level at the state injected there;
+# smoother: collective red-black Gauss-Seidel (the three unknowns of a node
+# solved together; nodes with (i + j) even first); restriction: the
+# transpose of the bilinear prolongation, field by field; coarsest level
+# solved exactly.
+# ---------------------------------------------------------------------------
+def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8):
+    """Per level: the Coupled system, its Jacobian (CSR) for a BE step of
+    size dt (inf: steady), the unknown indices of both colours."""
+    from . import levels as _nlev
+    nlev = _nlev(nr, nz, coarsest)
+    dt_inv = 0.0 if not np.isfinite(dt) else 1.0 / dt
+    out = []
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    V, ne, np_ = (np.ascontiguousarray(a, dtype=np.float64) for a in (V, ne, np_))
+    for l in range(nlev):
+        cp = Coupled(nr, nz, R, z, phys)
+        zero = np.zeros_like(V)
+        (_, (Ae, Ap)) = cp.residual(V, ne, np_, ne, np_, zero, zero, dt_inv)
+        J = cp.jacobian(V, ne, np_, Ae, Ap).tocsr()
+        colour = (cp.ii + cp.jj) % 2
+        idx = [np.nonzero(np.repeat(colour == c, 3))[0] for c in (0, 1)]
+        out.append(dict(cp=cp, J=J, z=z, idx=idx,
+                        lu=[spla.splu(J[ix][:, ix].tocsc()) for ix in idx]))
+        if l + 1 < nlev:
+            nr, nz = nr // 2, nz // 2
+            z = np.ascontiguousarray(z[::2])
+            V, ne, np_ = (np.ascontiguousarray(a[::2, ::2]) for a in (V, ne, np_))
+    return out
+
+
+def block_colour_sweep(L, f, x, colour):
+    """Every node of one colour takes the value that satisfies its three
+    equations with the other colour's current values (the nodes of one
+    colour do not couple to each other)."""
+    ix = L["idx"][colour]
+    r = f - L["J"] @ x
+    x[ix] += L["lu"][colour].solve(r[ix])
+
+
+def _fieldwise(L, vec, fn):
+    planes = L["cp"].unpack(vec)
+    return [fn(p) for p in planes]
+
+
+def block_restrict(L, Lc, r):
+    from . import restrict
+    planes = _fieldwise(L, r, lambda p: restrict(L["z"], p))
+    return Lc["cp"].pack(*[p for p in planes])
+
+
+def block_prolong(L, Lc, xc):
+    from . import prolong_add
+    out = []
+    for pc in Lc["cp"].unpack(xc):
+        pf = np.zeros((L["cp"].nr + 1, L["cp"].nz + 1))
+        prolong_add(L["z"], np.ascontiguousarray(pc), pf)
+        out.append(pf)
+    return L["cp"].pack(*out)
+
+
+def block_vcycle(levels, f, l=0, nu1=2, nu2=2):
+    """One V(nu1, nu2) cycle for J x = f on level l from x = 0; returns x."""
+    L = levels[l]
+    if l == len(levels) - 1:
+        return spla.spsolve(L["J"].tocsc(), f)
+    x = np.zeros_like(f)
+    for _ in range(nu1):
+        block_colour_sweep(L, f, x, 0)
+        block_colour_sweep(L, f, x, 1)
+    fc = block_restrict(L, levels[l + 1], f - L["J"] @ x)
+    x += block_prolong(L, levels[l + 1], block_vcycle(levels, fc, l + 1, nu1, nu2))
+    for _ in range(nu2):
+        block_colour_sweep(L, f, x, 0)
+        block_colour_sweep(L, f, x, 1)
+    return x

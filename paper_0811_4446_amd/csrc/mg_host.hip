@@ -738,6 +738,15 @@ int mg_steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, doub
     return steady_residual(c, ph, st, norm_out);
 }
 
+int mg_newton_precond(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt, const double *r,
+                      double *z) {
+    if (int e = check_ctx(c)) return e;
+    if (!ph || !st || !r || !z || !st->V || !st->ne || !st->np || !st->Se || !st->Sp)
+        return fail(MG_EINVAL, "null argument");
+    if (!(dt > 0)) return fail(MG_EINVAL, "dt must be > 0 (infinity for the steady Jacobian)");
+    return newton_precond(c, ph, st, dt, r, z);
+}
+
 int wn_param_count(void) { return kWnParams; }
 
 int wn_scratch_bytes(int32_t B, int32_t H, int32_t W, int64_t *bytes) {

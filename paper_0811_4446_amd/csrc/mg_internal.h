@@ -270,6 +270,7 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl);
 int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
                          mg_report *rep, bool *converged);
 int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep);
+int newton_precond(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt, const double *r, double *z);
 // mode 0: half-sweep, 1: one full sweep per launch, 2: two full sweeps per launch
 int time_block_smoother(mg_ctx *c, int reps, int mode, double *avg_ms);
 void drop_graphs(mg_ctx *c);

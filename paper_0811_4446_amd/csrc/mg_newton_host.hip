@@ -1156,6 +1156,31 @@ int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double 
     return MG_OK;
 }
 
+// One block V(nu1, nu2) cycle z = M r at the Newton Jacobian of the state
+// st, every level assembled as for an implicit step of size dt (dt = inf:
+// the steady Jacobian); the coarsest inverse on the context stream.
+int newton_precond(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt, const double *r, double *z) {
+    if (c->nw.m <= 0) return fail(MG_EINVAL, "no Newton workspace (krylov_m = 0)");
+    if (c->bt.n > 1) return fail(MG_EINVAL, "a single-problem context is needed");
+    hipStream_t s = c->stream;
+    const double dt_inv = std::isfinite(dt) ? 1.0 / dt : 0.0;
+    copy_state(c, st, c->nw.snap);
+    assemble_all(c, ph, st, dt_inv);
+    coarse_factor(c, s);
+    const int64_t vs = 3 * plane_of(c->lev[0]);
+    launch_fill(z, vs, 0.0, s);
+    if (c->nw.prec32) {
+        float *x32 = c->nw.lev[0].x32;
+        launch_planes_to_f32(r, c->nw.f32, vs, s, c->bt);
+        block_vcycle<float>(c, 0, c->nw.f32, x32, s);
+        launch_planes_to_f64(x32, z, vs, s, c->bt);
+    } else {
+        block_vcycle<double>(c, 0, r, z, s);
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
 int time_block_smoother(mg_ctx *c, int reps, int mode, double *avg_ms) {
     if (c->nw.m <= 0) return fail(MG_EINVAL, "no Newton workspace (krylov_m = 0)");
     const Level &L0 = c->lev[0];

@@ -94,6 +94,8 @@ SIGNATURES = {
                                           ctypes.POINTER(Report)]),
     "mg_set_tuning": (ctypes.c_int, [_VP, _I32, _I32]),
     "mg_steady_residual": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _PD]),
+    "mg_newton_precond": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), ctypes.c_double,
+                                         _VP, _VP]),
     "wn_param_count": (ctypes.c_int, []),
     "wn_scratch_bytes": (ctypes.c_int, [_I32, _I32, _I32, ctypes.POINTER(_I64)]),
     "wn_forward": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _I64, _VP]),
@@ -261,6 +263,18 @@ class Solver:
         r = _D(0.0)
         _check(lib().mg_steady_residual(self.ctx, ctypes.byref(phys), ctypes.byref(state), ctypes.byref(r)))
         return r.value
+
+    def field3(self):
+        """Three consecutive planes (n_e, n_p, V rows), the layout of
+        mg_newton_precond's vectors."""
+        return torch.zeros((3, self.nr + 1, self.pitch), dtype=torch.float64, device=self.device)
+
+    def precond(self, phys, state, dt, r, z):
+        """z = M r: one block V-cycle at the Newton Jacobian of `state`
+        (mg_newton_precond); r and z from field3()."""
+        assert r.shape == z.shape == (3, self.nr + 1, self.pitch)
+        _check(lib().mg_newton_precond(self.ctx, ctypes.byref(phys), ctypes.byref(state), float(dt), _ptr(r),
+                                       _ptr(z)))
 
     def time_kernel(self, which, eq=0, reps=50):
         ms = _D(0.0)

@@ -109,3 +109,83 @@ def test_steady_fixed_point_and_global_balance():
         from tests.test_oracle_pins import _electrode_outflow
         out = _electrode_outflow(1.0, z, s, mu, D, V, n)
         assert abs(out - src) <= 1e-9 * src
+
+
+def _hier(N, dt, coarsest=4, seed=0):
+    z, V, ne, np_ = _state(N, seed)[:4]
+    return NW.block_hierarchy(N, N, 1.0, z, dict(I.PHYS), V, ne, np_, dt, coarsest=coarsest)
+
+
+def test_block_colour_sweep_solves_its_nodes():
+    """After a half-sweep the three equations of every node of that colour
+    hold exactly (to rounding), and the other colour is untouched."""
+    L = _hier(16, 1e-2)[0]
+    rng = np.random.default_rng(3)
+    f = rng.normal(size=L["J"].shape[0])
+    x = rng.normal(size=f.size)
+    for c in (0, 1):
+        before = x.copy()
+        NW.block_colour_sweep(L, f, x, c)
+        r = f - L["J"] @ x
+        ix, other = L["idx"][c], L["idx"][1 - c]
+        assert np.abs(r[ix]).max() <= 1e-12 * np.abs(f).max() * 1e3
+        assert np.array_equal(x[other], before[other])
+
+
+def test_block_vcycle_single_level_is_the_exact_solve():
+    """With one level the cycle is the coarsest-grid solve: x = J^-1 f."""
+    levels = _hier(4, 1e-2, coarsest=4)
+    assert len(levels) == 1
+    f = np.random.default_rng(4).normal(size=levels[0]["J"].shape[0])
+    x = NW.block_vcycle(levels, f)
+    assert np.abs(levels[0]["J"] @ x - f).max() <= 1e-10 * np.abs(f).max()
+
+
+@pytest.mark.parametrize("dt", [1e-4])
+def test_block_vcycle_iteration_converges_to_the_solution(dt):
+    """At a small step (diagonally strong Jacobian) x <- x + V(f - J x)
+    converges to J^-1 f (a wrong sign, weight or transfer in the cycle would
+    stall or diverge), and the cycle is a linear map of f.  At larger steps
+    the stationary iteration need not converge (on this perturbed state it
+    diverges from dt = 1e-3), which is why the cycle preconditions FGMRES."""
+    levels = _hier(16, dt)
+    J = levels[0]["J"]
+    assert len(levels) == 3
+    rng = np.random.default_rng(5)
+    f = rng.normal(size=J.shape[0])
+    exact = NW.spla.spsolve(J.tocsc(), f)
+    x = np.zeros_like(f)
+    errs = []
+    for _ in range(25):
+        x += NW.block_vcycle(levels, f - J @ x)
+        errs.append(np.abs(x - exact).max() / np.abs(exact).max())
+    assert errs[-1] <= 1e-10, errs
+    g = rng.normal(size=f.size)
+    lin = NW.block_vcycle(levels, 2.0 * f - 3.0 * g)
+    assert np.abs(lin - (2.0 * NW.block_vcycle(levels, f) - 3.0 * NW.block_vcycle(levels, g))).max() \
+        <= 1e-12 * np.abs(lin).max()
+
+
+def test_block_transfers_are_adjoint_and_exact_on_bilinear():
+    """Field by field, restriction is the transpose of prolongation, and
+    prolongation reproduces functions bilinear in (r, z) at the fine nodes."""
+    levels = _hier(16, 1e-2)
+    L, Lc = levels[0], levels[1]
+    rng = np.random.default_rng(6)
+    u = rng.normal(size=Lc["J"].shape[0])
+    v = rng.normal(size=L["J"].shape[0])
+    lhs = np.dot(NW.block_prolong(L, Lc, u), v)
+    rhs = np.dot(u, NW.block_restrict(L, Lc, v))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    zc, zf = Lc["z"], L["z"]
+    rc = np.linspace(0.0, 1.0, 9)[:, None]
+    rf = np.linspace(0.0, 1.0, 17)[:, None]
+    # a field linear in r and constant in z (zero on the electrode rows, where corrections vanish)
+    gc = (1.0 + 2.0 * rc) * np.ones((1, zc.size))
+    gc[:, 0] = gc[:, -1] = 0.0
+    pf = Lc["cp"].pack(gc, 2 * gc, 3 * gc)
+    out = L["cp"].unpack(NW.block_prolong(L, Lc, pf))
+    want = (1.0 + 2.0 * rf) * np.ones((1, zf.size))
+    # away from the first and last fine interior nodes (their coarse neighbour is an electrode)
+    for k, fac in enumerate((1, 2, 3)):
+        assert np.abs(out[k][:, 2:-2] - fac * want[:, 2:-2]).max() <= 1e-13
