@@ -93,7 +93,8 @@ def test_relaxation_only_preconditioner_matches_oracle(monkeypatch):
 @pytest.mark.parametrize("N,dt,pre,mode", [(32, 1e-3, 0, "default"), (64, 0.1, 12, "default"),
                                             (64, 0.1, 12, "no_fuse"), (64, 0.1, 12, "one_sweep"),
                                             (64, 0.1, 12, "half"), (128, 1e-2, 0, "default"),
-                                            (64, 0.1, 12, "fp32")])
+                                            (64, 0.1, 12, "fp32"), ((32, 64), 1e-2, 0, "default"),
+                                            ((64, 32), 1e-2, 0, "no_fuse"), (64, float("inf"), 12, "default")])
 def test_block_vcycle_matches_oracle(N, dt, pre, mode, monkeypatch):
     """One block V(2,2) cycle z = M r at the Newton Jacobian of a state
     (mg_newton_precond) against the oracle's cycle written from its
@@ -103,33 +104,38 @@ def test_block_vcycle_matches_oracle(N, dt, pre, mode, monkeypatch):
     two sweeps per launch, half-sweeps, and the FP32 cycle."""
     _say("block vcycle", N, dt, pre, mode)
     m = M()
-    z, V, ne, np_, S = _start(N)
+    nr, nz = N if isinstance(N, tuple) else (N, N)
+    z = I.z_cos(nz)
+    ne = I.initial_density(nr, nz, 0)
+    np_ = ne.copy()
+    V = I.initial_potential(nr, nz, z)
+    S = I.source(nr, nz, z)
     ph = dict(I.PHYS)
     if pre:
-        cp = NW.Coupled(N, N, 1.0, z, ph)
+        cp = NW.Coupled(nr, nz, 1.0, z, ph)
         NW.steady(cp, V, ne, np_, S, S, max_steps=pre)
     env = {"no_fuse": "MGF_NO_FUSE", "one_sweep": "MGF_ONE_SWEEP", "half": "MGF_HALF_SWEEPS"}.get(mode)
     if env:
         monkeypatch.setenv(env, "1")
     prec = m.FP32_IR if mode == "fp32" else m.FP64
-    sol = m.Solver(N, N, z, coarsest=4, krylov_m=10, prec=prec)
+    sol = m.Solver(nr, nz, z, coarsest=4, krylov_m=10, prec=prec)
     if env:
         monkeypatch.delenv(env, raising=False)
     t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)]
     st = sol.state(t[0], t[1], t[2], t[3], t[3])
-    levels = NW.block_hierarchy(N, N, 1.0, z, ph, V, ne, np_, dt, coarsest=4)
+    levels = NW.block_hierarchy(nr, nz, 1.0, z, ph, V, ne, np_, dt, coarsest=4)
     assert len(levels) == sol.nlev, (len(levels), sol.nlev)
-    rng = np.random.default_rng(N + pre)
-    planes = [rng.normal(size=(N + 1, N + 1)) for _ in range(3)]
+    rng = np.random.default_rng(nr + 3 * nz + pre)
+    planes = [rng.normal(size=(nr + 1, nz + 1)) for _ in range(3)]
     for p_ in planes:
         p_[:, 0] = p_[:, -1] = 0.0
     import torch
     r, zt = sol.field3(), sol.field3()
     for k in range(3):
-        r[k, :, : N + 1] = torch.from_numpy(planes[k]).to(r.device)
+        r[k, :, : nz + 1] = torch.from_numpy(planes[k]).to(r.device)
     sol.precond(m.Physics.of(ph), st, dt, r, zt)
     torch.cuda.synchronize()
-    got = zt[:, :, : N + 1].cpu().numpy()
+    got = zt[:, :, : nz + 1].cpu().numpy()
     want = levels[0]["cp"].unpack(NW.block_vcycle(levels, levels[0]["cp"].pack(*planes)))
     tol = 1e-4 if mode == "fp32" else 1e-10
     for k in range(3):
