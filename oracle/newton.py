@@ -129,9 +129,10 @@ def newton_step(cp, V, ne, np_, Se, Sp, dt, max_newton=10, tol=1e-6, history=Non
         ne += dne
         np_ += dnp
         V += dV
-        rel = [np.abs(dne).sum() / max(np.abs(ne).sum(), 1e-300),
-               np.abs(dnp).sum() / max(np.abs(np_).sum(), 1e-300),
-               np.abs(dV).sum() / max(np.abs(V).sum(), 1e-300)]
+        un = (slice(None), slice(1, -1))  # unknown nodes only (electrode rows are fixed)
+        rel = [np.abs(dne[un]).sum() / max(np.abs(ne[un]).sum(), 1e-300),
+               np.abs(dnp[un]).sum() / max(np.abs(np_[un]).sum(), 1e-300),
+               np.abs(dV[un]).sum() / max(np.abs(V[un]).sum(), 1e-300)]
         if history is not None:
             history.append(rel)
         if not np.all(np.isfinite(du)):
@@ -142,13 +143,14 @@ def newton_step(cp, V, ne, np_, Se, Sp, dt, max_newton=10, tol=1e-6, history=Non
 
 
 def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
-           max_steps=100000, newton_tol=1e-6, max_newton=10, dts=None, log=None):
+           max_steps=100000, newton_tol=1e-6, max_newton=10, dts=None, log=None, attempts=None):
     """Steps with dt <- min(growth*dt, dt_max) until max over species of
     ||n^{k+1}-n^k||_2/||n^{k+1}||_2 < tol.  A step whose Newton iteration
     does not converge, or that ends with a density below -1e-10 times its
     mean magnitude, is rejected: it is retried with the last accepted step
     (Sec. 2), or with half the step if it already was that long.  If `dts`
-    is given, that sequence of accepted steps is replayed instead.
+    is given, that sequence of accepted steps is replayed instead.  If
+    `attempts` is a list, every tried step is appended as (dt, accepted).
     Returns (steps, rejected, dt_list)."""
     dt = dt0
     dt_acc = 0.0
@@ -164,6 +166,8 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
             un = (slice(None), slice(1, -1))
             ok = (ne[un].min() >= -1e-10 * np.abs(ne[un]).mean()
                   and np_[un].min() >= -1e-10 * np.abs(np_[un]).mean())
+        if attempts is not None:
+            attempts.append((dt, bool(ok)))
         if not ok:
             V[:], ne[:], np_[:] = s0
             rej += 1
@@ -182,6 +186,42 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
             break
         dt = min(growth * dt, dt_max)
     return acc, rej, seq
+
+
+def prolong_state(zf, Vc, nec, npc, phys):
+    """Multilevel prolongation (Sec. 2, last paragraphs): the state of the
+    grid one level coarser, interpolated onto the twice finer grid with the
+    multigrid prolongation (bilinear, z-distance weights) on the unknown
+    rows, and the electrode rows set to their boundary values."""
+    from . import prolong_add
+    nrc, nzc = Vc.shape[0] - 1, Vc.shape[1] - 1
+    out = []
+    for c, lo, hi in ((Vc, "V_bottom", "V_top"), (nec, "ne_bottom", "ne_top"), (npc, "np_bottom", "np_top")):
+        f = np.zeros((2 * nrc + 1, 2 * nzc + 1))
+        prolong_add(zf, np.ascontiguousarray(c, dtype=np.float64), f)
+        f[:, 0], f[:, -1] = phys[lo], phys[hi]
+        out.append(f)
+    return out
+
+
+def chain(R, z_of, phys, N0, N1, V, ne, np_, S_of, **steady_kw):
+    """Multilevel prolongation chain (Sec. 2): steady run on the N0 grid from
+    (V, ne, np_), then for each finer grid up to N1 the steady run from the
+    prolonged steady state of the grid before.  z_of(N) gives the axial
+    nodes, S_of(N, z) the source.  Returns the finest steady state and the
+    accepted step count of every stage."""
+    N = N0
+    stages = []
+    while True:
+        z = z_of(N)
+        cp = Coupled(N, N, R, z, phys)
+        S = S_of(N, z)
+        acc, rej, _ = steady(cp, V, ne, np_, S, S, **steady_kw)
+        stages.append((N, acc, rej))
+        if N == N1:
+            return (V, ne, np_), stages
+        V, ne, np_ = prolong_state(z_of(2 * N), V, ne, np_, phys)
+        N *= 2
 
 
 # ---------------------------------------------------------------------------
