@@ -421,6 +421,7 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
     if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
+    if (const char *e = getenv("MGF_CHAIN_MAX_BLOCKS")) c->nw.chain_max_blocks = atoi(e);
     if (const char *e = getenv("MGF_SWEEP_ROWS"))
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(e) == 16 ? 16 : 8;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
@@ -466,6 +467,8 @@ void mg_destroy(mg_ctx *ctx) {
     // work still queued (a speculative Arnoldi step) may copy into pinned memory
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->active_host) (void)hipHostFree(ctx->active_host);
+    for (hipEvent_t ev : ctx->active_ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (ctx->bpinned) (void)hipHostFree(ctx->bpinned);
     drop_graphs(ctx);
     if (ctx->nw.cap) (void)hipStreamDestroy(ctx->nw.cap);

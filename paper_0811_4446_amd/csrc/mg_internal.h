@@ -187,6 +187,9 @@ struct Carver {
     }
 };
 
+// Pinned staging slots of a batch's active flags (used in turn).
+constexpr int kActiveSlots = 8;
+
 // Per-level storage of the coupled (3x3-block) Newton path.
 struct BLevel {
     double *J;      // kBPlanes planes
@@ -225,6 +228,9 @@ struct NewtonWork {
     // many nodes; larger levels launch one sweep at a time, which is faster
     // there (measured crossover between 129^2 and 257^2)
     int64_t sweep2_max_nodes = 129 * 129;
+    // largest launch grid (workgroups) whose Gram-Schmidt passes form the
+    // previous pass's projections themselves (single problems only)
+    int chain_max_blocks = 512;
     hipEvent_t ev[2] = {nullptr, nullptr};  // readback of Arnoldi steps k (even / odd)
     // the coarsest factorisation runs on `side` as a branch of Arnoldi step 0
     // (fork: evf[0] on the step's stream; join: evf[1], awaited before the
@@ -258,7 +264,13 @@ struct mg_ctx {
     mgf::Batch bt;
     void *php_dev = nullptr;      // device NewtonPhys[bt.n] in batch mode
     double *lohi_dev = nullptr;   // device electrode values, 6 per problem
-    int *active_host = nullptr;   // pinned mirror of bt.active
+    // pinned staging of the active flags: kActiveSlots slots of bt.n flags,
+    // used in turn; a slot is rewritten only after the copy that last read
+    // it has run (its event), so back-to-back uploads never race
+    int *active_host = nullptr;
+    hipEvent_t active_ev[mgf::kActiveSlots] = {};
+    bool active_ev_used[mgf::kActiveSlots] = {};
+    int active_seq = 0;
     double *bpinned = nullptr;    // pinned batch readback buffer
     char *ws_base = nullptr;
     int64_t ws_bytes = 0;         // bytes of one problem's solver workspace

@@ -54,11 +54,11 @@ double3 field_weights(const mg_physics *ph) {
 // xc is set (fused_ok).
 void join_factor(mg_ctx *c, hipStream_t s);
 
-// Largest launch grid (workgroups) whose Gram-Schmidt passes form the
-// previous pass's projections themselves (measured: 325 workgroups at
-// 257x257 gain, several thousand at 1025x1025 lose); single problems only,
-// a batch's column sums cover all its problems in one launch.
-constexpr int kChainMaxBlocks = 512;
+// Gram-Schmidt passes that form the previous pass's projections themselves
+// pay on grids of at most chain_max_blocks workgroups (default 512;
+// measured: 325 workgroups at 257x257 gain, several thousand at 1025x1025
+// lose); single problems only, a batch's column sums cover all its problems
+// in one launch.
 
 template <class T>
 bool fused_ok(mg_ctx *c, int nu) { return c->nw.rb_fused && nu >= 2; }
@@ -327,7 +327,7 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     // Every workgroup of a chained pass reads all partials of the previous
     // one, so large grids (many workgroups) sum them in launches of their own.
     double *P0 = W.partials, *P1 = W.partials2;
-    if (c->bt.n == 1 && block_vec_blocks(g) <= kChainMaxBlocks) {
+    if (c->bt.n == 1 && block_vec_blocks(g) <= W.chain_max_blocks) {
         double *host = c->bt.n > 1 ? nullptr : c->pinned_dev + kSlot * (k & 1);
         launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, nullptr, s, c->bt, &J, zk);
         launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, false, P0, dev, host, P1, s, c->bt);
@@ -717,10 +717,16 @@ struct BatchRun {
     std::vector<int> act;   // host copy of the active flags
 };
 
+// Upload the active flags through the next pinned slot.  The host waits for
+// the copy that last used that slot (recorded event) before rewriting it.
 int set_active(mg_ctx *c, const std::vector<int> &act) {
-    for (int p = 0; p < c->bt.n; ++p) c->active_host[p] = act[p];
-    HIP_OK(hipMemcpyAsync((void *)c->bt.active, c->active_host, c->bt.n * sizeof(int), hipMemcpyHostToDevice,
-                          c->stream));
+    int k = c->active_seq++ % kActiveSlots;
+    if (c->active_ev_used[k]) HIP_OK(hipEventSynchronize(c->active_ev[k]));
+    int *slot = c->active_host + (size_t)k * c->bt.n;
+    for (int p = 0; p < c->bt.n; ++p) slot[p] = act[p];
+    HIP_OK(hipMemcpyAsync((void *)c->bt.active, slot, c->bt.n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipEventRecord(c->active_ev[k], c->stream));
+    c->active_ev_used[k] = true;
     return MG_OK;
 }
 
@@ -872,6 +878,7 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
     if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
+    if (const char *e = getenv("MGF_CHAIN_MAX_BLOCKS")) c->nw.chain_max_blocks = atoi(e);
     if (const char *sr = getenv("MGF_SWEEP_ROWS"))
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(sr) == 16 ? 16 : 8;
     c->ws_base = base;
@@ -886,7 +893,10 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     c->bt.n = nprob;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->pinned_dev, c->pinned, 0);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&c->active_host, nprob * sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->active_host, (size_t)kActiveSlots * nprob * sizeof(int), hipHostMallocDefault);
+    for (int k = 0; k < kActiveSlots && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&c->active_ev[k], hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&c->bpinned, (size_t)nprob * (2 * kMaxKrylov + 16) * sizeof(double),
                           hipHostMallocDefault);

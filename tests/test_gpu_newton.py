@@ -59,8 +59,9 @@ def test_newton_step_matches_oracle(N, dt, pre):
     sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-13, max_cycles=400, max_newton=20, newton_tol=1e-11)
     rep = sol.step(m.Physics.of(ph), st, dt, sc)
     assert rep.newton_its == its, (rep.newton_its, its)
-    for tt, ref in zip(t[:3], (V, ne, np_)):
-        assert relmax(sol.download(tt), ref) <= 1e-11
+    errs = [relmax(sol.download(tt), ref) for tt, ref in zip(t[:3], (V, ne, np_))]
+    print("newton step %s dt %g: max rel err %s" % (N, dt, errs))
+    assert max(errs) <= 1e-12, errs
 
 
 def test_relaxation_only_preconditioner_matches_oracle(monkeypatch):
@@ -83,7 +84,7 @@ def test_relaxation_only_preconditioner_matches_oracle(monkeypatch):
     rep = sol.step(m.Physics.of(ph), st, dt, sc)
     assert rep.newton_its == its, (rep.newton_its, its)
     for tt, ref in zip(t[:3], (V, ne, np_)):
-        assert relmax(sol.download(tt), ref) <= 1e-11
+        assert relmax(sol.download(tt), ref) <= 1e-12
     # without the coarse correction the linear solves need more iterations
     base, tb, stb = _gpu(N, *_start(N)[1:], krylov_m=30)
     rb = base.step(m.Physics.of(ph), stb, dt, sc)
@@ -137,7 +138,9 @@ def test_block_vcycle_matches_oracle(N, dt, pre, mode, monkeypatch):
     torch.cuda.synchronize()
     got = zt[:, :, : nz + 1].cpu().numpy()
     want = levels[0]["cp"].unpack(NW.block_vcycle(levels, levels[0]["cp"].pack(*planes)))
-    tol = 1e-4 if mode == "fp32" else 1e-10
+    tol = 1e-4 if mode == "fp32" else 1e-12
+    errs = [np.abs(got[k] - want[k]).max() / np.abs(want[k]).max() for k in range(3)]
+    print("block vcycle %s dt %g %s: max rel err %s" % (N, dt, mode, errs))
     for k in range(3):
         scale = np.abs(want[k]).max()
         assert np.abs(got[k] - want[k]).max() <= tol * scale, (k, np.abs(got[k] - want[k]).max() / scale)
@@ -252,7 +255,7 @@ def test_fused_rb_sweep_matches_half_sweeps(N, monkeypatch):
 def test_newton_step_rectangular_grid(nr, nz, prec_name):
     """N_r != N_z (ragged sweep tiles and a rectangular coarsest grid): one
     BE step after 10 oracle steps of the steady schedule matches the oracle's
-    Newton iterates (FP64 preconditioner: 1e-11; FP32 preconditioner inside
+    Newton iterates (FP64 preconditioner: 1e-12; FP32 preconditioner inside
     FP64 FGMRES, converged to the same tolerance: 1e-9)."""
     _say("newton step rectangular", nr, nz, prec_name)
     m = M()
@@ -271,6 +274,7 @@ def test_newton_step_rectangular_grid(nr, nz, prec_name):
     sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-13, max_cycles=400, max_newton=20, newton_tol=1e-11)
     rep = sol.step(m.Physics.of(ph), st, dt, sc)
     assert rep.newton_its == its, (rep.newton_its, its)
-    tol = 1e-11 if prec_name == "FP64" else 1e-9
-    for tt, ref in zip(t[:3], (V, ne, np_)):
-        assert relmax(sol.download(tt), ref) <= tol
+    tol = 1e-12 if prec_name == "FP64" else 1e-9
+    errs = [relmax(sol.download(tt), ref) for tt, ref in zip(t[:3], (V, ne, np_))]
+    print("rectangular %dx%d %s: max rel err %s" % (nr, nz, prec_name, errs))
+    assert max(errs) <= tol, errs

@@ -72,6 +72,46 @@ def test_gradient_matches_cpu_reference(B, H, W):
             off += n
 
 
+def test_train_steps_match_oracle_adam():
+    """Three wn_train_step calls (gradient + Adam, step counter 1..3) against
+    the oracle: the gradient of the bf16-emulated network (FP64) and the
+    oracle's Adam recurrences.  The first moment is linear in the gradients
+    (held to the gradient tolerance), the second moment quadratic; each
+    parameter's total move is compared wherever its gradient is not lost in
+    the bf16 noise."""
+    _say("wn train step vs oracle adam")
+    m = M()
+    p = _params(8)
+    rng = np.random.default_rng(9)
+    B, H, W = 1, 17, 24
+    x = rng.normal(size=(B, 7, H, W))
+    t = rng.normal(size=(B, 3, H, W))
+    x32, t32 = x.astype(np.float32), t.astype(np.float32)
+    lr = 1e-3
+    net = m.Net(p)
+    xt, tt = torch.tensor(x32, device="cuda"), torch.tensor(t32, device="cuda")
+    for _ in range(3):
+        net.train_step(xt, tt, lr=lr)
+    got_p = net.params.cpu().numpy().astype(np.float64)
+    got_m = net.m.cpu().numpy().astype(np.float64)
+    got_v = net.v.cpu().numpy().astype(np.float64)
+    p0 = p.astype(np.float32).astype(np.float64)
+    pr, mr, vr = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    gs = []
+    for step in (1, 2, 3):
+        _, g = cnn.loss_and_grad(pr, x32.astype(np.float64), t32.astype(np.float64), bf16=True)
+        gs.append(g)
+        cnn.adam(pr, g, mr, vr, step, lr=lr)
+    em = np.linalg.norm(got_m - mr) / np.linalg.norm(mr)
+    ev = np.linalg.norm(got_v - vr) / np.linalg.norm(vr)
+    big = np.min([np.abs(g) for g in gs], axis=0) >= 0.05 * np.max([np.abs(g).max() for g in gs])
+    ep = np.abs((got_p - p0) - (pr - p0))[big].max() / lr
+    print("adam x3: m rel %.2e, v rel %.2e, move err %.2e lr on %d params" % (em, ev, ep, big.sum()))
+    assert em <= 2e-2 and ev <= 4e-2
+    assert big.sum() >= 100 and ep <= 5e-2
+    assert np.abs(got_p - p0).max() <= 3 * lr * 1.01
+
+
 def test_training_reduces_loss():
     _say("wn train")
     m = M()
