@@ -239,6 +239,17 @@ int wn_grad(const float *params, const float *in, const float *target, int32_t B
 int wn_train_step(float *params, float *adam_m, float *adam_v, int32_t step, float lr, const float *in,
                   const float *target, int32_t B, int32_t H, int32_t W, double *loss_out, void *scratch,
                   int64_t scratch_bytes, void *stream);
+/* wn_forward without a scratch argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the activations live in one static
+ * device array per GPU (about 17 MB, held until the process ends), so the
+ * call allocates nothing.  Limit: B*H*W <= 66049 (one 257x257 image);
+ * larger batches return MG_EINVAL.  Same kernels and results as wn_forward
+ * (bitwise).  Calls that overlap on one GPU share that array and race:
+ * serialise them (one stream, or events).  Call with the stream's device
+ * current; the first call on a device looks up its array's address. */
+int wn_forward_noalloc(const float *params, const float *in, float *out, int32_t B, int32_t H, int32_t W,
+                       void *stream);
 /* Input planes of one sample (out: [7][H][W]) from the prolonged coarse
  * state `up` on the grid of `fine`: V/V_top, n_e/n_s, n_p/n_s, r/R, z/d,
  * V_top/5, log10(ratio)/3, where n_s (written to nscale_dev, one device

@@ -10,6 +10,9 @@
 // Activations are NHWC bf16 with 32 channel slots (H = radial nodes, W =
 // axial nodes, so a row is one radial line of the solver's fields).
 #include <math.h>
+#include <string.h>
+
+#include <mutex>
 
 #include "wn_net.h"
 
@@ -526,3 +529,95 @@ void launch_apply(const Geom &g, const double *Vu, const double *neu, const doub
 }
 
 }  // namespace mgf
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward pass (wn_forward_noalloc): the same kernels as
+// wn_forward, with the activations in one file-scope device array per GPU
+// instead of a caller-provided scratch buffer.  Buffers are reused across
+// layers (input planes -> A -> input buffer -> A; one pre-activation buffer
+// for every layer, which the forward pass only writes) and the last layer
+// writes the caller's output directly, so the results are bitwise those of
+// wn_forward.  Nothing in the forward pass accumulates into scratch memory,
+// so no clearing is needed; calls that overlap on one GPU race on it.
+// ---------------------------------------------------------------------------
+namespace mgf {
+namespace {
+
+constexpr int64_t kStaticMaxPixels = 257 * 257;  // B * H * W of one 257x257 image
+constexpr int64_t round256(int64_t n) { return (n + 255) / 256 * 256; }
+constexpr int64_t kStaticWeightBytes = 4 * 9 * kC * kC * 2;
+constexpr int64_t kStaticActBytes = kStaticMaxPixels * kC * 2;
+constexpr int64_t kStaticZBytes = kStaticMaxPixels * kC * 4;
+constexpr int64_t kStaticScratchBytes =
+    2 * round256(kStaticWeightBytes) + round256(4 * kC * 4) + 2 * round256(kStaticActBytes) + round256(kStaticZBytes);
+
+}  // namespace
+}  // namespace mgf
+
+// The array itself: in host code this name is only a stand-in for the
+// symbol; kernels receive the device address from hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[mgf::kStaticScratchBytes];
+
+namespace mgf {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char *g_static_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int static_scratch(char **out) {
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MG_EINVAL, "device %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256) return fail(MG_EHIP, "scratch array address %p", p);
+        g_static_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_static_ptr[dev];
+    return MG_OK;
+}
+
+}  // namespace
+}  // namespace mgf
+
+extern "C" int wn_forward_noalloc(const float *params, const float *in, float *out, int32_t B, int32_t H, int32_t W,
+                                  void *stream) {
+    using namespace mgf;
+    if (!params || !in || !out) return fail(MG_EINVAL, "null pointer");
+    if (B < 1 || H < 1 || W < 1) return fail(MG_EINVAL, "bad image batch shape %d x %d x %d", B, H, W);
+    if ((int64_t)B * H * W > kStaticMaxPixels)
+        return fail(MG_EINVAL, "B*H*W = %lld exceeds the %lld pixels of the static scratch array",
+                    (long long)B * H * W, (long long)kStaticMaxPixels);
+    char *base = nullptr;
+    if (int e = static_scratch(&base)) return e;
+    int64_t npix = (int64_t)B * H * W;
+    int64_t off = 0;
+    auto take = [&](int64_t n) {
+        char *p = base + off;
+        off += round256(n);
+        return p;
+    };
+    Scratch s;
+    memset(&s, 0, sizeof s);
+    s.WB = (__bf16 *)take(kStaticWeightBytes);
+    s.WT = (__bf16 *)take(kStaticWeightBytes);
+    s.bias = (float *)take(4 * kC * 4);
+    __bf16 *bx = (__bf16 *)take(npix * kC * 2);
+    __bf16 *ba = (__bf16 *)take(npix * kC * 2);
+    float *z = (float *)take(npix * kC * 4);
+    if (off > kStaticScratchBytes) return fail(MG_EINVAL, "static scratch layout overflow");
+    s.X0 = bx;
+    s.A[0] = ba;  // layer 1: input planes -> ba
+    s.A[1] = bx;  // layer 2: ba -> bx (the input planes are no longer read)
+    s.A[2] = ba;  // layer 3: bx -> ba; layer 4 reads ba
+    s.Z[0] = s.Z[1] = s.Z[2] = z;
+    s.OUT = out;
+    forward_pass(s, params, in, B, H, W, reinterpret_cast<hipStream_t>(stream));
+    HIP_OK(hipGetLastError());
+    return MG_OK;
+}

@@ -99,6 +99,7 @@ SIGNATURES = {
     "wn_param_count": (ctypes.c_int, []),
     "wn_scratch_bytes": (ctypes.c_int, [_I32, _I32, _I32, ctypes.POINTER(_I64)]),
     "wn_forward": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _I64, _VP]),
+    "wn_forward_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _VP]),
     "wn_grad": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _I32, _VP, _PD, _VP, _I64, _VP]),
     "wn_train_step": (ctypes.c_int, [_VP, _VP, _VP, _I32, ctypes.c_float, _VP, _VP, _I32, _I32, _I32, _PD, _VP,
                                      _I64, _VP]),
@@ -380,6 +381,15 @@ class Net:
         s, n = self.scratch(B, H, W)
         _check(lib().wn_forward(_ptr(self.params), _ptr(x), _ptr(out), B, H, W, _ptr(s), n,
                                 ctypes.c_void_p(self.stream.cuda_stream)))
+        return out
+
+    def forward_noalloc(self, x, out):
+        """wn_forward_noalloc: the forward pass with the library's static
+        scratch array (no scratch tensor; out is caller-allocated)."""
+        B, C, H, W = x.shape
+        assert out.shape == (B, 3, H, W) and out.dtype == torch.float32
+        _check(lib().wn_forward_noalloc(_ptr(self.params), _ptr(x), _ptr(out), B, H, W,
+                                        ctypes.c_void_p(self.stream.cuda_stream)))
         return out
 
     def grad(self, x, target):
