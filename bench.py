@@ -12,7 +12,12 @@ change per step drops below 1e-8.  Applied voltage V_top in {0.5, 1, 2}.
 
 A bench "step" is the timed 257x257 stage for all three voltages, from
 initial states already resident in HBM.  `value` is the mean
-time-to-steady per voltage (seconds, lower is better).
+time-to-steady per voltage (seconds, lower is better).  After the timed
+steps, once per voltage: the chain continued to 513x513 and prolonged to
+1025x1025, whose steady solve is timed with the FP64 and with the FP32
+block preconditioner (config.t1025).  The roofline entry is the kernel with
+the largest share of GPU time in the 257x257 solve; the finest-level sweep
+at 257x257 (cache-resident) and at 1025x1025 (HBM) is reported beside it.
 
 Prints one JSON line.  --gpus N with N > 1 exits: the solver runs on one GPU.
 """
@@ -109,34 +114,88 @@ def cpu_baseline(I, newton_its_gpu, vtop=1.0, N=256):
     du = spla.splu(J).solve(-cp.pack(Fe, Fp, FV))
     per_it = time.time() - t0
     assert du.shape[0] == J.shape[0]
-    return dict(value=round(per_it * newton_its_gpu, 1), unit="s", cores=1, kind="oracle",
-                sample="1 oracle Newton iteration at %dx%d (residual, Jacobian, sparse LU) = %.2f s, "
-                       "x %d Newton iterations of the GPU run (extrapolated)" % (N + 1, N + 1, per_it,
-                                                                                 newton_its_gpu))
+    return dict(value=round(per_it * newton_its_gpu, 1), unit="s", cores=1, kind="oracle", host=_host(),
+                sample="1 oracle Newton iteration at %dx%d (residual, Jacobian, sparse LU; single thread) = %.2f s "
+                       "from the seeded start (the sparse LU's cost depends on the grid, not on the state), x %d "
+                       "Newton iterations of the GPU run (extrapolated)" % (N + 1, N + 1, per_it, newton_its_gpu))
 
 
-def roofline(sol, N, reps=200):
-    """Roofline entry of the dominant kernel, the one-launch collective
-    red-black block sweep (k_block_rb_sweep) on the finest level: its
-    average launch duration from HIP events recorded on the library's
-    stream around `reps` consecutive sweeps (the Jacobian of the last
-    solve), against the algorithmic bytes of one sweep: per unknown node 27
-    Jacobian entries, 3 right-hand-side values and 3 old unknowns read, 3
-    new unknowns written (FP64)."""
+def _host():
+    """Host CPU model and logical core count (for the oracle baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(cpu=model, nproc=os.cpu_count())
+
+
+def _traffic(N):
     import hashlib
-    avg_ms = sol.time_kernel(4, 0, reps=reps)
-    nodes = (N + 1) * (N - 1)
     with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"])) as fh:
         src = fh.read()
     a, e = src.find(MEASURED_TRAFFIC["begin"]), src.find(MEASURED_TRAFFIC["end"])
     same = 0 <= a < e and hashlib.sha1(src[a:e].encode()).hexdigest() == MEASURED_TRAFFIC["sha1"]
-    traffic = MEASURED_TRAFFIC["bytes"].get(N) if same else None
+    return MEASURED_TRAFFIC["bytes"].get(N) if same else None
+
+
+def roofline(sol, N, reps=200, resident=None):
+    """Roofline entry of the one-launch collective red-black block sweep
+    (k_block_rb_sweep) on the finest level: its average launch duration from
+    HIP events recorded on the library's stream around `reps` consecutive
+    sweeps (the Jacobian of the last solve), against the algorithmic bytes
+    of one sweep: per unknown node 27 Jacobian entries, 3 right-hand-side
+    values and 3 old unknowns read, 3 new unknowns written (FP64)."""
+    avg_ms = sol.time_kernel(4, 0, reps=reps)
+    nodes = (N + 1) * (N - 1)
     bytes_launch = 8.0 * nodes * 36
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    return dict(bound="hbm", kernel="k_block_rb_sweep", level="%dx%d" % (N + 1, N + 1), achieved=round(achieved, 1),
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                avg_launch_us=round(avg_ms * 1e3, 3), algorithmic_bytes_per_launch=int(bytes_launch),
-                timed_launches=reps)
+    out = dict(bound="hbm", kernel="k_block_rb_sweep", level="%dx%d" % (N + 1, N + 1), achieved=round(achieved, 1),
+               peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=_traffic(N),
+               avg_launch_us=round(avg_ms * 1e3, 3), algorithmic_bytes_per_launch=int(bytes_launch),
+               timed_launches=reps)
+    if resident:
+        out["resident"] = resident
+    return out
+
+
+def roofline_dominant(sol, N, reps=200):
+    """Roofline entry of the kernel with the largest share of GPU time in the
+    257x257 steady solve: the two-sweep collective red-black launch
+    (k_block_rb_sweep2) that smooths the levels 129x129, 65x65 and 33x33
+    (twice per V-cycle each: pre- and post-smoothing).  Per level, the mean
+    duration of `reps` back-to-back launches between HIP events on the
+    library's stream (the Jacobian of the last solve); algorithmic bytes of
+    one launch: per unknown node 27 Jacobian entries, 3 right-hand-side and 3
+    old values read once, 3 new values written (FP64, 288 B).  The entry's
+    achieved rate is the sum of those bytes over one V-cycle's launches
+    divided by their summed durations.  The working set of these levels
+    (under 5 MB) sits in the 256 MB Infinity Cache and each launch lasts a
+    few microseconds: the launches are bound by latency, not by HBM."""
+    levels = []
+    tot_b = tot_t = 0.0
+    n = N
+    for l in range(1, sol.nlev):
+        n //= 2
+        if n > 128 or n <= 16:  # two-sweep launches: 129^2 down to 33^2; below, the coarse sub-cycle
+            continue
+        avg_ms = sol.time_kernel(5, l, reps=reps)
+        b = 8.0 * 36 * (n + 1) * (n - 1)
+        levels.append(dict(level="%dx%d" % (n + 1, n + 1), avg_launch_us=round(avg_ms * 1e3, 3),
+                           algorithmic_bytes=int(b), GBps=round(b / (avg_ms * 1e-3) / 1e9, 1)))
+        tot_b += 2 * b
+        tot_t += 2 * avg_ms * 1e-3
+    achieved = tot_b / tot_t / 1e9
+    return dict(bound="hbm", kernel="k_block_rb_sweep2", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                resident="Infinity Cache (levels 129x129..33x33 of the 257x257 solve, < 5 MB)",
+                limited_by="launch and barrier latency (microsecond launches)",
+                unit_of_work="one V-cycle's two-sweep launches (pre and post on each level)",
+                levels=levels, timed_launches_per_level=reps)
 
 
 def roofline_only(args, M, I):
@@ -587,6 +646,7 @@ def main():
     ap.add_argument("--lin-rtol", type=float, default=1e-3)
     ap.add_argument("--vtops", type=str, default="0.5,1,2")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-1025", action="store_true", help="skip the 1025x1025 FP64 / FP32 time-to-steady")
     ap.add_argument("--grid", type=int, default=256, help="finest N (256: 257x257 workload; 1024 for 1025x1025)")
     ap.add_argument("--sweep", action="store_true", help="batched parameter sweep instead of the chain")
     ap.add_argument("--nprob", type=int, default=512)
@@ -670,26 +730,79 @@ def main():
     for vt, rd in reps:
         log("V_top=%g steps=%d newton=%d fgmres=%d t=%.3f s" % (vt, rd["steps"], rd["newton_its"],
                                                               rd["vcycles"], rd["seconds"]))
-    roof = roofline(cases[-1][1], N)
+    roof_dom = roofline_dominant(cases[-1][1], N)
+    roof_fine = roofline(cases[-1][1], N, resident="Infinity Cache (257x257 working set about 19 MB)")
+    log("roofline (dominant kernel): %s" % roof_dom)
     steps_mean = sum(rd["steps"] for _, rd in reps) / len(reps)
     newton_mean = sum(rd["newton_its"] for _, rd in reps) / len(reps)
+    per_v = []
+    for vt in vtops:
+        rs = [rd for v, rd in reps if v == vt]
+        secs = sorted(rd["seconds"] for rd in rs)
+        per_v.append(dict(V_top=vt, steps=rs[0]["steps"], newton=rs[0]["newton_its"], fgmres=rs[0]["vcycles"],
+                          seconds_median=round(secs[len(secs) // 2], 4), seconds_min=round(secs[0], 4),
+                          seconds_max=round(secs[-1], 4), runs=len(rs)))
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "steady 257x257 from the prolonged 129x129 steady state, coupled Newton BE, "
-                               "dt x1.5 to 0.1, stop at relative change 1e-8",
+                               "dt x1.5 to 0.1, stop at relative change 1e-8 (value: mean time-to-steady per "
+                               "voltage, FP64)",
                    "grid": "257x257, r uniform, z cos-stretched", "V_top": vtops,
-                   "lin_rtol": args.lin_rtol, "mean_steps": steps_mean,
-                   "runs": [dict(V_top=vt, steps=rd["steps"], newton=rd["newton_its"], fgmres=rd["vcycles"],
-                                 seconds=round(rd["seconds"], 3)) for vt, rd in reps],
-                   "chain": [dict(V_top=c[0], stages=c[4]) for c in cases]},
-        "roofline": roof,
+                   "lin_rtol": args.lin_rtol, "mean_steps": steps_mean, "per_voltage": per_v,
+                   "chain": [dict(V_top=c[0], stages=c[4]) for c in cases],
+                   "roofline_finest_257": roof_fine},
+        "roofline": roof_dom,
     }
+    if not args.no_1025:
+        out["config"]["t1025"] = time_to_steady_1025(args, M, I, vtops)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(I, int(round(newton_mean)))
     print(json.dumps(out), flush=True)
+
+
+def time_to_steady_1025(args, M, I, vtops, N=1024):
+    """1025x1025: for each voltage the chain 65 -> 129 -> 257 -> 513 (FP64,
+    steady at each stage) prolonged to 1025x1025, then the 1025x1025 steady
+    solve from that state with the FP64 block preconditioner and with the
+    FP32 one (Newton, FGMRES and the stop rules in FP64 for both); one run
+    per form and voltage.  Also the roofline of the finest-level sweep on the
+    1025x1025 Jacobian (working set beyond the Infinity Cache)."""
+    import numpy as np
+    import torch
+    rows, roof, dmax = [], None, []
+    for vt in vtops:
+        fine, t, P, info = chain_to(M, I, N, vt, args.lin_rtol)
+        init = [x.clone() for x in t[:3]]
+        finals = {}
+        for form, prec in (("fp64", M.FP64), ("fp32", M.FP32_IR)):
+            sol = M.Solver(N, N, I.z_cos(N), krylov_m=30, coarsest=4, prec=prec)
+            tt = [x.clone() for x in init] + [t[3]]
+            torch.cuda.synchronize()
+            t0 = time.time()
+            code, rep = sol.steady(P, sol.state(tt[0], tt[1], tt[2], tt[3], tt[3]), schedule(M, args.lin_rtol))
+            torch.cuda.synchronize()
+            el = time.time() - t0
+            if code != 0:
+                raise RuntimeError("1025x1025 steady failed: %s" % M.lib().mg_last_error())
+            finals[form] = [sol.download(x) for x in tt[:3]]
+            rows.append(dict(V_top=vt, form=form, seconds=round(el, 3), steps=rep.steps, newton=rep.newton_its,
+                             fgmres=rep.vcycles))
+            log("1025: %s" % rows[-1])
+            if form == "fp64" and roof is None:
+                roof = roofline(sol, N, resident="HBM (1025x1025 working set about 300 MB, beyond the "
+                                                 "256 MB Infinity Cache)")
+            del sol
+            torch.cuda.empty_cache()
+        dmax.append(max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(finals["fp32"], finals["fp64"])))
+        del fine, t, init
+        torch.cuda.empty_cache()
+    mean = {f: round(float(np.mean([r["seconds"] for r in rows if r["form"] == f])), 4) for f in ("fp64", "fp32")}
+    return dict(workload="steady 1025x1025 from the prolonged 513x513 steady state (chain from 65x65), mean of "
+                         "the voltages", fp64_mean_s=mean["fp64"], fp32_preconditioner_mean_s=mean["fp32"],
+                fp32_vs_fp64_final_state_maxrel=max(dmax), runs=rows, roofline_finest_1025=roof)
 
 
 if __name__ == "__main__":

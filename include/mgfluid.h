@@ -290,13 +290,14 @@ int mg_residual(mg_ctx *ctx, int eq, const double *x, double *r);
 /* Time one kernel of the hot path: `reps` back-to-back launches on the
  * context's stream between two HIP events; *avg_ms receives the mean
  * duration of one launch.  which: 0 collective red-black block smoother
- * half-sweep of the Newton system (level 0; needs an assembled Jacobian),
- * 1 zebra z-line half-sweep, 2 point red-black half-sweep, 3 residual
- * (scalar equation `eq`, assembled before), 4 full collective red-black
- * sweep in one launch (both colours; level 0, assembled Jacobian), 5 two
- * full collective red-black sweeps in one launch (level 0, assembled
- * Jacobian; what the block V-cycle launches when nu1 and nu2 are even).
- * Overwrites the level-0 work vectors only.  Synchronises. */
+ * half-sweep of the Newton system (needs an assembled Jacobian), 1 zebra
+ * z-line half-sweep, 2 point red-black half-sweep, 3 residual (scalar
+ * equation `eq`, assembled before; level 0), 4 full collective red-black
+ * sweep in one launch (both colours; assembled Jacobian), 5 two full
+ * collective red-black sweeps in one launch (assembled Jacobian; what the
+ * block V-cycle launches on small levels when nu1 and nu2 are even).  For
+ * the block kernels (0, 4, 5) `eq` is the grid level (0 = finest).
+ * Overwrites that level's work vectors only.  Synchronises. */
 int mg_time_kernel(mg_ctx *ctx, int which, int eq, int32_t reps, double *avg_ms);
 
 /* Thread-local message of the last error. */

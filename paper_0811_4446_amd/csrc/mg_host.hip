@@ -705,7 +705,7 @@ int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
     if (int e = check_ctx(c)) return e;
     if (!avg_ms || reps < 1) return fail(MG_EINVAL, "bad reps or null output");
     if (which == 0 || which == 4 || which == 5)
-        return time_block_smoother(c, reps, which == 5 ? 2 : which == 4 ? 1 : 0, avg_ms);
+        return time_block_smoother(c, reps, which == 5 ? 2 : which == 4 ? 1 : 0, eq, avg_ms);
     if (int e = check_eq(eq)) return e;
     if (!c->assembled[eq]) return fail(MG_EINVAL, "equation %d not assembled", eq);
     if (which < 1 || which > 3) return fail(MG_EINVAL, "bad kernel id %d", which);

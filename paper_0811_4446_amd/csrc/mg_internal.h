@@ -284,7 +284,7 @@ int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double d
 int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedule *sc, mg_report *rep);
 int newton_precond(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt, const double *r, double *z);
 // mode 0: half-sweep, 1: one full sweep per launch, 2: two full sweeps per launch
-int time_block_smoother(mg_ctx *c, int reps, int mode, double *avg_ms);
+int time_block_smoother(mg_ctx *c, int reps, int mode, int level, double *avg_ms);
 void drop_graphs(mg_ctx *c);
 int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double *out);
 int64_t carve_ctx(mg_ctx *c, const mg_grid_desc *d, char *base);

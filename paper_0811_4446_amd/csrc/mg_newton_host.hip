@@ -1191,11 +1191,12 @@ int newton_precond(mg_ctx *c, const mg_physics *ph, const mg_state *st, double d
     return MG_OK;
 }
 
-int time_block_smoother(mg_ctx *c, int reps, int mode, double *avg_ms) {
+int time_block_smoother(mg_ctx *c, int reps, int mode, int level, double *avg_ms) {
     if (c->nw.m <= 0) return fail(MG_EINVAL, "no Newton workspace (krylov_m = 0)");
-    const Level &L0 = c->lev[0];
-    BOp J = bop(c, 0);
-    double *x = c->nw.lev[0].x, *x2 = c->nw.lev[0].x2;
+    if (level < 0 || level >= c->nlev) return fail(MG_EINVAL, "bad level %d", level);
+    const Level &L0 = c->lev[level];
+    BOp J = bop(c, level);
+    double *x = c->nw.lev[level].x, *x2 = c->nw.lev[level].x2;
     auto one = [&](int r) {
         if (mode == 2)
             launch_block_rb_sweep2<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, false, nullptr,
