@@ -63,7 +63,9 @@ def lib():
         L.or_volume.restype = _D
         L.or_volume.argtypes = [_I, _I, _D, _P, _I, _I]
         L.or_poisson_assemble.argtypes = [_I, _I, _D, _P, _D, _P, _P] + [_P] * 6
+        L.or_poisson_assemble_w.argtypes = [_I, _I, _D, _P, _D, _P, _P, _I, _P] + [_P] * 6
         L.or_sg_assemble.argtypes = [_I, _I, _D, _P, _I, _D, _D, _D, _P, _P, _P] + [_P] * 6
+        L.or_sg_assemble_w.argtypes = [_I, _I, _D, _P, _I, _D, _D, _D, _I, _P, _P, _P] + [_P] * 6
         L.or_apply.argtypes = [_I, _I] + [_P] * 7
         L.or_residual.argtypes = [_I, _I] + [_P] * 8
         L.or_relres.restype = _D
@@ -78,6 +80,9 @@ def lib():
         L.or_levels.argtypes = [_I, _I, _I]
         L.or_mg_create.restype = ctypes.c_void_p
         L.or_mg_create.argtypes = [_I, _I, _D, _P, _I, _I, _I, _I]
+        L.or_mg_create_w.restype = ctypes.c_void_p
+        L.or_mg_create_w.argtypes = [_I, _I, _D, _P, _I, _I, _I, _I, _I]
+        L.or_mg_assemble_poisson_w.argtypes = [ctypes.c_void_p, _D, _P, _P, _P]
         L.or_mg_destroy.argtypes = [ctypes.c_void_p]
         L.or_mg_nlev.restype = _I
         L.or_mg_nlev.argtypes = [ctypes.c_void_p]
@@ -91,6 +96,11 @@ def lib():
         L.or_mg_solve.restype = _I
         L.or_mg_solve.argtypes = [ctypes.c_void_p, _P, _D, _I,
                                   ctypes.POINTER(_I), ctypes.POINTER(_D)]
+        L.or_step_decoupled_w.restype = _I
+        L.or_step_decoupled_w.argtypes = [_I, _I, _D, _P, ctypes.POINTER(Phys),
+                                          _P, _P, _P, _P, _P, _D,
+                                          _I, _I, _I, _I, _D, _I, _I,
+                                          ctypes.POINTER(_I), ctypes.POINTER(_D)]
         L.or_step_decoupled.restype = _I
         L.or_step_decoupled.argtypes = [_I, _I, _D, _P, ctypes.POINTER(Phys),
                                         _P, _P, _P, _P, _P, _D,
@@ -129,21 +139,33 @@ def volumes(nr, nz, R, z):
     return v
 
 
-def poisson_assemble(nr, nz, R, z, k, ne=None, np_=None):
-    """Coefficients (a, b, c, d, e, f) of Eqs. (12)-(13) in FV form."""
+def poisson_assemble(nr, nz, R, z, k, ne=None, np_=None, wall=0, Vwall=None):
+    """Coefficients (a, b, c, d, e, f) of Eqs. (12)-(13) in FV form.  wall=1:
+    Dirichlet wall at r = R (identity rows i = nr, right-hand side Vwall)."""
     z = np.ascontiguousarray(z, dtype=np.float64)
     out = [_field(nr, nz) for _ in range(6)]
-    lib().or_poisson_assemble(nr, nz, R, _p(z), k, _p(ne), _p(np_), *[_p(o) for o in out])
+    if Vwall is not None:
+        Vwall = np.ascontiguousarray(Vwall, dtype=np.float64)
+    lib().or_poisson_assemble_w(nr, nz, R, _p(z), k, _p(ne), _p(np_), int(wall), _p(Vwall),
+                                *[_p(o) for o in out])
     return out
 
 
-def sg_assemble(nr, nz, R, z, s, mu, D, dt_inv, V, nk=None, S=None):
-    """Coefficients (a, b, c, d, e, f) of Eqs. (7)-(11) in FV form."""
+def sg_assemble(nr, nz, R, z, s, mu, D, dt_inv, V, nk=None, S=None, wall=0):
+    """Coefficients (a, b, c, d, e, f) of Eqs. (7)-(11) in FV form.  wall=1:
+    Dirichlet wall at r = R with density 0 (identity rows i = nr)."""
     z = np.ascontiguousarray(z, dtype=np.float64)
     out = [_field(nr, nz) for _ in range(6)]
-    lib().or_sg_assemble(nr, nz, R, _p(z), int(s), mu, D, dt_inv, _p(V), _p(nk), _p(S),
-                         *[_p(o) for o in out])
+    lib().or_sg_assemble_w(nr, nz, R, _p(z), int(s), mu, D, dt_inv, int(wall), _p(V), _p(nk), _p(S),
+                           *[_p(o) for o in out])
     return out
+
+
+def wall_values(z, V_bottom, V_top):
+    """Wall potential of the paper's experiment (Sec. 3): linear in z between
+    the electrode values."""
+    z = np.asarray(z, dtype=np.float64)
+    return V_bottom + (V_top - V_bottom) * ((z - z[0]) / (z[-1] - z[0]))
 
 
 def apply(coef, x):
@@ -206,10 +228,10 @@ def levels(nr, nz, coarsest=8):
 class MG:
     """Multigrid hierarchy (V(nu1, nu2) cycle) of the oracle."""
 
-    def __init__(self, nr, nz, R, z, coarsest=8, smoother=SMOOTH_ZEBRA, nu1=2, nu2=2):
+    def __init__(self, nr, nz, R, z, coarsest=8, smoother=SMOOTH_ZEBRA, nu1=2, nu2=2, wall=0):
         self.nr, self.nz, self.R = nr, nz, R
         self.z = np.ascontiguousarray(z, dtype=np.float64)
-        self.h = lib().or_mg_create(nr, nz, R, _p(self.z), coarsest, smoother, nu1, nu2)
+        self.h = lib().or_mg_create_w(nr, nz, R, _p(self.z), coarsest, smoother, nu1, nu2, int(wall))
         if not self.h:
             raise ValueError("grid not coarsenable to %d" % coarsest)
         self.nlev = lib().or_mg_nlev(self.h)
@@ -220,8 +242,10 @@ class MG:
             _lib.or_mg_destroy(h)
             self.h = None
 
-    def assemble_poisson(self, k, ne, np_):
-        lib().or_mg_assemble_poisson(self.h, k, _p(ne), _p(np_))
+    def assemble_poisson(self, k, ne, np_, Vwall=None):
+        if Vwall is not None:
+            Vwall = np.ascontiguousarray(Vwall, dtype=np.float64)
+        lib().or_mg_assemble_poisson_w(self.h, k, _p(ne), _p(np_), _p(Vwall))
 
     def assemble_sg(self, s, mu, D, dt_inv, V, nk, S):
         lib().or_mg_assemble_sg(self.h, int(s), mu, D, dt_inv, _p(V), _p(nk), _p(S))
@@ -251,14 +275,15 @@ class MG:
 
 
 def step_decoupled(R, z, phys, V, ne, np_, Se, Sp, dt, coarsest=8, smoother=SMOOTH_RB,
-                   nu1=2, nu2=2, rtol=1e-10, max_cycles=500):
+                   nu1=2, nu2=2, rtol=1e-10, max_cycles=500, wall=0):
     """One backward-Euler step (Eq. 7): Poisson with n^k, then SG electrons and
-    ions with the new potential.  Updates V, ne, np_ in place."""
+    ions with the new potential.  Updates V, ne, np_ in place.  wall=1:
+    Dirichlet wall at r = R (potential linear in z, densities 0)."""
     nr, nz = V.shape[0] - 1, V.shape[1] - 1
     z = np.ascontiguousarray(z, dtype=np.float64)
     cyc = (_I * 3)()
     rr = (_D * 3)()
-    st = lib().or_step_decoupled(nr, nz, R, _p(z), ctypes.byref(phys), _p(V), _p(ne), _p(np_),
-                                 _p(Se), _p(Sp), dt, coarsest, smoother, nu1, nu2, rtol,
-                                 max_cycles, cyc, rr)
+    st = lib().or_step_decoupled_w(nr, nz, R, _p(z), ctypes.byref(phys), _p(V), _p(ne), _p(np_),
+                                   _p(Se), _p(Sp), dt, coarsest, smoother, nu1, nu2, rtol,
+                                   max_cycles, int(wall), cyc, rr)
     return st, list(cyc), list(rr)

@@ -100,10 +100,26 @@ double or_bernoulli_G(double x)
 /* The electrode rows are not assembled (their coefficients are zero). */
 /* ------------------------------------------------------------------ */
 
+/* wall != 0: Dirichlet wall at r = R (the paper's experiment, Sec. 3): the
+ * nodes i = nr are fixed, their rows are the identity with right-hand side
+ * Vwall[j] (NULL: 0, the correction equations of the coarse levels). */
+void or_poisson_assemble_w(int nr, int nz, double R, const double *z, double k,
+                           const double *ne, const double *np, int wall,
+                           const double *Vwall, double *a, double *b, double *c,
+                           double *d, double *e, double *f);
+
 void or_poisson_assemble(int nr, int nz, double R, const double *z, double k,
                          const double *ne, const double *np,
                          double *a, double *b, double *c, double *d, double *e,
                          double *f)
+{
+    or_poisson_assemble_w(nr, nz, R, z, k, ne, np, 0, NULL, a, b, c, d, e, f);
+}
+
+void or_poisson_assemble_w(int nr, int nz, double R, const double *z, double k,
+                           const double *ne, const double *np, int wall,
+                           const double *Vwall, double *a, double *b, double *c,
+                           double *d, double *e, double *f)
 {
     double dr = R / nr;
     size_t n = (size_t)(nr + 1) * (nz + 1);
@@ -117,6 +133,11 @@ void or_poisson_assemble(int nr, int nz, double R, const double *z, double k,
         double w = radial_width(i, nr, R);
         for (int j = 1; j < nz; ++j) {
             size_t p = IDX(i, j, nz);
+            if (wall && i == nr) {
+                b[p] = 1.0;
+                f[p] = Vwall ? Vwall[j] : 0.0;
+                continue;
+            }
             double dzc = axial_width(z, j);
             double ca = (i > 0) ? face_radius(i - 1, nr, R) * dzc / dr : 0.0;
             double cc = (i < nr) ? face_radius(i, nr, R) * dzc / dr : 0.0;
@@ -146,11 +167,28 @@ void or_poisson_assemble(int nr, int nz, double R, const double *z, double k,
 /* dt_inv = 1/dt (0 gives the steady operator).                         */
 /* ------------------------------------------------------------------ */
 
+/* wall != 0: Dirichlet wall at r = R with density 0 there (Sec. 3): the
+ * rows i = nr are the identity with right-hand side 0. */
+void or_sg_assemble_w(int nr, int nz, double R, const double *z, int s,
+                      double mu, double D, double dt_inv, int wall,
+                      const double *V, const double *nk, const double *S,
+                      double *a, double *b, double *c, double *d, double *e,
+                      double *f);
+
 void or_sg_assemble(int nr, int nz, double R, const double *z, int s,
                     double mu, double D, double dt_inv,
                     const double *V, const double *nk, const double *S,
                     double *a, double *b, double *c, double *d, double *e,
                     double *f)
+{
+    or_sg_assemble_w(nr, nz, R, z, s, mu, D, dt_inv, 0, V, nk, S, a, b, c, d, e, f);
+}
+
+void or_sg_assemble_w(int nr, int nz, double R, const double *z, int s,
+                      double mu, double D, double dt_inv, int wall,
+                      const double *V, const double *nk, const double *S,
+                      double *a, double *b, double *c, double *d, double *e,
+                      double *f)
 {
     double dr = R / nr;
     double q = -(double)s * mu / D;
@@ -165,6 +203,10 @@ void or_sg_assemble(int nr, int nz, double R, const double *z, int s,
         double w = radial_width(i, nr, R);
         for (int j = 1; j < nz; ++j) {
             size_t p = IDX(i, j, nz);
+            if (wall && i == nr) {
+                b[p] = 1.0;
+                continue;
+            }
             double dzc = axial_width(z, j);
             double vol = w * dzc;
             double diag = vol * dt_inv;
@@ -531,7 +573,7 @@ typedef struct {
 } or_level;
 
 typedef struct {
-    int nlev, smoother, nu1, nu2;
+    int nlev, smoother, nu1, nu2, wall;
     or_level lev[20];
     double *work;
 } or_mg;
@@ -563,9 +605,18 @@ static double *alloc_field(int nr, int nz)
 }
 
 void or_mg_destroy(or_mg *h);
+or_mg *or_mg_create_w(int nr, int nz, double R, const double *z, int coarsest,
+                      int smoother, int nu1, int nu2, int wall);
 
 or_mg *or_mg_create(int nr, int nz, double R, const double *z, int coarsest,
                     int smoother, int nu1, int nu2)
+{
+    return or_mg_create_w(nr, nz, R, z, coarsest, smoother, nu1, nu2, 0);
+}
+
+/* wall != 0: every level has the Dirichlet wall rows at r = R. */
+or_mg *or_mg_create_w(int nr, int nz, double R, const double *z, int coarsest,
+                      int smoother, int nu1, int nu2, int wall)
 {
     int nlev = or_levels(nr, nz, coarsest);
     if (nlev < 1 || nlev > 20)
@@ -575,6 +626,7 @@ or_mg *or_mg_create(int nr, int nz, double R, const double *z, int coarsest,
     h->smoother = smoother;
     h->nu1 = nu1;
     h->nu2 = nu2;
+    h->wall = wall;
     for (int l = 0; l < nlev; ++l) {
         or_level *L = &h->lev[l];
         L->nr = nr >> l;
@@ -628,16 +680,23 @@ void or_mg_get(const or_mg *h, int l, int which, double *out)
     memcpy(out, src[which], (size_t)(L->nr + 1) * (L->nz + 1) * sizeof(double));
 }
 
-/* Poisson on every level; the charge enters the finest right-hand side. */
-void or_mg_assemble_poisson(or_mg *h, double k, const double *ne,
-                            const double *np)
+/* Poisson on every level; the charge (and the wall potential Vwall, nz+1
+ * values, with a Dirichlet wall) enters the finest right-hand side. */
+void or_mg_assemble_poisson_w(or_mg *h, double k, const double *ne,
+                              const double *np, const double *Vwall)
 {
     for (int l = 0; l < h->nlev; ++l) {
         or_level *L = &h->lev[l];
-        or_poisson_assemble(L->nr, L->nz, L->R, L->z, k, l == 0 ? ne : NULL,
-                            l == 0 ? np : NULL, L->a, L->b, L->c, L->d, L->e,
-                            L->f);
+        or_poisson_assemble_w(L->nr, L->nz, L->R, L->z, k, l == 0 ? ne : NULL,
+                              l == 0 ? np : NULL, h->wall, l == 0 ? Vwall : NULL,
+                              L->a, L->b, L->c, L->d, L->e, L->f);
     }
+}
+
+void or_mg_assemble_poisson(or_mg *h, double k, const double *ne,
+                            const double *np)
+{
+    or_mg_assemble_poisson_w(h, k, ne, np, NULL);
 }
 
 /* SG continuity on every level; coarse levels see the potential injected
@@ -655,9 +714,9 @@ void or_mg_assemble_sg(or_mg *h, int s, double mu, double D, double dt_inv,
     }
     for (int l = 0; l < h->nlev; ++l) {
         or_level *L = &h->lev[l];
-        or_sg_assemble(L->nr, L->nz, L->R, L->z, s, mu, D, dt_inv, L->V,
-                       l == 0 ? nk : NULL, l == 0 ? S : NULL, L->a, L->b, L->c,
-                       L->d, L->e, L->f);
+        or_sg_assemble_w(L->nr, L->nz, L->R, L->z, s, mu, D, dt_inv, h->wall,
+                         L->V, l == 0 ? nk : NULL, l == 0 ? S : NULL, L->a,
+                         L->b, L->c, L->d, L->e, L->f);
     }
 }
 
@@ -744,24 +803,62 @@ static void set_electrodes(int nr, int nz, double *u, double lo, double hi)
     }
 }
 
+/* Wall r = R (Sec. 3): potential interpolated linearly in z between the
+ * electrode values, densities 0. */
+static void set_wall(int nr, int nz, const double *z, const or_phys *ph,
+                     double *V, double *ne, double *np)
+{
+    for (int j = 0; j <= nz; ++j) {
+        double t = (z[j] - z[0]) / (z[nz] - z[0]);
+        V[IDX(nr, j, nz)] = ph->V_bottom + (ph->V_top - ph->V_bottom) * t;
+        ne[IDX(nr, j, nz)] = 0.0;
+        np[IDX(nr, j, nz)] = 0.0;
+    }
+}
+
+int or_step_decoupled_w(int nr, int nz, double R, const double *z,
+                        const or_phys *ph, double *V, double *ne, double *np,
+                        const double *Se, const double *Sp, double dt,
+                        int coarsest, int smoother, int nu1, int nu2,
+                        double rtol, int max_cycles, int wall, int *cycles3,
+                        double *relres3);
+
 int or_step_decoupled(int nr, int nz, double R, const double *z,
                       const or_phys *ph, double *V, double *ne, double *np,
                       const double *Se, const double *Sp, double dt,
                       int coarsest, int smoother, int nu1, int nu2, double rtol,
                       int max_cycles, int *cycles3, double *relres3)
 {
-    or_mg *h = or_mg_create(nr, nz, R, z, coarsest, smoother, nu1, nu2);
+    return or_step_decoupled_w(nr, nz, R, z, ph, V, ne, np, Se, Sp, dt, coarsest,
+                               smoother, nu1, nu2, rtol, max_cycles, 0, cycles3,
+                               relres3);
+}
+
+/* wall != 0: Dirichlet wall at r = R (set_wall values) on every equation. */
+int or_step_decoupled_w(int nr, int nz, double R, const double *z,
+                        const or_phys *ph, double *V, double *ne, double *np,
+                        const double *Se, const double *Sp, double dt,
+                        int coarsest, int smoother, int nu1, int nu2,
+                        double rtol, int max_cycles, int wall, int *cycles3,
+                        double *relres3)
+{
+    or_mg *h = or_mg_create_w(nr, nz, R, z, coarsest, smoother, nu1, nu2, wall);
     if (!h)
         return -1;
     size_t n = (size_t)(nr + 1) * (nz + 1);
     double *nk = malloc(n * sizeof(double));
+    double *Vw = malloc((size_t)(nz + 1) * sizeof(double));
     double dt_inv = 1.0 / dt;
     int st, worst = 0;
     set_electrodes(nr, nz, V, ph->V_bottom, ph->V_top);
     set_electrodes(nr, nz, ne, ph->ne_bottom, ph->ne_top);
     set_electrodes(nr, nz, np, ph->np_bottom, ph->np_top);
+    if (wall)
+        set_wall(nr, nz, z, ph, V, ne, np);
+    for (int j = 0; j <= nz; ++j)
+        Vw[j] = V[IDX(nr, j, nz)];
 
-    or_mg_assemble_poisson(h, ph->k, ne, np);
+    or_mg_assemble_poisson_w(h, ph->k, ne, np, wall ? Vw : NULL);
     st = or_mg_solve(h, V, rtol, max_cycles, &cycles3[0], &relres3[0]);
     if (st < worst)
         worst = st;
@@ -779,6 +876,7 @@ int or_step_decoupled(int nr, int nz, double R, const double *z,
         worst = st;
 
     free(nk);
+    free(Vw);
     or_mg_destroy(h);
     return worst;
 }
@@ -807,9 +905,21 @@ double or_bernoulli_dF(double x)
     return F * (1.0 - or_bernoulli_G(x)) / x;
 }
 
+void or_sg_dV_w(int nr, int nz, double R, const double *z, int s, double mu,
+                double D, int wall, const double *V, const double *n, double *a,
+                double *b, double *c, double *d, double *e);
+
 void or_sg_dV(int nr, int nz, double R, const double *z, int s, double mu,
               double D, const double *V, const double *n, double *a, double *b,
               double *c, double *d, double *e)
+{
+    or_sg_dV_w(nr, nz, R, z, s, mu, D, 0, V, n, a, b, c, d, e);
+}
+
+/* wall != 0: the wall rows (i = nr, identity) do not depend on V. */
+void or_sg_dV_w(int nr, int nz, double R, const double *z, int s, double mu,
+                double D, int wall, const double *V, const double *n, double *a,
+                double *b, double *c, double *d, double *e)
 {
     double dr = R / nr;
     double q = -(double)s * mu / D;
@@ -823,6 +933,8 @@ void or_sg_dV(int nr, int nz, double R, const double *z, int s, double mu,
         double w = radial_width(i, nr, R);
         for (int j = 1; j < nz; ++j) {
             size_t p = IDX(i, j, nz);
+            if (wall && i == nr)
+                continue;
             double dzc = axial_width(z, j);
             double center = 0.0;
             if (i < nr) { /* term g (G(al) n_p - F(al) n_{i+1}), al = q (V_{i+1} - V_p) */

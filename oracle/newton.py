@@ -19,20 +19,20 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import _p, lib, poisson_assemble, sg_assemble, apply, volumes
+from . import _p, lib, poisson_assemble, sg_assemble, apply, volumes, wall_values
 
 
-def _sg_dV(nr, nz, R, z, s, mu, D, V, n):
+def _sg_dV(nr, nz, R, z, s, mu, D, V, n, wall=0):
     L = lib()
     if not hasattr(L, "_dv_ready"):
         P = ctypes.POINTER(ctypes.c_double)
-        L.or_sg_dV.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, ctypes.c_int,
-                               ctypes.c_double, ctypes.c_double, P, P] + [P] * 5
+        L.or_sg_dV_w.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P] + [P] * 5
         L.or_bernoulli_dF.restype = ctypes.c_double
         L.or_bernoulli_dF.argtypes = [ctypes.c_double]
         L._dv_ready = True
     out = [np.zeros((nr + 1, nz + 1)) for _ in range(5)]
-    L.or_sg_dV(nr, nz, R, _p(z), int(s), mu, D, _p(V), _p(n), *[_p(o) for o in out])
+    L.or_sg_dV_w(nr, nz, R, _p(z), int(s), mu, D, int(wall), _p(V), _p(n), *[_p(o) for o in out])
     return out
 
 
@@ -42,14 +42,22 @@ def bernoulli_dF(x):
 
 
 class Coupled:
-    """Residual and Jacobian of the coupled BE system on one grid."""
+    """Residual and Jacobian of the coupled BE system on one grid.  wall=1:
+    the paper's Dirichlet wall at r = R (Sec. 3): potential linear in z
+    between the electrode values, densities 0; the wall nodes' equations are
+    u = u_wall (identity rows)."""
 
-    def __init__(self, nr, nz, R, z, phys):
+    def __init__(self, nr, nz, R, z, phys, wall=0):
         self.nr, self.nz, self.R = nr, nz, R
         self.z = np.ascontiguousarray(z, dtype=np.float64)
         self.ph = dict(phys)
+        self.wall = int(wall)
         self.vol = volumes(nr, nz, R, self.z)
-        self.P = poisson_assemble(nr, nz, R, self.z, 0.0)
+        self.P = poisson_assemble(nr, nz, R, self.z, 0.0, wall=self.wall)
+        self.interior = np.ones((nr + 1, nz + 1))  # 0 on the wall rows
+        if self.wall:
+            self.interior[nr, :] = 0.0
+            self.Vwall = wall_values(self.z, self.ph["V_bottom"], self.ph["V_top"])
         m = nz - 1
         self.m = m
         self.nun = (nr + 1) * m
@@ -62,14 +70,19 @@ class Coupled:
         V[:, 0], V[:, -1] = ph["V_bottom"], ph["V_top"]
         ne[:, 0], ne[:, -1] = ph["ne_bottom"], ph["ne_top"]
         np_[:, 0], np_[:, -1] = ph["np_bottom"], ph["np_top"]
+        if self.wall:
+            V[-1, :], ne[-1, :], np_[-1, :] = self.Vwall, 0.0, 0.0
 
     def residual(self, V, ne, np_, nek, npk, Se, Sp, dt_inv):
         ph, nr, nz, R, z = self.ph, self.nr, self.nz, self.R, self.z
-        Ae = sg_assemble(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], dt_inv, V, nek, Se)
-        Ap = sg_assemble(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], dt_inv, V, npk, Sp)
+        Ae = sg_assemble(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], dt_inv, V, nek, Se, wall=self.wall)
+        Ap = sg_assemble(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], dt_inv, V, npk, Sp, wall=self.wall)
         Fe = apply(Ae, ne) - Ae[5]
         Fp = apply(Ap, np_) - Ap[5]
-        FV = apply(self.P, V) - self.vol * ph["k"] * (np_ - ne)
+        rhsV = self.interior * self.vol * ph["k"] * (np_ - ne)
+        if self.wall:
+            rhsV[-1, 1:-1] = self.Vwall[1:-1]
+        FV = apply(self.P, V) - rhsV
         return (Fe, Fp, FV), (Ae, Ap)
 
     def pack(self, Fe, Fp, FV):
@@ -89,8 +102,8 @@ class Coupled:
     def jacobian(self, V, ne, np_, Ae, Ap):
         """Sparse 3x3-block five-point Jacobian (Eq. 14)."""
         ph, nr, nz, R, z = self.ph, self.nr, self.nz, self.R, self.z
-        eV = _sg_dV(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], V, ne)
-        pV = _sg_dV(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], V, np_)
+        eV = _sg_dV(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], V, ne, self.wall)
+        pV = _sg_dV(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], V, np_, self.wall)
         rows, cols, vals = [], [], []
         i, j, node, m = self.ii, self.jj, self.node, self.m
         offs = {0: (-1, 0), 1: (0, 0), 2: (1, 0), 3: (0, -1), 4: (0, 1)}  # a, b, c, d, e
@@ -105,7 +118,7 @@ class Coupled:
                 rows.append(3 * src + rf)
                 cols.append(3 * dst + cf)
                 vals.append(arr[sel])
-        kv = self.vol[i, j] * ph["k"]
+        kv = self.interior[i, j] * self.vol[i, j] * ph["k"]
         rows += [3 * node + 2, 3 * node + 2]
         cols += [3 * node + 0, 3 * node + 1]
         vals += [kv, -kv]
@@ -188,11 +201,12 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
     return acc, rej, seq
 
 
-def prolong_state(zf, Vc, nec, npc, phys):
+def prolong_state(zf, Vc, nec, npc, phys, wall=0):
     """Multilevel prolongation (Sec. 2, last paragraphs): the state of the
     grid one level coarser, interpolated onto the twice finer grid with the
     multigrid prolongation (bilinear, z-distance weights) on the unknown
-    rows, and the electrode rows set to their boundary values."""
+    rows, and the electrode rows (with wall=1 also the wall) set to their
+    boundary values."""
     from . import prolong_add
     nrc, nzc = Vc.shape[0] - 1, Vc.shape[1] - 1
     out = []
@@ -201,10 +215,13 @@ def prolong_state(zf, Vc, nec, npc, phys):
         prolong_add(zf, np.ascontiguousarray(c, dtype=np.float64), f)
         f[:, 0], f[:, -1] = phys[lo], phys[hi]
         out.append(f)
+    if wall:
+        out[0][-1, :] = wall_values(zf, phys["V_bottom"], phys["V_top"])
+        out[1][-1, :] = out[2][-1, :] = 0.0
     return out
 
 
-def chain(R, z_of, phys, N0, N1, V, ne, np_, S_of, **steady_kw):
+def chain(R, z_of, phys, N0, N1, V, ne, np_, S_of, wall=0, **steady_kw):
     """Multilevel prolongation chain (Sec. 2): steady run on the N0 grid from
     (V, ne, np_), then for each finer grid up to N1 the steady run from the
     prolonged steady state of the grid before.  z_of(N) gives the axial
@@ -214,13 +231,13 @@ def chain(R, z_of, phys, N0, N1, V, ne, np_, S_of, **steady_kw):
     stages = []
     while True:
         z = z_of(N)
-        cp = Coupled(N, N, R, z, phys)
+        cp = Coupled(N, N, R, z, phys, wall=wall)
         S = S_of(N, z)
         acc, rej, _ = steady(cp, V, ne, np_, S, S, **steady_kw)
         stages.append((N, acc, rej))
         if N == N1:
             return (V, ne, np_), stages
-        V, ne, np_ = prolong_state(z_of(2 * N), V, ne, np_, phys)
+        V, ne, np_ = prolong_state(z_of(2 * N), V, ne, np_, phys, wall=wall)
         N *= 2
 
 
@@ -234,7 +251,7 @@ def chain(R, z_of, phys, N0, N1, V, ne, np_, S_of, **steady_kw):
 # transpose of the bilinear prolongation, field by field; coarsest level
 # solved exactly.
 # ---------------------------------------------------------------------------
-def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8):
+def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8, wall=0):
     """Per level: the Coupled system, its Jacobian (CSR) for a BE step of
     size dt (inf: steady), the unknown indices of both colours."""
     from . import levels as _nlev
@@ -244,7 +261,7 @@ def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8):
     z = np.ascontiguousarray(z, dtype=np.float64)
     V, ne, np_ = (np.ascontiguousarray(a, dtype=np.float64) for a in (V, ne, np_))
     for l in range(nlev):
-        cp = Coupled(nr, nz, R, z, phys)
+        cp = Coupled(nr, nz, R, z, phys, wall=wall)
         zero = np.zeros_like(V)
         (_, (Ae, Ap)) = cp.residual(V, ne, np_, ne, np_, zero, zero, dt_inv)
         J = cp.jacobian(V, ne, np_, Ae, Ap).tocsr()

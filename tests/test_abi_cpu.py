@@ -43,7 +43,8 @@ def test_query_sizes():
 @pytest.mark.parametrize("kw,msg", [
     (dict(nr=60, nz=64), "cannot be coarsened"),
     (dict(nr=64, nz=64, coarsest=1), "cannot be coarsened"),
-    (dict(nr=64, nz=64, abi=2), "abi_version"),
+    (dict(nr=64, nz=64, abi=1), "abi_version"),
+    (dict(nr=64, nz=64, wall=2), "r_outer_bc"),
     (dict(nr=64, nz=64, zbad="order"), "strictly increasing"),
     (dict(nr=64, nz=64, zbad="start"), "start at 0"),
     (dict(nr=64, nz=64, smoother=7), "smoother"),
@@ -65,6 +66,8 @@ def test_query_rejects_bad_grids(kw, msg):
                     d=float(z[-1]) if kw.get("zbad") != "start" else 1.0)
     if "abi" in kw:
         d.abi_version = kw["abi"]
+    if "wall" in kw:
+        d.r_outer_bc = kw["wall"]
     with pytest.raises(M.MGError) as ei:
         M.query(d)
     assert ei.value.code == -1
