@@ -7,8 +7,9 @@
  * (r, z) in [0, R] x [0, d]; continuity Eqs. (1)-(2) with drift-diffusion
  * fluxes Eqs. (3)-(4), Poisson Eq. (5).  Axisymmetric; radial nodes
  * r_i = i R / nr (equidistant), axial nodes z_j given (non-equidistant).
- * Electrodes at z = 0 and z = d (Dirichlet), zero radial flux at r = 0 and
- * r = R.
+ * Electrodes at z = 0 and z = d (Dirichlet), zero radial flux at r = 0, and
+ * at r = R either zero radial flux or the Dirichlet wall of the paper's
+ * experiment (Sec. 3; mg_grid_desc.r_outer_bc).
  *
  * Memory.  Every device field is a row-major (nr+1) x pitch array of
  * doubles, element (i, j) at [i*pitch + j], i = radial node, j = axial node,
@@ -35,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MG_ABI_VERSION 1
+#define MG_ABI_VERSION 2
 
 #define MG_OK 0
 #define MG_EINVAL (-1)      /* bad argument (null pointer, grid, enum, version) */
@@ -65,7 +66,16 @@ typedef enum { MG_COUPLE_DECOUPLED = 0, MG_COUPLE_NEWTON = 2 } mg_coupling;
  *                iterative refinement
  *   krylov_m     restart length of the FGMRES solver of the coupled
  *                Newton systems (Eq. 14); 0 leaves that path (and its
- *                workspace) out, max 40                                  */
+ *                workspace) out, max 40
+ *   r_outer_bc   boundary at r = R: MG_WALL_ZERO_FLUX (0: zero radial
+ *                flux, half control volume) or MG_WALL_DIRICHLET (1: the
+ *                paper's wall, Sec. 3: potential interpolated linearly in z
+ *                between V_bottom and V_top, densities 0).  With the
+ *                Dirichlet wall the nodes i = nr are fixed on every level:
+ *                their equations are u = u_wall (identity rows), the rows
+ *                of i = nr-1 couple to them through the face r_{nr-1/2}.  */
+#define MG_WALL_ZERO_FLUX 0
+#define MG_WALL_DIRICHLET 1
 typedef struct {
     int32_t abi_version;
     int32_t nr, nz;
@@ -74,6 +84,7 @@ typedef struct {
     int32_t coarsest_n, nu1, nu2;
     int32_t smoother, prec;
     int32_t krylov_m;
+    int32_t r_outer_bc;
 } mg_grid_desc;
 
 /* Physics of Eqs. (3)-(5): mobilities, diffusion coefficients, the Poisson

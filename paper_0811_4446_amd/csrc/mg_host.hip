@@ -59,6 +59,8 @@ int validate(const mg_grid_desc *d) {
     if (d->smoother != MG_SMOOTH_RB && d->smoother != MG_SMOOTH_ZEBRA)
         return fail(MG_EINVAL, "bad smoother %d", d->smoother);
     if (d->prec != MG_FP64 && d->prec != MG_FP32_IR) return fail(MG_EINVAL, "bad precision %d", d->prec);
+    if (d->r_outer_bc != MG_WALL_ZERO_FLUX && d->r_outer_bc != MG_WALL_DIRICHLET)
+        return fail(MG_EINVAL, "bad r_outer_bc %d", d->r_outer_bc);
     if (d->nu1 < 0 || d->nu2 < 0 || d->nu1 + d->nu2 < 1 || d->nu1 > 16 || d->nu2 > 16)
         return fail(MG_EINVAL, "bad smoothing counts %d, %d", d->nu1, d->nu2);
     int nl = count_levels(d->nr, d->nz, d->coarsest_n);
@@ -98,6 +100,7 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
         L.g.nz = nz;
         L.g.ty = 4;
         L.g.sh = 8;
+        L.g.wall = d->r_outer_bc == MG_WALL_DIRICHLET ? 1 : 0;
         L.g.pitch = pitch;
         L.g.dr = d->R / nr;
         L.g.wr = cv.take<double>(nr + 1);
@@ -497,8 +500,10 @@ int sg_assemble(mg_ctx *c, int eq, const mg_physics *ph, const mg_state *st, dou
     if (eq == MG_EQ_POISSON) {
         if (!st->ne || !st->np || !st->V) return fail(MG_EINVAL, "Poisson needs V, ne and np");
         launch_set_electrodes(g0, st->V, ph->V_bottom, ph->V_top, s);
+        launch_set_wall(g0, st->V, ph->V_bottom, ph->V_top, s);
         for (int l = 0; l < c->nlev; ++l)
-            launch_poisson_assemble(c->lev[l].g, c->lev[l].op[eq], st->ne, st->np, ph->k, l == 0, s);
+            launch_poisson_assemble(c->lev[l].g, c->lev[l].op[eq], st->ne, st->np, ph->k, l == 0, ph->V_bottom,
+                                    ph->V_top, s);
     } else {
         bool el = eq == MG_EQ_ELECTRON;
         double *n = el ? st->ne : st->np;
@@ -511,6 +516,7 @@ int sg_assemble(mg_ctx *c, int eq, const mg_physics *ph, const mg_state *st, dou
         double q = -sgn * mu / D;
         double dt_inv = (dt > 0 && isfinite(dt)) ? 1.0 / dt : 0.0;
         launch_set_electrodes(g0, n, el ? ph->ne_bottom : ph->np_bottom, el ? ph->ne_top : ph->np_top, s);
+        launch_set_wall(g0, n, 0.0, 0.0, s);
         const double *V = st->V;
         for (int l = 0; l < c->nlev; ++l) {
             const Level &L = c->lev[l];
@@ -900,9 +906,7 @@ int prolong_state(mg_ctx *coarse, const mg_state *src, mg_ctx *fine, mg_state *d
     launch_prolong_state(gf, dst->V, gc, src->V, s);
     launch_prolong_state(gf, dst->ne, gc, src->ne, s);
     launch_prolong_state(gf, dst->np, gc, src->np, s);
-    launch_set_electrodes(gf, dst->V, ph->V_bottom, ph->V_top, s);
-    launch_set_electrodes(gf, dst->ne, ph->ne_bottom, ph->ne_top, s);
-    launch_set_electrodes(gf, dst->np, ph->np_bottom, ph->np_top, s);
+    set_boundary(gf, dst->V, dst->ne, dst->np, *ph, s);
     HIP_OK(hipGetLastError());
     return MG_OK;
 }

@@ -19,6 +19,7 @@ struct Geom {
     int nr, nz;
     int ty;             // radial rows per workgroup of the 2D kernels (tuning)
     int sh;             // radial rows of a red-black sweep tile: 8 (default) or 16
+    int wall;           // 1: Dirichlet wall at r = R (rows i = nr are identity rows)
     int64_t pitch;
     double dr;
     const double *wr;   // radial width of node i (area of its z-faces), nr+1
@@ -105,12 +106,18 @@ __device__ inline void pivot_search_wave0(const double *M, int64_t n2, int col, 
 
 // ---- kernel launchers (mg_kernels.hip) ----
 void launch_poisson_assemble(const Geom &g, Op<double> op, const double *ne, const double *np,
-                             double k, bool charge, hipStream_t s);
+                             double k, bool charge, double vlo, double vhi, hipStream_t s);
 void launch_sg_assemble(const Geom &g, Op<double> op, const double *V, const double *nk,
                         const double *S, double q, double D, double dt_inv, hipStream_t s);
 void launch_inject(const Geom &gf, const double *vf, const Geom &gc, double *vc, hipStream_t s);
 void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s,
                            const double *lohi = nullptr, const Batch &bt = Batch());
+// With a Dirichlet wall (g.wall): row i = nr of u := lo + (hi - lo) (z_j - z_0)/(z_nz - z_0)
+// (lohi: per-problem lo, hi); nothing otherwise.
+void launch_set_wall(const Geom &g, double *u, double lo, double hi, hipStream_t s,
+                     const double *lohi = nullptr, const Batch &bt = Batch());
+// Electrode rows and (with a wall) wall row of the three state fields.
+void set_boundary(const Geom &g, double *V, double *ne, double *np, const mg_physics &ph, hipStream_t s);
 void launch_fill(double *p, int64_t n, double v, hipStream_t s, const Batch &bt = Batch());
 void launch_fill(float *p, int64_t n, float v, hipStream_t s, const Batch &bt = Batch());
 template <class T>

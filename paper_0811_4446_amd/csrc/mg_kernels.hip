@@ -39,16 +39,28 @@ inline __device__ double bern_F(double x) {
 //   sum over faces area/dist * (V - V_nb) = vol * k * (n_p - n_e)
 // r-face i+1/2 has area r_{i+1/2} dzc_j and distance dr; z-face j+1/2 has
 // area w_i (radial width) and distance dz_j.  The axis has no inner face;
-// r = R has no outer face (zero radial flux).
+// r = R has no outer face (zero radial flux), or, with the Dirichlet wall of
+// Sec. 3, the wall nodes are fixed (identity rows, right-hand side the wall
+// potential on the finest level, 0 on the coarse levels).
 // ---------------------------------------------------------------------------
+__device__ inline double wall_value(const Geom &g, int j, double lo, double hi) {
+    return lo + (hi - lo) * ((g.z[j] - g.z[0]) / (g.z[g.nz] - g.z[0]));
+}
+
 __global__ void k_poisson_assemble(Geom g, Op<double> op, const double *__restrict__ ne,
-                                   const double *__restrict__ np, double k, int charge) {
+                                   const double *__restrict__ np, double k, int charge, double vlo, double vhi) {
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
     int64_t p = at(g, i, j);
     if (j == 0 || j == g.nz) {
         op.a[p] = op.b[p] = op.c[p] = op.d[p] = op.e[p] = op.f[p] = 0.0;
+        return;
+    }
+    if (g.wall && i == g.nr) {
+        op.a[p] = op.c[p] = op.d[p] = op.e[p] = 0.0;
+        op.b[p] = 1.0;
+        op.f[p] = charge ? wall_value(g, j, vlo, vhi) : 0.0;
         return;
     }
     double w = g.wr[i], dzc = g.dzc[j];
@@ -81,6 +93,11 @@ __global__ void k_sg_assemble(Geom g, Op<double> op, const double *__restrict__ 
     int64_t p = at(g, i, j);
     if (j == 0 || j == g.nz) {
         op.a[p] = op.b[p] = op.c[p] = op.d[p] = op.e[p] = op.f[p] = 0.0;
+        return;
+    }
+    if (g.wall && i == g.nr) {  // Dirichlet wall: density 0
+        op.a[p] = op.c[p] = op.d[p] = op.e[p] = op.f[p] = 0.0;
+        op.b[p] = 1.0;
         return;
     }
     double w = g.wr[i], dzc = g.dzc[j];
@@ -146,6 +163,20 @@ __global__ void k_set_electrodes(Geom g, double *u, double lo, double hi, const 
     if (i > g.nr) return;
     u[at(g, i, 0)] = lo;
     u[at(g, i, g.nz)] = hi;
+}
+
+__global__ void k_set_wall(Geom g, double *u, double lo, double hi, const double *lohi, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    u = boff(u, bo_);
+    g = geom_off(g, bo_);
+    if (lohi) {
+        lo = lohi[2 * blockIdx.z];
+        hi = lohi[2 * blockIdx.z + 1];
+    }
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > g.nz) return;
+    u[at(g, g.nr, j)] = wall_value(g, j, lo, hi);
 }
 
 template <class T>
@@ -1051,8 +1082,8 @@ __global__ void k_op_to_f32(Geom g, Op<double> o, Op<float> o32) {
 // ---------------------------------------------------------------------------
 
 void launch_poisson_assemble(const Geom &g, Op<double> op, const double *ne, const double *np,
-                             double k, bool charge, hipStream_t s) {
-    k_poisson_assemble<<<grid2d(g), blk2d(g), 0, s>>>(g, op, ne, np, k, charge ? 1 : 0);
+                             double k, bool charge, double vlo, double vhi, hipStream_t s) {
+    k_poisson_assemble<<<grid2d(g), blk2d(g), 0, s>>>(g, op, ne, np, k, charge ? 1 : 0, vlo, vhi);
 }
 
 void launch_sg_assemble(const Geom &g, Op<double> op, const double *V, const double *nk,
@@ -1067,6 +1098,21 @@ void launch_inject(const Geom &gf, const double *vf, const Geom &gc, double *vc,
 void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s, const double *lohi,
                            const Batch &bt) {
     k_set_electrodes<<<dim3((g.nr + 1 + 255) / 256, 1, bt.n), 256, 0, s>>>(g, u, lo, hi, lohi, bt);
+}
+
+void launch_set_wall(const Geom &g, double *u, double lo, double hi, hipStream_t s, const double *lohi,
+                     const Batch &bt) {
+    if (!g.wall) return;
+    k_set_wall<<<dim3((g.nz + 1 + 255) / 256, 1, bt.n), 256, 0, s>>>(g, u, lo, hi, lohi, bt);
+}
+
+void set_boundary(const Geom &g, double *V, double *ne, double *np, const mg_physics &ph, hipStream_t s) {
+    launch_set_electrodes(g, V, ph.V_bottom, ph.V_top, s);
+    launch_set_electrodes(g, ne, ph.ne_bottom, ph.ne_top, s);
+    launch_set_electrodes(g, np, ph.np_bottom, ph.np_top, s);
+    launch_set_wall(g, V, ph.V_bottom, ph.V_top, s);
+    launch_set_wall(g, ne, 0.0, 0.0, s);
+    launch_set_wall(g, np, 0.0, 0.0, s);
 }
 
 void launch_fill(double *p, int64_t n, double v, hipStream_t s, const Batch &bt) {

@@ -90,6 +90,15 @@ inline __device__ void assemble_node(const Geom &g, const BOp &J, int i, int j, 
         for (int k = 0; k < kBPlanes; ++k) J.pl(k)[p] = 0.0;
         return;
     }
+    if (g.wall && i == g.nr) {
+        // Dirichlet wall (Sec. 3): u = u_wall, identity block; the driver
+        // keeps the state's wall row at u_wall, so -F = 0 there
+        for (int k = 0; k < kBPlanes; ++k) J.pl(k)[p] = 0.0;
+        J.pl(kEE + 1)[p] = 1.0;
+        J.pl(kPP + 1)[p] = 1.0;
+        J.pl(kVV + 1)[p] = 1.0;
+        return;
+    }
     int64_t s = sidx(i, j);
     double w = g.wr[i], dzc = g.dzc[j], vol = w * dzc;
     double Vc = V[s], ec = ne[s], pc = np[s];

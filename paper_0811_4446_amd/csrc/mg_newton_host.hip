@@ -636,9 +636,7 @@ int newton_implicit_step(mg_ctx *c, const mg_physics *ph, mg_state *st, double d
                          mg_report *rep, bool *converged) {
     if (c->nw.m <= 0) return fail(MG_EINVAL, "context built with krylov_m = 0: no Newton workspace");
     const Level &L0 = c->lev[0];
-    launch_set_electrodes(L0.g, st->V, ph->V_bottom, ph->V_top, c->stream);
-    launch_set_electrodes(L0.g, st->ne, ph->ne_bottom, ph->ne_top, c->stream);
-    launch_set_electrodes(L0.g, st->np, ph->np_bottom, ph->np_top, c->stream);
+    set_boundary(L0.g, st->V, st->ne, st->np, *ph, c->stream);
     copy_state(c, st, c->nw.snap);
     int e = newton_iterate(c, ph, st, dt, sc, rep, converged);
     if (e) return e;
@@ -654,9 +652,7 @@ int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_
     mg_report *R = rep ? rep : &local;
     memset(R, 0, sizeof *R);
     const Level &L0 = c->lev[0];
-    launch_set_electrodes(L0.g, st->V, ph->V_bottom, ph->V_top, c->stream);
-    launch_set_electrodes(L0.g, st->ne, ph->ne_bottom, ph->ne_top, c->stream);
-    launch_set_electrodes(L0.g, st->np, ph->np_bottom, ph->np_top, c->stream);
+    set_boundary(L0.g, st->V, st->ne, st->np, *ph, c->stream);
     double dt = sc->dt0, dt_acc = 0.0, t = 0.0;
     int consecutive_rejects = 0;
     int status = MG_ENOCONV;
@@ -975,6 +971,9 @@ int batch_solve_steady(mg_ctx *c, const mg_physics *phys, const mg_schedule *sc,
         launch_set_electrodes(L0.g, st.V, 0, 0, s, c->lohi_dev, c->bt);
         launch_set_electrodes(L0.g, st.ne, 0, 0, s, c->lohi_dev + 2 * n, c->bt);
         launch_set_electrodes(L0.g, st.np, 0, 0, s, c->lohi_dev + 4 * n, c->bt);
+        launch_set_wall(L0.g, st.V, 0, 0, s, c->lohi_dev, c->bt);
+        launch_set_wall(L0.g, st.ne, 0, 0, s, nullptr, c->bt);
+        launch_set_wall(L0.g, st.np, 0, 0, s, nullptr, c->bt);
     }
     std::vector<double> dt(n, sc->dt0), dt_acc(n, 0.0), tt(n, 0.0), change(n, 0.0), relres(n, 0.0);
     std::vector<int> status(n, 0), steps(n, 0), rej(n, 0), newt(n, 0), fgm(n, 0), consec(n, 0);

@@ -19,11 +19,12 @@ import torch  # loaded first so that the library binds to torch's HIP runtime
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmgfluid.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 FP64, FP32_IR = 0, 1
 POISSON, ELECTRON, ION = 0, 1, 2
 SMOOTH_RB, SMOOTH_ZEBRA = 0, 1
 DECOUPLED, NEWTON = 0, 2
+WALL_ZERO_FLUX, WALL_DIRICHLET = 0, 1
 
 ERRORS = {-1: "MG_EINVAL", -2: "MG_EHIP", -3: "MG_ENOCONV", -4: "MG_ENONFINITE",
           -5: "MG_EREJECT", -6: "MG_ENOMEM"}
@@ -35,7 +36,7 @@ _PD = ctypes.POINTER(ctypes.c_double)
 class GridDesc(ctypes.Structure):
     _fields_ = [("abi_version", _I32), ("nr", _I32), ("nz", _I32), ("R", _D), ("d", _D),
                 ("z_host", _PD), ("coarsest_n", _I32), ("nu1", _I32), ("nu2", _I32),
-                ("smoother", _I32), ("prec", _I32), ("krylov_m", _I32)]
+                ("smoother", _I32), ("prec", _I32), ("krylov_m", _I32), ("r_outer_bc", _I32)]
 
 
 class Physics(ctypes.Structure):
@@ -145,10 +146,10 @@ def _ptr(t):
 
 
 def make_desc(nr, nz, z, R=1.0, d=1.0, coarsest=8, nu1=2, nu2=2, smoother=SMOOTH_ZEBRA, prec=FP64,
-              krylov_m=0):
+              krylov_m=0, r_outer_bc=WALL_ZERO_FLUX):
     z = np.ascontiguousarray(z, dtype=np.float64)
     desc = GridDesc(ABI_VERSION, nr, nz, R, d, z.ctypes.data_as(_PD), coarsest, nu1, nu2, smoother, prec,
-                    krylov_m)
+                    krylov_m, r_outer_bc)
     desc._z_keep = z
     return desc
 
@@ -163,13 +164,14 @@ class Solver:
     """One grid (and its multigrid hierarchy) on one device and stream."""
 
     def __init__(self, nr, nz, z, R=1.0, d=1.0, coarsest=8, nu1=2, nu2=2,
-                 smoother=SMOOTH_ZEBRA, prec=FP64, krylov_m=0, device="cuda:0", stream=None):
+                 smoother=SMOOTH_ZEBRA, prec=FP64, krylov_m=0, device="cuda:0", stream=None,
+                 r_outer_bc=WALL_ZERO_FLUX):
         if not torch.cuda.is_available():
             raise RuntimeError("mgfluid needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.nr, self.nz, self.R, self.d = nr, nz, R, d
         self.z = np.ascontiguousarray(z, dtype=np.float64)
         self.device = torch.device(device)
-        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, smoother, prec, krylov_m)
+        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, smoother, prec, krylov_m, r_outer_bc)
         self.pitch, self.ws_bytes = query(self.desc)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(self.ws_bytes // 8 + 64, dtype=torch.float64, device=self.device)
@@ -293,13 +295,13 @@ class Batch:
     """nprob same-shape problems solved together (one size class)."""
 
     def __init__(self, nr, nz, z, nprob, R=1.0, d=1.0, coarsest=4, nu1=2, nu2=2, prec=FP32_IR, krylov_m=20,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, r_outer_bc=WALL_ZERO_FLUX):
         if not torch.cuda.is_available():
             raise RuntimeError("mgfluid needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.nr, self.nz, self.n = nr, nz, nprob
         self.z = np.ascontiguousarray(z, dtype=np.float64)
         self.device = torch.device(device)
-        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, SMOOTH_ZEBRA, prec, krylov_m)
+        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, SMOOTH_ZEBRA, prec, krylov_m, r_outer_bc)
         self.pitch, _ = query(self.desc)
         stride, total = _I64(0), _I64(0)
         _check(lib().mg_batch_query(ctypes.byref(self.desc), nprob, ctypes.byref(stride), ctypes.byref(total)))
