@@ -556,6 +556,103 @@ def learned(args, M, I):
     print(json.dumps(out), flush=True)
 
 
+def argon(args, M, I):
+    """Sec. 3 of the paper: the obstructed argon glow discharge (SI units,
+    Dirichlet wall, sources S_e, S_p with the radial parameters (a, b) of the
+    two cases shown), solved by the multilevel prolongation chain 17x17 -> ...
+    -> N with the paper's time-step rule (dt from 1 ns, x5 per accepted step,
+    capped at 1 ms; steady when the relative density change per step is below
+    1e-6), FP64 Newton with the block multigrid preconditioner.  Reports the
+    ion current to the cathode, 2 pi e times the ion flow through the cathode
+    face, per stage, and the time of each stage.  The ion mobility is a stated
+    substitute, so the comparison with the paper's currents (0.59 mA and
+    0.035 mA) is context.  The oracle runs the same chain up to 65x65 on one
+    host core beside it."""
+    import numpy as np
+    import torch
+    R, d = I.ARGON_R, I.ARGON_D
+    ph = dict(I.ARGON)
+    P = M.Physics.of(ph)
+    sc = M.schedule(coupling=M.NEWTON, dt0=1e-9, growth=5.0, dt_max=1e-3, steady_tol=1e-6, lin_rtol=args.lin_rtol,
+                    max_cycles=400, newton_tol=1e-6, max_steps=2000)
+    paper = {(30.0, 24.0): 0.59e-3, (10.0, 1.0): 0.035e-3}
+    rows = []
+    for (a, b) in I.ARGON_CASES:
+        N = 16
+        z = I.z_cos(N, d)
+        V, ne, np_ = I.argon_initial(N, N, z)
+        Se, Sp = I.argon_sources(N, N, z, a, b)
+        sol = M.Solver(N, N, z, R=R, d=d, krylov_m=30, coarsest=4, r_outer_bc=M.WALL_DIRICHLET)
+        t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(Se), sol.upload(Sp)]
+        stages = []
+        t_chain = 0.0
+        while True:
+            st = sol.state(*t)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            code, rep = sol.steady(P, st, sc)
+            torch.cuda.synchronize()
+            el = time.time() - t0
+            t_chain += el
+            if code != 0:
+                raise RuntimeError("argon %dx%d: %s" % (N + 1, N + 1, M.lib().mg_last_error()))
+            fl = sol.boundary_flow(P, st)
+            cur = 2 * np.pi * I.ELEMENTARY_CHARGE * fl[3]
+            stages.append(dict(grid="%dx%d" % (N + 1, N + 1), seconds=round(el, 4), steps=rep.steps,
+                               rejected=rep.rejected, newton=rep.newton_its, fgmres=rep.vcycles,
+                               ion_current_cathode_A=cur, ion_flow_per_rad=dict(cathode=fl[3], anode=fl[4], wall=fl[5])))
+            log("argon a=%g b=%g: %s" % (a, b, stages[-1]))
+            if N == args.argon_grid:
+                break
+            N2 = 2 * N
+            z2 = I.z_cos(N2, d)
+            fine = M.Solver(N2, N2, z2, R=R, d=d, krylov_m=30, coarsest=4, r_outer_bc=M.WALL_DIRICHLET)
+            Se2, Sp2 = I.argon_sources(N2, N2, z2, a, b)
+            t2 = [fine.field(), fine.field(), fine.field(), fine.upload(Se2), fine.upload(Sp2)]
+            M.prolong_state(sol, st, fine, fine.state(*t2), P)
+            sol, t, N = fine, t2, N2
+        rows.append(dict(a=a, b=b, stages=stages, chain_seconds=round(t_chain, 3),
+                         ion_current_cathode_mA=round(stages[-1]["ion_current_cathode_A"] * 1e3, 5),
+                         paper_mA=paper[(a, b)] * 1e3))
+    out = {"metric": METRIC, "value": rows[0]["chain_seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "argon obstructed glow (Sec. 3), SI units, Dirichlet wall; multilevel prolongation "
+                                  "chain 17x17 -> %dx%d; value: whole chain of the first case (s)"
+                                  % (args.argon_grid + 1, args.argon_grid + 1),
+                      "ion_mobility_substitute_m2_per_Vs": I.ARGON_MU_P, "cases": rows}}
+    if not args.no_cpu:
+        out["cpu_baseline"] = argon_oracle(I, I.ARGON_CASES[0])
+    print(json.dumps(out), flush=True)
+
+
+def argon_oracle(I, case, N1=64):
+    """The oracle's argon chain 17x17 -> 65x65 (first case) on one host core:
+    its time and its ion current to the cathode."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+    from oracle import newton as NW
+    a, b = case
+    R, d = I.ARGON_R, I.ARGON_D
+    ph = dict(I.ARGON)
+    N = 16
+    V, ne, np_ = I.argon_initial(N, N, I.z_cos(N, d))
+    t0 = time.time()
+    while True:
+        z = I.z_cos(N, d)
+        cp = NW.Coupled(N, N, R, z, ph, wall=1)
+        Se, Sp = I.argon_sources(N, N, z, a, b)
+        NW.steady(cp, V, ne, np_, Se, Sp, dt0=1e-9, growth=5.0, dt_max=1e-3, tol=1e-6)
+        if N == N1:
+            break
+        V, ne, np_ = NW.prolong_state(I.z_cos(2 * N, d), V, ne, np_, ph, wall=1)
+        N *= 2
+    el = time.time() - t0
+    cur = 2 * np.pi * I.ELEMENTARY_CHARGE * NW.boundary_flow(R, I.z_cos(N1, d), 1, ph["mu_p"], ph["D_p"], V, np_, 1)[0]
+    return dict(value=round(el, 2), unit="s", cores=1, kind="oracle", host=_host(),
+                sample="the oracle's argon chain 17x17 -> %dx%d, case a=%g b=%g, single thread (sparse LU per "
+                       "Newton system); its ion current to the cathode %.5f mA" % (N1 + 1, N1 + 1, a, b, cur * 1e3))
+
+
 def fig1(args, M, I):
     """Sec. 3, Fig. 1 re-measured on this GPU: time to the steady state against N for plain relaxation
     (R: the coupled Newton path with its preconditioner reduced to V(2,2)'s four red-black sweeps on the
@@ -666,6 +763,8 @@ def main():
     ap.add_argument("--reps", type=int, default=200, help="timed half-sweeps of the roofline measurement")
     ap.add_argument("--trace-summary", type=str, default="", help="summarise a rocprofv3 CSV and exit")
     ap.add_argument("--fig1", action="store_true", help="Sec. 3 Fig. 1 re-measured: R / M / M+L time vs N")
+    ap.add_argument("--argon", action="store_true", help="Sec. 3 argon discharge: ion current to the cathode")
+    ap.add_argument("--argon-grid", type=int, default=256, help="finest N of the argon chain (power of two >= 16)")
     ap.add_argument("--fig1-grids", type=str, default="32,64,128,256", help="N values, each > 16")
     ap.add_argument("--fig1-rgrids", type=str, default="16,32",
                     help="N values of the relaxation-only runs (65x65 and above take minutes)")
@@ -696,6 +795,8 @@ def main():
         return learned(args, M, I)
     if args.fig1:
         return fig1(args, M, I)
+    if args.argon:
+        return argon(args, M, I)
     vtops = [float(v) for v in args.vtops.split(",")]
     N = args.grid
     if args.prec != "fp64":

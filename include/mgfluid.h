@@ -181,6 +181,18 @@ int solve_steady(mg_ctx *ctx, const mg_physics *phys, mg_state *st,
  * 1/vol) at the state st; needs krylov_m >= 1.  Synchronises. */
 int mg_steady_residual(mg_ctx *ctx, const mg_physics *phys, const mg_state *st, double *norm_out);
 
+/* Particle flow out of the domain through its boundaries at the state st,
+ * per radian of azimuth (multiply by 2 pi for the whole discharge, and by
+ * the elementary charge for a current): the Scharfetter-Gummel face fluxes
+ * of Eqs. (8)-(9) through the cathode (z = 0), the anode (z = d) and, with
+ * the Dirichlet wall, the wall face r_{nr-1/2}, summed with the faces'
+ * areas over the control volumes of the unknown nodes.  out (host, 6
+ * doubles): electrons {cathode, anode, wall}, ions {cathode, anode, wall}.
+ * The paper's observable (Sec. 3) is the ion current to the cathode,
+ * 2 pi e out[3].  At a steady state each species' outflow sum equals its
+ * source integral.  Synchronises. */
+int mg_boundary_flow(mg_ctx *ctx, const mg_physics *phys, const mg_state *st, double *out);
+
 /* The preconditioner of the Newton linear solves on its own (Sec. 2: the
  * Jacobian system of Eq. (14) solved by multigrid): assembles the 3x3-block
  * Jacobian at the state st on every level (coarse levels at the injected

@@ -201,6 +201,32 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
     return acc, rej, seq
 
 
+def boundary_flow(R, z, s, mu, D, V, n, wall=0):
+    """Particle flow per radian out of the domain (Sec. 3's observable is the
+    ion current to the cathode): the SG face fluxes of Eqs. (8)-(9) through
+    the cathode face z_{1/2}, the anode face z_{nz-1/2} and, with the
+    Dirichlet wall, the wall face r_{nr-1/2}, times the faces' areas, summed
+    over the unknown cells.  Returns (cathode, anode, wall)."""
+    from . import bernoulli_F
+    nr, nz = V.shape[0] - 1, V.shape[1] - 1
+    dr = R / nr
+    q = -s * mu / D
+    imax = nr - 1 if wall else nr
+    cath = anode = wflow = 0.0
+    for i in range(imax + 1):
+        w = dr * dr / 8 if i == 0 else (0.5 * dr * (R - 0.25 * dr) if i == nr else i * dr * dr)
+        al = q * (V[i, 1] - V[i, 0])
+        cath -= w * D / (z[1] - z[0]) * (n[i, 0] * bernoulli_F(-al) - n[i, 1] * bernoulli_F(al))
+        al = q * (V[i, nz] - V[i, nz - 1])
+        anode += w * D / (z[nz] - z[nz - 1]) * (n[i, nz - 1] * bernoulli_F(-al) - n[i, nz] * bernoulli_F(al))
+    if wall:
+        for j in range(1, nz):
+            area = (nr - 0.5) * dr * 0.5 * (z[j + 1] - z[j - 1])
+            al = q * (V[nr, j] - V[nr - 1, j])
+            wflow += area * D / dr * (n[nr - 1, j] * bernoulli_F(-al) - n[nr, j] * bernoulli_F(al))
+    return cath, anode, wflow
+
+
 def prolong_state(zf, Vc, nec, npc, phys, wall=0):
     """Multilevel prolongation (Sec. 2, last paragraphs): the state of the
     grid one level coarser, interpolated onto the twice finer grid with the

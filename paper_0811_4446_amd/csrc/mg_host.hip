@@ -747,6 +747,21 @@ int mg_steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, doub
     return steady_residual(c, ph, st, norm_out);
 }
 
+int mg_boundary_flow(mg_ctx *c, const mg_physics *ph, const mg_state *st, double *out) {
+    if (int e = check_ctx(c)) return e;
+    if (!ph || !st || !out || !st->V || !st->ne || !st->np) return fail(MG_EINVAL, "null argument");
+    if (!(ph->D_e > 0) || !(ph->D_p > 0)) return fail(MG_EINVAL, "need D_e, D_p > 0");
+    const Geom &g = c->lev[0].g;
+    hipStream_t s = c->stream;
+    launch_boundary_flow(g, st->V, st->ne, ph->mu_e / ph->D_e, ph->D_e, c->scal, s);
+    launch_boundary_flow(g, st->V, st->np, -ph->mu_p / ph->D_p, ph->D_p, c->scal + 3, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(c->pinned, c->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int k = 0; k < 6; ++k) out[k] = c->pinned[k];
+    return MG_OK;
+}
+
 int mg_newton_precond(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt, const double *r,
                       double *z) {
     if (int e = check_ctx(c)) return e;

@@ -116,6 +116,9 @@ void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipSt
 // (lohi: per-problem lo, hi); nothing otherwise.
 void launch_set_wall(const Geom &g, double *u, double lo, double hi, hipStream_t s,
                      const double *lohi = nullptr, const Batch &bt = Batch());
+// Particle flow out through cathode, anode and wall (3 device doubles).
+void launch_boundary_flow(const Geom &g, const double *V, const double *n, double q, double D, double *out,
+                          hipStream_t s);
 // Electrode rows and (with a wall) wall row of the three state fields.
 void set_boundary(const Geom &g, double *V, double *ne, double *np, const mg_physics &ph, hipStream_t s);
 void launch_fill(double *p, int64_t n, double v, hipStream_t s, const Batch &bt = Batch());

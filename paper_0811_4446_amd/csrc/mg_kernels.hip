@@ -179,6 +179,52 @@ __global__ void k_set_wall(Geom g, double *u, double lo, double hi, const double
     u[at(g, g.nr, j)] = wall_value(g, j, lo, hi);
 }
 
+// Particle flow (per radian of azimuth) out of the domain through the
+// boundaries, from the SG face fluxes of Eqs. (8)-(9) at the state (V, n):
+// out[0] cathode (face z_{1/2}, cells i < nr, or i <= nr without a wall),
+// out[1] anode (face z_{nz-1/2}), out[2] wall (face r_{nr-1/2}, j = 1..nz-1,
+// Dirichlet wall only).  One workgroup; fixed-order tree sums.
+__global__ __launch_bounds__(1024) void k_boundary_flow(Geom g, const double *__restrict__ V,
+                                                         const double *__restrict__ n, double q, double D,
+                                                         double *__restrict__ out) {
+    __shared__ double sh[3][1024];
+    const int t = threadIdx.x;
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    const int imax = g.wall ? g.nr - 1 : g.nr;
+    for (int i = t; i <= imax; i += 1024) {
+        const double w = g.wr[i];
+        {
+            const int64_t p0 = at(g, i, 0), p1 = at(g, i, 1);
+            const double al = q * (V[p1] - V[p0]);
+            const double phi = D / g.dz[0] * (n[p0] * bern_F(-al) - n[p1] * bern_F(al));
+            c0 += -phi * w;
+        }
+        {
+            const int64_t pa = at(g, i, g.nz - 1), pb = at(g, i, g.nz);
+            const double al = q * (V[pb] - V[pa]);
+            const double phi = D / g.dz[g.nz - 1] * (n[pa] * bern_F(-al) - n[pb] * bern_F(al));
+            c1 += phi * w;
+        }
+    }
+    if (g.wall)
+        for (int j = 1 + t; j < g.nz; j += 1024) {
+            const int64_t pa = at(g, g.nr - 1, j), pb = at(g, g.nr, j);
+            const double al = q * (V[pb] - V[pa]);
+            const double phi = D / g.dr * (n[pa] * bern_F(-al) - n[pb] * bern_F(al));
+            c2 += phi * g.fr[g.nr - 1] * g.dzc[j];
+        }
+    sh[0][t] = c0;
+    sh[1][t] = c1;
+    sh[2][t] = c2;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if (t < h)
+            for (int k = 0; k < 3; ++k) sh[k][t] += sh[k][t + h];
+        __syncthreads();
+    }
+    if (t < 3) out[t] = sh[t][0];
+}
+
 template <class T>
 __global__ void k_fill(T *p, int64_t n, T v, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
@@ -1104,6 +1150,11 @@ void launch_set_wall(const Geom &g, double *u, double lo, double hi, hipStream_t
                      const Batch &bt) {
     if (!g.wall) return;
     k_set_wall<<<dim3((g.nz + 1 + 255) / 256, 1, bt.n), 256, 0, s>>>(g, u, lo, hi, lohi, bt);
+}
+
+void launch_boundary_flow(const Geom &g, const double *V, const double *n, double q, double D, double *out,
+                          hipStream_t s) {
+    k_boundary_flow<<<1, 1024, 0, s>>>(g, V, n, q, D, out);
 }
 
 void set_boundary(const Geom &g, double *V, double *ne, double *np, const mg_physics &ph, hipStream_t s) {

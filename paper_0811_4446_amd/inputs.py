@@ -66,3 +66,49 @@ def sweep_draws(n, seed, sizes=(64, 128, 256, 512)):
         out.append(dict(N=N, V_top=vt, ratio=ratio, mu_e=ratio, D_e=0.01 * ratio,
                         mu_p=1.0, D_p=0.01))
     return out
+
+
+# ---------------------------------------------------------------------------
+# The paper's experiment (Sec. 3): obstructed glow discharge in argon, SI
+# units.  d = 1.1 cm, R = 2.7 cm, 255.9 V across the gap, p = 0.514 torr;
+# mu_e = 30/p m^2/(V s) (p in torr), D_e = mu_e kT_e/e with kT_e = 1 eV,
+# D_p = mu_p kT_p/e with kT_p = 0.026 eV; Dirichlet wall at r = R
+# (potential linear along it, densities 0).  The ion mobility comes from a
+# reference the paper cites without giving a value; mu_p here is a stated
+# substitute: the low-field reduced mobility of Ar+ in Ar, about 1.5 cm^2/(V s)
+# at the standard gas density, scaled to the density at 0.514 torr and 300 K.
+# ---------------------------------------------------------------------------
+ELEMENTARY_CHARGE = 1.602176634e-19
+EPSILON_0 = 8.8541878128e-12
+ARGON_P_TORR = 0.514
+ARGON_MU_P = 0.25  # m^2/(V s), substitute (see above)
+ARGON = dict(mu_e=30.0 / ARGON_P_TORR, D_e=30.0 / ARGON_P_TORR * 1.0, mu_p=ARGON_MU_P, D_p=ARGON_MU_P * 0.026,
+             k=ELEMENTARY_CHARGE / EPSILON_0, V_bottom=0.0, V_top=255.9,
+             ne_bottom=0.0, ne_top=0.0, np_bottom=0.0, np_top=0.0)
+ARGON_R = 0.027
+ARGON_D = 0.011
+# radial profile parameters (a, b) of the two cases shown in the paper
+ARGON_CASES = ((30.0, 24.0), (10.0, 1.0))
+
+
+def argon_sources(nr, nz, z, a, b, R=ARGON_R, d=ARGON_D):
+    """S_e, S_p of Sec. 3 (m^-3 s^-1) at the nodes: radial profile
+    1/(1 + exp(a r/R - b)) times the axial profiles
+    S_p ~ 0.35e22 (z/d)^2 exp(-50 (z/d)^8) and
+    S_e ~ 1.75e22 (z/d - 0.5) exp(-40 (z/d - 0.5)^2) for z/d > 0.5 (0 below);
+    the paper's L is the gap d."""
+    r = np.arange(nr + 1, dtype=np.float64) * (R / nr)
+    x = np.asarray(z, dtype=np.float64) / d
+    rad = 1.0 / (1.0 + np.exp(a * r / R - b))
+    sp = 0.35e22 * x ** 2 * np.exp(-50.0 * x ** 8)
+    se = np.where(x > 0.5, 1.75e22 * (x - 0.5) * np.exp(-40.0 * (x - 0.5) ** 2), 0.0)
+    return np.ascontiguousarray(rad[:, None] * se[None, :]), np.ascontiguousarray(rad[:, None] * sp[None, :])
+
+
+def argon_initial(nr, nz, z, n0=1.0e14, d=ARGON_D):
+    """Initial state of the argon runs: uniform densities n0 (m^-3) inside,
+    zero on the electrodes and the wall; potential linear in z."""
+    n = np.full((nr + 1, nz + 1), n0)
+    n[:, 0] = n[:, -1] = 0.0
+    n[-1, :] = 0.0
+    return initial_potential(nr, nz, z, 0.0, ARGON["V_top"], d), n, n.copy()

@@ -95,6 +95,7 @@ SIGNATURES = {
                                           ctypes.POINTER(Report)]),
     "mg_set_tuning": (ctypes.c_int, [_VP, _I32, _I32]),
     "mg_steady_residual": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _PD]),
+    "mg_boundary_flow": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _PD]),
     "mg_newton_precond": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), ctypes.c_double,
                                          _VP, _VP]),
     "wn_param_count": (ctypes.c_int, []),
@@ -266,6 +267,13 @@ class Solver:
         r = _D(0.0)
         _check(lib().mg_steady_residual(self.ctx, ctypes.byref(phys), ctypes.byref(state), ctypes.byref(r)))
         return r.value
+
+    def boundary_flow(self, phys, state):
+        """mg_boundary_flow: particle flow per radian out through cathode,
+        anode and wall, electrons then ions (6 floats)."""
+        out = (_D * 6)()
+        _check(lib().mg_boundary_flow(self.ctx, ctypes.byref(phys), ctypes.byref(state), out))
+        return [out[k] for k in range(6)]
 
     def field3(self):
         """Three consecutive planes (n_e, n_p, V rows), the layout of

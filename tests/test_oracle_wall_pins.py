@@ -245,3 +245,35 @@ def test_steady_with_wall_balances_sources_against_electrode_and_wall_outflow():
     for s, mu, D, n in ((-1, ph["mu_e"], ph["D_e"], ne), (1, ph["mu_p"], ph["D_p"], np_)):
         out = _outflow(1.0, z, s, mu, D, V, n)
         assert abs(out - src) <= 1e-9 * src, (s, out, src)
+
+
+@pytest.mark.parametrize("wall", [0, 1])
+def test_boundary_flow_equals_independent_face_sums(wall):
+    """newton.boundary_flow (cathode, anode, wall) equals the face sums
+    written here with 50-digit Bernoulli functions, and a BE step's particle
+    balance closes with it: sum vol ((n - n^k)/dt - S) = -(total outflow)."""
+    N, dt = 16, 1e-3
+    z = I.z_cos(N)
+    rng = np.random.default_rng(11 + wall)
+    V = np.ascontiguousarray(I.initial_potential(N, N, z) + 0.05 * rng.normal(size=(N + 1, N + 1)))
+    nk = rng.random((N + 1, N + 1))
+    nk[:, 0] = nk[:, -1] = 0.0
+    if wall:
+        nk[-1, :] = 0.0
+    S = I.source(N, N, z)
+    for s, mu, D in ((-1, 100.0, 1.0), (1, 1.0, 0.01)):
+        coef = O.sg_assemble(N, N, 1.0, z, s, mu, D, 1.0 / dt, V, nk, S, wall=wall)
+        n = nk.copy()
+        O.direct_solve(coef, n)
+        cath, anode, wflow = NW.boundary_flow(1.0, z, s, mu, D, V, n, wall)
+        if wall:
+            ref = _outflow(1.0, z, s, mu, D, V, n)
+            ref_e = _outflow_electrodes_only(1.0, z, s, mu, D, V, n)
+            assert abs((cath + anode) - ref_e) <= 1e-12 * abs(ref_e)
+            assert abs((cath + anode + wflow) - ref) <= 1e-12 * abs(ref)
+        else:
+            assert wflow == 0.0
+        vol = O.volumes(N, N, 1.0, z)
+        cells = (slice(0, N if wall else N + 1), slice(1, N))
+        lhs = (vol * ((n - nk) / dt - S))[cells].sum()
+        assert abs(lhs + cath + anode + wflow) <= 1e-10 * np.abs(vol * S).sum()
