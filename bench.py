@@ -653,6 +653,63 @@ def argon_oracle(I, case, N1=64):
                        "Newton system); its ion current to the cathode %.5f mA" % (N1 + 1, N1 + 1, a, b, cur * 1e3))
 
 
+def hybrid(args, M, I):
+    """The fluid solver inside a hybrid loop (Sec. 2: transport coefficients
+    supplied by lookup tables / a Monte Carlo code, the fluid equations
+    solved again after every cycle): 257x257 synthetic workload, cycle 0 the
+    steady state of the default chain (constant transport), then per cycle
+    the electron mobility and diffusion coefficient from a table of the field
+    strength at the current potential (mg_transport_table) and the steady
+    solve warm-started from the previous cycle's state (dt from 1e-3, x1.5,
+    capped at 0.1; stop at relative change 1e-8).  Reports each cycle's
+    solve time, steps, the change of the mobility field and the particle
+    flow through the electrodes."""
+    import numpy as np
+    import torch
+    N = args.grid
+    phys = dict(I.PHYS)
+    fine, t, P, info = chain_to(M, I, N, phys["V_top"], args.lin_rtol)
+    st = fine.state(t[0], t[1], t[2], t[3], t[3])
+    code, rep = fine.steady(P, st, schedule(M, args.lin_rtol))
+    if code != 0:
+        raise RuntimeError("cycle 0: %s" % M.lib().mg_last_error())
+    Et, mut, Dt = I.electron_transport_table()
+    tab = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (Et, mut, Dt)]
+    mu, D, mu_prev = fine.field(), fine.field(), fine.field()
+    mup, Dp = fine.field(phys["mu_p"]), fine.field(phys["D_p"])
+    sc = M.schedule(coupling=M.NEWTON, dt0=1e-3, growth=1.5, dt_max=0.1, steady_tol=1e-8, lin_rtol=args.lin_rtol,
+                    max_cycles=400, newton_tol=1e-6, max_steps=20000)
+    rows = [dict(cycle=0, steps=rep.steps, seconds=round(rep.seconds, 4), transport="constant",
+                 flow=fine.boundary_flow(P, st))]
+    log("hybrid cycle 0: %s" % rows[-1])
+    for cyc in range(1, args.hybrid_cycles + 1):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        fine.transport_table(t[0], *tab, mu, D)
+        torch.cuda.synchronize()
+        t_tab = time.time() - t0
+        dmu = float((mu[:, : N + 1] - mu_prev[:, : N + 1]).abs().max() / mu[:, : N + 1].abs().max()) if cyc > 1 else None
+        mu_prev.copy_(mu)
+        stc = fine.state(t[0], t[1], t[2], t[3], t[3], mu, D, mup, Dp)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        code, rep = fine.steady(P, stc, sc)
+        torch.cuda.synchronize()
+        el = time.time() - t0
+        if code != 0:
+            raise RuntimeError("hybrid cycle %d: %s" % (cyc, M.lib().mg_last_error()))
+        rows.append(dict(cycle=cyc, steps=rep.steps, newton=rep.newton_its, fgmres=rep.vcycles, seconds=round(el, 4),
+                         table_ms=round(t_tab * 1e3, 3), mobility_change=dmu, flow=fine.boundary_flow(P, stc)))
+        log("hybrid cycle %d: %s" % (cyc, rows[-1]))
+    out = {"metric": METRIC, "value": round(float(np.mean([r["seconds"] for r in rows[1:]])), 4), "unit": "s",
+           "n_gpus": 1, "steps": args.hybrid_cycles, "warmup": 0, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "hybrid loop at %dx%d: field-dependent electron transport from a table, steady "
+                                  "solve warm-started per cycle (value: mean seconds per cycle)" % (N + 1, N + 1),
+                      "cycles": rows, "table": dict(points=len(Et), E_max=float(Et[-1]))}}
+    print(json.dumps(out), flush=True)
+
+
 def fig1(args, M, I):
     """Sec. 3, Fig. 1 re-measured on this GPU: time to the steady state against N for plain relaxation
     (R: the coupled Newton path with its preconditioner reduced to V(2,2)'s four red-black sweeps on the
@@ -764,6 +821,8 @@ def main():
     ap.add_argument("--trace-summary", type=str, default="", help="summarise a rocprofv3 CSV and exit")
     ap.add_argument("--fig1", action="store_true", help="Sec. 3 Fig. 1 re-measured: R / M / M+L time vs N")
     ap.add_argument("--argon", action="store_true", help="Sec. 3 argon discharge: ion current to the cathode")
+    ap.add_argument("--hybrid", action="store_true", help="hybrid loop: table transport, warm-started solves")
+    ap.add_argument("--hybrid-cycles", type=int, default=5)
     ap.add_argument("--argon-grid", type=int, default=256, help="finest N of the argon chain (power of two >= 16)")
     ap.add_argument("--fig1-grids", type=str, default="32,64,128,256", help="N values, each > 16")
     ap.add_argument("--fig1-rgrids", type=str, default="16,32",
@@ -797,6 +856,8 @@ def main():
         return fig1(args, M, I)
     if args.argon:
         return argon(args, M, I)
+    if args.hybrid:
+        return hybrid(args, M, I)
     vtops = [float(v) for v in args.vtops.split(",")]
     N = args.grid
     if args.prec != "fp64":

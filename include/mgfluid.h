@@ -95,10 +95,20 @@ typedef struct {
     double ne_bottom, ne_top, np_bottom, np_top;
 } mg_physics;
 
-/* Device state in the field layout above (caller-owned). */
+/* Device state in the field layout above (caller-owned).
+ *   mue, De, mup, Dp  optional node values of the mobilities and diffusion
+ *                     coefficients (Sec. 2: mu(E), D(E) supplied by lookup
+ *                     tables or a Monte Carlo code, e.g. mg_transport_table);
+ *                     NULL: the constants of mg_physics.  Set mue and De (or
+ *                     mup and Dp) together.  Each face uses the arithmetic
+ *                     mean of its two nodes' values, alpha = -s mu/D (Eq. 10)
+ *                     with the face values; the values are held fixed during
+ *                     a solve (the Newton Jacobian differentiates in V, n
+ *                     only).  Not supported by batches. */
 typedef struct {
     double *V, *ne, *np;
     const double *Se, *Sp;
+    const double *mue, *De, *mup, *Dp;
 } mg_state;
 
 /* Time-stepping schedule (Sec. 2, last paragraphs): dt starts at dt0 and
@@ -180,6 +190,16 @@ int solve_steady(mg_ctx *ctx, const mg_physics *phys, mg_state *st,
  * (Eqs. 7-13 with dt = infinity; Poisson rows scaled by 1/k, every row by
  * 1/vol) at the state st; needs krylov_m >= 1.  Synchronises. */
 int mg_steady_residual(mg_ctx *ctx, const mg_physics *phys, const mg_state *st, double *norm_out);
+
+/* Node transport from tables of the field strength (Sec. 2: mu(E), D(E)
+ * from lookup tables): |E| = |grad V| at every node of the finest grid
+ * (central differences, one-sided at the electrodes and at r = R, radial
+ * component 0 on the axis), then piecewise-linear interpolation in the
+ * table (E_tab strictly increasing, ntab >= 2; clamped outside), written to
+ * mu_out and D_out (device fields, caller-owned, every node).  E_tab,
+ * mu_tab, D_tab: device arrays of ntab doubles.  Asynchronous. */
+int mg_transport_table(mg_ctx *ctx, const double *V, const double *E_tab, const double *mu_tab,
+                       const double *D_tab, int32_t ntab, double *mu_out, double *D_out);
 
 /* Particle flow out of the domain through its boundaries at the state st,
  * per radian of azimuth (multiply by 2 pi for the whole discharge, and by

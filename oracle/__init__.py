@@ -66,6 +66,7 @@ def lib():
         L.or_poisson_assemble_w.argtypes = [_I, _I, _D, _P, _D, _P, _P, _I, _P] + [_P] * 6
         L.or_sg_assemble.argtypes = [_I, _I, _D, _P, _I, _D, _D, _D, _P, _P, _P] + [_P] * 6
         L.or_sg_assemble_w.argtypes = [_I, _I, _D, _P, _I, _D, _D, _D, _I, _P, _P, _P] + [_P] * 6
+        L.or_sg_assemble_t.argtypes = [_I, _I, _D, _P, _I, _D, _D, _D, _I, _P, _P, _P, _P, _P] + [_P] * 6
         L.or_apply.argtypes = [_I, _I] + [_P] * 7
         L.or_residual.argtypes = [_I, _I] + [_P] * 8
         L.or_relres.restype = _D
@@ -89,6 +90,7 @@ def lib():
         L.or_mg_get.argtypes = [ctypes.c_void_p, _I, _I, _P]
         L.or_mg_assemble_poisson.argtypes = [ctypes.c_void_p, _D, _P, _P]
         L.or_mg_assemble_sg.argtypes = [ctypes.c_void_p, _I, _D, _D, _D, _P, _P, _P]
+        L.or_mg_assemble_sg_t.argtypes = [ctypes.c_void_p, _I, _D, _D, _D, _P, _P, _P, _P, _P]
         L.or_mg_vcycle.restype = _I
         L.or_mg_vcycle.argtypes = [ctypes.c_void_p, _P]
         L.or_mg_relres.restype = _D
@@ -151,13 +153,15 @@ def poisson_assemble(nr, nz, R, z, k, ne=None, np_=None, wall=0, Vwall=None):
     return out
 
 
-def sg_assemble(nr, nz, R, z, s, mu, D, dt_inv, V, nk=None, S=None, wall=0):
+def sg_assemble(nr, nz, R, z, s, mu, D, dt_inv, V, nk=None, S=None, wall=0, mun=None, Dn=None):
     """Coefficients (a, b, c, d, e, f) of Eqs. (7)-(11) in FV form.  wall=1:
-    Dirichlet wall at r = R with density 0 (identity rows i = nr)."""
+    Dirichlet wall at r = R with density 0 (identity rows i = nr).  mun, Dn:
+    node values of the mobility and diffusion coefficient (faces: mean of
+    the two nodes) instead of the constants mu, D."""
     z = np.ascontiguousarray(z, dtype=np.float64)
     out = [_field(nr, nz) for _ in range(6)]
-    lib().or_sg_assemble_w(nr, nz, R, _p(z), int(s), mu, D, dt_inv, int(wall), _p(V), _p(nk), _p(S),
-                           *[_p(o) for o in out])
+    lib().or_sg_assemble_t(nr, nz, R, _p(z), int(s), mu, D, dt_inv, int(wall), _p(mun), _p(Dn), _p(V), _p(nk),
+                           _p(S), *[_p(o) for o in out])
     return out
 
 
@@ -247,8 +251,8 @@ class MG:
             Vwall = np.ascontiguousarray(Vwall, dtype=np.float64)
         lib().or_mg_assemble_poisson_w(self.h, k, _p(ne), _p(np_), _p(Vwall))
 
-    def assemble_sg(self, s, mu, D, dt_inv, V, nk, S):
-        lib().or_mg_assemble_sg(self.h, int(s), mu, D, dt_inv, _p(V), _p(nk), _p(S))
+    def assemble_sg(self, s, mu, D, dt_inv, V, nk, S, mun=None, Dn=None):
+        lib().or_mg_assemble_sg_t(self.h, int(s), mu, D, dt_inv, _p(V), _p(nk), _p(S), _p(mun), _p(Dn))
 
     def coef(self, level=0):
         nr, nz = self.nr >> level, self.nz >> level

@@ -174,6 +174,15 @@ void or_sg_assemble_w(int nr, int nz, double R, const double *z, int s,
                       const double *V, const double *nk, const double *S,
                       double *a, double *b, double *c, double *d, double *e,
                       double *f);
+/* mun, Dn non-NULL: node values of the mobility and the diffusion
+ * coefficient (Sec. 2: field-dependent, supplied by lookup tables or a Monte
+ * Carlo code); every face uses the arithmetic mean of its two nodes, and
+ * alpha = -s mu_face/D_face (V_nb - V). */
+void or_sg_assemble_t(int nr, int nz, double R, const double *z, int s,
+                      double mu, double D, double dt_inv, int wall,
+                      const double *mun, const double *Dn, const double *V,
+                      const double *nk, const double *S, double *a, double *b,
+                      double *c, double *d, double *e, double *f);
 
 void or_sg_assemble(int nr, int nz, double R, const double *z, int s,
                     double mu, double D, double dt_inv,
@@ -190,8 +199,33 @@ void or_sg_assemble_w(int nr, int nz, double R, const double *z, int s,
                       double *a, double *b, double *c, double *d, double *e,
                       double *f)
 {
+    or_sg_assemble_t(nr, nz, R, z, s, mu, D, dt_inv, wall, NULL, NULL, V, nk, S,
+                     a, b, c, d, e, f);
+}
+
+/* Face coefficients: D of the face and q = -s mu/D, from the constants or
+ * from the means of the two nodes' values. */
+static void face_coef(int s, double mu, double D, const double *mun,
+                      const double *Dn, size_t p, size_t pn, double *Df,
+                      double *qf)
+{
+    if (mun && Dn) {
+        double m = 0.5 * (mun[p] + mun[pn]);
+        *Df = 0.5 * (Dn[p] + Dn[pn]);
+        *qf = -(double)s * m / *Df;
+    } else {
+        *Df = D;
+        *qf = -(double)s * mu / D;
+    }
+}
+
+void or_sg_assemble_t(int nr, int nz, double R, const double *z, int s,
+                      double mu, double D, double dt_inv, int wall,
+                      const double *mun, const double *Dn, const double *V,
+                      const double *nk, const double *S, double *a, double *b,
+                      double *c, double *d, double *e, double *f)
+{
     double dr = R / nr;
-    double q = -(double)s * mu / D;
     size_t n = (size_t)(nr + 1) * (nz + 1);
     memset(a, 0, n * sizeof(double));
     memset(b, 0, n * sizeof(double));
@@ -210,27 +244,36 @@ void or_sg_assemble_w(int nr, int nz, double R, const double *z, int s,
             double dzc = axial_width(z, j);
             double vol = w * dzc;
             double diag = vol * dt_inv;
+            double Df, q;
             if (i < nr) { /* face i+1/2 */
-                double g = face_radius(i, nr, R) * dzc * D / dr;
-                double al = q * (V[IDX(i + 1, j, nz)] - V[p]);
+                size_t pn = IDX(i + 1, j, nz);
+                face_coef(s, mu, D, mun, Dn, p, pn, &Df, &q);
+                double g = face_radius(i, nr, R) * dzc * Df / dr;
+                double al = q * (V[pn] - V[p]);
                 c[p] = -g * or_bernoulli_F(al);
                 diag += g * or_bernoulli_G(al);
             }
             if (i > 0) { /* face i-1/2, outward is -r */
-                double g = face_radius(i - 1, nr, R) * dzc * D / dr;
-                double al = q * (V[p] - V[IDX(i - 1, j, nz)]);
+                size_t pn = IDX(i - 1, j, nz);
+                face_coef(s, mu, D, mun, Dn, p, pn, &Df, &q);
+                double g = face_radius(i - 1, nr, R) * dzc * Df / dr;
+                double al = q * (V[p] - V[pn]);
                 a[p] = -g * or_bernoulli_G(al);
                 diag += g * or_bernoulli_F(al);
             }
             { /* face j+1/2 */
-                double g = w * D / (z[j + 1] - z[j]);
-                double al = q * (V[IDX(i, j + 1, nz)] - V[p]);
+                size_t pn = IDX(i, j + 1, nz);
+                face_coef(s, mu, D, mun, Dn, p, pn, &Df, &q);
+                double g = w * Df / (z[j + 1] - z[j]);
+                double al = q * (V[pn] - V[p]);
                 e[p] = -g * or_bernoulli_F(al);
                 diag += g * or_bernoulli_G(al);
             }
             { /* face j-1/2 */
-                double g = w * D / (z[j] - z[j - 1]);
-                double al = q * (V[p] - V[IDX(i, j - 1, nz)]);
+                size_t pn = IDX(i, j - 1, nz);
+                face_coef(s, mu, D, mun, Dn, p, pn, &Df, &q);
+                double g = w * Df / (z[j] - z[j - 1]);
+                double al = q * (V[p] - V[pn]);
                 d[p] = -g * or_bernoulli_G(al);
                 diag += g * or_bernoulli_F(al);
             }
@@ -569,7 +612,7 @@ typedef struct {
     int nr, nz;
     double R;
     double *z;
-    double *a, *b, *c, *d, *e, *f, *x, *r, *V;
+    double *a, *b, *c, *d, *e, *f, *x, *r, *V, *mu, *D;
 } or_level;
 
 typedef struct {
@@ -644,6 +687,8 @@ or_mg *or_mg_create_w(int nr, int nz, double R, const double *z, int coarsest,
         L->x = (l == 0) ? NULL : alloc_field(L->nr, L->nz);
         L->r = alloc_field(L->nr, L->nz);
         L->V = alloc_field(L->nr, L->nz);
+        L->mu = alloc_field(L->nr, L->nz);
+        L->D = alloc_field(L->nr, L->nz);
     }
     h->work = malloc(2 * (size_t)(nz + 1) * sizeof(double));
     return h;
@@ -665,6 +710,8 @@ void or_mg_destroy(or_mg *h)
         free(L->x);
         free(L->r);
         free(L->V);
+        free(L->mu);
+        free(L->D);
     }
     free(h->work);
     free(h);
@@ -701,23 +748,43 @@ void or_mg_assemble_poisson(or_mg *h, double k, const double *ne,
 
 /* SG continuity on every level; coarse levels see the potential injected
  * (coarse node value = coincident fine node value). */
-void or_mg_assemble_sg(or_mg *h, int s, double mu, double D, double dt_inv,
-                       const double *V, const double *nk, const double *S)
+/* SG operator on every level; coarse levels see the potential (and the
+ * node transport mun, Dn when given) injected: coarse node value =
+ * coincident fine node value. */
+void or_mg_assemble_sg_t(or_mg *h, int s, double mu, double D, double dt_inv,
+                         const double *V, const double *nk, const double *S,
+                         const double *mun, const double *Dn)
 {
-    memcpy(h->lev[0].V, V,
-           (size_t)(h->lev[0].nr + 1) * (h->lev[0].nz + 1) * sizeof(double));
+    size_t n0 = (size_t)(h->lev[0].nr + 1) * (h->lev[0].nz + 1) * sizeof(double);
+    int tr = mun && Dn;
+    memcpy(h->lev[0].V, V, n0);
+    if (tr) {
+        memcpy(h->lev[0].mu, mun, n0);
+        memcpy(h->lev[0].D, Dn, n0);
+    }
     for (int l = 1; l < h->nlev; ++l) {
         or_level *F = &h->lev[l - 1], *C = &h->lev[l];
         for (int I = 0; I <= C->nr; ++I)
-            for (int J = 0; J <= C->nz; ++J)
-                C->V[IDX(I, J, C->nz)] = F->V[IDX(2 * I, 2 * J, F->nz)];
+            for (int J = 0; J <= C->nz; ++J) {
+                size_t pc = IDX(I, J, C->nz), pf = IDX(2 * I, 2 * J, F->nz);
+                C->V[pc] = F->V[pf];
+                C->mu[pc] = F->mu[pf];
+                C->D[pc] = F->D[pf];
+            }
     }
     for (int l = 0; l < h->nlev; ++l) {
         or_level *L = &h->lev[l];
-        or_sg_assemble_w(L->nr, L->nz, L->R, L->z, s, mu, D, dt_inv, h->wall,
-                         L->V, l == 0 ? nk : NULL, l == 0 ? S : NULL, L->a,
-                         L->b, L->c, L->d, L->e, L->f);
+        or_sg_assemble_t(L->nr, L->nz, L->R, L->z, s, mu, D, dt_inv, h->wall,
+                         tr ? L->mu : NULL, tr ? L->D : NULL, L->V,
+                         l == 0 ? nk : NULL, l == 0 ? S : NULL, L->a, L->b,
+                         L->c, L->d, L->e, L->f);
     }
+}
+
+void or_mg_assemble_sg(or_mg *h, int s, double mu, double D, double dt_inv,
+                       const double *V, const double *nk, const double *S)
+{
+    or_mg_assemble_sg_t(h, s, mu, D, dt_inv, V, nk, S, NULL, NULL);
 }
 
 static void smooth(or_mg *h, or_level *L, double *x, int sweeps)
@@ -916,13 +983,27 @@ void or_sg_dV(int nr, int nz, double R, const double *z, int s, double mu,
     or_sg_dV_w(nr, nz, R, z, s, mu, D, 0, V, n, a, b, c, d, e);
 }
 
+void or_sg_dV_t(int nr, int nz, double R, const double *z, int s, double mu,
+                double D, int wall, const double *mun, const double *Dn,
+                const double *V, const double *n, double *a, double *b,
+                double *c, double *d, double *e);
+
 /* wall != 0: the wall rows (i = nr, identity) do not depend on V. */
 void or_sg_dV_w(int nr, int nz, double R, const double *z, int s, double mu,
                 double D, int wall, const double *V, const double *n, double *a,
                 double *b, double *c, double *d, double *e)
 {
+    or_sg_dV_t(nr, nz, R, z, s, mu, D, wall, NULL, NULL, V, n, a, b, c, d, e);
+}
+
+/* mun, Dn: node transport as in or_sg_assemble_t (held fixed: the
+ * derivative is with respect to V only). */
+void or_sg_dV_t(int nr, int nz, double R, const double *z, int s, double mu,
+                double D, int wall, const double *mun, const double *Dn,
+                const double *V, const double *n, double *a, double *b,
+                double *c, double *d, double *e)
+{
     double dr = R / nr;
-    double q = -(double)s * mu / D;
     size_t nn = (size_t)(nr + 1) * (nz + 1);
     memset(a, 0, nn * sizeof(double));
     memset(b, 0, nn * sizeof(double));
@@ -937,9 +1018,11 @@ void or_sg_dV_w(int nr, int nz, double R, const double *z, int s, double mu,
                 continue;
             double dzc = axial_width(z, j);
             double center = 0.0;
+            double Df, q;
             if (i < nr) { /* term g (G(al) n_p - F(al) n_{i+1}), al = q (V_{i+1} - V_p) */
                 size_t pn = IDX(i + 1, j, nz);
-                double g = face_radius(i, nr, R) * dzc * D / dr;
+                face_coef(s, mu, D, mun, Dn, p, pn, &Df, &q);
+                double g = face_radius(i, nr, R) * dzc * Df / dr;
                 double al = q * (V[pn] - V[p]);
                 double dF = or_bernoulli_dF(al);
                 double sl = g * ((dF + 1.0) * n[p] - dF * n[pn]);
@@ -948,7 +1031,8 @@ void or_sg_dV_w(int nr, int nz, double R, const double *z, int s, double mu,
             }
             if (i > 0) { /* term g (F(al) n_p - G(al) n_{i-1}), al = q (V_p - V_{i-1}) */
                 size_t pn = IDX(i - 1, j, nz);
-                double g = face_radius(i - 1, nr, R) * dzc * D / dr;
+                face_coef(s, mu, D, mun, Dn, p, pn, &Df, &q);
+                double g = face_radius(i - 1, nr, R) * dzc * Df / dr;
                 double al = q * (V[p] - V[pn]);
                 double dF = or_bernoulli_dF(al);
                 double sl = g * (dF * n[p] - (dF + 1.0) * n[pn]);
@@ -957,7 +1041,8 @@ void or_sg_dV_w(int nr, int nz, double R, const double *z, int s, double mu,
             }
             {
                 size_t pn = p + 1;
-                double g = w * D / (z[j + 1] - z[j]);
+                face_coef(s, mu, D, mun, Dn, p, pn, &Df, &q);
+                double g = w * Df / (z[j + 1] - z[j]);
                 double al = q * (V[pn] - V[p]);
                 double dF = or_bernoulli_dF(al);
                 double sl = g * ((dF + 1.0) * n[p] - dF * n[pn]);
@@ -966,7 +1051,8 @@ void or_sg_dV_w(int nr, int nz, double R, const double *z, int s, double mu,
             }
             {
                 size_t pn = p - 1;
-                double g = w * D / (z[j] - z[j - 1]);
+                face_coef(s, mu, D, mun, Dn, p, pn, &Df, &q);
+                double g = w * Df / (z[j] - z[j - 1]);
                 double al = q * (V[p] - V[pn]);
                 double dF = or_bernoulli_dF(al);
                 double sl = g * (dF * n[p] - (dF + 1.0) * n[pn]);

@@ -22,17 +22,18 @@ import scipy.sparse.linalg as spla
 from . import _p, lib, poisson_assemble, sg_assemble, apply, volumes, wall_values
 
 
-def _sg_dV(nr, nz, R, z, s, mu, D, V, n, wall=0):
+def _sg_dV(nr, nz, R, z, s, mu, D, V, n, wall=0, mun=None, Dn=None):
     L = lib()
     if not hasattr(L, "_dv_ready"):
         P = ctypes.POINTER(ctypes.c_double)
-        L.or_sg_dV_w.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, ctypes.c_int,
-                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P] + [P] * 5
+        L.or_sg_dV_t.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P, P, P] + [P] * 5
         L.or_bernoulli_dF.restype = ctypes.c_double
         L.or_bernoulli_dF.argtypes = [ctypes.c_double]
         L._dv_ready = True
     out = [np.zeros((nr + 1, nz + 1)) for _ in range(5)]
-    L.or_sg_dV_w(nr, nz, R, _p(z), int(s), mu, D, int(wall), _p(V), _p(n), *[_p(o) for o in out])
+    L.or_sg_dV_t(nr, nz, R, _p(z), int(s), mu, D, int(wall), _p(mun), _p(Dn), _p(V), _p(n),
+                 *[_p(o) for o in out])
     return out
 
 
@@ -47,11 +48,16 @@ class Coupled:
     between the electrode values, densities 0; the wall nodes' equations are
     u = u_wall (identity rows)."""
 
-    def __init__(self, nr, nz, R, z, phys, wall=0):
+    def __init__(self, nr, nz, R, z, phys, wall=0, transport=None):
         self.nr, self.nz, self.R = nr, nz, R
         self.z = np.ascontiguousarray(z, dtype=np.float64)
         self.ph = dict(phys)
         self.wall = int(wall)
+        # node values of mu_e, D_e, mu_p, D_p (Sec. 2: field-dependent transport
+        # supplied by tables); None: the constants of phys
+        self.tr = None
+        if transport is not None:
+            self.tr = {k: np.ascontiguousarray(transport[k], dtype=np.float64) for k in ("mue", "De", "mup", "Dp")}
         self.vol = volumes(nr, nz, R, self.z)
         self.P = poisson_assemble(nr, nz, R, self.z, 0.0, wall=self.wall)
         self.interior = np.ones((nr + 1, nz + 1))  # 0 on the wall rows
@@ -75,8 +81,11 @@ class Coupled:
 
     def residual(self, V, ne, np_, nek, npk, Se, Sp, dt_inv):
         ph, nr, nz, R, z = self.ph, self.nr, self.nz, self.R, self.z
-        Ae = sg_assemble(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], dt_inv, V, nek, Se, wall=self.wall)
-        Ap = sg_assemble(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], dt_inv, V, npk, Sp, wall=self.wall)
+        tr = self.tr or {}
+        Ae = sg_assemble(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], dt_inv, V, nek, Se, wall=self.wall,
+                         mun=tr.get("mue"), Dn=tr.get("De"))
+        Ap = sg_assemble(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], dt_inv, V, npk, Sp, wall=self.wall,
+                         mun=tr.get("mup"), Dn=tr.get("Dp"))
         Fe = apply(Ae, ne) - Ae[5]
         Fp = apply(Ap, np_) - Ap[5]
         rhsV = self.interior * self.vol * ph["k"] * (np_ - ne)
@@ -102,8 +111,9 @@ class Coupled:
     def jacobian(self, V, ne, np_, Ae, Ap):
         """Sparse 3x3-block five-point Jacobian (Eq. 14)."""
         ph, nr, nz, R, z = self.ph, self.nr, self.nz, self.R, self.z
-        eV = _sg_dV(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], V, ne, self.wall)
-        pV = _sg_dV(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], V, np_, self.wall)
+        tr = self.tr or {}
+        eV = _sg_dV(nr, nz, R, z, -1, ph["mu_e"], ph["D_e"], V, ne, self.wall, tr.get("mue"), tr.get("De"))
+        pV = _sg_dV(nr, nz, R, z, +1, ph["mu_p"], ph["D_p"], V, np_, self.wall, tr.get("mup"), tr.get("Dp"))
         rows, cols, vals = [], [], []
         i, j, node, m = self.ii, self.jj, self.node, self.m
         offs = {0: (-1, 0), 1: (0, 0), 2: (1, 0), 3: (0, -1), 4: (0, 1)}  # a, b, c, d, e
@@ -201,7 +211,7 @@ def steady(cp, V, ne, np_, Se, Sp, dt0=1e-4, growth=1.5, dt_max=0.1, tol=1e-8,
     return acc, rej, seq
 
 
-def boundary_flow(R, z, s, mu, D, V, n, wall=0):
+def boundary_flow(R, z, s, mu, D, V, n, wall=0, mun=None, Dn=None):
     """Particle flow per radian out of the domain (Sec. 3's observable is the
     ion current to the cathode): the SG face fluxes of Eqs. (8)-(9) through
     the cathode face z_{1/2}, the anode face z_{nz-1/2} and, with the
@@ -210,21 +220,62 @@ def boundary_flow(R, z, s, mu, D, V, n, wall=0):
     from . import bernoulli_F
     nr, nz = V.shape[0] - 1, V.shape[1] - 1
     dr = R / nr
-    q = -s * mu / D
+
+    def face(a, b):  # (D, q) of the face between nodes a and b
+        if mun is None:
+            return D, -s * mu / D
+        Df = 0.5 * (Dn[a] + Dn[b])
+        return Df, -s * 0.5 * (mun[a] + mun[b]) / Df
+
     imax = nr - 1 if wall else nr
     cath = anode = wflow = 0.0
     for i in range(imax + 1):
         w = dr * dr / 8 if i == 0 else (0.5 * dr * (R - 0.25 * dr) if i == nr else i * dr * dr)
+        Df, q = face((i, 0), (i, 1))
         al = q * (V[i, 1] - V[i, 0])
-        cath -= w * D / (z[1] - z[0]) * (n[i, 0] * bernoulli_F(-al) - n[i, 1] * bernoulli_F(al))
+        cath -= w * Df / (z[1] - z[0]) * (n[i, 0] * bernoulli_F(-al) - n[i, 1] * bernoulli_F(al))
+        Df, q = face((i, nz - 1), (i, nz))
         al = q * (V[i, nz] - V[i, nz - 1])
-        anode += w * D / (z[nz] - z[nz - 1]) * (n[i, nz - 1] * bernoulli_F(-al) - n[i, nz] * bernoulli_F(al))
+        anode += w * Df / (z[nz] - z[nz - 1]) * (n[i, nz - 1] * bernoulli_F(-al) - n[i, nz] * bernoulli_F(al))
     if wall:
         for j in range(1, nz):
             area = (nr - 0.5) * dr * 0.5 * (z[j + 1] - z[j - 1])
+            Df, q = face((nr - 1, j), (nr, j))
             al = q * (V[nr, j] - V[nr - 1, j])
-            wflow += area * D / dr * (n[nr - 1, j] * bernoulli_F(-al) - n[nr, j] * bernoulli_F(al))
+            wflow += area * Df / dr * (n[nr - 1, j] * bernoulli_F(-al) - n[nr, j] * bernoulli_F(al))
     return cath, anode, wflow
+
+
+def field_strength(R, z, V):
+    """|E| = |grad V| at every node (Eq. 6): central differences, one-sided at
+    the electrodes (z) and at r = R, radial component 0 on the axis."""
+    nr, nz = V.shape[0] - 1, V.shape[1] - 1
+    dr = R / nr
+    E = np.zeros_like(V)
+    for i in range(nr + 1):
+        for j in range(nz + 1):
+            if i == 0:
+                er = 0.0
+            elif i == nr:
+                er = (V[i, j] - V[i - 1, j]) / dr
+            else:
+                er = (V[i + 1, j] - V[i - 1, j]) / (2.0 * dr)
+            if j == 0:
+                ez = (V[i, 1] - V[i, 0]) / (z[1] - z[0])
+            elif j == nz:
+                ez = (V[i, nz] - V[i, nz - 1]) / (z[nz] - z[nz - 1])
+            else:
+                ez = (V[i, j + 1] - V[i, j - 1]) / (z[j + 1] - z[j - 1])
+            E[i, j] = np.sqrt(er * er + ez * ez)
+    return E
+
+
+def transport_from_table(R, z, V, Et, mut, Dt):
+    """Node mobility and diffusion coefficient from tables of the field
+    strength (Sec. 2: mu(E), D(E) from lookup tables): linear interpolation
+    between the bracketing entries, the end values outside the table."""
+    E = field_strength(R, z, V)
+    return np.interp(E, Et, mut), np.interp(E, Et, Dt)
 
 
 def prolong_state(zf, Vc, nec, npc, phys, wall=0):
@@ -277,7 +328,7 @@ def chain(R, z_of, phys, N0, N1, V, ne, np_, S_of, wall=0, **steady_kw):
 # transpose of the bilinear prolongation, field by field; coarsest level
 # solved exactly.
 # ---------------------------------------------------------------------------
-def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8, wall=0):
+def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8, wall=0, transport=None):
     """Per level: the Coupled system, its Jacobian (CSR) for a BE step of
     size dt (inf: steady), the unknown indices of both colours."""
     from . import levels as _nlev
@@ -286,8 +337,9 @@ def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8, wall=0):
     out = []
     z = np.ascontiguousarray(z, dtype=np.float64)
     V, ne, np_ = (np.ascontiguousarray(a, dtype=np.float64) for a in (V, ne, np_))
+    tr = transport
     for l in range(nlev):
-        cp = Coupled(nr, nz, R, z, phys, wall=wall)
+        cp = Coupled(nr, nz, R, z, phys, wall=wall, transport=tr)
         zero = np.zeros_like(V)
         (_, (Ae, Ap)) = cp.residual(V, ne, np_, ne, np_, zero, zero, dt_inv)
         J = cp.jacobian(V, ne, np_, Ae, Ap).tocsr()
@@ -299,6 +351,8 @@ def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8, wall=0):
             nr, nz = nr // 2, nz // 2
             z = np.ascontiguousarray(z[::2])
             V, ne, np_ = (np.ascontiguousarray(a[::2, ::2]) for a in (V, ne, np_))
+            if tr is not None:
+                tr = {k: np.ascontiguousarray(v[::2, ::2]) for k, v in tr.items()}
     return out
 
 

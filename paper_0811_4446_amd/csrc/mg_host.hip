@@ -101,6 +101,7 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
         L.g.ty = 4;
         L.g.sh = 8;
         L.g.wall = d->r_outer_bc == MG_WALL_DIRICHLET ? 1 : 0;
+        L.g.xcd = getenv("MGF_NO_XCD_ORDER") ? 0 : 1;
         L.g.pitch = pitch;
         L.g.dr = d->R / nr;
         L.g.wr = cv.take<double>(nr + 1);
@@ -131,6 +132,8 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
         L.x2 = cv.take<double>(nf);
         L.r = cv.take<double>(nf);
         L.vinj = cv.take<double>(nf);
+        L.muinj = cv.take<double>(nf);
+        L.Dinj = cv.take<double>(nf);
         if (ir) {
             L.x32 = cv.take<float>(nf);
             L.x2_32 = cv.take<float>(nf);
@@ -515,6 +518,8 @@ int sg_assemble(mg_ctx *c, int eq, const mg_physics *ph, const mg_state *st, dou
         double sgn = el ? -1.0 : 1.0;
         double q = -sgn * mu / D;
         double dt_inv = (dt > 0 && isfinite(dt)) ? 1.0 / dt : 0.0;
+        const double *mun = el ? st->mue : st->mup, *Dn = el ? st->De : st->Dp;
+        if ((mun == nullptr) != (Dn == nullptr)) return fail(MG_EINVAL, "node mobility and diffusion go together");
         launch_set_electrodes(g0, n, el ? ph->ne_bottom : ph->np_bottom, el ? ph->ne_top : ph->np_top, s);
         launch_set_wall(g0, n, 0.0, 0.0, s);
         const double *V = st->V;
@@ -523,8 +528,15 @@ int sg_assemble(mg_ctx *c, int eq, const mg_physics *ph, const mg_state *st, dou
             if (l > 0) {
                 launch_inject(c->lev[l - 1].g, V, L.g, L.vinj, s);
                 V = L.vinj;
+                if (mun) {  // node transport injected like the potential
+                    launch_inject(c->lev[l - 1].g, mun, L.g, L.muinj, s);
+                    launch_inject(c->lev[l - 1].g, Dn, L.g, L.Dinj, s);
+                    mun = L.muinj;
+                    Dn = L.Dinj;
+                }
             }
-            launch_sg_assemble(L.g, L.op[eq], V, l == 0 ? n : nullptr, l == 0 ? S : nullptr, q, D, dt_inv, s);
+            launch_sg_assemble(L.g, L.op[eq], V, l == 0 ? n : nullptr, l == 0 ? S : nullptr, q, D, dt_inv, s, mun,
+                               Dn, sgn);
         }
     }
     const Level &Lc = c->lev[c->nlev - 1];
@@ -753,12 +765,24 @@ int mg_boundary_flow(mg_ctx *c, const mg_physics *ph, const mg_state *st, double
     if (!(ph->D_e > 0) || !(ph->D_p > 0)) return fail(MG_EINVAL, "need D_e, D_p > 0");
     const Geom &g = c->lev[0].g;
     hipStream_t s = c->stream;
-    launch_boundary_flow(g, st->V, st->ne, ph->mu_e / ph->D_e, ph->D_e, c->scal, s);
-    launch_boundary_flow(g, st->V, st->np, -ph->mu_p / ph->D_p, ph->D_p, c->scal + 3, s);
+    if ((st->mue == nullptr) != (st->De == nullptr) || (st->mup == nullptr) != (st->Dp == nullptr))
+        return fail(MG_EINVAL, "node mobility and diffusion go together");
+    launch_boundary_flow(g, st->V, st->ne, ph->mu_e / ph->D_e, ph->D_e, c->scal, s, st->mue, st->De, -1.0);
+    launch_boundary_flow(g, st->V, st->np, -ph->mu_p / ph->D_p, ph->D_p, c->scal + 3, s, st->mup, st->Dp, 1.0);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(c->pinned, c->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     for (int k = 0; k < 6; ++k) out[k] = c->pinned[k];
+    return MG_OK;
+}
+
+int mg_transport_table(mg_ctx *c, const double *V, const double *E_tab, const double *mu_tab, const double *D_tab,
+                       int32_t ntab, double *mu_out, double *D_out) {
+    if (int e = check_ctx(c)) return e;
+    if (!V || !E_tab || !mu_tab || !D_tab || !mu_out || !D_out) return fail(MG_EINVAL, "null argument");
+    if (ntab < 2) return fail(MG_EINVAL, "a table needs at least 2 entries (got %d)", ntab);
+    launch_transport_table(c->lev[0].g, V, E_tab, mu_tab, D_tab, ntab, mu_out, D_out, c->stream);
+    HIP_OK(hipGetLastError());
     return MG_OK;
 }
 

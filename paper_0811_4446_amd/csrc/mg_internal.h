@@ -20,6 +20,7 @@ struct Geom {
     int ty;             // radial rows per workgroup of the 2D kernels (tuning)
     int sh;             // radial rows of a red-black sweep tile: 8 (default) or 16
     int wall;           // 1: Dirichlet wall at r = R (rows i = nr are identity rows)
+    int xcd;            // 1: sweep tiles in XCD-contiguous order (xcd_tile), 0: launch order
     int64_t pitch;
     double dr;
     const double *wr;   // radial width of node i (area of its z-faces), nr+1
@@ -28,6 +29,11 @@ struct Geom {
     const double *dz;   // z[j+1]-z[j], nz
     const double *dzc;  // axial control width (dz[j-1]+dz[j])/2, nz+1 (0 at electrodes)
     const double *wl;   // prolongation weight of coarse node J for fine node 2J+1, nz/2
+};
+
+// Optional node values of the transport coefficients (null: constants).
+struct NodeTransport {
+    const double *mue = nullptr, *De = nullptr, *mup = nullptr, *Dp = nullptr;
 };
 
 // Five-point operator plus right-hand side, FV (integrated) form:
@@ -42,6 +48,7 @@ struct Level {
     Op<double> op[3];
     Op<float> op32[3];
     double *x, *r, *vinj;
+    double *muinj, *Dinj;  // node transport injected to this level (scalar path)
     double *x2;        // partner of the level's field for one-launch sweeps
     float *x32, *r32, *x2_32;
     double *cinv[3];   // coarsest level only: transposed inverse, n x n
@@ -107,8 +114,10 @@ __device__ inline void pivot_search_wave0(const double *M, int64_t n2, int col, 
 // ---- kernel launchers (mg_kernels.hip) ----
 void launch_poisson_assemble(const Geom &g, Op<double> op, const double *ne, const double *np,
                              double k, bool charge, double vlo, double vhi, hipStream_t s);
+// mun, Dn: node transport (face = mean of its nodes; q = -sgn mu/D), or null (q, D)
 void launch_sg_assemble(const Geom &g, Op<double> op, const double *V, const double *nk,
-                        const double *S, double q, double D, double dt_inv, hipStream_t s);
+                        const double *S, double q, double D, double dt_inv, hipStream_t s,
+                        const double *mun = nullptr, const double *Dn = nullptr, double sgn = 0.0);
 void launch_inject(const Geom &gf, const double *vf, const Geom &gc, double *vc, hipStream_t s);
 void launch_set_electrodes(const Geom &g, double *u, double lo, double hi, hipStream_t s,
                            const double *lohi = nullptr, const Batch &bt = Batch());
@@ -118,7 +127,9 @@ void launch_set_wall(const Geom &g, double *u, double lo, double hi, hipStream_t
                      const double *lohi = nullptr, const Batch &bt = Batch());
 // Particle flow out through cathode, anode and wall (3 device doubles).
 void launch_boundary_flow(const Geom &g, const double *V, const double *n, double q, double D, double *out,
-                          hipStream_t s);
+                          hipStream_t s, const double *mun = nullptr, const double *Dn = nullptr, double sgn = 0.0);
+void launch_transport_table(const Geom &g, const double *V, const double *Et, const double *mut, const double *Dt,
+                            int ntab, double *mu, double *D, hipStream_t s);
 // Electrode rows and (with a wall) wall row of the three state fields.
 void set_boundary(const Geom &g, double *V, double *ne, double *np, const mg_physics &ph, hipStream_t s);
 void launch_fill(double *p, int64_t n, double v, hipStream_t s, const Batch &bt = Batch());

@@ -84,9 +84,23 @@ __global__ void k_poisson_assemble(Geom g, Op<double> op, const double *__restri
 //   alpha = q (V_{i+1} - V_i),  q = -s mu/D.
 // dt_inv = 0 gives the steady operator.
 // ---------------------------------------------------------------------------
+// Face coefficients (D, q = -sgn mu/D): from the node values (mean of the
+// two nodes) when mun is given, else the constants.
+__device__ inline void face_qd(const double *mun, const double *Dn, double sgn, int64_t p, int64_t pn, double q,
+                               double D, double &qf, double &Df) {
+    if (mun) {
+        Df = 0.5 * (Dn[p] + Dn[pn]);
+        qf = -sgn * (0.5 * (mun[p] + mun[pn])) / Df;
+    } else {
+        Df = D;
+        qf = q;
+    }
+}
+
 __global__ void k_sg_assemble(Geom g, Op<double> op, const double *__restrict__ V,
                               const double *__restrict__ nk, const double *__restrict__ S,
-                              double q, double D, double dt_inv) {
+                              double q0, double D0, double dt_inv, const double *__restrict__ mun,
+                              const double *__restrict__ Dn, double sgn) {
     int j = blockIdx.x * kTX + threadIdx.x;
     int i = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > g.nr || j > g.nz) return;
@@ -104,8 +118,9 @@ __global__ void k_sg_assemble(Geom g, Op<double> op, const double *__restrict__ 
     double vol = w * dzc;
     double vc = V[p];
     double diag = vol * dt_inv;
-    double ca = 0.0, cc = 0.0;
+    double ca = 0.0, cc = 0.0, q, D;
     if (i < g.nr) {
+        face_qd(mun, Dn, sgn, p, p + g.pitch, q0, D0, q, D);
         double gg = g.fr[i] * dzc * D / g.dr;
         double al = q * (V[p + g.pitch] - vc);
         double F = bern_F(al);
@@ -113,6 +128,7 @@ __global__ void k_sg_assemble(Geom g, Op<double> op, const double *__restrict__ 
         diag += gg * bern_F(-al);
     }
     if (i > 0) {
+        face_qd(mun, Dn, sgn, p, p - g.pitch, q0, D0, q, D);
         double gg = g.fr[i - 1] * dzc * D / g.dr;
         double al = q * (vc - V[p - g.pitch]);
         double F = bern_F(al);
@@ -121,12 +137,14 @@ __global__ void k_sg_assemble(Geom g, Op<double> op, const double *__restrict__ 
     }
     double ce, cd;
     {
+        face_qd(mun, Dn, sgn, p, p + 1, q0, D0, q, D);
         double gg = w * D / g.dz[j];
         double al = q * (V[p + 1] - vc);
         ce = -gg * bern_F(al);
         diag += gg * bern_F(-al);
     }
     {
+        face_qd(mun, Dn, sgn, p, p - 1, q0, D0, q, D);
         double gg = w * D / g.dz[j - 1];
         double al = q * (vc - V[p - 1]);
         cd = -gg * bern_F(-al);
@@ -185,22 +203,26 @@ __global__ void k_set_wall(Geom g, double *u, double lo, double hi, const double
 // out[1] anode (face z_{nz-1/2}), out[2] wall (face r_{nr-1/2}, j = 1..nz-1,
 // Dirichlet wall only).  One workgroup; fixed-order tree sums.
 __global__ __launch_bounds__(1024) void k_boundary_flow(Geom g, const double *__restrict__ V,
-                                                         const double *__restrict__ n, double q, double D,
-                                                         double *__restrict__ out) {
+                                                         const double *__restrict__ n, double q0, double D0,
+                                                         double *__restrict__ out, const double *__restrict__ mun,
+                                                         const double *__restrict__ Dn, double sgn) {
     __shared__ double sh[3][1024];
     const int t = threadIdx.x;
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
     const int imax = g.wall ? g.nr - 1 : g.nr;
     for (int i = t; i <= imax; i += 1024) {
         const double w = g.wr[i];
+        double q, D;
         {
             const int64_t p0 = at(g, i, 0), p1 = at(g, i, 1);
+            face_qd(mun, Dn, sgn, p0, p1, q0, D0, q, D);
             const double al = q * (V[p1] - V[p0]);
             const double phi = D / g.dz[0] * (n[p0] * bern_F(-al) - n[p1] * bern_F(al));
             c0 += -phi * w;
         }
         {
             const int64_t pa = at(g, i, g.nz - 1), pb = at(g, i, g.nz);
+            face_qd(mun, Dn, sgn, pa, pb, q0, D0, q, D);
             const double al = q * (V[pb] - V[pa]);
             const double phi = D / g.dz[g.nz - 1] * (n[pa] * bern_F(-al) - n[pb] * bern_F(al));
             c1 += phi * w;
@@ -209,6 +231,8 @@ __global__ __launch_bounds__(1024) void k_boundary_flow(Geom g, const double *__
     if (g.wall)
         for (int j = 1 + t; j < g.nz; j += 1024) {
             const int64_t pa = at(g, g.nr - 1, j), pb = at(g, g.nr, j);
+            double q, D;
+            face_qd(mun, Dn, sgn, pa, pb, q0, D0, q, D);
             const double al = q * (V[pb] - V[pa]);
             const double phi = D / g.dr * (n[pa] * bern_F(-al) - n[pb] * bern_F(al));
             c2 += phi * g.fr[g.nr - 1] * g.dzc[j];
@@ -223,6 +247,53 @@ __global__ __launch_bounds__(1024) void k_boundary_flow(Geom g, const double *__
         __syncthreads();
     }
     if (t < 3) out[t] = sh[t][0];
+}
+
+// Node transport from tables of |E| (see mg_transport_table): the field
+// strength from central differences of V (one-sided at the electrodes and
+// at r = R; the radial component vanishes on the axis), then linear
+// interpolation between the bracketing table entries (clamped).
+__global__ void k_transport_table(Geom g, const double *__restrict__ V, const double *__restrict__ Et,
+                                  const double *__restrict__ mut, const double *__restrict__ Dt, int ntab,
+                                  double *__restrict__ mu, double *__restrict__ Dv) {
+    int j = blockIdx.x * kTX + threadIdx.x;
+    int i = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > g.nr || j > g.nz) return;
+    const int64_t p = at(g, i, j);
+    double er = 0.0, ez;
+    if (i > 0 && i < g.nr)
+        er = (V[p + g.pitch] - V[p - g.pitch]) / (2.0 * g.dr);
+    else if (i == g.nr)
+        er = (V[p] - V[p - g.pitch]) / g.dr;
+    if (j == 0)
+        ez = (V[p + 1] - V[p]) / g.dz[0];
+    else if (j == g.nz)
+        ez = (V[p] - V[p - 1]) / g.dz[g.nz - 1];
+    else
+        ez = (V[p + 1] - V[p - 1]) / (g.dz[j - 1] + g.dz[j]);
+    const double E = sqrt(er * er + ez * ez);
+    double m, d;
+    if (E <= Et[0]) {
+        m = mut[0];
+        d = Dt[0];
+    } else if (E >= Et[ntab - 1]) {
+        m = mut[ntab - 1];
+        d = Dt[ntab - 1];
+    } else {
+        int lo = 0, hi = ntab - 1;  // Et[lo] < E < Et[hi]
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (Et[mid] <= E)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const double t = (E - Et[lo]) / (Et[hi] - Et[lo]);
+        m = mut[lo] + t * (mut[hi] - mut[lo]);
+        d = Dt[lo] + t * (Dt[hi] - Dt[lo]);
+    }
+    mu[p] = m;
+    Dv[p] = d;
 }
 
 template <class T>
@@ -634,7 +705,16 @@ __global__ __launch_bounds__(kSWs *(SH + STile<SH>::kSR)) void k_rb_sweep_s(Geom
     constexpr int W = kSWs + 2, W2 = kSWs + 4;
     __shared__ T lx[(kSH + 2) * W];
     __shared__ T lin[(kSH + 4) * W2];
-    const int i0 = blockIdx.y * kSH, j0 = blockIdx.x * kSWs;
+    int tx = blockIdx.x, ty = blockIdx.y;
+    if (g.xcd) {  // tiles in XCD-contiguous order (neighbouring tiles share ring lines in one L2)
+        const int nx = gridDim.x, n = gridDim.x * gridDim.y;
+        const int b = blockIdx.y * nx + blockIdx.x;
+        const int k = b & 7, q = n >> 3, r = n & 7;
+        const int t = k * q + (k < r ? k : r) + (b >> 3);
+        tx = t % nx;
+        ty = t / nx;
+    }
+    const int i0 = ty * kSH, j0 = tx * kSWs;
     const int ti = threadIdx.y, tj = threadIdx.x, tid = ti * kSWs + tj;
     for (int t = tid; t < (kSH + 4) * W2; t += kSWs * (kSH + kSR)) {
         const int ii = i0 - 2 + t / W2, jj = j0 - 2 + t % W2;
@@ -1133,8 +1213,14 @@ void launch_poisson_assemble(const Geom &g, Op<double> op, const double *ne, con
 }
 
 void launch_sg_assemble(const Geom &g, Op<double> op, const double *V, const double *nk,
-                        const double *S, double q, double D, double dt_inv, hipStream_t s) {
-    k_sg_assemble<<<grid2d(g), blk2d(g), 0, s>>>(g, op, V, nk, S, q, D, dt_inv);
+                        const double *S, double q, double D, double dt_inv, hipStream_t s, const double *mun,
+                        const double *Dn, double sgn) {
+    k_sg_assemble<<<grid2d(g), blk2d(g), 0, s>>>(g, op, V, nk, S, q, D, dt_inv, mun, Dn, sgn);
+}
+
+void launch_transport_table(const Geom &g, const double *V, const double *Et, const double *mut, const double *Dt,
+                            int ntab, double *mu, double *D, hipStream_t s) {
+    k_transport_table<<<grid2d(g), blk2d(g), 0, s>>>(g, V, Et, mut, Dt, ntab, mu, D);
 }
 
 void launch_inject(const Geom &gf, const double *vf, const Geom &gc, double *vc, hipStream_t s) {
@@ -1153,8 +1239,8 @@ void launch_set_wall(const Geom &g, double *u, double lo, double hi, hipStream_t
 }
 
 void launch_boundary_flow(const Geom &g, const double *V, const double *n, double q, double D, double *out,
-                          hipStream_t s) {
-    k_boundary_flow<<<1, 1024, 0, s>>>(g, V, n, q, D, out);
+                          hipStream_t s, const double *mun, const double *Dn, double sgn) {
+    k_boundary_flow<<<1, 1024, 0, s>>>(g, V, n, q, D, out, mun, Dn, sgn);
 }
 
 void set_boundary(const Geom &g, double *V, double *ne, double *np, const mg_physics &ph, hipStream_t s) {

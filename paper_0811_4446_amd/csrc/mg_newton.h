@@ -59,7 +59,7 @@ struct LevTab {
 void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
                             const double *nek, const double *npk, const double *Se, const double *Sp,
                             const NewtonPhys &ph, bool with_rhs, hipStream_t s, const NewtonPhys *php = nullptr,
-                            const Batch &bt = Batch());
+                            const Batch &bt = Batch(), const NodeTransport &tr = NodeTransport());
 template <class T>
 void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s,
                        const Batch &bt = Batch());
@@ -89,7 +89,7 @@ void launch_prolong3(const Geom &gf, T *xf, int64_t pf, const Geom &gc, const T 
 // (node (i, j) of level shift[k] reads the finest node (i, j) << shift[k]).
 void launch_newton_assemble_coarse(LevTab t, const double *V, const double *ne, const double *np, int64_t pitch0,
                                    const NewtonPhys &ph, hipStream_t s, const NewtonPhys *php = nullptr,
-                                   const Batch &bt = Batch());
+                                   const Batch &bt = Batch(), const NodeTransport &tr = NodeTransport());
 // FP32 copies t.J32[k] of every level's Jacobian t.J[k].
 void launch_block_to_f32_levels(LevTab t, hipStream_t s, const Batch &bt = Batch());
 void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, double *invT, hipStream_t s,

@@ -84,7 +84,8 @@ inline __device__ Face sg_face(bool plus, double q, double gd, double Vc, double
 template <class Ix>
 inline __device__ void assemble_node(const Geom &g, const BOp &J, int i, int j, Ix sidx, const double *V,
                                      const double *ne, const double *np, const double *nek, const double *npk,
-                                     const double *Se, const double *Sp, const NewtonPhys &ph, bool with_rhs) {
+                                     const double *Se, const double *Sp, const NewtonPhys &ph, bool with_rhs,
+                                     const NodeTransport &tr) {
     int64_t p = at(g, i, j);
     if (j == 0 || j == g.nz) {
         for (int k = 0; k < kBPlanes; ++k) J.pl(k)[p] = 0.0;
@@ -117,8 +118,18 @@ inline __device__ void assemble_node(const Geom &g, const BOp &J, int i, int j, 
         bool plus = (d == 2 || d == 4);
         int64_t q = nbp[d];
         double Vn = V[q];
-        Face fe = sg_face(plus, ph.qe, geo[d] * ph.De, Vc, Vn, ec, ne[q]);
-        Face fp = sg_face(plus, ph.qp, geo[d] * ph.Dp, Vc, Vn, pc, np[q]);
+        // face transport: the constants, or the mean of the two nodes' values
+        double qe = ph.qe, De = ph.De, qp = ph.qp, Dp = ph.Dp;
+        if (tr.mue) {
+            De = 0.5 * (tr.De[s] + tr.De[q]);
+            qe = (0.5 * (tr.mue[s] + tr.mue[q])) / De;  // -s mu/D, s = -1
+        }
+        if (tr.mup) {
+            Dp = 0.5 * (tr.Dp[s] + tr.Dp[q]);
+            qp = -(0.5 * (tr.mup[s] + tr.mup[q])) / Dp;  // s = +1
+        }
+        Face fe = sg_face(plus, qe, geo[d] * De, Vc, Vn, ec, ne[q]);
+        Face fp = sg_face(plus, qp, geo[d] * Dp, Vc, Vn, pc, np[q]);
         ee[d] = fe.nb_n;
         ee[1] += fe.c_n;
         eV[d] = fe.nb_V;
@@ -169,7 +180,7 @@ __global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, c
                                   const double *__restrict__ np, const double *__restrict__ nek,
                                   const double *__restrict__ npk, const double *__restrict__ Se,
                                   const double *__restrict__ Sp, NewtonPhys ph, int with_rhs,
-                                  const NewtonPhys *__restrict__ php, Batch bt) {
+                                  const NewtonPhys *__restrict__ php, Batch bt, NodeTransport tr) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     g = geom_off(g, bo_);
@@ -188,7 +199,7 @@ __global__ void k_newton_assemble(Geom g, BOp J, const double *__restrict__ V, c
     if (i > g.nr || j > g.nz) return;
     const int64_t pitch = g.pitch;
     assemble_node(g, J, i, j, [pitch](int a, int b) { return (int64_t)a * pitch + b; }, V, ne, np, nek, npk, Se, Sp,
-                  ph, with_rhs != 0);
+                  ph, with_rhs != 0, tr);
 }
 
 // Levels 1..n of the hierarchy in one launch: blockIdx.y ranges over the
@@ -200,7 +211,7 @@ __global__ __launch_bounds__(kTX *kLevTabTY) void k_newton_assemble_coarse(LevTa
                                                                           const double *__restrict__ np,
                                                                           int64_t pitch0, NewtonPhys ph,
                                                                           const NewtonPhys *__restrict__ php,
-                                                                          Batch bt) {
+                                                                          Batch bt, NodeTransport tr) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     int l = 0;
     while (l + 1 < t.n && (int)blockIdx.y >= t.y0[l + 1]) ++l;
@@ -218,7 +229,7 @@ __global__ __launch_bounds__(kTX *kLevTabTY) void k_newton_assemble_coarse(LevTa
     if (i > g.nr || j > g.nz) return;
     const int64_t si = pitch0 << t.shift[l], sj = int64_t(1) << t.shift[l];
     assemble_node(g, J, i, j, [si, sj](int a, int b) { return (int64_t)a * si + (int64_t)b * sj; }, V, ne, np,
-                  nullptr, nullptr, nullptr, nullptr, ph, false);
+                  nullptr, nullptr, nullptr, nullptr, ph, false, tr);
 }
 
 // Sum over the four neighbours of B_nb x_nb for the three rows; xnb(t, c)
@@ -352,6 +363,26 @@ __global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__re
     block_gs_node(g, J, f, x, i, j);
 }
 
+// Tile of a sweep workgroup.  The hardware deals workgroups to the eight
+// XCDs round-robin by linear index b (XCD = b mod 8); with g.xcd the tile of
+// workgroup b is t = start(b mod 8) + b / 8, so every XCD works through one
+// contiguous run of tiles in row-major order and neighbouring tiles, whose
+// rings overlap, read each other's Jacobian lines from the same L2.  A
+// permutation of the tiles: the arithmetic is unchanged.
+__device__ inline void sweep_tile(const Geom &g, int &tx, int &ty) {
+    if (!g.xcd) {
+        tx = blockIdx.x;
+        ty = blockIdx.y;
+        return;
+    }
+    const int nx = gridDim.x, n = gridDim.x * gridDim.y;
+    const int b = blockIdx.y * nx + blockIdx.x;
+    const int k = b & 7, q = n >> 3, r = n & 7;
+    const int t = k * q + (k < r ? k : r) + (b >> 3);
+    tx = t % nx;
+    ty = t / nx;
+}
+
 // One full collective red-black sweep (colour 0, then colour 1) from the
 // input to xout (xin and xout distinct, electrode rows zero).  The input is
 // xin, or zero (zin != 0, xin not read), or xin plus the bilinear
@@ -393,7 +424,9 @@ __global__ __launch_bounds__(kSW *(SH + SweepTile<SH>::kSR)) void k_block_rb_swe
     constexpr int W = kSW + 2, W2 = kSW + 4;
     __shared__ T lx[3][(kSH + 2) * W];
     __shared__ T lin[3][(kSH + 4) * W2];
-    const int i0 = blockIdx.y * kSH, j0 = blockIdx.x * kSW;
+    int tx, ty;
+    sweep_tile(g, tx, ty);
+    const int i0 = ty * kSH, j0 = tx * kSW;
     const int64_t plane = J.plane;
     const int ti = threadIdx.y, tj = threadIdx.x;
     const int tid = ti * kSW + tj;
@@ -545,7 +578,9 @@ __global__ __launch_bounds__(Sweep2Tile<SH>::kThreads) void k_block_rb_sweep2(
     }
 
     __shared__ T w[3][kWR * kWC];
-    const int i0 = blockIdx.y * SH, j0 = blockIdx.x * kSW;
+    int tx, ty;
+    sweep_tile(g, tx, ty);
+    const int i0 = ty * SH, j0 = tx * kSW;
     const int64_t plane = J.plane;
     const int tid = threadIdx.x;
     for (int t = tid; t < kWR * kWC; t += Tl::kThreads) {
@@ -1517,9 +1552,9 @@ static dim3 gz(dim3 g, const Batch &bt) { return dim3(g.x, g.y, bt.n); }
 void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const double *ne, const double *np,
                             const double *nek, const double *npk, const double *Se, const double *Sp,
                             const NewtonPhys &ph, bool with_rhs, hipStream_t s, const NewtonPhys *php,
-                            const Batch &bt) {
+                            const Batch &bt, const NodeTransport &tr) {
     k_newton_assemble<<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, V, ne, np, nek, npk, Se, Sp, ph, with_rhs ? 1 : 0,
-                                                         php, bt);
+                                                         php, bt, tr);
 }
 template <class T>
 void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s, const Batch &bt) {
@@ -1725,9 +1760,10 @@ void launch_block_to_f32_levels(LevTab t, hipStream_t s, const Batch &bt) {
     k_block_to_f32_levels<<<grid, dim3(kTX, kLevTabTY), 0, s>>>(t, bt);
 }
 void launch_newton_assemble_coarse(LevTab t, const double *V, const double *ne, const double *np, int64_t pitch0,
-                                   const NewtonPhys &ph, hipStream_t s, const NewtonPhys *php, const Batch &bt) {
+                                   const NewtonPhys &ph, hipStream_t s, const NewtonPhys *php, const Batch &bt,
+                                   const NodeTransport &tr) {
     dim3 grid = levtab_grid(t, bt);
-    k_newton_assemble_coarse<<<grid, dim3(kTX, kLevTabTY), 0, s>>>(t, V, ne, np, pitch0, ph, php, bt);
+    k_newton_assemble_coarse<<<grid, dim3(kTX, kLevTabTY), 0, s>>>(t, V, ne, np, pitch0, ph, php, bt, tr);
 }
 
 // planes -> FP32 copies (n planes of `plane` elements)

@@ -195,8 +195,13 @@ void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt
     np_.dt_inv = dt_inv;
     const double *snap = c->nw.snap;
     int64_t p0 = plane_of(c->lev[0]);
+    NodeTransport tr;
+    tr.mue = st->mue;
+    tr.De = st->De;
+    tr.mup = st->mup;
+    tr.Dp = st->Dp;
     launch_newton_assemble(c->lev[0].g, bop(c, 0), st->V, st->ne, st->np, snap + p0, snap + 2 * p0, st->Se,
-                           st->Sp, np_, true, s, static_cast<const NewtonPhys *>(c->php_dev), c->bt);
+                           st->Sp, np_, true, s, static_cast<const NewtonPhys *>(c->php_dev), c->bt, tr);
     if (c->nlev > 1) {
         // every coarser level at once, each at the finest state injected to it
         LevTab t;
@@ -207,7 +212,7 @@ void assemble_all(mg_ctx *c, const mg_physics *ph, const mg_state *st, double dt
             t.J[l - 1] = bop(c, l);
         }
         launch_newton_assemble_coarse(t, st->V, st->ne, st->np, c->lev[0].g.pitch, np_, s,
-                                      static_cast<const NewtonPhys *>(c->php_dev), c->bt);
+                                      static_cast<const NewtonPhys *>(c->php_dev), c->bt, tr);
     }
     if (c->nw.prec32) {
         // FP32 copies of every level's Jacobian (the coarsest inverse's copy
@@ -933,6 +938,7 @@ int batch_state(mg_ctx *c, int p, mg_state *out) {
     out->np = reinterpret_cast<double *>(r + 2 * nf0);
     out->Se = reinterpret_cast<const double *>(r + 3 * nf0);
     out->Sp = reinterpret_cast<const double *>(r + 4 * nf0);
+    out->mue = out->De = out->mup = out->Dp = nullptr;  // batches use the constants
     return MG_OK;
 }
 
@@ -1156,7 +1162,13 @@ int steady_residual(mg_ctx *c, const mg_physics *ph, const mg_state *st, double 
     const Level &L0 = c->lev[0];
     int64_t p0 = plane_of(L0);
     BOp J = bop(c, 0);
-    launch_newton_assemble(L0.g, J, st->V, st->ne, st->np, st->ne, st->np, st->Se, st->Sp, np_, true, s);
+    NodeTransport tr;
+    tr.mue = st->mue;
+    tr.De = st->De;
+    tr.mup = st->mup;
+    tr.Dp = st->Dp;
+    launch_newton_assemble(L0.g, J, st->V, st->ne, st->np, st->ne, st->np, st->Se, st->Sp, np_, true, s, nullptr,
+                           Batch(), tr);
     launch_cgs_pass(L0.g, J.pl(kFe), J.pl(kFe), 3 * p0, 1, p0, field_weights(ph), nullptr, true, c->nw.partials,
                     c->nw.dev, s);
     HIP_OK(hipMemcpyAsync(c->pinned, c->nw.dev, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -112,3 +112,17 @@ def argon_initial(nr, nz, z, n0=1.0e14, d=ARGON_D):
     n[:, 0] = n[:, -1] = 0.0
     n[-1, :] = 0.0
     return initial_potential(nr, nz, z, 0.0, ARGON["V_top"], d), n, n.copy()
+
+
+# ---------------------------------------------------------------------------
+# Field-dependent transport of the synthetic workload (Sec. 2: mu(E), D(E)
+# supplied by lookup tables, e.g. from a Monte Carlo code in a hybrid model):
+# an electron mobility that saturates with the field, mu_e = mu0/(1 + E/Es),
+# and an electron temperature that rises with it, D_e = mu_e T0 (1 + E/Et),
+# tabulated on 41 field values in [0, 20] (dimensionless units of PHYS).
+# ---------------------------------------------------------------------------
+def electron_transport_table(mu0=100.0, T0=0.01, Es=2.0, Et=5.0, emax=20.0, n=41):
+    """(E, mu_e(E), D_e(E)) sample arrays of the synthetic table."""
+    E = np.linspace(0.0, emax, n)
+    mu = mu0 / (1.0 + E / Es)
+    return E, mu, mu * T0 * (1.0 + E / Et)

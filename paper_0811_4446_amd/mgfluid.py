@@ -49,7 +49,8 @@ class Physics(ctypes.Structure):
 
 
 class State(ctypes.Structure):
-    _fields_ = [("V", _VP), ("ne", _VP), ("np", _VP), ("Se", _VP), ("Sp", _VP)]
+    _fields_ = [("V", _VP), ("ne", _VP), ("np", _VP), ("Se", _VP), ("Sp", _VP),
+                ("mue", _VP), ("De", _VP), ("mup", _VP), ("Dp", _VP)]
 
 
 class Schedule(ctypes.Structure):
@@ -96,6 +97,7 @@ SIGNATURES = {
     "mg_set_tuning": (ctypes.c_int, [_VP, _I32, _I32]),
     "mg_steady_residual": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _PD]),
     "mg_boundary_flow": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _PD]),
+    "mg_transport_table": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _I32, _VP, _VP]),
     "mg_newton_precond": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), ctypes.c_double,
                                          _VP, _VP]),
     "wn_param_count": (ctypes.c_int, []),
@@ -209,12 +211,22 @@ class Solver:
         torch.cuda.synchronize(self.device)
         return t[:, : self.nz + 1].cpu().numpy().copy()
 
-    def state(self, V, ne, np_, Se=None, Sp=None):
-        st = State(_ptr(V).value, _ptr(ne).value, _ptr(np_).value,
-                   _ptr(Se).value if Se is not None else None,
-                   _ptr(Sp).value if Sp is not None else None)
-        st._keep = (V, ne, np_, Se, Sp)
+    def state(self, V, ne, np_, Se=None, Sp=None, mue=None, De=None, mup=None, Dp=None):
+        """mg_state over device fields; mue, De, mup, Dp: optional node
+        transport fields (None: the physics constants)."""
+        opt = lambda t: _ptr(t).value if t is not None else None
+        st = State(_ptr(V).value, _ptr(ne).value, _ptr(np_).value, opt(Se), opt(Sp), opt(mue), opt(De), opt(mup),
+                   opt(Dp))
+        st._keep = (V, ne, np_, Se, Sp, mue, De, mup, Dp)
         return st
+
+    def transport_table(self, V, E_tab, mu_tab, D_tab, mu_out, D_out):
+        """mg_transport_table: node mobility and diffusion from tables of
+        |E| (device tensors; mu_out and D_out are fields)."""
+        n = E_tab.numel()
+        assert mu_tab.numel() == n and D_tab.numel() == n
+        _check(lib().mg_transport_table(self.ctx, _ptr(V), _ptr(E_tab), _ptr(mu_tab), _ptr(D_tab), n, _ptr(mu_out),
+                                        _ptr(D_out)))
 
     # ---- calls ----
     def assemble(self, eq, phys, state, dt=math.inf):

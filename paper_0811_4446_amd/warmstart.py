@@ -333,8 +333,9 @@ def compare(net, data, timed=8, criterion="run", log=print, prec=M.FP32_IR, atte
                    single_inference_seconds=[round(s["inference"], 4) for s in single["learned"]],
                    single_steps_plain=[s["steps"] for s in single["plain"]],
                    single_steps_learned=[s["steps"] for s in single["learned"]],
-                   time_ratio_median=float(np.median([l["seconds"] / p_["seconds"]
-                                                      for l, p_ in zip(single["learned"], single["plain"])])),
+                   time_ratio_median=(float(np.median([l["seconds"] / p_["seconds"]
+                                                       for l, p_ in zip(single["learned"], single["plain"])]))
+                                      if single["plain"] else None),
                    batch_seconds=dict(plain=res["plain"]["batch_seconds"], network=res["raw"]["batch_seconds"]))
     log(summary)
     summary["_chosen_finals"] = chosen
