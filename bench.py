@@ -33,16 +33,19 @@ sys.path.insert(0, ROOT)
 METRIC = ("time-to-steady at 257² & 1025² (s), V-cycle HBM GB/s; "
           "plain FP64 vs chosen forms")
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the finest-level sweep, from FETCH_SIZE and
-# WRITE_SIZE counter runs (x2.0 and x1.0 by a 512 MiB copy's counters; the
-# runs and tables are kept under profiles/).  Valid only for the kernel
-# source they were taken with (the text between the two markers, which holds
-# the sweep kernel and its device helpers): any change to it reports null.
+# HBM bytes per launch of the finest-level sweep (k_block_rb_sweep) and per
+# V-cycle of the two-sweep launches (k_block_rb_sweep2 on 129x129, 65x65,
+# 33x33, pre- and post-smoothing), from FETCH_SIZE and WRITE_SIZE counter
+# runs (x2.0 and x1.0 by a 512 MiB copy's counters; the runs and tables are
+# kept under profiles/).  Valid only for the kernel source they were taken
+# with (the text between the two markers, which holds both sweep kernels
+# and their device helpers): any change to it reports null.
 MEASURED_TRAFFIC = {"source": "paper_0811_4446_amd/csrc/mg_newton.hip",
                     "begin": "// Bilinear prolongation (z-distance weights) of one coarse field",
-                    "end": "// r = f - B x (apply == 0) or r = B x (apply == 1) at one node, 3 fields,",
-                    "sha1": "b39e9f5b84dc8975b4df88c7e2912092023d8678",
-                    "bytes": {256: 30641562, 1024: 491563827}}
+                    "end": "__global__ void k_block_residual(Geom g, BOpT<T> J",
+                    "sha1": "6607a2516993b7eac1a230194afc547ce2ca15d6",
+                    "bytes": {256: 19947212, 1024: 320607436},
+                    "sweep2_vcycle_bytes": {256: 18434252}}
 
 
 def log(*a):
@@ -134,13 +137,13 @@ def _host():
     return dict(cpu=model, nproc=os.cpu_count())
 
 
-def _traffic(N):
+def _traffic(N, key="bytes"):
     import hashlib
     with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"])) as fh:
         src = fh.read()
     a, e = src.find(MEASURED_TRAFFIC["begin"]), src.find(MEASURED_TRAFFIC["end"])
     same = 0 <= a < e and hashlib.sha1(src[a:e].encode()).hexdigest() == MEASURED_TRAFFIC["sha1"]
-    return MEASURED_TRAFFIC["bytes"].get(N) if same else None
+    return MEASURED_TRAFFIC[key].get(N) if same else None
 
 
 def roofline(sol, N, reps=200, resident=None):
@@ -191,7 +194,8 @@ def roofline_dominant(sol, N, reps=200):
         tot_t += 2 * avg_ms * 1e-3
     achieved = tot_b / tot_t / 1e9
     return dict(bound="hbm", kernel="k_block_rb_sweep2", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=_traffic(N, "sweep2_vcycle_bytes"),
+                algorithmic_bytes_per_unit=int(tot_b),
                 resident="Infinity Cache (levels 129x129..33x33 of the 257x257 solve, < 5 MB)",
                 limited_by="launch and barrier latency (microsecond launches)",
                 unit_of_work="one V-cycle's two-sweep launches (pre and post on each level)",
