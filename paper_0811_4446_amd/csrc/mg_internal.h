@@ -84,6 +84,26 @@ __host__ __device__ inline Geom geom_off(Geom g, int64_t off) {
 }
 
 #ifdef __HIPCC__
+constexpr int kSumLoads = 8;
+// sum of p[b * ld + c] over b = b0, b0 + step, ... < n, added in that order;
+// the loads are issued kSumLoads at a time (a long grid's partials would
+// otherwise be one dependent load per addition).
+inline __device__ double sum_strided(const double *__restrict__ p, int n, int b0, int step, int64_t ld, int c) {
+    double a = 0.0;
+    for (int b = b0; b < n; b += step * kSumLoads) {
+        double q[kSumLoads];
+#pragma unroll
+        for (int u = 0; u < kSumLoads; ++u) {
+            const int bb = b + u * step;
+            q[u] = bb < n ? p[(int64_t)bb * ld + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSumLoads; ++u)
+            if (b + u * step < n) a += q[u];
+    }
+    return a;
+}
+
 // Partial pivoting of the Gauss-Jordan factorisations: the first wavefront
 // finds the row r in [col, n) with the largest |M[r][col]| (the first such
 // row on ties, as a serial scan would) and stores it in *piv.  The caller

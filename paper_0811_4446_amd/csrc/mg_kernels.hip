@@ -567,8 +567,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
 
     __shared__ double sh[256 * 4];
     for (int c = 0; c < ncomp; ++c) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256) acc += part[b * ncomp + c];
+        double acc = sum_strided(part, nblocks, threadIdx.x, 256, ncomp, c);
         sh[c * 256 + threadIdx.x] = acc;
     }
     __syncthreads();

@@ -1376,8 +1376,7 @@ __global__ void k_scale_reduce(Geom g, const double *__restrict__ src, double *_
 
     __shared__ double n2s;
     if (threadIdx.y == 0) {
-        double a = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kTX) a += partials[b];
+        double a = sum_strided(partials, nblk, threadIdx.x, kTX, 1, 0);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
         if (threadIdx.x == 0) {
@@ -1409,8 +1408,7 @@ __global__ __launch_bounds__(256) void k_sum_cols(const double *__restrict__ par
 
     int c = blockIdx.x;
     __shared__ double sh[256];
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += 256) acc += part[(int64_t)b * ncomp + c];
+    double acc = sum_strided(part, nblocks, threadIdx.x, 256, ncomp, c);
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
