@@ -169,16 +169,19 @@ def roofline(sol, N, reps=200, resident=None):
 def roofline_dominant(sol, N, reps=200):
     """Roofline entry of the kernel with the largest share of GPU time in the
     257x257 steady solve: the two-sweep collective red-black launch
-    (k_block_rb_sweep2) that smooths the levels 129x129, 65x65 and 33x33
-    (twice per V-cycle each: pre- and post-smoothing).  Per level, the mean
-    duration of `reps` back-to-back launches between HIP events on the
-    library's stream (the Jacobian of the last solve); algorithmic bytes of
-    one launch: per unknown node 27 Jacobian entries, 3 right-hand-side and 3
-    old values read once, 3 new values written (FP64, 288 B).  The entry's
-    achieved rate is the sum of those bytes over one V-cycle's launches
-    divided by their summed durations.  The working set of these levels
-    (under 5 MB) sits in the 256 MB Infinity Cache and each launch lasts a
-    few microseconds: the launches are bound by latency, not by HBM."""
+    (k_block_rb_sweep2) on the levels 129x129, 65x65 and 33x33, twice per
+    V-cycle each: pre-smoothing (from a zero guess, with the residual
+    restricted to the next level in the same launch) and post-smoothing.
+    Per level and launch form, the mean duration of `reps` back-to-back
+    launches between HIP events on the library's stream (the Jacobian of
+    the last solve); algorithmic bytes of one launch: per unknown node 27
+    Jacobian entries, 3 right-hand-side and 3 old values read once, 3 new
+    values written (FP64, 288 B), plus 3 values per unknown coarse node
+    written by the restricting launch.  The entry's achieved rate is the sum
+    of those bytes over one V-cycle's launches divided by their summed
+    durations.  The working set of these levels (under 5 MB) sits in the
+    256 MB Infinity Cache and each launch lasts a few microseconds: the
+    launches are bound by latency, not by HBM."""
     levels = []
     tot_b = tot_t = 0.0
     n = N
@@ -186,19 +189,22 @@ def roofline_dominant(sol, N, reps=200):
         n //= 2
         if n > 128 or n <= 16:  # two-sweep launches: 129^2 down to 33^2; below, the coarse sub-cycle
             continue
-        avg_ms = sol.time_kernel(5, l, reps=reps)
+        pre_ms = sol.time_kernel(6, l, reps=reps)
+        post_ms = sol.time_kernel(5, l, reps=reps)
         b = 8.0 * 36 * (n + 1) * (n - 1)
-        levels.append(dict(level="%dx%d" % (n + 1, n + 1), avg_launch_us=round(avg_ms * 1e3, 3),
-                           algorithmic_bytes=int(b), GBps=round(b / (avg_ms * 1e-3) / 1e9, 1)))
-        tot_b += 2 * b
-        tot_t += 2 * avg_ms * 1e-3
+        bc = 8.0 * 3 * (n // 2 + 1) * (n // 2 - 1)
+        levels.append(dict(level="%dx%d" % (n + 1, n + 1), pre_restrict_launch_us=round(pre_ms * 1e3, 3),
+                           post_launch_us=round(post_ms * 1e3, 3), algorithmic_bytes_post=int(b),
+                           algorithmic_bytes_pre=int(b + bc)))
+        tot_b += 2 * b + bc
+        tot_t += (pre_ms + post_ms) * 1e-3
     achieved = tot_b / tot_t / 1e9
     return dict(bound="hbm", kernel="k_block_rb_sweep2", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=_traffic(N, "sweep2_vcycle_bytes"),
                 algorithmic_bytes_per_unit=int(tot_b),
                 resident="Infinity Cache (levels 129x129..33x33 of the 257x257 solve, < 5 MB)",
-                limited_by="launch and barrier latency (microsecond launches)",
-                unit_of_work="one V-cycle's two-sweep launches (pre and post on each level)",
+                limited_by="launch and memory latency (microsecond launches)",
+                unit_of_work="one V-cycle's two-sweep launches (pre with restriction, and post, on each level)",
                 levels=levels, timed_launches_per_level=reps)
 
 

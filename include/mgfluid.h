@@ -123,6 +123,10 @@ typedef struct {
     double newton_tol, reject_limit;
 } mg_schedule;
 
+/* Counts of a step or a steady run.  final_relres: weighted relative
+ * residual of the last linear solve (Newton path: FGMRES's recurrence value
+ * when that met lin_rtol, else the true residual of the iterate; decoupled
+ * path: the largest final relres of the step's three V-cycle solves). */
 typedef struct {
     int32_t steps, rejected, vcycles, newton_its;
     double last_change, final_relres, seconds, t_end;
@@ -338,9 +342,12 @@ int mg_residual(mg_ctx *ctx, int eq, const double *x, double *r);
  * equation `eq`, assembled before; level 0), 4 full collective red-black
  * sweep in one launch (both colours; assembled Jacobian), 5 two full
  * collective red-black sweeps in one launch (assembled Jacobian; what the
- * block V-cycle launches on small levels when nu1 and nu2 are even).  For
- * the block kernels (0, 4, 5) `eq` is the grid level (0 = finest).
- * Overwrites that level's work vectors only.  Synchronises. */
+ * block V-cycle launches on small levels when nu1 and nu2 are even), 6 the
+ * same two sweeps followed in the same launch by the residual restricted to
+ * the next coarser level (the V-cycle's last pre-smoothing launch on those
+ * levels; needs a coarser level).  For the block kernels (0, 4, 5, 6) `eq`
+ * is the grid level (0 = finest).  Overwrites that level's work vectors
+ * (and for 6 the coarser level's right-hand side) only.  Synchronises. */
 int mg_time_kernel(mg_ctx *ctx, int which, int eq, int32_t reps, double *avg_ms);
 
 /* Thread-local message of the last error. */

@@ -100,6 +100,7 @@ int64_t carve(mg_ctx *c, const mg_grid_desc *d, char *base) {
         L.g.nz = nz;
         L.g.ty = 4;
         L.g.sh = 8;
+        L.g.sh2 = 8;
         L.g.wall = d->r_outer_bc == MG_WALL_DIRICHLET ? 1 : 0;
         L.g.xcd = getenv("MGF_NO_XCD_ORDER") ? 0 : 1;
         L.g.pitch = pitch;
@@ -426,10 +427,13 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     c->nw.smoother_only = getenv("MGF_SMOOTHER_ONLY") != nullptr;
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
+    if (getenv("MGF_NO_SWEEP_RESTRICT")) c->nw.sweep2_restrict = false;
     if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
     if (const char *e = getenv("MGF_CHAIN_MAX_BLOCKS")) c->nw.chain_max_blocks = atoi(e);
     if (const char *e = getenv("MGF_SWEEP_ROWS"))
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(e) == 16 ? 16 : 8;
+    if (const char *e = getenv("MGF_SWEEP2_ROWS"))
+        for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh2 = atoi(e) == 4 ? 4 : 8;
     hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->pinned_dev, c->pinned, 0);
     if (e != hipSuccess) {
@@ -722,8 +726,8 @@ int solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_schedul
 int mg_time_kernel(mg_ctx *c, int which, int eq, int32_t reps, double *avg_ms) {
     if (int e = check_ctx(c)) return e;
     if (!avg_ms || reps < 1) return fail(MG_EINVAL, "bad reps or null output");
-    if (which == 0 || which == 4 || which == 5)
-        return time_block_smoother(c, reps, which == 5 ? 2 : which == 4 ? 1 : 0, eq, avg_ms);
+    if (which == 0 || which == 4 || which == 5 || which == 6)
+        return time_block_smoother(c, reps, which == 6 ? 3 : which == 5 ? 2 : which == 4 ? 1 : 0, eq, avg_ms);
     if (int e = check_eq(eq)) return e;
     if (!c->assembled[eq]) return fail(MG_EINVAL, "equation %d not assembled", eq);
     if (which < 1 || which > 3) return fail(MG_EINVAL, "bad kernel id %d", which);

@@ -19,6 +19,7 @@ struct Geom {
     int nr, nz;
     int ty;             // radial rows per workgroup of the 2D kernels (tuning)
     int sh;             // radial rows of a red-black sweep tile: 8 (default) or 16
+    int sh2;            // radial rows of a two-sweep tile: 8 (default) or 4
     int wall;           // 1: Dirichlet wall at r = R (rows i = nr are identity rows)
     int xcd;            // 1: sweep tiles in XCD-contiguous order (xcd_tile), 0: launch order
     int64_t pitch;
@@ -269,6 +270,7 @@ struct NewtonWork {
     // many nodes; larger levels launch one sweep at a time, which is faster
     // there (measured crossover between 129^2 and 257^2)
     int64_t sweep2_max_nodes = 129 * 129;
+    bool sweep2_restrict = true;  // last pre-smoothing two-sweep launch also restricts the residual
     // largest launch grid (workgroups) whose Gram-Schmidt passes form the
     // previous pass's projections themselves (single problems only)
     int chain_max_blocks = 512;

@@ -72,6 +72,11 @@ void launch_block_rb_sweep(const Geom &g, const BOpT<T> &J, const T *f, const T 
 template <class T>
 void launch_block_rb_sweep2(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
                             const Geom *gc, const T *xc, int64_t pc, hipStream_t s, const Batch &bt = Batch());
+// The same two sweeps, then the residual f - B xout restricted to the coarse
+// right-hand side fc (level gc, plane pc) in the same launch.
+template <class T>
+void launch_block_rb_sweep2_restrict(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
+                                     const Geom &gc, T *fc, int64_t pc, hipStream_t s, const Batch &bt = Batch());
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
                            hipStream_t s, const Batch &bt = Batch());

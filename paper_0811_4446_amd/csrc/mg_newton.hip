@@ -232,10 +232,29 @@ __global__ __launch_bounds__(kTX *kLevTabTY) void k_newton_assemble_coarse(LevTa
                   nullptr, nullptr, nullptr, nullptr, ph, false, tr);
 }
 
-// Sum over the four neighbours of B_nb x_nb for the three rows; xnb(t, c)
-// returns field c of neighbour t (0: i-1, 1: i+1, 2: j-1, 3: j+1).
-template <class T, class XNb>
-inline __device__ void nb_sum_of(const BOpT<T> &J, int64_t p, const bool (&has)[4], XNb xnb, T &se, T &sp, T &sv) {
+// The kernels whose results must agree bit for bit (one- and two-sweep
+// launches, half-sweeps, the fused coarse sub-cycle, with or without the
+// restriction in the smoothing launch) share the expressions below, with
+// every product-sum written as an explicit fused multiply-add: the rounding
+// then does not depend on how the compiler contracts each kernel's code.
+template <class T>
+__device__ inline T fmad(T a, T b, T c) {
+    return fma(a, b, c);
+}
+// acc + wi (wdn r[-1] + r[0] + wup r[+1]): one fine row's share of the
+// restriction (the transpose of the z-weighted bilinear prolongation).
+template <class T>
+__device__ inline T restrict_add(T acc, T wi, T wdn, T wup, T rm, T r0, T rp) {
+    return fmad(wi, fmad(wup, rp, fmad(wdn, rm, r0)), acc);
+}
+
+// Sum over the four neighbours of B_nb x_nb for the three rows; coef(q)
+// returns the node's Jacobian entry of plane q (from memory or from a row
+// held in registers: one expression for both, so every kernel rounds the
+// same way), xnb(t, c) field c of neighbour t (0: i-1, 1: i+1, 2: j-1,
+// 3: j+1).
+template <class T, class Coef, class XNb>
+inline __device__ void nb_sum_gen(Coef coef, const bool (&has)[4], XNb xnb, T &se, T &sp, T &sv) {
     const int dirs[4] = {0, 2, 3, 4};
     se = sp = sv = T(0);
 #pragma unroll
@@ -243,10 +262,21 @@ inline __device__ void nb_sum_of(const BOpT<T> &J, int64_t p, const bool (&has)[
         if (!has[t]) continue;
         int d = dirs[t];
         T v = xnb(t, 2);
-        se += J.pl(kEE + d)[p] * xnb(t, 0) + J.pl(kEV + d)[p] * v;
-        sp += J.pl(kPP + d)[p] * xnb(t, 1) + J.pl(kPV + d)[p] * v;
-        sv += J.pl(kVV + d)[p] * v;
+        se = fmad(coef(kEE + d), xnb(t, 0), fmad(coef(kEV + d), v, se));
+        sp = fmad(coef(kPP + d), xnb(t, 1), fmad(coef(kPV + d), v, sp));
+        sv = fmad(coef(kVV + d), v, sv);
     }
+}
+// Adds the centre block times the node's own values to the neighbour sums.
+template <class T, class Coef>
+inline __device__ void centre_add(Coef coef, T xe, T xp, T xv, T &se, T &sp, T &sv) {
+    se = fmad(coef(kEE + 1), xe, fmad(coef(kEV + 1), xv, se));
+    sp = fmad(coef(kPP + 1), xp, fmad(coef(kPV + 1), xv, sp));
+    sv = fmad(coef(kVV + 1), xv, fmad(coef(kVe), xe, fmad(coef(kVp), xp, sv)));
+}
+template <class T, class XNb>
+inline __device__ void nb_sum_of(const BOpT<T> &J, int64_t p, const bool (&has)[4], XNb xnb, T &se, T &sp, T &sv) {
+    nb_sum_gen<T>([&](int q) { return J.pl(q)[p]; }, has, xnb, se, sp, sv);
 }
 
 template <class T>
@@ -257,10 +287,10 @@ inline __device__ void nb_sum(const Geom &g, const BOpT<T> &J, const T *x, int64
     nb_sum_of(J, p, has, [&](int t, int c) { return x[nbp[t] + c * plane]; }, se, sp, sv);
 }
 
-// Bilinear prolongation (z-distance weights) of one coarse field c at fine
-// node (i, j) of an unknown row.
+// x plus the bilinear prolongation (z-distance weights) of one coarse field
+// c at fine node (i, j) of an unknown row.
 template <class T>
-inline __device__ T prolong_val(const Geom &gf, const Geom &gc, const T *c, int i, int j) {
+inline __device__ T prolong_add(T x, const Geom &gf, const Geom &gc, const T *c, int i, int j) {
     int I0 = i >> 1, I1 = (i + 1) >> 1;
     T v0, v1;
     if ((j & 1) == 0) {
@@ -269,10 +299,10 @@ inline __device__ T prolong_val(const Geom &gf, const Geom &gc, const T *c, int 
     } else {
         int J_ = j >> 1;
         T wl = gf.wl[J_], wu = T(1) - wl;
-        v0 = wl * c[at(gc, I0, J_)] + wu * c[at(gc, I0, J_ + 1)];
-        v1 = wl * c[at(gc, I1, J_)] + wu * c[at(gc, I1, J_ + 1)];
+        v0 = fmad(wl, c[at(gc, I0, J_)], wu * c[at(gc, I0, J_ + 1)]);
+        v1 = fmad(wl, c[at(gc, I1, J_)], wu * c[at(gc, I1, J_ + 1)]);
     }
-    return (i & 1) ? T(0.5) * (v0 + v1) : v0;
+    return (i & 1) ? fmad(T(0.5), v0 + v1, x) : x + v0;
 }
 
 template <class T>
@@ -281,9 +311,7 @@ inline __device__ void prolong3_node(const Geom &gf, T *xf, int64_t pf, const Ge
     int64_t p = at(gf, i, j);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        T v = xf[p + f * pf];
-        v += prolong_val(gf, gc, xc + f * pc, i, j);
-        xf[p + f * pf] = v;
+        xf[p + f * pf] = prolong_add(xf[p + f * pf], gf, gc, xc + f * pc, i, j);
     }
 }
 
@@ -291,6 +319,15 @@ inline __device__ void prolong3_node(const Geom &gf, T *xf, int64_t pf, const Ge
 template <class T>
 struct NodeRow {
     T ee[5], eV[5], pp[5], pV[5], VV[5], Ve, Vp, fe, fp, fv;
+    // centre-block factors that do not depend on the iterate: 1/ee, 1/pp,
+    // the couplings scaled by them, and 1 / (Schur complement of the
+    // potential), formed once per loaded row
+    T ie, ip, a, b, is;
+    // entry of Jacobian plane q (q a compile-time constant after unrolling)
+    __device__ T coef(int q) const {
+        return q < kEV ? ee[q] : q < kPP ? eV[q - kEV] : q < kPV ? pp[q - kPP] : q < kVV ? pV[q - kPV]
+               : q < kVe ? VV[q - kVV] : q == kVe ? Ve : Vp;
+    }
 };
 template <class T>
 inline __device__ void load_row(const BOpT<T> &J, const T *f, int64_t p, NodeRow<T> &R) {
@@ -308,28 +345,26 @@ inline __device__ void load_row(const BOpT<T> &J, const T *f, int64_t p, NodeRow
     R.fp = f[p + J.plane];
     R.fv = f[p + 2 * J.plane];
 }
+template <class T>
+inline __device__ void factor_row(NodeRow<T> &R) {
+    R.ie = T(1) / R.ee[1];
+    R.ip = T(1) / R.pp[1];
+    R.a = R.Ve * R.ie;
+    R.b = R.Vp * R.ip;
+    R.is = T(1) / fmad(-R.b, R.pV[1], fmad(-R.a, R.eV[1], R.VV[1]));
+}
 // Collective Gauss-Seidel update of one node: the neighbour sums of the
 // three rows, then the 3x3 centre block [[ee,0,eV],[0,pp,pV],[Ve,Vp,VV]]
-// solved exactly for (n_e, n_p, V), reduced to the potential first.
+// solved exactly for (n_e, n_p, V), reduced to the potential first, with
+// the factors of factor_row.
 template <class T, class XNb>
 inline __device__ void solve_row(const NodeRow<T> &R, const bool (&has)[4], XNb xnb, T &oe, T &op, T &ov) {
-    const int dirs[4] = {0, 2, 3, 4};
-    T se = T(0), sp = T(0), sv = T(0);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (!has[t]) continue;
-        int d = dirs[t];
-        T v = xnb(t, 2);
-        se += R.ee[d] * xnb(t, 0) + R.eV[d] * v;
-        sp += R.pp[d] * xnb(t, 1) + R.pV[d] * v;
-        sv += R.VV[d] * v;
-    }
+    T se, sp, sv;
+    nb_sum_gen<T>([&](int q) { return R.coef(q); }, has, xnb, se, sp, sv);
     T re = R.fe - se, rp = R.fp - sp, rv = R.fv - sv;
-    const T ie = T(1) / R.ee[1], ip = T(1) / R.pp[1];
-    T a = R.Ve * ie, b = R.Vp * ip;
-    ov = (rv - a * re - b * rp) / (R.VV[1] - a * R.eV[1] - b * R.pV[1]);
-    oe = (re - R.eV[1] * ov) * ie;
-    op = (rp - R.pV[1] * ov) * ip;
+    ov = fmad(-R.b, rp, fmad(-R.a, re, rv)) * R.is;
+    oe = fmad(-R.eV[1], ov, re) * R.ie;
+    op = fmad(-R.pV[1], ov, rp) * R.ip;
 }
 
 template <class T>
@@ -337,6 +372,7 @@ inline __device__ void block_gs_node(const Geom &g, const BOpT<T> &J, const T *f
     const int64_t p = at(g, i, j), plane = J.plane;
     NodeRow<T> R;
     load_row(J, f, p, R);
+    factor_row(R);
     const int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
     const bool has[4] = {i > 0, i < g.nr, true, true};
     T oe, op, ov;
@@ -430,19 +466,6 @@ __global__ __launch_bounds__(kSW *(SH + SweepTile<SH>::kSR)) void k_block_rb_swe
     const int64_t plane = J.plane;
     const int ti = threadIdx.y, tj = threadIdx.x;
     const int tid = ti * kSW + tj;
-    // phase 0: input over the window rows i0-2 .. i0+kSH+1, columns j0-2 .. j0+kSW+1
-    for (int t = tid; t < (kSH + 4) * W2; t += kSW * (kSH + kSR)) {
-        const int ii = i0 - 2 + t / W2, jj = j0 - 2 + t % W2;
-        if (ii < 0 || ii > g.nr || jj < 0 || jj > g.nz) continue;
-        const int64_t q = at(g, ii, jj);
-        const bool un = jj >= 1 && jj < g.nz;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T v = zin ? T(0) : xin[q + c * plane];
-            if (xc && un) v += prolong_val(g, gc, xc + c * pc, ii, jj);
-            lin[c][t] = v;
-        }
-    }
     // the node this thread updates in phase 1 or 2
     int ni, nj;
     if (ti < kSH) {
@@ -472,7 +495,23 @@ __global__ __launch_bounds__(kSW *(SH + SweepTile<SH>::kSR)) void k_block_rb_swe
     const bool tile = ti < kSH;
     const int64_t p = at(g, ni, nj);
     NodeRow<T> R;
+    // the Jacobian row loads are issued before the window's, so that both
+    // latencies overlap
     if (valid && (tile || red)) load_row(J, f, p, R);
+    // phase 0: input over the window rows i0-2 .. i0+kSH+1, columns j0-2 .. j0+kSW+1
+    for (int t = tid; t < (kSH + 4) * W2; t += kSW * (kSH + kSR)) {
+        const int ii = i0 - 2 + t / W2, jj = j0 - 2 + t % W2;
+        if (ii < 0 || ii > g.nr || jj < 0 || jj > g.nz) continue;
+        const int64_t q = at(g, ii, jj);
+        const bool un = jj >= 1 && jj < g.nz;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T v = zin ? T(0) : xin[q + c * plane];
+            if (xc && un) v = prolong_add(v, g, gc, xc + c * pc, ii, jj);
+            lin[c][t] = v;
+        }
+    }
+    if (valid && (tile || red)) factor_row(R);
     __syncthreads();
     auto in_at = [&](int ii, int jj, int c) { return lin[c][(ii - i0 + 2) * W2 + (jj - j0 + 2)]; };
     const bool has[4] = {ni > 0, ni < g.nr, true, true};
@@ -514,9 +553,7 @@ inline __device__ void block_apply_node(const Geom &g, const BOpT<T> &J, const T
     const int64_t plane = J.plane;
     nb_sum(g, J, x, plane, i, p, se, sp, sv);
     T xe = x[p], xp = x[p + plane], xv = x[p + 2 * plane];
-    se += J.pl(kEE + 1)[p] * xe + J.pl(kEV + 1)[p] * xv;
-    sp += J.pl(kPP + 1)[p] * xp + J.pl(kPV + 1)[p] * xv;
-    sv += J.pl(kVV + 1)[p] * xv + J.pl(kVe)[p] * xe + J.pl(kVp)[p] * xp;
+    centre_add<T>([&](int q) { return J.pl(q)[p]; }, xe, xp, xv, se, sp, sv);
 }
 
 template <class T>
@@ -542,29 +579,36 @@ inline __device__ void block_residual_node(const Geom &g, const BOpT<T> &J, cons
 
 // Two full collective red-black sweeps in one launch, xin -> xout (distinct
 // buffers, electrode rows zero), input as for k_block_rb_sweep.  Each
-// workgroup owns a kSW x SH tile T and keeps the window T+4 (every node
-// within 4 rows / columns of T) in LDS, updated in place:
-//   A: colour 0 on T+3 (first sweep), B: colour 1 on T+2,
-//   C: colour 0 on T+1 (second sweep), D: colour 1 on T,
+// workgroup owns a kSW x SH tile T and keeps the window T+(4+E) (every node
+// within 4+E rows / columns of T) in LDS, updated in place:
+//   A: colour 0 on T+(3+E) (first sweep), B: colour 1 on T+(2+E),
+//   C: colour 0 on T+(1+E) (second sweep), D: colour 1 on T+E,
 // so each phase reads only values the previous phases made current.  Each
-// thread holds the Jacobian rows of one colour-0 node of T+3 and one
-// colour-1 node of T+2 in registers; the arithmetic of every update is
+// thread holds the Jacobian rows of one colour-0 node of T+(3+E) and one
+// colour-1 node of T+(2+E) in registers; the arithmetic of every update is
 // that of the per-node block solve, so the result equals four half-sweeps
 // bit for bit, with one launch and one pass over the Jacobian.
-template <int SH>
+// With kRestrict (E = 2: the sweeps end current on T+2) the launch also
+// forms the residual f - B x on T+1 from the rows in registers and restricts
+// it to the coarse nodes (I, J) with (2I, 2J) in T (fc, coarse geometry gc,
+// plane pc): bitwise what k_block_residual_restrict computes from xout.
+// (Without it, gc / xc / pc are the optional prolongation-on-read input.)
+template <int SH, bool kRestrict = false>
 struct Sweep2Tile {
-    static constexpr int kR3 = SH + 6, kC3 = (kSW + 6) / 2;  // colour-0 nodes of T+3: rows x per row
-    static constexpr int kR2 = SH + 4, kC2 = (kSW + 4) / 2;  // colour-1 nodes of T+2
+    static constexpr int kE = kRestrict ? 2 : 0;
+    static constexpr int kR3 = SH + 2 * (3 + kE), kC3 = (kSW + 2 * (3 + kE)) / 2;  // colour-0 nodes of T+3+E
+    static constexpr int kR2 = SH + 2 * (2 + kE), kC2 = (kSW + 2 * (2 + kE)) / 2;  // colour-1 nodes of T+2+E
     static constexpr int kN = (kR3 * kC3 > kR2 * kC2) ? kR3 * kC3 : kR2 * kC2;
     static constexpr int kThreads = (kN + 63) / 64 * 64;
-    static constexpr int kWR = SH + 8, kWC = kSW + 8;  // window T+4
+    static constexpr int kWR = SH + 2 * (4 + kE), kWC = kSW + 2 * (4 + kE);  // window T+4+E
+    static constexpr int kRR = kRestrict ? SH + 2 : 1, kRC = kRestrict ? kSW + 2 : 1;  // residual on T+1
 };
-template <class T, int SH>
-__global__ __launch_bounds__(Sweep2Tile<SH>::kThreads) void k_block_rb_sweep2(
+template <class T, int SH, bool kRestrict>
+__global__ __launch_bounds__((Sweep2Tile<SH, kRestrict>::kThreads)) void k_block_rb_sweep2(
     Geom g, BOpT<T> J, const T *__restrict__ f, const T *__restrict__ xin, T *__restrict__ xout, int zin, Geom gc,
-    const T *__restrict__ xc, int64_t pc, Batch bt) {
-    using Tl = Sweep2Tile<SH>;
-    constexpr int kWR = Tl::kWR, kWC = Tl::kWC;
+    const T *__restrict__ xc, int64_t pc, T *__restrict__ fc, Batch bt) {
+    using Tl = Sweep2Tile<SH, kRestrict>;
+    constexpr int kWR = Tl::kWR, kWC = Tl::kWC, kE = Tl::kE, kM = 4 + kE;
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     g = geom_off(g, bo_);
@@ -572,40 +616,28 @@ __global__ __launch_bounds__(Sweep2Tile<SH>::kThreads) void k_block_rb_sweep2(
     f = boff(f, bo_);
     xin = boff(xin, bo_);
     xout = boff(xout, bo_);
-    if (xc) {
-        gc = geom_off(gc, bo_);
-        xc = boff(xc, bo_);
-    }
+    if (xc || kRestrict) gc = geom_off(gc, bo_);
+    if (xc) xc = boff(xc, bo_);
+    if (kRestrict) fc = boff(fc, bo_);
 
     __shared__ T w[3][kWR * kWC];
+    __shared__ T lr[3][Tl::kRR * Tl::kRC];
     int tx, ty;
     sweep_tile(g, tx, ty);
     const int i0 = ty * SH, j0 = tx * kSW;
     const int64_t plane = J.plane;
     const int tid = threadIdx.x;
-    for (int t = tid; t < kWR * kWC; t += Tl::kThreads) {
-        const int ii = i0 - 4 + t / kWC, jj = j0 - 4 + t % kWC;
-        if (ii < 0 || ii > g.nr || jj < 0 || jj > g.nz) continue;
-        const int64_t q = at(g, ii, jj);
-        const bool un = jj >= 1 && jj < g.nz;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T v = zin ? T(0) : xin[q + c * plane];
-            if (xc && un) v += prolong_val(g, gc, xc + c * pc, ii, jj);
-            w[c][t] = v;
-        }
-    }
-    // this thread's colour-0 node of T+3 (a) and colour-1 node of T+2 (b)
+    // this thread's colour-0 node of T+3+E (a) and colour-1 node of T+2+E (b)
     int ai = -1, aj = 0, bi = -1, bj = 0;
     if (tid < Tl::kR3 * Tl::kC3) {
         const int r = tid / Tl::kC3, k = tid % Tl::kC3;
-        ai = i0 - 3 + r;
-        aj = j0 - 3 + 2 * k + ((i0 + j0 + r) & 1);
+        ai = i0 - (3 + kE) + r;
+        aj = j0 - (3 + kE) + 2 * k + ((i0 + j0 + r) & 1);
     }
     if (tid < Tl::kR2 * Tl::kC2) {
         const int r = tid / Tl::kC2, k = tid % Tl::kC2;
-        bi = i0 - 2 + r;
-        bj = j0 - 2 + 2 * k + ((i0 + j0 + r + 1) & 1);
+        bi = i0 - (2 + kE) + r;
+        bj = j0 - (2 + kE) + 2 * k + ((i0 + j0 + r + 1) & 1);
     }
     const bool va = ai >= 0 && ai <= g.nr && aj >= 1 && aj < g.nz;
     const bool vb = bi >= 0 && bi <= g.nr && bj >= 1 && bj < g.nz;
@@ -613,8 +645,25 @@ __global__ __launch_bounds__(Sweep2Tile<SH>::kThreads) void k_block_rb_sweep2(
     NodeRow<T> Ra, Rb;
     if (va) load_row(J, f, pa, Ra);
     if (vb) load_row(J, f, pb, Rb);
+    // (row loads first: the window loads below overlap their latency)
+    for (int t = tid; t < kWR * kWC; t += Tl::kThreads) {
+        const int ii = i0 - kM + t / kWC, jj = j0 - kM + t % kWC;
+        if (ii < 0 || ii > g.nr || jj < 0 || jj > g.nz) continue;
+        const int64_t q = at(g, ii, jj);
+        const bool un = jj >= 1 && jj < g.nz;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T v = zin ? T(0) : xin[q + c * plane];
+            if (xc && un) v = prolong_add(v, g, gc, xc + c * pc, ii, jj);
+            w[c][t] = v;
+        }
+    }
+    if constexpr (kRestrict)
+        for (int t = tid; t < Tl::kRR * Tl::kRC; t += Tl::kThreads) lr[0][t] = lr[1][t] = lr[2][t] = T(0);
+    if (va) factor_row(Ra);
+    if (vb) factor_row(Rb);
     const int dni[4] = {-1, 1, 0, 0}, dnj[4] = {0, 0, -1, 1};
-    auto widx = [&](int ii, int jj) { return (ii - i0 + 4) * kWC + (jj - j0 + 4); };
+    auto widx = [&](int ii, int jj) { return (ii - i0 + kM) * kWC + (jj - j0 + kM); };
     auto update = [&](const NodeRow<T> &R, int ni, int nj, bool write) {
         const bool has[4] = {ni > 0, ni < g.nr, true, true};
         T oe, op, ov;
@@ -638,9 +687,53 @@ __global__ __launch_bounds__(Sweep2Tile<SH>::kThreads) void k_block_rb_sweep2(
     __syncthreads();
     if (vb) update(Rb, bi, bj, false);  // B
     __syncthreads();
-    if (va && in_ring(ai, aj, 1)) update(Ra, ai, aj, in_ring(ai, aj, 0));  // C
+    if (va && in_ring(ai, aj, 1 + kE)) update(Ra, ai, aj, in_ring(ai, aj, 0));  // C
     __syncthreads();
-    if (vb && in_ring(bi, bj, 0)) update(Rb, bi, bj, true);  // D
+    if (vb && in_ring(bi, bj, kE)) update(Rb, bi, bj, in_ring(bi, bj, 0));  // D
+    if constexpr (kRestrict) {
+        __syncthreads();
+        // residual on T+1 (x current on T+2), the expressions of block_apply_node
+        auto resid = [&](const NodeRow<T> &R, int ni, int nj) {
+            const bool has[4] = {ni > 0, ni < g.nr, true, true};
+            T se, sp, sv;
+            nb_sum_gen<T>([&](int q) { return R.coef(q); }, has,
+                          [&](int t, int c) { return w[c][widx(ni + dni[t], nj + dnj[t])]; }, se, sp, sv);
+            const int l = widx(ni, nj);
+            centre_add<T>([&](int q) { return R.coef(q); }, w[0][l], w[1][l], w[2][l], se, sp, sv);
+            const int m = (ni - i0 + 1) * Tl::kRC + (nj - j0 + 1);
+            lr[0][m] = R.fe - se;
+            lr[1][m] = R.fp - sp;
+            lr[2][m] = R.fv - sv;
+        };
+        if (va && in_ring(ai, aj, 1)) resid(Ra, ai, aj);
+        if (vb && in_ring(bi, bj, 1)) resid(Rb, bi, bj);
+        __syncthreads();
+        // full weighting onto the coarse nodes of T, as k_block_residual_restrict
+        constexpr int kCI = SH / 2, kCJ = kSW / 2;
+        for (int t = tid; t < kCI * kCJ; t += Tl::kThreads) {
+            const int I = i0 / 2 + t / kCJ, J_ = j0 / 2 + t % kCJ;
+            if (I > gc.nr || J_ > gc.nz) continue;
+            const int64_t q = at(gc, I, J_);
+            if (J_ == 0 || J_ == gc.nz) {
+                fc[q] = fc[q + pc] = fc[q + 2 * pc] = T(0);
+                continue;
+            }
+            T wdn = T(1) - g.wl[J_ - 1], wup = g.wl[J_];
+            T acc[3] = {0, 0, 0};
+            for (int di = -1; di <= 1; ++di) {
+                int i = 2 * I + di;
+                if (i < 0 || i > g.nr) continue;
+                T wi = (di == 0) ? T(1) : T(0.5);
+                const int l = (i - i0 + 1) * Tl::kRC + (2 * J_ - j0 + 1);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    acc[c] = restrict_add(acc[c], wi, wdn, wup, lr[c][l - 1], lr[c][l], lr[c][l + 1]);
+            }
+            fc[q] = acc[0];
+            fc[q + pc] = acc[1];
+            fc[q + 2 * pc] = acc[2];
+        }
+    }
 }
 
 template <class T>
@@ -680,7 +773,7 @@ inline __device__ void restrict3_node(const Geom &gf, const T *rf, int64_t pf, c
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             const T *r = rf + f * pf;
-            acc[f] += wi * (wdn * r[p - 1] + r[p] + wup * r[p + 1]);
+            acc[f] = restrict_add(acc[f], wi, wdn, wup, r[p - 1], r[p], r[p + 1]);
         }
     }
     fc[q] = acc[0];
@@ -760,7 +853,7 @@ __global__ __launch_bounds__(1024) void k_block_residual_restrict(Geom gf, BOpT<
         T wi = (di == 0) ? T(1) : T(0.5);
         const int l = (i - fi0) * FW + (2 * J_ - fj0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += wi * (wdn * lr[c][l - 1] + lr[c][l] + wup * lr[c][l + 1]);
+        for (int c = 0; c < 3; ++c) acc[c] = restrict_add(acc[c], wi, wdn, wup, lr[c][l - 1], lr[c][l], lr[c][l + 1]);
     }
     fc[q] = acc[0];
     fc[q + pc] = acc[1];
@@ -1059,48 +1152,48 @@ struct SubMem<T, true> {
     // right-hand side into LDS, and zero corrections on every level.  Segment
     // q < n is level q's kStaged matrix planes (a level's right-hand-side
     // planes are written by the restriction before they are read, and the
-    // top level uses f0), segment n the 3 planes of f0; value
-    // e of a segment is row R = e / (nz + 1) (R = plane * (nr + 1) + i, which
-    // starts R * pitch values into the array since planes are (nr + 1) *
-    // pitch apart), column e % (nz + 1).  One segment is at most kB values
-    // per thread (the pool bound); the next segment's loads are issued before
-    // the current segment's stores, so the latencies overlap.
+    // top level uses f0), segment n the 3 planes of f0; value e of a segment
+    // is row R = e / (nz + 1) (R = plane * (nr + 1) + i, which starts R *
+    // pitch values into the array since planes are (nr + 1) * pitch apart),
+    // column e % (nz + 1).  Each segment gets its own run of ceil(size / kB)
+    // consecutive threads (at most 969 for a full pool), each of which loads
+    // at most kB values of it, so every load of the staging is issued before
+    // the first store waits.
     __device__ void stage_all() const {
         const int n = F.n;
-        constexpr int kB = (kSubPool + 1023) / 1024;
-        auto load = [&](int q, T(&v)[kB]) {
+        constexpr int kB = 16;
+        static_assert(kSubPool / kB + kMaxFused + 1 <= 1024, "one run of threads per segment");
+        int q = -1, first = 0, cnt = 0;
+        for (int t = 0, start = 0; t <= n; ++t) {
+            const int c = ((t < n ? kStaged : 3) * nodes(t < n ? t : 0) + kB - 1) / kB;
+            if (q < 0 && (int)threadIdx.x < start + c) {
+                q = t;
+                first = start;
+                cnt = c;
+            }
+            start += c;
+        }
+        if (q >= 0) {
             const int qq = q < n ? q : 0;
             const int w = F.g[qq].nz + 1, size = (q < n ? kStaged : 3) * (F.g[qq].nr + 1) * w;
             const uint32_t mg = F.wmagic[qq];
             const int64_t pitch = F.g[qq].pitch;
             const T *src = boff(q < n ? F.J[q] : F.f0, bo);
+            T *dst = pool + (q < n ? off(q) : off(n));
+            const int lt = threadIdx.x - first;
+            T v[kB];
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
-                const int e = threadIdx.x + u * 1024;
+                const int e = lt + u * cnt;
                 if (e < size) {
                     const int R = (int)__umulhi((uint32_t)e, mg);
                     v[u] = src[(int64_t)R * pitch + (e - R * w)];
                 }
             }
-        };
-        auto store = [&](int q, const T(&v)[kB]) {
-            const int qq = q < n ? q : 0;
-            const int size = (q < n ? kStaged : 3) * nodes(qq);
-            T *dst = pool + (q < n ? off(q) : off(n));
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
-                const int e = threadIdx.x + u * 1024;
+                const int e = lt + u * cnt;
                 if (e < size) dst[e] = v[u];
-            }
-        };
-        T va[kB], vb[kB];
-        load(0, va);
-        for (int q = 0; q <= n; q += 2) {
-            if (q + 1 <= n) load(q + 1, vb);
-            store(q, va);
-            if (q + 1 <= n) {
-                if (q + 2 <= n) load(q + 2, va);
-                store(q + 1, vb);
             }
         }
         for (int q = 0; q < n; ++q) {
@@ -1578,10 +1671,28 @@ template <class T>
 void launch_block_rb_sweep2(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
                             const Geom *gc, const T *xc, int64_t pc, hipStream_t s, const Batch &bt) {
     const Geom &gcc = gc ? *gc : g;
-    using Tl = Sweep2Tile<8>;
+    if (g.sh2 == 4) {
+        dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + 4 - 1) / 4);
+        k_block_rb_sweep2<T, 4, false><<<gz(grid, bt), Sweep2Tile<4>::kThreads, 0, s>>>(
+            g, J, f, xin, xout, zin ? 1 : 0, gcc, xc, pc, nullptr, bt);
+        return;
+    }
     dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + 8 - 1) / 8);
-    k_block_rb_sweep2<T, 8><<<gz(grid, bt), Tl::kThreads, 0, s>>>(g, J, f, xin, xout, zin ? 1 : 0, gcc, xc, pc,
-                                                                   bt);
+    k_block_rb_sweep2<T, 8, false><<<gz(grid, bt), Sweep2Tile<8>::kThreads, 0, s>>>(g, J, f, xin, xout, zin ? 1 : 0,
+                                                                                  gcc, xc, pc, nullptr, bt);
+}
+template <class T>
+void launch_block_rb_sweep2_restrict(const Geom &g, const BOpT<T> &J, const T *f, const T *xin, T *xout, bool zin,
+                                     const Geom &gc, T *fc, int64_t pc, hipStream_t s, const Batch &bt) {
+    if (g.sh2 == 4) {
+        dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + 4 - 1) / 4);
+        k_block_rb_sweep2<T, 4, true><<<gz(grid, bt), Sweep2Tile<4, true>::kThreads, 0, s>>>(
+            g, J, f, xin, xout, zin ? 1 : 0, gc, nullptr, pc, fc, bt);
+        return;
+    }
+    dim3 grid((g.nz + 1 + kSW - 1) / kSW, (g.nr + 1 + 8 - 1) / 8);
+    k_block_rb_sweep2<T, 8, true><<<gz(grid, bt), Sweep2Tile<8, true>::kThreads, 0, s>>>(
+        g, J, f, xin, xout, zin ? 1 : 0, gc, nullptr, pc, fc, bt);
 }
 template <class T>
 void launch_block_residual(const Geom &g, const BOpT<T> &J, const T *f, const T *x, T *r, bool apply,
@@ -1803,6 +1914,9 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
                                            const Geom *, const T *, int64_t, hipStream_t, const Batch &);     \
     template void launch_block_rb_sweep2<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,  \
                                             const Geom *, const T *, int64_t, hipStream_t, const Batch &);    \
+    template void launch_block_rb_sweep2_restrict<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *,  \
+                                                     bool, const Geom &, T *, int64_t, hipStream_t,             \
+                                                     const Batch &);                                            \
     template void launch_block_residual<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
                                            hipStream_t, const Batch &);                                      \
     template void launch_restrict3<T>(const Geom &, const T *, int64_t, const Geom &, T *, int64_t,          \

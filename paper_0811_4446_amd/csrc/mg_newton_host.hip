@@ -143,12 +143,19 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         T *mid = (n2 & 1) ? x2 : x;  // iterate between pre- and post-smoothing
         auto other = [&](T *b) { return b == x ? x2 : x; };
         T *cur = (n1 & 1) ? mid : other(mid);
-        launch_block_rb_sweep2<T>(L.g, J, f, nullptr, cur, true, nullptr, nullptr, 0, s, c->bt);
-        for (int k = 1; k < n1; ++k) {
-            launch_block_rb_sweep2<T>(L.g, J, f, cur, other(cur), false, nullptr, nullptr, 0, s, c->bt);
-            cur = other(cur);
+        // the last pre-smoothing launch also forms the restricted residual
+        // (unless switched off: then its own launch)
+        const bool fuse_r = c->nw.sweep2_restrict;
+        for (int k = 0; k < n1; ++k) {
+            const T *in = k == 0 ? nullptr : cur;
+            T *out = k == 0 ? cur : other(cur);
+            if (k == n1 - 1 && fuse_r)
+                launch_block_rb_sweep2_restrict<T>(L.g, J, f, in, out, k == 0, C.g, fc, plane_of(C), s, c->bt);
+            else
+                launch_block_rb_sweep2<T>(L.g, J, f, in, out, k == 0, nullptr, nullptr, 0, s, c->bt);
+            cur = out;
         }
-        launch_residual_restrict<T>(L.g, J, f, cur, C.g, fc, plane_of(C), s, c->bt);
+        if (!fuse_r) launch_residual_restrict<T>(L.g, J, f, cur, C.g, fc, plane_of(C), s, c->bt);
         block_vcycle<T>(c, l + 1, fc, xc, s);
         for (int k = 0; k < n2; ++k) {
             const bool first = k == 0;
@@ -426,23 +433,19 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
     double *ybuf = c->pinned + 2 * kSlot, *sbuf = c->pinned + 2 * kSlot + kMaxKrylov + 8;
     Arnoldi A;
     launch_fill(W.delta, vs, 0.0, s);
-    // r0 = b
+    // r0 = b; its norm goes to pinned memory and is read with the first
+    // Arnoldi step's readback, so no host round trip precedes that step (a
+    // zero or non-finite norm is acted on then)
     launch_cgs_pass(g, const_cast<double *>(b), b, vs, 1, p0, cw, nullptr, true, W.partials, dev, s);
     HIP_OK(hipMemcpyAsync(sbuf, dev, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    double beta0 = sqrt(sbuf[0]);
+    launch_scale_by_norm(g, b, W.V, p0, dev, s);
     *its = 0;
     *relres = 0.0;
-    if (!(beta0 > 0)) {
-        if (!isfinite(beta0)) return fail(MG_ENONFINITE, "Newton residual is not finite");
-        return MG_OK;
-    }
-    launch_scale_by_norm(g, b, W.V, p0, dev, s);
-    double beta = beta0;
+    double beta0 = -1.0, beta = -1.0;
     int total = 0;
     const int prev = W.last_its;
     while (true) {
-        A.start(beta);
+        if (beta0 >= 0) A.start(beta);
         int k = 0;
         double est = beta, est_prev = beta;
         bool next_launched = false;
@@ -465,6 +468,17 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
                 next_launched = false;
             }
             HIP_OK(hipEventSynchronize(W.ev[k & 1]));
+            if (beta0 < 0) {
+                // first step of the solve: the norm of r0 is in sbuf by now
+                beta0 = beta = sqrt(sbuf[0]);
+                if (!(beta0 > 0)) {
+                    HIP_OK(hipStreamSynchronize(s));  // drain a speculative step
+                    if (!isfinite(beta0)) return fail(MG_ENONFINITE, "Newton residual is not finite");
+                    return MG_OK;  // b = 0: delta = 0
+                }
+                A.start(beta0);
+                est = est_prev = beta0;
+            }
             const double *host = c->pinned + kSlot * (k & 1);
             for (int i = 0; i <= k; ++i) A.H[i][k] = host[i] + host[m + 1 + i];
             A.H[k + 1][k] = sqrt(host[2 * m + 2]);
@@ -488,17 +502,24 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
         for (int i = 0; i < k; ++i) ybuf[i] = y[i];
         HIP_OK(hipMemcpyAsync(dev + 3 * m + 8, ybuf, k * sizeof(double), hipMemcpyHostToDevice, s));
         launch_axpy_multi(g, W.delta, W.Z, vs, k, p0, dev + 3 * m + 8, 1.0, s);
+        *its = total;
+        W.last_its = total;
+        if (est <= rtol * beta0) {
+            // converged by the recurrence's residual (that of the iterate in
+            // exact arithmetic): no true-residual round trip; the caller's
+            // next synchronisation covers the update
+            *relres = est / beta0;
+            return MG_OK;
+        }
         // true residual for the restart / final check
         launch_block_residual<double>(g, J, b, W.delta, W.w, false, s);
         launch_cgs_pass(g, W.w, W.w, vs, 1, p0, cw, nullptr, true, W.partials, dev, s);
         HIP_OK(hipMemcpyAsync(sbuf, dev, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         beta = sqrt(sbuf[0]);
-        *its = total;
-        W.last_its = total;
         *relres = beta / beta0;
         if (!isfinite(beta)) return fail(MG_ENONFINITE, "FGMRES residual is not finite");
-        if (beta <= rtol * beta0 * 1.0000001 || est <= rtol * beta0) return MG_OK;
+        if (beta <= rtol * beta0 * 1.0000001) return MG_OK;
         if (total >= maxit)
             return fail(MG_ENOCONV, "FGMRES: relative residual %.3e after %d iterations", beta / beta0, total);
         launch_scale_by_norm(g, W.w, W.V, p0, dev, s);
@@ -521,9 +542,14 @@ void restore_state(mg_ctx *c, const double *src, mg_state *st) {
     launch_copy_field(L0.g, src + 2 * p0, st->np, c->stream, c->bt);
 }
 
+void launch_step_change(mg_ctx *c, const mg_state *st, double *out);
+
 // Newton iterations of one BE step; the step's starting state is in W.snap.
+// With `change`, every iteration also forms the step's relative density
+// change against W.snap (launch_step_change) and reads it back with the
+// Newton reduction; *change is set when the step converges.
 int newton_iterate(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, const mg_schedule *sc,
-                   mg_report *rep, bool *converged) {
+                   mg_report *rep, bool *converged, double *change = nullptr) {
     hipStream_t s = c->stream;
     const Level &L0 = c->lev[0];
     int64_t p0 = plane_of(L0);
@@ -543,7 +569,8 @@ int newton_iterate(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, con
         if (e == MG_ENOCONV || e == MG_ENONFINITE) return MG_OK;  // step fails: caller rejects
         if (e) return e;
         launch_newton_update(L0.g, st->V, st->ne, st->np, c->nw.delta, p0, c->nw.partials, c->scal, s);
-        HIP_OK(hipMemcpyAsync(c->pinned, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (change) launch_step_change(c, st, c->scal + 8);
+        HIP_OK(hipMemcpyAsync(c->pinned, c->scal, (change ? 12 : 8) * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         const double *o = c->pinned;
         double re = o[0] / fmax(o[1], 1e-300), rp = o[2] / fmax(o[3], 1e-300), rv = o[4] / fmax(o[5], 1e-300);
@@ -555,28 +582,24 @@ int newton_iterate(mg_ctx *c, const mg_physics *ph, mg_state *st, double dt, con
             // the converged densities must be non-negative to rounding
             double cnt = (double)(L0.g.nr + 1) * (L0.g.nz - 1);
             *converged = o[6] >= -1e-10 * o[1] / cnt && o[7] >= -1e-10 * o[3] / cnt;
+            if (change) *change = fmax(sqrt(o[8] / fmax(o[9], 1e-300)), sqrt(o[10] / fmax(o[11], 1e-300)));
             return MG_OK;
         }
     }
     return MG_OK;
 }
 
-// Relative change max_species ||n - n^k||_2 / ||n||_2 against the snapshot.
-int step_change(mg_ctx *c, const mg_state *st, double *change, double *minn) {
+// ||n - n^k||_2^2 and ||n||_2^2 of both species against the snapshot, to
+// out[0..3] (device).
+void launch_step_change(mg_ctx *c, const mg_state *st, double *out) {
     const Level &L0 = c->lev[0];
     int64_t p0 = plane_of(L0);
     hipStream_t s = c->stream;
     int nb = 0;
     launch_diff_norms(L0.g, st->ne, c->nw.snap + p0, c->partials, &nb, s);
-    launch_sum_partials(c->partials, nb, 2, c->scal, s);
+    launch_sum_partials(c->partials, nb, 2, out, s);
     launch_diff_norms(L0.g, st->np, c->nw.snap + 2 * p0, c->partials, &nb, s);
-    launch_sum_partials(c->partials, nb, 2, c->scal + 2, s);
-    HIP_OK(hipMemcpyAsync(c->pinned, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    const double *o = c->pinned;
-    *change = fmax(sqrt(o[0] / fmax(o[1], 1e-300)), sqrt(o[2] / fmax(o[3], 1e-300)));
-    (void)minn;
-    return MG_OK;
+    launch_sum_partials(c->partials, nb, 2, out + 2, s);
 }
 
 }  // namespace
@@ -664,7 +687,8 @@ int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_
     while (R->steps < sc->max_steps) {
         copy_state(c, st, c->nw.snap);
         bool ok = false;
-        int e = newton_iterate(c, ph, st, dt, sc, R, &ok);
+        double ch = 0;
+        int e = newton_iterate(c, ph, st, dt, sc, R, &ok, &ch);
         if (e) return e;
         if (!ok) {
             restore_state(c, c->nw.snap, st);
@@ -680,10 +704,7 @@ int newton_solve_steady(mg_ctx *c, const mg_physics *ph, mg_state *st, const mg_
         consecutive_rejects = 0;
         R->steps++;
         t += dt;
-        double ch = 0;
-        e = step_change(c, st, &ch, nullptr);
-        if (e) return e;
-        R->last_change = ch;
+        R->last_change = ch;  // relative density change of the step (Sec. 2 stop rule)
         if (!isfinite(ch)) {
             status = fail(MG_ENONFINITE, "density change is not finite");
             break;
@@ -878,10 +899,13 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     c->nw.smoother_only = getenv("MGF_SMOOTHER_ONLY") != nullptr;
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
+    if (getenv("MGF_NO_SWEEP_RESTRICT")) c->nw.sweep2_restrict = false;
     if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
     if (const char *e = getenv("MGF_CHAIN_MAX_BLOCKS")) c->nw.chain_max_blocks = atoi(e);
     if (const char *sr = getenv("MGF_SWEEP_ROWS"))
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(sr) == 16 ? 16 : 8;
+    if (const char *e = getenv("MGF_SWEEP2_ROWS"))
+        for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh2 = atoi(e) == 4 ? 4 : 8;
     c->ws_base = base;
     c->ws_bytes = wsb;
     int64_t stride = toff / nprob;
@@ -1208,8 +1232,14 @@ int time_block_smoother(mg_ctx *c, int reps, int mode, int level, double *avg_ms
     const Level &L0 = c->lev[level];
     BOp J = bop(c, level);
     double *x = c->nw.lev[level].x, *x2 = c->nw.lev[level].x2;
+    if (mode == 3 && level + 1 >= c->nlev) return fail(MG_EINVAL, "level %d has no coarser level", level);
     auto one = [&](int r) {
-        if (mode == 2)
+        if (mode == 3) {
+            const Level &C = c->lev[level + 1];
+            BOp Jc = bop(c, level + 1);
+            launch_block_rb_sweep2_restrict<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, false,
+                                                    C.g, Jc.pl(kFe), plane_of(C), c->stream);
+        } else if (mode == 2)
             launch_block_rb_sweep2<double>(L0.g, J, J.pl(kFe), (r & 1) ? x2 : x, (r & 1) ? x : x2, false, nullptr,
                                            nullptr, 0, c->stream);
         else if (mode == 1)

@@ -214,15 +214,23 @@ def test_fused_rb_sweep_matches_half_sweeps(N, monkeypatch):
     ph = dict(I.PHYS)
     cp = NW.Coupled(N, N, 1.0, z, ph)
     NW.steady(cp, V, ne, np_, S, S, max_steps=15)
-    # two: pairs of sweeps per launch on every launched level; mixed: only on
-    # levels of at most 5000 nodes (65^2 and 33^2), single sweeps above
+    # two: pairs of sweeps per launch on every launched level (the last
+    # pre-smoothing launch also restricting the residual); two_sep: the same
+    # with the restriction in its own launch; two_r4: 4-row two-sweep tiles;
+    # mixed: pairs only on levels of at most 5000 nodes (65^2 and 33^2),
+    # single sweeps above
+    big = str(10 ** 9)
     modes = {"half": {"MGF_HALF_SWEEPS": "1"}, "one": {"MGF_ONE_SWEEP": "1"},
-             "two": {"MGF_TWO_SWEEP_NODES": str(10 ** 9)}, "mixed": {"MGF_TWO_SWEEP_NODES": "5000"}}
+             "two": {"MGF_TWO_SWEEP_NODES": big},
+             "two_sep": {"MGF_TWO_SWEEP_NODES": big, "MGF_NO_SWEEP_RESTRICT": "1"},
+             "two_r4": {"MGF_TWO_SWEEP_NODES": big, "MGF_SWEEP2_ROWS": "4"},
+             "mixed": {"MGF_TWO_SWEEP_NODES": "5000"}}
+    envs = ("MGF_HALF_SWEEPS", "MGF_ONE_SWEEP", "MGF_TWO_SWEEP_NODES", "MGF_NO_SWEEP_RESTRICT", "MGF_SWEEP2_ROWS")
     for prec in (m.FP64, m.FP32_IR):
         for rows in (1, 2, 4, 16):
             results = {}
             for mode, env in modes.items():
-                for k in ("MGF_HALF_SWEEPS", "MGF_ONE_SWEEP", "MGF_TWO_SWEEP_NODES"):
+                for k in envs:
                     if k in env:
                         monkeypatch.setenv(k, env[k])
                     else:
@@ -233,12 +241,12 @@ def test_fused_rb_sweep_matches_half_sweeps(N, monkeypatch):
                 for dt in (1e-3, 1e-2, 0.1):
                     sol.step(m.Physics.of(ph), st, dt, sc)
                 results[mode] = [sol.download(x) for x in t[:3]]
-            for mode in ("one", "two", "mixed"):
+            for mode in modes:
                 for a, b in zip(results[mode], results["half"]):
                     assert np.array_equal(a, b), (prec, rows, mode)
         # the 16-row one-sweep tile gives the same bits as the default 8-row one
-        monkeypatch.delenv("MGF_HALF_SWEEPS", raising=False)
-        monkeypatch.delenv("MGF_TWO_SWEEP_NODES", raising=False)
+        for k in envs:
+            monkeypatch.delenv(k, raising=False)
         monkeypatch.setenv("MGF_ONE_SWEEP", "1")
         monkeypatch.setenv("MGF_SWEEP_ROWS", "16")
         sol, t, st = _gpu(N, V, ne, np_, S, krylov_m=20, prec=prec)
