@@ -428,6 +428,7 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
     if (getenv("MGF_NO_SWEEP_RESTRICT")) c->nw.sweep2_restrict = false;
+    if (const char *e = getenv("MGF_TWO_SWEEP_PRE_NODES")) c->nw.sweep2_pre_max_nodes = atoll(e);
     if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
     if (const char *e = getenv("MGF_CHAIN_MAX_BLOCKS")) c->nw.chain_max_blocks = atoi(e);
     if (const char *e = getenv("MGF_SWEEP_ROWS"))

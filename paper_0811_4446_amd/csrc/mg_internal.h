@@ -271,6 +271,9 @@ struct NewtonWork {
     // there (measured crossover between 129^2 and 257^2)
     int64_t sweep2_max_nodes = 129 * 129;
     bool sweep2_restrict = true;  // last pre-smoothing two-sweep launch also restricts the residual
+    // pre-smoothing alone in pairs (restricting) on levels of at most this
+    // many nodes (post-smoothing then one sweep per launch)
+    int64_t sweep2_pre_max_nodes = 257 * 257;
     // largest launch grid (workgroups) whose Gram-Schmidt passes form the
     // previous pass's projections themselves (single problems only)
     int chain_max_blocks = 512;

@@ -1346,6 +1346,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
 // The loads of a lane's partials are issued together (kChainLoads per pass:
 // one pass for the grids that chain their passes), then added in order.
 constexpr int kChainLoads = 8;
+constexpr int kCgsRegs = 8;  // basis vectors a Gram-Schmidt pass keeps in registers
 inline __device__ void reduce_projections(const double *__restrict__ part, int nblk, int nv, double *hs,
                                           double *out, double *out_host) {
     for (int v = threadIdx.y; v < nv; v += blockDim.y) {
@@ -1375,6 +1376,12 @@ inline __device__ void reduce_projections(const double *__restrict__ part, int n
     __syncthreads();
 }
 
+// NV > 0: at most NV basis vectors (nv <= NV); a node's basis values are
+// loaded once into registers, before the previous pass's projections are
+// summed (their loads overlap), and serve both the update and the dot
+// products.  NV = 0: any nv, the basis read as it is used.  Both forms do
+// the same arithmetic (explicit fused multiply-adds in the same order).
+template <int NV>
 __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ w, const double *__restrict__ basis,
                                                    int64_t vstride, int nv, int64_t plane, double3 cw,
                                                    const double *__restrict__ h_sub, int self_norm, BOp Jop,
@@ -1396,13 +1403,28 @@ __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ 
     const int i = blockIdx.y * blockDim.y + threadIdx.y;
     __shared__ double sh[kMaxTY][kMaxKrylov + 1];
     __shared__ double hs[kMaxKrylov + 1];
+    const bool ok = i <= g.nr && j >= 1 && j < g.nz;
+    const int64_t p = ok ? at(g, i, j) : 0;
+    // basis values of this node (register form)
+    double bv[NV > 0 ? NV : 1][3];
+    const bool upd = h_part || h_sub;
+    if constexpr (NV > 0) {
+        if (ok && (upd || !self_norm)) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) {
+                    const double *bb = basis + v * vstride + p;
+                    bv[v][0] = bb[0];
+                    bv[v][1] = bb[plane];
+                    bv[v][2] = bb[2 * plane];
+                }
+        }
+    }
     if (h_part) {
         // the previous pass's projections, formed here instead of by a launch of their own
         reduce_projections(boff(h_part, bo_), h_nblk, nv, hs, boff(h_out, bo_), h_host);
         h_sub = hs;
     }
-    const bool ok = i <= g.nr && j >= 1 && j < g.nz;
-    const int64_t p = ok ? at(g, i, j) : 0;
     double wf[3] = {0.0, 0.0, 0.0};
     if (z && i <= g.nr && (j == 0 || j == g.nz)) {
         const int64_t pb = at(g, i, j);
@@ -1414,35 +1436,51 @@ __global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ 
         w[p + plane] = wf[1];
         w[p + 2 * plane] = wf[2];
     } else if (ok) {
-        for (int f = 0; f < 3; ++f) {
-            const int64_t q = p + f * plane;
-            double acc = w[q];
-            if (h_sub) {
+        for (int f = 0; f < 3; ++f) wf[f] = w[p + f * plane];
+        if (h_sub) {
+            if constexpr (NV > 0) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v < nv && h_sub[v] != 0.0)
+                        for (int f = 0; f < 3; ++f) wf[f] = fmad(-h_sub[v], bv[v][f], wf[f]);
+            } else {
                 for (int v = 0; v < nv; ++v)
-                    if (h_sub[v] != 0.0) acc += -1.0 * h_sub[v] * basis[v * vstride + q];
-                w[q] = acc;
+                    if (h_sub[v] != 0.0)
+                        for (int f = 0; f < 3; ++f) wf[f] = fmad(-h_sub[v], basis[v * vstride + p + f * plane], wf[f]);
             }
-            wf[f] = acc;
+            for (int f = 0; f < 3; ++f) w[p + f * plane] = wf[f];
         }
     }
     const double iv = ok ? 1.0 / (g.wr[i] * g.dzc[j]) : 0.0;
     const double we = wf[0] * cw.x * cw.x * iv * iv;
     const double wp = wf[1] * cw.y * cw.y * iv * iv;
     const double wv = wf[2] * cw.z * cw.z * iv * iv;
-    const int nd = self_norm ? 1 : nv;
-    for (int v = 0; v < nd; ++v) {
-        double s = 0.0;
-        if (ok) {
-            if (self_norm) {
-                s = we * wf[0] + wp * wf[1] + wv * wf[2];
-            } else {
-                const double *b = basis + v * vstride;
-                s = we * b[p] + wp * b[p + plane] + wv * b[p + 2 * plane];
-            }
-        }
+    auto dot3 = [&](double b0, double b1, double b2) { return fmad(wv, b2, fmad(wp, b1, we * b0)); };
+    auto wave_sum = [](double s) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
+        return s;
+    };
+    const int nd = self_norm ? 1 : nv;
+    if (self_norm) {
+        const double s = wave_sum(ok ? dot3(wf[0], wf[1], wf[2]) : 0.0);
+        if (threadIdx.x == 0) sh[threadIdx.y][0] = s;
+    } else if constexpr (NV > 0) {
+        double sv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sv[v] = (ok && v < nv) ? dot3(bv[v][0], bv[v][1], bv[v][2]) : 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < nv) {
+                const double s = wave_sum(sv[v]);
+                if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
+            }
+    } else {
+        for (int v = 0; v < nv; ++v) {
+            const double *b = basis + v * vstride;
+            const double s = wave_sum(ok ? dot3(b[p], b[p + plane], b[p + 2 * plane]) : 0.0);
+            if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
+        }
     }
     __syncthreads();
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
@@ -1756,9 +1794,9 @@ void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstr
                      double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
                      const Batch &bt, const BOp *J, const double *z) {
     dim3 gr = grid2d(g);
-    k_cgs_pass<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, h_sub, self_norm ? 1 : 0,
-                                               J ? *J : BOp{nullptr, 0}, z, partials, nullptr, 0, nullptr,
-                                               nullptr, bt);
+    auto k = nv <= kCgsRegs ? k_cgs_pass<kCgsRegs> : k_cgs_pass<0>;
+    k<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, h_sub, self_norm ? 1 : 0,
+                                      J ? *J : BOp{nullptr, 0}, z, partials, nullptr, 0, nullptr, nullptr, bt);
     if (out) {
         int nd = self_norm ? 1 : nv;
         k_sum_cols<<<dim3(nd, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nd, out, bt);
@@ -1774,9 +1812,10 @@ void launch_cgs_pass_chained(const Geom &g, double *w, const double *basis, int6
                              double3 cw, bool self_norm, const double *h_part, double *h_out, double *h_host,
                              double *partials, hipStream_t s, const Batch &bt) {
     dim3 gr = grid2d(g);
-    k_cgs_pass<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, nullptr, self_norm ? 1 : 0,
-                                               BOp{nullptr, 0}, nullptr, partials, h_part, (int)(gr.x * gr.y),
-                                               h_out, h_host, bt);
+    auto k = nv <= kCgsRegs ? k_cgs_pass<kCgsRegs> : k_cgs_pass<0>;
+    k<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, nullptr, self_norm ? 1 : 0,
+                                      BOp{nullptr, 0}, nullptr, partials, h_part, (int)(gr.x * gr.y), h_out, h_host,
+                                      bt);
 }
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                        const double *h, double sign, hipStream_t s, const Batch &bt) {

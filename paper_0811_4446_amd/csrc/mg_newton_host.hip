@@ -71,6 +71,16 @@ bool sweep2_ok(const mg_ctx *c, int l) {
     return c->nw.rb_fused && (int64_t)(g.nr + 1) * (g.nz + 1) * c->bt.n <= c->nw.sweep2_max_nodes &&
            c->desc.nu1 >= 2 && c->desc.nu2 >= 2 && c->desc.nu1 % 2 == 0 && c->desc.nu2 % 2 == 0;
 }
+// Pre-smoothing alone in pairs (its last launch restricting the residual),
+// post-smoothing one sweep per launch: levels above the two-sweep bound up
+// to sweep2_pre_max_nodes, where the launch saved by the restriction pays
+// for the slower two-sweep launch.
+bool sweep2_pre_ok(const mg_ctx *c, int l) {
+    const Geom &g = c->lev[l].g;
+    return c->nw.rb_fused && c->nw.sweep2_restrict &&
+           (int64_t)(g.nr + 1) * (g.nz + 1) * c->bt.n <= c->nw.sweep2_pre_max_nodes && c->desc.nu1 >= 2 &&
+           c->desc.nu1 % 2 == 0 && c->desc.nu2 >= 2;
+}
 
 template <class T>
 void block_smooth(mg_ctx *c, int l, const BOpT<T> &J, const T *f, T *x, int nu, bool x_zero, const T *xc,
@@ -163,6 +173,26 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
                                       first ? xc : nullptr, plane_of(C), s, c->bt);
             cur = other(cur);
         }
+        return;
+    }
+    if (sweep2_pre_ok(c, l)) {
+        // pre-smoothing in pairs landing in x (the first from a zero guess,
+        // the last restricting the residual), post-smoothing one sweep per
+        // launch from x (the first adding the prolonged correction)
+        T *x2 = Prec<T>::x2(c, l);
+        const int n1 = c->desc.nu1 / 2;
+        T *cur = (n1 & 1) ? x : x2;
+        for (int k = 0; k < n1; ++k) {
+            const T *in = k == 0 ? nullptr : cur;
+            T *out = k == 0 ? cur : (cur == x ? x2 : x);
+            if (k == n1 - 1)
+                launch_block_rb_sweep2_restrict<T>(L.g, J, f, in, out, k == 0, C.g, fc, plane_of(C), s, c->bt);
+            else
+                launch_block_rb_sweep2<T>(L.g, J, f, in, out, k == 0, nullptr, nullptr, 0, s, c->bt);
+            cur = out;
+        }
+        block_vcycle<T>(c, l + 1, fc, xc, s);
+        block_smooth<T>(c, l, J, f, x, c->desc.nu2, false, xc, s);
         return;
     }
     // without a fused first sweep the zero guess has to be written
@@ -900,6 +930,7 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     c->nw.rb_fused = getenv("MGF_HALF_SWEEPS") == nullptr;
     if (getenv("MGF_ONE_SWEEP")) c->nw.sweep2_max_nodes = 0;
     if (getenv("MGF_NO_SWEEP_RESTRICT")) c->nw.sweep2_restrict = false;
+    if (const char *e = getenv("MGF_TWO_SWEEP_PRE_NODES")) c->nw.sweep2_pre_max_nodes = atoll(e);
     if (const char *e = getenv("MGF_TWO_SWEEP_NODES")) c->nw.sweep2_max_nodes = atoll(e);
     if (const char *e = getenv("MGF_CHAIN_MAX_BLOCKS")) c->nw.chain_max_blocks = atoi(e);
     if (const char *sr = getenv("MGF_SWEEP_ROWS"))
