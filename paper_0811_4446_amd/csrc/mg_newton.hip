@@ -1346,7 +1346,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
 // The loads of a lane's partials are issued together (kChainLoads per pass:
 // one pass for the grids that chain their passes), then added in order.
 constexpr int kChainLoads = 8;
-constexpr int kCgsRegs = 8;  // basis vectors a Gram-Schmidt pass keeps in registers
+constexpr int kCgsRegs = 8, kCgsRegs2 = 16;  // basis vectors a Gram-Schmidt pass keeps in registers
 inline __device__ void reduce_projections(const double *__restrict__ part, int nblk, int nv, double *hs,
                                           double *out, double *out_host) {
     for (int v = threadIdx.y; v < nv; v += blockDim.y) {
@@ -1379,10 +1379,13 @@ inline __device__ void reduce_projections(const double *__restrict__ part, int n
 // NV > 0: at most NV basis vectors (nv <= NV); a node's basis values are
 // loaded once into registers, before the previous pass's projections are
 // summed (their loads overlap), and serve both the update and the dot
-// products.  NV = 0: any nv, the basis read as it is used.  Both forms do
-// the same arithmetic (explicit fused multiply-adds in the same order).
+// products (NV = 16 only for workgroups of at most 256 threads, whose
+// register budget holds them).  NV = 0: any nv, the basis read as it is
+// used.  All forms do the same arithmetic (explicit fused multiply-adds in
+// the same order).
 template <int NV>
-__global__ __launch_bounds__(1024) void k_cgs_pass(Geom g, double *__restrict__ w, const double *__restrict__ basis,
+__global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double *__restrict__ w,
+                                                                  const double *__restrict__ basis,
                                                    int64_t vstride, int nv, int64_t plane, double3 cw,
                                                    const double *__restrict__ h_sub, int self_norm, BOp Jop,
                                                    const double *__restrict__ z, double *__restrict__ partials,
@@ -1790,11 +1793,17 @@ int block_vec_blocks(const Geom &g) {
     dim3 gr = grid2d(g);
     return (int)(gr.x * gr.y);
 }
+// The Gram-Schmidt pass form for nv basis vectors and the launch's workgroup size.
+decltype(&k_cgs_pass<0>) cgs_kernel(const Geom &g, int nv) {
+    if (nv <= kCgsRegs) return k_cgs_pass<kCgsRegs>;
+    if (nv <= kCgsRegs2 && kTX * g.ty <= 256) return k_cgs_pass<kCgsRegs2>;
+    return k_cgs_pass<0>;
+}
 void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                      double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
                      const Batch &bt, const BOp *J, const double *z) {
     dim3 gr = grid2d(g);
-    auto k = nv <= kCgsRegs ? k_cgs_pass<kCgsRegs> : k_cgs_pass<0>;
+    auto k = cgs_kernel(g, nv);
     k<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, h_sub, self_norm ? 1 : 0,
                                       J ? *J : BOp{nullptr, 0}, z, partials, nullptr, 0, nullptr, nullptr, bt);
     if (out) {
@@ -1812,7 +1821,7 @@ void launch_cgs_pass_chained(const Geom &g, double *w, const double *basis, int6
                              double3 cw, bool self_norm, const double *h_part, double *h_out, double *h_host,
                              double *partials, hipStream_t s, const Batch &bt) {
     dim3 gr = grid2d(g);
-    auto k = nv <= kCgsRegs ? k_cgs_pass<kCgsRegs> : k_cgs_pass<0>;
+    auto k = cgs_kernel(g, nv);
     k<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, nullptr, self_norm ? 1 : 0,
                                       BOp{nullptr, 0}, nullptr, partials, h_part, (int)(gr.x * gr.y), h_out, h_host,
                                       bt);
