@@ -324,9 +324,11 @@ def chain(R, z_of, phys, N0, N1, V, ne, np_, S_of, wall=0, **steady_kw):
 # oracle's level rule stops (coarse z nodes are every second fine node),
 # the Jacobian rediscretised on every level at the state injected there;
 # smoother: collective red-black Gauss-Seidel (the three unknowns of a node
-# solved together; nodes with (i + j) even first); restriction: the
-# transpose of the bilinear prolongation, field by field; coarsest level
-# solved exactly.
+# solved together; nodes with (i + j) even first), or block zebra z-line
+# Gauss-Seidel (all unknowns of an axial line i solved together, the 3x3-
+# block tridiagonal system of Eq. (14) along z; even lines first); the
+# restriction: the transpose of the bilinear prolongation, field by field;
+# coarsest level solved exactly.
 # ---------------------------------------------------------------------------
 def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8, wall=0, transport=None):
     """Per level: the Coupled system, its Jacobian (CSR) for a BE step of
@@ -345,8 +347,13 @@ def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8, wall=0, tran
         J = cp.jacobian(V, ne, np_, Ae, Ap).tocsr()
         colour = (cp.ii + cp.jj) % 2
         idx = [np.nonzero(np.repeat(colour == c, 3))[0] for c in (0, 1)]
+        # zebra: lines of one parity do not couple to each other (the
+        # five-point stencil reaches i +- 1 only), so the restriction of J to
+        # them is one block-tridiagonal system per line
+        lidx = [np.nonzero(np.repeat(cp.ii % 2 == c, 3))[0] for c in (0, 1)]
         out.append(dict(cp=cp, J=J, z=z, idx=idx,
-                        lu=[spla.splu(J[ix][:, ix].tocsc()) for ix in idx]))
+                        lu=[spla.splu(J[ix][:, ix].tocsc()) for ix in idx],
+                        lidx=lidx, llu=[spla.splu(J[ix][:, ix].tocsc()) for ix in lidx]))
         if l + 1 < nlev:
             nr, nz = nr // 2, nz // 2
             z = np.ascontiguousarray(z[::2])
@@ -356,13 +363,15 @@ def block_hierarchy(nr, nz, R, z, phys, V, ne, np_, dt, coarsest=8, wall=0, tran
     return out
 
 
-def block_colour_sweep(L, f, x, colour):
+def block_colour_sweep(L, f, x, colour, lines=False):
     """Every node of one colour takes the value that satisfies its three
     equations with the other colour's current values (the nodes of one
-    colour do not couple to each other)."""
-    ix = L["idx"][colour]
+    colour do not couple to each other).  lines: the colours are the axial
+    lines of even and odd i, and every line of the colour satisfies all its
+    equations at once (block zebra z-line Gauss-Seidel)."""
+    ix = (L["lidx"] if lines else L["idx"])[colour]
     r = f - L["J"] @ x
-    x[ix] += L["lu"][colour].solve(r[ix])
+    x[ix] += (L["llu"] if lines else L["lu"])[colour].solve(r[ix])
 
 
 def _fieldwise(L, vec, fn):
@@ -386,18 +395,20 @@ def block_prolong(L, Lc, xc):
     return L["cp"].pack(*out)
 
 
-def block_vcycle(levels, f, l=0, nu1=2, nu2=2):
-    """One V(nu1, nu2) cycle for J x = f on level l from x = 0; returns x."""
+def block_vcycle(levels, f, l=0, nu1=2, nu2=2, lines=False):
+    """One V(nu1, nu2) cycle for J x = f on level l from x = 0; returns x.
+    lines: block zebra z-line smoothing on every level above the coarsest
+    (else collective red-black point smoothing)."""
     L = levels[l]
     if l == len(levels) - 1:
         return spla.spsolve(L["J"].tocsc(), f)
     x = np.zeros_like(f)
     for _ in range(nu1):
-        block_colour_sweep(L, f, x, 0)
-        block_colour_sweep(L, f, x, 1)
+        block_colour_sweep(L, f, x, 0, lines)
+        block_colour_sweep(L, f, x, 1, lines)
     fc = block_restrict(L, levels[l + 1], f - L["J"] @ x)
-    x += block_prolong(L, levels[l + 1], block_vcycle(levels, fc, l + 1, nu1, nu2))
+    x += block_prolong(L, levels[l + 1], block_vcycle(levels, fc, l + 1, nu1, nu2, lines))
     for _ in range(nu2):
-        block_colour_sweep(L, f, x, 0)
-        block_colour_sweep(L, f, x, 1)
+        block_colour_sweep(L, f, x, 0, lines)
+        block_colour_sweep(L, f, x, 1, lines)
     return x

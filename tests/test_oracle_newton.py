@@ -189,3 +189,79 @@ def test_block_transfers_are_adjoint_and_exact_on_bilinear():
     # away from the first and last fine interior nodes (their coarse neighbour is an electrode)
     for k, fac in enumerate((1, 2, 3)):
         assert np.abs(out[k][:, 2:-2] - fac * want[:, 2:-2]).max() <= 1e-13
+
+
+def test_block_zebra_sweep_solves_its_lines():
+    """Block zebra z-line half-sweep (all unknowns of the axial lines of one
+    parity solved together): lines of one parity share no matrix entry (the
+    five-point stencil reaches i +- 1 only), after the half-sweep every
+    equation of those lines holds to rounding, and the other lines are
+    untouched."""
+    L = _hier(16, 1e-2)[0]
+    cp = L["cp"]
+    for c in (0, 1):
+        sub = L["J"][L["lidx"][c]][:, L["lidx"][c]].tocoo()
+        lines = cp.ii[L["lidx"][c] // 3]
+        assert np.array_equal(lines[sub.row], lines[sub.col])
+    rng = np.random.default_rng(13)
+    f = rng.normal(size=L["J"].shape[0])
+    x = rng.normal(size=f.size)
+    for c in (0, 1):
+        before = x.copy()
+        NW.block_colour_sweep(L, f, x, c, lines=True)
+        r = f - L["J"] @ x
+        ix, other = L["lidx"][c], L["lidx"][1 - c]
+        assert np.abs(r[ix]).max() <= 1e-12 * np.abs(f).max() * 1e3
+        assert np.array_equal(x[other], before[other])
+
+
+def test_block_zebra_sweep_is_exact_without_radial_coupling():
+    """With the entries that couple different axial lines removed, the
+    system splits into independent lines and one zebra sweep (both
+    parities) from any start is its exact solution; the point red-black
+    sweep is not."""
+    import scipy.sparse as sps
+    L = _hier(16, 1e-2)[0]
+    cp = L["cp"]
+    J = L["J"].tocoo()
+    keep = cp.ii[J.row // 3] == cp.ii[J.col // 3]
+    Jm = sps.csr_matrix((J.data[keep], (J.row[keep], J.col[keep])), shape=J.shape)
+    Lm = dict(L, J=Jm, llu=[NW.spla.splu(Jm[ix][:, ix].tocsc()) for ix in L["lidx"]],
+              lu=[NW.spla.splu(Jm[ix][:, ix].tocsc()) for ix in L["idx"]])
+    rng = np.random.default_rng(14)
+    f = rng.normal(size=J.shape[0])
+    exact = NW.spla.spsolve(Jm.tocsc(), f)
+    x = rng.normal(size=f.size)
+    NW.block_colour_sweep(Lm, f, x, 0, lines=True)
+    NW.block_colour_sweep(Lm, f, x, 1, lines=True)
+    assert np.abs(x - exact).max() <= 1e-10 * np.abs(exact).max()
+    y = rng.normal(size=f.size)
+    NW.block_colour_sweep(Lm, f, y, 0)
+    NW.block_colour_sweep(Lm, f, y, 1)
+    assert np.abs(y - exact).max() > 1e-3 * np.abs(exact).max()
+
+
+def test_block_zebra_vcycle_converges_and_beats_point_smoothing():
+    """The zebra cycle is a linear map, its stationary iteration converges
+    to J^-1 f, and on the cos-stretched axial grid (cells much shorter in z
+    than in r near the electrodes) it reduces the error faster per cycle
+    than the point red-black cycle."""
+    levels = _hier(16, 1e-4)
+    J = levels[0]["J"]
+    rng = np.random.default_rng(15)
+    f = rng.normal(size=J.shape[0])
+    exact = NW.spla.spsolve(J.tocsc(), f)
+    errs = {}
+    for lines in (False, True):
+        x = np.zeros_like(f)
+        e = []
+        for _ in range(16):
+            x += NW.block_vcycle(levels, f - J @ x, lines=lines)
+            e.append(np.abs(x - exact).max() / np.abs(exact).max())
+        errs[lines] = e
+    assert errs[True][-1] <= 1e-10, errs[True]
+    assert errs[True][5] < 0.5 * errs[False][5], (errs[True][5], errs[False][5])
+    g = rng.normal(size=f.size)
+    lin = NW.block_vcycle(levels, 2.0 * f - 3.0 * g, lines=True)
+    ref = 2.0 * NW.block_vcycle(levels, f, lines=True) - 3.0 * NW.block_vcycle(levels, g, lines=True)
+    assert np.abs(lin - ref).max() <= 1e-12 * np.abs(lin).max()
