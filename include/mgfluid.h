@@ -50,7 +50,14 @@ typedef struct mg_ctx mg_ctx;
 
 typedef enum { MG_FP64 = 0, MG_FP32_IR = 1 } mg_prec;
 typedef enum { MG_EQ_POISSON = 0, MG_EQ_ELECTRON = 1, MG_EQ_ION = 2 } mg_eq;
-typedef enum { MG_SMOOTH_RB = 0, MG_SMOOTH_ZEBRA = 1 } mg_smoother;
+/* Smoothers.  MG_SMOOTH_RB: red-black point Gauss-Seidel (scalar
+ * equations) and collective red-black (the 3x3 node blocks of the Newton
+ * system, Eq. 14).  MG_SMOOTH_ZEBRA: zebra z-line Gauss-Seidel for the
+ * scalar equations, collective red-black for the Newton system.
+ * MG_SMOOTH_ZEBRA_BLOCK: zebra z-line for both; on the Newton system each
+ * axial line's 3x3-block tridiagonal system along z is solved exactly
+ * (block Thomas), even lines first, on every level above the coarsest. */
+typedef enum { MG_SMOOTH_RB = 0, MG_SMOOTH_ZEBRA = 1, MG_SMOOTH_ZEBRA_BLOCK = 2 } mg_smoother;
 typedef enum { MG_COUPLE_DECOUPLED = 0, MG_COUPLE_NEWTON = 2 } mg_coupling;
 
 /* Grid and multigrid configuration.
@@ -61,7 +68,7 @@ typedef enum { MG_COUPLE_DECOUPLED = 0, MG_COUPLE_NEWTON = 2 } mg_coupling;
  *                z[0] = 0 and z[nz] = d; copied during mg_setup
  *   coarsest_n   smaller dimension of the coarsest grid (>= 2; default 8)
  *   nu1, nu2     pre- and post-smoothing sweeps of the V-cycle
- *   smoother     mg_smoother: red-black point or zebra z-line Gauss-Seidel
+ *   smoother     mg_smoother (above)
  *   prec         mg_prec: FP64 cycles, or FP32 cycles inside FP64
  *                iterative refinement
  *   krylov_m     restart length of the FGMRES solver of the coupled

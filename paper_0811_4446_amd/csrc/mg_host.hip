@@ -56,7 +56,7 @@ int validate(const mg_grid_desc *d) {
         return fail(MG_EINVAL, "abi_version %d, library has %d", d->abi_version, MG_ABI_VERSION);
     if (!d->z_host) return fail(MG_EINVAL, "null z_host");
     if (!(d->R > 0) || !(d->d > 0)) return fail(MG_EINVAL, "R and d must be positive");
-    if (d->smoother != MG_SMOOTH_RB && d->smoother != MG_SMOOTH_ZEBRA)
+    if (d->smoother != MG_SMOOTH_RB && d->smoother != MG_SMOOTH_ZEBRA && d->smoother != MG_SMOOTH_ZEBRA_BLOCK)
         return fail(MG_EINVAL, "bad smoother %d", d->smoother);
     if (d->prec != MG_FP64 && d->prec != MG_FP32_IR) return fail(MG_EINVAL, "bad precision %d", d->prec);
     if (d->r_outer_bc != MG_WALL_ZERO_FLUX && d->r_outer_bc != MG_WALL_DIRICHLET)

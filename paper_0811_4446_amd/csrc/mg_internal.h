@@ -238,6 +238,7 @@ struct BLevel {
     double *x, *r;  // 3-field correction and residual
     double *x2;     // partner of x for the fused red-black sweep (zero electrode rows)
     double *cinvT;  // coarsest level: transposed inverse of the block matrix
+    double *zt;     // block zebra smoother: 12 planes of line-elimination factors (else null)
     // FP32 copies for the mixed-precision preconditioner
     float *J32, *x32, *r32, *cinvT32, *x2_32;
 };

@@ -63,6 +63,11 @@ void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const 
 template <class T>
 void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s,
                        const Batch &bt = Batch());
+// Block zebra z-line half-sweep of the lines i = colour, colour + 2, ...;
+// tmp: 12 planes of the level's plane size (elimination factors).
+template <class T>
+void launch_block_zline(const Geom &g, const BOpT<T> &J, const T *f, T *x, T *tmp, int colour, hipStream_t s,
+                        const Batch &bt = Batch());
 // One full red-black sweep xin -> xout; zin: input zero; gc/xc/pc: input is
 // xin plus the prolongation of the coarse correction xc (level gc, plane pc).
 template <class T>

@@ -399,6 +399,130 @@ __global__ void k_block_rbgs(Geom g, BOpT<T> J, const T *__restrict__ f, T *__re
     block_gs_node(g, J, f, x, i, j);
 }
 
+// Block zebra z-line half-sweep: every axial line i of parity `colour`
+// (one thread per line) solves its 3x3-block tridiagonal system along z,
+//   L_j x_{j-1} + C_j x_j + U_j x_{j+1} = f_j - (couplings to lines i -+ 1),
+// with the other parity's current values, by block forward elimination and
+// back substitution (block Thomas): P_j = D_j^-1 U_j and y_j = D_j^-1 (g_j -
+// L_j y_{j-1}) with D_j = C_j - L_j P_{j-1} go to tmp (12 planes: P row-
+// major, then y), then x_j = y_j - P_j x_{j+1}.  The electrode rows hold
+// zero corrections, so the first and last unknowns have no outer coupling.
+// The coefficients of node j+1 are loaded while node j is eliminated.
+template <class T>
+struct ZlRow {
+    T c[kFe];     // Jacobian planes 0 .. kVp of the node
+    T g[3];       // f minus the couplings to the neighbouring lines
+};
+template <class T>
+inline __device__ void zl_load(const Geom &g, const BOpT<T> &J, const T *f, const T *x, int i, int j, ZlRow<T> &R) {
+    const int64_t p = at(g, i, j), plane = J.plane;
+#pragma unroll
+    for (int q = 0; q < kFe; ++q) R.c[q] = J.pl(q)[p];
+    T ge = f[p], gp = f[p + plane], gv = f[p + 2 * plane];
+    const int dirs[2] = {0, 2};
+    const bool has[2] = {i > 0, i < g.nr};
+    const int64_t nb[2] = {p - g.pitch, p + g.pitch};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (!has[t]) continue;
+        const int d = dirs[t];
+        const T xe = x[nb[t]], xp = x[nb[t] + plane], xv = x[nb[t] + 2 * plane];
+        ge = fmad(-R.c[kEE + d], xe, fmad(-R.c[kEV + d], xv, ge));
+        gp = fmad(-R.c[kPP + d], xp, fmad(-R.c[kPV + d], xv, gp));
+        gv = fmad(-R.c[kVV + d], xv, gv);
+    }
+    R.g[0] = ge;
+    R.g[1] = gp;
+    R.g[2] = gv;
+}
+template <class T>
+__global__ __launch_bounds__(64) void k_block_zline(Geom g, BOpT<T> J, const T *__restrict__ f, T *__restrict__ x,
+                                                    T *__restrict__ tmp, int colour, Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    g = geom_off(g, bo_);
+    J.base = boff(J.base, bo_);
+    f = boff(f, bo_);
+    x = boff(x, bo_);
+    tmp = boff(tmp, bo_);
+    const int i = 2 * (blockIdx.x * blockDim.x + threadIdx.x) + colour;
+    if (i > g.nr) return;
+    const int64_t plane = J.plane;
+    const int n = g.nz - 1;  // unknowns j = 1 .. n
+    T P[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, y[3] = {0, 0, 0};
+    ZlRow<T> cur, nxt;
+    zl_load(g, J, f, x, i, 1, cur);
+    for (int j = 1; j <= n; ++j) {
+        if (j < n) zl_load(g, J, f, x, i, j + 1, nxt);
+        const T *c = cur.c;
+        // D = C - L P_{j-1}, r = g - L y_{j-1}  (L = [[ee3,0,eV3],[0,pp3,pV3],[0,0,VV3]])
+        T D[9] = {c[kEE + 1], T(0), c[kEV + 1], T(0), c[kPP + 1], c[kPV + 1], c[kVe], c[kVp], c[kVV + 1]};
+        T r0 = cur.g[0], r1 = cur.g[1], r2 = cur.g[2];
+        if (j > 1) {
+            const T le = c[kEE + 3], lev = c[kEV + 3], lp = c[kPP + 3], lpv = c[kPV + 3], lv = c[kVV + 3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                D[k] = fmad(-le, P[k], fmad(-lev, P[6 + k], D[k]));
+                D[3 + k] = fmad(-lp, P[3 + k], fmad(-lpv, P[6 + k], D[3 + k]));
+                D[6 + k] = fmad(-lv, P[6 + k], D[6 + k]);
+            }
+            r0 = fmad(-le, y[0], fmad(-lev, y[2], r0));
+            r1 = fmad(-lp, y[1], fmad(-lpv, y[2], r1));
+            r2 = fmad(-lv, y[2], r2);
+        }
+        // D^-1 by the adjugate
+        const T a00 = fmad(D[4], D[8], -D[5] * D[7]), a01 = fmad(D[2], D[7], -D[1] * D[8]),
+                a02 = fmad(D[1], D[5], -D[2] * D[4]);
+        const T a10 = fmad(D[5], D[6], -D[3] * D[8]), a11 = fmad(D[0], D[8], -D[2] * D[6]),
+                a12 = fmad(D[2], D[3], -D[0] * D[5]);
+        const T a20 = fmad(D[3], D[7], -D[4] * D[6]), a21 = fmad(D[1], D[6], -D[0] * D[7]),
+                a22 = fmad(D[0], D[4], -D[1] * D[3]);
+        const T id = T(1) / fmad(D[0], a00, fmad(D[1], a10, D[2] * a20));
+        const T Di[9] = {a00 * id, a01 * id, a02 * id, a10 * id, a11 * id, a12 * id, a20 * id, a21 * id, a22 * id};
+        // y_j = D^-1 r; P_j = D^-1 U (U = [[ee4,0,eV4],[0,pp4,pV4],[0,0,VV4]]; none for the last unknown)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) y[k] = fmad(Di[3 * k], r0, fmad(Di[3 * k + 1], r1, Di[3 * k + 2] * r2));
+        const bool last = j == n;
+        const T ue = last ? T(0) : c[kEE + 4], uev = last ? T(0) : c[kEV + 4], up = last ? T(0) : c[kPP + 4],
+                upv = last ? T(0) : c[kPV + 4], uv = last ? T(0) : c[kVV + 4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            P[3 * k] = Di[3 * k] * ue;
+            P[3 * k + 1] = Di[3 * k + 1] * up;
+            P[3 * k + 2] = fmad(Di[3 * k], uev, fmad(Di[3 * k + 1], upv, Di[3 * k + 2] * uv));
+        }
+        const int64_t p = at(g, i, j);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) tmp[p + k * plane] = P[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tmp[p + (9 + k) * plane] = y[k];
+        cur = nxt;
+    }
+    // back substitution from the last unknown (x_n = y_n, held in y)
+    T xe = y[0], xp = y[1], xv = y[2];
+    int64_t p = at(g, i, n);
+    x[p] = xe;
+    x[p + plane] = xp;
+    x[p + 2 * plane] = xv;
+    for (int j = n - 1; j >= 1; --j) {
+        p = at(g, i, j);
+        T Pj[9], yj[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Pj[k] = tmp[p + k * plane];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) yj[k] = tmp[p + (9 + k) * plane];
+        const T ne = fmad(-Pj[0], xe, fmad(-Pj[1], xp, fmad(-Pj[2], xv, yj[0])));
+        const T np = fmad(-Pj[3], xe, fmad(-Pj[4], xp, fmad(-Pj[5], xv, yj[1])));
+        const T nv = fmad(-Pj[6], xe, fmad(-Pj[7], xp, fmad(-Pj[8], xv, yj[2])));
+        xe = ne;
+        xp = np;
+        xv = nv;
+        x[p] = xe;
+        x[p + plane] = xp;
+        x[p + 2 * plane] = xv;
+    }
+}
+
 // Tile of a sweep workgroup.  The hardware deals workgroups to the eight
 // XCDs round-robin by linear index b (XCD = b mod 8); with g.xcd the tile of
 // workgroup b is t = start(b mod 8) + b / 8, so every XCD works through one
@@ -1689,6 +1813,12 @@ void launch_newton_assemble(const Geom &g, const BOp &J, const double *V, const 
                                                          php, bt, tr);
 }
 template <class T>
+void launch_block_zline(const Geom &g, const BOpT<T> &J, const T *f, T *x, T *tmp, int colour, hipStream_t s,
+                        const Batch &bt) {
+    const int lines = (g.nr + 2 - colour) / 2;  // i = colour, colour + 2, ... <= nr
+    k_block_zline<T><<<dim3((lines + 63) / 64, 1, bt.n), 64, 0, s>>>(g, J, f, x, tmp, colour, bt);
+}
+template <class T>
 void launch_block_rbgs(const Geom &g, const BOpT<T> &J, const T *f, T *x, int colour, hipStream_t s, const Batch &bt) {
     k_block_rbgs<T><<<gz(grid2d(g), bt), blk2d(g), 0, s>>>(g, J, f, x, colour, bt);
 }
@@ -1960,6 +2090,8 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
                                        const Batch &);                                                       \
     template void launch_block_rb_sweep<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,   \
                                            const Geom *, const T *, int64_t, hipStream_t, const Batch &);     \
+    template void launch_block_zline<T>(const Geom &, const BOpT<T> &, const T *, T *, T *, int, hipStream_t,  \
+                                        const Batch &);                                                      \
     template void launch_block_rb_sweep2<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *, bool,  \
                                             const Geom *, const T *, int64_t, hipStream_t, const Batch &);    \
     template void launch_block_rb_sweep2_restrict<T>(const Geom &, const BOpT<T> &, const T *, const T *, T *,  \

@@ -29,6 +29,7 @@ struct Prec<double> {
     static double *x(mg_ctx *c, int l) { return c->nw.lev[l].x; }
     static double *r(mg_ctx *c, int l) { return c->nw.lev[l].r; }
     static double *x2(mg_ctx *c, int l) { return c->nw.lev[l].x2; }
+    static double *zt(mg_ctx *c, int l) { return c->nw.lev[l].zt; }
     static const double *inv(mg_ctx *c) { return c->nw.lev[c->nlev - 1].cinvT; }
 };
 template <>
@@ -37,6 +38,8 @@ struct Prec<float> {
     static float *x(mg_ctx *c, int l) { return c->nw.lev[l].x32; }
     static float *r(mg_ctx *c, int l) { return c->nw.lev[l].r32; }
     static float *x2(mg_ctx *c, int l) { return c->nw.lev[l].x2_32; }
+    // the FP64 factor planes hold the FP32 ones (same plane stride in elements)
+    static float *zt(mg_ctx *c, int l) { return reinterpret_cast<float *>(c->nw.lev[l].zt); }
     static const float *inv(mg_ctx *c) { return c->nw.lev[c->nlev - 1].cinvT32; }
 };
 
@@ -82,10 +85,23 @@ bool sweep2_pre_ok(const mg_ctx *c, int l) {
            c->desc.nu1 % 2 == 0 && c->desc.nu2 >= 2;
 }
 
+// Block zebra z-line smoothing selected (MG_SMOOTH_ZEBRA_BLOCK).
+bool zebra_block(const mg_ctx *c) { return c->desc.smoother == MG_SMOOTH_ZEBRA_BLOCK; }
+
 template <class T>
 void block_smooth(mg_ctx *c, int l, const BOpT<T> &J, const T *f, T *x, int nu, bool x_zero, const T *xc,
                   hipStream_t s) {
     const Geom &g = c->lev[l].g;
+    if (zebra_block(c)) {
+        // nu zebra sweeps (even lines, then odd) on x, which holds the
+        // iterate (written zero first when x_zero; a coarse correction xc is
+        // added by its own launch)
+        if (x_zero) launch_fill(x, 3 * plane_of(c->lev[l]), T(0), s, c->bt);
+        if (xc) launch_prolong3<T>(g, x, plane_of(c->lev[l]), c->lev[l + 1].g, xc, plane_of(c->lev[l + 1]), s, c->bt);
+        for (int k = 0; k < nu; ++k)
+            for (int col = 0; col < 2; ++col) launch_block_zline<T>(g, J, f, x, Prec<T>::zt(c, l), col, s, c->bt);
+        return;
+    }
     int k = 0;
     if (fused_ok<T>(c, nu)) {
         T *x2 = Prec<T>::x2(c, l);
@@ -108,15 +124,19 @@ template <class T>
 void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     const Level &L = c->lev[l];
     BOpT<T> J = Prec<T>::op(c, l);
+    const bool zb = zebra_block(c);
     if (l == 0 && c->nw.smoother_only) {
-        // relaxation only: nu1 + nu2 collective red-black sweeps from zero
+        // relaxation only: nu1 + nu2 sweeps from zero (collective red-black,
+        // or block zebra)
         const int nu = c->desc.nu1 + c->desc.nu2;
-        const bool zs = fused_ok<T>(c, nu);
+        const bool zs = zb || fused_ok<T>(c, nu);
         if (!zs) launch_fill(x, 3 * plane_of(L), T(0), s, c->bt);
         block_smooth<T>(c, 0, J, f, x, nu, zs, nullptr, s);
         return;
     }
-    if (c->nw.fuse && L.g.nr <= c->nw.fuse_max && L.g.nz <= c->nw.fuse_max && c->nlev - l <= kMaxFused) {
+    // (the block zebra smoother runs on every level above the coarsest, by
+    // per-level launches)
+    if (!zb && c->nw.fuse && L.g.nr <= c->nw.fuse_max && L.g.nz <= c->nw.fuse_max && c->nlev - l <= kMaxFused) {
         FusedLevelsT<T> F;
         memset(&F, 0, sizeof F);
         F.n = c->nlev - l;
@@ -144,7 +164,7 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
     BOpT<T> Jc = Prec<T>::op(c, l + 1);
     T *fc = Jc.pl(kFe);
     T *xc = Prec<T>::x(c, l + 1);
-    if (sweep2_ok(c, l)) {
+    if (!zb && sweep2_ok(c, l)) {
         // sweeps in pairs, alternating between x and x2: the first from a zero
         // guess, the first post-smoothing pair adding the prolonged correction
         // as it stages its input; the buffer order makes the last pair land in x
@@ -175,7 +195,7 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         }
         return;
     }
-    if (sweep2_pre_ok(c, l)) {
+    if (!zb && sweep2_pre_ok(c, l)) {
         // pre-smoothing in pairs landing in x (the first from a zero guess,
         // the last restricting the residual), post-smoothing one sweep per
         // launch from x (the first adding the prolonged correction)
@@ -196,7 +216,7 @@ void block_vcycle(mg_ctx *c, int l, const T *f, T *x, hipStream_t s) {
         return;
     }
     // without a fused first sweep the zero guess has to be written
-    const bool zero_sweep = fused_ok<T>(c, c->desc.nu1);
+    const bool zero_sweep = zb || fused_ok<T>(c, c->desc.nu1);
     if (!zero_sweep) launch_fill(x, 3 * plane_of(L), T(0), s, c->bt);
     block_smooth<T>(c, l, J, f, x, c->desc.nu1, zero_sweep, nullptr, s);
     if (c->nw.rb_fused) {
@@ -650,6 +670,7 @@ void carve_newton(mg_ctx *c, const mg_grid_desc *d, Carver &cv, int nl) {
         B.x = cv.take<double>(3 * pl);
         B.x2 = cv.take<double>(3 * pl);
         B.r = cv.take<double>(3 * pl);
+        if (d->smoother == MG_SMOOTH_ZEBRA_BLOCK) B.zt = cv.take<double>(12 * pl);
         bool p32 = d->prec == MG_FP32_IR;
         if (p32) {
             B.J32 = cv.take<float>(kBPlanes * pl);

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmgfluid.so")
 ABI_VERSION = 2
 FP64, FP32_IR = 0, 1
 POISSON, ELECTRON, ION = 0, 1, 2
-SMOOTH_RB, SMOOTH_ZEBRA = 0, 1
+SMOOTH_RB, SMOOTH_ZEBRA, SMOOTH_ZEBRA_BLOCK = 0, 1, 2
 DECOUPLED, NEWTON = 0, 2
 WALL_ZERO_FLUX, WALL_DIRICHLET = 0, 1
 
@@ -315,13 +315,13 @@ class Batch:
     """nprob same-shape problems solved together (one size class)."""
 
     def __init__(self, nr, nz, z, nprob, R=1.0, d=1.0, coarsest=4, nu1=2, nu2=2, prec=FP32_IR, krylov_m=20,
-                 device="cuda:0", stream=None, r_outer_bc=WALL_ZERO_FLUX):
+                 device="cuda:0", stream=None, r_outer_bc=WALL_ZERO_FLUX, smoother=SMOOTH_ZEBRA):
         if not torch.cuda.is_available():
             raise RuntimeError("mgfluid needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.nr, self.nz, self.n = nr, nz, nprob
         self.z = np.ascontiguousarray(z, dtype=np.float64)
         self.device = torch.device(device)
-        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, SMOOTH_ZEBRA, prec, krylov_m, r_outer_bc)
+        self.desc = make_desc(nr, nz, self.z, R, d, coarsest, nu1, nu2, smoother, prec, krylov_m, r_outer_bc)
         self.pitch, _ = query(self.desc)
         stride, total = _I64(0), _I64(0)
         _check(lib().mg_batch_query(ctypes.byref(self.desc), nprob, ctypes.byref(stride), ctypes.byref(total)))

@@ -36,21 +36,21 @@ def _draw(N, nprob, seed):
     return probs
 
 
-@pytest.mark.parametrize("N,nprob,prec", [(16, 5, 1), (32, 4, 1), (32, 3, 0)])
-def test_batch_equals_single_problem_solves(N, nprob, prec):
-    _say("batch vs single", N, nprob, prec)
+@pytest.mark.parametrize("N,nprob,prec,smoother", [(16, 5, 1, 1), (32, 4, 1, 1), (32, 3, 0, 1), (32, 3, 0, 2)])
+def test_batch_equals_single_problem_solves(N, nprob, prec, smoother):
+    _say("batch vs single", N, nprob, prec, smoother)
     m = M()
     z = I.z_cos(N)
     probs = _draw(N, nprob, 12345)
     sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-3, max_cycles=200, newton_tol=1e-6, steady_tol=1e-8,
                     max_steps=3000)
-    B = m.Batch(N, N, z, nprob, prec=prec, krylov_m=20)
+    B = m.Batch(N, N, z, nprob, prec=prec, krylov_m=20, smoother=smoother)
     for p, (phys, V, ne, np_, S) in enumerate(probs):
         B.set_problem(p, V, ne, np_, S)
     code, reps = B.steady([m.Physics.of(pr[0]) for pr in probs], sc)
     assert code == 0, m.lib().mg_last_error()
     for p, (phys, V, ne, np_, S) in enumerate(probs):
-        sol = m.Solver(N, N, z, krylov_m=20, coarsest=4, prec=prec)
+        sol = m.Solver(N, N, z, krylov_m=20, coarsest=4, prec=prec, smoother=smoother)
         t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)]
         c1, rep = sol.steady(m.Physics.of(phys), sol.state(t[0], t[1], t[2], t[3], t[3]), sc)
         assert c1 == 0

@@ -91,18 +91,73 @@ def test_relaxation_only_preconditioner_matches_oracle(monkeypatch):
     assert rep.vcycles > rb.vcycles, (rep.vcycles, rb.vcycles)
 
 
+@pytest.mark.parametrize("N,dt,pre,prec_name", [(32, 1e-3, 12, "FP64"), (64, 0.1, 25, "FP64"),
+                                                 (64, 0.1, 25, "FP32_IR")])
+def test_newton_step_block_zebra_matches_oracle(N, dt, pre, prec_name):
+    """One BE step with the block zebra z-line preconditioner (FP64 or FP32
+    cycles; FGMRES and Newton in FP64): the oracle's exact Newton iterates,
+    same iteration count, within 1e-12."""
+    _say("newton step zebra", N, dt, pre, prec_name)
+    m = M()
+    z, V, ne, np_, S = _start(N)
+    ph = dict(I.PHYS)
+    cp = NW.Coupled(N, N, 1.0, z, ph)
+    if pre:
+        NW.steady(cp, V, ne, np_, S, S, max_steps=pre)
+    sol, t, st = _gpu(N, V, ne, np_, S, smoother=m.SMOOTH_ZEBRA_BLOCK, prec=getattr(m, prec_name))
+    ok, its = NW.newton_step(cp, V, ne, np_, S, S, dt, max_newton=20, tol=1e-11)
+    assert ok
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-13, max_cycles=400, max_newton=20, newton_tol=1e-11)
+    rep = sol.step(m.Physics.of(ph), st, dt, sc)
+    assert rep.newton_its == its, (rep.newton_its, its)
+    errs = [relmax(sol.download(tt), ref) for tt, ref in zip(t[:3], (V, ne, np_))]
+    print("newton step zebra %s dt %g %s: max rel err %s, %d FGMRES" % (N, dt, prec_name, errs, rep.vcycles))
+    assert max(errs) <= 1e-12, errs
+
+
+def test_block_zebra_preconditions_with_fewer_iterations():
+    """On the cos-stretched axial grid the block zebra cycle is the stronger
+    preconditioner: the same Newton step (65x65 and 129x129, dt = 0.1, linear
+    tolerance 1e-6) takes fewer FGMRES iterations than with point smoothing,
+    and both reach the same state."""
+    m = M()
+    ph = dict(I.PHYS)
+    for N, pre in ((64, 25), (128, 25)):
+        _say("zebra iterations", N)
+        z, V, ne, np_, S = _start(N)
+        cp = NW.Coupled(N, N, 1.0, z, ph)
+        NW.steady(cp, V, ne, np_, S, S, max_steps=pre)
+        its, states = {}, {}
+        for sm in (m.SMOOTH_ZEBRA, m.SMOOTH_ZEBRA_BLOCK):
+            sol, t, st = _gpu(N, V, ne, np_, S, smoother=sm)
+            sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-6, max_cycles=400, max_newton=20, newton_tol=1e-10)
+            rep = sol.step(m.Physics.of(ph), st, 0.1, sc)
+            its[sm] = (rep.newton_its, rep.vcycles)
+            states[sm] = [sol.download(x) for x in t[:3]]
+        print("%dx%d FGMRES iterations (Newton, FGMRES): point %s, zebra %s" % (N + 1, N + 1, its[m.SMOOTH_ZEBRA],
+                                                                                 its[m.SMOOTH_ZEBRA_BLOCK]))
+        assert its[m.SMOOTH_ZEBRA_BLOCK][1] < its[m.SMOOTH_ZEBRA][1]
+        for a, b in zip(states[m.SMOOTH_ZEBRA_BLOCK], states[m.SMOOTH_ZEBRA]):
+            assert relmax(a, b) <= 1e-8
+
+
 @pytest.mark.parametrize("N,dt,pre,mode", [(32, 1e-3, 0, "default"), (64, 0.1, 12, "default"),
                                             (64, 0.1, 12, "no_fuse"), (64, 0.1, 12, "one_sweep"),
                                             (64, 0.1, 12, "half"), (128, 1e-2, 0, "default"),
                                             (64, 0.1, 12, "fp32"), ((32, 64), 1e-2, 0, "default"),
-                                            ((64, 32), 1e-2, 0, "no_fuse"), (64, float("inf"), 12, "default")])
+                                            ((64, 32), 1e-2, 0, "no_fuse"), (64, float("inf"), 12, "default"),
+                                            (32, 1e-3, 0, "zebra"), (64, 0.1, 12, "zebra"),
+                                            ((32, 64), 1e-2, 0, "zebra"), ((64, 32), float("inf"), 12, "zebra"),
+                                            (64, 0.1, 12, "zebra_fp32")])
 def test_block_vcycle_matches_oracle(N, dt, pre, mode, monkeypatch):
     """One block V(2,2) cycle z = M r at the Newton Jacobian of a state
     (mg_newton_precond) against the oracle's cycle written from its
     definition, element by element: rediscretised coarse Jacobians at the
     injected state, collective red-black sweeps, R = P^T, exact coarsest
     solve.  Covers the coarse sub-cycle and the per-level launches, one and
-    two sweeps per launch, half-sweeps, and the FP32 cycle."""
+    two sweeps per launch, half-sweeps, the FP32 cycle, and the block zebra
+    z-line smoother (every axial line's block-tridiagonal system solved by
+    block elimination on the GPU, by sparse LU in the oracle)."""
     _say("block vcycle", N, dt, pre, mode)
     m = M()
     nr, nz = N if isinstance(N, tuple) else (N, N)
@@ -118,8 +173,10 @@ def test_block_vcycle_matches_oracle(N, dt, pre, mode, monkeypatch):
     env = {"no_fuse": "MGF_NO_FUSE", "one_sweep": "MGF_ONE_SWEEP", "half": "MGF_HALF_SWEEPS"}.get(mode)
     if env:
         monkeypatch.setenv(env, "1")
-    prec = m.FP32_IR if mode == "fp32" else m.FP64
-    sol = m.Solver(nr, nz, z, coarsest=4, krylov_m=10, prec=prec)
+    prec = m.FP32_IR if mode in ("fp32", "zebra_fp32") else m.FP64
+    lines = mode.startswith("zebra")
+    sol = m.Solver(nr, nz, z, coarsest=4, krylov_m=10, prec=prec,
+                   smoother=m.SMOOTH_ZEBRA_BLOCK if lines else m.SMOOTH_ZEBRA)
     if env:
         monkeypatch.delenv(env, raising=False)
     t = [sol.upload(V), sol.upload(ne), sol.upload(np_), sol.upload(S)]
@@ -137,8 +194,8 @@ def test_block_vcycle_matches_oracle(N, dt, pre, mode, monkeypatch):
     sol.precond(m.Physics.of(ph), st, dt, r, zt)
     torch.cuda.synchronize()
     got = zt[:, :, : nz + 1].cpu().numpy()
-    want = levels[0]["cp"].unpack(NW.block_vcycle(levels, levels[0]["cp"].pack(*planes)))
-    tol = 1e-4 if mode == "fp32" else 1e-12
+    want = levels[0]["cp"].unpack(NW.block_vcycle(levels, levels[0]["cp"].pack(*planes), lines=lines))
+    tol = 1e-4 if mode in ("fp32", "zebra_fp32") else 1e-12
     errs = [np.abs(got[k] - want[k]).max() / np.abs(want[k]).max() for k in range(3)]
     print("block vcycle %s dt %g %s: max rel err %s" % (N, dt, mode, errs))
     for k in range(3):
