@@ -832,6 +832,7 @@ def main():
     ap.add_argument("--fig1", action="store_true", help="Sec. 3 Fig. 1 re-measured: R / M / M+L time vs N")
     ap.add_argument("--argon", action="store_true", help="Sec. 3 argon discharge: ion current to the cathode")
     ap.add_argument("--hybrid", action="store_true", help="hybrid loop: table transport, warm-started solves")
+    ap.add_argument("--zebra", action="store_true", help="time-to-steady: point vs block zebra z-line smoother")
     ap.add_argument("--hybrid-cycles", type=int, default=5)
     ap.add_argument("--argon-grid", type=int, default=256, help="finest N of the argon chain (power of two >= 16)")
     ap.add_argument("--fig1-grids", type=str, default="32,64,128,256", help="N values, each > 16")
@@ -870,6 +871,8 @@ def main():
         return hybrid(args, M, I)
     vtops = [float(v) for v in args.vtops.split(",")]
     N = args.grid
+    if args.zebra:
+        return compare_smoothers(args, M, I, N, vtops)
     if args.prec != "fp64":
         return compare_precisions(args, M, I, N, vtops)
     cases = []
@@ -932,6 +935,46 @@ def main():
         out["config"]["t1025"] = time_to_steady_1025(args, M, I, vtops)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(I, int(round(newton_mean)))
+    print(json.dumps(out), flush=True)
+
+
+def compare_smoothers(args, M, I, N, vtops):
+    """Time-to-steady on N x N from the prolonged N/2 steady state with the
+    collective red-black point smoother and with the block zebra z-line
+    smoother (MG_SMOOTH_ZEBRA_BLOCK), same state, schedule and FP64 path;
+    one run per smoother and voltage after one untimed run."""
+    import numpy as np
+    import torch
+    rows = []
+    for vt in vtops:
+        fine, t, P, info = chain_to(M, I, N, vt, args.lin_rtol)
+        init = [x.clone() for x in t[:3]]
+        finals = {}
+        for name, sm in (("point", M.SMOOTH_ZEBRA), ("zebra_block", M.SMOOTH_ZEBRA_BLOCK)):
+            sol = M.Solver(N, N, I.z_cos(N), krylov_m=30, coarsest=4, smoother=sm)
+            for k in range(2):
+                tt = [x.clone() for x in init] + [t[3]]
+                torch.cuda.synchronize()
+                t0 = time.time()
+                code, rep = sol.steady(P, sol.state(tt[0], tt[1], tt[2], tt[3], tt[3]), schedule(M, args.lin_rtol))
+                torch.cuda.synchronize()
+                el = time.time() - t0
+                if code != 0:
+                    raise RuntimeError("steady (%s) failed: %s" % (name, M.lib().mg_last_error()))
+            finals[name] = [sol.download(x) for x in tt[:3]]
+            rows.append(dict(V_top=vt, smoother=name, seconds=round(el, 4), steps=rep.steps,
+                             newton=rep.newton_its, fgmres=rep.vcycles))
+            log("%dx%d V_top=%g %s: %.3f s, %d steps, %d Newton, %d FGMRES" % (N + 1, N + 1, vt, name, el, rep.steps,
+                                                                              rep.newton_its, rep.vcycles))
+        rows.append(dict(V_top=vt, zebra_vs_point_maxrel=[
+            float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(finals["zebra_block"], finals["point"])]))
+    mean = {k: round(sum(r["seconds"] for r in rows if r.get("smoother") == k) / len(vtops), 4)
+            for k in ("point", "zebra_block")}
+    out = {"metric": METRIC, "value": mean["zebra_block"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "steady %dx%d from the prolonged %dx%d state, point vs block zebra smoother "
+                                  "(value: zebra mean)" % (N + 1, N + 1, N // 2 + 1, N // 2 + 1),
+                      "mean_seconds": mean, "runs": rows}}
     print(json.dumps(out), flush=True)
 
 
