@@ -231,6 +231,15 @@ def roofline_only(args, M, I):
     b.copy_(a)
     torch.cuda.synchronize()
     roof["calibration_copy_bytes"] = a.numel() * 8
+    # practical ceiling of this GPU's HBM for a streaming kernel: a plain
+    # 512 MiB device copy (read + write bytes), 20 back to back
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    roof["plain_copy_GBps"] = round(2 * a.numel() * 8 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
     print(json.dumps({"roofline": roof}), flush=True)
 
 
