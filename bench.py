@@ -41,11 +41,11 @@ HBM_PEAK_GBS = 8000.0
 # with (the text between the two markers, which holds both sweep kernels
 # and their device helpers): any change to it reports null.
 MEASURED_TRAFFIC = {"source": "paper_0811_4446_amd/csrc/mg_newton.hip",
-                    "begin": "// Bilinear prolongation (z-distance weights) of one coarse field",
+                    "begin": "// x plus the bilinear prolongation (z-distance weights) of one coarse field",
                     "end": "__global__ void k_block_residual(Geom g, BOpT<T> J",
-                    "sha1": "6607a2516993b7eac1a230194afc547ce2ca15d6",
-                    "bytes": {256: 19947212, 1024: 320607436},
-                    "sweep2_vcycle_bytes": {256: 18434252}}
+                    "sha1": "c8749accfbbad713a3c3fc615e9c67c093a485eb",
+                    "bytes": {256: 20511539, 1024: 313476403},
+                    "sweep2_vcycle_bytes": {256: 20192357}}
 
 
 def log(*a):
@@ -243,13 +243,14 @@ def roofline_only(args, M, I):
     print(json.dumps({"roofline": roof}), flush=True)
 
 
-def trace_summary(path, top=25, tail_kernel="k_block_rb_sweep<", tail=200):
+def trace_summary(path, top=25, tail_kernel="k_block_rb_sweep", tail=200):
     """Summary of a rocprofv3 CSV: a kernel trace (per kernel and grid
     shape: calls, total and average duration) or a counter collection (per
     kernel, grid shape and counter: dispatches and mean value).  For a
-    trace, also the mean duration of the last `tail` dispatches of
-    `tail_kernel` on its largest grid: the roofline loop's launches, which
-    come last in the benchmark."""
+    trace, also the mean duration of the last `tail` dispatches of every
+    kernel whose name contains `tail_kernel`, per grid shape: the roofline
+    loops' launches, which come last for each of their grids in the
+    benchmark."""
     import csv
     import collections
     agg = collections.OrderedDict()
@@ -272,7 +273,7 @@ def trace_summary(path, top=25, tail_kernel="k_block_rb_sweep<", tail=200):
                 e[0] += 1
                 e[1] += d
                 if tail_kernel in name:
-                    tails[grid].append((int(row["Start_Timestamp"]), d))
+                    tails[key].append((int(row["Start_Timestamp"]), d))
             else:
                 key = (name[:70], grid, row["Counter_Name"])
                 e = agg.setdefault(key, [0, 0.0])
@@ -283,16 +284,11 @@ def trace_summary(path, top=25, tail_kernel="k_block_rb_sweep<", tail=200):
         print("%-70s %-16s %9s %12s %10s %7s" % ("kernel", "grid", "calls", "total_ms", "avg_us", "share"))
         for (name, grid), (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
             print("%-70s %-16s %9d %12.3f %10.3f %6.2f%%" % (name, grid, c, t / 1e6, t / c / 1e3, 100.0 * t / tot))
-        if tails:
-            def size(g):
-                n = 1
-                for v in g.split("x"):
-                    n *= int(v)
-                return n
-            grid = max(tails, key=size)
-            last = [d for _, d in sorted(tails[grid])[-tail:]]
-            print("last %d dispatches of %s on grid %s: mean %.3f us" % (len(last), tail_kernel.rstrip("<"), grid,
-                                                                        sum(last) / len(last) / 1e3))
+        for (name, grid), v in sorted(tails.items()):
+            if len(v) < tail:
+                continue
+            last = [d for _, d in sorted(v)[-tail:]]
+            print("last %d dispatches of %s on grid %s: mean %.3f us" % (tail, name, grid, sum(last) / tail / 1e3))
     else:
         print("%-70s %-16s %-14s %9s %16s" % ("kernel", "grid", "counter", "dispatches", "mean_per_dispatch"))
         for (name, grid, cn), (c, v) in agg.items():
