@@ -470,7 +470,9 @@ def sweep(args, M, I):
     U(0.2, 5), mu_e/mu_p ~ logU(10, 1000).  Problems of one size form one
     batch (every kernel launch advances the whole batch); the FP32 block
     preconditioner sits inside FP64 FGMRES/Newton; launch shapes come from
-    the autotuner."""
+    the autotuner.  The batches run one after another, or with --concurrent
+    all at once (solve_steady_batches: each batch on a stream and a host
+    thread of its own)."""
     import numpy as np
     import torch
     from paper_0811_4446_amd import autotune
@@ -482,12 +484,15 @@ def sweep(args, M, I):
     sched = schedule(M, args.lin_rtol)
     rows, total_t, total_cycles_bytes = [], 0.0, 0.0
     t_all = time.time()
-    for N in sorted(classes):
-        items = classes[N]
+    # algorithmic bytes of one FP32 block V(2,2) preconditioner cycle per fine
+    # node: 4 collective half-sweep pairs x 36 values, residual 36,
+    # restriction ~3.75, prolongation ~6.75, all levels x 4/3, 4 B each
+    vbytes = (4 * 36 + 36 + 3.75 + 6.75) * 4.0 / 3.0 * 4.0
+
+    def build(N, items, stream):
         z = I.z_cos(N)
-        B = M.Batch(N, N, z, len(items), prec=M.FP32_IR, krylov_m=20)
-        phys = []
-        init = []
+        B = M.Batch(N, N, z, len(items), prec=M.FP32_IR, krylov_m=20, stream=stream)
+        phys, init = [], []
         for q, d in items:
             ph = dict(I.PHYS)
             ph.update(V_top=d["V_top"], mu_e=d["mu_e"], D_e=d["D_e"], mu_p=d["mu_p"], D_p=d["D_p"])
@@ -501,34 +506,57 @@ def sweep(args, M, I):
 
         choice, tim = autotune.tune(B, phys, reset, 1, log=log)
         reset()
-        torch.cuda.synchronize()
-        t0 = time.time()
-        code, reps = B.steady(phys, sched)
-        torch.cuda.synchronize()
-        el = time.time() - t0
+        return B, phys, choice
+
+    def row(N, items, B, reps, el, choice):
         ok = sum(1 for r in reps if r["steps"] > 0 and r["last_change"] < 1e-8)
         cyc = sum(r["vcycles"] for r in reps)
-        nodes = (N + 1) * (N + 1)
-        # algorithmic bytes of one FP32 block V(2,2) preconditioner cycle per
-        # fine node: 4 collective half-sweep pairs x 36 values, residual 36,
-        # restriction ~3.75, prolongation ~6.75, all levels x 4/3, 4 B each
-        vbytes = (4 * 36 + 36 + 3.75 + 6.75) * 4.0 / 3.0 * 4.0
-        total_cycles_bytes += cyc * nodes * vbytes
-        total_t += el
-        rows.append(dict(grid="%dx%d" % (N + 1, N + 1), problems=len(items), converged=ok, code=code,
-                         seconds=round(el, 3), tuning=dict(rows_per_block=choice[0], fuse_max=choice[1]),
-                         steps_mean=float(np.mean([r["steps"] for r in reps])),
-                         ms_per_problem_step=round(1e3 * el / max(1, sum(r["steps"] for r in reps)), 4),
-                         fgmres_total=int(cyc), newton_total=int(sum(r["newton_its"] for r in reps))))
-        log(rows[-1])
-        del B
-        torch.cuda.empty_cache()
+        return dict(grid="%dx%d" % (N + 1, N + 1), problems=len(items), converged=ok,
+                    seconds=None if el is None else round(el, 3),
+                    tuning=dict(rows_per_block=choice[0], fuse_max=choice[1]),
+                    steps_mean=float(np.mean([r["steps"] for r in reps])),
+                    ms_per_problem_step=None if el is None else round(1e3 * el / max(1, sum(r["steps"] for r in reps)), 4),
+                    fgmres_total=int(cyc), newton_total=int(sum(r["newton_its"] for r in reps))), cyc
+
+    if args.concurrent:
+        built = []
+        for N in sorted(classes):
+            B, phys, choice = build(N, classes[N], torch.cuda.Stream())
+            built.append((N, B, phys, choice))
+        torch.cuda.synchronize()
+        t0 = time.time()
+        code, reps_all = M.solve_batches([b[1] for b in built], [b[2] for b in built], sched)
+        torch.cuda.synchronize()
+        total_t = time.time() - t0
+        for (N, B, phys, choice), reps in zip(built, reps_all):
+            r, cyc = row(N, classes[N], B, reps, None, choice)
+            r["code"] = code
+            total_cycles_bytes += cyc * (N + 1) * (N + 1) * vbytes
+            rows.append(r)
+            log(r)
+    else:
+        for N in sorted(classes):
+            B, phys, choice = build(N, classes[N], None)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            code, reps = B.steady(phys, sched)
+            torch.cuda.synchronize()
+            el = time.time() - t0
+            r, cyc = row(N, classes[N], B, reps, el, choice)
+            r["code"] = code
+            total_cycles_bytes += cyc * (N + 1) * (N + 1) * vbytes
+            total_t += el
+            rows.append(r)
+            log(r)
+            del B
+            torch.cuda.empty_cache()
     wall = time.time() - t_all
     out = {"metric": METRIC, "value": round(total_t, 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
            "data": "synthetic",
            "config": {"workload": "parameter sweep of %d independent steady solves, grids 65..513, batched per "
-                                  "grid size, FP32 block preconditioner in FP64 Newton-FGMRES" % args.nprob,
+                                  "grid size (%s), FP32 block preconditioner in FP64 Newton-FGMRES"
+                                  % (args.nprob, "all batches at once" if args.concurrent else "one batch after another"),
                       "solves_per_s": round(args.nprob / total_t, 3), "wall_incl_setup_and_tuning_s": round(wall, 1),
                       "preconditioner_GBps_lower_bound": round(total_cycles_bytes / total_t / 1e9, 1),
                       "classes": rows}}
@@ -819,6 +847,7 @@ def main():
     ap.add_argument("--grid", type=int, default=256, help="finest N (256: 257x257 workload; 1024 for 1025x1025)")
     ap.add_argument("--sweep", action="store_true", help="batched parameter sweep instead of the chain")
     ap.add_argument("--nprob", type=int, default=512)
+    ap.add_argument("--concurrent", action="store_true", help="sweep: all size classes at once (own streams)")
     ap.add_argument("--sweep-ref", type=int, default=0, help="solve this many problems per size class of the "
                                                               "sweep one at a time (reference for the batch)")
     ap.add_argument("--learned", action="store_true", help="learned warm start: train and compare on 257x257")

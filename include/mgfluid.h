@@ -270,6 +270,17 @@ int mg_batch_state(mg_ctx *batch, int32_t p, mg_state *out);
  * worst per-problem status. */
 int solve_steady_batch(mg_ctx *batch, const mg_physics *phys, const mg_schedule *sched, mg_report *reports);
 
+/* Several batches at once (e.g. one per grid size of a parameter sweep with
+ * uneven sizes): solve_steady_batch for every batch, each driven by a host
+ * thread of its own on the device current at its setup, so that the
+ * batches' launches overlap on the GPU when their contexts were set up on
+ * different streams (on one stream they run one after another).  phys[i]
+ * and reports[i] are host arrays of batch i's nprob entries; a batch may
+ * appear once.  Blocks until every batch has finished; returns MG_OK or the
+ * status of the lowest-numbered batch that failed, with its message. */
+int solve_steady_batches(mg_ctx *const *batches, int32_t nbatch, const mg_physics *const *phys,
+                         const mg_schedule *sched, mg_report *const *reports);
+
 /* ---- learned warm start (replaces the coarse-to-fine extrapolation of the
  * multilevel prolongation, Sec. 2) ----
  * Network: four 3x3 convolutions with zero padding, 7 -> 32 -> 32 -> 32 -> 3

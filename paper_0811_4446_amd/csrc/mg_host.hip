@@ -9,6 +9,8 @@
 
 #include <chrono>
 #include <new>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "mg_internal.h"
@@ -419,6 +421,7 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
     c->zhost.assign(desc->z_host, desc->z_host + desc->nz + 1);
     c->desc.z_host = c->zhost.data();
     c->stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
     carve(c, desc, reinterpret_cast<char *>(workspace));
     // debugging switches: per-level launches instead of the fused coarse
     // sub-cycle, eager launches instead of captured graphs
@@ -932,6 +935,40 @@ int solve_steady_batch(mg_ctx *c, const mg_physics *phys, const mg_schedule *sc,
     for (int p = 0; p < c->bt.n; ++p)
         if (!(phys[p].D_e > 0) || !(phys[p].D_p > 0)) return fail(MG_EINVAL, "problem %d: need D > 0", p);
     return batch_solve_steady(c, phys, sc, reports);
+}
+
+int solve_steady_batches(mg_ctx *const *batches, int32_t nbatch, const mg_physics *const *phys,
+                         const mg_schedule *sc, mg_report *const *reports) {
+    if (!batches || !phys || !sc || !reports) return fail(MG_EINVAL, "null argument");
+    if (nbatch < 1 || nbatch > 64) return fail(MG_EINVAL, "nbatch = %d outside 1..64", nbatch);
+    for (int i = 0; i < nbatch; ++i) {
+        if (!batches[i] || !phys[i] || !reports[i]) return fail(MG_EINVAL, "batch %d: null argument", i);
+        if (int e = check_ctx(batches[i])) return e;
+        if (!batches[i]->ws_base) return fail(MG_EINVAL, "batch %d: not a batch context", i);
+        for (int j = 0; j < i; ++j)
+            if (batches[j] == batches[i]) return fail(MG_EINVAL, "batch %d is also batch %d", i, j);
+    }
+    // one host thread per batch, on the batch's device; each thread's status
+    // and error message are collected and the first failing batch reported
+    std::vector<int> status(nbatch, MG_OK);
+    std::vector<std::string> msg(nbatch);
+    std::vector<std::thread> threads;
+    threads.reserve(nbatch);
+    for (int i = 0; i < nbatch; ++i)
+        threads.emplace_back([&, i] {
+            mg_ctx *c = batches[i];
+            if (hipSetDevice(c->device) != hipSuccess) {
+                status[i] = MG_EHIP;
+                msg[i] = "hipSetDevice failed";
+                return;
+            }
+            status[i] = solve_steady_batch(c, phys[i], sc, reports[i]);
+            if (status[i]) msg[i] = mg_last_error();
+        });
+    for (auto &t : threads) t.join();
+    for (int i = 0; i < nbatch; ++i)
+        if (status[i]) return fail(status[i], "batch %d: %s", i, msg[i].c_str());
+    return MG_OK;
 }
 
 int prolong_state(mg_ctx *coarse, const mg_state *src, mg_ctx *fine, mg_state *dst, const mg_physics *ph) {

@@ -298,6 +298,7 @@ struct mg_ctx {
     int nlev = 0;
     mgf::Level lev[mgf::kMaxLevels];
     hipStream_t stream = nullptr;
+    int device = 0;              // HIP device current at setup (the context's work runs there)
     double *partials = nullptr;  // residual-kernel block sums
     double *scal = nullptr;      // device scalars
     double *coarse_scratch = nullptr;

@@ -943,6 +943,7 @@ int batch_setup(const mg_grid_desc *d, int nprob, void *workspace, int64_t bytes
     c->zhost.assign(d->z_host, d->z_host + d->nz + 1);
     c->desc.z_host = c->zhost.data();
     c->stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
     char *base = reinterpret_cast<char *>(workspace);
     carve_ctx(c, d, base);
     c->nw.fuse = getenv("MGF_NO_FUSE") == nullptr;

@@ -94,6 +94,8 @@ SIGNATURES = {
     "mg_batch_state": (ctypes.c_int, [_VP, _I32, ctypes.POINTER(State)]),
     "solve_steady_batch": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(Schedule),
                                           ctypes.POINTER(Report)]),
+    "solve_steady_batches": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, ctypes.POINTER(_VP), ctypes.POINTER(Schedule),
+                                            ctypes.POINTER(_VP)]),
     "mg_set_tuning": (ctypes.c_int, [_VP, _I32, _I32]),
     "mg_steady_residual": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _PD]),
     "mg_boundary_flow": (ctypes.c_int, [_VP, ctypes.POINTER(Physics), ctypes.POINTER(State), _PD]),
@@ -344,9 +346,12 @@ class Batch:
             self.views.append(v)
 
     def set_problem(self, p, V, ne, np_, S):
-        for name, arr in (("V", V), ("ne", ne), ("np", np_), ("Se", S), ("Sp", S)):
-            t = self.views[p][name]
-            t[:, : self.nz + 1] = torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float64)).to(self.device)
+        # on the batch's stream, so that its solve sees the values whatever
+        # stream is current
+        with torch.cuda.stream(self.stream):
+            for name, arr in (("V", V), ("ne", ne), ("np", np_), ("Se", S), ("Sp", S)):
+                t = self.views[p][name]
+                t[:, : self.nz + 1] = torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float64)).to(self.device)
 
     def get(self, p, name):
         torch.cuda.synchronize(self.device)
@@ -371,6 +376,21 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def solve_batches(batches, phys_lists, sched):
+    """Steady solves of several batches at once (solve_steady_batches): the
+    library drives each batch from a host thread of its own, so batches set
+    up on different streams overlap on the GPU.  Returns (code, per-batch
+    report lists)."""
+    n = len(batches)
+    ctxs = (_VP * n)(*[b.ctx.value for b in batches])
+    Ps = [(Physics * b.n)(*pl) for b, pl in zip(batches, phys_lists)]
+    Rs = [(Report * b.n)() for b in batches]
+    parr = (_VP * n)(*[ctypes.cast(P, _VP).value for P in Ps])
+    rarr = (_VP * n)(*[ctypes.cast(R, _VP).value for R in Rs])
+    code = lib().solve_steady_batches(ctxs, n, parr, ctypes.byref(sched), rarr)
+    return code, [[R[i].as_dict() for i in range(b.n)] for b, R in zip(batches, Rs)]
 
 
 class Net:

@@ -81,6 +81,7 @@ def test_null_arguments_fail_before_device_work():
     assert lib.vcycle(None, 0, None, 1, None) == -1
     assert lib.sg_assemble(None, 0, None, None, 0.0) == -1
     assert lib.solve_steady(None, None, None, None, None) == -1
+    assert lib.solve_steady_batches(None, 0, None, None, None) == -1
     assert b"null" in lib.mg_last_error()
 
 

@@ -108,3 +108,42 @@ def test_every_launch_shape_gives_the_same_step():
                 ref = res
             for a, b in zip(res, ref):
                 assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max(), (ty, fm)
+
+
+def test_concurrent_batches_of_uneven_sizes_equal_separate_solves():
+    """Batches of different grid sizes (17x17 x 3 and 33x33 x 2), each on a
+    stream of its own, solved together by solve_steady_batches (one host
+    thread per batch): every problem ends bit for bit where its batch ends
+    when solved alone."""
+    _say("concurrent batches 17x3 + 33x2")
+    import torch
+    m = M()
+    sc = m.schedule(coupling=m.NEWTON, lin_rtol=1e-3, max_cycles=200, newton_tol=1e-6, steady_tol=1e-8,
+                    max_steps=3000)
+    specs = [(16, 3, 777), (32, 2, 778)]
+
+    def make(streams):
+        out = []
+        for (N, nprob, seed), stream in zip(specs, streams):
+            B = m.Batch(N, N, I.z_cos(N), nprob, prec=1, krylov_m=20, stream=stream)
+            probs = _draw(N, nprob, seed)
+            for p, (phys, V, ne, np_, S) in enumerate(probs):
+                B.set_problem(p, V, ne, np_, S)
+            out.append((B, [m.Physics.of(pr[0]) for pr in probs]))
+        return out
+
+    alone = []
+    for B, phys in make([None, None]):
+        code, reps = B.steady(phys, sc)
+        assert code == 0, m.lib().mg_last_error()
+        alone.append((reps, {(p, k): B.get(p, k) for p in range(B.n) for k in ("V", "ne", "np")}))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    both = make(streams)
+    code, reps_all = m.solve_batches([b for b, _ in both], [ph for _, ph in both], sc)
+    assert code == 0, m.lib().mg_last_error()
+    for (B, _), reps, (reps1, fields1) in zip(both, reps_all, alone):
+        for p in range(B.n):
+            assert reps[p]["steps"] == reps1[p]["steps"] and reps[p]["vcycles"] == reps1[p]["vcycles"], (reps[p],
+                                                                                                  reps1[p])
+            for k in ("V", "ne", "np"):
+                assert np.array_equal(B.get(p, k), fields1[(p, k)]), (B.nr, p, k)
