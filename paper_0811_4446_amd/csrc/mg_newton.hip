@@ -1327,6 +1327,48 @@ struct SubMem<T, true> {
     }
 };
 
+// nsweeps collective red-black sweeps of one level inside the sub-cycle's
+// workgroup.  When every node of the level has a thread of its own, that
+// thread loads its Jacobian row and factors once and keeps them in
+// registers over all the half-sweeps (the arithmetic of block_gs_node);
+// otherwise block_gs_node per node and half-sweep.
+template <class T>
+inline __device__ void subcycle_smooth(const Geom &g, const BOpT<T> &J, const T *f, T *x, int nsweeps) {
+    const int nodes = (g.nr + 1) * (g.nz + 1), nt = blockDim.x;
+    if (nodes <= nt) {
+        const int t = threadIdx.x, i = t / (g.nz + 1), j = t % (g.nz + 1);
+        const bool mine = t < nodes && j >= 1 && j < g.nz;
+        const int64_t p = mine ? at(g, i, j) : 0, plane = J.plane;
+        NodeRow<T> R;
+        if (mine) {
+            load_row(J, f, p, R);
+            factor_row(R);
+        }
+        const int64_t nbp[4] = {p - g.pitch, p + g.pitch, p - 1, p + 1};
+        const bool has[4] = {i > 0, i < g.nr, true, true};
+        for (int s = 0; s < nsweeps; ++s)
+            for (int col = 0; col < 2; ++col) {
+                if (mine && ((i + j) & 1) == col) {
+                    T oe, op, ov;
+                    solve_row(R, has, [&](int k, int c) { return x[nbp[k] + c * plane]; }, oe, op, ov);
+                    x[p] = oe;
+                    x[p + plane] = op;
+                    x[p + 2 * plane] = ov;
+                }
+                __syncthreads();
+            }
+        return;
+    }
+    for (int s = 0; s < nsweeps; ++s)
+        for (int col = 0; col < 2; ++col) {
+            for (int t = threadIdx.x; t < nodes; t += nt) {
+                const int i = t / (g.nz + 1), j = t % (g.nz + 1);
+                if (j >= 1 && j < g.nz && ((i + j) & 1) == col) block_gs_node(g, J, f, x, i, j);
+            }
+            __syncthreads();
+        }
+}
+
 // The coarse end of the block V-cycle in one workgroup: levels 0..n-1 of
 // `F` (the last is the coarsest) are small enough that per-level launches
 // would cost more than the work, so one workgroup runs their smoothing,
@@ -1386,14 +1428,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
         T *r = rof(q);
         const int nodes = (g.nr + 1) * (g.nz + 1);
         // every level's correction starts from zero (set while staging)
-        for (int s = 0; s < F.nu1; ++s)
-            for (int col = 0; col < 2; ++col) {
-                for (int t = threadIdx.x; t < nodes; t += nt) {
-                    int i = t / (g.nz + 1), j = t % (g.nz + 1);
-                    if (j >= 1 && j < g.nz && ((i + j) & 1) == col) block_gs_node(g, J, f, x, i, j);
-                }
-                __syncthreads();
-            }
+        subcycle_smooth(g, J, f, x, F.nu1);
         for (int t = threadIdx.x; t < nodes; t += nt) {
             int i = t / (g.nz + 1), j = t % (g.nz + 1);
             block_residual_node(g, J, f, x, r, 0, i, j);
@@ -1429,14 +1464,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
             if (j >= 1 && j < g.nz) prolong3_node(g, x, J.plane, gc, xc, M.xplane(q + 1), i, j);
         }
         __syncthreads();
-        for (int s = 0; s < F.nu2; ++s)
-            for (int col = 0; col < 2; ++col) {
-                for (int t = threadIdx.x; t < nodes; t += nt) {
-                    int i = t / (g.nz + 1), j = t % (g.nz + 1);
-                    if (j >= 1 && j < g.nz && ((i + j) & 1) == col) block_gs_node(g, J, f, x, i, j);
-                }
-                __syncthreads();
-            }
+        subcycle_smooth(g, J, f, x, F.nu2);
     }
     if constexpr (kLds) {
         __syncthreads();

@@ -53,13 +53,13 @@ def steady_properties(N, phys, V, ne, np_, S):
 
 def test_bench_257_chain_ends_steady():
     """bench.py's timed workload for V_top = 1: chain 65 -> 129 -> 257 with
-    FP64 preconditioner, FGMRES to 1e-3 inside Newton, stop at relative
+    FP64 preconditioner, FGMRES to bench.LIN_RTOL inside Newton, stop at relative
     change 1e-8 per step."""
     _say("bench workload 257 V_top=1")
     import bench
     m = M()
-    fine, t, P, info = bench.chain_to(m, I, 256, 1.0, 1e-3)
-    code, rep = fine.steady(P, fine.state(t[0], t[1], t[2], t[3], t[3]), bench.schedule(m, 1e-3))
+    fine, t, P, info = bench.chain_to(m, I, 256, 1.0, bench.LIN_RTOL)
+    code, rep = fine.steady(P, fine.state(t[0], t[1], t[2], t[3], t[3]), bench.schedule(m, bench.LIN_RTOL))
     assert code == 0 and rep.last_change < 1e-8
     phys = dict(I.PHYS)
     phys["V_top"] = 1.0
@@ -76,9 +76,9 @@ def test_bench_1025_fp32_preconditioner_ends_steady():
     _say("bench workload 1025 fp32 V_top=1")
     import bench
     m = M()
-    fine, t, P, info = bench.chain_to(m, I, 1024, 1.0, 1e-3)
+    fine, t, P, info = bench.chain_to(m, I, 1024, 1.0, bench.LIN_RTOL)
     sol = m.Solver(1024, 1024, I.z_cos(1024), krylov_m=30, coarsest=4, prec=m.FP32_IR)
-    code, rep = sol.steady(P, sol.state(t[0], t[1], t[2], t[3], t[3]), bench.schedule(m, 1e-3))
+    code, rep = sol.steady(P, sol.state(t[0], t[1], t[2], t[3], t[3]), bench.schedule(m, bench.LIN_RTOL))
     assert code == 0 and rep.last_change < 1e-8
     phys = dict(I.PHYS)
     phys["V_top"] = 1.0
@@ -107,7 +107,7 @@ def test_sweep_batch_problems_end_steady():
         phys.append(ph)
         ne = I.initial_density(N, N, 1000 + q)
         B.set_problem(p, I.initial_potential(N, N, z, 0.0, ph["V_top"]), ne, ne.copy(), I.source(N, N, z))
-    code, reps = B.steady([m.Physics.of(ph) for ph in phys], bench.schedule(m, 1e-3))
+    code, reps = B.steady([m.Physics.of(ph) for ph in phys], bench.schedule(m, bench.LIN_RTOL))
     assert code == 0
     S = I.source(N, N, z)
     for p, ph in enumerate(phys):
@@ -116,3 +116,29 @@ def test_sweep_batch_problems_end_steady():
         print("problem", p, "steps", reps[p]["steps"], "residual", res, "balance", bal)
         assert max(res.values()) < 1e-5
         assert max(bal.values()) < 1e-5
+
+
+def test_bench_linear_tolerance_keeps_the_steady_state():
+    """The benchmark's inexact-Newton tolerance (bench.LIN_RTOL for every
+    FGMRES solve) against FGMRES to 1e-10, from the same prolonged 257x257
+    state (V_top = 1): the same accepted steps and a final state within 1e-9
+    relative per field."""
+    _say("bench tolerance vs tight solves 257")
+    import bench
+    import torch
+    m = M()
+    fine, t, P, info = bench.chain_to(m, I, 256, 1.0, bench.LIN_RTOL)
+    init = [x.clone() for x in t[:3]]
+    out = {}
+    for rt in (bench.LIN_RTOL, 1e-10):
+        tt = [x.clone() for x in init] + [t[3]]
+        code, rep = fine.steady(P, fine.state(tt[0], tt[1], tt[2], tt[3], tt[3]), bench.schedule(m, rt))
+        assert code == 0
+        torch.cuda.synchronize()
+        out[rt] = (rep.steps, [fine.download(x) for x in tt[:3]])
+    steps, fields = out[bench.LIN_RTOL]
+    steps_t, fields_t = out[1e-10]
+    errs = [float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(fields, fields_t)]
+    print("257: steps %d / %d, max rel diff per field %s" % (steps, steps_t, errs))
+    assert steps == steps_t
+    assert max(errs) <= 1e-9, errs
