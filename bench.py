@@ -840,6 +840,27 @@ def fig1(args, M, I):
           flush=True)
 
 
+def network(args, M):
+    """Throughput of the warm-start network's kernels with random weights at
+    257x257 (the timings do not depend on the weights)."""
+    import numpy as np
+    from paper_0811_4446_amd import warmstart as WS
+    rng = np.random.default_rng(0)
+    p = []
+    for ci, co in [(7, 32), (32, 32), (32, 32), (32, 3)]:
+        p.append(rng.normal(size=co * ci * 9) * np.sqrt(2.0 / (9 * ci)))
+        p.append(rng.normal(size=co) * 0.1)
+    net = M.Net(np.concatenate(p))
+    rows = [WS.network_throughput(net, B=b, H=257, W=257) for b in (1, 8)]
+    for r in rows:
+        log("network throughput: %s" % r)
+    f8 = rows[1]
+    print(json.dumps({"metric": "warm-start network forward throughput", "value": f8["forward_tflops"],
+                      "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16",
+                      "data": "synthetic", "config": {"workload": "4-layer 3x3 CNN 7-32-32-32-3 at 257x257",
+                                                      "rows": rows}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -878,6 +899,8 @@ def main():
     ap.add_argument("--fig1-rgrids", type=str, default="16,32",
                     help="N values of the relaxation-only runs (65x65 and above take minutes)")
     ap.add_argument("--fig1-rmax-cycles", type=int, default=20000, help="FGMRES iterations per Newton, R runs")
+    ap.add_argument("--network", action="store_true",
+                    help="warm-start network alone: forward (batch 1 and 8) and gradient (batch 8) at 257x257")
     ap.add_argument("--prec", choices=["fp64", "fp32", "both"], default="fp64",
                     help="block preconditioner precision (FGMRES and Newton stay FP64)")
     args = ap.parse_args()
@@ -902,6 +925,8 @@ def main():
         return sweep(args, M, I)
     if args.learned:
         return learned(args, M, I)
+    if args.network:
+        return network(args, M)
     if args.fig1:
         return fig1(args, M, I)
     if args.argon:

@@ -284,12 +284,19 @@ int solve_steady_batches(mg_ctx *const *batches, int32_t nbatch, const mg_physic
 /* ---- learned warm start (replaces the coarse-to-fine extrapolation of the
  * multilevel prolongation, Sec. 2) ----
  * Network: four 3x3 convolutions with zero padding, 7 -> 32 -> 32 -> 32 -> 3
- * channels, exact-erf GELU after the first three.  Parameters: one FP32
+ * channels, GELU in its erf form (z Phi(z), not the tanh approximation;
+ * Phi evaluated in FP32 to 2.4e-6 relative) after the first three.
+ * Parameters: one FP32
  * device array of wn_param_count() values, per layer W[co][ci][3][3] then
  * b[co].  Images are FP32 NCHW: inputs [B][7][H][W], outputs and targets
  * [B][3][H][W], with H = nr+1 (radial nodes) and W = nz+1 (axial nodes).
  * The convolutions run in bf16 on MFMA with FP32 accumulation.  `scratch`
  * is caller-allocated device memory of wn_scratch_bytes(B, H, W) bytes.
+ * wn_forward runs the four layers in one kernel per 16 x 16 output tile with
+ * the activations on chip (batches beyond 2^24 such tiles return
+ * MG_EINVAL); wn_grad and wn_train_step store every layer's activations in
+ * scratch for the backward pass, so their forward outputs can differ from
+ * wn_forward's in the last bf16 bits (summation order of the first layer).
  * All calls are asynchronous on `stream` unless they return a loss. */
 int wn_param_count(void);
 int wn_scratch_bytes(int32_t B, int32_t H, int32_t W, int64_t *bytes);
@@ -306,13 +313,15 @@ int wn_train_step(float *params, float *adam_m, float *adam_v, int32_t step, flo
                   int64_t scratch_bytes, void *stream);
 /* wn_forward without a scratch argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
- * harnesses that forbid allocation): the activations live in one static
- * device array per GPU (about 17 MB, held until the process ends), so the
- * call allocates nothing.  Limit: B*H*W <= 66049 (one 257x257 image);
- * larger batches return MG_EINVAL.  Same kernels and results as wn_forward
- * (bitwise).  Calls that overlap on one GPU share that array and race:
- * serialise them (one stream, or events).  Call with the stream's device
- * current; the first call on a device looks up its array's address. */
+ * harnesses that forbid allocation): the packed bf16 weights live in one
+ * static device array per GPU (155 KB, held until the process ends), so the
+ * call allocates nothing.  The forward pass keeps its activations on chip,
+ * so the array does not grow with the image: any batch of at most 2^24
+ * tiles of 16 x 16 pixels is accepted, larger ones return MG_EINVAL.  Same
+ * kernels and results as wn_forward (bitwise).  Calls that overlap on one
+ * GPU share that array and race: serialise them (one stream, or events).
+ * Call with the stream's device current; the first call on a device looks
+ * up its array's address. */
 int wn_forward_noalloc(const float *params, const float *in, float *out, int32_t B, int32_t H, int32_t W,
                        void *stream);
 /* Input planes of one sample (out: [7][H][W]) from the prolonged coarse

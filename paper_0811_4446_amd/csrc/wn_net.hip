@@ -1,5 +1,5 @@
 // Learned warm start: a 4-layer 3x3 convolutional network (7 -> 32 -> 32 ->
-// 32 -> 3 channels, exact-erf GELU after the first three layers, zero
+// 32 -> 3 channels, erf-form GELU after the first three layers, zero
 // padding) that maps the prolonged coarse steady state (plus coordinate and
 // parameter planes) to a correction of it on the fine grid.  Forward and
 // input-gradient convolutions run on MFMA (v_mfma_f32_16x16x32_bf16: bf16
@@ -37,17 +37,50 @@ inline __host__ __device__ int64_t param_offset(int l) {
     return off;
 }
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU with the exact normal CDF, Phi(z) = erfc(-z / sqrt 2) / 2.  erfc is
+// the Chebyshev fit of Press et al. (Numerical Recipes, sec. 6.2): erfc(u) =
+// t exp(-u^2 + P(t)), t = 1 / (1 + u/2), u >= 0, relative error below 1.2e-7
+// for every u, and erfc(-u) = 2 - erfc(u).  One branch-free path of ~15
+// vector instructions (hardware reciprocal and exp2), against ~40 with both
+// branches of the library erff; with FP32 rounding the result stays within
+// 2.4e-6 relative (|z| <= 5) and 4e-7 absolute of the exact GELU, far below
+// the bf16 rounding of the stored activations.
+__device__ inline float half_erfc_fit(float u) {  // erfc(u) / 2, u >= 0
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, u, 1.0f));
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    return 0.5f * t * __builtin_amdgcn_exp2f(fmaf(-u, u, p) * 1.44269504088896341f);
+}
+__device__ inline float normal_cdf(float z) {
+    const float h = half_erfc_fit(fabsf(z) * 0.70710678118654752f);
+    return z >= 0.0f ? 1.0f - h : h;
+}
+__device__ inline float gelu(float z) { return z * normal_cdf(z); }
 __device__ inline float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return normal_cdf(z) + z * __builtin_amdgcn_exp2f(-0.5f * 1.44269504088896341f * z * z) * 0.39894228040143268f;
 }
 
 // params (FP32, per layer W[co][ci][3][3] then b[co]) -> bf16 weight
 // tiles: WB[l][tap][co][ci] for the forward pass and WT[l][tap'][ci][co]
 // (taps mirrored) for the input gradient; biases copied to FP32 [l][32].
+// WF0 (may be null): the first layer with its taps folded into K for the
+// fused forward pass, [co][8 * tap + ci], 96 slots per row, zero for ci = 7
+// and tap >= 9.
 __global__ void k_pack_weights(const float *__restrict__ params, __bf16 *__restrict__ WB, __bf16 *__restrict__ WT,
-                               float *__restrict__ bias) {
+                               float *__restrict__ bias, __bf16 *__restrict__ WF0) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;  // over 4 * 9 * 32 * 32
+    if (WF0 && t < kC * 96) {
+        int co = t / 96, tap = (t % 96) / 8, ci = t % 8;
+        WF0[t] = (__bf16)((tap < 9 && ci < 7) ? params[((int64_t)co * 7 + ci) * 9 + tap] : 0.0f);
+    }
     if (t >= 4 * 9 * kC * kC) return;
     int l = t / (9 * kC * kC), r = t % (9 * kC * kC);
     int tap = r / (kC * kC), co = (r / kC) % kC, ci = r % kC;
@@ -130,6 +163,257 @@ __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ in, 
                 if (co < 3) out_f[(((int64_t)b * 3 + co) * H + y) * W + px] = v + bias[co];
             } else {
                 out_act[pix * kC + co] = (__bf16)(v * gelu_grad(zprev[pix * kC + co]));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused forward pass (inference): one workgroup computes all four layers for
+// a kFT x kFT tile of output pixels of one image and keeps every
+// intermediate activation in LDS, so the only HBM traffic is the 7 input
+// planes (with a 4-pixel halo) and the 3 output planes.  Layer l's region is
+// the output tile grown by 3 - l pixels on each side; pixels of a region
+// outside the image hold zero, which is the zero padding of every layer.
+//
+// The MFMA computes D (output channels x 16 pixels) = W (channels x K) *
+// X (K x 16 pixels): lane (m, kg) supplies W[m][8kg..8kg+7] and the 8-channel
+// chunk kg of pixel m, and receives channels 4kg..4kg+3 of pixel m.  The
+// first layer (7 input channels) folds its nine taps into K: k = 8 * tap +
+// ci, 96 slots, three MFMAs per 16 output channels instead of nine.
+//
+// LDS activations are chunk planes: plane j holds channels 8j..8j+7 of every
+// pixel of the region as one 16-byte record, so the 16 lanes that read one
+// chunk of 16 consecutive pixels touch 256 contiguous bytes.
+// ---------------------------------------------------------------------------
+constexpr int kFT = 16;            // output tile side
+constexpr int kFIn = kFT + 8;      // input region side
+constexpr int kFThreads = 256;     // four waves
+constexpr int kFK0 = 96;           // folded K of the first layer (12 taps x 8 channel slots)
+constexpr int kFBufA = 4 * (kFT + 6) * (kFT + 6);  // 16-byte records: layer-1 output, then layer-3 output
+constexpr int kFBufB = 4 * (kFT + 4) * (kFT + 4);  // layer-2 output; the input planes before it
+static_assert(kFIn * kFIn <= kFBufB, "input planes must fit in the layer-2 buffer");
+static_assert(4 * (kFT + 2) * (kFT + 2) <= kFBufA, "layer-3 output must fit in the first buffer");
+
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
+// Bias plus GELU (or zero outside the image) of the four channels a lane
+// holds, packed for one 8-byte LDS store.
+__device__ inline bf16x4 fused_act(f32x4 acc, const float *b4, bool inside) {
+    bf16x4 o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = (__bf16)(inside ? gelu(acc[i] + b4[i]) : 0.0f);
+    return o;
+}
+
+// Pixel p of a region of side S (clamped to the region's last pixel when p
+// lies past it, so that every LDS address stays inside the region).
+template <int S>
+__device__ inline void region_rc(int p, int &r, int &c) {
+    const int pc = p < S * S ? p : S * S - 1;
+    r = pc / S;
+    c = pc % S;
+}
+
+// One hidden 32 -> 32 layer over a region of side S (input region side
+// S + 2, chunk-plane stride (S + 2)^2; output chunk-plane stride S^2).
+// (oy, ox): image coordinates of the output region's first pixel.  A wave
+// takes two blocks of 16 pixels at a time (blk and blk + 4), so four
+// independent MFMA chains are in flight and one block's GELU overlaps the
+// other's; a block past the region is computed but not stored.
+template <int S>
+__device__ inline void fused_hidden(const bf16x8 *__restrict__ src, bf16x4 *__restrict__ dst,
+                                    const bf16x8 (&w)[9][2], const float (&b)[2][4], int oy, int ox, int H, int W,
+                                    int wave, int m, int kg) {
+    constexpr int SI = S + 2, NI = SI * SI, NO = S * S, NB = (NO + 15) / 16, NW = kFThreads / 64;
+    for (int blk = wave; blk < NB; blk += 2 * NW) {
+        const int p = blk * 16 + m, q = (blk + NW) * 16 + m;
+        int rp, cp, rq, cq;
+        region_rc<S>(p, rp, cp);
+        region_rc<S>(q, rq, cq);
+        const bf16x8 *sp = src + kg * NI + rp * SI + cp;
+        const bf16x8 *sq = src + kg * NI + rq * SI + cq;
+        f32x4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0}, e0 = {0, 0, 0, 0}, e1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const bf16x8 x = sp[(tap / 3) * SI + tap % 3];
+            const bf16x8 y = sq[(tap / 3) * SI + tap % 3];
+            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[tap][0], x, a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[tap][1], x, a1, 0, 0, 0);
+            e0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[tap][0], y, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[tap][1], y, e1, 0, 0, 0);
+        }
+        // channels 4kg..4kg+3 (+16): plane (kg >> 1) (+2), half kg & 1
+        if (p < NO) {
+            const int gy = oy + rp, gx = ox + cp;
+            const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            dst[((kg >> 1) * NO + p) * 2 + (kg & 1)] = fused_act(a0, b[0], inside);
+            dst[((2 + (kg >> 1)) * NO + p) * 2 + (kg & 1)] = fused_act(a1, b[1], inside);
+        }
+        if (q < NO) {
+            const int gy = oy + rq, gx = ox + cq;
+            const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            dst[((kg >> 1) * NO + q) * 2 + (kg & 1)] = fused_act(e0, b[0], inside);
+            dst[((2 + (kg >> 1)) * NO + q) * 2 + (kg & 1)] = fused_act(e1, b[1], inside);
+        }
+    }
+}
+
+__device__ inline void load_hidden_weights(const __bf16 *__restrict__ wl, int m, int kg, bf16x8 (&w)[9][2]) {
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            w[tap][h] = *reinterpret_cast<const bf16x8 *>(wl + ((int64_t)tap * kC + 16 * h + m) * kC + 8 * kg);
+}
+
+__device__ inline void load_bias(const float *__restrict__ bl, int kg, float (&b)[2][4]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[h][i] = bl[16 * h + 4 * kg + i];
+}
+
+// in: FP32 NCHW [B][7][H][W]; WF0: first layer [32][96] bf16 (k = 8 * tap +
+// ci); WB: [4][9][32][32] bf16 ([layer][tap][co][ci], layer 0 unused);
+// bias: FP32 [4][32]; out: FP32 NCHW [B][3][H][W].  Tiles are numbered
+// (image, tile row, tile column); workgroup g takes tiles g, g + gridDim.x,
+// ...  Keeping the two hidden layers' weights resident across tiles would
+// need 296 registers per lane, one wave per SIMD instead of two, so each
+// layer's weights (up to 72 registers per lane) are reloaded per tile.
+__global__ __launch_bounds__(kFThreads) void k_wn_forward_fused(const float *__restrict__ in,
+                                                               const __bf16 *__restrict__ WF0,
+                                                               const __bf16 *__restrict__ WB,
+                                                               const float *__restrict__ bias, int B, int H, int W,
+                                                               float *__restrict__ out) {
+    __shared__ bf16x8 bufA[kFBufA];
+    __shared__ bf16x8 bufB[kFBufB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    const int tiles_x = (W + kFT - 1) / kFT, tiles_y = (H + kFT - 1) / kFT;
+    const int64_t ntiles = (int64_t)B * tiles_x * tiles_y;
+    float bl[2][4];
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tx = (int)(tile % tiles_x);
+        const int ty = (int)((tile / tiles_x) % tiles_y);
+        const int b = (int)(tile / ((int64_t)tiles_x * tiles_y));
+        const int y0 = ty * kFT, x0 = tx * kFT;
+        // The weight pointer is made opaque per tile so that the compiler
+        // does not hoist every layer's weight loads out of the tile loop
+        // (all four layers' fragments at once would not fit two waves per
+        // SIMD); each layer's are loaded while the layer before it runs.
+        const __bf16 *wb = WB;
+        asm volatile("" : "+s"(wb));
+
+        // First-layer weights: A fragments of the folded K.
+        bf16x8 w0[3][2];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                w0[j][h] = *reinterpret_cast<const bf16x8 *>(WF0 + (int64_t)(16 * h + m) * kFK0 + 32 * j + 8 * kg);
+        load_bias(bias, kg, bl);
+        bf16x8 w1[9][2];
+        load_hidden_weights(wb + (int64_t)1 * 9 * kC * kC, m, kg, w1);
+
+        // Input planes of the region (side kFIn, origin (y0 - 4, x0 - 4))
+        // as bf16 records of 8 channel slots (the eighth is zero) in bufB.
+        // The previous tile's last reads of bufB ended at its third barrier.
+        for (int q = tid; q < kFIn * kFIn; q += kFThreads) {
+            const int gy = y0 - 4 + q / kFIn, gx = x0 - 4 + q % kFIn;
+            bf16x8 v = {};
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                const float *src = in + ((int64_t)b * 7 * H + gy) * W + gx;
+#pragma unroll
+                for (int ci = 0; ci < 7; ++ci) v[ci] = (__bf16)src[(int64_t)ci * H * W];
+            }
+            bufB[q] = v;
+        }
+        __syncthreads();
+
+        // Layer 1: 7 -> 32 over side kFT + 6, taps folded into K; two
+        // blocks of 16 pixels per wave at a time, as in fused_hidden.
+        {
+            constexpr int S = kFT + 6, NO = S * S, NB = (NO + 15) / 16, NW = kFThreads / 64;
+            bf16x4 *dst = reinterpret_cast<bf16x4 *>(bufA);
+            const bf16x8 zero8 = {};
+            for (int blk = wave; blk < NB; blk += 2 * NW) {
+                const int p = blk * 16 + m, q = (blk + NW) * 16 + m;
+                int rp, cp, rq, cq;
+                region_rc<S>(p, rp, cp);
+                region_rc<S>(q, rq, cq);
+                f32x4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0}, e0 = {0, 0, 0, 0}, e1 = {0, 0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int tap = 4 * j + kg;
+                    const int off = (tap / 3) * kFIn + tap % 3;
+                    const bf16x8 x = tap < 9 ? bufB[rp * kFIn + cp + off] : zero8;
+                    const bf16x8 y = tap < 9 ? bufB[rq * kFIn + cq + off] : zero8;
+                    a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0[j][0], x, a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0[j][1], x, a1, 0, 0, 0);
+                    e0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0[j][0], y, e0, 0, 0, 0);
+                    e1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0[j][1], y, e1, 0, 0, 0);
+                }
+                if (p < NO) {
+                    const int gy = y0 - 3 + rp, gx = x0 - 3 + cp;
+                    const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+                    dst[((kg >> 1) * NO + p) * 2 + (kg & 1)] = fused_act(a0, bl[0], inside);
+                    dst[((2 + (kg >> 1)) * NO + p) * 2 + (kg & 1)] = fused_act(a1, bl[1], inside);
+                }
+                if (q < NO) {
+                    const int gy = y0 - 3 + rq, gx = x0 - 3 + cq;
+                    const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+                    dst[((kg >> 1) * NO + q) * 2 + (kg & 1)] = fused_act(e0, bl[0], inside);
+                    dst[((2 + (kg >> 1)) * NO + q) * 2 + (kg & 1)] = fused_act(e1, bl[1], inside);
+                }
+            }
+        }
+        load_bias(bias + kC, kg, bl);
+        bf16x8 w2[9][2];
+        load_hidden_weights(wb + (int64_t)2 * 9 * kC * kC, m, kg, w2);
+        __syncthreads();
+
+        // Layer 2: bufA (side kFT + 6) -> bufB (side kFT + 4).
+        fused_hidden<kFT + 4>(bufA, reinterpret_cast<bf16x4 *>(bufB), w1, bl, y0 - 2, x0 - 2, H, W, wave, m, kg);
+        load_bias(bias + 2 * kC, kg, bl);
+        bf16x8 w3[9];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+            w3[tap] = *reinterpret_cast<const bf16x8 *>(wb + (((int64_t)3 * 9 + tap) * kC + m) * kC + 8 * kg);
+        __syncthreads();
+
+        // Layer 3: bufB (side kFT + 4) -> bufA (side kFT + 2).
+        fused_hidden<kFT + 2>(bufB, reinterpret_cast<bf16x4 *>(bufA), w2, bl, y0 - 1, x0 - 1, H, W, wave, m, kg);
+        __syncthreads();
+
+        // Layer 4: 32 -> 3 over the output tile; output channels 0..15 on
+        // one MFMA (3 real), lanes kg == 0 hold channels 0..3.  The next
+        // tile's first layer writes bufA only after its staging barrier,
+        // which every wave reaches after these reads.
+        {
+            constexpr int S = kFT, SI = S + 2, NI = SI * SI, NB = S * S / 16;
+            float b3[3];
+#pragma unroll
+            for (int co = 0; co < 3; ++co) b3[co] = bias[3 * kC + co];
+            for (int blk = wave; blk < NB; blk += kFThreads / 64) {
+                const int p = blk * 16 + m;
+                const int r = p / S, c = p % S;
+                const bf16x8 *s0 = bufA + kg * NI + r * SI + c;
+                f32x4 a = {0, 0, 0, 0}, e = {0, 0, 0, 0};
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) {
+                    if (tap < 5)
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[tap], s0[(tap / 3) * SI + tap % 3], a, 0, 0, 0);
+                    else
+                        e = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[tap], s0[(tap / 3) * SI + tap % 3], e, 0, 0, 0);
+                }
+                a += e;
+                const int gy = y0 + r, gx = x0 + c;
+                if (kg == 0 && gy < H && gx < W) {
+#pragma unroll
+                    for (int co = 0; co < 3; ++co) out[(((int64_t)b * 3 + co) * H + gy) * W + gx] = a[co] + b3[co];
+                }
             }
         }
     }
@@ -254,21 +538,31 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
     if (wave == 0 && lane < kC) o[9 * kC * kC + lane] = accb;
 }
 
-// grad (param layout of layer l) = sum over workgroups of the partials.
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwg, int ci_real, int co_real,
-                               float *__restrict__ grad) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+// grad (param layout of layer l) = sum over workgroups of the partials.  A
+// workgroup owns 64 consecutive entries e; wave w adds the partials of
+// workgroups w, w + 4, w + 8, ... in eight interleaved running sums, and the
+// four waves' sums are combined in a fixed order, so the result does not
+// depend on scheduling.  (One thread per entry over all partials used only
+// 37 workgroups and ran at ~0.5 TB/s.)
+constexpr int kWrEntries = 64;
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part, int nwg, int ci_real,
+                                                      int co_real, float *__restrict__ grad) {
+    __shared__ float sums[4][kWrEntries];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int E = 9 * kC * kC + kC;
-    if (e >= E) return;
-    // eight independent running sums (workgroups g = k mod 8), combined in a
-    // fixed order: the loads overlap instead of waiting on one add chain
+    const int e = blockIdx.x * kWrEntries + lane;
     float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int g = 0;
-    for (; g + 8 <= nwg; g += 8)
+    if (e < E) {
+        int g = wave, k = 0;
+        for (; g + 28 < nwg; g += 32)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] += part[(int64_t)(g + k) * E + e];
-    for (int k = 0; g < nwg; ++g, ++k) acc[k] += part[(int64_t)g * E + e];
-    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+            for (int u = 0; u < 8; ++u) acc[u] += part[(int64_t)(g + 4 * u) * E + e];
+        for (; g < nwg; g += 4, k = (k + 1) & 7) acc[k] += part[(int64_t)g * E + e];
+    }
+    sums[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    if (wave != 0 || e >= E) return;
+    const float s = (sums[0][lane] + sums[1][lane]) + (sums[2][lane] + sums[3][lane]);
     if (e < 9 * kC * kC) {
         int co = e / (kC * 9), ci = (e / 9) % kC, tap = e % 9;
         if (co < co_real && ci < ci_real) grad[((int64_t)co * ci_real + ci) * 9 + tap] = s;
@@ -305,7 +599,7 @@ __global__ void k_sum_double(const double *__restrict__ part, int n, double *__r
 }
 
 struct Scratch {
-    __bf16 *WB, *WT, *X0, *A[3], *DZ[2];
+    __bf16 *WB, *WT, *WF0, *X0, *A[3], *DZ[2];
     float *bias, *Z[3], *OUT, *part, *grad;
     double *lpart, *loss;
     int nwg;
@@ -326,6 +620,7 @@ Scratch carve_scratch(char *base, int B, int H, int W, int64_t *bytes) {
     s.WB = (__bf16 *)take(4 * 9 * kC * kC * 2);
     s.WT = (__bf16 *)take(4 * 9 * kC * kC * 2);
     s.bias = (float *)take(4 * kC * 4);
+    s.WF0 = (__bf16 *)take(kC * kFK0 * 2);
     s.X0 = (__bf16 *)take(npix * kC * 2);
     for (int i = 0; i < 3; ++i) s.A[i] = (__bf16 *)take(npix * kC * 2);
     for (int i = 0; i < 3; ++i) s.Z[i] = (float *)take(npix * kC * 4);
@@ -342,7 +637,7 @@ Scratch carve_scratch(char *base, int B, int H, int W, int64_t *bytes) {
 
 void forward_pass(const Scratch &s, const float *params, const float *in, int B, int H, int W, hipStream_t st) {
     int64_t npix = (int64_t)B * H * W;
-    k_pack_weights<<<(4 * 9 * kC * kC + 255) / 256, 256, 0, st>>>(params, s.WB, s.WT, s.bias);
+    k_pack_weights<<<(4 * 9 * kC * kC + 255) / 256, 256, 0, st>>>(params, s.WB, s.WT, s.bias, nullptr);
     k_pack_input<<<(unsigned)((npix * kC + 255) / 256), 256, 0, st>>>(in, s.X0, B, H, W);
     int64_t tiles = (int64_t)B * H * ((W + 15) / 16);
     unsigned g = (unsigned)((tiles + 3) / 4);
@@ -354,6 +649,38 @@ void forward_pass(const Scratch &s, const float *params, const float *in, int B,
     }
     k_conv3x3<1><<<g, 256, 0, st>>>(x, s.WB + (int64_t)3 * 9 * kC * kC, s.bias + 3 * kC, B, H, W, nullptr, nullptr,
                                       s.OUT, nullptr);
+}
+
+// Inference: weights packed into s (WB, bias, WF0), then the fused kernel
+// from the caller's input planes to the caller's output planes.
+constexpr int64_t kFusedMaxTiles = (int64_t)1 << 24;
+
+int64_t fused_tiles(int B, int H, int W) {
+    return (int64_t)B * ((H + kFT - 1) / kFT) * ((W + kFT - 1) / kFT);
+}
+
+// Compute units of the current device (looked up once per device).
+int fused_cus() {
+    static std::mutex mu;
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+void forward_fused(const Scratch &s, const float *params, const float *in, float *out, int B, int H, int W,
+                   hipStream_t st) {
+    k_pack_weights<<<(4 * 9 * kC * kC + 255) / 256, 256, 0, st>>>(params, s.WB, s.WT, s.bias, s.WF0);
+    const int64_t tiles = fused_tiles(B, H, W);
+    const int64_t slots = 2 * (int64_t)fused_cus();  // two 56.6 KB LDS workgroups per compute unit
+    k_wn_forward_fused<<<(unsigned)(tiles < slots ? tiles : slots), kFThreads, 0, st>>>(in, s.WF0, s.WB, s.bias, B,
+                                                                                       H, W, out);
 }
 
 // Loss and gradient into s.grad (forward pass already run).
@@ -368,8 +695,9 @@ void backward_pass(const Scratch &s, const float *target, int B, int H, int W, h
     for (int l = 3; l >= 0; --l) {
         const __bf16 *aprev = (l == 0) ? s.X0 : s.A[l - 1];
         k_wgrad_mfma<<<s.nwg, 576, 0, st>>>(s.DZ[cur], aprev, B, H, W, s.part);
-        k_wgrad_reduce<<<(9 * kC * kC + kC + 255) / 256, 256, 0, st>>>(s.part, s.nwg, kLayersH[l].ci,
-                                                                        kLayersH[l].co, s.grad + param_offset(l));
+        const unsigned nred = (9 * kC * kC + kC + kWrEntries - 1) / kWrEntries;
+        k_wgrad_reduce<<<nred, 256, 0, st>>>(s.part, s.nwg, kLayersH[l].ci, kLayersH[l].co,
+                                             s.grad + param_offset(l));
         if (l > 0) {
             k_conv3x3<2><<<g, 256, 0, st>>>(s.DZ[cur], s.WT + (int64_t)l * 9 * kC * kC, nullptr, B, H, W,
                                               s.DZ[cur ^ 1], nullptr, nullptr, s.Z[l - 1]);
@@ -468,9 +796,11 @@ int64_t wn_scratch_size(int B, int H, int W) {
 
 int wn_forward_impl(const float *params, const float *in, float *out, int B, int H, int W, void *scratch,
                     hipStream_t st) {
+    if (fused_tiles(B, H, W) > kFusedMaxTiles)
+        return fail(MG_EINVAL, "image batch %d x %d x %d exceeds %lld tiles of %d x %d pixels", B, H, W,
+                    (long long)kFusedMaxTiles, kFT, kFT);
     Scratch s = carve_scratch((char *)scratch, B, H, W, nullptr);
-    forward_pass(s, params, in, B, H, W, st);
-    HIP_OK(hipMemcpyAsync(out, s.OUT, (size_t)B * 3 * H * W * 4, hipMemcpyDeviceToDevice, st));
+    forward_fused(s, params, in, out, B, H, W, st);
     HIP_OK(hipGetLastError());
     return MG_OK;
 }
@@ -531,25 +861,22 @@ void launch_apply(const Geom &g, const double *Vu, const double *neu, const doub
 }  // namespace mgf
 
 // ---------------------------------------------------------------------------
-// Allocation-free forward pass (wn_forward_noalloc): the same kernels as
-// wn_forward, with the activations in one file-scope device array per GPU
-// instead of a caller-provided scratch buffer.  Buffers are reused across
-// layers (input planes -> A -> input buffer -> A; one pre-activation buffer
-// for every layer, which the forward pass only writes) and the last layer
-// writes the caller's output directly, so the results are bitwise those of
-// wn_forward.  Nothing in the forward pass accumulates into scratch memory,
-// so no clearing is needed; calls that overlap on one GPU race on it.
+// Allocation-free forward pass (wn_forward_noalloc): the same two kernels as
+// wn_forward (weight packing, then the fused forward pass), with the packed
+// weights in one file-scope device array per GPU instead of a caller-provided
+// scratch buffer.  The fused kernel keeps every activation in LDS, so the
+// array holds only the packed weights and biases (a fixed 155 KB whatever the
+// image size) and the results are bitwise those of wn_forward.  Packing
+// overwrites the whole array on every call, so nothing needs clearing; calls
+// that overlap on one GPU race on it.
 // ---------------------------------------------------------------------------
 namespace mgf {
 namespace {
 
-constexpr int64_t kStaticMaxPixels = 257 * 257;  // B * H * W of one 257x257 image
 constexpr int64_t round256(int64_t n) { return (n + 255) / 256 * 256; }
 constexpr int64_t kStaticWeightBytes = 4 * 9 * kC * kC * 2;
-constexpr int64_t kStaticActBytes = kStaticMaxPixels * kC * 2;
-constexpr int64_t kStaticZBytes = kStaticMaxPixels * kC * 4;
 constexpr int64_t kStaticScratchBytes =
-    2 * round256(kStaticWeightBytes) + round256(4 * kC * 4) + 2 * round256(kStaticActBytes) + round256(kStaticZBytes);
+    2 * round256(kStaticWeightBytes) + round256(4 * kC * 4) + round256(kC * kFK0 * 2);
 
 }  // namespace
 }  // namespace mgf
@@ -590,12 +917,11 @@ extern "C" int wn_forward_noalloc(const float *params, const float *in, float *o
     using namespace mgf;
     if (!params || !in || !out) return fail(MG_EINVAL, "null pointer");
     if (B < 1 || H < 1 || W < 1) return fail(MG_EINVAL, "bad image batch shape %d x %d x %d", B, H, W);
-    if ((int64_t)B * H * W > kStaticMaxPixels)
-        return fail(MG_EINVAL, "B*H*W = %lld exceeds the %lld pixels of the static scratch array",
-                    (long long)B * H * W, (long long)kStaticMaxPixels);
+    if (fused_tiles(B, H, W) > kFusedMaxTiles)
+        return fail(MG_EINVAL, "image batch %d x %d x %d exceeds %lld tiles of %d x %d pixels", B, H, W,
+                    (long long)kFusedMaxTiles, kFT, kFT);
     char *base = nullptr;
     if (int e = static_scratch(&base)) return e;
-    int64_t npix = (int64_t)B * H * W;
     int64_t off = 0;
     auto take = [&](int64_t n) {
         char *p = base + off;
@@ -607,17 +933,9 @@ extern "C" int wn_forward_noalloc(const float *params, const float *in, float *o
     s.WB = (__bf16 *)take(kStaticWeightBytes);
     s.WT = (__bf16 *)take(kStaticWeightBytes);
     s.bias = (float *)take(4 * kC * 4);
-    __bf16 *bx = (__bf16 *)take(npix * kC * 2);
-    __bf16 *ba = (__bf16 *)take(npix * kC * 2);
-    float *z = (float *)take(npix * kC * 4);
+    s.WF0 = (__bf16 *)take(kC * kFK0 * 2);
     if (off > kStaticScratchBytes) return fail(MG_EINVAL, "static scratch layout overflow");
-    s.X0 = bx;
-    s.A[0] = ba;  // layer 1: input planes -> ba
-    s.A[1] = bx;  // layer 2: ba -> bx (the input planes are no longer read)
-    s.A[2] = ba;  // layer 3: bx -> ba; layer 4 reads ba
-    s.Z[0] = s.Z[1] = s.Z[2] = z;
-    s.OUT = out;
-    forward_pass(s, params, in, B, H, W, reinterpret_cast<hipStream_t>(stream));
+    forward_fused(s, params, in, out, B, H, W, reinterpret_cast<hipStream_t>(stream));
     HIP_OK(hipGetLastError());
     return MG_OK;
 }

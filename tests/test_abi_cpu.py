@@ -85,6 +85,20 @@ def test_null_arguments_fail_before_device_work():
     assert b"null" in lib.mg_last_error()
 
 
+def test_forward_noalloc_rejects_batches_beyond_one_launch():
+    """2^24 tiles of 16 x 16 pixels is the launch limit of the fused forward
+    pass; one more image's worth is refused before any device call (the fake
+    addresses are never dereferenced)."""
+    import ctypes
+    lib = M.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    tiles = 17 * 17  # one 257 x 257 image
+    B = (1 << 24) // tiles + 1
+    assert lib.wn_forward_noalloc(fake, fake, fake, B, 257, 257, None) == -1
+    assert b"tiles" in lib.mg_last_error()
+    assert lib.wn_forward_noalloc(fake, fake, fake, 0, 257, 257, None) == -1
+
+
 def test_setup_rejects_small_workspace_without_touching_it():
     d = M.make_desc(64, 64, inputs.z_cos(64))
     pitch, ws = M.query(d)

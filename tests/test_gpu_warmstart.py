@@ -32,7 +32,7 @@ def _params(seed):
     return np.concatenate(out)
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 9, 20), (1, 17, 33), (1, 257, 257)])
+@pytest.mark.parametrize("B,H,W", [(2, 9, 20), (1, 17, 33), (1, 5, 3), (3, 40, 17), (1, 257, 257)])
 def test_forward_matches_cpu_reference(B, H, W):
     _say("wn forward", B, H, W)
     m = M()
