@@ -112,13 +112,36 @@ template <class T>
 void launch_block_subcycle(const FusedLevelsT<T> &F, hipStream_t s, const Batch &bt = Batch());
 void launch_planes_to_f32(const double *src, float *dst, int64_t n, hipStream_t s, const Batch &bt = Batch());
 void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t s, const Batch &bt = Batch());
+// Deferred (lagged) second projection of the Arnoldi vector.  fin_h: the
+// pass first finalises basis slot nv-1, which holds u (one projection
+// removed): slot = (u - sum_{v<nv-1} fin_h[v] basis_v) / sqrt(*fin_nu2)
+// (written through fin_out, the same slot), and uses the result as basis
+// vector nv-1.  next: the updated w is stored there (the next basis slot,
+// zero on the electrode columns) instead of in w.  with_norm: the partial
+// sums also hold (w, w) after the nv projections.
+struct CgsLag {
+    const double *fin_h = nullptr;
+    const double *fin_nu2 = nullptr;
+    double *fin_out = nullptr;
+    double *next = nullptr;
+    int with_norm = 0;
+};
 // Gram-Schmidt pass: w = J z (if J and z) or w -= sum_v h_sub[v] basis_v
 // (if h_sub), then the partial sums of the weighted (w, basis_v), v < nv,
 // or of (w, w) when self_norm; with out != nullptr a second launch adds them
 // into out[].
 void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                      double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
-                     const Batch &bt = Batch(), const BOp *J = nullptr, const double *z = nullptr);
+                     const Batch &bt = Batch(), const BOp *J = nullptr, const double *z = nullptr,
+                     const CgsLag &lag = CgsLag());
+// nu^2 = h[nv] - sum_{v<nv} h[v]^2 (the k_sum_cols output of a with_norm
+// pass) to out and, when given, to pinned out_host.
+void launch_lagged_nu2(double *h, int nv, double *out, double *out_host, hipStream_t s, const Batch &bt = Batch());
+// The same from the partials of a with_norm pass over grid g (nv + 1
+// columns), summed in the chained passes' order: h to dev_h, nu^2 to
+// dev_nu2, and to the pinned host copies when given.
+void launch_lagged_reduce(const Geom &g, const double *partials, int nv, double *dev_h, double *dev_nu2,
+                          double *host_h, double *host_nu2, hipStream_t s, const Batch &bt = Batch());
 // dst = src / |.| from the norm partials of a self_norm pass; out[0] = |.|^2
 // (also to out_host, pinned host memory, when given).
 void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
@@ -129,7 +152,7 @@ void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t 
 // w -= V h and its own partials (partials must not alias h_part).
 void launch_cgs_pass_chained(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                              double3 cw, bool self_norm, const double *h_part, double *h_out, double *h_host,
-                             double *partials, hipStream_t s, const Batch &bt = Batch());
+                             double *partials, hipStream_t s, const Batch &bt = Batch(), const CgsLag &lag = CgsLag());
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                        const double *h, double sign, hipStream_t s, const Batch &bt = Batch());
 void launch_scale_by_norm(const Geom &g, const double *src, double *dst, int64_t plane, const double *nrm2,

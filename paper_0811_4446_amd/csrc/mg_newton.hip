@@ -1528,6 +1528,14 @@ inline __device__ void reduce_projections(const double *__restrict__ part, int n
     __syncthreads();
 }
 
+// Squared norm of u - V h for u with (u, u) = ww and projections h = V^T u
+// onto an orthonormal V (Pythagoras), the subtraction in a fixed order.
+inline __device__ double lagged_nu2(const double *h, int nv, double ww) {
+    double n2 = ww;
+    for (int v = 0; v < nv; ++v) n2 = fmad(-h[v], h[v], n2);
+    return n2;
+}
+
 // NV > 0: at most NV basis vectors (nv <= NV); a node's basis values are
 // loaded once into registers, before the previous pass's projections are
 // summed (their loads overlap), and serve both the update and the dot
@@ -1543,7 +1551,7 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
                                                    const double *__restrict__ z, double *__restrict__ partials,
                                                    const double *__restrict__ h_part, int h_nblk,
                                                    double *__restrict__ h_out, double *__restrict__ h_host,
-                                                   Batch bt) {
+                                                   CgsLag lag, Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
     g = geom_off(g, bo_);
@@ -1553,13 +1561,20 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
     partials = boff(partials, bo_);
     z = boff(z, bo_);
     Jop.base = boff(Jop.base, bo_);
+    lag.fin_h = boff(lag.fin_h, bo_);
+    lag.fin_nu2 = boff(lag.fin_nu2, bo_);
+    lag.fin_out = boff(lag.fin_out, bo_);
+    lag.next = boff(lag.next, bo_);
 
     const int j = blockIdx.x * kTX + threadIdx.x;
     const int i = blockIdx.y * blockDim.y + threadIdx.y;
     __shared__ double sh[kMaxTY][kMaxKrylov + 1];
     __shared__ double hs[kMaxKrylov + 1];
+    __shared__ double hf[kMaxKrylov + 1];
+    __shared__ double inv_nu;
     const bool ok = i <= g.nr && j >= 1 && j < g.nz;
     const int64_t p = ok ? at(g, i, j) : 0;
+    const int kf = nv - 1;  // the basis slot finalised by this pass (lag.fin_h)
     // basis values of this node (register form)
     double bv[NV > 0 ? NV : 1][3];
     const bool upd = h_part || h_sub;
@@ -1573,6 +1588,53 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
                     bv[v][1] = bb[plane];
                     bv[v][2] = bb[2 * plane];
                 }
+        }
+    }
+    // Deferred second projection and normalisation of basis slot kf: it
+    // holds u = w' of the previous Arnoldi step (one projection removed);
+    // v = (u - sum_{v<kf} hf_v b_v) / nu with nu^2 = (u, u) - |hf|^2.  The
+    // node's finalised values replace slot kf in memory and in the dot
+    // products below (vf; slot kf is not read again).
+    double vf[3] = {0.0, 0.0, 0.0};
+    if (lag.fin_h) {
+        const int t = threadIdx.y * kTX + threadIdx.x;
+        for (int v = t; v < kf; v += kTX * blockDim.y) hf[v] = lag.fin_h[v];
+        if (t == 0) {
+            const double n2 = *lag.fin_nu2;
+            inv_nu = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+        }
+        __syncthreads();
+        if (ok) {
+            double u[3];
+            if constexpr (NV > 0) {
+                // register indices stay compile-time constants
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v == kf)
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) u[f] = bv[v][f];
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v < kf)
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) u[f] = fmad(-hf[v], bv[v][f], u[f]);
+            } else {
+                for (int f = 0; f < 3; ++f) u[f] = basis[kf * vstride + p + f * plane];
+                for (int v = 0; v < kf; ++v)
+                    for (int f = 0; f < 3; ++f) u[f] = fmad(-hf[v], basis[v * vstride + p + f * plane], u[f]);
+            }
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                vf[f] = u[f] * inv_nu;
+                lag.fin_out[p + f * plane] = vf[f];
+            }
+            if constexpr (NV > 0) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v == kf)
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) bv[v][f] = vf[f];
+            }
         }
     }
     if (h_part) {
@@ -1603,8 +1665,13 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
                     if (h_sub[v] != 0.0)
                         for (int f = 0; f < 3; ++f) wf[f] = fmad(-h_sub[v], basis[v * vstride + p + f * plane], wf[f]);
             }
-            for (int f = 0; f < 3; ++f) w[p + f * plane] = wf[f];
+            double *dst = lag.next ? lag.next : w;
+            for (int f = 0; f < 3; ++f) dst[p + f * plane] = wf[f];
         }
+    }
+    if (lag.next && i <= g.nr && (j == 0 || j == g.nz)) {
+        const int64_t pb = at(g, i, j);
+        lag.next[pb] = lag.next[pb + plane] = lag.next[pb + 2 * plane] = 0.0;
     }
     const double iv = ok ? 1.0 / (g.wr[i] * g.dzc[j]) : 0.0;
     const double we = wf[0] * cw.x * cw.x * iv * iv;
@@ -1616,25 +1683,39 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
         return s;
     };
-    const int nd = self_norm ? 1 : nv;
+    const int nd = self_norm ? 1 : nv + (lag.with_norm ? 1 : 0);
     if (self_norm) {
         const double s = wave_sum(ok ? dot3(wf[0], wf[1], wf[2]) : 0.0);
         if (threadIdx.x == 0) sh[threadIdx.y][0] = s;
-    } else if constexpr (NV > 0) {
-        double sv[NV];
+    } else {
+        if constexpr (NV > 0) {
+            double sv[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sv[v] = (ok && v < nv) ? dot3(bv[v][0], bv[v][1], bv[v][2]) : 0.0;
+            for (int v = 0; v < NV; ++v) sv[v] = (ok && v < nv) ? dot3(bv[v][0], bv[v][1], bv[v][2]) : 0.0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            if (v < nv) {
-                const double s = wave_sum(sv[v]);
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) {
+                    const double s = wave_sum(sv[v]);
+                    if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
+                }
+        } else {
+            for (int v = 0; v < nv; ++v) {
+                double d = 0.0;
+                if (ok) {
+                    if (lag.fin_h && v == kf) {
+                        d = dot3(vf[0], vf[1], vf[2]);
+                    } else {
+                        const double *b = basis + v * vstride;
+                        d = dot3(b[p], b[p + plane], b[p + 2 * plane]);
+                    }
+                }
+                const double s = wave_sum(d);
                 if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
             }
-    } else {
-        for (int v = 0; v < nv; ++v) {
-            const double *b = basis + v * vstride;
-            const double s = wave_sum(ok ? dot3(b[p], b[p + plane], b[p + 2 * plane]) : 0.0);
-            if (threadIdx.x == 0) sh[threadIdx.y][v] = s;
+        }
+        if (lag.with_norm) {
+            const double s = wave_sum(ok ? dot3(wf[0], wf[1], wf[2]) : 0.0);
+            if (threadIdx.x == 0) sh[threadIdx.y][nv] = s;
         }
     }
     __syncthreads();
@@ -1645,6 +1726,49 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
         for (int y = 0; y < (int)blockDim.y; ++y) s += sh[y][t];
         partials[(int64_t)blk * nd + t] = s;
     }
+}
+
+// Projections h_v (v < nv) and nu^2 = (w, w) - |h|^2 from the nblk
+// workgroup partials of a with_norm pass (nv + 1 columns), summed in the
+// chained passes' fixed order; to dev_h / dev_nu2 and, when given, to the
+// pinned host copies.  One workgroup of kTX x 4 threads per problem.  (The
+// last workgroup of the pass itself could sum them, but its device-scope
+// release then writes back its XCD's L2 from every workgroup.)
+__global__ __launch_bounds__(256) void k_lagged_reduce(const double *__restrict__ part, int nblk, int nv,
+                                                       double *__restrict__ dev_h, double *__restrict__ dev_nu2,
+                                                       double *__restrict__ host_h, double *__restrict__ host_nu2,
+                                                       Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    part = boff(part, bo_);
+    dev_h = boff(dev_h, bo_);
+    dev_nu2 = boff(dev_nu2, bo_);
+    __shared__ double hs[kMaxKrylov + 1];
+    reduce_projections(part, nblk, nv + 1, hs, nullptr, nullptr);
+    const int t = threadIdx.y * kTX + threadIdx.x;
+    for (int v = t; v < nv; v += kTX * blockDim.y) {
+        dev_h[v] = hs[v];
+        if (host_h) host_h[v] = hs[v];
+    }
+    if (t == 0) {
+        const double n2 = lagged_nu2(hs, nv, hs[nv]);
+        *dev_nu2 = n2;
+        if (host_nu2) *host_nu2 = n2;
+    }
+}
+
+// nu^2 = ww - sum_v h_v^2 for the unchained passes: h (nv values) and ww
+// (at h[nv]) from k_sum_cols; one thread per problem.
+__global__ void k_lagged_nu2(double *__restrict__ h, int nv, double *__restrict__ out, double *__restrict__ out_host,
+                             Batch bt) {
+    if (bt.active && !bt.active[blockIdx.z]) return;
+    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
+    h = boff(h, bo_);
+    out = boff(out, bo_);
+    if (threadIdx.x != 0) return;
+    const double n2 = lagged_nu2(h, nv, h[nv]);
+    *out = n2;
+    if (out_host) *out_host = n2;
 }
 
 // dst = src / sqrt(n2) with n2 the sum of the nblk norm partials (formed in
@@ -1959,15 +2083,24 @@ decltype(&k_cgs_pass<0>) cgs_kernel(const Geom &g, int nv) {
 }
 void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                      double3 cw, const double *h_sub, bool self_norm, double *partials, double *out, hipStream_t s,
-                     const Batch &bt, const BOp *J, const double *z) {
+                     const Batch &bt, const BOp *J, const double *z, const CgsLag &lag) {
     dim3 gr = grid2d(g);
     auto k = cgs_kernel(g, nv);
     k<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, h_sub, self_norm ? 1 : 0,
-                                      J ? *J : BOp{nullptr, 0}, z, partials, nullptr, 0, nullptr, nullptr, bt);
+                                      J ? *J : BOp{nullptr, 0}, z, partials, nullptr, 0, nullptr, nullptr, lag, bt);
     if (out) {
-        int nd = self_norm ? 1 : nv;
+        int nd = self_norm ? 1 : nv + (lag.with_norm ? 1 : 0);
         k_sum_cols<<<dim3(nd, 1, bt.n), 256, 0, s>>>(partials, (int)(gr.x * gr.y), nd, out, bt);
     }
+}
+void launch_lagged_nu2(double *h, int nv, double *out, double *out_host, hipStream_t s, const Batch &bt) {
+    k_lagged_nu2<<<dim3(1, 1, bt.n), 64, 0, s>>>(h, nv, out, out_host, bt);
+}
+void launch_lagged_reduce(const Geom &g, const double *partials, int nv, double *dev_h, double *dev_nu2,
+                          double *host_h, double *host_nu2, hipStream_t s, const Batch &bt) {
+    dim3 gr = grid2d(g);
+    k_lagged_reduce<<<dim3(1, 1, bt.n), dim3(kTX, 4), 0, s>>>(partials, (int)(gr.x * gr.y), nv, dev_h, dev_nu2,
+                                                               host_h, host_nu2, bt);
 }
 void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
                          double *out, hipStream_t s, const Batch &bt, double *out_host) {
@@ -1977,12 +2110,12 @@ void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t 
 }
 void launch_cgs_pass_chained(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                              double3 cw, bool self_norm, const double *h_part, double *h_out, double *h_host,
-                             double *partials, hipStream_t s, const Batch &bt) {
+                             double *partials, hipStream_t s, const Batch &bt, const CgsLag &lag) {
     dim3 gr = grid2d(g);
     auto k = cgs_kernel(g, nv);
     k<<<gz(gr, bt), blk2d(g), 0, s>>>(g, w, basis, vstride, nv, plane, cw, nullptr, self_norm ? 1 : 0,
                                       BOp{nullptr, 0}, nullptr, partials, h_part, (int)(gr.x * gr.y), h_out, h_host,
-                                      bt);
+                                      lag, bt);
 }
 void launch_axpy_multi(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                        const double *h, double sign, hipStream_t s, const Batch &bt) {

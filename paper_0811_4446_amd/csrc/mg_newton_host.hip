@@ -339,6 +339,11 @@ struct Arnoldi {
     }
 };
 
+// Hessenberg subdiagonal from nu^2 = (w', w') - |h2|^2: a value rounded
+// below zero (w' inside the basis to working precision) is a breakdown,
+// zero; a non-finite one stays non-finite.
+double subdiag(double nu2) { return nu2 < 0.0 ? 0.0 : sqrt(nu2); }
+
 // Copy `count` device doubles at `dev` of every problem of the batch to
 // host[p * count ...] (one strided copy).
 void readback(mg_ctx *c, double *host, const double *dev, int count, hipStream_t s) {
@@ -349,9 +354,25 @@ void readback(mg_ctx *c, double *host, const double *dev, int count, hipStream_t
                                (size_t)c->bt.n, hipMemcpyDeviceToHost, s);
 }
 
-// One Arnoldi step k: z_k = M v_k (block V-cycle), w = J z_k, two passes of
-// classical Gram-Schmidt against v_0..v_k, v_{k+1} = w/|w|, and the
-// readback of the k+1 projections (twice) and |w|^2 to pinned memory.
+// One Arnoldi step k.  Basis slot k holds u_k: v_0 for k = 0, otherwise the
+// vector w' of step k-1, from which one projection has been removed.
+//   z_k = M u_k (block V-cycle; flexible GMRES admits any z_k, J Z = V H is
+//         what the least-squares update needs);
+//   pass 1: slot k := v_k = (u_k - V_{<k} h2) / nu_k, the second projection
+//           and the normalisation deferred from step k-1; w = J z_k and
+//           h1 = V_{<=k}^T w;
+//   pass 2: w' = w - V h1 into slot k+1, partial sums of h2 = V^T w' and
+//           (w', w');
+//   their sums and nu_{k+1}^2 = (w', w') - |h2|^2 (Pythagoras: v_{k+1}
+//           would be (w' - V h2) / nu_{k+1}).
+// The Hessenberg column is h1 + h2 with subdiagonal nu_{k+1}, the column two
+// full classical Gram-Schmidt passes give, with one pass over the basis and
+// one launch fewer per step (three instead of four on chained grids: the
+// third pass and the norm-and-scale launch become one small reduction).
+// h1, h2 and nu^2 go to the device scalars
+// ([0..k], [m+1..m+1+k], [2m+2]) and to pinned memory: a single problem's
+// straight to one of two pinned slots (step k+1 can run while the host
+// reads step k), a batch's copied afterwards.
 void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     NewtonWork &W = c->nw;
     const Level &L0 = c->lev[0];
@@ -360,7 +381,7 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     BOp J = bop(c, 0);
     const int m = W.m;
     double *dev = W.dev;
-    double *vk = W.V + k * vs, *zk = W.Z + k * vs, *vk1 = W.V + (k + 1) * vs;
+    double *uk = W.V + k * vs, *zk = W.Z + k * vs, *uk1 = W.V + (k + 1) * vs;
     if (k == 0) {
         // the coarsest factorisation (of the Jacobian assembled before this
         // solve) overlaps the fine-level part of the first V-cycle
@@ -371,38 +392,38 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
         W.join_pending = true;
     }
     if (W.prec32) {
-        // preconditioner in FP32: z_k = M32 v_k (the Krylov space stays FP64)
+        // preconditioner in FP32: z_k = M32 u_k (the Krylov space stays FP64)
         float *x32 = W.lev[0].x32;
-        launch_planes_to_f32(vk, W.f32, vs, s, c->bt);
+        launch_planes_to_f32(uk, W.f32, vs, s, c->bt);
         block_vcycle<float>(c, 0, W.f32, x32, s);
         launch_planes_to_f64(x32, zk, vs, s, c->bt);
     } else {
-        block_vcycle<double>(c, 0, vk, zk, s);
+        block_vcycle<double>(c, 0, uk, zk, s);
     }
     join_factor(c, s);  // (already joined by the V-cycle's coarse end)
-    // w = J z_k, then classical Gram-Schmidt twice: h1 = V^T w; w -= V h1,
-    // h2 = V^T w; w -= V h2, |w|^2.  Each pass forms the previous pass's
-    // projections from its workgroup partials (two partial buffers in turn).
-    // A single problem's projections and |w|^2 go straight to one of two
-    // pinned slots (step k+1 can run while the host reads step k); a batch's
-    // are copied afterwards.
+    CgsLag fin;
+    if (k > 0) {
+        fin.fin_h = dev + m + 1;
+        fin.fin_nu2 = dev + 2 * m + 2;
+        fin.fin_out = uk;
+    }
+    CgsLag l2;
+    l2.next = uk1;
+    l2.with_norm = 1;
     // Every workgroup of a chained pass reads all partials of the previous
-    // one, so large grids (many workgroups) sum them in launches of their own.
+    // one (and one workgroup sums the second pass's), so large grids (many
+    // workgroups) sum them in launches of their own.
     double *P0 = W.partials, *P1 = W.partials2;
     if (c->bt.n == 1 && block_vec_blocks(g) <= W.chain_max_blocks) {
-        double *host = c->bt.n > 1 ? nullptr : c->pinned_dev + kSlot * (k & 1);
-        launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, nullptr, s, c->bt, &J, zk);
-        launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, false, P0, dev, host, P1, s, c->bt);
-        launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, true, P1, dev + (m + 1),
-                                host ? host + (m + 1) : nullptr, P0, s, c->bt);
-        launch_scale_reduce(g, W.w, vk1, p0, P0, dev + 2 * m + 2, s, c->bt, host ? host + 2 * m + 2 : nullptr);
-        if (c->bt.n > 1) readback(c, c->bpinned, dev, 2 * m + 3, s);
+        double *host = c->pinned_dev + kSlot * (k & 1);
+        launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, nullptr, s, c->bt, &J, zk, fin);
+        launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, false, P0, dev, host, P1, s, c->bt, l2);
+        launch_lagged_reduce(g, P1, k + 1, dev + m + 1, dev + 2 * m + 2, host + m + 1, host + 2 * m + 2, s, c->bt);
         return;
     }
-    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, dev, s, c->bt, &J, zk);
-    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev, false, P0, dev + (m + 1), s, c->bt);
-    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev + (m + 1), true, P0, nullptr, s, c->bt);
-    launch_scale_reduce(g, W.w, vk1, p0, P0, dev + 2 * m + 2, s, c->bt);
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, dev, s, c->bt, &J, zk, fin);
+    launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev, false, P0, dev + (m + 1), s, c->bt, nullptr, nullptr, l2);
+    launch_lagged_nu2(dev + (m + 1), k + 1, dev + 2 * m + 2, nullptr, s, c->bt);
     readback(c, c->bt.n > 1 ? c->bpinned : c->pinned + kSlot * (k & 1), dev, 2 * m + 3, s);
 }
 
@@ -531,7 +552,7 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
             }
             const double *host = c->pinned + kSlot * (k & 1);
             for (int i = 0; i <= k; ++i) A.H[i][k] = host[i] + host[m + 1 + i];
-            A.H[k + 1][k] = sqrt(host[2 * m + 2]);
+            A.H[k + 1][k] = subdiag(host[2 * m + 2]);
             ++total;
             c->vcycles++;
             est_prev = est;
@@ -872,7 +893,7 @@ int fgmres_batch(mg_ctx *c, double3 cw, double rtol, int maxit, const std::vecto
                 if (!iter[p]) continue;
                 const double *hp = host + (size_t)p * (2 * m + 3);
                 for (int i = 0; i <= k; ++i) A[p].H[i][k] = hp[i] + hp[m + 1 + i];
-                A[p].H[k + 1][k] = sqrt(hp[2 * m + 2]);
+                A[p].H[k + 1][k] = subdiag(hp[2 * m + 2]);
                 est[p] = A[p].add(k);
                 kp[p] = k + 1;
                 its[p]++;
