@@ -142,10 +142,6 @@ void launch_lagged_nu2(double *h, int nv, double *out, double *out_host, hipStre
 // dev_nu2, and to the pinned host copies when given.
 void launch_lagged_reduce(const Geom &g, const double *partials, int nv, double *dev_h, double *dev_nu2,
                           double *host_h, double *host_nu2, hipStream_t s, const Batch &bt = Batch());
-// dst = src / |.| from the norm partials of a self_norm pass; out[0] = |.|^2
-// (also to out_host, pinned host memory, when given).
-void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
-                         double *out, hipStream_t s, const Batch &bt = Batch(), double *out_host = nullptr);
 // A Gram-Schmidt pass that first forms the projections h = V^T w of the
 // previous pass from that pass's workgroup partials h_part (same launch
 // grid; the result also to h_out and, when given, to pinned h_host), then

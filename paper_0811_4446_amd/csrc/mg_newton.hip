@@ -1488,7 +1488,8 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
 // h_sub), at every unknown node, then the per-workgroup partial sums of the
 // weighted dot products of (the updated) w with basis_0..basis_{nv-1}, or
 // with w itself (self_norm).  The grid-wide sums are formed by a following
-// launch (k_sum_cols or k_scale_reduce) in a fixed order.
+// launch (k_sum_cols, k_lagged_reduce, or the next chained pass) in a fixed
+// order.
 // Projections h_v = sum over the nblk workgroup partials (partial b of
 // column v at part[b * nv + v]) in a fixed order: lane l adds the partials b
 // = l, l + 64, ... in turn, then the 64 lane sums are combined by an xor
@@ -1769,42 +1770,6 @@ __global__ void k_lagged_nu2(double *__restrict__ h, int nv, double *__restrict_
     const double n2 = lagged_nu2(h, nv, h[nv]);
     *out = n2;
     if (out_host) *out_host = n2;
-}
-
-// dst = src / sqrt(n2) with n2 the sum of the nblk norm partials (formed in
-// the same fixed order by every workgroup; workgroup 0 also stores it).
-__global__ void k_scale_reduce(Geom g, const double *__restrict__ src, double *__restrict__ dst, int64_t plane,
-                               const double *__restrict__ partials, int nblk, double *__restrict__ out,
-                               double *__restrict__ out_host, Batch bt) {
-    if (bt.active && !bt.active[blockIdx.z]) return;
-    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
-    g = geom_off(g, bo_);
-    src = boff(src, bo_);
-    dst = boff(dst, bo_);
-    partials = boff(partials, bo_);
-    out = boff(out, bo_);
-
-    __shared__ double n2s;
-    if (threadIdx.y == 0) {
-        double a = sum_strided(partials, nblk, threadIdx.x, kTX, 1, 0);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
-        if (threadIdx.x == 0) {
-            n2s = a;
-            if (blockIdx.x == 0 && blockIdx.y == 0) {
-                out[0] = a;
-                if (out_host) out_host[0] = a;
-            }
-        }
-    }
-    __syncthreads();
-    const int j = blockIdx.x * kTX + threadIdx.x;
-    const int i = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i > g.nr || j > g.nz) return;
-    const int64_t p = at(g, i, j);
-    const double s = 1.0 / sqrt(n2s);
-    const bool un = j >= 1 && j < g.nz;
-    for (int f = 0; f < 3; ++f) dst[p + f * plane] = un ? src[p + f * plane] * s : 0.0;
 }
 
 // out[c] = sum over blocks of partials[b*ncomp + c], fixed order (one
@@ -2101,12 +2066,6 @@ void launch_lagged_reduce(const Geom &g, const double *partials, int nv, double 
     dim3 gr = grid2d(g);
     k_lagged_reduce<<<dim3(1, 1, bt.n), dim3(kTX, 4), 0, s>>>(partials, (int)(gr.x * gr.y), nv, dev_h, dev_nu2,
                                                                host_h, host_nu2, bt);
-}
-void launch_scale_reduce(const Geom &g, const double *src, double *dst, int64_t plane, const double *partials,
-                         double *out, hipStream_t s, const Batch &bt, double *out_host) {
-    dim3 gr = grid2d(g);
-    k_scale_reduce<<<gz(gr, bt), blk2d(g), 0, s>>>(g, src, dst, plane, partials, (int)(gr.x * gr.y), out,
-                                                   out_host, bt);
 }
 void launch_cgs_pass_chained(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                              double3 cw, bool self_norm, const double *h_part, double *h_out, double *h_host,
