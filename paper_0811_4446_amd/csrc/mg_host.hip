@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "mg_internal.h"
+#include "mg_newton.h"
 #include "wn_net.h"
 
 namespace {
@@ -438,7 +439,7 @@ int mg_setup(const mg_grid_desc *desc, void *workspace, int64_t workspace_bytes,
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh = atoi(e) == 16 ? 16 : 8;
     if (const char *e = getenv("MGF_SWEEP2_ROWS"))
         for (int l = 0; l < c->nlev; ++l) c->lev[l].g.sh2 = atoi(e) == 4 ? 4 : 8;
-    hipError_t e = hipHostMalloc((void **)&c->pinned, 512 * sizeof(double), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&c->pinned, kPinnedDoubles * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->pinned_dev, c->pinned, 0);
     if (e != hipSuccess) {
         if (c->pinned) (void)hipHostFree(c->pinned);

@@ -9,6 +9,12 @@ constexpr int kMaxKrylov = 40;
 // 512 pinned doubles hold two slots, the least-squares solution and scalars
 constexpr int kSlot = 128;
 static_assert(2 * kSlot + 2 * kMaxKrylov + 16 <= 512, "pinned layout");
+// After those 512 doubles: two slots of the second Gram-Schmidt pass's
+// workgroup partials (chained grids of at most kChainCap workgroups, up to
+// kMaxKrylov + 1 columns), which the host sums itself.
+constexpr int kChainCap = 512;
+constexpr int64_t kPartSlot = (int64_t)kChainCap * (kMaxKrylov + 1);
+constexpr int64_t kPinnedDoubles = 512 + 2 * kPartSlot;
 constexpr int kBPlanes = 30;
 constexpr int kEE = 0, kEV = 5, kPP = 10, kPV = 15, kVV = 20, kVe = 25, kVp = 26, kFe = 27, kFp = 28, kFV = 29;
 
@@ -119,12 +125,19 @@ void launch_planes_to_f64(const float *src, double *dst, int64_t n, hipStream_t 
 // vector nv-1.  next: the updated w is stored there (the next basis slot,
 // zero on the electrode columns) instead of in w.  with_norm: the partial
 // sums also hold (w, w) after the nv projections.
+// fin_part (instead of fin_h, fin_nu2): the partials of the previous step's
+// second pass (fin_nblk workgroups, nv columns: nv-1 projections and
+// (u, u)), summed by every workgroup in the chained order.  part_host: the
+// pass also stores its partials there (pinned host memory).
 struct CgsLag {
     const double *fin_h = nullptr;
     const double *fin_nu2 = nullptr;
+    const double *fin_part = nullptr;
+    int fin_nblk = 0;
     double *fin_out = nullptr;
     double *next = nullptr;
     int with_norm = 0;
+    double *part_host = nullptr;
 };
 // Gram-Schmidt pass: w = J z (if J and z) or w -= sum_v h_sub[v] basis_v
 // (if h_sub), then the partial sums of the weighted (w, basis_v), v < nv,
@@ -137,11 +150,6 @@ void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstr
 // nu^2 = h[nv] - sum_{v<nv} h[v]^2 (the k_sum_cols output of a with_norm
 // pass) to out and, when given, to pinned out_host.
 void launch_lagged_nu2(double *h, int nv, double *out, double *out_host, hipStream_t s, const Batch &bt = Batch());
-// The same from the partials of a with_norm pass over grid g (nv + 1
-// columns), summed in the chained passes' order: h to dev_h, nu^2 to
-// dev_nu2, and to the pinned host copies when given.
-void launch_lagged_reduce(const Geom &g, const double *partials, int nv, double *dev_h, double *dev_nu2,
-                          double *host_h, double *host_nu2, hipStream_t s, const Batch &bt = Batch());
 // A Gram-Schmidt pass that first forms the projections h = V^T w of the
 // previous pass from that pass's workgroup partials h_part (same launch
 // grid; the result also to h_out and, when given, to pinned h_host), then

@@ -1488,8 +1488,7 @@ __global__ __launch_bounds__(1024) void k_block_subcycle(FusedLevelsT<T> F, Batc
 // h_sub), at every unknown node, then the per-workgroup partial sums of the
 // weighted dot products of (the updated) w with basis_0..basis_{nv-1}, or
 // with w itself (self_norm).  The grid-wide sums are formed by a following
-// launch (k_sum_cols, k_lagged_reduce, or the next chained pass) in a fixed
-// order.
+// launch (k_sum_cols, or the next chained pass) in a fixed order.
 // Projections h_v = sum over the nblk workgroup partials (partial b of
 // column v at part[b * nv + v]) in a fixed order: lane l adds the partials b
 // = l, l + 64, ... in turn, then the 64 lane sums are combined by an xor
@@ -1597,12 +1596,22 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
     // node's finalised values replace slot kf in memory and in the dot
     // products below (vf; slot kf is not read again).
     double vf[3] = {0.0, 0.0, 0.0};
-    if (lag.fin_h) {
+    const bool fin = lag.fin_h || lag.fin_part;
+    if (fin) {
         const int t = threadIdx.y * kTX + threadIdx.x;
-        for (int v = t; v < kf; v += kTX * blockDim.y) hf[v] = lag.fin_h[v];
-        if (t == 0) {
-            const double n2 = *lag.fin_nu2;
-            inv_nu = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+        if (lag.fin_part) {
+            // the previous second pass's partials: kf projections and (u, u)
+            reduce_projections(boff(lag.fin_part, bo_), lag.fin_nblk, kf + 1, hf, nullptr, nullptr);
+            if (t == 0) {
+                const double n2 = lagged_nu2(hf, kf, hf[kf]);
+                inv_nu = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+            }
+        } else {
+            for (int v = t; v < kf; v += kTX * blockDim.y) hf[v] = lag.fin_h[v];
+            if (t == 0) {
+                const double n2 = *lag.fin_nu2;
+                inv_nu = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+            }
         }
         __syncthreads();
         if (ok) {
@@ -1703,7 +1712,7 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
             for (int v = 0; v < nv; ++v) {
                 double d = 0.0;
                 if (ok) {
-                    if (lag.fin_h && v == kf) {
+                    if (fin && v == kf) {
                         d = dot3(vf[0], vf[1], vf[2]);
                     } else {
                         const double *b = basis + v * vstride;
@@ -1726,35 +1735,7 @@ __global__ __launch_bounds__(NV > 8 ? 256 : 1024) void k_cgs_pass(Geom g, double
         double s = 0.0;
         for (int y = 0; y < (int)blockDim.y; ++y) s += sh[y][t];
         partials[(int64_t)blk * nd + t] = s;
-    }
-}
-
-// Projections h_v (v < nv) and nu^2 = (w, w) - |h|^2 from the nblk
-// workgroup partials of a with_norm pass (nv + 1 columns), summed in the
-// chained passes' fixed order; to dev_h / dev_nu2 and, when given, to the
-// pinned host copies.  One workgroup of kTX x 4 threads per problem.  (The
-// last workgroup of the pass itself could sum them, but its device-scope
-// release then writes back its XCD's L2 from every workgroup.)
-__global__ __launch_bounds__(256) void k_lagged_reduce(const double *__restrict__ part, int nblk, int nv,
-                                                       double *__restrict__ dev_h, double *__restrict__ dev_nu2,
-                                                       double *__restrict__ host_h, double *__restrict__ host_nu2,
-                                                       Batch bt) {
-    if (bt.active && !bt.active[blockIdx.z]) return;
-    const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
-    part = boff(part, bo_);
-    dev_h = boff(dev_h, bo_);
-    dev_nu2 = boff(dev_nu2, bo_);
-    __shared__ double hs[kMaxKrylov + 1];
-    reduce_projections(part, nblk, nv + 1, hs, nullptr, nullptr);
-    const int t = threadIdx.y * kTX + threadIdx.x;
-    for (int v = t; v < nv; v += kTX * blockDim.y) {
-        dev_h[v] = hs[v];
-        if (host_h) host_h[v] = hs[v];
-    }
-    if (t == 0) {
-        const double n2 = lagged_nu2(hs, nv, hs[nv]);
-        *dev_nu2 = n2;
-        if (host_nu2) *host_nu2 = n2;
+        if (lag.part_host) lag.part_host[(int64_t)blk * nd + t] = s;
     }
 }
 
@@ -2060,12 +2041,6 @@ void launch_cgs_pass(const Geom &g, double *w, const double *basis, int64_t vstr
 }
 void launch_lagged_nu2(double *h, int nv, double *out, double *out_host, hipStream_t s, const Batch &bt) {
     k_lagged_nu2<<<dim3(1, 1, bt.n), 64, 0, s>>>(h, nv, out, out_host, bt);
-}
-void launch_lagged_reduce(const Geom &g, const double *partials, int nv, double *dev_h, double *dev_nu2,
-                          double *host_h, double *host_nu2, hipStream_t s, const Batch &bt) {
-    dim3 gr = grid2d(g);
-    k_lagged_reduce<<<dim3(1, 1, bt.n), dim3(kTX, 4), 0, s>>>(partials, (int)(gr.x * gr.y), nv, dev_h, dev_nu2,
-                                                               host_h, host_nu2, bt);
 }
 void launch_cgs_pass_chained(const Geom &g, double *w, const double *basis, int64_t vstride, int nv, int64_t plane,
                              double3 cw, bool self_norm, const double *h_part, double *h_out, double *h_host,

@@ -339,6 +339,34 @@ struct Arnoldi {
     }
 };
 
+// A batch context (any number of problems, one included) reads its Arnoldi
+// columns from the batch readback buffer.
+bool is_batch(const mg_ctx *c) { return c->bpinned != nullptr; }
+
+// Whether the Arnoldi step chains its Gram-Schmidt passes (a single-problem
+// context, a grid of few workgroups): then the host sums the second pass's
+// partials.
+bool chained_cgs(const mg_ctx *c) {
+    const int nb = block_vec_blocks(c->lev[0].g);
+    return !is_batch(c) && nb <= c->nw.chain_max_blocks && nb <= kChainCap;
+}
+
+// Column v of the nblk x nd workgroup partials, summed as the kernels'
+// chained reduction sums it: 64 running sums (partial b into sum b mod 64,
+// in increasing b), then pairwise at distances 32, 16, ..., 1; the sum that
+// ends in slot 0.
+double host_column_sum(const double *part, int nblk, int nd, int v) {
+    double a[64];
+    for (int l = 0; l < 64; ++l) a[l] = 0.0;
+    for (int b = 0; b < nblk; ++b) a[b & 63] += part[(int64_t)b * nd + v];
+    for (int off = 32; off > 0; off >>= 1) {
+        double t[64];
+        for (int l = 0; l < 64; ++l) t[l] = a[l] + a[l ^ off];
+        for (int l = 0; l < 64; ++l) a[l] = t[l];
+    }
+    return a[0];
+}
+
 // Hessenberg subdiagonal from nu^2 = (w', w') - |h2|^2: a value rounded
 // below zero (w' inside the basis to working precision) is a breakdown,
 // zero; a non-finite one stays non-finite.
@@ -366,13 +394,14 @@ void readback(mg_ctx *c, double *host, const double *dev, int count, hipStream_t
 //   their sums and nu_{k+1}^2 = (w', w') - |h2|^2 (Pythagoras: v_{k+1}
 //           would be (w' - V h2) / nu_{k+1}).
 // The Hessenberg column is h1 + h2 with subdiagonal nu_{k+1}, the column two
-// full classical Gram-Schmidt passes give, with one pass over the basis and
-// one launch fewer per step (three instead of four on chained grids: the
-// third pass and the norm-and-scale launch become one small reduction).
+// full classical Gram-Schmidt passes give, with one pass over the basis
+// fewer per step, and two launches instead of four on chained grids (the
+// sums of pass 2 are formed by the next step's pass 1 and by the host).
 // h1, h2 and nu^2 go to the device scalars
 // ([0..k], [m+1..m+1+k], [2m+2]) and to pinned memory: a single problem's
 // straight to one of two pinned slots (step k+1 can run while the host
-// reads step k), a batch's copied afterwards.
+// reads step k; on chained grids h1 and pass 2's partials), a batch's
+// copied afterwards.
 void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     NewtonWork &W = c->nw;
     const Level &L0 = c->lev[0];
@@ -411,20 +440,27 @@ void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     l2.next = uk1;
     l2.with_norm = 1;
     // Every workgroup of a chained pass reads all partials of the previous
-    // one (and one workgroup sums the second pass's), so large grids (many
-    // workgroups) sum them in launches of their own.
+    // one: pass 2 those of pass 1, and pass 1 those of the previous step's
+    // pass 2, which the host sums too from its pinned copy (the same order,
+    // the same bits).  Large grids (many workgroups) and batches sum them in
+    // launches of their own.
     double *P0 = W.partials, *P1 = W.partials2;
-    if (c->bt.n == 1 && block_vec_blocks(g) <= W.chain_max_blocks) {
+    if (chained_cgs(c)) {
         double *host = c->pinned_dev + kSlot * (k & 1);
+        if (k > 0) {
+            fin.fin_h = fin.fin_nu2 = nullptr;
+            fin.fin_part = P1;
+            fin.fin_nblk = block_vec_blocks(g);
+        }
+        l2.part_host = c->pinned_dev + 512 + kPartSlot * (k & 1);
         launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, nullptr, s, c->bt, &J, zk, fin);
         launch_cgs_pass_chained(g, W.w, W.V, vs, k + 1, p0, cw, false, P0, dev, host, P1, s, c->bt, l2);
-        launch_lagged_reduce(g, P1, k + 1, dev + m + 1, dev + 2 * m + 2, host + m + 1, host + 2 * m + 2, s, c->bt);
         return;
     }
     launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, nullptr, false, P0, dev, s, c->bt, &J, zk, fin);
     launch_cgs_pass(g, W.w, W.V, vs, k + 1, p0, cw, dev, false, P0, dev + (m + 1), s, c->bt, nullptr, nullptr, l2);
     launch_lagged_nu2(dev + (m + 1), k + 1, dev + 2 * m + 2, nullptr, s, c->bt);
-    readback(c, c->bt.n > 1 ? c->bpinned : c->pinned + kSlot * (k & 1), dev, 2 * m + 3, s);
+    readback(c, is_batch(c) ? c->bpinned : c->pinned + kSlot * (k & 1), dev, 2 * m + 3, s);
 }
 
 int run_arnoldi(mg_ctx *c, int k, double3 cw);
@@ -502,6 +538,8 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
     double *dev = W.dev;  // [0..m] dots, [m+1..2m+1] second pass, [2m+2] norm^2, y at [3m+8..]
     const int m = W.m;
     double *ybuf = c->pinned + 2 * kSlot, *sbuf = c->pinned + 2 * kSlot + kMaxKrylov + 8;
+    const bool chained = chained_cgs(c);
+    const int nblk = block_vec_blocks(g);
     Arnoldi A;
     launch_fill(W.delta, vs, 0.0, s);
     // r0 = b; its norm goes to pinned memory and is read with the first
@@ -551,8 +589,19 @@ int fgmres(mg_ctx *c, const mg_physics *ph, double rtol, int maxit, int *its, do
                 est = est_prev = beta0;
             }
             const double *host = c->pinned + kSlot * (k & 1);
-            for (int i = 0; i <= k; ++i) A.H[i][k] = host[i] + host[m + 1 + i];
-            A.H[k + 1][k] = subdiag(host[2 * m + 2]);
+            if (chained) {
+                // second projections and (w', w') from the pinned partials of pass 2
+                const double *pp = c->pinned + 512 + kPartSlot * (k & 1);
+                double h2[kMaxKrylov + 1];
+                for (int i = 0; i <= k + 1; ++i) h2[i] = host_column_sum(pp, nblk, k + 2, i);
+                double nu2 = h2[k + 1];
+                for (int i = 0; i <= k; ++i) nu2 = fma(-h2[i], h2[i], nu2);
+                for (int i = 0; i <= k; ++i) A.H[i][k] = host[i] + h2[i];
+                A.H[k + 1][k] = subdiag(nu2);
+            } else {
+                for (int i = 0; i <= k; ++i) A.H[i][k] = host[i] + host[m + 1 + i];
+                A.H[k + 1][k] = subdiag(host[2 * m + 2]);
+            }
             ++total;
             c->vcycles++;
             est_prev = est;

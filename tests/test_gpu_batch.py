@@ -36,7 +36,8 @@ def _draw(N, nprob, seed):
     return probs
 
 
-@pytest.mark.parametrize("N,nprob,prec,smoother", [(16, 5, 1, 1), (32, 4, 1, 1), (32, 3, 0, 1), (32, 3, 0, 2)])
+@pytest.mark.parametrize("N,nprob,prec,smoother", [(16, 5, 1, 1), (16, 1, 1, 1), (32, 4, 1, 1), (32, 3, 0, 1),
+                                                   (32, 3, 0, 2)])
 def test_batch_equals_single_problem_solves(N, nprob, prec, smoother):
     _say("batch vs single", N, nprob, prec, smoother)
     m = M()
