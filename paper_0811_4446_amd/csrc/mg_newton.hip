@@ -1072,7 +1072,8 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor(Geom g, BOp J, dou
 
 // Same factorisation with the augmented matrix resident in LDS (n <= 63).
 constexpr int kLdsGJ = 63;
-__global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J, double *__restrict__ invT,
+constexpr int kFactorThreads = 1024;  // workgroup of the LDS Gauss-Jordan factorisation
+__global__ __launch_bounds__(kFactorThreads) void k_block_coarse_factor_lds(Geom g, BOp J, double *__restrict__ invT,
                                                                   Batch bt) {
     if (bt.active && !bt.active[blockIdx.z]) return;
     const int64_t bo_ = (int64_t)blockIdx.z * bt.stride;
@@ -1085,7 +1086,6 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
     const int n2 = 2 * n;
     // two copies of the augmented matrix: column step k reads one, writes the other
     __shared__ double Mb[2][kLdsGJ * 2 * kLdsGJ];
-    __shared__ int piv;
     double *M = Mb[0];
     for (int t = threadIdx.x; t < n * n2; t += blockDim.x) M[t] = 0.0;
     __syncthreads();
@@ -1109,39 +1109,63 @@ __global__ __launch_bounds__(1024) void k_block_coarse_factor_lds(Geom g, BOp J,
         for (int f = 0; f < 3; ++f) M[(rowb + f) * n2 + n + rowb + f] = 1.0;
     }
     __syncthreads();
-    // Gauss-Jordan with partial pivoting, two barriers per column: the pivot
-    // search, then every element of the next copy in one pass (scaled pivot
-    // row, exchanged row, other rows eliminated against the scaled pivot row),
-    // each thread's elements loaded before any is stored.
-    constexpr int kPer = (kLdsGJ * 2 * kLdsGJ + 1023) / 1024;
+    // Gauss-Jordan with partial pivoting, one barrier per column: every
+    // element of the next copy in one pass (scaled pivot row, exchanged row,
+    // other rows eliminated against the scaled pivot row), each thread's
+    // elements loaded before any is stored; meanwhile wavefront 0 forms the
+    // next column's new values in its lanes (one row each, n <= 64) and finds
+    // that column's pivot (largest magnitude, first row on ties) from them,
+    // so no separate search phase follows.  The pivot indices alternate
+    // between two slots.
+    __shared__ int pivs[2];
+    pivot_search_wave0(Mb[0], n2, 0, n, &pivs[0]);
+    __syncthreads();
+    // element (rr, cc) of the next copy, the same expression on both paths
+    auto gj_elem = [&](const double *A, int rr, int cc, int col, int pv, double pinv, double fpv) {
+        const double prc = A[pv * n2 + cc] * pinv;
+        if (rr == col) return prc;
+        const double src = (rr == pv) ? A[col * n2 + cc] : A[rr * n2 + cc];
+        const double fct = (rr == pv) ? fpv : A[rr * n2 + col];
+        return (fct != 0.0) ? fmad(-fct, prc, src) : src;
+    };
+    constexpr int kPer = (kLdsGJ * 2 * kLdsGJ + kFactorThreads - 1) / kFactorThreads;
     const int total = n * n2;
     int cur = 0;
     for (int col = 0; col < n; ++col) {
         const double *A = Mb[cur];
         double *B = Mb[cur ^ 1];
-        pivot_search_wave0(A, n2, col, n, &piv);
-        __syncthreads();
-        const int pv = piv;
+        const int pv = pivs[col & 1];
         const double pinv = 1.0 / A[pv * n2 + col];
         const double fpv = A[col * n2 + col];
         double v[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int t = threadIdx.x + k * 1024;
+            const int t = threadIdx.x + k * kFactorThreads;
             if (t >= total) break;
             const int rr = t / n2, cc = t - rr * n2;
-            const double prc = A[pv * n2 + cc] * pinv;
-            if (rr == col) {
-                v[k] = prc;
-            } else {
-                const double src = (rr == pv) ? A[col * n2 + cc] : A[rr * n2 + cc];
-                const double fct = (rr == pv) ? fpv : A[rr * n2 + col];
-                v[k] = (fct != 0.0) ? src - fct * prc : src;
+            v[k] = gj_elem(A, rr, cc, col, pv, pinv, fpv);
+        }
+        if (threadIdx.x < 64 && col + 1 < n) {
+            const int r = threadIdx.x;
+            int best = n;
+            double bv = -1.0;
+            if (r > col && r < n) {
+                bv = fabs(gj_elem(A, r, col + 1, col, pv, pinv, fpv));
+                best = r;
             }
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ov = __shfl_xor(bv, off);
+                const int ob = __shfl_xor(best, off);
+                if (ov > bv || (ov == bv && ob < best)) {
+                    bv = ov;
+                    best = ob;
+                }
+            }
+            if (r == 0) pivs[(col + 1) & 1] = best < n ? best : col + 1;
         }
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int t = threadIdx.x + k * 1024;
+            const int t = threadIdx.x + k * kFactorThreads;
             if (t >= total) break;
             B[t] = v[k];
         }
@@ -1988,7 +2012,7 @@ void launch_block_coarse_factor(const Geom &g, const BOp &J, double *scratch, do
                                 const Batch &bt) {
     int n = 3 * (g.nr + 1) * (g.nz - 1);
     if (n <= kLdsGJ)
-        k_block_coarse_factor_lds<<<dim3(1, 1, bt.n), 1024, 0, s>>>(g, J, invT, bt);
+        k_block_coarse_factor_lds<<<dim3(1, 1, bt.n), kFactorThreads, 0, s>>>(g, J, invT, bt);
     else
         k_block_coarse_factor<<<dim3(1, 1, bt.n), 1024, 0, s>>>(g, J, scratch, invT, bt);
 }
