@@ -93,79 +93,20 @@ __global__ void k_pack_weights(const float *__restrict__ params, __bf16 *__restr
     if (tap == 0 && ci == 0) bias[l * kC + co] = (co < d.co) ? W[(int64_t)d.co * d.ci * 9 + co] : 0.0f;
 }
 
-// FP32 NCHW [B][7][H][W] -> bf16 NHWC with 32 channel slots (zeros beyond 7).
+// FP32 NCHW [B][7][H][W] -> bf16 NHWC with 32 channel slots (zeros beyond
+// 7): one thread per pixel and group of 8 slots, one 16-byte store each.
 __global__ void k_pack_input(const float *__restrict__ in, __bf16 *__restrict__ x, int B, int H, int W) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t npix = (int64_t)B * H * W;
-    if (t >= npix * kC) return;
-    int c = (int)(t % kC);
-    int64_t pix = t / kC;
-    int64_t b = pix / ((int64_t)H * W), hw = pix % ((int64_t)H * W);
-    x[t] = (__bf16)(c < 7 ? in[(b * 7 + c) * H * W + hw] : 0.0f);
-}
-
-// ---------------------------------------------------------------------------
-// 3x3 convolution as an implicit GEMM on MFMA.  One wavefront computes 16
-// consecutive pixels of one image row x 32 output channels: for each of the
-// 9 taps it multiplies the 16x32 bf16 input patch (pixels x input channels)
-// by the 32x32 weight tile (two 16x16x32 MFMAs, FP32 accumulators).
-// Operand layout of v_mfma_f32_16x16x32_bf16 (checked on the device):
-// lane l holds A[l%16][8*(l/16)..+7], B[8*(l/16)..+7][l%16] and returns
-// D[4*(l/16)+i][l%16], i = 0..3.
-// MODE 0: hidden layer   -> z (FP32) and gelu(z) (bf16)
-// MODE 1: last layer     -> FP32 NCHW output, channels < 3
-// MODE 2: input gradient -> (sum) * gelu'(zprev), bf16
-// ---------------------------------------------------------------------------
-template <int MODE>
-__global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ in, const __bf16 *__restrict__ w,
-                                                 const float *__restrict__ bias, int B, int H, int W,
-                                                 __bf16 *__restrict__ out_act, float *__restrict__ out_z,
-                                                 float *__restrict__ out_f, const float *__restrict__ zprev) {
-    const int lane = threadIdx.x & 63;
-    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int tiles_x = (W + 15) >> 4;
-    const int64_t ntiles = (int64_t)B * H * tiles_x;
-    if (tile >= ntiles) return;
-    const int xt = (int)(tile % tiles_x);
-    const int64_t by = tile / tiles_x;
-    const int y = (int)(by % H);
-    const int b = (int)(by / H);
-    const int x0 = xt * 16;
-    const int m = lane & 15, kg = lane >> 4;
-    f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    const bf16x8 zero8 = {};
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over npix * 4
+    const int64_t npix = (int64_t)B * H * W;
+    if (t >= npix * (kC / 8)) return;
+    const int c8 = (int)(t % (kC / 8));
+    const int64_t pix = t / (kC / 8);
+    const int64_t b = pix / ((int64_t)H * W), hw = pix % ((int64_t)H * W);
+    bf16x8 v = {};
+    if (c8 == 0)
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1, xx = x0 + m + tap % 3 - 1;
-        bf16x8 a = zero8;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-            a = *reinterpret_cast<const bf16x8 *>(in + (((int64_t)b * H + yy) * W + xx) * kC + 8 * kg);
-        const __bf16 *wt = w + (int64_t)tap * kC * kC;
-        bf16x8 w0 = *reinterpret_cast<const bf16x8 *>(wt + (int64_t)m * kC + 8 * kg);
-        bf16x8 w1 = *reinterpret_cast<const bf16x8 *>(wt + (int64_t)(16 + m) * kC + 8 * kg);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc1, 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int px = x0 + 4 * kg + i;
-        if (px >= W) continue;
-        const int64_t pix = ((int64_t)b * H + y) * W + px;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int co = h * 16 + m;
-            float v = (h == 0) ? acc0[i] : acc1[i];
-            if (MODE == 0) {
-                v += bias[co];
-                out_z[pix * kC + co] = v;
-                out_act[pix * kC + co] = (__bf16)gelu(v);
-            } else if (MODE == 1) {
-                if (co < 3) out_f[(((int64_t)b * 3 + co) * H + y) * W + px] = v + bias[co];
-            } else {
-                out_act[pix * kC + co] = (__bf16)(v * gelu_grad(zprev[pix * kC + co]));
-            }
-        }
-    }
+        for (int c = 0; c < 7; ++c) v[c] = (__bf16)in[(b * 7 + c) * H * W + hw];
+    *reinterpret_cast<bf16x8 *>(x + pix * kC + 8 * c8) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -419,6 +360,89 @@ __global__ __launch_bounds__(kFThreads) void k_wn_forward_fused(const float *__r
     }
 }
 
+// ---------------------------------------------------------------------------
+// One 3x3 convolution layer for the training passes (every layer's
+// activations are kept in HBM for the backward pass).  One workgroup per
+// 16 x 16 output tile: the input tile with its one-pixel halo is staged once
+// in LDS (8-channel planes of 16-byte records, as in the fused forward
+// pass), the 32 x 32 weights of the nine taps stay in registers, and each
+// wave takes rows of 16 pixels: D (output channels x pixels) = W X on
+// v_mfma_f32_16x16x32_bf16, lanes (m, kg) receiving channels 4kg..4kg+3 (+16)
+// of pixel m.  Activations are NHWC with 32 channel slots.
+// MODE 0: hidden layer   -> z (FP32) and gelu(z) (bf16)
+// MODE 1: last layer     -> FP32 NCHW output, channels < 3
+// MODE 2: input gradient -> (sum) * gelu'(zprev), bf16 (w: the mirrored,
+//         transposed weights, the same [tap][out][in] layout)
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(kFThreads) void k_conv3x3_tile(const __bf16 *__restrict__ in,
+                                                            const __bf16 *__restrict__ w,
+                                                            const float *__restrict__ bias, int B, int H, int W,
+                                                            __bf16 *__restrict__ out_act, float *__restrict__ out_z,
+                                                            float *__restrict__ out_f, const float *__restrict__ zprev) {
+    constexpr int SI = kFT + 2, NI = SI * SI;
+    __shared__ bf16x8 tile[4 * NI];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    const int tiles_x = (W + kFT - 1) / kFT, tiles_y = (H + kFT - 1) / kFT;
+    const int tx = (int)(blockIdx.x % tiles_x);
+    const int ty = (int)((blockIdx.x / tiles_x) % tiles_y);
+    const int b = (int)(blockIdx.x / ((unsigned)tiles_x * tiles_y));
+    if (b >= B) return;
+    const int y0 = ty * kFT, x0 = tx * kFT;
+    bf16x8 wr[9][2];
+    load_hidden_weights(w, m, kg, wr);
+    for (int q = tid; q < 4 * NI; q += kFThreads) {
+        const int pix = q >> 2, c = q & 3;
+        const int gy = y0 - 1 + pix / SI, gx = x0 - 1 + pix % SI;
+        bf16x8 v = {};
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = *reinterpret_cast<const bf16x8 *>(in + (((int64_t)b * H + gy) * W + gx) * kC + 8 * c);
+        tile[c * NI + pix] = v;
+    }
+    __syncthreads();
+    for (int r = wave; r < kFT; r += kFThreads / 64) {
+        const bf16x8 *s0 = tile + kg * NI + r * SI + m;
+        f32x4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const bf16x8 x = s0[(tap / 3) * SI + tap % 3];
+            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[tap][0], x, a0, 0, 0, 0);
+            if (MODE != 1) a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[tap][1], x, a1, 0, 0, 0);
+        }
+        const int gy = y0 + r, gx = x0 + m;
+        if (gy >= H || gx >= W) continue;
+        const int64_t pix = ((int64_t)b * H + gy) * W + gx;
+        if (MODE == 1) {
+            if (kg == 0) {
+#pragma unroll
+                for (int co = 0; co < 3; ++co) out_f[(((int64_t)b * 3 + co) * H + gy) * W + gx] = a0[co] + bias[co];
+            }
+            continue;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const f32x4 acc = h == 0 ? a0 : a1;
+            const int c0 = 16 * h + 4 * kg;
+            bf16x4 o;
+            if (MODE == 0) {
+                f32x4 z;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    z[i] = acc[i] + bias[c0 + i];
+                    o[i] = (__bf16)gelu(z[i]);
+                }
+                *reinterpret_cast<f32x4 *>(out_z + pix * kC + c0) = z;
+            } else {
+                const f32x4 zp = *reinterpret_cast<const f32x4 *>(zprev + pix * kC + c0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = (__bf16)(acc[i] * gelu_grad(zp[i]));
+            }
+            *reinterpret_cast<bf16x4 *>(out_act + pix * kC + c0) = o;
+        }
+    }
+}
+
 // MSE loss over B*3*H*W outputs: per-block partial sums of squared errors
 // and the output gradient 2 (out - target) / count as bf16 NHWC (3 of the
 // 32 channel slots).
@@ -430,16 +454,18 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out, cons
     if (t < npix) {
         int64_t b = t / ((int64_t)H * W), hw = t % ((int64_t)H * W);
         double inv = 2.0 / (3.0 * (double)npix);
-        for (int c = 0; c < kC; ++c) {
-            float g = 0.0f;
-            if (c < 3) {
-                int64_t q = (b * 3 + c) * H * W + hw;
-                float e = out[q] - tgt[q];
-                s += (double)e * e;
-                g = (float)(inv * e);
-            }
-            dz[t * kC + c] = (__bf16)g;
+        bf16x8 g8 = {};
+        for (int c = 0; c < 3; ++c) {
+            int64_t q = (b * 3 + c) * H * W + hw;
+            float e = out[q] - tgt[q];
+            s += (double)e * e;
+            g8[c] = (__bf16)(float)(inv * e);
         }
+        // slots 3..31 are zero: four 16-byte stores
+        bf16x8 *d = reinterpret_cast<bf16x8 *>(dz + t * kC);
+        const bf16x8 zero8 = {};
+        d[0] = g8;
+        d[1] = d[2] = d[3] = zero8;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -635,30 +661,30 @@ Scratch carve_scratch(char *base, int B, int H, int W, int64_t *bytes) {
     return s;
 }
 
-void forward_pass(const Scratch &s, const float *params, const float *in, int B, int H, int W, hipStream_t st) {
-    int64_t npix = (int64_t)B * H * W;
-    k_pack_weights<<<(4 * 9 * kC * kC + 255) / 256, 256, 0, st>>>(params, s.WB, s.WT, s.bias, nullptr);
-    k_pack_input<<<(unsigned)((npix * kC + 255) / 256), 256, 0, st>>>(in, s.X0, B, H, W);
-    int64_t tiles = (int64_t)B * H * ((W + 15) / 16);
-    unsigned g = (unsigned)((tiles + 3) / 4);
-    const __bf16 *x = s.X0;
-    for (int l = 0; l < 3; ++l) {
-        k_conv3x3<0><<<g, 256, 0, st>>>(x, s.WB + (int64_t)l * 9 * kC * kC, s.bias + l * kC, B, H, W, s.A[l], s.Z[l],
-                                          nullptr, nullptr);
-        x = s.A[l];
-    }
-    k_conv3x3<1><<<g, 256, 0, st>>>(x, s.WB + (int64_t)3 * 9 * kC * kC, s.bias + 3 * kC, B, H, W, nullptr, nullptr,
-                                      s.OUT, nullptr);
-}
-
-// Inference: weights packed into s (WB, bias, WF0), then the fused kernel
-// from the caller's input planes to the caller's output planes.
+// Tiles of kFT x kFT output pixels of a batch (one workgroup each).
 constexpr int64_t kFusedMaxTiles = (int64_t)1 << 24;
 
 int64_t fused_tiles(int B, int H, int W) {
     return (int64_t)B * ((H + kFT - 1) / kFT) * ((W + kFT - 1) / kFT);
 }
 
+void forward_pass(const Scratch &s, const float *params, const float *in, int B, int H, int W, hipStream_t st) {
+    int64_t npix = (int64_t)B * H * W;
+    k_pack_weights<<<(4 * 9 * kC * kC + 255) / 256, 256, 0, st>>>(params, s.WB, s.WT, s.bias, nullptr);
+    k_pack_input<<<(unsigned)((npix * (kC / 8) + 255) / 256), 256, 0, st>>>(in, s.X0, B, H, W);
+    const unsigned g = (unsigned)fused_tiles(B, H, W);
+    const __bf16 *x = s.X0;
+    for (int l = 0; l < 3; ++l) {
+        k_conv3x3_tile<0><<<g, kFThreads, 0, st>>>(x, s.WB + (int64_t)l * 9 * kC * kC, s.bias + l * kC, B, H, W,
+                                                   s.A[l], s.Z[l], nullptr, nullptr);
+        x = s.A[l];
+    }
+    k_conv3x3_tile<1><<<g, kFThreads, 0, st>>>(x, s.WB + (int64_t)3 * 9 * kC * kC, s.bias + 3 * kC, B, H, W, nullptr,
+                                               nullptr, s.OUT, nullptr);
+}
+
+// Inference: weights packed into s (WB, bias, WF0), then the fused kernel
+// from the caller's input planes to the caller's output planes.
 // Compute units of the current device (looked up once per device).
 int fused_cus() {
     static std::mutex mu;
@@ -689,8 +715,7 @@ void backward_pass(const Scratch &s, const float *target, int B, int H, int W, h
     unsigned nb = (unsigned)((npix + 255) / 256);
     k_mse<<<nb, 256, 0, st>>>(s.OUT, target, B, H, W, s.DZ[0], s.lpart);
     k_sum_double<<<1, 256, 0, st>>>(s.lpart, (int)nb, s.loss);
-    int64_t tiles = (int64_t)B * H * ((W + 15) / 16);
-    unsigned g = (unsigned)((tiles + 3) / 4);
+    const unsigned g = (unsigned)fused_tiles(B, H, W);
     int cur = 0;
     for (int l = 3; l >= 0; --l) {
         const __bf16 *aprev = (l == 0) ? s.X0 : s.A[l - 1];
@@ -699,8 +724,8 @@ void backward_pass(const Scratch &s, const float *target, int B, int H, int W, h
         k_wgrad_reduce<<<nred, 256, 0, st>>>(s.part, s.nwg, kLayersH[l].ci, kLayersH[l].co,
                                              s.grad + param_offset(l));
         if (l > 0) {
-            k_conv3x3<2><<<g, 256, 0, st>>>(s.DZ[cur], s.WT + (int64_t)l * 9 * kC * kC, nullptr, B, H, W,
-                                              s.DZ[cur ^ 1], nullptr, nullptr, s.Z[l - 1]);
+            k_conv3x3_tile<2><<<g, kFThreads, 0, st>>>(s.DZ[cur], s.WT + (int64_t)l * 9 * kC * kC, nullptr, B, H,
+                                                       W, s.DZ[cur ^ 1], nullptr, nullptr, s.Z[l - 1]);
             cur ^= 1;
         }
     }
