@@ -397,11 +397,11 @@ void readback(mg_ctx *c, double *host, const double *dev, int count, hipStream_t
 // full classical Gram-Schmidt passes give, with one pass over the basis
 // fewer per step, and two launches instead of four on chained grids (the
 // sums of pass 2 are formed by the next step's pass 1 and by the host).
-// h1, h2 and nu^2 go to the device scalars
-// ([0..k], [m+1..m+1+k], [2m+2]) and to pinned memory: a single problem's
+// h1 goes to the device scalars [0..k]; on large grids and for batches h2
+// and nu^2 too ([m+1..m+1+k], [2m+2]).  A single problem's values go
 // straight to one of two pinned slots (step k+1 can run while the host
-// reads step k; on chained grids h1 and pass 2's partials), a batch's
-// copied afterwards.
+// reads step k): h1 and, on chained grids, pass 2's partials, otherwise
+// h2 and nu^2; a batch's are copied afterwards.
 void arnoldi_step(mg_ctx *c, int k, double3 cw, hipStream_t s) {
     NewtonWork &W = c->nw;
     const Level &L0 = c->lev[0];
