@@ -483,16 +483,20 @@ constexpr int kWgChunk = 32;
 // a[p + (dy, dx)][ci], i.e. D (co x ci) += A (co x 32 pixels) * B (32
 // pixels x ci) per chunk of 32 consecutive pixels of one image row, two by
 // two 16x16x32 bf16 tiles with FP32 accumulators.  Wave `tap` of the
-// 9-wave workgroup owns one tap; the chunk's dz (transposed, [co][pixel]) and
-// the nine shifted input windows (transposed, [tap][ci][pixel]) are staged
-// in LDS so every operand is one aligned 16-byte LDS read.  Wave 0 also sums
-// dz for the bias gradient.  Every workgroup writes its partial sums in the
+// 9-wave workgroup owns one tap.  The chunk's dz (transposed, [co][pixel])
+// and the three input rows it reads (transposed, [row][ci][pixel], pixels
+// x0-1..x0+32, each value stored once) are staged in LDS; a tap's operand
+// of 8 pixels starting dx pixels into the row is cut from two aligned
+// 16-byte LDS reads (a shift by 0, 1 or 2 bf16 slots).  Wave 0 also sums dz
+// for the bias gradient.  Every workgroup writes its partial sums in the
 // layout k_wgrad_reduce adds in a fixed order.
-constexpr int kWgPad = 40;  // LDS row length (pixels) of the transposed tiles
+constexpr int kWgPad = 40;   // LDS row length (pixels) of the transposed dz
+constexpr int kWgRow = 48;   // LDS row length of the transposed input rows (34 used, 16-byte multiple)
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ a,
                                                     int B, int H, int W, float *__restrict__ part) {
     __shared__ __attribute__((aligned(16))) __bf16 sdz[kC][kWgPad];
-    __shared__ __attribute__((aligned(16))) __bf16 sa[9][kC][kWgPad];
+    __shared__ __attribute__((aligned(16))) __bf16 sa[3][kC][kWgRow];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int m = lane & 15, kg = lane >> 4;
     const int tap = wave, ky = tap / 3, kx = tap % 3;
@@ -502,9 +506,14 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
 #pragma unroll
         for (int h2 = 0; h2 < 2; ++h2) acc[h][h2] = f32x4{0, 0, 0, 0};
     float accb = 0.0f;
+    // the slots past the 34 staged pixels are read (and shifted out) only
+    const __bf16 zero = (__bf16)0.0f;
+    for (int q = t; q < 3 * kC * (kWgRow - (kWgChunk + 2)); q += blockDim.x) {
+        const int w = kWgRow - (kWgChunk + 2);
+        sa[q / (kC * w)][(q / w) % kC][kWgChunk + 2 + q % w] = zero;
+    }
     const int chunks_x = (W + kWgChunk - 1) / kWgChunk;
     const int64_t nchunks = (int64_t)B * H * chunks_x;
-    const __bf16 zero = (__bf16)0.0f;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int cx = (int)(ch % chunks_x);
         const int64_t by = ch / chunks_x;
@@ -519,8 +528,7 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
 #pragma unroll
             for (int u = 0; u < 8; ++u) sdz[c8 + u][p] = v[u];
         }
-        // the three input rows y-1..y+1 over pixels x0-1..x0+32, each value
-        // written to the (up to three) shifted copies of the taps that read it
+        // the three input rows y-1..y+1 over pixels x0-1..x0+32
         for (int q = t; q < 3 * (kWgChunk + 2) * (kC / 8); q += blockDim.x) {
             const int r = q / ((kWgChunk + 2) * (kC / 8)), P = (q / (kC / 8)) % (kWgChunk + 2);
             const int c8 = (q % (kC / 8)) * 8;
@@ -529,19 +537,26 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
             if (yy >= 0 && yy < H && xx >= 0 && xx < W)
                 v = *reinterpret_cast<const bf16x8 *>(a + (((int64_t)b * H + yy) * W + xx) * kC + c8);
 #pragma unroll
-            for (int kxx = 0; kxx < 3; ++kxx) {
-                const int p = P - kxx;
-                if (p < 0 || p >= kWgChunk) continue;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) sa[r * 3 + kxx][c8 + u][p] = v[u];
-            }
+            for (int u = 0; u < 8; ++u) sa[r][c8 + u][P] = v[u];
         }
         __syncthreads();
         bf16x8 A[2], Bm[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             A[h] = *reinterpret_cast<const bf16x8 *>(&sdz[h * 16 + m][8 * kg]);
-            Bm[h] = *reinterpret_cast<const bf16x8 *>(&sa[tap][h * 16 + m][8 * kg]);
+            // slots 8kg + kx .. 8kg + kx + 7 of row ky (slot P holds pixel x0 - 1 + P)
+            const u32x4 q0 = *reinterpret_cast<const u32x4 *>(&sa[ky][h * 16 + m][8 * kg]);
+            const u32x4 q1 = *reinterpret_cast<const u32x4 *>(&sa[ky][h * 16 + m][8 * kg + 8]);
+            u32x4 r;
+            if (kx == 0) {
+                r = q0;
+            } else if (kx == 2) {
+                r = u32x4{q0[1], q0[2], q0[3], q1[0]};
+            } else {
+                r = u32x4{__builtin_amdgcn_alignbyte(q0[1], q0[0], 2), __builtin_amdgcn_alignbyte(q0[2], q0[1], 2),
+                          __builtin_amdgcn_alignbyte(q0[3], q0[2], 2), __builtin_amdgcn_alignbyte(q1[0], q0[3], 2)};
+            }
+            Bm[h] = __builtin_bit_cast(bf16x8, r);
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h)
