@@ -475,23 +475,26 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out, cons
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// Pixels per weight-gradient chunk (one MFMA K step).
-constexpr int kWgChunk = 32;
+// Pixels per weight-gradient chunk: kWgSteps MFMA K steps of 32 pixels
+// between two barriers.
+constexpr int kWgSteps = 2;
+constexpr int kWgChunk = 32 * kWgSteps;
 
 // Weight and bias gradient of one layer on MFMA.  Per tap (dy, dx) the
 // gradient is a GEMM over pixels: dW_tap[co][ci] = sum_p dz[p][co] *
 // a[p + (dy, dx)][ci], i.e. D (co x ci) += A (co x 32 pixels) * B (32
-// pixels x ci) per chunk of 32 consecutive pixels of one image row, two by
+// pixels x ci) per K step of 32 consecutive pixels of one image row, two by
 // two 16x16x32 bf16 tiles with FP32 accumulators.  Wave `tap` of the
 // 9-wave workgroup owns one tap.  The chunk's dz (transposed, [co][pixel])
 // and the three input rows it reads (transposed, [row][ci][pixel], pixels
-// x0-1..x0+32, each value stored once) are staged in LDS; a tap's operand
+// x0-1..x0+kWgChunk, each value stored once) are staged in LDS; a tap's operand
 // of 8 pixels starting dx pixels into the row is cut from two aligned
 // 16-byte LDS reads (a shift by 0, 1 or 2 bf16 slots).  Wave 0 also sums dz
 // for the bias gradient.  Every workgroup writes its partial sums in the
 // layout k_wgrad_reduce adds in a fixed order.
-constexpr int kWgPad = 40;   // LDS row length (pixels) of the transposed dz
-constexpr int kWgRow = 48;   // LDS row length of the transposed input rows (34 used, 16-byte multiple)
+constexpr int kWgPad = kWgChunk + 8;    // LDS row length (pixels) of the transposed dz
+constexpr int kWgRow = kWgChunk + 16;   // LDS row length of the transposed input rows (kWgChunk + 2 used)
+static_assert(kWgPad % 8 == 0 && kWgRow % 8 == 0, "16-byte LDS rows");
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ a,
                                                     int B, int H, int W, float *__restrict__ part) {
@@ -506,7 +509,7 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
 #pragma unroll
         for (int h2 = 0; h2 < 2; ++h2) acc[h][h2] = f32x4{0, 0, 0, 0};
     float accb = 0.0f;
-    // the slots past the 34 staged pixels are read (and shifted out) only
+    // the slots past the kWgChunk + 2 staged pixels are read (and shifted out) only
     const __bf16 zero = (__bf16)0.0f;
     for (int q = t; q < 3 * kC * (kWgRow - (kWgChunk + 2)); q += blockDim.x) {
         const int w = kWgRow - (kWgChunk + 2);
@@ -520,7 +523,7 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
         const int y = (int)(by % H), b = (int)(by / H);
         const int x0 = cx * kWgChunk;
         __syncthreads();
-        // dz: 32 pixels x 4 groups of 8 channels, one 16-byte load each
+        // dz: kWgChunk pixels x 4 groups of 8 channels, one 16-byte load each
         for (int q = t; q < kWgChunk * (kC / 8); q += blockDim.x) {
             const int p = q / (kC / 8), c8 = (q % (kC / 8)) * 8, x = x0 + p;
             bf16x8 v = {};
@@ -528,7 +531,7 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
 #pragma unroll
             for (int u = 0; u < 8; ++u) sdz[c8 + u][p] = v[u];
         }
-        // the three input rows y-1..y+1 over pixels x0-1..x0+32
+        // the three input rows y-1..y+1 over pixels x0-1..x0+kWgChunk
         for (int q = t; q < 3 * (kWgChunk + 2) * (kC / 8); q += blockDim.x) {
             const int r = q / ((kWgChunk + 2) * (kC / 8)), P = (q / (kC / 8)) % (kWgChunk + 2);
             const int c8 = (q % (kC / 8)) * 8;
@@ -540,29 +543,33 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
             for (int u = 0; u < 8; ++u) sa[r][c8 + u][P] = v[u];
         }
         __syncthreads();
-        bf16x8 A[2], Bm[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            A[h] = *reinterpret_cast<const bf16x8 *>(&sdz[h * 16 + m][8 * kg]);
-            // slots 8kg + kx .. 8kg + kx + 7 of row ky (slot P holds pixel x0 - 1 + P)
-            const u32x4 q0 = *reinterpret_cast<const u32x4 *>(&sa[ky][h * 16 + m][8 * kg]);
-            const u32x4 q1 = *reinterpret_cast<const u32x4 *>(&sa[ky][h * 16 + m][8 * kg + 8]);
-            u32x4 r;
-            if (kx == 0) {
-                r = q0;
-            } else if (kx == 2) {
-                r = u32x4{q0[1], q0[2], q0[3], q1[0]};
-            } else {
-                r = u32x4{__builtin_amdgcn_alignbyte(q0[1], q0[0], 2), __builtin_amdgcn_alignbyte(q0[2], q0[1], 2),
-                          __builtin_amdgcn_alignbyte(q0[3], q0[2], 2), __builtin_amdgcn_alignbyte(q1[0], q0[3], 2)};
+        for (int st = 0; st < kWgSteps; ++st) {
+            const int o = 32 * st + 8 * kg;  // first pixel slot of this lane's K group
+            bf16x8 A[2], Bm[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                A[h] = *reinterpret_cast<const bf16x8 *>(&sdz[h * 16 + m][o]);
+                // slots o + kx .. o + kx + 7 of row ky (slot P holds pixel x0 - 1 + P)
+                const u32x4 q0 = *reinterpret_cast<const u32x4 *>(&sa[ky][h * 16 + m][o]);
+                const u32x4 q1 = *reinterpret_cast<const u32x4 *>(&sa[ky][h * 16 + m][o + 8]);
+                u32x4 r;
+                if (kx == 0) {
+                    r = q0;
+                } else if (kx == 2) {
+                    r = u32x4{q0[1], q0[2], q0[3], q1[0]};
+                } else {
+                    r = u32x4{__builtin_amdgcn_alignbyte(q0[1], q0[0], 2), __builtin_amdgcn_alignbyte(q0[2], q0[1], 2),
+                              __builtin_amdgcn_alignbyte(q0[3], q0[2], 2), __builtin_amdgcn_alignbyte(q1[0], q0[3], 2)};
+                }
+                Bm[h] = __builtin_bit_cast(bf16x8, r);
             }
-            Bm[h] = __builtin_bit_cast(bf16x8, r);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2)
+                    acc[h][h2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], Bm[h2], acc[h][h2], 0, 0, 0);
         }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int h2 = 0; h2 < 2; ++h2)
-                acc[h][h2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[h], Bm[h2], acc[h][h2], 0, 0, 0);
         if (wave == 0 && lane < kC)
             for (int p = 0; p < kWgChunk; ++p) accb += (float)sdz[lane][p];
     }
