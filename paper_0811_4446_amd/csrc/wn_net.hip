@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out, cons
 
 // Pixels per weight-gradient chunk: kWgSteps MFMA K steps of 32 pixels
 // between two barriers.
-constexpr int kWgSteps = 2;
+constexpr int kWgSteps = 4;
 constexpr int kWgChunk = 32 * kWgSteps;
 
 // Weight and bias gradient of one layer on MFMA.  Per tap (dy, dx) the
@@ -545,6 +545,7 @@ __global__ __launch_bounds__(576) void k_wgrad_mfma(const __bf16 *__restrict__ d
         __syncthreads();
 #pragma unroll
         for (int st = 0; st < kWgSteps; ++st) {
+            if (x0 + 32 * st >= W) break;  // a step wholly past the row's end adds nothing
             const int o = 32 * st + 8 * kg;  // first pixel slot of this lane's K group
             bf16x8 A[2], Bm[2];
 #pragma unroll
